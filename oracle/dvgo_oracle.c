@@ -1,0 +1,713 @@
+/*
+ * FP64 CPU oracle for the per-ray training step of direct voxel-grid radiance fields
+ * (Sun, Sun & Chen, "Improved Direct Voxel Grid Optimization for Radiance Fields
+ * Reconstruction", arXiv 2206.05085).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct reference
+ * that the HIP path is checked against.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load it.  It shares no code, header or constant with
+ * the HIP library.
+ *
+ * Conventions.  Every floating-point input arrives as the same float32 buffer the GPU
+ * receives and is widened to double at its point of use; every result is double.  All
+ * per-ray work is independent and runs under OpenMP; scatters into grids run serially in
+ * (ray, sample, corner) order so results are deterministic.
+ *
+ * Where the paper leaves a detail open, the reading taken here is stated at the function
+ * that uses it.  Functions that follow an exact definition implement that definition
+ * directly (for instance the double sum of Eq. 1, not its O(N) rewrite), so that a reader
+ * can check each line against the paper.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_VERSION 1
+
+typedef struct {
+    const float *data;   /* [nx][ny][nz][cs] channel-last */
+    int32_t n[3];
+    int32_t cs;          /* floats per vertex */
+    int32_t C;           /* channels used */
+    float bmin[3], bmax[3];
+} orc_grid;
+
+int orc_version(void) { return ORC_VERSION; }
+
+/* Shift b of the density activation.  Section 5.4 fixes the initial alpha (1e-4) at a
+ * 0.5-voxel step but does not write the activation out.  Reading: sigma =
+ * softplus(raw + b), alpha = 1 - exp(-sigma * delta), with b chosen so that raw = 0 at
+ * delta = delta_ref gives alpha_init:  (1 + e^b)^(-delta_ref) = 1 - alpha_init. */
+double orc_act_shift(double alpha_init, double delta_ref)
+{
+    return log(pow(1.0 - alpha_init, -1.0 / delta_ref) - 1.0);
+}
+
+static double softplus(double z) { return z > 0 ? z + log1p(exp(-z)) : log1p(exp(z)); }
+static double sigmoid(double z)
+{
+    if (z >= 0) return 1.0 / (1.0 + exp(-z));
+    double e = exp(z);
+    return e / (1.0 + e);
+}
+
+/* ------------------------------------------------------------------ interpolation */
+
+/* Trilinear interpolation on a vertex grid whose corner vertices sit on the box corners
+ * (the paper queries its grids through a library routine, section 4; reading: vertex i is
+ * at bmin + i (bmax - bmin)/(n - 1)).  A coordinate is clamped to the box, and a point on
+ * the upper face uses the last cell with fraction 1.  Corner c = 4 dx + 2 dy + dz. */
+static void corners(const orc_grid *g, const float *p, int64_t idx[8], double wt[8])
+{
+    int64_t i0[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        double lo = g->bmin[a], hi = g->bmax[a];
+        double u = ((double)p[a] - lo) / (hi - lo) * (double)(g->n[a] - 1);
+        if (!(u > 0.0)) u = 0.0; /* also maps NaN to 0 */
+        if (u > g->n[a] - 1) u = g->n[a] - 1;
+        int64_t i = (int64_t)floor(u);
+        if (i > g->n[a] - 2) i = g->n[a] - 2;
+        i0[a] = i;
+        f[a] = u - (double)i;
+    }
+    for (int c = 0; c < 8; ++c) {
+        int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+        idx[c] = (((i0[0] + dx) * g->n[1] + (i0[1] + dy)) * g->n[2] + (i0[2] + dz)) * g->cs;
+        wt[c] = (dx ? f[0] : 1.0 - f[0]) * (dy ? f[1] : 1.0 - f[1]) * (dz ? f[2] : 1.0 - f[2]);
+    }
+}
+
+static void interp(const orc_grid *g, const float *p, double *out)
+{
+    int64_t idx[8];
+    double wt[8];
+    corners(g, p, idx, wt);
+    for (int ch = 0; ch < g->C; ++ch) out[ch] = 0.0;
+    for (int c = 0; c < 8; ++c)
+        for (int ch = 0; ch < g->C; ++ch) out[ch] += wt[c] * (double)g->data[idx[c] + ch];
+}
+
+/* Adjoint of interp: grad[vertex] += weight * g.  grad has the grid's [..][cs] layout. */
+static void interp_adjoint(const orc_grid *g, const float *p, const double *gv, double *grad)
+{
+    int64_t idx[8];
+    double wt[8];
+    corners(g, p, idx, wt);
+    for (int c = 0; c < 8; ++c)
+        for (int ch = 0; ch < g->C; ++ch) grad[idx[c] + ch] += wt[c] * gv[ch];
+}
+
+void orc_gather(const orc_grid *g, int64_t S, const float *xyz, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < S; ++k) interp(g, xyz + 3 * k, out + k * g->C);
+}
+
+void orc_scatter(const orc_grid *g, int64_t S, const float *xyz, const double *gv, double *grad)
+{
+    for (int64_t k = 0; k < S; ++k) interp_adjoint(g, xyz + 3 * k, gv + k * g->C, grad);
+}
+
+/* ---------------------------------------------------------------- distortion loss */
+
+/* Eq. 1 written out: for one ray with weights w, interval midpoints m and lengths l,
+ *   D = sum_i sum_j w_i w_j |m_i - m_j| + (1/3) sum_i w_i^2 l_i.                     */
+static double dist_ray(int n, const double *w, const float *m, const float *l)
+{
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) a += w[i] * w[j] * fabs((double)m[i] - (double)m[j]);
+        b += w[i] * w[i] * (double)l[i];
+    }
+    return a + b / 3.0;
+}
+
+/* Derivative of Eq. 1 by w_k, written out (Eq. 3 plus the derivative of the second term,
+ * which Eq. 3 leaves out; Eq. 3's third sum should read w_i m_i):
+ *   dD/dw_k = 2 sum_j w_j |m_k - m_j| + (2/3) w_k l_k.                                 */
+static void dist_ray_grad(int n, const double *w, const float *m, const float *l, double *g)
+{
+    for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += w[j] * fabs((double)m[k] - (double)m[j]);
+        g[k] = 2.0 * s + 2.0 / 3.0 * w[k] * (double)l[k];
+    }
+}
+
+void orc_distortion(int32_t R, const int32_t *offs, const double *w, const float *m, const float *l, double *D)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t o = offs[r];
+        D[r] = dist_ray(offs[r + 1] - offs[r], w + o, m + o, l + o);
+    }
+}
+
+void orc_distortion_grad(int32_t R, const int32_t *offs, const double *w, const float *m, const float *l,
+                         const double *gD, double *gw)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t o = offs[r];
+        int n = offs[r + 1] - offs[r];
+        dist_ray_grad(n, w + o, m + o, l + o, gw + o);
+        for (int k = 0; k < n; ++k) gw[o + k] *= gD[r];
+    }
+}
+
+/* The O(N) rewrite of Eq. 2 exactly as the paper states it: with sorted midpoints the
+ * first term equals 2 sum_i w_i (m_i P_i - PM_i), where P_i and PM_i are the exclusive
+ * prefix sums of w and w*m.  Kept as a second form so tests can confirm the rewrite. */
+void orc_distortion_prefix(int32_t R, const int32_t *offs, const double *w, const float *m, const float *l, double *D)
+{
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t o = offs[r];
+        int n = offs[r + 1] - offs[r];
+        double P = 0.0, PM = 0.0, first = 0.0, second = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double wi = w[o + i], mi = m[o + i];
+            first += 2.0 * wi * (mi * P - PM);
+            second += wi * wi * (double)l[o + i];
+            P += wi;
+            PM += wi * mi;
+        }
+        D[r] = first + second / 3.0;
+    }
+}
+
+/* Eq. 3 (third sum corrected to w_i m_i) plus (2/3) w_k l_k, with prefix and suffix sums. */
+void orc_distortion_prefix_grad(int32_t R, const int32_t *offs, const double *w, const float *m, const float *l,
+                                double *gw)
+{
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t o = offs[r];
+        int n = offs[r + 1] - offs[r];
+        double totW = 0.0, totWM = 0.0;
+        for (int i = 0; i < n; ++i) { totW += w[o + i]; totWM += w[o + i] * m[o + i]; }
+        double P = 0.0, PM = 0.0;
+        for (int k = 0; k < n; ++k) {
+            double wk = w[o + k], mk = m[o + k];
+            double SW = totW - P - wk, SWM = totWM - PM - wk * mk;
+            gw[o + k] = 2.0 * mk * P - 2.0 * PM + 2.0 * SWM - 2.0 * mk * SW + 2.0 / 3.0 * wk * (double)l[o + k];
+            P += wk;
+            PM += wk * mk;
+        }
+    }
+}
+
+/* -------------------------------------------------------------------- rendering */
+
+/* Per-ray forward quantities for one ray.  Colour is either interpolated from a colour
+ * grid (identity activation; reading for the grid-colour mode) or given per sample.
+ *
+ * Density to alpha (section 3): sigma = softplus(raw + b), alpha = 1 - exp(-sigma delta).
+ * Front-to-back accumulation: T_0 = 1, T_{k+1} = T_k (1 - alpha_k), w_k = T_k alpha_k,
+ * C = sum_k w_k c_k + T_N bg.  Halting (section 3): once the accumulated transmittance
+ * T_k drops below halt_T (> 0), sample k and all later samples are skipped (w = 0) and
+ * T_N is that T_k.  halt_T = 0 disables it. */
+typedef struct {
+    int n, halt;        /* halt = index of the first skipped sample, n if none */
+    double *raw, *c, *x, *alpha, *T, *w;  /* T has n+1 entries */
+} ray_fwd;
+
+static void ray_forward(ray_fwd *rf, int n, const float *xyz, const float *delta, const orc_grid *dens,
+                        const orc_grid *col, const double *srgb, double act_shift, double halt_T)
+{
+    rf->n = n;
+    rf->T[0] = 1.0;
+    rf->halt = n;
+    for (int k = 0; k < n; ++k) {
+        interp(dens, xyz + 3 * k, &rf->raw[k]);
+        if (col) interp(col, xyz + 3 * k, rf->c + 3 * k);
+        else for (int ch = 0; ch < 3; ++ch) rf->c[3 * k + ch] = srgb[3 * k + ch];
+        double sigma = softplus(rf->raw[k] + act_shift);
+        rf->x[k] = sigma * (double)delta[k];
+        rf->alpha[k] = -expm1(-rf->x[k]);
+    }
+    for (int k = 0; k < n; ++k) {
+        if (rf->halt == n && halt_T > 0.0 && rf->T[k] < halt_T) rf->halt = k;
+        if (rf->halt <= k) {
+            rf->w[k] = 0.0;
+            rf->T[k + 1] = rf->T[k];
+            continue;
+        }
+        rf->w[k] = rf->T[k] * rf->alpha[k];
+        rf->T[k + 1] = rf->T[k] * exp(-rf->x[k]);
+    }
+}
+
+static ray_fwd alloc_ray(int n)
+{
+    ray_fwd rf;
+    size_t m = (size_t)(n > 0 ? n : 1);
+    rf.raw = malloc(m * sizeof(double));
+    rf.c = malloc(3 * m * sizeof(double));
+    rf.x = malloc(m * sizeof(double));
+    rf.alpha = malloc(m * sizeof(double));
+    rf.T = malloc((m + 1) * sizeof(double));
+    rf.w = malloc(m * sizeof(double));
+    return rf;
+}
+
+static void free_ray(ray_fwd *rf)
+{
+    free(rf->raw); free(rf->c); free(rf->x); free(rf->alpha); free(rf->T); free(rf->w);
+}
+
+/* Forward render of a ragged batch.  Outputs per ray: rgb[R,3], T_N[R], D[R] (Eq. 1 on
+ * the ray's weights with the caller's normalised midpoints and lengths); optionally the
+ * per-sample weights w[S] and alphas. */
+void orc_render_forward(int32_t R, const int32_t *offs, const float *xyz, const float *delta, const float *s_mid,
+                        const float *s_len, const orc_grid *dens, const orc_grid *col, const double *srgb,
+                        double act_shift, double halt_T, const double *bg,
+                        double *rgb, double *T_N, double *D, double *w_out, double *alpha_out)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t o = offs[r];
+        int n = offs[r + 1] - offs[r];
+        ray_fwd rf = alloc_ray(n);
+        ray_forward(&rf, n, xyz + 3 * o, delta + o, dens, col, srgb ? srgb + 3 * o : NULL, act_shift, halt_T);
+        double TN = rf.T[n];
+        for (int ch = 0; ch < 3; ++ch) {
+            double acc = 0.0;
+            for (int k = 0; k < n; ++k) acc += rf.w[k] * rf.c[3 * k + ch];
+            rgb[3 * r + ch] = acc + TN * bg[ch];
+        }
+        T_N[r] = TN;
+        if (D) D[r] = dist_ray(n, rf.w, s_mid + o, s_len + o);
+        if (w_out) for (int k = 0; k < n; ++k) w_out[o + k] = rf.w[k];
+        if (alpha_out) for (int k = 0; k < n; ++k) alpha_out[o + k] = rf.alpha[k];
+        free_ray(&rf);
+    }
+}
+
+/* Backward of the forward render by the chain rule, for upstream gradients
+ * G_C = dL/dC [R,3], G_D = dL/dD [R] (or NULL) and G_T = dL/dT_N [R] (or NULL).
+ *
+ * With g_k = G_C . c_k + G_D dD/dw_k (the direct dependence of L on w_k):
+ *   dw_i/dx_k = T_{k+1} if i = k,  -w_i if i > k,  0 if i < k;  dT_N/dx_k = -T_N,
+ * so dL/dx_k = T_{k+1} g_k - sum_{i>k} g_i w_i - (G_C . bg + G_T) T_N, and
+ * dL/draw_k = dL/dx_k * delta_k * sigmoid(raw_k + b);  dL/dc_k = w_k G_C.
+ * Skipped (halted) samples receive no gradient.  The inner sum is evaluated directly,
+ * O(N^2) per ray, on purpose.
+ *
+ * Outputs (accumulated, +=): grad_dens (density grid layout), grad_col (colour grid
+ * layout, grid-colour mode) or grad_srgb [S,3] (per-sample colour mode). */
+void orc_render_backward(int32_t R, const int32_t *offs, const float *xyz, const float *delta, const float *s_mid,
+                         const float *s_len, const orc_grid *dens, const orc_grid *col, const double *srgb,
+                         double act_shift, double halt_T, const double *bg,
+                         const double *G_C, const double *G_D, const double *G_T,
+                         double *grad_dens, double *grad_col, double *grad_srgb)
+{
+    int64_t S = offs[R];
+    double *draw = calloc((size_t)(S > 0 ? S : 1), sizeof(double));
+    double *dc = calloc((size_t)(S > 0 ? 3 * S : 1), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int32_t r = 0; r < R; ++r) {
+        int64_t o = offs[r];
+        int n = offs[r + 1] - offs[r];
+        ray_fwd rf = alloc_ray(n);
+        ray_forward(&rf, n, xyz + 3 * o, delta + o, dens, col, srgb ? srgb + 3 * o : NULL, act_shift, halt_T);
+        double *g = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        double *dDdw = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        double gd = G_D ? G_D[r] : 0.0;
+        if (G_D) dist_ray_grad(n, rf.w, s_mid + o, s_len + o, dDdw);
+        for (int k = 0; k < n; ++k) {
+            double gc = 0.0;
+            for (int ch = 0; ch < 3; ++ch) gc += G_C[3 * r + ch] * rf.c[3 * k + ch];
+            g[k] = gc + (G_D ? gd * dDdw[k] : 0.0);
+        }
+        double tail = (G_T ? G_T[r] : 0.0);
+        for (int ch = 0; ch < 3; ++ch) tail += G_C[3 * r + ch] * bg[ch];
+        tail *= rf.T[n];
+        for (int k = 0; k < n; ++k) {
+            if (k >= rf.halt) { draw[o + k] = 0.0; continue; }
+            double later = 0.0;
+            for (int i = k + 1; i < n; ++i) later += g[i] * rf.w[i];
+            double dx = rf.T[k + 1] * g[k] - later - tail;
+            draw[o + k] = dx * (double)delta[k + o] * sigmoid(rf.raw[k] + act_shift);
+            for (int ch = 0; ch < 3; ++ch) dc[3 * (o + k) + ch] = rf.w[k] * G_C[3 * r + ch];
+        }
+        free(g);
+        free(dDdw);
+        free_ray(&rf);
+    }
+    for (int64_t k = 0; k < S; ++k) {
+        interp_adjoint(dens, xyz + 3 * k, draw + k, grad_dens);
+        if (col && grad_col) interp_adjoint(col, xyz + 3 * k, dc + 3 * k, grad_col);
+    }
+    if (grad_srgb) for (int64_t k = 0; k < 3 * S; ++k) grad_srgb[k] += dc[k];
+    free(draw);
+    free(dc);
+}
+
+/* Per-sample alpha only (density path of the forward); used for the coarse proposal pass. */
+void orc_alpha(int64_t S, const float *xyz, const float *delta, const orc_grid *dens, double act_shift, double *alpha)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < S; ++k) {
+        double raw;
+        interp(dens, xyz + 3 * k, &raw);
+        alpha[k] = -expm1(-softplus(raw + act_shift) * (double)delta[k]);
+    }
+}
+
+/* Photometric + distortion loss: L = (1/(3R)) sum ||C_r - target_r||^2 + lambda (1/R) sum D_r
+ * (reading: both terms are means over rays).  Returns L; writes G_C and G_D. */
+double orc_loss_head(int32_t R, const double *rgb, const float *target, const double *D, double lambda,
+                     double *G_C, double *G_D)
+{
+    double L = 0.0;
+    for (int32_t r = 0; r < R; ++r) {
+        for (int ch = 0; ch < 3; ++ch) {
+            double e = rgb[3 * r + ch] - (double)target[3 * r + ch];
+            L += e * e / (3.0 * R);
+            if (G_C) G_C[3 * r + ch] = 2.0 * e / (3.0 * R);
+        }
+        if (D) L += lambda * D[r] / R;
+        if (G_D) G_D[r] = lambda / R;
+    }
+    return L;
+}
+
+/* ------------------------------------------------------------------- colour MLP */
+
+/* View-direction encoding: [d, sin(2^0 d), ..., sin(2^{F-1} d), cos(2^0 d), ..., cos(2^{F-1} d)],
+ * each block xyz in order: 3 + 6F values. */
+static void view_pe(const float *d, int F, double *pe)
+{
+    for (int a = 0; a < 3; ++a) pe[a] = d[a];
+    for (int q = 0; q < F; ++q)
+        for (int a = 0; a < 3; ++a) {
+            double v = ldexp((double)d[a], q);
+            pe[3 + 3 * q + a] = sin(v);
+            pe[3 + 3 * F + 3 * q + a] = cos(v);
+        }
+}
+
+/* Hybrid colour head: input [feat(C), PE(d)], two hidden ReLU layers of H, sigmoid RGB. */
+typedef struct {
+    const float *W1, *b1, *W2, *b2, *W3, *b3;  /* [H][C+3+6F], [H], [H][H], [H], [3][H], [3] */
+    int32_t C, F, H;
+} orc_mlp;
+
+static int64_t find_ray(int32_t R, const int32_t *offs, int64_t k)
+{
+    int64_t lo = 0, hi = R - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) / 2;
+        if (offs[mid] <= k) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+static void mlp_fwd_one(const orc_mlp *P, const double *x, double *z1, double *h1, double *z2, double *h2, double *rgb)
+{
+    int I = P->C + 3 + 6 * P->F, H = P->H;
+    for (int i = 0; i < H; ++i) {
+        double s = P->b1[i];
+        for (int j = 0; j < I; ++j) s += (double)P->W1[i * I + j] * x[j];
+        z1[i] = s;
+        h1[i] = s > 0 ? s : 0.0;
+    }
+    for (int i = 0; i < H; ++i) {
+        double s = P->b2[i];
+        for (int j = 0; j < H; ++j) s += (double)P->W2[i * H + j] * h1[j];
+        z2[i] = s;
+        h2[i] = s > 0 ? s : 0.0;
+    }
+    for (int i = 0; i < 3; ++i) {
+        double s = P->b3[i];
+        for (int j = 0; j < H; ++j) s += (double)P->W3[i * H + j] * h2[j];
+        rgb[i] = sigmoid(s);
+    }
+}
+
+void orc_mlp_forward(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
+                     double *rgb)
+{
+    int64_t S = offs[R];
+    int I = P->C + 3 + 6 * P->F, H = P->H;
+#pragma omp parallel
+    {
+        double *x = malloc(sizeof(double) * I), *buf = malloc(sizeof(double) * 4 * H);
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < S; ++k) {
+            int64_t r = find_ray(R, offs, k);
+            for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
+            view_pe(dirs + 3 * r, P->F, x + P->C);
+            mlp_fwd_one(P, x, buf, buf + H, buf + 2 * H, buf + 3 * H, rgb + 3 * k);
+        }
+        free(x);
+        free(buf);
+    }
+}
+
+/* Backward of the colour head for upstream grad_rgb [S,3]: writes grad_feat [S,C] and
+ * accumulates (+=) the parameter gradients, serially in sample order. */
+void orc_mlp_backward(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
+                      const double *grad_rgb, double *grad_feat,
+                      double *gW1, double *gb1, double *gW2, double *gb2, double *gW3, double *gb3)
+{
+    int64_t S = offs[R];
+    int I = P->C + 3 + 6 * P->F, H = P->H;
+    double *x = malloc(sizeof(double) * I);
+    double *z1 = malloc(sizeof(double) * H), *h1 = malloc(sizeof(double) * H);
+    double *z2 = malloc(sizeof(double) * H), *h2 = malloc(sizeof(double) * H);
+    double *d2 = malloc(sizeof(double) * H), *d1 = malloc(sizeof(double) * H);
+    double rgb[3], d3[3];
+    for (int64_t k = 0; k < S; ++k) {
+        int64_t r = find_ray(R, offs, k);
+        for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
+        view_pe(dirs + 3 * r, P->F, x + P->C);
+        mlp_fwd_one(P, x, z1, h1, z2, h2, rgb);
+        for (int i = 0; i < 3; ++i) {
+            d3[i] = grad_rgb[3 * k + i] * rgb[i] * (1.0 - rgb[i]);
+            gb3[i] += d3[i];
+            for (int j = 0; j < H; ++j) gW3[i * H + j] += d3[i] * h2[j];
+        }
+        for (int j = 0; j < H; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < 3; ++i) s += (double)P->W3[i * H + j] * d3[i];
+            d2[j] = z2[j] > 0 ? s : 0.0;
+        }
+        for (int i = 0; i < H; ++i) {
+            gb2[i] += d2[i];
+            for (int j = 0; j < H; ++j) gW2[i * H + j] += d2[i] * h1[j];
+        }
+        for (int j = 0; j < H; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < H; ++i) s += (double)P->W2[i * H + j] * d2[i];
+            d1[j] = z1[j] > 0 ? s : 0.0;
+        }
+        for (int i = 0; i < H; ++i) {
+            gb1[i] += d1[i];
+            for (int j = 0; j < I; ++j) gW1[i * I + j] += d1[i] * x[j];
+        }
+        for (int c = 0; c < P->C; ++c) {
+            double s = 0.0;
+            for (int i = 0; i < H; ++i) s += (double)P->W1[i * I + c] * d1[i];
+            grad_feat[k * P->C + c] = s;
+        }
+    }
+    free(x); free(z1); free(h1); free(z2); free(h2); free(d2); free(d1);
+}
+
+/* ------------------------------------------------------------------------- Adam */
+
+/* Adam with bias correction and 1-based step t; elements whose gradient is exactly zero
+ * (either sign) are skipped, leaving parameter and both moments untouched (section 3,
+ * fused Adam that does not update grid points with zero gradient). */
+void orc_adam(int64_t n, double *p, const double *g, double *m, double *v, double lr, double beta1,
+              double beta2, double eps, int32_t t, int32_t skip_zero)
+{
+    double bc1 = 1.0 - pow(beta1, t), bc2 = 1.0 - pow(beta2, t);
+    for (int64_t i = 0; i < n; ++i) {
+        if (skip_zero && g[i] == 0.0) continue;
+        m[i] = beta1 * m[i] + (1.0 - beta1) * g[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
+        double mh = m[i] / bc1, vh = v[i] / bc2;
+        p[i] -= lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* -------------------------------------------------------------- proposal network */
+
+/* Round to bfloat16 with round-to-nearest-even, via float32 (the kernel's own operand
+ * precision is float32 before it narrows to bfloat16). */
+static double bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (double)f; /* inf / nan */
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+void orc_bf16_round(int64_t n, const double *in, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = bf16(in[i]);
+}
+
+/* Proposal MLP: L linear layers with ReLU between them, sizes[0] -> ... -> sizes[L].
+ * Each layer's weights and inputs are rounded to bfloat16 before the product; products
+ * accumulate in double; biases stay in full precision.  Output: logits [R, sizes[L]]. */
+typedef struct {
+    int32_t L;
+    int32_t sizes[8];
+    const float *W[8], *b[8];
+} orc_prop;
+
+static void prop_fwd_one(const orc_prop *P, const double *x0, double *acts /* sum of sizes */, double *z /* per layer */)
+{
+    /* acts holds the bf16-rounded input of every layer; z the pre-activation of every layer */
+    int off = 0, zoff = 0;
+    for (int i = 0; i < P->sizes[0]; ++i) acts[i] = bf16(x0[i]);
+    for (int l = 0; l < P->L; ++l) {
+        int I = P->sizes[l], O = P->sizes[l + 1];
+        const double *in = acts + off;
+        for (int o = 0; o < O; ++o) {
+            double s = 0.0;
+            for (int i = 0; i < I; ++i) s += bf16((double)P->W[l][o * I + i]) * in[i];
+            s += (double)P->b[l][o];
+            z[zoff + o] = s;
+            if (l + 1 < P->L) acts[off + I + o] = bf16(s > 0 ? s : 0.0);
+        }
+        off += I;
+        zoff += O;
+    }
+}
+
+static int prop_total(const orc_prop *P, int upto)
+{
+    int t = 0;
+    for (int l = 0; l < upto; ++l) t += P->sizes[l];
+    return t;
+}
+
+/* Logits, softmax probabilities and the entropy -sum p ln p of every ray. */
+void orc_prop_forward(const orc_prop *P, int32_t R, const double *x, double *logits, double *prob, double *entropy)
+{
+    int B = P->sizes[P->L], I0 = P->sizes[0];
+    int na = prop_total(P, P->L), nz = prop_total(P, P->L + 1) - I0;
+#pragma omp parallel
+    {
+        double *acts = malloc(sizeof(double) * na), *z = malloc(sizeof(double) * nz);
+#pragma omp for schedule(static)
+        for (int32_t r = 0; r < R; ++r) {
+            prop_fwd_one(P, x + (int64_t)r * I0, acts, z);
+            const double *lg = z + nz - B;
+            double mx = lg[0];
+            for (int b = 1; b < B; ++b) mx = lg[b] > mx ? lg[b] : mx;
+            double s = 0.0;
+            for (int b = 0; b < B; ++b) s += exp(lg[b] - mx);
+            double H = 0.0;
+            for (int b = 0; b < B; ++b) {
+                double p = exp(lg[b] - mx) / s;
+                if (logits) logits[(int64_t)r * B + b] = lg[b];
+                if (prob) prob[(int64_t)r * B + b] = p;
+                if (p > 0) H -= p * log(p);
+            }
+            if (entropy) entropy[r] = H;
+        }
+        free(acts);
+        free(z);
+    }
+}
+
+/* Cross-entropy -(1/R) sum_r sum_b p_rb ln softmax(z_r)_b against target histograms p,
+ * and its backward through the network.  The gradient at the logits is
+ * (softmax(z) - p)/R.  In the backward, every gradient that enters a product (the
+ * gradient at a layer's output) is rounded to bfloat16 like the weights and inputs.
+ * Parameter gradients are accumulated (+=); returns the loss. */
+double orc_prop_backward(const orc_prop *P, int32_t R, const double *x, const double *target,
+                         double **gW, double **gb)
+{
+    int B = P->sizes[P->L], I0 = P->sizes[0];
+    int na = prop_total(P, P->L), nz = prop_total(P, P->L + 1) - I0;
+    double *acts = malloc(sizeof(double) * na), *z = malloc(sizeof(double) * nz);
+    double *dz = malloc(sizeof(double) * 1024), *din = malloc(sizeof(double) * 1024);
+    double loss = 0.0;
+    for (int32_t r = 0; r < R; ++r) {
+        prop_fwd_one(P, x + (int64_t)r * I0, acts, z);
+        const double *lg = z + nz - B;
+        double mx = lg[0];
+        for (int b = 1; b < B; ++b) mx = lg[b] > mx ? lg[b] : mx;
+        double s = 0.0;
+        for (int b = 0; b < B; ++b) s += exp(lg[b] - mx);
+        const double *tg = target + (int64_t)r * B;
+        for (int b = 0; b < B; ++b) {
+            double lp = lg[b] - mx - log(s);
+            loss -= tg[b] * lp / R;
+            dz[b] = (exp(lp) - tg[b]) / R;
+        }
+        /* walk layers backwards; dz holds dL/dz of layer l (size O) */
+        int zoff = nz, aoff = na;
+        for (int l = P->L - 1; l >= 0; --l) {
+            int I = P->sizes[l], O = P->sizes[l + 1];
+            zoff -= O;
+            aoff -= I;
+            const double *in = acts + aoff;
+            for (int o = 0; o < O; ++o) dz[o] = bf16(dz[o]);
+            for (int o = 0; o < O; ++o) {
+                gb[l][o] += dz[o];
+                for (int i = 0; i < I; ++i) gW[l][o * I + i] += dz[o] * in[i];
+            }
+            if (l == 0) break;
+            for (int i = 0; i < I; ++i) {
+                double t = 0.0;
+                for (int o = 0; o < O; ++o) t += bf16((double)P->W[l][o * I + i]) * dz[o];
+                din[i] = z[zoff - I + i] > 0 ? t : 0.0; /* ReLU of the previous layer */
+            }
+            for (int i = 0; i < I; ++i) dz[i] = din[i];
+        }
+    }
+    free(acts); free(z); free(dz); free(din);
+    return loss;
+}
+
+/* Target histogram of a rendered ray: h_b = sum of the weights of samples whose
+ * normalised midpoint falls into bin b of B equal bins on [0,1]; normalised to sum 1
+ * when the total is at least min_mass, otherwise uniform. */
+void orc_histogram(int32_t R, const int32_t *offs, const double *w, const float *s_mid, int32_t B, double min_mass,
+                   double *hist)
+{
+    for (int32_t r = 0; r < R; ++r) {
+        double *h = hist + (int64_t)r * B, tot = 0.0;
+        for (int b = 0; b < B; ++b) h[b] = 0.0;
+        for (int64_t k = offs[r]; k < offs[r + 1]; ++k) {
+            int b = (int)floor((double)s_mid[k] * B);
+            if (b < 0) b = 0;
+            if (b > B - 1) b = B - 1;
+            h[b] += w[k];
+            tot += w[k];
+        }
+        for (int b = 0; b < B; ++b) h[b] = tot >= min_mass ? h[b] / tot : 1.0 / B;
+    }
+}
+
+/* Inverse-CDF placement of n fine samples per ray from a piecewise-constant density of
+ * B equal bins on s in [0,1] with bin masses p.  u_j = (j + 1/2)/n; sample j lies in the
+ * first bin b whose right CDF value exceeds u_j (zero-mass bins are never chosen), at
+ * s_j = (b + (u_j - CDF_b)/p_b)/B.  Each fine sample owns the interval between the
+ * midpoints to its neighbours, closed by 0 and 1: s_mid = s_j, s_len = its length.
+ * Bounded rays map s linearly to t in [t_near, t_far]: x = o + t d, and delta is the
+ * interval's t-length over the voxel size. */
+void orc_resample(int32_t R, int32_t B, const double *p, int32_t n, const float *o, const float *d, const float *tn,
+                  const float *tf, double voxel, double *xyz, double *delta, double *s_mid, double *s_len)
+{
+    double *cdf = malloc(sizeof(double) * (B + 1)), *s = malloc(sizeof(double) * n);
+    for (int32_t r = 0; r < R; ++r) {
+        const double *pr = p + (int64_t)r * B;
+        cdf[0] = 0.0;
+        for (int b = 0; b < B; ++b) cdf[b + 1] = cdf[b] + pr[b];
+        for (int j = 0; j < n; ++j) {
+            double u = (j + 0.5) / n * cdf[B];
+            int b = 0;
+            while (b < B - 1 && !(cdf[b + 1] > u)) ++b;
+            double frac = pr[b] > 0 ? (u - cdf[b]) / pr[b] : 0.5;
+            if (frac < 0) frac = 0;
+            if (frac > 1) frac = 1;
+            s[j] = (b + frac) / B;
+        }
+        double len = (double)tf[r] - (double)tn[r];
+        for (int j = 0; j < n; ++j) {
+            double lo = j == 0 ? 0.0 : 0.5 * (s[j - 1] + s[j]);
+            double hi = j == n - 1 ? 1.0 : 0.5 * (s[j] + s[j + 1]);
+            int64_t k = (int64_t)r * n + j;
+            double t = (double)tn[r] + s[j] * len;
+            for (int a = 0; a < 3; ++a) xyz[3 * k + a] = (double)o[3 * r + a] + t * (double)d[3 * r + a];
+            s_mid[k] = s[j];
+            s_len[k] = hi - lo;
+            delta[k] = (hi - lo) * len / voxel;
+        }
+    }
+    free(cdf);
+    free(s);
+}

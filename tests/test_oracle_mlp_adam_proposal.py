@@ -1,0 +1,171 @@
+"""Pins of the oracle's colour MLP, Adam step and proposal network.
+
+The MLP reduces to torch float64 Linear/ReLU/Sigmoid (a library routine) and its
+backward to torch autograd; Adam with all-non-zero gradients reduces to
+torch.optim.Adam in float64; the proposal network reduces to torch float64 with
+bfloat16 rounding applied by torch's own conversion, and its resampler to closed forms.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+torch.set_num_threads(4)
+
+
+def _pe(d, F):
+    d = torch.as_tensor(d, dtype=torch.float64)
+    fr = [d * (2.0 ** q) for q in range(F)]
+    return torch.cat([d] + [torch.sin(v) for v in fr] + [torch.cos(v) for v in fr], dim=-1)
+
+
+def _torch_mlp(mlp, feat, dirs_per_sample, F=4):
+    W = [torch.tensor(w, dtype=torch.float64, requires_grad=True) for w in mlp.W]
+    b = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in mlp.b]
+    f = torch.tensor(feat, dtype=torch.float64, requires_grad=True)
+    x = torch.cat([f, _pe(dirs_per_sample, F)], dim=-1)
+    h = torch.relu(torch.nn.functional.linear(x, W[0], b[0]))
+    h = torch.relu(torch.nn.functional.linear(h, W[1], b[1]))
+    rgb = torch.sigmoid(torch.nn.functional.linear(h, W[2], b[2]))
+    return rgb, f, W, b
+
+
+def test_mlp_matches_torch(orc):
+    rng = np.random.default_rng(40)
+    mlp = synth.mlp_weights(rng, bias_std=0.3)
+    offs = np.array([0, 5, 5, 17, 30], np.int32)
+    S = int(offs[-1])
+    dirs = synth.scenes._unit(rng.standard_normal((4, 3))).astype(np.float32)
+    feat = rng.standard_normal((S, 12))
+    rgb = orc.mlp_forward(mlp, offs, dirs, feat)
+    ray_of = np.repeat(np.arange(4), np.diff(offs))
+    trgb, f, W, b = _torch_mlp(mlp, feat, dirs[ray_of].astype(np.float64))
+    np.testing.assert_allclose(rgb, trgb.detach().numpy(), rtol=1e-12, atol=1e-14)
+    g = rng.standard_normal((S, 3))
+    (trgb * torch.tensor(g)).sum().backward()
+    gf, gW, gb = orc.mlp_backward(mlp, offs, dirs, feat, g)
+    np.testing.assert_allclose(gf, f.grad.numpy(), rtol=1e-10, atol=1e-13)
+    for a, t in zip(gW + gb, W + b):
+        np.testing.assert_allclose(a, t.grad.numpy(), rtol=1e-10, atol=1e-13)
+
+
+def test_adam_matches_torch_and_skips_zero(orc):
+    rng = np.random.default_rng(41)
+    n = 1000
+    p = rng.standard_normal(n)
+    tp = torch.tensor(p.copy(), requires_grad=True)
+    opt = torch.optim.Adam([tp], lr=0.05, betas=(0.9, 0.99), eps=1e-8)
+    m = np.zeros(n)
+    v = np.zeros(n)
+    for t in range(1, 4):
+        g = rng.standard_normal(n)
+        tp.grad = torch.tensor(g)
+        opt.step()
+        p, m, v = orc.adam(p, g, m, v, 0.05, 0.9, 0.99, 1e-8, t)
+    np.testing.assert_allclose(p, tp.detach().numpy(), rtol=1e-13, atol=1e-15)
+    # zero-gradient elements (either sign of zero) are left bit-for-bit untouched
+    g = rng.standard_normal(n)
+    g[::3] = 0.0
+    g[1::7] = -0.0
+    p2, m2, v2 = orc.adam(p, g, m, v, 0.05, 0.9, 0.99, 1e-8, 4)
+    z = (g == 0)
+    assert np.array_equal(p2[z], p[z]) and np.array_equal(m2[z], m[z]) and np.array_equal(v2[z], v[z])
+    assert (p2[~z] != p[~z]).all()
+
+
+def _bf(t):
+    return t.to(torch.bfloat16).to(torch.float64)
+
+
+def test_bf16_rounding_matches_torch(orc):
+    rng = np.random.default_rng(42)
+    x = np.concatenate([rng.standard_normal(1000) * 10.0 ** rng.integers(-8, 8, 1000), [0.0, -0.0, 1.0, 3.0]])
+    np.testing.assert_array_equal(orc.bf16_round(x), _bf(torch.tensor(x).to(torch.float32).to(torch.float64)).numpy())
+
+
+def _torch_prop(pw, x, target):
+    W = [torch.tensor(w, dtype=torch.float64, requires_grad=True) for w in pw.W]
+    b = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in pw.b]
+    a = _bf(torch.tensor(x, dtype=torch.float64))
+    L = len(W)
+    for l in range(L):
+        Wb = W[l] + (_bf(W[l].detach()) - W[l].detach())          # rounded weights, identity gradient
+        z = torch.nn.functional.linear(a, Wb, b[l])
+        z.register_hook(_bf)                                      # rounded output gradient
+        if l + 1 < L:
+            h = torch.relu(z)
+            a = h + (_bf(h.detach()) - h.detach())
+    logp = torch.log_softmax(z, dim=-1)
+    loss = -(torch.tensor(target) * logp).sum() / x.shape[0]
+    return z, loss, W, b
+
+
+def test_proposal_matches_torch_bf16(orc):
+    rng = np.random.default_rng(43)
+    pw = synth.proposal_weights(rng, bias_std=0.1)
+    R = 37
+    x = rng.random((R, 64)) * 0.3
+    tgt = rng.random((R, 64))
+    tgt /= tgt.sum(1, keepdims=True)
+    lg, pr, H = orc.prop_forward(pw, x)
+    z, loss, W, b = _torch_prop(pw, x, tgt)
+    np.testing.assert_allclose(lg, z.detach().numpy(), rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(pr, torch.softmax(z, -1).detach().numpy(), rtol=1e-12)
+    np.testing.assert_allclose(H, -(pr * np.log(pr)).sum(1), rtol=1e-12)
+    loss.backward()
+    L, gW, gb = orc.prop_backward(pw, x, tgt)
+    assert L == pytest.approx(loss.item(), rel=1e-12)
+    for a, t in zip(gW + gb, W + b):
+        np.testing.assert_allclose(a, t.grad.numpy(), rtol=1e-9, atol=1e-14)
+
+
+def test_proposal_entropy_uniform_and_ce_gradient(orc):
+    pw = synth.proposal_weights(np.random.default_rng(44))
+    for w in pw.W[-1:]:
+        w[:] = 0.0
+    x = np.random.default_rng(45).random((3, 64))
+    lg, pr, H = orc.prop_forward(pw, x)
+    np.testing.assert_allclose(H, np.log(64), rtol=1e-12)
+    # with a zero last layer the bias gradient is sum_r bf16((softmax - p)/R) = sum_r bf16((1/64 - p)/R)
+    tgt = np.zeros((3, 64))
+    tgt[:, 5] = 1.0
+    _, _, gb = orc.prop_backward(pw, x, tgt)
+    expect = orc.bf16_round((1.0 / 64 - tgt) / 3).sum(0)
+    np.testing.assert_allclose(gb[-1], expect, rtol=1e-12)
+
+
+def test_histogram(orc):
+    offs = np.array([0, 4, 4, 7], np.int32)
+    w = np.array([0.1, 0.2, 0.3, 0.4, 1e-6, 1e-6, 1e-6])
+    sm = np.array([0.01, 0.26, 0.51, 0.99, 0.1, 0.2, 0.3], np.float32)
+    h = orc.histogram(offs, w, sm, B=4, min_mass=1e-4)
+    np.testing.assert_allclose(h[0], [0.1, 0.2, 0.3, 0.4])
+    np.testing.assert_allclose(h[1], 0.25)   # empty ray: uniform
+    np.testing.assert_allclose(h[2], 0.25)   # too little mass: uniform
+    np.testing.assert_allclose(h.sum(1), 1.0)
+
+
+def test_resample_closed_forms(orc):
+    R, B, n = 3, 64, 48
+    rays = synth.Rays(np.zeros((R, 3), np.float32), np.tile(np.array([0, 0, 1], np.float32), (R, 1)),
+                      np.array([1.0, 2.0, 0.5], np.float32), np.array([3.0, 2.5, 4.5], np.float32), np.ones(R, bool))
+    p = np.zeros((R, B))
+    p[0] = 1.0 / B                # uniform -> s_j = (j + 1/2)/n
+    p[1, 17] = 1.0                # one-hot bin b -> s_j = (b + (j + 1/2)/n)/B
+    p[2, [3, 40]] = [0.25, 0.75]  # two bins: the first quarter of u lands in bin 3
+    out = orc.resample(p, n, rays, voxel=0.01)
+    j = np.arange(n)
+    sm = out["s_mid"].reshape(R, n)
+    np.testing.assert_allclose(sm[0], (j + 0.5) / n, rtol=1e-13)
+    np.testing.assert_allclose(sm[1], (17 + (j + 0.5) / n) / B, rtol=1e-13)
+    u = (j + 0.5) / n
+    exp2 = np.where(u < 0.25, (3 + u / 0.25) / B, (40 + (u - 0.25) / 0.75) / B)
+    np.testing.assert_allclose(sm[2], exp2, rtol=1e-12)
+    sl = out["s_len"].reshape(R, n)
+    np.testing.assert_allclose(sl.sum(1), 1.0, rtol=1e-13)
+    assert (sl > 0).all() and (np.diff(sm, axis=1) > 0).all()
+    span = (rays.t_far - rays.t_near).astype(np.float64)
+    np.testing.assert_allclose(out["delta"].reshape(R, n), sl * span[:, None] / 0.01, rtol=1e-13)
+    z = out["xyz"].reshape(R, n, 3)[..., 2]
+    np.testing.assert_allclose(z, rays.t_near[:, None] + sm * span[:, None], rtol=1e-13)
