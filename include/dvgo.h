@@ -1,0 +1,209 @@
+/*
+ * dvgo.h -- C-ABI of libdvgo.so, the MI355X (gfx950) kernels of the per-ray training step
+ * of direct voxel-grid radiance fields (Sun, Sun & Chen, arXiv 2206.05085).
+ *
+ * General conventions (apply to every entry point below)
+ * ------------------------------------------------------
+ * Return value:  DVGO_OK (0) or a negative DVGO_ERR_* code.  A human-readable detail of the
+ *   last failure on the calling thread is returned by dvgo_last_error().  No C++ exception
+ *   crosses this interface.  On an error nothing has been enqueued.
+ * Memory:  every array pointer is a DEVICE pointer owned by the caller (hipMalloc'd or
+ *   torch-allocated on the current device), unless stated otherwise.  The library never
+ *   allocates in these calls.  Where scratch memory is needed the caller passes a workspace
+ *   whose minimum size is returned by the matching *_size query.
+ * Streams:  `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls are
+ *   asynchronous on that stream; argument validation is synchronous and host-side only (it
+ *   never reads device memory).
+ * Gradients:  gradients into parameter grids and weights are ACCUMULATED (+=), never
+ *   overwritten: the caller zeroes them (or lets dvgo_grid_adam_step zero them).  This is the
+ *   paper's convention of adding gradients into the tensor between backward and the
+ *   optimiser step (section 2, efficient TV loss).  Per-sample and per-ray gradient outputs
+ *   are written (overwritten).
+ * Floating point:  float32 everywhere.  NaN/Inf propagate; nothing traps.  Gradient
+ *   accumulation uses atomics, so summation order (and the last bits) may vary run to run.
+ * Ragged batches:  ray r owns samples ray_offsets[r] .. ray_offsets[r+1]-1 of every
+ *   per-sample array; ray_offsets has n_rays+1 non-decreasing entries with ray_offsets[0] = 0
+ *   and ray_offsets[n_rays] = n_samples (section 2, uneven numbers of points per ray).
+ *   Within a ray s_mid must be non-decreasing (section 2 assumes sorted midpoints).
+ *   These two device-side properties are the caller's contract; they are not checked.
+ * Structs carry `struct_size` = sizeof(struct) for ABI evolution; a mismatch is DVGO_ERR_ABI.
+ */
+#ifndef DVGO_H
+#define DVGO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DVGO_ABI_VERSION 1
+
+enum {
+    DVGO_OK = 0,
+    DVGO_ERR_NULL = -1,        /* a required pointer is NULL */
+    DVGO_ERR_SHAPE = -2,       /* inconsistent or unsupported sizes */
+    DVGO_ERR_RANGE = -3,       /* a size or index exceeds what the kernels address */
+    DVGO_ERR_WORKSPACE = -5,   /* workspace / state buffer smaller than its query says */
+    DVGO_ERR_HIP = -6,         /* a HIP runtime call (launch) failed */
+    DVGO_ERR_UNSUPPORTED = -7, /* a mode or parameter value that is not implemented */
+    DVGO_ERR_ABI = -8          /* struct_size mismatch */
+};
+
+enum { DVGO_COLOR_GRID = 0, DVGO_COLOR_SAMPLES = 1 };
+
+/* Dense vertex grid, channel-last: value (i,j,k,c) at data[((i*ny + j)*nz + k)*ch_stride + c].
+ * Vertex i along x sits at xyz_min[0] + i*(xyz_max[0]-xyz_min[0])/(nx-1) (vertices on the box
+ * corners).  A query point is clamped to the box; trilinear weights use the enclosing cell.
+ * Requirements: nx,ny,nz >= 2; 1 <= channels <= ch_stride <= 16; xyz_max > xyz_min;
+ * nx*ny*nz*ch_stride < 2^31.  `grad` (same layout) receives += in backward calls; it may be
+ * NULL where a call does not write it. */
+typedef struct dvgo_grid {
+    uint32_t struct_size;
+    int32_t nx, ny, nz;
+    int32_t channels;
+    int32_t ch_stride;
+    float xyz_min[3];
+    float xyz_max[3];
+    const float *data;
+    float *grad;
+} dvgo_grid;
+
+/* Flattened ragged batch of samples (point queries) along rays.
+ * xyz [S,3]: query points in grid coordinates' world frame.
+ * delta [S]: length of the sample's interval in voxel units (the alpha step, section 5.4).
+ * s_mid [S], s_len [S]: midpoint and length of the sample's interval in the per-ray
+ *   normalised coordinate s in [0,1] that the distortion loss uses (Eq. 1). */
+typedef struct dvgo_samples {
+    uint32_t struct_size;
+    int32_t n_rays;
+    int64_t n_samples;
+    const int32_t *ray_offsets;
+    const float *xyz;
+    const float *delta;
+    const float *s_mid;
+    const float *s_len;
+} dvgo_samples;
+
+/* act_shift: b in sigma = softplus(raw + b) (section 3 density-to-alpha; b sets the initial
+ *   alpha, section 5.4).  halt_T: stop a ray once its accumulated transmittance falls below
+ *   this value (section 3; the paper uses 1e-3); 0 disables halting.  bg: background colour
+ *   composited with the final transmittance.  color_mode: DVGO_COLOR_GRID (colour =
+ *   trilinear value of a 3-channel colour grid) or DVGO_COLOR_SAMPLES (colour given per
+ *   sample, e.g. by the colour MLP).  want_dist: also compute the distortion loss (Eq. 1). */
+typedef struct dvgo_render_params {
+    uint32_t struct_size;
+    float act_shift;
+    float halt_T;
+    float bg[3];
+    int32_t color_mode;
+    int32_t want_dist;
+} dvgo_render_params;
+
+/* Colour MLP: input [features(in_feat), view-direction encoding(3 + 6*n_freq)] -> hidden ->
+ * hidden -> 3 with ReLU, ReLU, sigmoid (the hybrid colour of Table 1).  View encoding of a
+ * unit direction d: [d, sin(2^0 d) .. sin(2^(F-1) d), cos(2^0 d) .. cos(2^(F-1) d)], each block
+ * in x,y,z order.  Weights are row-major [out][in] (W1 [H][in_feat+3+6F], W2 [H][H],
+ * W3 [3][H]); the g* pointers receive += in dvgo_mlp_backward.
+ * Supported: in_feat <= 12, n_freq <= 4 (so the input fits 48 columns), hidden = 128. */
+typedef struct dvgo_color_mlp {
+    uint32_t struct_size;
+    int32_t in_feat;
+    int32_t n_freq;
+    int32_t hidden;
+    const float *W1, *b1, *W2, *b2, *W3, *b3;
+    float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
+} dvgo_color_mlp;
+
+int dvgo_abi_version(void);
+const char *dvgo_last_error(void);
+
+/* Size in bytes of the per-batch state that dvgo_render_forward saves for
+ * dvgo_render_backward (per-ray halt index and per-64-sample chunk checkpoints). */
+int dvgo_render_state_size(int32_t n_rays, int64_t n_samples, size_t *bytes);
+
+/* Forward volume rendering of a ragged batch (section 3 rendering utilities, section 2 Eq. 1).
+ * Per sample k: raw_k = trilinear(density, x_k); sigma_k = softplus(raw_k + act_shift);
+ * alpha_k = 1 - exp(-sigma_k delta_k); T_0 = 1, T_{k+1} = T_k (1 - alpha_k); w_k = T_k alpha_k.
+ * Per ray: rgb = sum_k w_k c_k + T_N bg; T_final = T_N; dist = Eq. 1 on (w, s_mid, s_len)
+ * computed in O(N) by prefix scans.
+ * color: the 3-channel colour grid (DVGO_COLOR_GRID) or NULL; sample_rgb [S,3] for
+ * DVGO_COLOR_SAMPLES, else NULL.  Outputs rgb [R,3], T_final [R], dist [R] (NULL allowed
+ * when want_dist = 0).  state: device buffer of dvgo_render_state_size bytes, written here
+ * and read by the backward; it must stay unchanged in between. */
+int dvgo_render_forward(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                        const dvgo_grid *color, const float *sample_rgb, float *rgb, float *T_final, float *dist,
+                        void *state, size_t state_bytes, void *stream);
+
+/* Backward of dvgo_render_forward (recomputes each ray from the saved chunk checkpoints;
+ * no per-sample intermediates are stored).  Upstream gradients: grad_rgb [R,3] (required),
+ * grad_dist [R] and grad_T [R] (NULL = zero).  T_final must be the forward's output.
+ * Writes: density->grad += dL/d(density values); in grid mode color->grad += dL/d(colour
+ * values); in sample mode grad_sample_rgb [S,3] = dL/dc (overwritten; zero for halted
+ * samples).  The derivative of the distortion term follows Eq. 3 (its third sum read as
+ * w_i m_i) plus the derivative of Eq. 1's second term, (2/3) w_k s_len_k. */
+int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                         const dvgo_grid *color, const float *sample_rgb, const float *T_final, const void *state,
+                         size_t state_bytes, const float *grad_rgb, const float *grad_dist, const float *grad_T,
+                         float *grad_sample_rgb, void *stream);
+
+/* Size of the workspace dvgo_distortion_loss needs when grad_w is requested. */
+int dvgo_distortion_workspace_size(int32_t n_rays, int64_t n_samples, size_t *bytes);
+
+/* Distortion loss of section 2 on given weights (Eq. 1, computed in O(N) per ray by the
+ * prefix-sum rewrite of Eq. 2 and the prefix/suffix form of Eq. 3).  Inputs w, s_mid, s_len
+ * [S] on the ray_offsets layout.  loss [R] (may be NULL) receives D_r.  If grad_loss [R] and
+ * grad_w [S] are both non-NULL, grad_w += grad_loss[r] * dD_r/dw_k; this needs `ws` of
+ * dvgo_distortion_workspace_size bytes (else ws may be NULL). */
+int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w,
+                         const float *s_mid, const float *s_len, float *loss, const float *grad_loss, float *grad_w,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* Fused Adam over n float32 elements (section 3, re-implemented Adam): with 1-based step t,
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).
+ * skip_zero_grad != 0: elements whose gradient is exactly zero are skipped entirely (p, m,
+ * v untouched), as the paper does for grid points without gradient.  zero_grad_after != 0:
+ * the gradient is reset to zero for the next step. */
+int dvgo_grid_adam_step(float *param, float *grad, float *exp_avg, float *exp_avg_sq, int64_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t step, int32_t skip_zero_grad,
+                        int32_t zero_grad_after, void *stream);
+
+/* Trilinear gather of every channel at n_samples points: out [S, channels] row-major. */
+int dvgo_grid_gather(const dvgo_grid *g, int64_t n_samples, const float *xyz, float *out, void *stream);
+
+/* Adjoint of dvgo_grid_gather: g->grad += scatter of grad_out [S, channels]. */
+int dvgo_grid_scatter(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
+                      void *stream);
+
+/* Per-sample alpha of the density path only (trilinear, softplus shift, 1 - exp(-sigma delta)):
+ * alpha [S].  Used for the coarse samples of the proposal stage. */
+int dvgo_alpha(const dvgo_grid *density, int64_t n_samples, const float *xyz, const float *delta, float act_shift,
+               float *alpha, void *stream);
+
+/* Workspace for the colour MLP (per-ray direction encodings and per-block weight-gradient
+ * partials). */
+int dvgo_mlp_workspace_size(const dvgo_color_mlp *m, int32_t n_rays, int64_t n_samples, size_t *bytes);
+
+/* Colour MLP forward on FP32 matrix cores: rgb [S,3] from feat [S, in_feat] and the
+ * direction dirs [R,3] of each sample's ray. */
+int dvgo_mlp_forward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
+                     int64_t n_samples, const float *feat, float *rgb, void *ws, size_t ws_bytes, void *stream);
+
+/* Colour MLP backward (recomputes the forward): grad_feat [S, in_feat] written; weight and
+ * bias gradients accumulated into m->g*. */
+int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
+                      int64_t n_samples, const float *feat, const float *grad_rgb, float *grad_feat, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Loss head: loss[0] = (1/(3R)) sum ||rgb_r - target_r||^2 + dist_weight (1/R) sum dist_r
+ * (dist may be NULL: no distortion term); grad_rgb [R,3] and grad_dist [R] (may be NULL)
+ * receive dloss/drgb and dloss/ddist.  The paper weights the distortion term by 1e-2
+ * (sections 5.3, 5.4). */
+int dvgo_loss_head(int32_t n_rays, const float *rgb, const float *target, const float *dist, float dist_weight,
+                   float *loss, float *grad_rgb, float *grad_dist, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVGO_H */

@@ -1,0 +1,282 @@
+// Internal helpers shared by the gfx950 kernels of libdvgo (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dvgo.h"
+
+namespace dvgo {
+
+// ----------------------------------------------------------------------------- wave64
+
+// All scans run across the 64 lanes of one wavefront (CDNA wave64).
+__device__ __forceinline__ int lane() { return (int)__lane_id(); }
+
+// inclusive prefix sum: lane l gets sum of lanes 0..l
+__device__ __forceinline__ float wave_incl(float v) {
+    const int l = lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        float t = __shfl_up(v, d, 64);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+// exclusive prefix from an inclusive one (lane 0 gets 0); exact, no subtraction
+__device__ __forceinline__ float wave_excl(float incl) {
+    float t = __shfl_up(incl, 1, 64);
+    return lane() == 0 ? 0.f : t;
+}
+
+// inclusive suffix sum: lane l gets sum of lanes l..63
+__device__ __forceinline__ float wave_incl_rev(float v) {
+    const int l = lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        float t = __shfl_down(v, d, 64);
+        if (l + d < 64) v += t;
+    }
+    return v;
+}
+
+// exclusive suffix from an inclusive suffix (lane 63 gets 0)
+__device__ __forceinline__ float wave_excl_rev(float incl_rev) {
+    float t = __shfl_down(incl_rev, 1, 64);
+    return lane() == 63 ? 0.f : t;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ float bcast(float v, int src) { return __shfl(v, src, 64); }
+
+// --------------------------------------------------------------------------- math
+
+__device__ __forceinline__ float softplusf(float z) {
+    return z > 0.f ? z + log1pf(expf(-z)) : log1pf(expf(z));
+}
+
+__device__ __forceinline__ float sigmoidf(float z) {
+    if (z >= 0.f) return 1.f / (1.f + expf(-z));
+    float e = expf(z);
+    return e / (1.f + e);
+}
+
+// --------------------------------------------------------------------------- grids
+
+// Device view of a dvgo_grid.  The world->index map u = x*s + o per axis is carried as
+// double-float pairs (hi + lo) so the cell index and the fractional position are exact to
+// float32 precision of the fraction itself, not of u (u reaches 319 on a 320^3 grid).
+struct DevGrid {
+    const float *data;
+    float *grad;
+    int n[3];
+    int cs;  // floats per vertex
+    int C;   // channels used
+    int sx, sy;  // strides (floats) of x and y; z stride is cs
+    float s_hi[3], s_lo[3], o_hi[3], o_lo[3];
+};
+
+struct Tri {
+    int base;     // float offset of corner (0,0,0)
+    float w[8];   // corner c = 4dx + 2dy + dz
+};
+
+// Cell index i0 in [0, n-2] and fraction f in [0, 1] of coordinate x on one axis.
+__device__ __forceinline__ void axis_coord(float x, float shi, float slo, float ohi, float olo, int n, int &i0,
+                                           float &f) {
+    // The error-free transforms below need each operation rounded on its own: an FMA
+    // formed from x*shi + ohi would break the two-sum.
+#pragma clang fp contract(off)
+    // x*shi exactly as p + pe (FMA), then p + ohi exactly as u + e (two-sum)
+    float p = x * shi;
+    float pe = fmaf(x, shi, -p);
+    float u = p + ohi;
+    float bb = u - p;
+    float e = (p - (u - bb)) + (ohi - bb);
+    float lo = e + pe + fmaf(x, slo, olo);
+    float fl = floorf(u);
+    float fr = (u - fl) + lo;  // u - fl is exact
+    if (fr < 0.f) { fl -= 1.f; fr += 1.f; }
+    else if (fr >= 1.f) { fl += 1.f; fr -= 1.f; }
+    const float top = (float)(n - 2);
+    if (!(fl >= 0.f)) { i0 = 0; f = 0.f; }               // below the box (or NaN)
+    else if (fl > top) { i0 = n - 2; f = 1.f; }          // on or above the upper face
+    else { i0 = (int)fl; f = fr; }
+}
+
+__device__ __forceinline__ Tri trilinear(const DevGrid &g, float x, float y, float z) {
+    int ix, iy, iz;
+    float fx, fy, fz;
+    axis_coord(x, g.s_hi[0], g.s_lo[0], g.o_hi[0], g.o_lo[0], g.n[0], ix, fx);
+    axis_coord(y, g.s_hi[1], g.s_lo[1], g.o_hi[1], g.o_lo[1], g.n[1], iy, fy);
+    axis_coord(z, g.s_hi[2], g.s_lo[2], g.o_hi[2], g.o_lo[2], g.n[2], iz, fz);
+    Tri t;
+    t.base = ix * g.sx + iy * g.sy + iz * g.cs;
+    const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) t.w[c] = (wx[(c >> 2) & 1] * wy[(c >> 1) & 1]) * wz[c & 1];
+    return t;
+}
+
+// Cell and fractions of a point (the inputs of the trilinear weights), kept for the
+// aggregated scatter below.
+struct Cell {
+    int ix, iy, iz;
+    float fx, fy, fz;
+};
+
+__device__ __forceinline__ Cell cell_of(const DevGrid &g, float x, float y, float z) {
+    Cell c;
+    axis_coord(x, g.s_hi[0], g.s_lo[0], g.o_hi[0], g.o_lo[0], g.n[0], c.ix, c.fx);
+    axis_coord(y, g.s_hi[1], g.s_lo[1], g.o_hi[1], g.o_lo[1], g.n[1], c.iy, c.fy);
+    axis_coord(z, g.s_hi[2], g.s_lo[2], g.o_hi[2], g.o_lo[2], g.n[2], c.iz, c.fz);
+    return c;
+}
+
+__device__ __forceinline__ float corner_weight(const Cell &c, int dx, int dy, int dz) {
+    return ((dx ? c.fx : 1.f - c.fx) * (dy ? c.fy : 1.f - c.fy)) * (dz ? c.fz : 1.f - c.fz);
+}
+
+// Adjoint of trilinear interpolation for the 64 points held by the lanes of a wave, with
+// the contributions that land on the same vertex summed inside the wave before the atomic.
+//
+// Points come from consecutive samples along rays, so the lanes that touch one vertex form
+// runs of neighbouring lanes.  A (lane, corner) pair is the head of its run when the lane
+// before does not touch that vertex; the head walks forward over the following lanes while
+// they still touch the vertex, adds their weighted values (each lane's corner for that
+// vertex follows from its own cell), and alone issues the atomics.  Every contribution is
+// counted once: a non-head belongs to exactly one run, whose head reaches it.  All lanes
+// must call this (it shuffles); lanes with valid == false contribute nothing.
+template <int NC>
+__device__ __forceinline__ void scatter_wave(const DevGrid &g, bool valid, const Cell &cl, const float (&v)[NC],
+                                             int nch = NC) {
+    const int ln = lane();
+    const int px = __shfl_up(cl.ix, 1, 64), py = __shfl_up(cl.iy, 1, 64), pz = __shfl_up(cl.iz, 1, 64);
+    const bool pvalid = (__shfl_up(valid ? 1 : 0, 1, 64) != 0) && ln > 0;
+    float acc[8][NC];
+    unsigned head = 0;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+        const int ax = cl.ix + dx - px, ay = cl.iy + dy - py, az = cl.iz + dz - pz;
+        const bool prev_touches = pvalid && (unsigned)ax <= 1u && (unsigned)ay <= 1u && (unsigned)az <= 1u;
+        if (valid && !prev_touches) head |= 1u << c;
+        const float w = corner_weight(cl, dx, dy, dz);
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) acc[c][ch] = w * v[ch];
+    }
+    unsigned active = head;
+    for (int k = 1; k < 64; ++k) {
+        if (__ballot(active != 0) == 0ull) break;
+        const int src = ln + k < 64 ? ln + k : ln;
+        const int nx = __shfl(cl.ix, src, 64), ny = __shfl(cl.iy, src, 64), nz = __shfl(cl.iz, src, 64);
+        Cell nc;
+        nc.fx = __shfl(cl.fx, src, 64);
+        nc.fy = __shfl(cl.fy, src, 64);
+        nc.fz = __shfl(cl.fz, src, 64);
+        const bool nvalid = (__shfl(valid ? 1 : 0, src, 64) != 0) && ln + k < 64;
+        float nv[NC];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) nv[ch] = __shfl(v[ch], src, 64);
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            if (!(active & (1u << c))) continue;
+            const int ax = cl.ix + ((c >> 2) & 1) - nx, ay = cl.iy + ((c >> 1) & 1) - ny,
+                      az = cl.iz + (c & 1) - nz;
+            if (nvalid && (unsigned)ax <= 1u && (unsigned)ay <= 1u && (unsigned)az <= 1u) {
+                const float w = corner_weight(nc, ax, ay, az);
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch) acc[c][ch] += w * nv[ch];
+            } else {
+                active &= ~(1u << c);
+            }
+        }
+    }
+    const int base = cl.ix * g.sx + cl.iy * g.sy + cl.iz * g.cs;
+    if (NC == 1) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (head & (1u << c))
+                unsafeAtomicAdd(g.grad + base + ((c >> 2) & 1) * g.sx + ((c >> 1) & 1) * g.sy + (c & 1) * g.cs,
+                                acc[c][0]);
+        return;
+    }
+    // Multi-channel: compact the heads of each corner through this wave's LDS slice and
+    // issue the atomics with consecutive lanes on consecutive channels of one vertex, so one
+    // instruction covers a few whole vertex rows instead of one float of 64 vertices.
+    extern __shared__ float scatter_lds[];
+    float *vals = scatter_lds + (threadIdx.x >> 6) * (64 * (NC + 1));
+    int *keys = reinterpret_cast<int *>(vals + 64 * NC);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const bool h = (head >> c) & 1u;
+        const unsigned long long m = __ballot(h);
+        if (m == 0ull) continue;
+        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        const int nh = __popcll(m);
+        if (h) {
+            keys[rank] = base + ((c >> 2) & 1) * g.sx + ((c >> 1) & 1) * g.sy + (c & 1) * g.cs;
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) vals[rank * NC + ch] = acc[c][ch];
+        }
+        __threadfence_block();
+        for (int i = ln; i < nh * NC; i += 64) {
+            const int e = i / NC, ch = i - e * NC;
+            if (ch < nch) unsafeAtomicAdd(g.grad + keys[e] + ch, vals[i]);
+        }
+        __threadfence_block();
+    }
+}
+
+// bytes of dynamic LDS a block of `threads` needs for scatter_wave<NC>
+__host__ __device__ constexpr int scatter_lds_bytes(int NC, int threads) {
+    return NC == 1 ? 0 : (threads / 64) * 64 * (NC + 1) * 4;
+}
+
+__device__ __forceinline__ Tri tri_from_cell(const DevGrid &g, const Cell &c) {
+    Tri t;
+    t.base = c.ix * g.sx + c.iy * g.sy + c.iz * g.cs;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) t.w[k] = corner_weight(c, (k >> 2) & 1, (k >> 1) & 1, k & 1);
+    return t;
+}
+
+__device__ __forceinline__ int corner_off(const DevGrid &g, int c) {
+    return ((c >> 2) & 1) * g.sx + ((c >> 1) & 1) * g.sy + (c & 1) * g.cs;
+}
+
+__device__ __forceinline__ float interp_ch(const DevGrid &g, const Tri &t, int ch) {
+    float acc = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc += t.w[c] * g.data[t.base + corner_off(g, c) + ch];
+    return acc;
+}
+
+__device__ __forceinline__ void scatter_ch(const DevGrid &g, const Tri &t, int ch, float v) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) unsafeAtomicAdd(&g.grad[t.base + corner_off(g, c) + ch], t.w[c] * v);
+}
+
+// ------------------------------------------------------------------------- host side
+
+int set_error(int code, const char *fmt, ...);
+int check_hip(hipError_t e, const char *what);
+int make_dev_grid(const dvgo_grid *g, const char *name, DevGrid *out, bool need_grad);
+
+// checkpoint slot of the chunk starting at sample c0 of ray r (rays own disjoint slot ranges)
+__host__ __device__ __forceinline__ int64_t ckpt_slot(int64_t beg, int r, int64_t c0) {
+    return beg / 64 + r + (c0 - beg) / 64;
+}
+__host__ __device__ __forceinline__ int64_t ckpt_count(int32_t n_rays, int64_t n_samples) {
+    return n_samples / 64 + n_rays + 1;
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace dvgo

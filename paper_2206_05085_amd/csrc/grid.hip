@@ -1,0 +1,329 @@
+// Grid gather/scatter, alpha, fused Adam, loss head and the host-side plumbing of libdvgo.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include "dvgo_internal.h"
+
+namespace dvgo {
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what) {
+    if (e == hipSuccess) return DVGO_OK;
+    return set_error(DVGO_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int make_dev_grid(const dvgo_grid *g, const char *name, DevGrid *out, bool need_grad) {
+    if (!g) return set_error(DVGO_ERR_NULL, "%s grid is NULL", name);
+    if (g->struct_size != sizeof(dvgo_grid)) return set_error(DVGO_ERR_ABI, "%s: dvgo_grid.struct_size mismatch", name);
+    if (g->nx < 2 || g->ny < 2 || g->nz < 2) return set_error(DVGO_ERR_SHAPE, "%s: every grid dimension must be >= 2", name);
+    if (g->channels < 1 || g->ch_stride < g->channels || g->ch_stride > 16)
+        return set_error(DVGO_ERR_SHAPE, "%s: need 1 <= channels <= ch_stride <= 16", name);
+    const int64_t total = (int64_t)g->nx * g->ny * g->nz * g->ch_stride;
+    if (total >= ((int64_t)1 << 31)) return set_error(DVGO_ERR_RANGE, "%s: grid has >= 2^31 floats", name);
+    if (!g->data) return set_error(DVGO_ERR_NULL, "%s: data is NULL", name);
+    if (need_grad && !g->grad) return set_error(DVGO_ERR_NULL, "%s: grad is NULL", name);
+    out->data = g->data;
+    out->grad = g->grad;
+    out->n[0] = g->nx;
+    out->n[1] = g->ny;
+    out->n[2] = g->nz;
+    out->cs = g->ch_stride;
+    out->C = g->channels;
+    out->sy = g->nz * g->ch_stride;
+    out->sx = g->ny * out->sy;
+    for (int a = 0; a < 3; ++a) {
+        const double lo = g->xyz_min[a], hi = g->xyz_max[a];
+        if (!(hi > lo)) return set_error(DVGO_ERR_SHAPE, "%s: xyz_max must exceed xyz_min", name);
+        const double s = (double)(out->n[a] - 1) / (hi - lo);
+        const double o = -lo * s;
+        out->s_hi[a] = (float)s;
+        out->s_lo[a] = (float)(s - (double)out->s_hi[a]);
+        out->o_hi[a] = (float)o;
+        out->o_lo[a] = (float)(o - (double)out->o_hi[a]);
+    }
+    return DVGO_OK;
+}
+
+}  // namespace dvgo
+
+using namespace dvgo;
+
+namespace {
+
+constexpr int kBlock = 256;
+
+int grid_blocks(int64_t work, int per_block = kBlock) {
+    int64_t b = (work + per_block - 1) / per_block;
+    if (b > 65535 * 16) b = 65535 * 16;
+    return (int)(b < 1 ? 1 : b);
+}
+
+__global__ __launch_bounds__(kBlock) void gather_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
+                                                        float *__restrict__ out) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < S; k += (int64_t)gridDim.x * kBlock) {
+        const Tri t = trilinear(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+        float acc[16];
+#pragma unroll
+        for (int ch = 0; ch < 16; ++ch) acc[ch] = 0.f;
+        if ((g.cs & 3) == 0) {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float4 *p = reinterpret_cast<const float4 *>(g.data + t.base + corner_off(g, c));
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (4 * q < g.C) {
+                        const float4 v = p[q];
+                        acc[4 * q] += t.w[c] * v.x;
+                        acc[4 * q + 1] += t.w[c] * v.y;
+                        acc[4 * q + 2] += t.w[c] * v.z;
+                        acc[4 * q + 3] += t.w[c] * v.w;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const float *p = g.data + t.base + corner_off(g, c);
+#pragma unroll
+                for (int ch = 0; ch < 16; ++ch)
+                    if (ch < g.C) acc[ch] += t.w[c] * p[ch];
+            }
+        }
+#pragma unroll
+        for (int ch = 0; ch < 16; ++ch)
+            if (ch < g.C) out[k * g.C + ch] = acc[ch];
+    }
+}
+
+// One lane per sample, 64 consecutive samples per wave: consecutive samples lie along a
+// ray, so contributions to shared vertices are summed in the wave before the atomics.
+template <int NC>
+__global__ __launch_bounds__(kBlock) void scatter_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
+                                                         const float *__restrict__ gout) {
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
+    for (int64_t base = wave * 64; base < S; base += nwaves * 64) {
+        const int64_t k = base + lane();
+        const bool valid = k < S;
+        Cell cl{0, 0, 0, 0.f, 0.f, 0.f};
+        float v[NC];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) v[ch] = 0.f;
+        if (valid) {
+            cl = cell_of(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch)
+                if (ch < g.C) v[ch] = gout[k * g.C + ch];
+        }
+        scatter_wave<NC>(g, valid, cl, v, g.C);
+    }
+}
+
+template <int NC>
+void launch_scatter(const DevGrid &dg, int64_t S, const float *xyz, const float *gout, hipStream_t st) {
+    int64_t waves = (S + 63) / 64;
+    int64_t blocks = (waves + 3) / 4;
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    hipLaunchKernelGGL(scatter_kernel<NC>, dim3((unsigned)blocks), dim3(kBlock), scatter_lds_bytes(NC, kBlock), st, dg,
+                       S, xyz, gout);
+}
+
+__global__ __launch_bounds__(kBlock) void alpha_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
+                                                       const float *__restrict__ delta, float shift,
+                                                       float *__restrict__ alpha) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < S; k += (int64_t)gridDim.x * kBlock) {
+        const Tri t = trilinear(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+        const float raw = interp_ch(g, t, 0);
+        alpha[k] = -expm1f(-softplusf(raw + shift) * delta[k]);
+    }
+}
+
+struct AdamArgs {
+    float *p, *g, *m, *v;
+    int64_t n;
+    float lr_t;          // lr / (1 - beta1^t)
+    float inv_sqrt_bc2;  // 1 / sqrt(1 - beta2^t)
+    float b1, b2, eps;
+    int skip, zero;
+};
+
+__device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, float &m, float &v) {
+    m = a.b1 * m + (1.f - a.b1) * g;
+    v = a.b2 * v + (1.f - a.b2) * (g * g);
+    p -= a.lr_t * m / (sqrtf(v) * a.inv_sqrt_bc2 + a.eps);
+}
+
+// Streams the four arrays as float4 (the 16-byte-aligned body) with a scalar head/tail.
+// With skip, a float4 group whose four gradients are all zero is not read further and
+// nothing is written; within a partly non-zero group the zero-gradient lanes keep their
+// values bit for bit.
+__global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, int64_t n4) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t tid = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    float4 *P = reinterpret_cast<float4 *>(a.p + head), *G = reinterpret_cast<float4 *>(a.g + head);
+    float4 *M = reinterpret_cast<float4 *>(a.m + head), *V = reinterpret_cast<float4 *>(a.v + head);
+    for (int64_t i = tid; i < n4; i += stride) {
+        const float4 g = G[i];
+        const bool nz[4] = {g.x != 0.f, g.y != 0.f, g.z != 0.f, g.w != 0.f};
+        if (a.skip && !(nz[0] | nz[1] | nz[2] | nz[3])) continue;
+        float4 p = P[i], m = M[i], v = V[i];
+        if (!a.skip || nz[0]) adam_one(a, g.x, p.x, m.x, v.x);
+        if (!a.skip || nz[1]) adam_one(a, g.y, p.y, m.y, v.y);
+        if (!a.skip || nz[2]) adam_one(a, g.z, p.z, m.z, v.z);
+        if (!a.skip || nz[3]) adam_one(a, g.w, p.w, m.w, v.w);
+        P[i] = p;
+        M[i] = m;
+        V[i] = v;
+        if (a.zero) G[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    // scalar head [0, head) and tail [head + 4 n4, n)
+    const int64_t tail0 = head + 4 * n4;
+    const int64_t nscalar = head + (a.n - tail0);
+    for (int64_t j = tid; j < nscalar; j += stride) {
+        const int64_t i = j < head ? j : tail0 + (j - head);
+        const float g = a.g[i];
+        if (a.skip && g == 0.f) continue;
+        adam_one(a, g, a.p[i], a.m[i], a.v[i]);
+        if (a.zero) a.g[i] = 0.f;
+    }
+}
+
+// single block: the loss is written (not accumulated), so no pre-zeroed scalar is needed
+__global__ __launch_bounds__(1024) void loss_head_kernel(int R, const float *__restrict__ rgb,
+                                                         const float *__restrict__ tgt, const float *__restrict__ dist,
+                                                         float lam, float *loss, float *grad_rgb, float *grad_dist) {
+    __shared__ float red[16];
+    float acc = 0.f;
+    const float inv3R = 1.f / (3.f * (float)R), invR = 1.f / (float)R;
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        float e2 = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float e = rgb[3 * r + ch] - tgt[3 * r + ch];
+            e2 += e * e;
+            if (grad_rgb) grad_rgb[3 * r + ch] = 2.f * e * inv3R;
+        }
+        acc += e2 * inv3R;
+        if (dist) acc += lam * dist[r] * invR;
+        if (grad_dist) grad_dist[r] = lam * invR;
+    }
+    acc = wave_sum(acc);
+    if (lane() == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        float v = threadIdx.x < (blockDim.x >> 6) ? red[threadIdx.x] : 0.f;
+        v = wave_sum(v);
+        if (threadIdx.x == 0 && loss) loss[0] = v;
+    }
+}
+
+}  // namespace
+
+extern "C" int dvgo_abi_version(void) { return DVGO_ABI_VERSION; }
+
+extern "C" const char *dvgo_last_error(void) { return g_err; }
+
+extern "C" int dvgo_grid_gather(const dvgo_grid *g, int64_t n_samples, const float *xyz, float *out, void *stream) {
+    DevGrid dg;
+    int rc = make_dev_grid(g, "grid", &dg, false);
+    if (rc) return rc;
+    if (n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_samples");
+    if (n_samples == 0) return DVGO_OK;
+    if (!xyz || !out) return set_error(DVGO_ERR_NULL, "xyz or out is NULL");
+    if ((g->ch_stride & 3) == 0 && ((uintptr_t)g->data & 15))
+        return set_error(DVGO_ERR_SHAPE, "grid data must be 16-byte aligned when ch_stride is a multiple of 4");
+    hipLaunchKernelGGL(gather_kernel, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream, dg,
+                       n_samples, xyz, out);
+    return check_hip(hipGetLastError(), "gather_kernel launch");
+}
+
+extern "C" int dvgo_grid_scatter(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
+                                 void *stream) {
+    DevGrid dg;
+    int rc = make_dev_grid(g, "grid", &dg, true);
+    if (rc) return rc;
+    if (n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_samples");
+    if (n_samples == 0) return DVGO_OK;
+    if (!xyz || !grad_out) return set_error(DVGO_ERR_NULL, "xyz or grad_out is NULL");
+    const hipStream_t st = (hipStream_t)stream;
+    const int C = g->channels;
+    if (C == 1) launch_scatter<1>(dg, n_samples, xyz, grad_out, st);
+    else if (C <= 3) launch_scatter<3>(dg, n_samples, xyz, grad_out, st);
+    else if (C <= 4) launch_scatter<4>(dg, n_samples, xyz, grad_out, st);
+    else if (C <= 8) launch_scatter<8>(dg, n_samples, xyz, grad_out, st);
+    else if (C <= 12) launch_scatter<12>(dg, n_samples, xyz, grad_out, st);
+    else launch_scatter<16>(dg, n_samples, xyz, grad_out, st);
+    return check_hip(hipGetLastError(), "scatter_kernel launch");
+}
+
+extern "C" int dvgo_alpha(const dvgo_grid *density, int64_t n_samples, const float *xyz, const float *delta,
+                          float act_shift, float *alpha, void *stream) {
+    DevGrid dg;
+    int rc = make_dev_grid(density, "density", &dg, false);
+    if (rc) return rc;
+    if (n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_samples");
+    if (n_samples == 0) return DVGO_OK;
+    if (!xyz || !delta || !alpha) return set_error(DVGO_ERR_NULL, "xyz, delta or alpha is NULL");
+    hipLaunchKernelGGL(alpha_kernel, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream, dg,
+                       n_samples, xyz, delta, act_shift, alpha);
+    return check_hip(hipGetLastError(), "alpha_kernel launch");
+}
+
+extern "C" int dvgo_grid_adam_step(float *param, float *grad, float *exp_avg, float *exp_avg_sq, int64_t n,
+                                   float lr, float beta1, float beta2, float eps, int32_t step,
+                                   int32_t skip_zero_grad, int32_t zero_grad_after, void *stream) {
+    if (n < 0) return set_error(DVGO_ERR_SHAPE, "negative n");
+    if (n == 0) return DVGO_OK;
+    if (!param || !grad || !exp_avg || !exp_avg_sq) return set_error(DVGO_ERR_NULL, "an Adam array is NULL");
+    if (step < 1) return set_error(DVGO_ERR_RANGE, "step is 1-based");
+    if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
+        return set_error(DVGO_ERR_RANGE, "betas must be in [0, 1)");
+    const uintptr_t al = (uintptr_t)param & 15;
+    if (((uintptr_t)grad & 15) != al || ((uintptr_t)exp_avg & 15) != al || ((uintptr_t)exp_avg_sq & 15) != al ||
+        (al & 3))
+        return set_error(DVGO_ERR_SHAPE, "param, grad and moments must share their 16-byte alignment");
+    AdamArgs a;
+    a.p = param;
+    a.g = grad;
+    a.m = exp_avg;
+    a.v = exp_avg_sq;
+    a.n = n;
+    const double bc1 = 1.0 - pow((double)beta1, step), bc2 = 1.0 - pow((double)beta2, step);
+    a.lr_t = (float)((double)lr / bc1);
+    a.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+    a.b1 = beta1;
+    a.b2 = beta2;
+    a.eps = eps;
+    a.skip = skip_zero_grad != 0;
+    a.zero = zero_grad_after != 0;
+    int64_t head = al ? (int64_t)((16 - al) / 4) : 0;
+    if (head > n) head = n;
+    const int64_t n4 = (n - head) / 4;
+    const int blocks = grid_blocks(n4 > 0 ? n4 : n, kBlock);
+    const int cap = 256 * 8;  // a few waves per CU; each thread streams many float4 groups
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks < cap ? blocks : cap), dim3(kBlock), 0, (hipStream_t)stream, a, head,
+                       n4);
+    return check_hip(hipGetLastError(), "adam_kernel launch");
+}
+
+extern "C" int dvgo_loss_head(int32_t n_rays, const float *rgb, const float *target, const float *dist,
+                              float dist_weight, float *loss, float *grad_rgb, float *grad_dist, void *stream) {
+    if (n_rays < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays");
+    if (n_rays == 0) return DVGO_OK;
+    if (!rgb || !target) return set_error(DVGO_ERR_NULL, "rgb or target is NULL");
+    if (!loss && !grad_rgb && !grad_dist) return set_error(DVGO_ERR_NULL, "no output requested");
+    hipLaunchKernelGGL(loss_head_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, n_rays, rgb, target, dist,
+                       dist_weight, loss, grad_rgb, grad_dist);
+    return check_hip(hipGetLastError(), "loss_head_kernel launch");
+}

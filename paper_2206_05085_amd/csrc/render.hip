@@ -1,0 +1,408 @@
+// Volume rendering forward/backward and the O(N) distortion loss on ragged rays (gfx950).
+//
+// One wavefront owns one ray and walks it in chunks of 64 samples (one sample per lane).
+// Within a chunk every prefix quantity is a wave64 scan; across chunks a carry is kept.
+//   forward : log-transmittance L (exclusive scan of sigma*delta), the weight prefix W,
+//             and the distortion prefix Q; colour and distortion are reduced per lane.
+//   backward: chunks are visited last-to-first.  Prefix state is restored from a per-chunk
+//             checkpoint (L, W, Q) written by the forward, suffix state (sum of later
+//             weights, Q', and the sum of later g*w) is carried from the chunk after.
+//
+// Distortion (section 2).  Eq. 1's first term equals 2 sum_i w_i Q_i with
+//   Q_i = sum_{j<i} w_j (m_i - m_j),  Q_{i+1} = Q_i + W_{<=i} (m_{i+1} - m_i),
+// which is Eq. 2's prefix-sum rewrite arranged so that every added term is non-negative
+// (midpoints are sorted), i.e. free of the cancellation between m_i P_i and PM_i that the
+// literal form of Eq. 2 suffers in float32.  Its derivative (Eq. 3, plus the derivative of
+// the second term of Eq. 1) is
+//   dD/dw_k = 2 (Q_k + Q'_k) + (2/3) w_k l_k,   Q'_k = sum_{i>k} w_i (m_i - m_k),
+// with the suffix recurrence Q'_k = Q'_{k+1} + (m_{k+1} - m_k) W_{>k}.
+//
+// Compositing backward.  With g_k = dL/dC . c_k + dL/dD dD/dw_k:
+//   dL/dx_k = T_{k+1} g_k - S_k,   S_k = sum_{i>k} g_i w_i + (dL/dC . bg + dL/dT_N) T_N,
+//   dL/draw_k = dL/dx_k * delta_k * sigmoid(raw_k + b),   dL/dc_k = w_k dL/dC.
+#include <stdio.h>
+#include <string.h>
+
+#include "dvgo_internal.h"
+
+using namespace dvgo;
+
+namespace {
+
+struct RenderArgs {
+    int n_rays;
+    const int *offs;
+    const float *xyz, *delta, *s_mid, *s_len;
+    DevGrid dens, col;
+    const float *srgb;
+    float act_shift, halt_T, bg0, bg1, bg2;
+    int want_dist;
+    // forward outputs / saved state
+    float *rgb, *T_final, *dist;
+    int *halt_idx;
+    float4 *ckpt;
+    // backward
+    const float *T_in, *grad_rgb, *grad_dist, *grad_T;
+    float *grad_srgb;
+};
+
+struct SampleIn {
+    float raw, c0, c1, c2, x, alpha, m, mn, l, delta;
+    Cell cd, cc;  // cells of the density and colour grids
+};
+
+__device__ __forceinline__ void zero_sample(SampleIn &s) {
+    s.x = s.alpha = s.m = s.mn = s.l = s.c0 = s.c1 = s.c2 = s.delta = s.raw = 0.f;
+    s.cd = Cell{0, 0, 0, 0.f, 0.f, 0.f};
+    s.cc = s.cd;
+}
+
+template <int MODE>
+__device__ __forceinline__ void load_sample(const RenderArgs &a, int k, bool has_next, SampleIn &s) {
+    const float px = a.xyz[3 * k], py = a.xyz[3 * k + 1], pz = a.xyz[3 * k + 2];
+    s.cd = cell_of(a.dens, px, py, pz);
+    s.raw = interp_ch(a.dens, tri_from_cell(a.dens, s.cd), 0);
+    if (MODE == DVGO_COLOR_GRID) {
+        s.cc = cell_of(a.col, px, py, pz);
+        const Tri tc = tri_from_cell(a.col, s.cc);
+        s.c0 = interp_ch(a.col, tc, 0);
+        s.c1 = interp_ch(a.col, tc, 1);
+        s.c2 = interp_ch(a.col, tc, 2);
+    } else {
+        s.c0 = a.srgb[3 * k];
+        s.c1 = a.srgb[3 * k + 1];
+        s.c2 = a.srgb[3 * k + 2];
+    }
+    s.delta = a.delta[k];
+    s.x = softplusf(s.raw + a.act_shift) * s.delta;
+    s.alpha = -expm1f(-s.x);
+    s.m = a.s_mid[k];
+    s.l = a.s_len[k];
+    s.mn = has_next ? a.s_mid[k + 1] : 0.f;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= a.n_rays) return;
+    const int ln = lane();
+    const int beg = a.offs[r], end = a.offs[r + 1];
+    float L = 0.f, W = 0.f, Q = 0.f;
+    float accC0 = 0.f, accC1 = 0.f, accC2 = 0.f, accD = 0.f;
+    int halt = end;
+    float T_halt = 1.f;
+    int64_t ck = ckpt_slot(beg, r, beg);
+    for (int c0 = beg; c0 < end; c0 += 64, ++ck) {
+        if (ln == 0) a.ckpt[ck] = make_float4(L, W, Q, 0.f);
+        const int k = c0 + ln;
+        const bool valid = k < end;
+        const bool has_next = k + 1 < end;
+        SampleIn s;
+        if (valid) load_sample<MODE>(a, k, has_next, s);
+        else zero_sample(s);
+        const float xi = wave_incl(s.x);
+        const float T = expf(-(L + wave_excl(xi)));
+        if (a.halt_T > 0.f) {
+            const unsigned long long hm = __ballot(valid && T < a.halt_T);
+            if (hm) {
+                const int f = __ffsll(hm) - 1;
+                halt = c0 + f;
+                T_halt = bcast(T, f);
+            }
+        }
+        const bool live = valid && k < halt;
+        const float w = live ? T * s.alpha : 0.f;
+        const float wi = wave_incl(w);
+        const float u = (live && has_next) ? (W + wi) * (s.mn - s.m) : 0.f;
+        const float ui = wave_incl(u);
+        const float Qk = Q + wave_excl(ui);
+        accD += w * (2.f * Qk + w * s.l * (1.f / 3.f));
+        accC0 += w * s.c0;
+        accC1 += w * s.c1;
+        accC2 += w * s.c2;
+        L += bcast(xi, 63);
+        W += bcast(wi, 63);
+        Q += bcast(ui, 63);
+        if (halt < end) break;
+    }
+    accC0 = wave_sum(accC0);
+    accC1 = wave_sum(accC1);
+    accC2 = wave_sum(accC2);
+    accD = wave_sum(accD);
+    if (ln == 0) {
+        const float TN = halt < end ? T_halt : expf(-L);
+        a.rgb[3 * r] = accC0 + TN * a.bg0;
+        a.rgb[3 * r + 1] = accC1 + TN * a.bg1;
+        a.rgb[3 * r + 2] = accC2 + TN * a.bg2;
+        a.T_final[r] = TN;
+        if (a.want_dist) a.dist[r] = accD;
+        a.halt_idx[r] = halt;
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= a.n_rays) return;
+    const int ln = lane();
+    const int beg = a.offs[r], end = a.offs[r + 1];
+    const int hend = a.halt_idx[r];
+    const float g0 = a.grad_rgb[3 * r], g1 = a.grad_rgb[3 * r + 1], g2 = a.grad_rgb[3 * r + 2];
+    const float gD = a.grad_dist ? a.grad_dist[r] : 0.f;
+    const float gT = a.grad_T ? a.grad_T[r] : 0.f;
+    float Scar = (g0 * a.bg0 + g1 * a.bg1 + g2 * a.bg2 + gT) * a.T_in[r];
+    float Wgt = 0.f, Qp = 0.f;
+    if (MODE == DVGO_COLOR_SAMPLES) {
+        for (int k = hend + ln; k < end; k += 64) {
+            a.grad_srgb[3 * k] = 0.f;
+            a.grad_srgb[3 * k + 1] = 0.f;
+            a.grad_srgb[3 * k + 2] = 0.f;
+        }
+    }
+    if (hend <= beg) return;
+    const int nch = (hend - beg + 63) / 64;
+    const float b = a.act_shift;
+    for (int ci = nch - 1; ci >= 0; --ci) {
+        const int c0 = beg + ci * 64;
+        const float4 cp = a.ckpt[ckpt_slot(beg, r, c0)];
+        const int k = c0 + ln;
+        const bool valid = k < hend;
+        const bool has_next = k + 1 < hend;
+        SampleIn s;
+        if (valid) load_sample<MODE>(a, k, has_next, s);
+        else zero_sample(s);
+        const float xi = wave_incl(s.x);
+        const float T = expf(-(cp.x + wave_excl(xi)));
+        const float Tn = expf(-(cp.x + xi));
+        const float w = valid ? T * s.alpha : 0.f;
+        const float wi = wave_incl(w);
+        const float u = (valid && has_next) ? (cp.y + wi) * (s.mn - s.m) : 0.f;
+        const float Qk = cp.z + wave_excl(wave_incl(u));
+        const float wr = wave_incl_rev(w);
+        const float wgt = Wgt + wave_excl_rev(wr);
+        const float v = (valid && has_next) ? (s.mn - s.m) * wgt : 0.f;
+        const float Qpk = Qp + wave_incl_rev(v);
+        float g = g0 * s.c0 + g1 * s.c1 + g2 * s.c2;
+        if (gD != 0.f) g += gD * (2.f * (Qk + Qpk) + (2.f / 3.f) * w * s.l);
+        const float gwr = wave_incl_rev(g * w);
+        const float Sk = Scar + wave_excl_rev(gwr);
+        const float draw = valid ? (Tn * g - Sk) * s.delta * sigmoidf(s.raw + b) : 0.f;
+        const float dd[1] = {draw};
+        scatter_wave<1>(a.dens, valid, s.cd, dd);
+        if (MODE == DVGO_COLOR_GRID) {
+            const float dc[3] = {w * g0, w * g1, w * g2};
+            scatter_wave<3>(a.col, valid, s.cc, dc);
+        } else if (valid) {
+            a.grad_srgb[3 * k] = w * g0;
+            a.grad_srgb[3 * k + 1] = w * g1;
+            a.grad_srgb[3 * k + 2] = w * g2;
+        }
+        Wgt += bcast(wr, 0);
+        Qp = bcast(Qpk, 0);
+        Scar += bcast(gwr, 0);
+    }
+}
+
+// Standalone distortion loss on given weights; forward sweep, then (if requested) a
+// reverse sweep that reads the chunk checkpoints this same wave wrote.
+__global__ __launch_bounds__(256) void distortion_kernel(int n_rays, const int *offs, const float *wv,
+                                                         const float *mv, const float *lv, float *loss,
+                                                         const float *gl, float *gw, float2 *ckpt) {
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= n_rays) return;
+    const int ln = lane();
+    const int beg = offs[r], end = offs[r + 1];
+    const bool bwd = gw != nullptr;
+    float W = 0.f, Q = 0.f, accD = 0.f;
+    int64_t ck = ckpt_slot(beg, r, beg);
+    for (int c0 = beg; c0 < end; c0 += 64, ++ck) {
+        if (bwd && ln == 0) ckpt[ck] = make_float2(W, Q);
+        const int k = c0 + ln;
+        const bool valid = k < end, has_next = k + 1 < end;
+        const float w = valid ? wv[k] : 0.f;
+        const float m = valid ? mv[k] : 0.f;
+        const float mn = has_next ? mv[k + 1] : 0.f;
+        const float l = valid ? lv[k] : 0.f;
+        const float wi = wave_incl(w);
+        const float u = has_next ? (W + wi) * (mn - m) : 0.f;
+        const float ui = wave_incl(u);
+        const float Qk = Q + wave_excl(ui);
+        accD += w * (2.f * Qk + w * l * (1.f / 3.f));
+        W += bcast(wi, 63);
+        Q += bcast(ui, 63);
+    }
+    accD = wave_sum(accD);
+    if (loss && ln == 0) loss[r] = accD;
+    if (!bwd || end <= beg) return;
+    __threadfence_block();
+    const float gD = gl[r];
+    float Wgt = 0.f, Qp = 0.f;
+    const int nch = (end - beg + 63) / 64;
+    for (int ci = nch - 1; ci >= 0; --ci) {
+        const int c0 = beg + ci * 64;
+        const float2 cp = ckpt[ckpt_slot(beg, r, c0)];
+        const int k = c0 + ln;
+        const bool valid = k < end, has_next = k + 1 < end;
+        const float w = valid ? wv[k] : 0.f;
+        const float m = valid ? mv[k] : 0.f;
+        const float mn = has_next ? mv[k + 1] : 0.f;
+        const float l = valid ? lv[k] : 0.f;
+        const float wi = wave_incl(w);
+        const float u = has_next ? (cp.x + wi) * (mn - m) : 0.f;
+        const float Qk = cp.y + wave_excl(wave_incl(u));
+        const float wr = wave_incl_rev(w);
+        const float wgt = Wgt + wave_excl_rev(wr);  // every lane must join the shuffle
+        const float v = has_next ? (mn - m) * wgt : 0.f;
+        const float Qpk = Qp + wave_incl_rev(v);
+        if (valid) gw[k] += gD * (2.f * (Qk + Qpk) + (2.f / 3.f) * w * l);
+        Wgt += bcast(wr, 0);
+        Qp = bcast(Qpk, 0);
+    }
+}
+
+int check_samples(const dvgo_samples *s) {
+    if (!s) return set_error(DVGO_ERR_NULL, "samples is NULL");
+    if (s->struct_size != sizeof(dvgo_samples)) return set_error(DVGO_ERR_ABI, "dvgo_samples.struct_size mismatch");
+    if (s->n_rays < 0 || s->n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays or n_samples");
+    if (s->n_samples >= (int64_t)1 << 31) return set_error(DVGO_ERR_RANGE, "n_samples must be < 2^31");
+    if (!s->ray_offsets) return set_error(DVGO_ERR_NULL, "ray_offsets is NULL");
+    if (s->n_samples > 0 && (!s->xyz || !s->delta || !s->s_mid || !s->s_len))
+        return set_error(DVGO_ERR_NULL, "a per-sample array is NULL");
+    return DVGO_OK;
+}
+
+int fill_render_args(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                     const dvgo_grid *color, const float *sample_rgb, bool bwd, RenderArgs &a) {
+    if (!p) return set_error(DVGO_ERR_NULL, "params is NULL");
+    if (p->struct_size != sizeof(dvgo_render_params))
+        return set_error(DVGO_ERR_ABI, "dvgo_render_params.struct_size mismatch");
+    int rc = check_samples(s);
+    if (rc) return rc;
+    if (p->color_mode != DVGO_COLOR_GRID && p->color_mode != DVGO_COLOR_SAMPLES)
+        return set_error(DVGO_ERR_UNSUPPORTED, "unknown color_mode %d", p->color_mode);
+    if (!(p->halt_T >= 0.f && p->halt_T < 1.f)) return set_error(DVGO_ERR_RANGE, "halt_T must be in [0, 1)");
+    memset(&a, 0, sizeof(a));
+    rc = make_dev_grid(density, "density", &a.dens, bwd);
+    if (rc) return rc;
+    if (p->color_mode == DVGO_COLOR_GRID) {
+        if (!color) return set_error(DVGO_ERR_NULL, "color grid is NULL in DVGO_COLOR_GRID mode");
+        rc = make_dev_grid(color, "color", &a.col, bwd);
+        if (rc) return rc;
+        if (color->channels < 3) return set_error(DVGO_ERR_SHAPE, "color grid needs 3 channels");
+    } else if (s->n_samples > 0 && !sample_rgb) {
+        return set_error(DVGO_ERR_NULL, "sample_rgb is NULL in DVGO_COLOR_SAMPLES mode");
+    }
+    a.n_rays = s->n_rays;
+    a.offs = s->ray_offsets;
+    a.xyz = s->xyz;
+    a.delta = s->delta;
+    a.s_mid = s->s_mid;
+    a.s_len = s->s_len;
+    a.srgb = sample_rgb;
+    a.act_shift = p->act_shift;
+    a.halt_T = p->halt_T;
+    a.bg0 = p->bg[0];
+    a.bg1 = p->bg[1];
+    a.bg2 = p->bg[2];
+    a.want_dist = p->want_dist != 0;
+    return DVGO_OK;
+}
+
+size_t state_bytes(int32_t n_rays, int64_t n_samples) {
+    return align_up((size_t)n_rays * 4, 256) + (size_t)ckpt_count(n_rays, n_samples) * sizeof(float4);
+}
+
+void split_state(void *state, int32_t n_rays, int **halt, float4 **ck) {
+    *halt = (int *)state;
+    *ck = (float4 *)((char *)state + align_up((size_t)n_rays * 4, 256));
+}
+
+}  // namespace
+
+extern "C" int dvgo_render_state_size(int32_t n_rays, int64_t n_samples, size_t *bytes) {
+    if (!bytes) return set_error(DVGO_ERR_NULL, "bytes is NULL");
+    if (n_rays < 0 || n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative size");
+    *bytes = state_bytes(n_rays, n_samples);
+    return DVGO_OK;
+}
+
+extern "C" int dvgo_render_forward(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                                   const dvgo_grid *color, const float *sample_rgb, float *rgb, float *T_final,
+                                   float *dist, void *state, size_t state_bytes_, void *stream) {
+    RenderArgs a;
+    int rc = fill_render_args(p, s, density, color, sample_rgb, false, a);
+    if (rc) return rc;
+    if (s->n_rays == 0) return DVGO_OK;
+    if (!rgb || !T_final || !state) return set_error(DVGO_ERR_NULL, "rgb, T_final or state is NULL");
+    if (p->want_dist && !dist) return set_error(DVGO_ERR_NULL, "dist is NULL with want_dist");
+    if (state_bytes_ < state_bytes(s->n_rays, s->n_samples))
+        return set_error(DVGO_ERR_WORKSPACE, "state buffer too small (%zu < %zu)", state_bytes_,
+                         state_bytes(s->n_rays, s->n_samples));
+    a.rgb = rgb;
+    a.T_final = T_final;
+    a.dist = dist;
+    split_state(state, s->n_rays, &a.halt_idx, &a.ckpt);
+    const dim3 grid((s->n_rays + 3) / 4), block(256);
+    if (p->color_mode == DVGO_COLOR_GRID)
+        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_GRID>, grid, block, 0, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_SAMPLES>, grid, block, 0, (hipStream_t)stream, a);
+    return check_hip(hipGetLastError(), "render_fwd_kernel launch");
+}
+
+extern "C" int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                                    const dvgo_grid *color, const float *sample_rgb, const float *T_final,
+                                    const void *state, size_t state_bytes_, const float *grad_rgb,
+                                    const float *grad_dist, const float *grad_T, float *grad_sample_rgb,
+                                    void *stream) {
+    RenderArgs a;
+    int rc = fill_render_args(p, s, density, color, sample_rgb, true, a);
+    if (rc) return rc;
+    if (s->n_rays == 0) return DVGO_OK;
+    if (!T_final || !state || !grad_rgb) return set_error(DVGO_ERR_NULL, "T_final, state or grad_rgb is NULL");
+    if (p->color_mode == DVGO_COLOR_SAMPLES && s->n_samples > 0 && !grad_sample_rgb)
+        return set_error(DVGO_ERR_NULL, "grad_sample_rgb is NULL in DVGO_COLOR_SAMPLES mode");
+    if (state_bytes_ < state_bytes(s->n_rays, s->n_samples))
+        return set_error(DVGO_ERR_WORKSPACE, "state buffer too small");
+    a.T_in = T_final;
+    a.grad_rgb = grad_rgb;
+    a.grad_dist = p->want_dist ? grad_dist : nullptr;
+    a.grad_T = grad_T;
+    a.grad_srgb = grad_sample_rgb;
+    split_state(const_cast<void *>(state), s->n_rays, &a.halt_idx, &a.ckpt);
+    const dim3 grid((s->n_rays + 3) / 4), block(256);
+    if (p->color_mode == DVGO_COLOR_GRID)
+        hipLaunchKernelGGL(render_bwd_kernel<DVGO_COLOR_GRID>, grid, block, scatter_lds_bytes(3, 256),
+                           (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(render_bwd_kernel<DVGO_COLOR_SAMPLES>, grid, block, 0, (hipStream_t)stream, a);
+    return check_hip(hipGetLastError(), "render_bwd_kernel launch");
+}
+
+extern "C" int dvgo_distortion_workspace_size(int32_t n_rays, int64_t n_samples, size_t *bytes) {
+    if (!bytes) return set_error(DVGO_ERR_NULL, "bytes is NULL");
+    if (n_rays < 0 || n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative size");
+    *bytes = (size_t)ckpt_count(n_rays, n_samples) * sizeof(float2);
+    return DVGO_OK;
+}
+
+extern "C" int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w,
+                                    const float *s_mid, const float *s_len, float *loss, const float *grad_loss,
+                                    float *grad_w, void *ws, size_t ws_bytes, void *stream) {
+    if (n_rays < 0 || n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays or n_samples");
+    if (n_samples >= (int64_t)1 << 31) return set_error(DVGO_ERR_RANGE, "n_samples must be < 2^31");
+    if (n_rays == 0) return DVGO_OK;
+    if (!ray_offsets) return set_error(DVGO_ERR_NULL, "ray_offsets is NULL");
+    if (n_samples > 0 && (!w || !s_mid || !s_len)) return set_error(DVGO_ERR_NULL, "w, s_mid or s_len is NULL");
+    const bool bwd = grad_loss && grad_w;
+    if (!loss && !bwd) return set_error(DVGO_ERR_NULL, "nothing to compute: loss and grad_w are NULL");
+    if ((grad_loss == nullptr) != (grad_w == nullptr))
+        return set_error(DVGO_ERR_NULL, "grad_loss and grad_w must both be given for the backward");
+    size_t need = (size_t)ckpt_count(n_rays, n_samples) * sizeof(float2);
+    if (bwd && (!ws || ws_bytes < need)) return set_error(DVGO_ERR_WORKSPACE, "workspace too small (%zu < %zu)",
+                                                           ws_bytes, need);
+    const dim3 grid((n_rays + 3) / 4), block(256);
+    hipLaunchKernelGGL(distortion_kernel, grid, block, 0, (hipStream_t)stream, n_rays, ray_offsets, w, s_mid, s_len,
+                       loss, bwd ? grad_loss : nullptr, bwd ? grad_w : nullptr, (float2 *)ws);
+    return check_hip(hipGetLastError(), "distortion_kernel launch");
+}

@@ -1,0 +1,336 @@
+"""Thin Python binding of libdvgo: one function per C entry point, same names without the
+``dvgo_`` prefix.  These functions only check and marshal arguments (torch CUDA tensors ->
+device pointers, the current HIP stream); all arithmetic runs in the HIP kernels.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import COLOR_GRID, COLOR_SAMPLES, ColorMLP, Grid, RenderParams, Samples, call
+
+__all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "render_state_size", "render_forward",
+           "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "grid_gather",
+           "grid_scatter", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
+           "COLOR_GRID", "COLOR_SAMPLES"]
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _chk(t, name, dtype=torch.float32, numel=None, last=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live on the GPU (libdvgo has no CPU path)")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    if last is not None and (t.dim() == 0 or t.shape[-1] != last):
+        raise ValueError(f"{name} must have last dimension {last}")
+    return t
+
+
+def act_shift(alpha_init: float = 1e-4, delta_ref: float = 0.5) -> float:
+    """Shift b of sigma = softplus(raw + b) such that raw = 0 gives alpha_init at a step of
+    delta_ref voxels (the initial-alpha setting of section 5.4)."""
+    return math.log(math.expm1(-math.log1p(-alpha_init) / delta_ref))
+
+
+@dataclass
+class SampleBatch:
+    """A ragged sample batch resident on the GPU (see dvgo_samples in include/dvgo.h)."""
+    ray_offsets: torch.Tensor  # int32 [R+1]
+    xyz: torch.Tensor          # [S,3]
+    delta: torch.Tensor        # [S]
+    s_mid: torch.Tensor        # [S]
+    s_len: torch.Tensor        # [S]
+    n_rays: int
+    n_samples: int
+
+    @classmethod
+    def from_arrays(cls, ray_offsets, xyz, delta, s_mid, s_len, device="cuda"):
+        def f(a, dt=torch.float32):
+            return torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
+        offs = f(ray_offsets, torch.int32)
+        n_rays = offs.numel() - 1
+        n_samples = int(xyz.shape[0]) if hasattr(xyz, "shape") else len(xyz)
+        return cls(offs, f(xyz).reshape(-1, 3), f(delta), f(s_mid), f(s_len), n_rays, n_samples)
+
+    def struct(self) -> Samples:
+        _chk(self.ray_offsets, "ray_offsets", torch.int32, self.n_rays + 1)
+        for name in ("xyz", "delta", "s_mid", "s_len"):
+            _chk(getattr(self, name), name, numel=self.n_samples * (3 if name == "xyz" else 1))
+        return Samples(C_size(Samples), self.n_rays, self.n_samples, _p(self.ray_offsets), _p(self.xyz),
+                       _p(self.delta), _p(self.s_mid), _p(self.s_len))
+
+
+def C_size(struct_type) -> int:
+    import ctypes
+    return ctypes.sizeof(struct_type)
+
+
+@dataclass
+class DeviceGrid:
+    """A dense channel-last vertex grid [nx, ny, nz, ch_stride] on the GPU plus its box."""
+    data: torch.Tensor
+    xyz_min: Sequence[float]
+    xyz_max: Sequence[float]
+    grad: Optional[torch.Tensor] = None
+    channels: Optional[int] = None
+
+    def struct(self, need_grad=False) -> Grid:
+        _chk(self.data, "grid data")
+        if self.data.dim() != 4:
+            raise ValueError("grid data must be [nx, ny, nz, ch_stride]")
+        nx, ny, nz, cs = self.data.shape
+        if self.grad is not None:
+            _chk(self.grad, "grid grad", numel=self.data.numel())
+        elif need_grad:
+            raise ValueError("grid grad buffer is required here")
+        g = Grid()
+        g.struct_size = C_size(Grid)
+        g.nx, g.ny, g.nz = nx, ny, nz
+        g.channels = cs if self.channels is None else self.channels
+        g.ch_stride = cs
+        g.xyz_min[:] = [float(v) for v in self.xyz_min]
+        g.xyz_max[:] = [float(v) for v in self.xyz_max]
+        g.data = _p(self.data)
+        g.grad = _p(self.grad)
+        return g
+
+
+@dataclass
+class MLPParams:
+    """Colour MLP weights [out][in] (float32 on the GPU) and their gradient buffers."""
+    W: list
+    b: list
+    gW: Optional[list] = None
+    gb: Optional[list] = None
+    in_feat: int = 12
+    n_freq: int = 4
+
+    def struct(self, need_grad=False) -> ColorMLP:
+        for i, (w, b) in enumerate(zip(self.W, self.b)):
+            _chk(w, f"W{i + 1}")
+            _chk(b, f"b{i + 1}")
+        m = ColorMLP()
+        m.struct_size = C_size(ColorMLP)
+        m.in_feat, m.n_freq, m.hidden = self.in_feat, self.n_freq, int(self.W[1].shape[0])
+        m.W1, m.W2, m.W3 = [_p(w) for w in self.W]
+        m.b1, m.b2, m.b3 = [_p(b) for b in self.b]
+        if self.gW is not None:
+            for t in list(self.gW) + list(self.gb):
+                _chk(t, "mlp gradient")
+            m.gW1, m.gW2, m.gW3 = [_p(w) for w in self.gW]
+            m.gb1, m.gb2, m.gb3 = [_p(b) for b in self.gb]
+        elif need_grad:
+            raise ValueError("MLP gradient buffers are required here")
+        return m
+
+
+def _params(act_shift_: float, halt_T: float, bg, color_mode: int, want_dist: bool) -> RenderParams:
+    p = RenderParams()
+    p.struct_size = C_size(RenderParams)
+    p.act_shift = act_shift_
+    p.halt_T = halt_T
+    p.bg[:] = [float(v) for v in bg]
+    p.color_mode = color_mode
+    p.want_dist = 1 if want_dist else 0
+    return p
+
+
+def _size(fn, *args) -> int:
+    import ctypes
+    out = ctypes.c_size_t(0)
+    call(fn, *args, ctypes.byref(out))
+    return int(out.value)
+
+
+def render_state_size(n_rays: int, n_samples: int) -> int:
+    return _size("dvgo_render_state_size", n_rays, n_samples)
+
+
+def render_forward(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid] = None,
+                   sample_rgb: Optional[torch.Tensor] = None, *, act_shift_: float, halt_T: float = 0.0,
+                   bg=(1.0, 1.0, 1.0), want_dist: bool = True, out=None, state: Optional[torch.Tensor] = None):
+    """Returns (rgb [R,3], T_final [R], dist [R] or None, state)."""
+    import ctypes
+    mode = COLOR_GRID if color is not None else COLOR_SAMPLES
+    R, S = batch.n_rays, batch.n_samples
+    dev = batch.xyz.device
+    if out is None:
+        out = (torch.empty(R, 3, device=dev), torch.empty(R, device=dev), torch.empty(R, device=dev))
+    rgb, T, dist = out
+    if state is None:
+        state = torch.empty(render_state_size(R, S), dtype=torch.uint8, device=dev)
+    if sample_rgb is not None:
+        _chk(sample_rgb, "sample_rgb", numel=3 * S)
+    p = _params(act_shift_, halt_T, bg, mode, want_dist)
+    s = batch.struct()
+    gd = density.struct()
+    gc = color.struct() if color is not None else None
+    call("dvgo_render_forward", ctypes.byref(p), ctypes.byref(s), ctypes.byref(gd),
+         ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), _p(rgb), _p(T),
+         _p(dist) if want_dist else None, _p(state), state.numel(), _stream())
+    return rgb, T, (dist if want_dist else None), state
+
+
+def render_backward(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid], sample_rgb, T_final,
+                    state, grad_rgb, grad_dist=None, grad_T=None, *, act_shift_: float, halt_T: float = 0.0,
+                    bg=(1.0, 1.0, 1.0), want_dist: bool = True, grad_sample_rgb=None):
+    """Accumulates into density.grad (and color.grad); returns grad_sample_rgb (sample mode)."""
+    import ctypes
+    mode = COLOR_GRID if color is not None else COLOR_SAMPLES
+    R, S = batch.n_rays, batch.n_samples
+    _chk(grad_rgb, "grad_rgb", numel=3 * R)
+    if grad_dist is not None:
+        _chk(grad_dist, "grad_dist", numel=R)
+    if grad_T is not None:
+        _chk(grad_T, "grad_T", numel=R)
+    if mode == COLOR_SAMPLES and grad_sample_rgb is None:
+        grad_sample_rgb = torch.empty(S, 3, device=batch.xyz.device)
+    p = _params(act_shift_, halt_T, bg, mode, want_dist)
+    s = batch.struct()
+    gd = density.struct(need_grad=True)
+    gc = color.struct(need_grad=True) if color is not None else None
+    call("dvgo_render_backward", ctypes.byref(p), ctypes.byref(s), ctypes.byref(gd),
+         ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), _p(T_final), _p(state), state.numel(),
+         _p(grad_rgb), _p(grad_dist), _p(grad_T), _p(grad_sample_rgb), _stream())
+    return grad_sample_rgb
+
+
+def distortion_workspace_size(n_rays: int, n_samples: int) -> int:
+    return _size("dvgo_distortion_workspace_size", n_rays, n_samples)
+
+
+def distortion_loss(ray_offsets, w, s_mid, s_len, grad_loss=None, grad_w=None, loss=None, ws=None):
+    """Returns loss [R]; with grad_loss, also accumulates dD/dw into grad_w (allocated if None)."""
+    R = ray_offsets.numel() - 1
+    S = w.numel()
+    _chk(ray_offsets, "ray_offsets", torch.int32)
+    for t, n in ((w, "w"), (s_mid, "s_mid"), (s_len, "s_len")):
+        _chk(t, n, numel=S)
+    if loss is None:
+        loss = torch.empty(R, device=w.device)
+    if grad_loss is not None:
+        _chk(grad_loss, "grad_loss", numel=R)
+        if grad_w is None:
+            grad_w = torch.zeros(S, device=w.device)
+        if ws is None:
+            ws = torch.empty(distortion_workspace_size(R, S), dtype=torch.uint8, device=w.device)
+    call("dvgo_distortion_loss", R, _p(ray_offsets), S, _p(w), _p(s_mid), _p(s_len), _p(loss), _p(grad_loss),
+         _p(grad_w), _p(ws), 0 if ws is None else ws.numel(), _stream())
+    return loss, grad_w
+
+
+def grid_adam_step(param, grad, exp_avg, exp_avg_sq, *, lr, beta1=0.9, beta2=0.99, eps=1e-8, step,
+                   skip_zero_grad=True, zero_grad_after=False):
+    n = param.numel()
+    for t, nm in ((param, "param"), (grad, "grad"), (exp_avg, "exp_avg"), (exp_avg_sq, "exp_avg_sq")):
+        _chk(t, nm, numel=n)
+    call("dvgo_grid_adam_step", _p(param), _p(grad), _p(exp_avg), _p(exp_avg_sq), n, lr, beta1, beta2, eps, step,
+         1 if skip_zero_grad else 0, 1 if zero_grad_after else 0, _stream())
+
+
+def grid_gather(grid: DeviceGrid, xyz, out=None):
+    import ctypes
+    g = grid.struct()
+    S = xyz.numel() // 3
+    _chk(xyz, "xyz", numel=3 * S)
+    if out is None:
+        out = torch.empty(S, g.channels, device=xyz.device)
+    _chk(out, "out", numel=S * g.channels)
+    call("dvgo_grid_gather", ctypes.byref(g), S, _p(xyz), _p(out), _stream())
+    return out
+
+
+def grid_scatter(grid: DeviceGrid, xyz, grad_out):
+    import ctypes
+    g = grid.struct(need_grad=True)
+    S = xyz.numel() // 3
+    _chk(xyz, "xyz", numel=3 * S)
+    _chk(grad_out, "grad_out", numel=S * g.channels)
+    call("dvgo_grid_scatter", ctypes.byref(g), S, _p(xyz), _p(grad_out), _stream())
+
+
+def alpha(density: DeviceGrid, xyz, delta, act_shift_: float, out=None):
+    import ctypes
+    g = density.struct()
+    S = delta.numel()
+    _chk(xyz, "xyz", numel=3 * S)
+    _chk(delta, "delta", numel=S)
+    if out is None:
+        out = torch.empty(S, device=delta.device)
+    call("dvgo_alpha", ctypes.byref(g), S, _p(xyz), _p(delta), act_shift_, _p(out), _stream())
+    return out
+
+
+def mlp_workspace_size(mlp: MLPParams, n_rays: int, n_samples: int) -> int:
+    import ctypes
+    return _size("dvgo_mlp_workspace_size", ctypes.byref(mlp.struct()), n_rays, n_samples)
+
+
+def _mlp_ws(mlp, R, S, ws, dev):
+    need = mlp_workspace_size(mlp, R, S)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    return ws
+
+
+def mlp_forward(mlp: MLPParams, ray_offsets, dirs, feat, rgb=None, ws=None):
+    import ctypes
+    R = ray_offsets.numel() - 1
+    S = feat.shape[0]
+    _chk(ray_offsets, "ray_offsets", torch.int32)
+    _chk(dirs, "dirs", numel=3 * R)
+    _chk(feat, "feat", numel=S * mlp.in_feat)
+    if rgb is None:
+        rgb = torch.empty(S, 3, device=feat.device)
+    ws = _mlp_ws(mlp, R, S, ws, feat.device)
+    m = mlp.struct()
+    call("dvgo_mlp_forward", ctypes.byref(m), R, _p(ray_offsets), _p(dirs), S, _p(feat), _p(rgb), _p(ws),
+         ws.numel(), _stream())
+    return rgb
+
+
+def mlp_backward(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, grad_feat=None, ws=None):
+    import ctypes
+    R = ray_offsets.numel() - 1
+    S = feat.shape[0]
+    _chk(grad_rgb, "grad_rgb", numel=3 * S)
+    if grad_feat is None:
+        grad_feat = torch.empty(S, mlp.in_feat, device=feat.device)
+    ws = _mlp_ws(mlp, R, S, ws, feat.device)
+    m = mlp.struct(need_grad=True)
+    call("dvgo_mlp_backward", ctypes.byref(m), R, _p(ray_offsets), _p(dirs), S, _p(feat), _p(grad_rgb),
+         _p(grad_feat), _p(ws), ws.numel(), _stream())
+    return grad_feat
+
+
+def loss_head(rgb, target, dist, dist_weight, loss=None, grad_rgb=None, grad_dist=None):
+    R = rgb.shape[0]
+    _chk(rgb, "rgb", numel=3 * R)
+    _chk(target, "target", numel=3 * R)
+    if dist is not None:
+        _chk(dist, "dist", numel=R)
+    dev = rgb.device
+    loss = torch.empty(1, device=dev) if loss is None else loss
+    grad_rgb = torch.empty(R, 3, device=dev) if grad_rgb is None else grad_rgb
+    if grad_dist is None and dist is not None:
+        grad_dist = torch.empty(R, device=dev)
+    call("dvgo_loss_head", R, _p(rgb), _p(target), _p(dist), dist_weight, _p(loss), _p(grad_rgb), _p(grad_dist),
+         _stream())
+    return loss, grad_rgb, grad_dist

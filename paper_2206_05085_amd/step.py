@@ -1,0 +1,145 @@
+"""The per-ray training step on one GPU: every stage is a libdvgo kernel.
+
+Feature-grid mode (hybrid colour, Table 1):
+    grid_gather(features) -> mlp_forward -> render_forward (density gather, alpha,
+    compositing, distortion) -> loss_head -> render_backward (density grad +=, d rgb)
+    -> mlp_backward (d features, MLP grads +=) -> grid_scatter (feature grad +=)
+    -> grid_adam_step x 3 (density, features, MLP) with zero-gradient skipping on the grids.
+Colour-grid mode: render_forward/backward with a 3-channel colour grid, then Adam.
+
+All buffers are allocated once per batch shape, so a step allocates nothing and can be
+captured in a HIP graph (``capture``/``replay``).
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import ops
+
+
+class TrainStep:
+    def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
+                 bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
+                 device="cuda"):
+        """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
+        color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU."""
+        def dev(a):
+            return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
+
+        self.device = device
+        self.box = (tuple(float(v) for v in box[0]), tuple(float(v) for v in box[1]))
+        self.grid_mode = color is not None
+        self.shift = ops.act_shift() if act_shift is None else act_shift
+        self.halt_T, self.bg, self.lam = halt_T, tuple(bg), dist_weight
+        self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
+        self.t = 0
+        self.density = self._param(dev(density))
+        if self.grid_mode:
+            self.color = self._param(dev(color))
+        else:
+            self.feat = self._param(dev(feat))
+            Ws, bs = mlp
+            flat = torch.cat([dev(w).reshape(-1) for w in Ws] + [dev(b).reshape(-1) for b in bs])
+            self.mlp_flat = self._param(flat)
+            views, gviews, o = [], [], 0
+            for t in [dev(w) for w in Ws] + [dev(b) for b in bs]:
+                views.append(self.mlp_flat["p"][o:o + t.numel()].view(t.shape))
+                gviews.append(self.mlp_flat["g"][o:o + t.numel()].view(t.shape))
+                o += t.numel()
+            self.mlp = ops.MLPParams(views[:3], views[3:], gviews[:3], gviews[3:], in_feat=int(self.feat["p"].shape[-1]),
+                                     n_freq=n_freq)
+        self.batch = None
+
+    @staticmethod
+    def _param(p):
+        return {"p": p, "g": torch.zeros_like(p), "m": torch.zeros_like(p), "v": torch.zeros_like(p)}
+
+    def grid(self, which) -> ops.DeviceGrid:
+        d = getattr(self, which)
+        return ops.DeviceGrid(d["p"], self.box[0], self.box[1], grad=d["g"],
+                              channels=3 if which == "color" else None)
+
+    def bind(self, batch: ops.SampleBatch, dirs, target):
+        """Attach a sample batch (already on the GPU) and allocate every per-batch buffer."""
+        R, S = batch.n_rays, batch.n_samples
+        d = self.device
+        self.batch = batch
+        self.dirs = torch.as_tensor(dirs).to(d, torch.float32).contiguous()
+        self.target = torch.as_tensor(target).to(d, torch.float32).contiguous()
+        self.rgb, self.T, self.dist = (torch.empty(R, 3, device=d), torch.empty(R, device=d),
+                                       torch.empty(R, device=d))
+        self.state = torch.empty(ops.render_state_size(R, S), dtype=torch.uint8, device=d)
+        self.loss = torch.zeros(1, device=d)
+        self.g_rgb, self.g_dist = torch.empty(R, 3, device=d), torch.empty(R, device=d)
+        if not self.grid_mode:
+            C = self.mlp.in_feat
+            self.feat_s = torch.empty(S, C, device=d)
+            self.rgb_s = torch.empty(S, 3, device=d)
+            self.g_rgb_s = torch.empty(S, 3, device=d)
+            self.g_feat_s = torch.empty(S, C, device=d)
+            self.mlp_ws = torch.empty(max(ops.mlp_workspace_size(self.mlp, R, S), 1), dtype=torch.uint8, device=d)
+        return self
+
+    # --------------------------------------------------------------- stages
+    def forward(self):
+        b = self.batch
+        if self.grid_mode:
+            ops.render_forward(b, self.grid("density"), self.grid("color"), None, act_shift_=self.shift,
+                               halt_T=self.halt_T, bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist),
+                               state=self.state)
+        else:
+            ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
+            ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws)
+            ops.render_forward(b, self.grid("density"), None, self.rgb_s, act_shift_=self.shift, halt_T=self.halt_T,
+                               bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist), state=self.state)
+        ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, grad_rgb=self.g_rgb,
+                      grad_dist=self.g_dist)
+
+    def backward(self):
+        b = self.batch
+        if self.grid_mode:
+            ops.render_backward(b, self.grid("density"), self.grid("color"), None, self.T, self.state, self.g_rgb,
+                                self.g_dist, None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg)
+        else:
+            ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb,
+                                self.g_dist, None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg,
+                                grad_sample_rgb=self.g_rgb_s)
+            ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
+                             ws=self.mlp_ws)
+            ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+
+    def optimise(self):
+        self.t += 1
+        b1, b2 = self.betas
+        groups = [("density", self.lr_grid, True), ("color" if self.grid_mode else "feat", self.lr_grid, True)]
+        if not self.grid_mode:
+            groups.append(("mlp_flat", self.lr_mlp, False))
+        for name, lr, skip in groups:
+            d = getattr(self, name)
+            ops.grid_adam_step(d["p"], d["g"], d["m"], d["v"], lr=lr, beta1=b1, beta2=b2, eps=self.eps, step=self.t,
+                               skip_zero_grad=skip, zero_grad_after=True)
+
+    def step(self):
+        self.forward()
+        self.backward()
+        self.optimise()
+        return self.loss
+
+    # ----------------------------------------------------------- HIP graphs
+    def capture(self, warmup: int = 1) -> Optional[torch.cuda.CUDAGraph]:
+        """Capture forward+backward+Adam of the bound batch in a graph.  The Adam step
+        counter is baked into the captured launch arguments, so a replayed graph keeps
+        the bias correction of the step it was captured at (the steady-state regime)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            for _ in range(warmup):
+                self.step()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g

@@ -1,0 +1,38 @@
+"""Tolerance rule shared by the GPU parity tests.
+
+FP32 results are compared with the FP64 oracle per output tensor x (GPU) vs y (oracle):
+pass iff BOTH
+  normwise     ||x - y||_2 <= rtol ||y||_2, and
+  elementwise  |x_i - y_i| <= rtol * max(|y_i|, floor * ||y||_inf).
+rtol is 1e-5 for forward values and 1e-4 for gradients; floor is 1e-3 for forward values
+and 1e-2 for gradients.  The floor exists because per-sample density gradients carry an
+inherent cancellation (T_{k+1} g_k - S_k) and because float32 transmittance underflows
+for opaque rays where float64 does not; the normwise bound keeps the comparison strict.
+"""
+import numpy as np
+
+FWD = dict(rtol=1e-5, floor=1e-3)
+GRAD = dict(rtol=1e-4, floor=1e-2)
+
+
+def close(x, y, rtol, floor, name="value", scale=None):
+    """scale (optional, per element): the magnitude the result is conditioned on, e.g.
+    sum_c w_c |G_c| for an interpolated value whose terms cancel; the elementwise bound
+    then uses max(|y_i|, floor * ||y||_inf, scale_i)."""
+    x = np.asarray(x, np.float64).ravel()
+    y = np.asarray(y, np.float64).ravel()
+    assert x.shape == y.shape, f"{name}: shape {x.shape} vs {y.shape}"
+    assert np.isfinite(x).all(), f"{name}: non-finite values"
+    ny = np.linalg.norm(y)
+    err = np.linalg.norm(x - y)
+    assert err <= rtol * ny + 1e-30, f"{name}: normwise error {err / max(ny, 1e-300):.3e} > {rtol}"
+    if y.size:
+        bound = rtol * np.maximum(np.abs(y), floor * np.abs(y).max())
+        if scale is not None:
+            bound = np.maximum(bound, rtol * np.asarray(scale, np.float64).ravel())
+        bad = np.abs(x - y) > bound + 1e-30
+        if bad.any():
+            i = np.argmax(np.abs(x - y) - bound)
+            raise AssertionError(f"{name}: {bad.sum()} of {y.size} elements out of bound; worst at {i}: "
+                                 f"gpu {x[i]:.9g} oracle {y[i]:.9g} bound {bound[i]:.3g}")
+    return err / max(ny, 1e-300)

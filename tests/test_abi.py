@@ -1,0 +1,127 @@
+"""The C-ABI library loads without a GPU, exports every symbol include/dvgo.h declares, its
+struct layouts match the Python binding, and host-side validation returns the documented
+error codes (these calls return before any device work)."""
+import ctypes as C
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dvgo.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2206_05085_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.skip("libdvgo.so not built (run __graft_entry__.build())")
+    return _lib
+
+
+def declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(dvgo_\w+)\s*\(", txt, re.M)))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared()
+    assert len(names) >= 14
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.SIGNATURES), "binding signatures and header disagree"
+
+
+def test_abi_version(L):
+    assert L.lib().dvgo_abi_version() == L.ABI_VERSION
+
+
+def test_struct_layouts_match_header(L, tmp_path):
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dvgo.h"\n'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dvgo_grid), sizeof(dvgo_samples),'
+                   'sizeof(dvgo_render_params), sizeof(dvgo_color_mlp), offsetof(dvgo_grid, data),'
+                   'offsetof(dvgo_color_mlp, gW1));return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(L.Grid), C.sizeof(L.Samples), C.sizeof(L.RenderParams), C.sizeof(L.ColorMLP),
+            L.Grid.data.offset, L.ColorMLP.gW1.offset]
+    assert got == want
+
+
+def _err(L):
+    return L.lib().dvgo_last_error().decode()
+
+
+def test_validation_errors(L):
+    lib = L.lib()
+    # NULL params
+    assert lib.dvgo_render_forward(None, None, None, None, None, None, None, None, None, 0, None) == -1
+    assert "params" in _err(L)
+    # struct_size mismatch
+    p = L.RenderParams()
+    p.struct_size = 3
+    s = L.Samples()
+    s.struct_size = C.sizeof(L.Samples)
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), None, None, None, None, None, None, None, 0, None) == -8
+    p.struct_size = C.sizeof(L.RenderParams)
+    # unknown colour mode
+    p.color_mode = 7
+    s.ray_offsets = 1
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), None, None, None, None, None, None, None, 0, None) == -7
+    # bad grid dims
+    p.color_mode = L.COLOR_SAMPLES
+    g = L.Grid()
+    g.struct_size = C.sizeof(L.Grid)
+    g.nx, g.ny, g.nz, g.channels, g.ch_stride = 1, 4, 4, 1, 1
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, None, None, None, None, None, 0,
+                                   None) == -2
+    assert "dimension" in _err(L)
+    # halting threshold out of range
+    p.halt_T = 1.5
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, None, None, None, None, None, 0,
+                                   None) == -3
+    # state too small (valid otherwise; fails before any launch)
+    p.halt_T = 0.0
+    g.nx = 4
+    g.xyz_min[:] = [-1, -1, -1]
+    g.xyz_max[:] = [1, 1, 1]
+    g.data = 64
+    s.n_rays, s.n_samples = 4, 10
+    s.xyz = s.delta = s.s_mid = s.s_len = 64
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, 64, 64, 64, 64, 64, 1, None) == -5
+    # Adam: NULL arrays, zero step, mismatched alignment
+    assert lib.dvgo_grid_adam_step(None, None, None, None, 10, 0.1, 0.9, 0.99, 1e-8, 1, 1, 0, None) == -1
+    assert lib.dvgo_grid_adam_step(16, 16, 16, 16, 10, 0.1, 0.9, 0.99, 1e-8, 0, 1, 0, None) == -3
+    assert lib.dvgo_grid_adam_step(16, 20, 16, 16, 10, 0.1, 0.9, 0.99, 1e-8, 1, 1, 0, None) == -2
+    # distortion: backward without workspace
+    assert lib.dvgo_distortion_loss(2, 64, 10, 64, 64, 64, None, 64, 64, None, 0, None) == -5
+    # MLP: unsupported hidden width
+    m = L.ColorMLP()
+    m.struct_size = C.sizeof(L.ColorMLP)
+    m.in_feat, m.n_freq, m.hidden = 12, 4, 64
+    out = C.c_size_t()
+    assert lib.dvgo_mlp_workspace_size(C.byref(m), 4, 10, C.byref(out)) == -7
+    m.hidden = 128
+    assert lib.dvgo_mlp_workspace_size(C.byref(m), 4, 10, C.byref(out)) == -1  # NULL weights
+    # sizes
+    assert lib.dvgo_render_state_size(8192, 10 ** 6, C.byref(out)) == 0 and out.value > 0
+    assert lib.dvgo_render_state_size(-1, 0, C.byref(out)) == -2
+
+
+def test_binding_refuses_cpu_tensors(L):
+    import torch
+    from paper_2206_05085_amd import ops
+    with pytest.raises(ValueError, match="GPU"):
+        ops.grid_adam_step(*(torch.zeros(4) for _ in range(4)), lr=0.1, step=1)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    code = ("import paper_2206_05085_amd._lib as L; L.LIB_PATH = '/nonexistent/libdvgo.so'; L._lib = None\n"
+            "try:\n    L.lib()\nexcept RuntimeError as e:\n    print('raised', e)\n")
+    out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT).decode()
+    assert out.startswith("raised")

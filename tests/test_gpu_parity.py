@@ -1,0 +1,326 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle on seeded inputs.
+
+Every test prints the case it runs before touching the GPU.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import FWD, GRAD, close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dv():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2206_05085_amd as pkg
+    pkg.lib()  # raises if the HIP library is missing
+    from paper_2206_05085_amd import ops
+    return ops
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def T(a, dt=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)
+
+
+def dgrid(ops, g: synth.Grid, grad=False, channels=None):
+    data = T(g.data)
+    return ops.DeviceGrid(data, g.xyz_min, g.xyz_max, grad=torch.zeros_like(data) if grad else None,
+                          channels=channels)
+
+
+def dbatch(ops, s: synth.Samples):
+    return ops.SampleBatch.from_arrays(s.ray_offsets, s.xyz, s.delta, s.s_mid, s.s_len)
+
+
+def sub_samples(s: synth.Samples, rays):
+    """Samples of a subset of rays (in the given order)."""
+    offs = [0]
+    idx = []
+    for r in rays:
+        a, b = s.ray_offsets[r], s.ray_offsets[r + 1]
+        idx.append(np.arange(a, b))
+        offs.append(offs[-1] + b - a)
+    idx = np.concatenate(idx) if idx else np.zeros(0, np.int64)
+    return synth.Samples(np.asarray(offs, np.int32), s.xyz[idx], s.delta[idx], s.s_mid[idx], s.s_len[idx]), idx
+
+
+# ------------------------------------------------------------------ distortion
+
+
+@pytest.mark.parametrize("lengths", [[0, 1, 2, 3, 7, 63, 64, 65, 127, 128, 129, 300, 1024, 0],
+                                     list(np.random.default_rng(5).integers(0, 400, 257))])
+def test_distortion_matches_oracle(dv, lengths):
+    say("distortion", len(lengths), "rays", sum(lengths), "samples")
+    rng = np.random.default_rng(7)
+    offs, w, m, l = synth.random_ragged(rng, lengths)
+    gl = rng.standard_normal(len(lengths)).astype(np.float32)
+    loss, gw = dv.distortion_loss(T(offs, torch.int32), T(w), T(m), T(l), grad_loss=T(gl))
+    torch.cuda.synchronize()
+    D = oracle.distortion(offs, w.astype(np.float64), m, l)
+    G = oracle.distortion_grad(offs, w.astype(np.float64), m, l, gl.astype(np.float64))
+    close(loss.cpu().numpy(), D, **FWD, name="D")
+    close(gw.cpu().numpy(), G, **GRAD, name="dD/dw")
+
+
+def test_distortion_closed_form_on_gpu(dv):
+    # uniform weights 1/N on N equal intervals of [0,1]: D = 1/3 for every N
+    lengths = [1, 2, 5, 64, 65, 256, 1000]
+    offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    w = np.concatenate([np.full(n, 1.0 / n) for n in lengths]).astype(np.float32)
+    m = np.concatenate([(np.arange(n) + 0.5) / n for n in lengths]).astype(np.float32)
+    l = np.concatenate([np.full(n, 1.0 / n) for n in lengths]).astype(np.float32)
+    say("distortion closed form")
+    loss, _ = dv.distortion_loss(T(offs, torch.int32), T(w), T(m), T(l))
+    np.testing.assert_allclose(loss.cpu().numpy(), 1.0 / 3.0, rtol=2e-6)
+
+
+# ------------------------------------------------------------------ rendering
+
+
+def _check_render(dv, wl, smp, color_mode, rays=None, halt_T=0.0, seed=0, grad_T=True):
+    rng = np.random.default_rng(seed)
+    R, S = smp.n_rays, smp.n_samples
+    shift = oracle.act_shift()
+    bg = (0.25, 0.5, 1.0)
+    dens = dgrid(dv, wl.density, grad=True)
+    b = dbatch(dv, smp)
+    if color_mode == "grid":
+        col = dgrid(dv, wl.color, grad=True, channels=3)
+        srgb = None
+    else:
+        col = None
+        srgb = rng.random((S, 3)).astype(np.float32)
+    rgb, Tf, D, state = dv.render_forward(b, dens, col, None if srgb is None else T(srgb), act_shift_=float(shift),
+                                          halt_T=halt_T, bg=bg)
+    GC = rng.standard_normal((R, 3)).astype(np.float32)
+    GD = rng.standard_normal(R).astype(np.float32)
+    GT = rng.standard_normal(R).astype(np.float32) if grad_T else None
+    gs = dv.render_backward(b, dens, col, None if srgb is None else T(srgb), Tf, state, T(GC), T(GD),
+                            None if GT is None else T(GT), act_shift_=float(shift), halt_T=halt_T, bg=bg)
+    torch.cuda.synchronize()
+    o = oracle.render_forward(smp, wl.density, wl.color if col is not None else None, srgb=srgb,
+                              shift=float(np.float32(shift)), halt_T=halt_T, bg=bg)
+    og = oracle.render_backward(smp, wl.density, GC.astype(np.float64), GD.astype(np.float64),
+                                None if GT is None else GT.astype(np.float64),
+                                color=wl.color if col is not None else None, srgb=srgb,
+                                shift=float(np.float32(shift)), halt_T=halt_T, bg=bg)
+    close(rgb.cpu().numpy(), o["rgb"], **FWD, name="rgb")
+    close(Tf.cpu().numpy(), o["T"], **FWD, name="T_final")
+    close(D.cpu().numpy(), o["D"], **FWD, name="distortion")
+    close(dens.grad.cpu().numpy(), og["grad_density"], **GRAD, name="grad density")
+    if col is not None:
+        close(col.grad.cpu().numpy(), og["grad_color"], **GRAD, name="grad colour grid")
+    else:
+        close(gs.cpu().numpy(), og["grad_srgb"], **GRAD, name="grad sample rgb")
+
+
+def test_render_grid_mode_config1(dv):
+    wl = synth.config1()
+    say("render grid-colour, 32^3, 1024 rays x 128")
+    _check_render(dv, wl, wl.samples, "grid")
+
+
+def test_render_sample_mode_config2_grid(dv):
+    # the 160^3 grid at full size, 512 of the pinhole rays (ragged, empty rays included)
+    wl = synth.config2(R=512)
+    say("render sample-colour, 160^3, 512 rays, S =", wl.samples.n_samples)
+    _check_render(dv, wl, wl.samples, "samples", seed=1)
+
+
+def test_render_ragged_unbounded_config3(dv):
+    wl = synth.config3(R=96)
+    say("render sample-colour, 320^3 contracted, 96 lognormal rays, S =", wl.samples.n_samples)
+    _check_render(dv, wl, wl.samples, "samples", seed=2)
+
+
+def test_render_edge_cases(dv):
+    # empty rays, single-sample rays, exact multiples of 64 and their neighbours, and rays
+    # whose points sit on the box faces and corners
+    rng = np.random.default_rng(3)
+    wl = synth.config1(R=8)
+    lengths = [0, 1, 2, 63, 64, 65, 128, 129, 0, 1]
+    offs = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int32)
+    S = int(offs[-1])
+    xyz = rng.uniform(-1, 1, (S, 3)).astype(np.float32)
+    xyz[:5] = np.array([[1, 1, 1], [-1, -1, -1], [1, -1, 0], [1.5, 0, 0], [0, 0, -3]], np.float32)
+    s_mid = np.concatenate([(np.arange(n) + 0.5) / max(n, 1) for n in lengths]).astype(np.float32)
+    s_len = np.concatenate([np.full(n, 1.0 / max(n, 1)) for n in lengths]).astype(np.float32)
+    delta = rng.uniform(0.05, 2.0, S).astype(np.float32)
+    smp = synth.Samples(offs, xyz, delta, s_mid, s_len)
+    say("render edge cases", lengths)
+    _check_render(dv, wl, smp, "grid", seed=4)
+    _check_render(dv, wl, smp, "samples", seed=5, grad_T=False)
+
+
+def test_render_halting_paper_mode(dv):
+    # halt at T < 1e-3 (section 3).  A float32/float64 difference can move the halt index
+    # of a ray sitting at the threshold; such rays are compared with the slack the rule
+    # allows (thr * (max|c| + |bg|)), all others exactly as without halting.
+    wl = synth.config1(R=256)
+    wl.density.data += np.float32(6.0)
+    smp = wl.samples
+    thr = 1e-3
+    dens = dgrid(dv, wl.density)
+    col = dgrid(dv, wl.color, channels=3)
+    b = dbatch(dv, smp)
+    shift = float(np.float32(oracle.act_shift()))
+    say("render halting thr=1e-3, 256 rays")
+    rgb, Tf, D, state = dv.render_forward(b, dens, col, None, act_shift_=shift, halt_T=thr)
+    torch.cuda.synchronize()
+    o = oracle.render_forward(smp, wl.density, wl.color, shift=shift, halt_T=thr)
+    rgb = rgb.cpu().numpy()
+    diff = np.abs(rgb - o["rgb"]).max(axis=1)
+    exact = diff <= 1e-5 * np.maximum(np.abs(o["rgb"]).max(axis=1), 1e-3)
+    assert exact.mean() >= 0.99, f"halt agreement {exact.mean():.4f}"
+    assert (diff[~exact] <= thr * (1.0 + 1.0) + 1e-5).all()
+    assert (Tf.cpu().numpy() >= 0).all()
+
+
+# ------------------------------------------------------------ gather / scatter
+
+
+@pytest.mark.parametrize("C", [1, 3, 12])
+def test_gather_scatter(dv, C):
+    rng = np.random.default_rng(10 + C)
+    g = synth.normal_grid(rng, 24, C)
+    S = 5000
+    xyz = rng.uniform(-1.1, 1.1, (S, 3)).astype(np.float32)
+    y = rng.standard_normal((S, C)).astype(np.float32)
+    say("gather/scatter C =", C)
+    dg = dgrid(dv, g, grad=True)
+    out = dv.grid_gather(dg, T(xyz))
+    dv.grid_scatter(dg, T(xyz), T(y))
+    torch.cuda.synchronize()
+    # an interpolated value is a sum of 8 weighted vertex values that may cancel: its
+    # float32 error is relative to sum_c w_c |G_c|, the gather of |G|
+    absg = synth.Grid(np.abs(g.data), g.xyz_min, g.xyz_max)
+    close(out.cpu().numpy(), oracle.gather(g, xyz), **FWD, name="gather", scale=oracle.gather(absg, xyz))
+    close(dg.grad.cpu().numpy(), oracle.scatter(g, xyz, y.astype(np.float64)), **GRAD, name="scatter")
+
+
+@pytest.mark.parametrize("pattern", ["rays", "one_cell", "interleaved"])
+def test_scatter_shared_vertices(dv, pattern):
+    # the scatter sums contributions to shared vertices inside a wave before the atomics;
+    # these layouts make many lanes of a wave hit the same vertices
+    rng = np.random.default_rng(40)
+    if pattern == "rays":
+        wl = synth.config2(R=256)
+        g, xyz = wl.feat, wl.samples.xyz
+    else:
+        g = synth.normal_grid(rng, 16, 12)
+        S = 3000
+        if pattern == "one_cell":
+            xyz = (0.1 + 0.01 * rng.random((S, 3))).astype(np.float32)
+        else:
+            a = (0.1 + 0.01 * rng.random((S, 3)))
+            b = (-0.5 + 0.01 * rng.random((S, 3)))
+            xyz = np.where((np.arange(S) % 2 == 0)[:, None], a, b).astype(np.float32)
+    S = xyz.shape[0]
+    y = rng.standard_normal((S, g.channels)).astype(np.float32)
+    say("scatter shared vertices:", pattern, "S =", S)
+    dg = dgrid(dv, g, grad=True)
+    dv.grid_scatter(dg, T(xyz), T(y))
+    torch.cuda.synchronize()
+    close(dg.grad.cpu().numpy(), oracle.scatter(g, xyz, y.astype(np.float64)), **GRAD, name="scatter")
+
+
+def test_alpha(dv):
+    wl = synth.config2(R=64)
+    smp = wl.samples
+    say("alpha, 160^3")
+    a = dv.alpha(dgrid(dv, wl.density), T(smp.xyz), T(smp.delta), float(oracle.act_shift()))
+    torch.cuda.synchronize()
+    close(a.cpu().numpy(), oracle.alpha(smp.xyz, smp.delta, wl.density, float(np.float32(oracle.act_shift()))),
+          **FWD, name="alpha")
+
+
+# ----------------------------------------------------------------------- MLP
+
+
+def _mlp_case(dv, S_lengths, seed, bias_std=0.3):
+    rng = np.random.default_rng(seed)
+    mlp = synth.mlp_weights(rng, bias_std=bias_std)
+    offs = np.concatenate([[0], np.cumsum(S_lengths)]).astype(np.int32)
+    R = len(S_lengths)
+    S = int(offs[-1])
+    dirs = synth.scenes._unit(rng.standard_normal((R, 3))).astype(np.float32)
+    feat = rng.standard_normal((S, 12)).astype(np.float32)
+    grgb = rng.standard_normal((S, 3)).astype(np.float32)
+    W = [T(w) for w in mlp.W]
+    b = [T(v) for v in mlp.b]
+    gW = [torch.zeros_like(w) for w in W]
+    gb = [torch.zeros_like(v) for v in b]
+    P = dv.MLPParams(W, b, gW, gb)
+    rgb = dv.mlp_forward(P, T(offs, torch.int32), T(dirs), T(feat))
+    gf = dv.mlp_backward(P, T(offs, torch.int32), T(dirs), T(feat), T(grgb))
+    torch.cuda.synchronize()
+    ref = oracle.mlp_forward(mlp, offs, dirs, feat.astype(np.float64))
+    rgf, rgW, rgb_ = oracle.mlp_backward(mlp, offs, dirs, feat.astype(np.float64), grgb.astype(np.float64))
+    close(rgb.cpu().numpy(), ref, **FWD, name="mlp rgb")
+    close(gf.cpu().numpy(), rgf, **GRAD, name="mlp d feat")
+    for i in range(3):
+        close(gW[i].cpu().numpy(), rgW[i], **GRAD, name=f"mlp dW{i + 1}")
+        close(gb[i].cpu().numpy(), rgb_[i], **GRAD, name=f"mlp db{i + 1}")
+
+
+def test_mlp_small_ragged(dv):
+    say("mlp 300 samples (ragged, partial tiles)")
+    _mlp_case(dv, [0, 5, 1, 64, 100, 0, 130], seed=20)
+
+
+def test_mlp_multi_block(dv):
+    say("mlp ~40k samples")
+    _mlp_case(dv, list(np.random.default_rng(21).integers(0, 300, 256)), seed=22)
+
+
+# ---------------------------------------------------------------------- Adam
+
+
+def test_adam(dv):
+    rng = np.random.default_rng(30)
+    n = 100003
+    p, m = rng.standard_normal(n).astype(np.float32), (0.1 * rng.standard_normal(n)).astype(np.float32)
+    v = rng.random(n).astype(np.float32) * 0.01
+    g = rng.standard_normal(n).astype(np.float32)
+    g[rng.random(n) < 0.4] = 0.0
+    g[7] = -0.0
+    tp, tg, tm, tv = T(p), T(g), T(m), T(v)
+    say("adam n =", n)
+    dv.grid_adam_step(tp[1:], tg[1:], tm[1:], tv[1:], lr=0.05, beta1=0.9, beta2=0.99, eps=1e-8, step=3,
+                      skip_zero_grad=True, zero_grad_after=True)
+    torch.cuda.synchronize()
+    # the kernel receives float32 hyper-parameters; the oracle takes the same values
+    f = lambda x: float(np.float32(x))  # noqa: E731
+    op, om, ov = oracle.adam(p[1:], g[1:], m[1:], v[1:], f(0.05), f(0.9), f(0.99), f(1e-8), 3)
+    P, M, V = tp.cpu().numpy()[1:], tm.cpu().numpy()[1:], tv.cpu().numpy()[1:]
+    z = g[1:] == 0
+    assert np.array_equal(P[z], p[1:][z]) and np.array_equal(M[z], m[1:][z]) and np.array_equal(V[z], v[1:][z])
+    close(P, op, **FWD, name="param")
+    # m = b1 m + (1 - b1) g can cancel: its float32 error is relative to |b1 m| + |(1 - b1) g|
+    close(M, om, **FWD, name="exp_avg", scale=0.9 * np.abs(m[1:]) + 0.1 * np.abs(g[1:]))
+    close(V, ov, **FWD, name="exp_avg_sq")
+    assert not tg[1:].any().item()
+    assert tg[0].item() == g[0]
+
+
+def test_loss_head(dv):
+    rng = np.random.default_rng(31)
+    R = 8192
+    rgb, tgt, D = rng.random((R, 3)).astype(np.float32), rng.random((R, 3)).astype(np.float32), rng.random(R)
+    D = D.astype(np.float32)
+    say("loss head")
+    L, gr, gd = dv.loss_head(T(rgb), T(tgt), T(D), 0.01)
+    torch.cuda.synchronize()
+    oL, oGC, oGD = oracle.loss_head(rgb.astype(np.float64), tgt, D.astype(np.float64), 0.01)
+    close(L.cpu().numpy(), [oL], **FWD, name="loss")
+    close(gr.cpu().numpy(), oGC, **FWD, name="dL/drgb")
+    close(gd.cpu().numpy(), oGD, **FWD, name="dL/dD")
