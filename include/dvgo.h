@@ -162,12 +162,18 @@ int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, int64_t n_s
 
 /* Fused Adam over n float32 elements (section 3, re-implemented Adam): with 1-based step t,
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).
+ * t is `step`, or, when step_dev is not NULL, the int32 at step_dev read by the kernel (so a
+ * captured HIP graph can advance it between replays with dvgo_counter_add); t must be >= 1.
  * skip_zero_grad != 0: elements whose gradient is exactly zero are skipped entirely (p, m,
  * v untouched), as the paper does for grid points without gradient.  zero_grad_after != 0:
  * the gradient is reset to zero for the next step. */
 int dvgo_grid_adam_step(float *param, float *grad, float *exp_avg, float *exp_avg_sq, int64_t n, float lr,
-                        float beta1, float beta2, float eps, int32_t step, int32_t skip_zero_grad,
-                        int32_t zero_grad_after, void *stream);
+                        float beta1, float beta2, float eps, int32_t step, const int32_t *step_dev,
+                        int32_t skip_zero_grad, int32_t zero_grad_after, void *stream);
+
+/* counter[0] += delta on the device (one thread); used to advance the Adam step counter
+ * inside captured graphs. */
+int dvgo_counter_add(int32_t *counter, int32_t delta, void *stream);
 
 /* Trilinear gather of every channel at n_samples points: out [S, channels] row-major. */
 int dvgo_grid_gather(const dvgo_grid *g, int64_t n_samples, const float *xyz, float *out, void *stream);

@@ -8,10 +8,10 @@ and wraps it with numpy.  It shares nothing with the HIP library.
 Parity status per function (pins live in ``tests/test_oracle_*.py``):
 
 * gather / scatter: pinned (linear-field reproduction, vertex values, adjoint identity).
-* distortion (Eq. 1) and its gradient: pinned (closed forms, brute force in Python,
-  finite differences, Euler identity, paper's O(N) rewrite).
+* distortion (Eq. 1) and its gradient: pinned (closed forms, the paper's O(N) rewrite,
+  2-homogeneity, shift and reflection invariance, Euler identity, finite differences).
 * render forward / backward: pinned (closed-form constant-density ray, invariants,
-  finite differences, torch float64 autograd of an independent formulation).
+  the alpha_init identity, halting rule, finite differences of the oracle's forward).
 * colour MLP: pinned against torch float64 Linear/ReLU/Sigmoid and autograd.
 * Adam: pinned against torch.optim.Adam in float64; skip rule checked bitwise.
 * proposal network: pinned against torch float64 with bfloat16-rounded operands;
@@ -271,6 +271,18 @@ def mlp_forward(mlp, offs, dirs, feat, F=4):
     rgb = np.zeros((feat.shape[0], 3))
     lib().orc_mlp_forward(C.byref(P), C.c_int32(R), _ptr(offs), _ptr(dirs), _ptr(feat), _ptr(rgb))
     return rgb
+
+
+def mlp_margin(mlp, offs, dirs, feat, F=4):
+    """Per-sample relative distance of the colour head's hidden pre-activations from 0."""
+    keep = _Keep()
+    feat = keep(_c(feat, np.float64))
+    P = _mlp_struct(mlp, keep, feat.shape[1], F)
+    offs = keep(_c(offs, np.int32))
+    dirs = keep(_c(dirs, np.float32))
+    out = np.zeros(feat.shape[0])
+    lib().orc_mlp_margin(C.byref(P), C.c_int32(offs.shape[0] - 1), _ptr(offs), _ptr(dirs), _ptr(feat), _ptr(out))
+    return out
 
 
 def mlp_backward(mlp, offs, dirs, feat, grad_rgb, F=4):

@@ -448,18 +448,17 @@ void orc_mlp_forward(const orc_mlp *P, int32_t R, const int32_t *offs, const flo
 
 /* Backward of the colour head for upstream grad_rgb [S,3]: writes grad_feat [S,C] and
  * accumulates (+=) the parameter gradients, serially in sample order. */
-void orc_mlp_backward(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
-                      const double *grad_rgb, double *grad_feat,
-                      double *gW1, double *gb1, double *gW2, double *gb2, double *gW3, double *gb3)
+static void mlp_backward_range(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs,
+                               const double *feat, const double *grad_rgb, double *grad_feat, int64_t k0, int64_t k1,
+                               double *gW1, double *gb1, double *gW2, double *gb2, double *gW3, double *gb3)
 {
-    int64_t S = offs[R];
     int I = P->C + 3 + 6 * P->F, H = P->H;
     double *x = malloc(sizeof(double) * I);
     double *z1 = malloc(sizeof(double) * H), *h1 = malloc(sizeof(double) * H);
     double *z2 = malloc(sizeof(double) * H), *h2 = malloc(sizeof(double) * H);
     double *d2 = malloc(sizeof(double) * H), *d1 = malloc(sizeof(double) * H);
     double rgb[3], d3[3];
-    for (int64_t k = 0; k < S; ++k) {
+    for (int64_t k = k0; k < k1; ++k) {
         int64_t r = find_ray(R, offs, k);
         for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
         view_pe(dirs + 3 * r, P->F, x + P->C);
@@ -494,6 +493,83 @@ void orc_mlp_backward(const orc_mlp *P, int32_t R, const int32_t *offs, const fl
         }
     }
     free(x); free(z1); free(h1); free(z2); free(h2); free(d2); free(d1);
+}
+
+/* Distance of every sample from the colour head's ReLU kinks: the smallest |z| / scale
+ * over both hidden layers, where scale = |b| + sum |W x| is the magnitude the float32
+ * pre-activation is rounded against.  Below ~1e-5 a float32 evaluation may switch the unit
+ * the other way than float64 does, a non-differentiable point of the loss. */
+void orc_mlp_margin(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
+                    double *margin)
+{
+    int64_t S = offs[R];
+    int I = P->C + 3 + 6 * P->F, H = P->H;
+#pragma omp parallel
+    {
+        double *x = malloc(sizeof(double) * I), *h1 = malloc(sizeof(double) * H);
+#pragma omp for schedule(static)
+        for (int64_t k = 0; k < S; ++k) {
+            int64_t r = find_ray(R, offs, k);
+            for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
+            view_pe(dirs + 3 * r, P->F, x + P->C);
+            double mg = INFINITY;
+            for (int i = 0; i < H; ++i) {
+                double z = P->b1[i], a = fabs((double)P->b1[i]);
+                for (int j = 0; j < I; ++j) {
+                    z += (double)P->W1[i * I + j] * x[j];
+                    a += fabs((double)P->W1[i * I + j] * x[j]);
+                }
+                h1[i] = z > 0 ? z : 0.0;
+                if (a > 0 && fabs(z) / a < mg) mg = fabs(z) / a;
+            }
+            for (int i = 0; i < H; ++i) {
+                double z = P->b2[i], a = fabs((double)P->b2[i]);
+                for (int j = 0; j < H; ++j) {
+                    z += (double)P->W2[i * H + j] * h1[j];
+                    a += fabs((double)P->W2[i * H + j] * h1[j]);
+                }
+                if (a > 0 && fabs(z) / a < mg) mg = fabs(z) / a;
+            }
+            margin[k] = mg;
+        }
+        free(x);
+        free(h1);
+    }
+}
+
+/* Backward of the colour head for upstream grad_rgb [S,3]: writes grad_feat [S,C] and
+ * accumulates (+=) the parameter gradients.  Samples are split into fixed contiguous
+ * blocks whose partial sums are added in block order, so the result does not depend on
+ * the number of threads. */
+void orc_mlp_backward(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
+                      const double *grad_rgb, double *grad_feat,
+                      double *gW1, double *gb1, double *gW2, double *gb2, double *gW3, double *gb3)
+{
+    int64_t S = offs[R];
+    int I = P->C + 3 + 6 * P->F, H = P->H;
+    const int64_t BLK = 4096;
+    int64_t nb = (S + BLK - 1) / BLK;
+    int64_t np = (int64_t)H * I + H + (int64_t)H * H + H + 3 * H + 3;
+    double *part = calloc((size_t)(nb > 0 ? nb : 1) * np, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nb; ++b) {
+        double *q = part + b * np;
+        double *qW1 = q, *qb1 = qW1 + (int64_t)H * I, *qW2 = qb1 + H, *qb2 = qW2 + (int64_t)H * H, *qW3 = qb2 + H,
+               *qb3 = qW3 + 3 * H;
+        int64_t k1 = (b + 1) * BLK < S ? (b + 1) * BLK : S;
+        mlp_backward_range(P, R, offs, dirs, feat, grad_rgb, grad_feat, b * BLK, k1, qW1, qb1, qW2, qb2, qW3, qb3);
+    }
+    for (int64_t b = 0; b < nb; ++b) {
+        const double *q = part + b * np;
+        int64_t o = 0;
+        for (int64_t i = 0; i < (int64_t)H * I; ++i) gW1[i] += q[o++];
+        for (int i = 0; i < H; ++i) gb1[i] += q[o++];
+        for (int64_t i = 0; i < (int64_t)H * H; ++i) gW2[i] += q[o++];
+        for (int i = 0; i < H; ++i) gb2[i] += q[o++];
+        for (int i = 0; i < 3 * H; ++i) gW3[i] += q[o++];
+        for (int i = 0; i < 3; ++i) gb3[i] += q[o++];
+    }
+    free(part);
 }
 
 /* ------------------------------------------------------------------------- Adam */

@@ -154,9 +154,19 @@ struct AdamArgs {
     int64_t n;
     float lr_t;          // lr / (1 - beta1^t)
     float inv_sqrt_bc2;  // 1 / sqrt(1 - beta2^t)
-    float b1, b2, eps;
+    float b1, b2, eps, lr;
+    const int *step_dev;  // when set, t is read here and lr_t / inv_sqrt_bc2 are recomputed
     int skip, zero;
 };
+
+__device__ __forceinline__ void adam_bias(AdamArgs &a) {
+    if (a.step_dev) {
+        const int t = *a.step_dev;
+        const double bc1 = 1.0 - pow((double)a.b1, t), bc2 = 1.0 - pow((double)a.b2, t);
+        a.lr_t = (float)((double)a.lr / bc1);
+        a.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+    }
+}
 
 __device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, float &m, float &v) {
     m = a.b1 * m + (1.f - a.b1) * g;
@@ -169,6 +179,7 @@ __device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, f
 // nothing is written; within a partly non-zero group the zero-gradient lanes keep their
 // values bit for bit.
 __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, int64_t n4) {
+    adam_bias(a);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t tid = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     float4 *P = reinterpret_cast<float4 *>(a.p + head), *G = reinterpret_cast<float4 *>(a.g + head);
@@ -280,13 +291,24 @@ extern "C" int dvgo_alpha(const dvgo_grid *density, int64_t n_samples, const flo
     return check_hip(hipGetLastError(), "alpha_kernel launch");
 }
 
+__global__ void counter_add_kernel(int *c, int d) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) c[0] += d;
+}
+
+extern "C" int dvgo_counter_add(int32_t *counter, int32_t delta, void *stream) {
+    if (!counter) return set_error(DVGO_ERR_NULL, "counter is NULL");
+    hipLaunchKernelGGL(counter_add_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, counter, delta);
+    return check_hip(hipGetLastError(), "counter_add_kernel launch");
+}
+
 extern "C" int dvgo_grid_adam_step(float *param, float *grad, float *exp_avg, float *exp_avg_sq, int64_t n,
                                    float lr, float beta1, float beta2, float eps, int32_t step,
-                                   int32_t skip_zero_grad, int32_t zero_grad_after, void *stream) {
+                                   const int32_t *step_dev, int32_t skip_zero_grad, int32_t zero_grad_after,
+                                   void *stream) {
     if (n < 0) return set_error(DVGO_ERR_SHAPE, "negative n");
     if (n == 0) return DVGO_OK;
     if (!param || !grad || !exp_avg || !exp_avg_sq) return set_error(DVGO_ERR_NULL, "an Adam array is NULL");
-    if (step < 1) return set_error(DVGO_ERR_RANGE, "step is 1-based");
+    if (!step_dev && step < 1) return set_error(DVGO_ERR_RANGE, "step is 1-based");
     if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f))
         return set_error(DVGO_ERR_RANGE, "betas must be in [0, 1)");
     const uintptr_t al = (uintptr_t)param & 15;
@@ -299,9 +321,12 @@ extern "C" int dvgo_grid_adam_step(float *param, float *grad, float *exp_avg, fl
     a.m = exp_avg;
     a.v = exp_avg_sq;
     a.n = n;
-    const double bc1 = 1.0 - pow((double)beta1, step), bc2 = 1.0 - pow((double)beta2, step);
+    const int t = step_dev ? 1 : step;
+    const double bc1 = 1.0 - pow((double)beta1, t), bc2 = 1.0 - pow((double)beta2, t);
     a.lr_t = (float)((double)lr / bc1);
     a.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+    a.lr = lr;
+    a.step_dev = step_dev;
     a.b1 = beta1;
     a.b2 = beta2;
     a.eps = eps;

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import COLOR_GRID, COLOR_SAMPLES, ColorMLP, Grid, RenderParams, Samples, call
 
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "render_state_size", "render_forward",
-           "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "grid_gather",
+           "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather",
            "grid_scatter", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
            "COLOR_GRID", "COLOR_SAMPLES"]
 
@@ -236,13 +236,21 @@ def distortion_loss(ray_offsets, w, s_mid, s_len, grad_loss=None, grad_w=None, l
     return loss, grad_w
 
 
-def grid_adam_step(param, grad, exp_avg, exp_avg_sq, *, lr, beta1=0.9, beta2=0.99, eps=1e-8, step,
-                   skip_zero_grad=True, zero_grad_after=False):
+def grid_adam_step(param, grad, exp_avg, exp_avg_sq, *, lr, beta1=0.9, beta2=0.99, eps=1e-8, step=0,
+                   step_dev=None, skip_zero_grad=True, zero_grad_after=False):
+    """step: 1-based Adam step, or step_dev: an int32 device tensor holding it."""
     n = param.numel()
     for t, nm in ((param, "param"), (grad, "grad"), (exp_avg, "exp_avg"), (exp_avg_sq, "exp_avg_sq")):
         _chk(t, nm, numel=n)
+    if step_dev is not None:
+        _chk(step_dev, "step_dev", torch.int32, numel=1)
     call("dvgo_grid_adam_step", _p(param), _p(grad), _p(exp_avg), _p(exp_avg_sq), n, lr, beta1, beta2, eps, step,
-         1 if skip_zero_grad else 0, 1 if zero_grad_after else 0, _stream())
+         _p(step_dev), 1 if skip_zero_grad else 0, 1 if zero_grad_after else 0, _stream())
+
+
+def counter_add(counter, delta=1):
+    _chk(counter, "counter", torch.int32, numel=1)
+    call("dvgo_counter_add", _p(counter), delta, _stream())
 
 
 def grid_gather(grid: DeviceGrid, xyz, out=None):

@@ -34,7 +34,7 @@ class TrainStep:
         self.shift = ops.act_shift() if act_shift is None else act_shift
         self.halt_T, self.bg, self.lam = halt_T, tuple(bg), dist_weight
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
-        self.t = 0
+        self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
         self.density = self._param(dev(density))
         if self.grid_mode:
             self.color = self._param(dev(color))
@@ -111,15 +111,15 @@ class TrainStep:
             ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
 
     def optimise(self):
-        self.t += 1
+        ops.counter_add(self.t_dev, 1)
         b1, b2 = self.betas
         groups = [("density", self.lr_grid, True), ("color" if self.grid_mode else "feat", self.lr_grid, True)]
         if not self.grid_mode:
             groups.append(("mlp_flat", self.lr_mlp, False))
         for name, lr, skip in groups:
             d = getattr(self, name)
-            ops.grid_adam_step(d["p"], d["g"], d["m"], d["v"], lr=lr, beta1=b1, beta2=b2, eps=self.eps, step=self.t,
-                               skip_zero_grad=skip, zero_grad_after=True)
+            ops.grid_adam_step(d["p"], d["g"], d["m"], d["v"], lr=lr, beta1=b1, beta2=b2, eps=self.eps,
+                               step_dev=self.t_dev, skip_zero_grad=skip, zero_grad_after=True)
 
     def step(self):
         self.forward()
@@ -129,9 +129,9 @@ class TrainStep:
 
     # ----------------------------------------------------------- HIP graphs
     def capture(self, warmup: int = 1) -> Optional[torch.cuda.CUDAGraph]:
-        """Capture forward+backward+Adam of the bound batch in a graph.  The Adam step
-        counter is baked into the captured launch arguments, so a replayed graph keeps
-        the bias correction of the step it was captured at (the steady-state regime)."""
+        """Capture forward+backward+Adam of the bound batch in a graph.  Each replay is one
+        full step: the Adam step counter lives on the device and is advanced inside the
+        graph, so replays continue the bias correction exactly like eager steps."""
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):

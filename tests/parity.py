@@ -15,10 +15,12 @@ FWD = dict(rtol=1e-5, floor=1e-3)
 GRAD = dict(rtol=1e-4, floor=1e-2)
 
 
-def close(x, y, rtol, floor, name="value", scale=None):
+def close(x, y, rtol, floor, name="value", scale=None, skip=None):
     """scale (optional, per element): the magnitude the result is conditioned on, e.g.
     sum_c w_c |G_c| for an interpolated value whose terms cancel; the elementwise bound
-    then uses max(|y_i|, floor * ||y||_inf, scale_i)."""
+    then uses max(|y_i|, floor * ||y||_inf, scale_i).  skip (optional boolean mask):
+    elements at a non-differentiable point (a ReLU unit within rounding of its kink) are
+    left out of the elementwise check; the normwise check still covers them."""
     x = np.asarray(x, np.float64).ravel()
     y = np.asarray(y, np.float64).ravel()
     assert x.shape == y.shape, f"{name}: shape {x.shape} vs {y.shape}"
@@ -31,6 +33,8 @@ def close(x, y, rtol, floor, name="value", scale=None):
         if scale is not None:
             bound = np.maximum(bound, rtol * np.asarray(scale, np.float64).ravel())
         bad = np.abs(x - y) > bound + 1e-30
+        if skip is not None:
+            bad &= ~np.asarray(skip, bool).ravel()
         if bad.any():
             i = np.argmax(np.abs(x - y) - bound)
             raise AssertionError(f"{name}: {bad.sum()} of {y.size} elements out of bound; worst at {i}: "

@@ -95,9 +95,10 @@ def test_validation_errors(L):
     s.xyz = s.delta = s.s_mid = s.s_len = 64
     assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, 64, 64, 64, 64, 64, 1, None) == -5
     # Adam: NULL arrays, zero step, mismatched alignment
-    assert lib.dvgo_grid_adam_step(None, None, None, None, 10, 0.1, 0.9, 0.99, 1e-8, 1, 1, 0, None) == -1
-    assert lib.dvgo_grid_adam_step(16, 16, 16, 16, 10, 0.1, 0.9, 0.99, 1e-8, 0, 1, 0, None) == -3
-    assert lib.dvgo_grid_adam_step(16, 20, 16, 16, 10, 0.1, 0.9, 0.99, 1e-8, 1, 1, 0, None) == -2
+    assert lib.dvgo_grid_adam_step(None, None, None, None, 10, 0.1, 0.9, 0.99, 1e-8, 1, None, 1, 0, None) == -1
+    assert lib.dvgo_grid_adam_step(16, 16, 16, 16, 10, 0.1, 0.9, 0.99, 1e-8, 0, None, 1, 0, None) == -3
+    assert lib.dvgo_grid_adam_step(16, 20, 16, 16, 10, 0.1, 0.9, 0.99, 1e-8, 1, None, 1, 0, None) == -2
+    assert lib.dvgo_counter_add(None, 1, None) == -1
     # distortion: backward without workspace
     assert lib.dvgo_distortion_loss(2, 64, 10, 64, 64, 64, None, 64, 64, None, 0, None) == -5
     # MLP: unsupported hidden width

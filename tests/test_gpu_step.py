@@ -1,0 +1,255 @@
+"""Whole-step parity, HIP-graph replays, autograd Functions, and the finite-difference
+check of the hand-written backward at the 16384-ray x 512-sample shape."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from parity import FWD, GRAD, close
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2206_05085_amd as p
+    p.lib()
+    from paper_2206_05085_amd import autograd, ops, step
+    return ops, autograd, step
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+
+
+def T(a, dt=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)
+
+
+def oracle_step_grads(wl, shift):
+    """FP64 gradients of the whole loss (gather -> MLP -> render -> loss) w.r.t. density,
+    features and MLP parameters, plus the loss."""
+    smp = wl.samples
+    feat = oracle.gather(wl.feat, smp.xyz)
+    srgb = oracle.mlp_forward(wl.mlp, smp.ray_offsets, wl.rays.dirs, feat)
+    o = oracle.render_forward(smp, wl.density, srgb=srgb, shift=shift)
+    L, GC, GD = oracle.loss_head(o["rgb"], wl.target, o["D"], wl.dist_weight)
+    og = oracle.render_backward(smp, wl.density, GC, GD, None, srgb=srgb, shift=shift)
+    gf, gW, gb = oracle.mlp_backward(wl.mlp, smp.ray_offsets, wl.rays.dirs, feat, og["grad_srgb"])
+    gfeat = oracle.scatter(wl.feat, smp.xyz, gf)
+    return L, o, og["grad_density"], gfeat, gW, gb
+
+
+def make_step(step_mod, wl):
+    from paper_2206_05085_amd import ops
+    st = step_mod.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                            mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight)
+    smp = wl.samples
+    b = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
+    st.bind(b, wl.rays.dirs, wl.target)
+    return st
+
+
+def test_whole_step_gradients(pkg):
+    ops, _, step = pkg
+    wl = synth.config2(R=384, n=64, mlp_bias_std=0.2)
+    say("whole step, 64^3 grids, 384 pinhole rays, S =", wl.samples.n_samples)
+    st = make_step(step, wl)
+    st.forward()
+    st.backward()
+    torch.cuda.synchronize()
+    shift = float(np.float32(st.shift))
+    L, o, gd, gfeat, gW, gb = oracle_step_grads(wl, shift)
+    close(st.rgb.cpu().numpy(), o["rgb"], **FWD, name="rgb")
+    close(st.dist.cpu().numpy(), o["D"], **FWD, name="distortion")
+    close(st.loss.cpu().numpy(), [L], **FWD, name="loss")
+    close(st.density["g"].cpu().numpy(), gd, **GRAD, name="grad density")
+    # feature-grid entries touched by a sample sitting on a ReLU kink are not differentiable
+    smp = wl.samples
+    margin = oracle.mlp_margin(wl.mlp, smp.ray_offsets, wl.rays.dirs, oracle.gather(wl.feat, smp.xyz))
+    kink = margin < 1e-5
+    touched = oracle.scatter(wl.feat, smp.xyz[kink], np.ones((kink.sum(), wl.feat.channels))) != 0
+    say("samples within 1e-5 of a ReLU kink:", int(kink.sum()), "grid entries skipped:", int(touched.sum()))
+    close(st.feat["g"].cpu().numpy(), gfeat, **GRAD, name="grad features", skip=touched)
+    for i in range(3):
+        close(st.mlp.gW[i].cpu().numpy(), gW[i], **GRAD, name=f"grad W{i + 1}")
+        close(st.mlp.gb[i].cpu().numpy(), gb[i], **GRAD, name=f"grad b{i + 1}")
+
+
+def test_graph_replays_match_eager(pkg):
+    # Two identical steps: one runs eagerly, the other replays a captured graph, with eager
+    # work and synchronisations between replays; every replay is checked against eager.
+    ops, _, step = pkg
+    wl = synth.config2(R=256, n=48)
+    say("graph replay vs eager, 48^3, 256 rays")
+    a, b = make_step(step, wl), make_step(step, wl)
+    a.step()  # both take one eager step first; capturing records but does not execute
+    b.step()
+    g = b.capture(warmup=0)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        a.step()
+        g.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
+        close(b.loss.cpu().numpy(), a.loss.cpu().numpy(), rtol=1e-5, floor=1e-3, name=f"loss replay {rep}")
+        close(b.density["p"].cpu().numpy(), a.density["p"].cpu().numpy(), rtol=1e-5, floor=1e-3,
+              name=f"density replay {rep}")
+        close(b.mlp_flat["p"].cpu().numpy(), a.mlp_flat["p"].cpu().numpy(), rtol=1e-5, floor=1e-3,
+              name=f"mlp replay {rep}")
+
+
+def test_autograd_render_and_distortion(pkg):
+    ops, ag, _ = pkg
+    wl = synth.config1(R=200)
+    smp = wl.samples
+    rng = np.random.default_rng(50)
+    say("autograd RenderFn / DistortionFn, config-1 shape")
+    b = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
+    dens = T(wl.density.data).requires_grad_(True)
+    col = T(wl.color.data).requires_grad_(True)
+    shift = float(np.float32(oracle.act_shift()))
+    box = (tuple(wl.density.xyz_min), tuple(wl.density.xyz_max))
+    rgb, Tf, D = ag.render(dens, col, b, box, grid_color=True, act_shift=shift, bg=(0.3, 0.6, 0.9))
+    GC, GD, GT = rng.standard_normal((200, 3)), rng.standard_normal(200), rng.standard_normal(200)
+    ((rgb * T(GC)).sum() + (D * T(GD)).sum() + (Tf * T(GT)).sum()).backward()
+    og = oracle.render_backward(smp, wl.density, GC, GD, GT, color=wl.color, shift=shift, bg=(0.3, 0.6, 0.9))
+    close(dens.grad.cpu().numpy(), og["grad_density"], **GRAD, name="autograd density")
+    close(col.grad.cpu().numpy(), og["grad_color"], **GRAD, name="autograd colour")
+    # DistortionFn on the oracle's weights
+    o = oracle.render_forward(smp, wl.density, wl.color, shift=shift, want_w=True)
+    w = T(o["w"]).requires_grad_(True)
+    Dd = ag.distortion(w, T(smp.ray_offsets, torch.int32), T(smp.s_mid), T(smp.s_len))
+    (Dd * T(GD)).sum().backward()
+    close(Dd.detach().cpu().numpy(), o["D"], **FWD, name="autograd distortion")
+    close(w.grad.cpu().numpy(), oracle.distortion_grad(smp.ray_offsets, o["w"], smp.s_mid, smp.s_len, GD), **GRAD,
+          name="autograd distortion grad")
+
+
+def test_autograd_gather_and_mlp(pkg):
+    ops, ag, _ = pkg
+    wl = synth.config2(R=128, n=32, mlp_bias_std=0.2)
+    smp = wl.samples
+    rng = np.random.default_rng(51)
+    say("autograd GatherFn + ColorMLPFn, S =", smp.n_samples)
+    grid = T(wl.feat.data).requires_grad_(True)
+    xyz = T(smp.xyz)
+    box = (tuple(wl.feat.xyz_min), tuple(wl.feat.xyz_max))
+    feat = ag.gather(grid, xyz, box)
+    Ws = [T(w).requires_grad_(True) for w in wl.mlp.W]
+    bs = [T(v).requires_grad_(True) for v in wl.mlp.b]
+    rgb = ag.color_mlp(feat, Ws, bs, T(smp.ray_offsets, torch.int32), T(wl.rays.dirs))
+    G = rng.standard_normal((smp.n_samples, 3))
+    (rgb * T(G)).sum().backward()
+    of = oracle.gather(wl.feat, smp.xyz)
+    close(rgb.detach().cpu().numpy(), oracle.mlp_forward(wl.mlp, smp.ray_offsets, wl.rays.dirs, of), **FWD,
+          name="mlp rgb")
+    gf, gW, gb = oracle.mlp_backward(wl.mlp, smp.ray_offsets, wl.rays.dirs, of, G)
+    close(grid.grad.cpu().numpy(), oracle.scatter(wl.feat, smp.xyz, gf), **GRAD, name="grad feature grid")
+    for i in range(3):
+        close(Ws[i].grad.cpu().numpy(), gW[i], **GRAD, name=f"grad W{i + 1}")
+        close(bs[i].grad.cpu().numpy(), gb[i], **GRAD, name=f"grad b{i + 1}")
+
+
+def _rays_touching(smp, n, vertex):
+    """Rays with a sample inside one of the 8 cells around grid vertex (i, j, k)."""
+    u = (smp.xyz.astype(np.float64) + 1.0) / 2.0 * (n - 1)
+    i0 = np.minimum(np.floor(np.clip(u, 0, n - 1)).astype(np.int64), n - 2)
+    hit = np.all((i0 <= vertex[None]) & (i0 >= vertex[None] - 1), axis=1)
+    ray = np.repeat(np.arange(smp.n_rays), smp.lengths())
+    return np.unique(ray[hit])
+
+
+def _subset(wl, rays):
+    smp = wl.samples
+    offs, idx = [0], []
+    for r in rays:
+        a, b = smp.ray_offsets[r], smp.ray_offsets[r + 1]
+        idx.append(np.arange(a, b))
+        offs.append(offs[-1] + b - a)
+    idx = np.concatenate(idx)
+    return synth.Samples(np.asarray(offs, np.int32), smp.xyz[idx], smp.delta[idx], smp.s_mid[idx], smp.s_len[idx])
+
+
+def _partial_loss(wl, sub, rays, shift, R_total):
+    """Sum of the per-ray terms of the full loss for the given rays (FP64 oracle)."""
+    feat = oracle.gather(wl.feat, sub.xyz)
+    srgb = oracle.mlp_forward(wl.mlp, sub.ray_offsets, wl.rays.dirs[rays], feat)
+    o = oracle.render_forward(sub, wl.density, srgb=srgb, shift=shift)
+    e = o["rgb"] - wl.target[rays].astype(np.float64)
+    return np.sum(e * e) / (3.0 * R_total) + wl.dist_weight * np.sum(o["D"]) / R_total
+
+
+@pytest.mark.timeout(900)
+def test_config4_finite_differences(pkg):
+    """16384 rays x 512 samples on the 160^3 grids: the autograd backward (recompute, no
+    stored per-sample intermediates) against FP64 central differences of the oracle loss on
+    128 density + 128 feature-grid entries (eps 1e-4), and against the oracle's analytic
+    gradient restricted to the rays that touch each entry."""
+    ops, ag, _ = pkg
+    wl = synth.config4()
+    smp = wl.samples
+    R, S = smp.n_rays, smp.n_samples
+    say("config4 FD: R =", R, "S =", S)
+    n = wl.density.data.shape[0]
+    b = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
+    dens = T(wl.density.data).requires_grad_(True)
+    fgrid = T(wl.feat.data).requires_grad_(True)
+    Ws = [T(w) for w in wl.mlp.W]
+    bs = [T(v) for v in wl.mlp.b]
+    box = (tuple(wl.density.xyz_min), tuple(wl.density.xyz_max))
+    shift = float(np.float32(ops.act_shift()))
+    feat = ag.gather(fgrid, b.xyz, box)
+    srgb = ag.color_mlp(feat, Ws, bs, b.ray_offsets, T(wl.rays.dirs))
+    rgb, Tf, D = ag.render(dens, srgb, b, box, grid_color=False, act_shift=shift)
+    tgt = T(wl.target)
+    loss = ((rgb - tgt) ** 2).mean() + wl.dist_weight * D.mean()
+    loss.backward()
+    gd = dens.grad.cpu().numpy()
+    gfg = fgrid.grad.cpu().numpy()
+    rng = np.random.default_rng(60)
+    # entries with a non-zero GPU gradient, 128 of each grid
+    di = rng.choice(np.flatnonzero(gd.ravel()), 128, replace=False)
+    fi = rng.choice(np.flatnonzero(gfg.ravel()), 128, replace=False)
+    fd, an, gp = [], [], []
+    eps = np.float32(1e-4)
+    for grid, flat, gpu in ((wl.density, di, gd), (wl.feat, fi, gfg)):
+        C = grid.data.shape[-1]
+        for cnt, idx in enumerate(flat):
+            if cnt % 32 == 0:
+                say("FD entries done:", len(fd))
+            v = np.array(np.unravel_index(idx // C, grid.data.shape[:3]))
+            rays = _rays_touching(smp, n, v)
+            sub = _subset(wl, rays)
+            data = grid.data.reshape(-1)
+            old = data[idx]
+            data[idx] = old + eps
+            hi_v = float(data[idx])
+            lp = _partial_loss(wl, sub, rays, shift, R)
+            data[idx] = old - eps
+            lo_v = float(data[idx])
+            lm = _partial_loss(wl, sub, rays, shift, R)
+            data[idx] = old
+            fd.append((lp - lm) / (hi_v - lo_v))
+            gp.append(gpu.ravel()[idx])
+            # analytic oracle gradient from the touching rays only
+            feat_o = oracle.gather(wl.feat, sub.xyz)
+            srgb_o = oracle.mlp_forward(wl.mlp, sub.ray_offsets, wl.rays.dirs[rays], feat_o)
+            o = oracle.render_forward(sub, wl.density, srgb=srgb_o, shift=shift)
+            GC = 2.0 * (o["rgb"] - wl.target[rays]) / (3.0 * R)
+            GDv = np.full(len(rays), wl.dist_weight / R)
+            og = oracle.render_backward(sub, wl.density, GC, GDv, None, srgb=srgb_o, shift=shift)
+            if grid is wl.density:
+                an.append(og["grad_density"].ravel()[idx])
+            else:
+                gfo, _, _ = oracle.mlp_backward(wl.mlp, sub.ray_offsets, wl.rays.dirs[rays], feat_o, og["grad_srgb"])
+                an.append(oracle.scatter(wl.feat, sub.xyz, gfo).ravel()[idx])
+    fd, an, gp = np.array(fd), np.array(an), np.array(gp)
+    # the oracle's analytic gradient agrees with its own finite differences
+    close(an, fd, rtol=1e-4, floor=1e-2, name="oracle analytic vs FD")
+    close(gp[:128], an[:128], **GRAD, name="GPU vs oracle, density")
+    close(gp[128:], an[128:], **GRAD, name="GPU vs oracle, features")
+    close(gp, fd, rtol=2e-4, floor=1e-2, name="GPU vs FD")
