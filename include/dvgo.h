@@ -51,7 +51,7 @@ enum {
     DVGO_ERR_ABI = -8          /* struct_size mismatch */
 };
 
-enum { DVGO_COLOR_GRID = 0, DVGO_COLOR_SAMPLES = 1 };
+enum { DVGO_COLOR_GRID = 0, DVGO_COLOR_SAMPLES = 1, DVGO_COLOR_NONE = 2 };
 
 /* Dense vertex grid, channel-last: value (i,j,k,c) at data[((i*ny + j)*nz + k)*ch_stride + c].
  * Vertex i along x sits at xyz_min[0] + i*(xyz_max[0]-xyz_min[0])/(nx-1) (vertices on the box
@@ -90,8 +90,9 @@ typedef struct dvgo_samples {
  *   alpha, section 5.4).  halt_T: stop a ray once its accumulated transmittance falls below
  *   this value (section 3; the paper uses 1e-3); 0 disables halting.  bg: background colour
  *   composited with the final transmittance.  color_mode: DVGO_COLOR_GRID (colour =
- *   trilinear value of a 3-channel colour grid) or DVGO_COLOR_SAMPLES (colour given per
- *   sample, e.g. by the colour MLP).  want_dist: also compute the distortion loss (Eq. 1). */
+ *   trilinear value of a 3-channel colour grid), DVGO_COLOR_SAMPLES (colour given per
+ *   sample, e.g. by the colour MLP) or DVGO_COLOR_NONE (density only: every sample colour is
+ *   0, forward only).  want_dist: also compute the distortion loss (Eq. 1). */
 typedef struct dvgo_render_params {
     uint32_t struct_size;
     float act_shift;
@@ -130,11 +131,12 @@ int dvgo_render_state_size(int32_t n_rays, int64_t n_samples, size_t *bytes);
  * computed in O(N) by prefix scans.
  * color: the 3-channel colour grid (DVGO_COLOR_GRID) or NULL; sample_rgb [S,3] for
  * DVGO_COLOR_SAMPLES, else NULL.  Outputs rgb [R,3], T_final [R], dist [R] (NULL allowed
- * when want_dist = 0).  state: device buffer of dvgo_render_state_size bytes, written here
- * and read by the backward; it must stay unchanged in between. */
+ * when want_dist = 0), and optionally the per-sample weights sample_w [S] (NULL: not
+ * written; halted samples get 0).  state: device buffer of dvgo_render_state_size bytes,
+ * written here and read by the backward; it must stay unchanged in between. */
 int dvgo_render_forward(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
                         const dvgo_grid *color, const float *sample_rgb, float *rgb, float *T_final, float *dist,
-                        void *state, size_t state_bytes, void *stream);
+                        float *sample_w, void *state, size_t state_bytes, void *stream);
 
 /* Backward of dvgo_render_forward (recomputes each ray from the saved chunk checkpoints;
  * no per-sample intermediates are stored).  Upstream gradients: grad_rgb [R,3] (required),
@@ -208,6 +210,81 @@ int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ra
  * (sections 5.3, 5.4). */
 int dvgo_loss_head(int32_t n_rays, const float *rgb, const float *target, const float *dist, float dist_weight,
                    float *loss, float *grad_rgb, float *grad_dist, void *stream);
+
+/* ------------------------------------------------------------------ proposal stage
+ * Learned sample placement (not part of the paper, which relies on its occupancy mask,
+ * section 1): a coarse density-only pass feeds a small MLP that predicts where a ray's
+ * weight lies; fine samples are drawn there, with plain uniform sampling as fallback. */
+
+/* Rays of a bounded scene: origins [R,3], unit directions [R,3], and the clipped interval
+ * [t_near, t_far] [R] (t_far <= t_near marks a ray that misses the scene box). */
+typedef struct dvgo_rays {
+    uint32_t struct_size;
+    int32_t n_rays;
+    const float *origins;
+    const float *dirs;
+    const float *t_near;
+    const float *t_far;
+} dvgo_rays;
+
+/* Proposal MLP: n_layers linear layers n_bins -> hidden -> ... -> n_bins with ReLU between,
+ * float32 master weights W[l] [out][in] and b[l] [out]; the kernels round weights,
+ * activations and back-propagated gradients to bfloat16 (round to nearest even) and
+ * accumulate products in float32.  gW/gb receive += in dvgo_proposal_backward.
+ * Supported: n_bins = 64, hidden = 64, n_layers = 4. */
+typedef struct dvgo_proposal {
+    uint32_t struct_size;
+    int32_t n_bins;
+    int32_t hidden;
+    int32_t n_layers;
+    const float *W[4];
+    const float *b[4];
+    float *gW[4];
+    float *gb[4];
+} dvgo_proposal;
+
+/* Coarse pass: 64 uniform samples per ray at s = (k+1/2)/64 of [t_near, t_far], density-
+ * only alpha (same activation as dvgo_render_forward, delta = (t_far-t_near)/64/voxel),
+ * front-to-back weights w_k, network input feat_k = ln(1 + w_k/eps) [R,64]; w_coarse [R,64]
+ * (may be NULL) receives the weights. */
+int dvgo_proposal_coarse(const dvgo_rays *rays, const dvgo_grid *density, float act_shift, float voxel, float eps,
+                         float *feat, float *w_coarse, void *stream);
+
+/* Proposal forward: logits [R,64], softmax probabilities prob [R,64] and entropy
+ * -sum p ln p [R] (each output may be NULL, not all).  feat/logits/prob 16-byte aligned. */
+int dvgo_proposal_forward(const dvgo_proposal *p, int32_t n_rays, const float *feat, float *logits, float *prob,
+                          float *entropy, void *stream);
+
+int dvgo_proposal_workspace_size(const dvgo_proposal *p, int32_t n_rays, size_t *bytes);
+
+/* Proposal training backward: cross-entropy -(1/R) sum_r sum_b target_rb ln softmax(z_r)_b
+ * against target histograms [R,64] (rows sum to 1); loss[0] (may be NULL) receives the loss,
+ * p->gW / p->gb receive += the gradients.  ws: dvgo_proposal_workspace_size bytes. */
+int dvgo_proposal_backward(const dvgo_proposal *p, int32_t n_rays, const float *feat, const float *target,
+                           float *loss, void *ws, size_t ws_bytes, void *stream);
+
+/* Training target: histogram of rendered weights w [S] over n_bins equal bins of s_mid,
+ * normalised to sum 1 when the ray's total weight is at least min_mass, else uniform:
+ * hist [R, n_bins].  Supported: n_bins = 64. */
+int dvgo_histogram(int32_t n_rays, const int32_t *ray_offsets, const float *w, const float *s_mid, int32_t n_bins,
+                   float min_mass, float *hist, void *stream);
+
+/* Offsets of the fine batch: rays that miss get 0 samples, rays with entropy > tau get
+ * n_plain (fallback to plain uniform sampling), the others n_fine; writes the exclusive
+ * prefix ray_offsets [R+1].  Needs 1 <= n_fine <= 256. */
+int dvgo_resample_offsets(const dvgo_rays *rays, const float *entropy, float tau, int32_t n_fine, int32_t n_plain,
+                          int32_t *ray_offsets, void *stream);
+
+/* Fills the fine batch laid out by dvgo_resample_offsets.  Fallback rays: s_mid =
+ * (k+1/2)/n_plain, s_len = 1/n_plain.  Others (interval resampling): n_fine+1 interval ends
+ * e_j = F^{-1}(j/n_fine) of the 64-bin piecewise-constant density prob [R,64] (first bin whose
+ * right CDF exceeds u, linear inside the bin; u = 1 maps to the right edge of the last bin
+ * with mass); sample j is the interval [e_j, e_{j+1}] at its midpoint: s_mid = (e_j+e_{j+1})/2,
+ * s_len = e_{j+1} - e_j.  Points x = o + t d, t = t_near + s (t_far - t_near); delta = s_len
+ * (t_far - t_near)/voxel.  Outputs hold ray_offsets[R] samples. */
+int dvgo_resample(const dvgo_rays *rays, const float *prob, const float *entropy, float tau,
+                  const int32_t *ray_offsets, int32_t n_fine, int32_t n_plain, float voxel, float *xyz, float *delta,
+                  float *s_mid, float *s_len, void *stream);
 
 #ifdef __cplusplus
 }

@@ -285,6 +285,26 @@ def mlp_margin(mlp, offs, dirs, feat, F=4):
     return out
 
 
+def mlp_kink_slack(mlp, offs, dirs, feat, grad_rgb, thr=1e-5, F=4):
+    """Per-element slack of the colour-head gradients at ReLU kinks (see orc_mlp_kink_slack).
+    Returns (slack_feat [S,C], [W1, W2, W3] slacks, [b1, b2, b3] slacks)."""
+    keep = _Keep()
+    feat = keep(_c(feat, np.float64))
+    P = _mlp_struct(mlp, keep, feat.shape[1], F)
+    offs = keep(_c(offs, np.int32))
+    dirs = keep(_c(dirs, np.float32))
+    gr = keep(_c(grad_rgb, np.float64))
+    sizes = [mlp.W[0].size, mlp.b[0].size, mlp.W[1].size, mlp.b[1].size, mlp.W[2].size, mlp.b[2].size]
+    sf = np.zeros_like(feat)
+    sp = np.zeros(sum(sizes))
+    lib().orc_mlp_kink_slack(C.byref(P), C.c_int32(offs.shape[0] - 1), _ptr(offs), _ptr(dirs), _ptr(feat), _ptr(gr),
+                             C.c_double(thr), _ptr(sf), _ptr(sp))
+    parts = np.split(sp, np.cumsum(sizes)[:-1])
+    W = [parts[0].reshape(mlp.W[0].shape), parts[2].reshape(mlp.W[1].shape), parts[4].reshape(mlp.W[2].shape)]
+    b = [parts[1], parts[3], parts[5]]
+    return sf, W, b
+
+
 def mlp_backward(mlp, offs, dirs, feat, grad_rgb, F=4):
     """Returns (grad_feat [S,C], [gW1, gW2, gW3], [gb1, gb2, gb3])."""
     keep = _Keep()
@@ -386,3 +406,44 @@ def resample(prob, n, rays, voxel):
     lib().orc_resample(C.c_int32(R), C.c_int32(B), _ptr(prob), C.c_int32(n), _ptr(o), _ptr(d), _ptr(tn), _ptr(tf),
                        C.c_double(voxel), _ptr(xyz), _ptr(dl), _ptr(sm), _ptr(sl))
     return dict(xyz=xyz, delta=dl, s_mid=sm, s_len=sl)
+
+
+def proposal_coarse(rays, density, voxel, B=64, eps=1e-4, shift=None):
+    """Returns (w_coarse [R,B], feat [R,B]) of the proposal's coarse pass."""
+    keep = _Keep()
+    gd = grid_struct(density, keep)
+    o, d = keep(_c(rays.origins, np.float32)), keep(_c(rays.dirs, np.float32))
+    tn, tf = keep(_c(rays.t_near, np.float32)), keep(_c(rays.t_far, np.float32))
+    R = o.shape[0]
+    w = np.zeros((R, B))
+    f = np.zeros((R, B))
+    shift = act_shift() if shift is None else shift
+    lib().orc_proposal_coarse(C.c_int32(R), _ptr(o), _ptr(d), _ptr(tn), _ptr(tf), C.byref(gd), C.c_double(shift),
+                              C.c_double(voxel), C.c_int32(B), C.c_double(eps), _ptr(w), _ptr(f))
+    return w, f
+
+
+def resample_batch(prob, H, tau, n_fine, n_plain, rays, voxel):
+    """Returns dict(ray_offsets, xyz, delta, s_mid, s_len) of the proposal's ragged fine batch."""
+    prob = _c(prob, np.float64)
+    Hh = _c(H, np.float64)
+    R, B = prob.shape
+    o, d = _c(rays.origins, np.float32), _c(rays.dirs, np.float32)
+    tn, tf = _c(rays.t_near, np.float32), _c(rays.t_far, np.float32)
+    cap = R * max(n_fine, n_plain)
+    offs = np.zeros(R + 1, np.int32)
+    xyz, dl, sm, sl = np.zeros((cap, 3)), np.zeros(cap), np.zeros(cap), np.zeros(cap)
+    lib().orc_resample_batch(C.c_int32(R), C.c_int32(B), _ptr(prob), _ptr(Hh), C.c_double(tau), C.c_int32(n_fine),
+                             C.c_int32(n_plain), _ptr(o), _ptr(d), _ptr(tn), _ptr(tf), C.c_double(voxel), _ptr(offs),
+                             _ptr(xyz), _ptr(dl), _ptr(sm), _ptr(sl))
+    S = int(offs[-1])
+    return dict(ray_offsets=offs, xyz=xyz[:S], delta=dl[:S], s_mid=sm[:S], s_len=sl[:S])
+
+
+def softmax_entropy(logits):
+    lg = _c(logits, np.float64)
+    R, B = lg.shape
+    p = np.zeros((R, B))
+    H = np.zeros(R)
+    lib().orc_softmax_entropy(C.c_int32(R), C.c_int32(B), _ptr(lg), _ptr(p), _ptr(H))
+    return p, H

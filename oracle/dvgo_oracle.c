@@ -537,6 +537,97 @@ void orc_mlp_margin(const orc_mlp *P, int32_t R, const int32_t *offs, const floa
     }
 }
 
+/* One sample's contribution to every colour-head gradient, with the ReLU mask of one
+ * hidden unit optionally inverted (flip_layer 1 or 2, unit flip_unit; 0 = none).
+ * out = [dfeat (C) | dW1 | db1 | dW2 | db2 | dW3 | db3]. */
+static void mlp_sample_grads(const orc_mlp *P, const double *x, const double *g, int flip_layer, int flip_unit,
+                             double *out)
+{
+    int I = P->C + 3 + 6 * P->F, H = P->H;
+    double *z1 = malloc(sizeof(double) * H), *h1 = malloc(sizeof(double) * H);
+    double *z2 = malloc(sizeof(double) * H), *h2 = malloc(sizeof(double) * H);
+    double *d2 = malloc(sizeof(double) * H), *d1 = malloc(sizeof(double) * H), rgb[3], d3[3];
+    mlp_fwd_one(P, x, z1, h1, z2, h2, rgb);
+    double *df = out, *W1 = df + P->C, *b1 = W1 + (int64_t)H * I, *W2 = b1 + H, *b2 = W2 + (int64_t)H * H,
+           *W3 = b2 + H, *b3 = W3 + 3 * H;
+    for (int i = 0; i < 3; ++i) {
+        d3[i] = g[i] * rgb[i] * (1.0 - rgb[i]);
+        b3[i] = d3[i];
+        for (int j = 0; j < H; ++j) W3[i * H + j] = d3[i] * h2[j];
+    }
+    for (int j = 0; j < H; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < 3; ++i) t += (double)P->W3[i * H + j] * d3[i];
+        int on = z2[j] > 0;
+        if (flip_layer == 2 && flip_unit == j) on = !on;
+        d2[j] = on ? t : 0.0;
+    }
+    for (int i = 0; i < H; ++i) {
+        b2[i] = d2[i];
+        for (int j = 0; j < H; ++j) W2[i * H + j] = d2[i] * h1[j];
+    }
+    for (int j = 0; j < H; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < H; ++i) t += (double)P->W2[i * H + j] * d2[i];
+        int on = z1[j] > 0;
+        if (flip_layer == 1 && flip_unit == j) on = !on;
+        d1[j] = on ? t : 0.0;
+    }
+    for (int i = 0; i < H; ++i) {
+        b1[i] = d1[i];
+        for (int j = 0; j < I; ++j) W1[i * I + j] = d1[i] * x[j];
+    }
+    for (int c = 0; c < P->C; ++c) {
+        double t = 0.0;
+        for (int i = 0; i < H; ++i) t += (double)P->W1[i * I + c] * d1[i];
+        df[c] = t;
+    }
+    free(z1); free(h1); free(z2); free(h2); free(d2); free(d1);
+}
+
+/* Slack of the colour-head gradients at non-differentiable points: for every hidden unit
+ * whose pre-activation is within thr (relative to |b| + sum |W x|) of its ReLU kink, the
+ * absolute change of each gradient when that unit's mask is inverted, summed over such
+ * units.  Either mask is a valid (sub)gradient there, so a float32 evaluation may land on
+ * either side.  slack_feat [S,C] and slack_par [n_params] (W1, b1, W2, b2, W3, b3) are
+ * accumulated (+=). */
+void orc_mlp_kink_slack(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
+                        const double *grad_rgb, double thr, double *slack_feat, double *slack_par)
+{
+    int64_t S = offs[R];
+    int I = P->C + 3 + 6 * P->F, H = P->H;
+    int64_t np = (int64_t)H * I + H + (int64_t)H * H + H + 3 * H + 3, nout = P->C + np;
+    double *x = malloc(sizeof(double) * I), *a = malloc(sizeof(double) * nout), *b = malloc(sizeof(double) * nout);
+    double *z1 = malloc(sizeof(double) * H), *h1 = malloc(sizeof(double) * H);
+    for (int64_t k = 0; k < S; ++k) {
+        int64_t r = find_ray(R, offs, k);
+        for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
+        view_pe(dirs + 3 * r, P->F, x + P->C);
+        int computed = 0;
+        for (int layer = 1; layer <= 2; ++layer)
+            for (int i = 0; i < H; ++i) {
+                double z, mag;
+                if (layer == 1) {
+                    z = P->b1[i];
+                    mag = fabs((double)P->b1[i]);
+                    for (int j = 0; j < I; ++j) { z += (double)P->W1[i * I + j] * x[j]; mag += fabs((double)P->W1[i * I + j] * x[j]); }
+                    z1[i] = z;
+                    h1[i] = z > 0 ? z : 0.0;
+                } else {
+                    z = P->b2[i];
+                    mag = fabs((double)P->b2[i]);
+                    for (int j = 0; j < H; ++j) { z += (double)P->W2[i * H + j] * h1[j]; mag += fabs((double)P->W2[i * H + j] * h1[j]); }
+                }
+                if (!(mag > 0 && fabs(z) < thr * mag)) continue;
+                if (!computed) { mlp_sample_grads(P, x, grad_rgb + 3 * k, 0, 0, a); computed = 1; }
+                mlp_sample_grads(P, x, grad_rgb + 3 * k, layer, i, b);
+                for (int c = 0; c < P->C; ++c) slack_feat[k * P->C + c] += fabs(b[c] - a[c]);
+                for (int64_t q = 0; q < np; ++q) slack_par[q] += fabs(b[P->C + q] - a[P->C + q]);
+            }
+    }
+    free(x); free(a); free(b); free(z1); free(h1);
+}
+
 /* Backward of the colour head for upstream grad_rgb [S,3]: writes grad_feat [S,C] and
  * accumulates (+=) the parameter gradients.  Samples are split into fixed contiguous
  * blocks whose partial sums are added in block order, so the result does not depend on
@@ -748,42 +839,146 @@ void orc_histogram(int32_t R, const int32_t *offs, const double *w, const float 
     }
 }
 
-/* Inverse-CDF placement of n fine samples per ray from a piecewise-constant density of
- * B equal bins on s in [0,1] with bin masses p.  u_j = (j + 1/2)/n; sample j lies in the
- * first bin b whose right CDF value exceeds u_j (zero-mass bins are never chosen), at
- * s_j = (b + (u_j - CDF_b)/p_b)/B.  Each fine sample owns the interval between the
- * midpoints to its neighbours, closed by 0 and 1: s_mid = s_j, s_len = its length.
- * Bounded rays map s linearly to t in [t_near, t_far]: x = o + t d, and delta is the
- * interval's t-length over the voxel size. */
+/* Inverse CDF of a piecewise-constant density of B equal bins on s in [0,1] with bin
+ * masses p (cdf[b] = sum of the first b masses): the point where the CDF reaches u.
+ * For 0 <= u < cdf[B] it lies in the first bin whose right CDF value exceeds u (zero-mass
+ * bins are never chosen), linearly inside the bin; u >= cdf[B] maps to the right edge of
+ * the last bin with mass. */
+static double inv_cdf(int B, const double *p, const double *cdf, double u)
+{
+    if (!(u < cdf[B])) {
+        int b = B - 1;
+        while (b > 0 && !(p[b] > 0)) --b;
+        return (b + 1.0) / B;
+    }
+    int b = 0;
+    while (b < B - 1 && !(cdf[b + 1] > u)) ++b;
+    double frac = p[b] > 0 ? (u - cdf[b]) / p[b] : 0.0;
+    if (frac < 0) frac = 0;
+    if (frac > 1) frac = 1;
+    return (b + frac) / B;
+}
+
+/* Interval resampling of n fine samples per ray: n + 1 interval ends e_j = F^{-1}(u_j) at
+ * u_j = (j/n) * cdf[B] (F the piecewise-constant CDF above), sample j = the interval
+ * [e_j, e_{j+1}] represented by its midpoint: s_mid = (e_j + e_{j+1})/2, s_len = e_{j+1} - e_j.
+ * Stretches of zero mass outside [e_0, e_n] carry no sample.  Bounded rays map s linearly to
+ * t in [t_near, t_far]: x = o + t d; delta is the interval's t-length over the voxel size. */
+static void resample_ray(int B, const double *pr, double *cdf, double *e, int n, const float *o, const float *d,
+                         double tn, double tf, double voxel, double *xyz, double *delta, double *s_mid, double *s_len)
+{
+    cdf[0] = 0.0;
+    for (int b = 0; b < B; ++b) cdf[b + 1] = cdf[b] + pr[b];
+    for (int j = 0; j <= n; ++j) e[j] = inv_cdf(B, pr, cdf, (double)j / n * cdf[B]);
+    double len = tf - tn;
+    for (int j = 0; j < n; ++j) {
+        double sm = 0.5 * (e[j] + e[j + 1]), t = tn + sm * len;
+        for (int a = 0; a < 3; ++a) xyz[3 * j + a] = (double)o[a] + t * (double)d[a];
+        s_mid[j] = sm;
+        s_len[j] = e[j + 1] - e[j];
+        delta[j] = s_len[j] * len / voxel;
+    }
+}
+
 void orc_resample(int32_t R, int32_t B, const double *p, int32_t n, const float *o, const float *d, const float *tn,
                   const float *tf, double voxel, double *xyz, double *delta, double *s_mid, double *s_len)
 {
-    double *cdf = malloc(sizeof(double) * (B + 1)), *s = malloc(sizeof(double) * n);
+    double *cdf = malloc(sizeof(double) * (B + 1)), *e = malloc(sizeof(double) * (n + 1));
     for (int32_t r = 0; r < R; ++r) {
-        const double *pr = p + (int64_t)r * B;
-        cdf[0] = 0.0;
-        for (int b = 0; b < B; ++b) cdf[b + 1] = cdf[b] + pr[b];
-        for (int j = 0; j < n; ++j) {
-            double u = (j + 0.5) / n * cdf[B];
-            int b = 0;
-            while (b < B - 1 && !(cdf[b + 1] > u)) ++b;
-            double frac = pr[b] > 0 ? (u - cdf[b]) / pr[b] : 0.5;
-            if (frac < 0) frac = 0;
-            if (frac > 1) frac = 1;
-            s[j] = (b + frac) / B;
+        int64_t k = (int64_t)r * n;
+        resample_ray(B, p + (int64_t)r * B, cdf, e, n, o + 3 * r, d + 3 * r, tn[r], tf[r], voxel, xyz + 3 * k,
+                     delta + k, s_mid + k, s_len + k);
+    }
+    free(cdf);
+    free(e);
+}
+
+/* Coarse pass of the proposal stage (learned sample placement; not part of the paper,
+ * which relies on its occupancy mask, section 1): B uniform samples per ray at
+ * s = (k + 1/2)/B between t_near and t_far, density-only alpha (the same activation as
+ * the render), front-to-back weights w_k = T_k alpha_k, and the network input
+ * feat_k = ln(1 + w_k / eps).  Rays with t_far <= t_near get zeros. */
+void orc_proposal_coarse(int32_t R, const float *o, const float *d, const float *tn, const float *tf,
+                         const orc_grid *dens, double act_shift, double voxel, int32_t B, double eps, double *w_out,
+                         double *feat_out)
+{
+#pragma omp parallel for schedule(static)
+    for (int32_t r = 0; r < R; ++r) {
+        double *w = w_out + (int64_t)r * B, *f = feat_out + (int64_t)r * B;
+        double a = tn[r], b = tf[r];
+        if (!(b > a)) {
+            for (int k = 0; k < B; ++k) w[k] = f[k] = 0.0;
+            continue;
         }
+        double delta = (b - a) / B / voxel, T = 1.0;
+        for (int k = 0; k < B; ++k) {
+            double t = a + (k + 0.5) / B * (b - a);
+            float p[3];
+            for (int ax = 0; ax < 3; ++ax) p[ax] = (float)((double)o[3 * r + ax] + t * (double)d[3 * r + ax]);
+            double raw;
+            interp(dens, p, &raw);
+            double x = softplus(raw + act_shift) * delta;
+            double alpha = -expm1(-x);
+            w[k] = T * alpha;
+            T *= exp(-x);
+            f[k] = log1p(w[k] / eps);
+        }
+    }
+}
+
+/* Ragged fine batch from proposal probabilities p [R,B] and entropies H [R]:
+ * rays with t_far <= t_near get no samples; rays with H > tau fall back to n_plain
+ * uniform samples (s_mid = (k + 1/2)/n_plain, s_len = 1/n_plain); the others get n_fine
+ * samples by interval resampling as in orc_resample.  Points: x = o + t d with t linear
+ * in s on [t_near, t_far]; delta = s_len (t_far - t_near) / voxel.  offs [R+1] is written;
+ * the per-sample outputs must hold offs[R] entries. */
+void orc_resample_batch(int32_t R, int32_t B, const double *p, const double *H, double tau, int32_t n_fine,
+                        int32_t n_plain, const float *o, const float *d, const float *tn, const float *tf, double voxel,
+                        int32_t *offs, double *xyz, double *delta, double *s_mid, double *s_len)
+{
+    offs[0] = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        int n = !(tf[r] > tn[r]) ? 0 : (H[r] > tau ? n_plain : n_fine);
+        offs[r + 1] = offs[r] + n;
+    }
+    double *cdf = malloc(sizeof(double) * (B + 1)), *s = malloc(sizeof(double) * (n_fine + 1));
+    for (int32_t r = 0; r < R; ++r) {
+        int n = offs[r + 1] - offs[r];
+        if (n == 0) continue;
         double len = (double)tf[r] - (double)tn[r];
-        for (int j = 0; j < n; ++j) {
-            double lo = j == 0 ? 0.0 : 0.5 * (s[j - 1] + s[j]);
-            double hi = j == n - 1 ? 1.0 : 0.5 * (s[j] + s[j + 1]);
-            int64_t k = (int64_t)r * n + j;
-            double t = (double)tn[r] + s[j] * len;
-            for (int a = 0; a < 3; ++a) xyz[3 * k + a] = (double)o[3 * r + a] + t * (double)d[3 * r + a];
-            s_mid[k] = s[j];
-            s_len[k] = hi - lo;
-            delta[k] = (hi - lo) * len / voxel;
+        int64_t base = offs[r];
+        if (n == n_plain && H[r] > tau) {
+            for (int k = 0; k < n; ++k) {
+                double sm = (k + 0.5) / n, t = (double)tn[r] + sm * len;
+                for (int a = 0; a < 3; ++a) xyz[3 * (base + k) + a] = (double)o[3 * r + a] + t * (double)d[3 * r + a];
+                s_mid[base + k] = sm;
+                s_len[base + k] = 1.0 / n;
+                delta[base + k] = len / n / voxel;
+            }
+            continue;
         }
+        resample_ray(B, p + (int64_t)r * B, cdf, s, n, o + 3 * r, d + 3 * r, tn[r], tf[r], voxel, xyz + 3 * base,
+                     delta + base, s_mid + base, s_len + base);
     }
     free(cdf);
     free(s);
+}
+
+/* Softmax probabilities and entropy -sum p ln p of given logits [R,B] (per row). */
+void orc_softmax_entropy(int32_t R, int32_t B, const double *logits, double *prob, double *H)
+{
+    for (int32_t r = 0; r < R; ++r) {
+        const double *z = logits + (int64_t)r * B;
+        double mx = z[0];
+        for (int b = 1; b < B; ++b) mx = z[b] > mx ? z[b] : mx;
+        double s = 0.0;
+        for (int b = 0; b < B; ++b) s += exp(z[b] - mx);
+        double h = 0.0;
+        for (int b = 0; b < B; ++b) {
+            double p = exp(z[b] - mx) / s;
+            prob[(int64_t)r * B + b] = p;
+            if (p > 0) h -= p * log(p);
+        }
+        H[r] = h;
+    }
 }

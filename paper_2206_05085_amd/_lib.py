@@ -15,7 +15,7 @@ VP = C.c_void_p
 OK = 0
 ERRORS = {-1: "ERR_NULL", -2: "ERR_SHAPE", -3: "ERR_RANGE", -5: "ERR_WORKSPACE", -6: "ERR_HIP",
           -7: "ERR_UNSUPPORTED", -8: "ERR_ABI"}
-COLOR_GRID, COLOR_SAMPLES = 0, 1
+COLOR_GRID, COLOR_SAMPLES, COLOR_NONE = 0, 1, 2
 
 
 class DvgoError(RuntimeError):
@@ -46,14 +46,25 @@ class ColorMLP(C.Structure):
                 ("gW1", VP), ("gb1", VP), ("gW2", VP), ("gb2", VP), ("gW3", VP), ("gb3", VP)]
 
 
+class Rays(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_rays", C.c_int32), ("origins", VP), ("dirs", VP),
+                ("t_near", VP), ("t_far", VP)]
+
+
+class Proposal(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("n_bins", C.c_int32), ("hidden", C.c_int32), ("n_layers", C.c_int32),
+                ("W", VP * 4), ("b", VP * 4), ("gW", VP * 4), ("gb", VP * 4)]
+
+
 _I32, _I64, _F, _SZP = C.c_int32, C.c_int64, C.c_float, C.POINTER(C.c_size_t)
+_PR, _PQ = C.POINTER(Rays), C.POINTER(Proposal)
 _PG, _PS, _PP, _PM = C.POINTER(Grid), C.POINTER(Samples), C.POINTER(RenderParams), C.POINTER(ColorMLP)
 
 SIGNATURES = {
     "dvgo_abi_version": (C.c_int, []),
     "dvgo_last_error": (C.c_char_p, []),
     "dvgo_render_state_size": (C.c_int, [_I32, _I64, _SZP]),
-    "dvgo_render_forward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, VP, VP, C.c_size_t, VP]),
+    "dvgo_render_forward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_render_backward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, C.c_size_t, VP, VP, VP, VP, VP]),
     "dvgo_distortion_workspace_size": (C.c_int, [_I32, _I64, _SZP]),
     "dvgo_distortion_loss": (C.c_int, [_I32, VP, _I64, VP, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
@@ -66,6 +77,13 @@ SIGNATURES = {
     "dvgo_mlp_forward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_loss_head": (C.c_int, [_I32, VP, VP, VP, _F, VP, VP, VP, VP]),
+    "dvgo_proposal_coarse": (C.c_int, [_PR, _PG, _F, _F, _F, VP, VP, VP]),
+    "dvgo_proposal_forward": (C.c_int, [_PQ, _I32, VP, VP, VP, VP, VP]),
+    "dvgo_proposal_workspace_size": (C.c_int, [_PQ, _I32, _SZP]),
+    "dvgo_proposal_backward": (C.c_int, [_PQ, _I32, VP, VP, VP, VP, C.c_size_t, VP]),
+    "dvgo_histogram": (C.c_int, [_I32, VP, VP, VP, _I32, _F, VP, VP]),
+    "dvgo_resample_offsets": (C.c_int, [_PR, VP, _F, _I32, _I32, VP, VP]),
+    "dvgo_resample": (C.c_int, [_PR, VP, VP, _F, VP, _I32, _I32, _F, VP, VP, VP, VP, VP]),
 }
 
 _lib = None

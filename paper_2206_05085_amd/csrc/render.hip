@@ -38,7 +38,7 @@ struct RenderArgs {
     float act_shift, halt_T, bg0, bg1, bg2;
     int want_dist;
     // forward outputs / saved state
-    float *rgb, *T_final, *dist;
+    float *rgb, *T_final, *dist, *sample_w;
     int *halt_idx;
     float4 *ckpt;
     // backward
@@ -68,10 +68,12 @@ __device__ __forceinline__ void load_sample(const RenderArgs &a, int k, bool has
         s.c0 = interp_ch(a.col, tc, 0);
         s.c1 = interp_ch(a.col, tc, 1);
         s.c2 = interp_ch(a.col, tc, 2);
-    } else {
+    } else if (MODE == DVGO_COLOR_SAMPLES) {
         s.c0 = a.srgb[3 * k];
         s.c1 = a.srgb[3 * k + 1];
         s.c2 = a.srgb[3 * k + 2];
+    } else {
+        s.c0 = s.c1 = s.c2 = 0.f;
     }
     s.delta = a.delta[k];
     s.x = softplusf(s.raw + a.act_shift) * s.delta;
@@ -112,6 +114,7 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a) {
         }
         const bool live = valid && k < halt;
         const float w = live ? T * s.alpha : 0.f;
+        if (a.sample_w && valid) a.sample_w[k] = w;
         const float wi = wave_incl(w);
         const float u = (live && has_next) ? (W + wi) * (s.mn - s.m) : 0.f;
         const float ui = wave_incl(u);
@@ -123,7 +126,11 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a) {
         L += bcast(xi, 63);
         W += bcast(wi, 63);
         Q += bcast(ui, 63);
-        if (halt < end) break;
+        if (halt < end) {
+            if (a.sample_w)
+                for (int kk = c0 + 64 + ln; kk < end; kk += 64) a.sample_w[kk] = 0.f;
+            break;
+        }
     }
     accC0 = wave_sum(accC0);
     accC1 = wave_sum(accC1);
@@ -278,8 +285,10 @@ int fill_render_args(const dvgo_render_params *p, const dvgo_samples *s, const d
         return set_error(DVGO_ERR_ABI, "dvgo_render_params.struct_size mismatch");
     int rc = check_samples(s);
     if (rc) return rc;
-    if (p->color_mode != DVGO_COLOR_GRID && p->color_mode != DVGO_COLOR_SAMPLES)
+    if (p->color_mode != DVGO_COLOR_GRID && p->color_mode != DVGO_COLOR_SAMPLES && p->color_mode != DVGO_COLOR_NONE)
         return set_error(DVGO_ERR_UNSUPPORTED, "unknown color_mode %d", p->color_mode);
+    if (bwd && p->color_mode == DVGO_COLOR_NONE)
+        return set_error(DVGO_ERR_UNSUPPORTED, "DVGO_COLOR_NONE is forward only");
     if (!(p->halt_T >= 0.f && p->halt_T < 1.f)) return set_error(DVGO_ERR_RANGE, "halt_T must be in [0, 1)");
     memset(&a, 0, sizeof(a));
     rc = make_dev_grid(density, "density", &a.dens, bwd);
@@ -289,7 +298,7 @@ int fill_render_args(const dvgo_render_params *p, const dvgo_samples *s, const d
         rc = make_dev_grid(color, "color", &a.col, bwd);
         if (rc) return rc;
         if (color->channels < 3) return set_error(DVGO_ERR_SHAPE, "color grid needs 3 channels");
-    } else if (s->n_samples > 0 && !sample_rgb) {
+    } else if (p->color_mode == DVGO_COLOR_SAMPLES && s->n_samples > 0 && !sample_rgb) {
         return set_error(DVGO_ERR_NULL, "sample_rgb is NULL in DVGO_COLOR_SAMPLES mode");
     }
     a.n_rays = s->n_rays;
@@ -328,7 +337,7 @@ extern "C" int dvgo_render_state_size(int32_t n_rays, int64_t n_samples, size_t 
 
 extern "C" int dvgo_render_forward(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
                                    const dvgo_grid *color, const float *sample_rgb, float *rgb, float *T_final,
-                                   float *dist, void *state, size_t state_bytes_, void *stream) {
+                                   float *dist, float *sample_w, void *state, size_t state_bytes_, void *stream) {
     RenderArgs a;
     int rc = fill_render_args(p, s, density, color, sample_rgb, false, a);
     if (rc) return rc;
@@ -341,12 +350,15 @@ extern "C" int dvgo_render_forward(const dvgo_render_params *p, const dvgo_sampl
     a.rgb = rgb;
     a.T_final = T_final;
     a.dist = dist;
+    a.sample_w = sample_w;
     split_state(state, s->n_rays, &a.halt_idx, &a.ckpt);
     const dim3 grid((s->n_rays + 3) / 4), block(256);
     if (p->color_mode == DVGO_COLOR_GRID)
         hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_GRID>, grid, block, 0, (hipStream_t)stream, a);
-    else
+    else if (p->color_mode == DVGO_COLOR_SAMPLES)
         hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_SAMPLES>, grid, block, 0, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_NONE>, grid, block, 0, (hipStream_t)stream, a);
     return check_hip(hipGetLastError(), "render_fwd_kernel launch");
 }
 

@@ -11,7 +11,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import COLOR_GRID, COLOR_SAMPLES, ColorMLP, Grid, RenderParams, Samples, call
+from ._lib import COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, ColorMLP, Grid, Proposal, Rays, RenderParams, Samples, call
 
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather",
@@ -165,10 +165,12 @@ def render_state_size(n_rays: int, n_samples: int) -> int:
 
 def render_forward(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid] = None,
                    sample_rgb: Optional[torch.Tensor] = None, *, act_shift_: float, halt_T: float = 0.0,
-                   bg=(1.0, 1.0, 1.0), want_dist: bool = True, out=None, state: Optional[torch.Tensor] = None):
-    """Returns (rgb [R,3], T_final [R], dist [R] or None, state)."""
+                   bg=(1.0, 1.0, 1.0), want_dist: bool = True, out=None, state: Optional[torch.Tensor] = None,
+                   sample_w: Optional[torch.Tensor] = None, density_only: bool = False):
+    """Returns (rgb [R,3], T_final [R], dist [R] or None, state).  sample_w [S], if given,
+    receives the per-sample weights; density_only renders with zero sample colours."""
     import ctypes
-    mode = COLOR_GRID if color is not None else COLOR_SAMPLES
+    mode = COLOR_NONE if density_only else (COLOR_GRID if color is not None else COLOR_SAMPLES)
     R, S = batch.n_rays, batch.n_samples
     dev = batch.xyz.device
     if out is None:
@@ -178,13 +180,15 @@ def render_forward(batch: SampleBatch, density: DeviceGrid, color: Optional[Devi
         state = torch.empty(render_state_size(R, S), dtype=torch.uint8, device=dev)
     if sample_rgb is not None:
         _chk(sample_rgb, "sample_rgb", numel=3 * S)
+    if sample_w is not None:
+        _chk(sample_w, "sample_w", numel=S)
     p = _params(act_shift_, halt_T, bg, mode, want_dist)
     s = batch.struct()
     gd = density.struct()
     gc = color.struct() if color is not None else None
     call("dvgo_render_forward", ctypes.byref(p), ctypes.byref(s), ctypes.byref(gd),
          ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), _p(rgb), _p(T),
-         _p(dist) if want_dist else None, _p(state), state.numel(), _stream())
+         _p(dist) if want_dist else None, _p(sample_w), _p(state), state.numel(), _stream())
     return rgb, T, (dist if want_dist else None), state
 
 
@@ -342,3 +346,140 @@ def loss_head(rgb, target, dist, dist_weight, loss=None, grad_rgb=None, grad_dis
     call("dvgo_loss_head", R, _p(rgb), _p(target), _p(dist), dist_weight, _p(loss), _p(grad_rgb), _p(grad_dist),
          _stream())
     return loss, grad_rgb, grad_dist
+
+
+# --------------------------------------------------------------- proposal stage
+
+
+@dataclass
+class RayBatch:
+    """Bounded-scene rays on the GPU (see dvgo_rays)."""
+    origins: torch.Tensor
+    dirs: torch.Tensor
+    t_near: torch.Tensor
+    t_far: torch.Tensor
+
+    @classmethod
+    def from_arrays(cls, origins, dirs, t_near, t_far, device="cuda"):
+        f = lambda a: torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()  # noqa: E731
+        return cls(f(origins).reshape(-1, 3), f(dirs).reshape(-1, 3), f(t_near), f(t_far))
+
+    @property
+    def n_rays(self):
+        return int(self.t_near.numel())
+
+    def struct(self) -> Rays:
+        R = self.n_rays
+        for t, n, k in ((self.origins, "origins", 3), (self.dirs, "dirs", 3), (self.t_near, "t_near", 1),
+                        (self.t_far, "t_far", 1)):
+            _chk(t, n, numel=k * R)
+        return Rays(C_size(Rays), R, _p(self.origins), _p(self.dirs), _p(self.t_near), _p(self.t_far))
+
+
+@dataclass
+class ProposalParams:
+    """Proposal MLP float32 master weights (4 layers, 64 wide) and gradient buffers."""
+    W: list
+    b: list
+    gW: Optional[list] = None
+    gb: Optional[list] = None
+
+    def struct(self, need_grad=False) -> Proposal:
+        import ctypes
+        q = Proposal()
+        q.struct_size = C_size(Proposal)
+        q.n_bins, q.hidden, q.n_layers = int(self.W[-1].shape[0]), int(self.W[0].shape[0]), len(self.W)
+        for i, (w, b) in enumerate(zip(self.W, self.b)):
+            _chk(w, f"proposal W{i}")
+            _chk(b, f"proposal b{i}")
+            q.W[i], q.b[i] = _p(w), _p(b)
+        if self.gW is not None:
+            for i, (w, b) in enumerate(zip(self.gW, self.gb)):
+                _chk(w, f"proposal gW{i}")
+                _chk(b, f"proposal gb{i}")
+                q.gW[i], q.gb[i] = _p(w), _p(b)
+        elif need_grad:
+            raise ValueError("proposal gradient buffers are required here")
+        del ctypes
+        return q
+
+
+def proposal_coarse(rays: RayBatch, density: DeviceGrid, *, act_shift_: float, voxel: float, eps: float = 1e-4,
+                    feat=None, w_coarse=None):
+    import ctypes
+    R = rays.n_rays
+    dev = rays.t_near.device
+    feat = torch.empty(R, 64, device=dev) if feat is None else feat
+    r = rays.struct()
+    g = density.struct()
+    call("dvgo_proposal_coarse", ctypes.byref(r), ctypes.byref(g), act_shift_, voxel, eps, _p(feat), _p(w_coarse),
+         _stream())
+    return feat, w_coarse
+
+
+def proposal_forward(prop: ProposalParams, feat, logits=None, prob=None, entropy=None):
+    import ctypes
+    R = feat.shape[0]
+    _chk(feat, "feat", numel=64 * R)
+    dev = feat.device
+    logits = torch.empty(R, 64, device=dev) if logits is None else logits
+    prob = torch.empty(R, 64, device=dev) if prob is None else prob
+    entropy = torch.empty(R, device=dev) if entropy is None else entropy
+    q = prop.struct()
+    call("dvgo_proposal_forward", ctypes.byref(q), R, _p(feat), _p(logits), _p(prob), _p(entropy), _stream())
+    return logits, prob, entropy
+
+
+def proposal_workspace_size(prop: ProposalParams, n_rays: int) -> int:
+    import ctypes
+    return _size("dvgo_proposal_workspace_size", ctypes.byref(prop.struct()), n_rays)
+
+
+def proposal_backward(prop: ProposalParams, feat, target, loss=None, ws=None):
+    import ctypes
+    R = feat.shape[0]
+    _chk(feat, "feat", numel=64 * R)
+    _chk(target, "target", numel=64 * R)
+    loss = torch.empty(1, device=feat.device) if loss is None else loss
+    need = proposal_workspace_size(prop, R)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=feat.device)
+    q = prop.struct(need_grad=True)
+    call("dvgo_proposal_backward", ctypes.byref(q), R, _p(feat), _p(target), _p(loss), _p(ws), ws.numel(), _stream())
+    return loss
+
+
+def histogram(ray_offsets, w, s_mid, n_bins=64, min_mass=1e-4, hist=None):
+    R = ray_offsets.numel() - 1
+    _chk(ray_offsets, "ray_offsets", torch.int32)
+    _chk(w, "w")
+    _chk(s_mid, "s_mid", numel=w.numel())
+    hist = torch.empty(R, n_bins, device=w.device) if hist is None else hist
+    call("dvgo_histogram", R, _p(ray_offsets), _p(w), _p(s_mid), n_bins, min_mass, _p(hist), _stream())
+    return hist
+
+
+def resample_offsets(rays: RayBatch, entropy, tau, n_fine=48, n_plain=256, ray_offsets=None):
+    import ctypes
+    R = rays.n_rays
+    _chk(entropy, "entropy", numel=R)
+    ray_offsets = torch.empty(R + 1, dtype=torch.int32, device=entropy.device) if ray_offsets is None else ray_offsets
+    r = rays.struct()
+    call("dvgo_resample_offsets", ctypes.byref(r), _p(entropy), tau, n_fine, n_plain, _p(ray_offsets), _stream())
+    return ray_offsets
+
+
+def resample(rays: RayBatch, prob, entropy, tau, ray_offsets, n_samples, voxel, n_fine=48, n_plain=256, out=None):
+    """Fills a fine batch of n_samples (= ray_offsets[-1]) samples; returns a SampleBatch."""
+    import ctypes
+    R = rays.n_rays
+    _chk(prob, "prob", numel=64 * R)
+    dev = prob.device
+    if out is None:
+        out = (torch.empty(n_samples, 3, device=dev), torch.empty(n_samples, device=dev),
+               torch.empty(n_samples, device=dev), torch.empty(n_samples, device=dev))
+    xyz, dl, sm, sl = out
+    r = rays.struct()
+    call("dvgo_resample", ctypes.byref(r), _p(prob), _p(entropy), tau, _p(ray_offsets), n_fine, n_plain, voxel,
+         _p(xyz), _p(dl), _p(sm), _p(sl), _stream())
+    return SampleBatch(ray_offsets, xyz, dl, sm, sl, R, int(n_samples))

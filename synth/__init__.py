@@ -10,5 +10,5 @@ from .scenes import (  # noqa: F401
     blob_density, normal_grid, uniform_grid,
     rays_at_box, pinhole_rays, rays_into_ball, slab_interval,
     uniform_samples, disparity_samples, mlp_weights, proposal_weights,
-    config1, config2, config3, config4, config5, random_ragged,
+    config1, config2, config3, config4, config5, random_ragged, proposal_rays,
 )

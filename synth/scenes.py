@@ -125,8 +125,9 @@ def _axis(n, lo, hi):
     return lo + (hi - lo) * np.arange(n, dtype=np.float64) / (n - 1)
 
 
-def blob_density(rng, n, xyz_min=-1.0, xyz_max=1.0, n_blobs=8, center_box=0.6) -> Grid:
-    """Density logits N(0,1) + sum of Gaussian blobs (amplitude U[6,14], sigma U[0.05,0.2])."""
+def blob_density(rng, n, xyz_min=-1.0, xyz_max=1.0, n_blobs=8, center_box=0.6, return_blobs=False):
+    """Density logits N(0,1) + sum of Gaussian blobs (amplitude U[6,14], sigma U[0.05,0.2]).
+    With return_blobs, also returns the blob term alone ([n,n,n] float32)."""
     lo = np.full(3, xyz_min, np.float64)
     hi = np.full(3, xyz_max, np.float64)
     base = rng.standard_normal((n, n, n), dtype=np.float32)
@@ -139,7 +140,8 @@ def blob_density(rng, n, xyz_min=-1.0, xyz_max=1.0, n_blobs=8, center_box=0.6) -
         g = [np.exp(-(axes[a] - mu[b, a]) ** 2 / (2 * sd[b] ** 2)).astype(F32) for a in range(3)]
         acc += F32(amp[b]) * (g[0][:, None, None] * g[1][None, :, None] * g[2][None, None, :])
     data = (base + acc).astype(F32)[..., None]
-    return Grid(np.ascontiguousarray(data), lo.astype(F32), hi.astype(F32))
+    g = Grid(np.ascontiguousarray(data), lo.astype(F32), hi.astype(F32))
+    return (g, acc) if return_blobs else g
 
 
 def normal_grid(rng, n, C, xyz_min=-1.0, xyz_max=1.0) -> Grid:
@@ -395,12 +397,30 @@ def config4(R=16384, N=512, n=160, C=12) -> Workload:
     return Workload("config4", w2.density, None, w2.feat, w2.mlp, rays, smp, tgt)
 
 
-def config5(R=8192, n=160, C=12, held_out=False) -> Workload:
-    """Proposal: config-2 grids and MLP; rays for training (stream 3) or held-out (stream 6)."""
+def clear_free_space(density: Grid, blobs, keep_above=1.0, empty=-20.0) -> Grid:
+    """Variant of a blob scene whose free space has been emptied, as occupancy masking and
+    the distortion loss's compactness leave a trained grid (sections 1 and 2): vertices whose
+    blob term is below `keep_above` get the logit `empty`; the blobs keep their noise."""
+    data = np.where(blobs[..., None] >= keep_above, density.data, F32(empty)).astype(F32)
+    return Grid(np.ascontiguousarray(data), density.xyz_min, density.xyz_max)
+
+
+def config5(R=8192, n=160, C=12, held_out=False, cleared=False) -> Workload:
+    """Proposal: config-2 grids and MLP; rays for training (stream 3) or held-out (stream 6).
+    cleared=True empties the free space of the density grid (see clear_free_space)."""
     w2 = config2(R=8, n=n, C=C)
+    if cleared:
+        dens, blobs = blob_density(_rng(2, 0), n, return_blobs=True)   # config 2's density draw
+        w2.density = clear_free_space(dens, blobs)
     rays = pinhole_rays(_rng(5, 6 if held_out else 3), R)
     smp = uniform_samples(rays, 256, w2.density.voxel_size())
     tgt = _rng(5, 5).random((R, 3)).astype(F32)
     wl = Workload("config5", w2.density, None, w2.feat, w2.mlp, rays, smp, tgt)
     wl.extra["proposal"] = proposal_weights(_rng(5, 7))
     return wl
+
+
+def proposal_rays(R, stream, n=160):
+    """Pinhole rays over the config-5 scene: stream 3 trains, 6 tunes, 8 evaluates."""
+    box = (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    return pinhole_rays(_rng(5, stream), R, bmin=box[0], bmax=box[1])

@@ -15,12 +15,14 @@ FWD = dict(rtol=1e-5, floor=1e-3)
 GRAD = dict(rtol=1e-4, floor=1e-2)
 
 
-def close(x, y, rtol, floor, name="value", scale=None, skip=None):
+def close(x, y, rtol, floor, name="value", scale=None, skip=None, slack=None):
     """scale (optional, per element): the magnitude the result is conditioned on, e.g.
     sum_c w_c |G_c| for an interpolated value whose terms cancel; the elementwise bound
     then uses max(|y_i|, floor * ||y||_inf, scale_i).  skip (optional boolean mask):
     elements at a non-differentiable point (a ReLU unit within rounding of its kink) are
-    left out of the elementwise check; the normwise check still covers them."""
+    left out of the elementwise check; the normwise check still covers them.  slack
+    (optional, per element): an absolute allowance added to the elementwise bound, e.g. the
+    change a gradient sees when a ReLU unit at its kink switches side."""
     x = np.asarray(x, np.float64).ravel()
     y = np.asarray(y, np.float64).ravel()
     assert x.shape == y.shape, f"{name}: shape {x.shape} vs {y.shape}"
@@ -33,6 +35,8 @@ def close(x, y, rtol, floor, name="value", scale=None, skip=None):
         if scale is not None:
             bound = np.maximum(bound, rtol * np.asarray(scale, np.float64).ravel())
         bad = np.abs(x - y) > bound + 1e-30
+        if slack is not None:
+            bad &= np.abs(x - y) > bound + np.asarray(slack, np.float64).ravel()
         if skip is not None:
             bad &= ~np.asarray(skip, bool).ravel()
         if bad.any():

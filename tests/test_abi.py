@@ -60,30 +60,30 @@ def _err(L):
 def test_validation_errors(L):
     lib = L.lib()
     # NULL params
-    assert lib.dvgo_render_forward(None, None, None, None, None, None, None, None, None, 0, None) == -1
+    assert lib.dvgo_render_forward(None, None, None, None, None, None, None, None, None, None, 0, None) == -1
     assert "params" in _err(L)
     # struct_size mismatch
     p = L.RenderParams()
     p.struct_size = 3
     s = L.Samples()
     s.struct_size = C.sizeof(L.Samples)
-    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), None, None, None, None, None, None, None, 0, None) == -8
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), None, None, None, None, None, None, None, None, 0, None) == -8
     p.struct_size = C.sizeof(L.RenderParams)
     # unknown colour mode
     p.color_mode = 7
     s.ray_offsets = 1
-    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), None, None, None, None, None, None, None, 0, None) == -7
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), None, None, None, None, None, None, None, None, 0, None) == -7
     # bad grid dims
     p.color_mode = L.COLOR_SAMPLES
     g = L.Grid()
     g.struct_size = C.sizeof(L.Grid)
     g.nx, g.ny, g.nz, g.channels, g.ch_stride = 1, 4, 4, 1, 1
-    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, None, None, None, None, None, 0,
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, None, None, None, None, None, None, 0,
                                    None) == -2
     assert "dimension" in _err(L)
     # halting threshold out of range
     p.halt_T = 1.5
-    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, None, None, None, None, None, 0,
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, None, None, None, None, None, None, 0,
                                    None) == -3
     # state too small (valid otherwise; fails before any launch)
     p.halt_T = 0.0
@@ -93,7 +93,7 @@ def test_validation_errors(L):
     g.data = 64
     s.n_rays, s.n_samples = 4, 10
     s.xyz = s.delta = s.s_mid = s.s_len = 64
-    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, 64, 64, 64, 64, 64, 1, None) == -5
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), C.byref(g), None, 64, 64, 64, 64, None, 64, 1, None) == -5
     # Adam: NULL arrays, zero step, mismatched alignment
     assert lib.dvgo_grid_adam_step(None, None, None, None, 10, 0.1, 0.9, 0.99, 1e-8, 1, None, 1, 0, None) == -1
     assert lib.dvgo_grid_adam_step(16, 16, 16, 16, 10, 0.1, 0.9, 0.99, 1e-8, 0, None, 1, 0, None) == -3
@@ -109,6 +109,19 @@ def test_validation_errors(L):
     assert lib.dvgo_mlp_workspace_size(C.byref(m), 4, 10, C.byref(out)) == -7
     m.hidden = 128
     assert lib.dvgo_mlp_workspace_size(C.byref(m), 4, 10, C.byref(out)) == -1  # NULL weights
+    # proposal: unsupported widths, NULL rays
+    q = L.Proposal()
+    q.struct_size = C.sizeof(L.Proposal)
+    q.n_bins, q.hidden, q.n_layers = 32, 64, 4
+    assert lib.dvgo_proposal_forward(C.byref(q), 4, 64, 64, 64, 64, None) == -7
+    assert lib.dvgo_proposal_coarse(None, None, 0.0, 1.0, 1e-4, 64, None, None) == -1
+    rr = L.Rays()
+    rr.struct_size = C.sizeof(L.Rays)
+    rr.n_rays = 4
+    assert lib.dvgo_resample_offsets(C.byref(rr), 64, 3.0, 48, 256, 64, None) == -1   # NULL ray arrays
+    rr.origins = rr.dirs = rr.t_near = rr.t_far = 64
+    assert lib.dvgo_resample_offsets(C.byref(rr), 64, 3.0, 300, 256, 64, None) == -3  # n_fine > 256
+    assert lib.dvgo_histogram(4, 64, 64, 64, 32, 1e-4, 64, None) == -7
     # sizes
     assert lib.dvgo_render_state_size(8192, 10 ** 6, C.byref(out)) == 0 and out.value > 0
     assert lib.dvgo_render_state_size(-1, 0, C.byref(out)) == -2

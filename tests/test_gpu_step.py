@@ -67,16 +67,22 @@ def test_whole_step_gradients(pkg):
     close(st.dist.cpu().numpy(), o["D"], **FWD, name="distortion")
     close(st.loss.cpu().numpy(), [L], **FWD, name="loss")
     close(st.density["g"].cpu().numpy(), gd, **GRAD, name="grad density")
-    # feature-grid entries touched by a sample sitting on a ReLU kink are not differentiable
+    # A hidden unit whose pre-activation sits within float32 rounding of its ReLU kink may
+    # switch side between float32 and float64; both are valid there.  The oracle computes,
+    # per element, how much each gradient moves when such a unit switches (the slack).
     smp = wl.samples
-    margin = oracle.mlp_margin(wl.mlp, smp.ray_offsets, wl.rays.dirs, oracle.gather(wl.feat, smp.xyz))
-    kink = margin < 1e-5
-    touched = oracle.scatter(wl.feat, smp.xyz[kink], np.ones((kink.sum(), wl.feat.channels))) != 0
-    say("samples within 1e-5 of a ReLU kink:", int(kink.sum()), "grid entries skipped:", int(touched.sum()))
-    close(st.feat["g"].cpu().numpy(), gfeat, **GRAD, name="grad features", skip=touched)
+    feat = oracle.gather(wl.feat, smp.xyz)
+    srgb = oracle.mlp_forward(wl.mlp, smp.ray_offsets, wl.rays.dirs, feat)
+    o2 = oracle.render_forward(smp, wl.density, srgb=srgb, shift=shift)
+    _, GC, GD = oracle.loss_head(o2["rgb"], wl.target, o2["D"], wl.dist_weight)
+    g_srgb = oracle.render_backward(smp, wl.density, GC, GD, None, srgb=srgb, shift=shift)["grad_srgb"]
+    sf, sW, sb = oracle.mlp_kink_slack(wl.mlp, smp.ray_offsets, wl.rays.dirs, feat, g_srgb)
+    slack_grid = oracle.scatter(wl.feat, smp.xyz, sf)   # every vertex weight is <= 1, so this bounds the move
+    say("kink slack: max feature-grid slack", float(np.abs(slack_grid).max()))
+    close(st.feat["g"].cpu().numpy(), gfeat, **GRAD, name="grad features", slack=np.abs(slack_grid))
     for i in range(3):
-        close(st.mlp.gW[i].cpu().numpy(), gW[i], **GRAD, name=f"grad W{i + 1}")
-        close(st.mlp.gb[i].cpu().numpy(), gb[i], **GRAD, name=f"grad b{i + 1}")
+        close(st.mlp.gW[i].cpu().numpy(), gW[i], **GRAD, name=f"grad W{i + 1}", slack=sW[i])
+        close(st.mlp.gb[i].cpu().numpy(), gb[i], **GRAD, name=f"grad b{i + 1}", slack=sb[i])
 
 
 def test_graph_replays_match_eager(pkg):

@@ -159,13 +159,62 @@ def test_resample_closed_forms(orc):
     sm = out["s_mid"].reshape(R, n)
     np.testing.assert_allclose(sm[0], (j + 0.5) / n, rtol=1e-13)
     np.testing.assert_allclose(sm[1], (17 + (j + 0.5) / n) / B, rtol=1e-13)
-    u = (j + 0.5) / n
-    exp2 = np.where(u < 0.25, (3 + u / 0.25) / B, (40 + (u - 0.25) / 0.75) / B)
-    np.testing.assert_allclose(sm[2], exp2, rtol=1e-12)
+    # interval ends at u = k/n; the interval that straddles the empty bins 4..39 spans the gap
+    u = np.arange(n + 1) / n
+    ends = np.where(u < 0.25, (3 + u / 0.25) / B, (40 + (u - 0.25) / 0.75) / B)
+    np.testing.assert_allclose(sm[2], 0.5 * (ends[1:] + ends[:-1]), rtol=1e-12)
     sl = out["s_len"].reshape(R, n)
-    np.testing.assert_allclose(sl.sum(1), 1.0, rtol=1e-13)
+    np.testing.assert_allclose(sl[2], np.diff(ends), rtol=1e-12)
+    # the intervals tile the support of the density: [0,1], bin 17, bins 3..40
+    np.testing.assert_allclose(sl.sum(1), [1.0, 1.0 / B, 38.0 / B], rtol=1e-12)
     assert (sl > 0).all() and (np.diff(sm, axis=1) > 0).all()
     span = (rays.t_far - rays.t_near).astype(np.float64)
     np.testing.assert_allclose(out["delta"].reshape(R, n), sl * span[:, None] / 0.01, rtol=1e-13)
     z = out["xyz"].reshape(R, n, 3)[..., 2]
     np.testing.assert_allclose(z, rays.t_near[:, None] + sm * span[:, None], rtol=1e-13)
+
+
+def test_proposal_coarse_pins(orc):
+    # weights of the coarse pass equal the render's weights on the same 64 uniform samples
+    # (an independent code path), sum with the final transmittance to one, and a constant
+    # field gives the closed form w_k = exp(-k s d)(1 - exp(-s d)).
+    wl = synth.config2(R=64, n=32)
+    vox = wl.density.voxel_size()
+    w, f = orc.proposal_coarse(wl.rays, wl.density, vox)
+    smp = synth.uniform_samples(wl.rays, 64, vox)
+    o = orc.render_forward(smp, wl.density, srgb=np.zeros((smp.n_samples, 3)), want_w=True)
+    hit = wl.rays.hit
+    assert (w[~hit] == 0).all() and (f[~hit] == 0).all()
+    # float32 sample positions in the render batch vs float64 positions here: tiny differences
+    np.testing.assert_allclose(w[hit].ravel(), o["w"], rtol=1e-4, atol=1e-9)
+    np.testing.assert_allclose(w[hit].sum(1) + o["T"][hit], 1.0, atol=1e-6)
+    np.testing.assert_allclose(f, np.log1p(w / 1e-4), rtol=1e-13)
+    const = synth.Grid(np.full((4, 4, 4, 1), 2.0, np.float32), wl.density.xyz_min, wl.density.xyz_max)
+    wc, _ = orc.proposal_coarse(wl.rays, const, vox)
+    sig = np.log1p(np.exp(2.0 + orc.act_shift()))
+    for r in np.nonzero(hit)[0][:5]:
+        dl = (float(wl.rays.t_far[r]) - float(wl.rays.t_near[r])) / 64 / vox
+        k = np.arange(64)
+        np.testing.assert_allclose(wc[r], np.exp(-k * sig * dl) * (1 - np.exp(-sig * dl)), rtol=1e-10)
+
+
+def test_resample_batch_fallback_and_offsets(orc):
+    R, B = 4, 64
+    rays = synth.Rays(np.zeros((R, 3), np.float32), np.tile(np.array([1, 0, 0], np.float32), (R, 1)),
+                      np.array([1.0, 0.0, 2.0, 0.5], np.float32), np.array([2.0, 0.0, 4.0, 1.5], np.float32),
+                      np.array([True, False, True, True]))
+    p = np.full((R, B), 1.0 / B)
+    p[3] = 0.0
+    p[3, 10] = 1.0
+    H = np.array([0.5, 0.5, 9.0, 0.1])     # ray 2 above tau -> plain samples; ray 1 misses
+    out = orc.resample_batch(p, H, tau=3.0, n_fine=48, n_plain=256, rays=rays, voxel=0.1)
+    assert list(np.diff(out["ray_offsets"])) == [48, 0, 256, 48]
+    o = out["ray_offsets"]
+    j = np.arange(48)
+    np.testing.assert_allclose(out["s_mid"][o[0]:o[1]], (j + 0.5) / 48, rtol=1e-13)
+    k = np.arange(256)
+    np.testing.assert_allclose(out["s_mid"][o[2]:o[3]], (k + 0.5) / 256, rtol=1e-13)
+    np.testing.assert_allclose(out["s_len"][o[2]:o[3]], 1 / 256)
+    np.testing.assert_allclose(out["delta"][o[2]:o[3]], 2.0 / 256 / 0.1)
+    np.testing.assert_allclose(out["s_mid"][o[3]:o[4]], (10 + (j + 0.5) / 48) / 64, rtol=1e-13)
+    np.testing.assert_allclose(out["xyz"][o[2]:o[3], 0], 2.0 + 2.0 * (k + 0.5) / 256, rtol=1e-13)
