@@ -216,6 +216,91 @@ def proposal_leg(steps=1500, batch=8192, pool=65536, n_eval=8192, log=None, clea
             "speedup_vs_plain256": round(ms_plain / ms_prop, 3), "eval_rays": n_eval, "tau_sweep": sweep}
 
 
+def ragged_leg(R=8192, steps=20, log=None):
+    """Unbounded ragged batch (320^3 contracted grids, lognormal lengths 32-1024): render
+    forward + backward under three schedules (one wave per ray in batch order; the autotuned
+    persistent longest-first launch; one launch per power-of-two length bucket), and the whole
+    training step with the tuned schedule replayed from a HIP graph."""
+    import torch
+
+    import synth
+    from paper_2206_05085_amd import ops
+    from paper_2206_05085_amd.step import TrainStep
+
+    def say(*a):
+        if log:
+            print("[ragged]", *a, file=sys.stderr, flush=True)
+
+    say("generating the 320^3 unbounded workload")
+    wl = synth.config3(R=R)
+    smp = wl.samples
+    S = smp.n_samples
+    st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                   mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight)
+    b = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
+    st.bind(b, wl.rays.dirs, wl.target)
+    st.forward()
+    torch.cuda.synchronize()
+    order, cls = ops.ray_schedule(b.ray_offsets)
+    c = cls.cpu().numpy()
+    buckets = []
+    for lo, hi in ((1, 1), (2, 2), (3, 4), (5, 8), (9, 16), (17, 63)):
+        a, z = c[63 - hi], c[63 - lo + 1]
+        if z > a:
+            buckets.append(ops.Schedule(order[a:z].contiguous(), 4, 0))
+
+    def time_render(scheds):
+        def once():
+            for sc in scheds:
+                ops.render_forward(b, st.grid("density"), None, st.rgb_s, act_shift_=st.shift,
+                                   out=(st.rgb, st.T, st.dist), state=st.state, schedule=sc)
+            for sc in scheds:
+                ops.render_backward(b, st.grid("density"), None, st.rgb_s, st.T, st.state, st.g_rgb, st.g_dist, None,
+                                    act_shift_=st.shift, grad_sample_rgb=st.g_rgb_s, schedule=sc)
+        for _ in range(3):
+            once()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            once()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    st.loss.zero_()
+    ops.loss_head(st.rgb, st.target, st.dist, st.lam, loss=st.loss, grad_rgb=st.g_rgb, grad_dist=st.g_dist)
+    ms_plain = time_render([None])
+    ms_bucket = time_render(buckets)
+    tuned, ms_tune = st.tune(longest_first=True)
+    ms_tuned = time_render([tuned])
+    say("render fwd+bwd ms: batch order %.3f, per-bucket %.3f, tuned %.3f (wpb %d, grid %d)"
+        % (ms_plain, ms_bucket, ms_tuned, tuned.waves_per_block, tuned.grid_waves))
+    st.density["g"].zero_()
+    st.feat["g"].zero_()
+    st.mlp_flat["g"].zero_()
+    g = st.capture(warmup=1)
+    for _ in range(3):
+        g.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / steps
+    lens = smp.lengths()
+    return {"workload": f"320^3 contracted grids, {R} rays, lognormal lengths 32-1024 (S={S}, max {lens.max()})",
+            "render_fwd_bwd_ms": {"one_wave_per_ray_batch_order": round(ms_plain, 4),
+                                  "per_length_bucket_launches": round(ms_bucket, 4),
+                                  "autotuned_persistent_longest_first": round(ms_tuned, 4)},
+            "render_samples_per_s": {"one_wave_per_ray_batch_order": round(S / (ms_plain * 1e-3), 1),
+                                     "per_length_bucket_launches": round(S / (ms_bucket * 1e-3), 1),
+                                     "autotuned_persistent_longest_first": round(S / (ms_tuned * 1e-3), 1)},
+            "tuned_shape": {"waves_per_block": tuned.waves_per_block, "grid_waves": tuned.grid_waves},
+            "step_ms_graph": round(ms_step, 4), "step_samples_per_s": round(S / (ms_step * 1e-3), 1),
+            "buckets": len(buckets)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -226,6 +311,7 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=8192)
     ap.add_argument("--rays", type=int, default=8192)
     ap.add_argument("--no-proposal", action="store_true")
+    ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=1500)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -341,6 +427,9 @@ def main():
                       "rays": R, "live_samples": S, "graph": use_graph, "parallelism": "single GPU"},
            "roofline": roof, "roofline_render": roof_render,
            "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()}, "loss": loss, "wall_s": round(wall, 3)}
+    if not args.no_ragged:
+        print("[bench] ragged unbounded batch: schedules", file=sys.stderr, flush=True)
+        out["ragged"] = ragged_leg(log=True)
     if not args.no_proposal:
         print("[bench] proposal stage: train, tune, evaluate", file=sys.stderr, flush=True)
         out["proposal"] = {

@@ -100,6 +100,15 @@ typedef struct dvgo_render_params {
     float bg[3];
     int32_t color_mode;
     int32_t want_dist;
+    /* Schedule (all zero = one wave per ray, 4 waves per block).  ray_list (device, may be
+     * NULL): the rays to process, in this order, each listed at most once; rays not listed
+     * are left untouched.  n_list: entries of ray_list.  waves_per_block: 1..16 (0 = 4).
+     * grid_waves: 0 = one wave per listed ray; > 0 = a persistent grid of that many waves,
+     * wave i taking list entries i, i + grid_waves, ... (longest-first lists balance it). */
+    const int32_t *ray_list;
+    int32_t n_list;
+    int32_t waves_per_block;
+    int32_t grid_waves;
 } dvgo_render_params;
 
 /* Colour MLP: input [features(in_feat), view-direction encoding(3 + 6*n_freq)] -> hidden ->
@@ -149,6 +158,23 @@ int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samples *s, con
                          const dvgo_grid *color, const float *sample_rgb, const float *T_final, const void *state,
                          size_t state_bytes, const float *grad_rgb, const float *grad_dist, const float *grad_T,
                          float *grad_sample_rgb, void *stream);
+
+/* Schedule of a ragged batch: order [R] = the rays sorted by decreasing number of 64-sample
+ * chunks (ceil(length/64), lengths above 63 chunks share the last class; order within a
+ * class is unspecified), and class_offsets [65]: order[class_offsets[k] .. class_offsets[k+1])
+ * are the rays with 63 - k chunks (k = 63: empty rays).  One block; stream-ordered. */
+int dvgo_ray_schedule(int32_t n_rays, const int32_t *ray_offsets, int32_t *order, int32_t *class_offsets,
+                      void *stream);
+
+/* Project autotuner for the render kernels: times forward + backward of this batch for a set
+ * of launch shapes (waves per block x persistent grid sizes, honouring p->ray_list) with HIP
+ * events on `stream` and returns the fastest in *waves_per_block, *grid_waves (and its time
+ * in *ms, may be NULL).  Results are cached per (colour mode, rays, samples, list) in the
+ * process; a cached shape returns without timing.  Synchronises the stream and allocates
+ * scratch outputs: not for use inside graph capture.  Parameter gradients are untouched. */
+int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                         const dvgo_grid *color, const float *sample_rgb, int32_t *waves_per_block,
+                         int32_t *grid_waves, float *ms, void *stream);
 
 /* Size of the workspace dvgo_distortion_loss needs when grad_w is requested. */
 int dvgo_distortion_workspace_size(int32_t n_rays, int64_t n_samples, size_t *bytes);

@@ -37,7 +37,8 @@ class Samples(C.Structure):
 
 class RenderParams(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("act_shift", C.c_float), ("halt_T", C.c_float),
-                ("bg", C.c_float * 3), ("color_mode", C.c_int32), ("want_dist", C.c_int32)]
+                ("bg", C.c_float * 3), ("color_mode", C.c_int32), ("want_dist", C.c_int32),
+                ("ray_list", VP), ("n_list", C.c_int32), ("waves_per_block", C.c_int32), ("grid_waves", C.c_int32)]
 
 
 class ColorMLP(C.Structure):
@@ -66,6 +67,9 @@ SIGNATURES = {
     "dvgo_render_state_size": (C.c_int, [_I32, _I64, _SZP]),
     "dvgo_render_forward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_render_backward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, C.c_size_t, VP, VP, VP, VP, VP]),
+    "dvgo_ray_schedule": (C.c_int, [_I32, VP, VP, VP, VP]),
+    "dvgo_render_autotune": (C.c_int, [_PP, _PS, _PG, _PG, VP, C.POINTER(_I32), C.POINTER(_I32),
+                                       C.POINTER(C.c_float), VP]),
     "dvgo_distortion_workspace_size": (C.c_int, [_I32, _I64, _SZP]),
     "dvgo_distortion_loss": (C.c_int, [_I32, VP, _I64, VP, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_grid_adam_step": (C.c_int, [VP, VP, VP, VP, _I64, _F, _F, _F, _F, _I32, VP, _I32, _I32, VP]),

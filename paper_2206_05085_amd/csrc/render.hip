@@ -23,6 +23,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "dvgo_internal.h"
 
 using namespace dvgo;
@@ -44,7 +48,18 @@ struct RenderArgs {
     // backward
     const float *T_in, *grad_rgb, *grad_dist, *grad_T;
     float *grad_srgb;
+    // schedule: rays ray_list[0..n_list) (identity when NULL), taken by the waves of the grid
+    // in turn (wave i handles entries i, i + n_waves, ...)
+    const int *ray_list;
+    int n_list;
 };
+
+// the wave's share of the ray list; every lane of a wave sees the same sequence
+#define FOR_EACH_RAY(a, r)                                                                              \
+    for (int _i = blockIdx.x * (int)(blockDim.x >> 6) + (int)(threadIdx.x >> 6),                        \
+             _nw = (int)gridDim.x * (int)(blockDim.x >> 6);                                               \
+         _i < (a).n_list; _i += _nw)                                                                      \
+        for (int r = (a).ray_list ? (a).ray_list[_i] : _i, _once = 1; _once; _once = 0)
 
 struct SampleIn {
     float raw, c0, c1, c2, x, alpha, m, mn, l, delta;
@@ -84,9 +99,7 @@ __device__ __forceinline__ void load_sample(const RenderArgs &a, int k, bool has
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a) {
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= a.n_rays) return;
+__device__ __forceinline__ void render_fwd_ray(const RenderArgs &a, int r) {
     const int ln = lane();
     const int beg = a.offs[r], end = a.offs[r + 1];
     float L = 0.f, W = 0.f, Q = 0.f;
@@ -148,9 +161,12 @@ __global__ __launch_bounds__(256) void render_fwd_kernel(RenderArgs a) {
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a) {
-    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (r >= a.n_rays) return;
+__global__ __launch_bounds__(1024) void render_fwd_kernel(RenderArgs a) {
+    FOR_EACH_RAY(a, r) render_fwd_ray<MODE>(a, r);
+}
+
+template <int MODE>
+__device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
     const int ln = lane();
     const int beg = a.offs[r], end = a.offs[r + 1];
     const int hend = a.halt_idx[r];
@@ -208,6 +224,11 @@ __global__ __launch_bounds__(256) void render_bwd_kernel(RenderArgs a) {
         Qp = bcast(Qpk, 0);
         Scar += bcast(gwr, 0);
     }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void render_bwd_kernel(RenderArgs a) {
+    FOR_EACH_RAY(a, r) render_bwd_ray<MODE>(a, r);
 }
 
 // Standalone distortion loss on given weights; forward sweep, then (if requested) a
@@ -314,7 +335,48 @@ int fill_render_args(const dvgo_render_params *p, const dvgo_samples *s, const d
     a.bg1 = p->bg[1];
     a.bg2 = p->bg[2];
     a.want_dist = p->want_dist != 0;
+    if (p->ray_list) {
+        if (p->n_list < 0 || p->n_list > s->n_rays) return set_error(DVGO_ERR_RANGE, "n_list must be in [0, n_rays]");
+        a.ray_list = p->ray_list;
+        a.n_list = p->n_list;
+    } else {
+        a.ray_list = nullptr;
+        a.n_list = s->n_rays;
+    }
+    if (p->waves_per_block < 0 || p->waves_per_block > 16) return set_error(DVGO_ERR_RANGE, "waves_per_block in 0..16");
+    if (p->grid_waves < 0) return set_error(DVGO_ERR_RANGE, "grid_waves must be >= 0");
     return DVGO_OK;
+}
+
+struct Launch {
+    dim3 grid, block;
+};
+
+Launch launch_shape(const dvgo_render_params *p, int n_list) {
+    const int wpb = p->waves_per_block ? p->waves_per_block : 4;
+    int waves = p->grid_waves ? (p->grid_waves < n_list ? p->grid_waves : n_list) : n_list;
+    if (waves < 1) waves = 1;
+    return Launch{dim3((waves + wpb - 1) / wpb), dim3(64 * wpb)};
+}
+
+int launch_fwd(const dvgo_render_params *p, const RenderArgs &a, hipStream_t st) {
+    const Launch L = launch_shape(p, a.n_list);
+    if (p->color_mode == DVGO_COLOR_GRID)
+        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_GRID>, L.grid, L.block, 0, st, a);
+    else if (p->color_mode == DVGO_COLOR_SAMPLES)
+        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_SAMPLES>, L.grid, L.block, 0, st, a);
+    else
+        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_NONE>, L.grid, L.block, 0, st, a);
+    return check_hip(hipGetLastError(), "render_fwd_kernel launch");
+}
+
+int launch_bwd(const dvgo_render_params *p, const RenderArgs &a, hipStream_t st) {
+    const Launch L = launch_shape(p, a.n_list);
+    if (p->color_mode == DVGO_COLOR_GRID)
+        hipLaunchKernelGGL(render_bwd_kernel<DVGO_COLOR_GRID>, L.grid, L.block, scatter_lds_bytes(3, L.block.x), st, a);
+    else
+        hipLaunchKernelGGL(render_bwd_kernel<DVGO_COLOR_SAMPLES>, L.grid, L.block, 0, st, a);
+    return check_hip(hipGetLastError(), "render_bwd_kernel launch");
 }
 
 size_t state_bytes(int32_t n_rays, int64_t n_samples) {
@@ -352,14 +414,8 @@ extern "C" int dvgo_render_forward(const dvgo_render_params *p, const dvgo_sampl
     a.dist = dist;
     a.sample_w = sample_w;
     split_state(state, s->n_rays, &a.halt_idx, &a.ckpt);
-    const dim3 grid((s->n_rays + 3) / 4), block(256);
-    if (p->color_mode == DVGO_COLOR_GRID)
-        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_GRID>, grid, block, 0, (hipStream_t)stream, a);
-    else if (p->color_mode == DVGO_COLOR_SAMPLES)
-        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_SAMPLES>, grid, block, 0, (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_NONE>, grid, block, 0, (hipStream_t)stream, a);
-    return check_hip(hipGetLastError(), "render_fwd_kernel launch");
+    if (a.n_list == 0) return DVGO_OK;
+    return launch_fwd(p, a, (hipStream_t)stream);
 }
 
 extern "C" int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
@@ -382,13 +438,172 @@ extern "C" int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samp
     a.grad_T = grad_T;
     a.grad_srgb = grad_sample_rgb;
     split_state(const_cast<void *>(state), s->n_rays, &a.halt_idx, &a.ckpt);
-    const dim3 grid((s->n_rays + 3) / 4), block(256);
-    if (p->color_mode == DVGO_COLOR_GRID)
-        hipLaunchKernelGGL(render_bwd_kernel<DVGO_COLOR_GRID>, grid, block, scatter_lds_bytes(3, 256),
-                           (hipStream_t)stream, a);
-    else
-        hipLaunchKernelGGL(render_bwd_kernel<DVGO_COLOR_SAMPLES>, grid, block, 0, (hipStream_t)stream, a);
-    return check_hip(hipGetLastError(), "render_bwd_kernel launch");
+    if (a.n_list == 0) return DVGO_OK;
+    return launch_bwd(p, a, (hipStream_t)stream);
+}
+
+// ------------------------------------------------------------------- scheduling
+
+namespace {
+
+constexpr int NCLASS = 64;
+
+__global__ __launch_bounds__(1024) void schedule_kernel(int R, const int *offs, int *order, int *class_offsets) {
+    __shared__ int hist[NCLASS], start[NCLASS], cursor[NCLASS];
+    for (int c = threadIdx.x; c < NCLASS; c += blockDim.x) {
+        hist[c] = 0;
+        cursor[c] = 0;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        const int ch = (offs[r + 1] - offs[r] + 63) / 64;
+        atomicAdd(&hist[ch < NCLASS - 1 ? ch : NCLASS - 1], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int pos = 0;
+        for (int k = 0; k < NCLASS; ++k) {  // class k holds rays with 63 - k chunks
+            const int c = NCLASS - 1 - k;
+            start[c] = pos;
+            class_offsets[k] = pos;
+            pos += hist[c];
+        }
+        class_offsets[NCLASS] = pos;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < R; r += blockDim.x) {
+        int ch = (offs[r + 1] - offs[r] + 63) / 64;
+        ch = ch < NCLASS - 1 ? ch : NCLASS - 1;
+        order[start[ch] + atomicAdd(&cursor[ch], 1)] = r;
+    }
+}
+
+struct TuneKey {
+    int mode, want_dist;
+    int n_rays;
+    long long n_samples;
+    const void *list;
+    int n_list;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(mode, want_dist, n_rays, n_samples, list, n_list) <
+               std::tie(o.mode, o.want_dist, o.n_rays, o.n_samples, o.list, o.n_list);
+    }
+};
+struct TuneVal {
+    int wpb, grid_waves;
+    float ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+}  // namespace
+
+extern "C" int dvgo_ray_schedule(int32_t n_rays, const int32_t *ray_offsets, int32_t *order, int32_t *class_offsets,
+                                 void *stream) {
+    if (n_rays < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays");
+    if (!ray_offsets || !order || !class_offsets) return set_error(DVGO_ERR_NULL, "an argument is NULL");
+    hipLaunchKernelGGL(schedule_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, n_rays, ray_offsets, order,
+                       class_offsets);
+    return check_hip(hipGetLastError(), "schedule_kernel launch");
+}
+
+extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                                    const dvgo_grid *color, const float *sample_rgb, int32_t *waves_per_block,
+                                    int32_t *grid_waves, float *ms, void *stream) {
+    RenderArgs a;
+    int rc = fill_render_args(p, s, density, color, sample_rgb, false, a);
+    if (rc) return rc;
+    if (p->color_mode == DVGO_COLOR_NONE) return set_error(DVGO_ERR_UNSUPPORTED, "autotune needs a colour mode");
+    if (!waves_per_block || !grid_waves) return set_error(DVGO_ERR_NULL, "output pointers are NULL");
+    const TuneKey key{p->color_mode, p->want_dist, s->n_rays, (long long)s->n_samples, p->ray_list, a.n_list};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            *waves_per_block = it->second.wpb;
+            *grid_waves = it->second.grid_waves;
+            if (ms) *ms = it->second.ms;
+            return DVGO_OK;
+        }
+    }
+    const int R = s->n_rays;
+    const int64_t S = s->n_samples;
+    const hipStream_t st = (hipStream_t)stream;
+    // scratch outputs; gradients go to scratch grids so the caller's buffers are untouched
+    const size_t n_dens = (size_t)density->nx * density->ny * density->nz * density->ch_stride;
+    const size_t n_col = color ? (size_t)color->nx * color->ny * color->nz * color->ch_stride : 0;
+    float *buf = nullptr;
+    const size_t nf = (size_t)R * 3 + 2 * (size_t)R + (size_t)R * 3 + 2 * (size_t)R + n_dens + n_col + (size_t)S * 3;
+    void *state = nullptr;
+    const size_t sb = state_bytes(R, S);
+    if (hipMalloc(&buf, nf * sizeof(float)) != hipSuccess || hipMalloc(&state, sb) != hipSuccess) {
+        if (buf) hipFree(buf);
+        return set_error(DVGO_ERR_HIP, "autotune scratch allocation failed");
+    }
+    float *rgb = buf, *T = rgb + 3 * (size_t)R, *dist = T + R, *grgb = dist + R, *gdist = grgb + 3 * (size_t)R,
+          *gT = gdist + R, *gden = gT + R, *gcol = gden + n_dens, *gs = gcol + n_col;
+    hipMemsetD32Async((hipDeviceptr_t)grgb, 0x3f800000, 3 * (size_t)R + 2 * (size_t)R, st);  // ones
+    dvgo_grid dg = *density, cg;
+    dg.grad = gden;
+    if (color) {
+        cg = *color;
+        cg.grad = gcol;
+    }
+    RenderArgs fa = a, ba;
+    fa.rgb = rgb;
+    fa.T_final = T;
+    fa.dist = dist;
+    fa.sample_w = nullptr;
+    split_state(state, R, &fa.halt_idx, &fa.ckpt);
+    rc = fill_render_args(p, s, &dg, color ? &cg : nullptr, sample_rgb, true, ba);
+    ba.T_in = T;
+    ba.grad_rgb = grgb;
+    ba.grad_dist = p->want_dist ? gdist : nullptr;
+    ba.grad_T = gT;
+    ba.grad_srgb = gs;
+    ba.halt_idx = fa.halt_idx;
+    ba.ckpt = fa.ckpt;
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    TuneVal best{4, 0, 1e30f};
+    const int wpbs[] = {2, 4, 8, 16};
+    const int grids[] = {0, 1024, 2048, 4096, 8192, 16384};
+    for (int wi = 0; wi < 4 && !rc; ++wi) {
+        for (int gi = 0; gi < 6 && !rc; ++gi) {
+            if (grids[gi] >= a.n_list && grids[gi] != 0) continue;
+            dvgo_render_params q = *p;
+            q.waves_per_block = wpbs[wi];
+            q.grid_waves = grids[gi];
+            rc = launch_fwd(&q, fa, st);  // warm-up
+            if (!rc) rc = launch_bwd(&q, ba, st);
+            hipEventRecord(e0, st);
+            for (int rep = 0; rep < 3 && !rc; ++rep) {
+                rc = launch_fwd(&q, fa, st);
+                if (!rc) rc = launch_bwd(&q, ba, st);
+            }
+            hipEventRecord(e1, st);
+            hipEventSynchronize(e1);
+            float t = 0.f;
+            hipEventElapsedTime(&t, e0, e1);
+            t /= 3.f;
+            if (!rc && t < best.ms) best = TuneVal{wpbs[wi], grids[gi], t};
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamSynchronize(st);
+    hipFree(buf);
+    hipFree(state);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = best;
+    }
+    *waves_per_block = best.wpb;
+    *grid_waves = best.grid_waves;
+    if (ms) *ms = best.ms;
+    return DVGO_OK;
 }
 
 extern "C" int dvgo_distortion_workspace_size(int32_t n_rays, int64_t n_samples, size_t *bytes) {

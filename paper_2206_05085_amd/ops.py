@@ -13,7 +13,8 @@ import torch
 from . import _lib
 from ._lib import COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, ColorMLP, Grid, Proposal, Rays, RenderParams, Samples, call
 
-__all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "render_state_size", "render_forward",
+__all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
+           "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather",
            "grid_scatter", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
            "COLOR_GRID", "COLOR_SAMPLES"]
@@ -141,7 +142,17 @@ class MLPParams:
         return m
 
 
-def _params(act_shift_: float, halt_T: float, bg, color_mode: int, want_dist: bool) -> RenderParams:
+@dataclass
+class Schedule:
+    """Launch schedule of the render kernels (see dvgo_render_params): an optional device
+    list of rays (e.g. longest first), waves per block and a persistent grid size."""
+    ray_list: Optional[torch.Tensor] = None
+    waves_per_block: int = 0
+    grid_waves: int = 0
+
+
+def _params(act_shift_: float, halt_T: float, bg, color_mode: int, want_dist: bool,
+            schedule: Optional[Schedule] = None) -> RenderParams:
     p = RenderParams()
     p.struct_size = C_size(RenderParams)
     p.act_shift = act_shift_
@@ -149,7 +160,42 @@ def _params(act_shift_: float, halt_T: float, bg, color_mode: int, want_dist: bo
     p.bg[:] = [float(v) for v in bg]
     p.color_mode = color_mode
     p.want_dist = 1 if want_dist else 0
+    if schedule is not None:
+        if schedule.ray_list is not None:
+            _chk(schedule.ray_list, "ray_list", torch.int32)
+            p.ray_list = _p(schedule.ray_list)
+            p.n_list = schedule.ray_list.numel()
+        p.waves_per_block = schedule.waves_per_block
+        p.grid_waves = schedule.grid_waves
     return p
+
+
+def ray_schedule(ray_offsets, order=None, class_offsets=None):
+    """Rays sorted by decreasing chunk count (longest first) and the 65 class offsets."""
+    R = ray_offsets.numel() - 1
+    _chk(ray_offsets, "ray_offsets", torch.int32)
+    order = torch.empty(R, dtype=torch.int32, device=ray_offsets.device) if order is None else order
+    class_offsets = torch.empty(65, dtype=torch.int32, device=ray_offsets.device) if class_offsets is None else class_offsets
+    call("dvgo_ray_schedule", R, _p(ray_offsets), _p(order), _p(class_offsets), _stream())
+    return order, class_offsets
+
+
+def render_autotune(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid] = None,
+                    sample_rgb: Optional[torch.Tensor] = None, *, act_shift_: float, halt_T: float = 0.0,
+                    bg=(1.0, 1.0, 1.0), want_dist: bool = True, ray_list: Optional[torch.Tensor] = None):
+    """Runs the library's autotuner; returns (Schedule, ms per forward + backward)."""
+    import ctypes
+    mode = COLOR_GRID if color is not None else COLOR_SAMPLES
+    sched = Schedule(ray_list=ray_list)
+    p = _params(act_shift_, halt_T, bg, mode, want_dist, sched)
+    s = batch.struct()
+    gd = density.struct()
+    gc = color.struct() if color is not None else None
+    wpb, gw, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0)
+    call("dvgo_render_autotune", ctypes.byref(p), ctypes.byref(s), ctypes.byref(gd),
+         ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), ctypes.byref(wpb), ctypes.byref(gw),
+         ctypes.byref(ms), _stream())
+    return Schedule(ray_list, wpb.value, gw.value), ms.value
 
 
 def _size(fn, *args) -> int:
@@ -166,7 +212,8 @@ def render_state_size(n_rays: int, n_samples: int) -> int:
 def render_forward(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid] = None,
                    sample_rgb: Optional[torch.Tensor] = None, *, act_shift_: float, halt_T: float = 0.0,
                    bg=(1.0, 1.0, 1.0), want_dist: bool = True, out=None, state: Optional[torch.Tensor] = None,
-                   sample_w: Optional[torch.Tensor] = None, density_only: bool = False):
+                   sample_w: Optional[torch.Tensor] = None, density_only: bool = False,
+                   schedule: Optional[Schedule] = None):
     """Returns (rgb [R,3], T_final [R], dist [R] or None, state).  sample_w [S], if given,
     receives the per-sample weights; density_only renders with zero sample colours."""
     import ctypes
@@ -182,7 +229,7 @@ def render_forward(batch: SampleBatch, density: DeviceGrid, color: Optional[Devi
         _chk(sample_rgb, "sample_rgb", numel=3 * S)
     if sample_w is not None:
         _chk(sample_w, "sample_w", numel=S)
-    p = _params(act_shift_, halt_T, bg, mode, want_dist)
+    p = _params(act_shift_, halt_T, bg, mode, want_dist, schedule)
     s = batch.struct()
     gd = density.struct()
     gc = color.struct() if color is not None else None
@@ -194,7 +241,8 @@ def render_forward(batch: SampleBatch, density: DeviceGrid, color: Optional[Devi
 
 def render_backward(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid], sample_rgb, T_final,
                     state, grad_rgb, grad_dist=None, grad_T=None, *, act_shift_: float, halt_T: float = 0.0,
-                    bg=(1.0, 1.0, 1.0), want_dist: bool = True, grad_sample_rgb=None):
+                    bg=(1.0, 1.0, 1.0), want_dist: bool = True, grad_sample_rgb=None,
+                    schedule: Optional[Schedule] = None):
     """Accumulates into density.grad (and color.grad); returns grad_sample_rgb (sample mode)."""
     import ctypes
     mode = COLOR_GRID if color is not None else COLOR_SAMPLES
@@ -206,7 +254,7 @@ def render_backward(batch: SampleBatch, density: DeviceGrid, color: Optional[Dev
         _chk(grad_T, "grad_T", numel=R)
     if mode == COLOR_SAMPLES and grad_sample_rgb is None:
         grad_sample_rgb = torch.empty(S, 3, device=batch.xyz.device)
-    p = _params(act_shift_, halt_T, bg, mode, want_dist)
+    p = _params(act_shift_, halt_T, bg, mode, want_dist, schedule)
     s = batch.struct()
     gd = density.struct(need_grad=True)
     gc = color.struct(need_grad=True) if color is not None else None

@@ -51,6 +51,7 @@ class TrainStep:
             self.mlp = ops.MLPParams(views[:3], views[3:], gviews[:3], gviews[3:], in_feat=int(self.feat["p"].shape[-1]),
                                      n_freq=n_freq)
         self.batch = None
+        self.schedule = None
 
     @staticmethod
     def _param(p):
@@ -82,18 +83,30 @@ class TrainStep:
             self.mlp_ws = torch.empty(max(ops.mlp_workspace_size(self.mlp, R, S), 1), dtype=torch.uint8, device=d)
         return self
 
+    def tune(self, longest_first: bool = True):
+        """Pick the render kernels' launch shape with the library's autotuner (on the bound
+        batch; call outside graph capture).  Returns (Schedule, ms of render fwd + bwd)."""
+        b = self.batch
+        order = ops.ray_schedule(b.ray_offsets)[0] if longest_first else None
+        colour = self.grid("color") if self.grid_mode else None
+        srgb = None if self.grid_mode else self.rgb_s
+        self.schedule, ms = ops.render_autotune(b, self.grid("density"), colour, srgb, act_shift_=self.shift,
+                                                halt_T=self.halt_T, bg=self.bg, ray_list=order)
+        return self.schedule, ms
+
     # --------------------------------------------------------------- stages
     def forward(self):
         b = self.batch
         if self.grid_mode:
             ops.render_forward(b, self.grid("density"), self.grid("color"), None, act_shift_=self.shift,
                                halt_T=self.halt_T, bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist),
-                               state=self.state)
+                               state=self.state, schedule=self.schedule)
         else:
             ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
             ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws)
             ops.render_forward(b, self.grid("density"), None, self.rgb_s, act_shift_=self.shift, halt_T=self.halt_T,
-                               bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist), state=self.state)
+                               bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist), state=self.state,
+                               schedule=self.schedule)
         ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, grad_rgb=self.g_rgb,
                       grad_dist=self.g_dist)
 
@@ -101,11 +114,12 @@ class TrainStep:
         b = self.batch
         if self.grid_mode:
             ops.render_backward(b, self.grid("density"), self.grid("color"), None, self.T, self.state, self.g_rgb,
-                                self.g_dist, None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg)
+                                self.g_dist, None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg,
+                                schedule=self.schedule)
         else:
             ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb,
                                 self.g_dist, None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg,
-                                grad_sample_rgb=self.g_rgb_s)
+                                grad_sample_rgb=self.g_rgb_s, schedule=self.schedule)
             ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
                              ws=self.mlp_ws)
             ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
