@@ -215,17 +215,22 @@ int dvgo_grid_scatter(const dvgo_grid *g, int64_t n_samples, const float *xyz, c
 int dvgo_alpha(const dvgo_grid *density, int64_t n_samples, const float *xyz, const float *delta, float act_shift,
                float *alpha, void *stream);
 
-/* Workspace for the colour MLP (per-ray direction encodings and per-block weight-gradient
- * partials). */
+/* Workspace for the colour MLP (split weight image, per-ray direction encodings, tile
+ * start rays and per-block weight-gradient partials). */
 int dvgo_mlp_workspace_size(const dvgo_color_mlp *m, int32_t n_rays, int64_t n_samples, size_t *bytes);
 
-/* Colour MLP forward on FP32 matrix cores: rgb [S,3] from feat [S, in_feat] and the
- * direction dirs [R,3] of each sample's ray. */
+/* Colour MLP forward: rgb [S,3] from feat [S, in_feat] and the direction dirs [R,3] of each
+ * sample's ray.  Products run on FP16 matrix cores with every operand split into two FP16
+ * parts under a power-of-two scale (hi*hi + hi*lo + lo*hi, FP32 accumulation), which keeps
+ * them within about 2^-22 relative; results match an FP32 evaluation to rounding.  Inputs
+ * and hidden activations are supported up to about 2^30 in magnitude. */
 int dvgo_mlp_forward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
                      int64_t n_samples, const float *feat, float *rgb, void *ws, size_t ws_bytes, void *stream);
 
-/* Colour MLP backward (recomputes the forward): grad_feat [S, in_feat] written; weight and
- * bias gradients accumulated into m->g*. */
+/* Colour MLP backward (recomputes the forward, same split-FP16 arithmetic): grad_feat
+ * [S, in_feat] written; weight and bias gradients accumulated into m->g*.  A hidden unit whose
+ * pre-activation lies within rounding of its ReLU kink may take either side, as in any
+ * floating-point evaluation. */
 int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
                       int64_t n_samples, const float *feat, const float *grad_rgb, float *grad_feat, void *ws,
                       size_t ws_bytes, void *stream);

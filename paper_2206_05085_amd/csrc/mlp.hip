@@ -1,14 +1,31 @@
 // Colour MLP of the hybrid representation (Table 1): [features, view encoding] -> 128 ->
-// 128 -> RGB, forward and backward on gfx950 FP32 matrix cores (v_mfma_f32_16x16x4_f32).
+// 128 -> RGB, forward and backward on gfx950 FP16 matrix cores with FP32-grade products.
 //
-// Layout.  Activations are kept "hidden-major": a 16x16 MFMA tile holds 16 hidden units
-// (rows) x 16 samples (columns), and lane (q = lane/16, j = lane%16) owns rows 4q..4q+3
-// of column j.  The next layer consumes a tile in place by ordering its reduction index
-// as k = 16*tile + 4q + r: the B operand of K-step (tile, r) is the lane's own r-th
-// accumulator element, and the matching A operand W[out][16*tile + 4q + r] is four
-// consecutive floats of one weight row (one 16-byte LDS read for four K-steps).
-// Weight gradients reduce over samples, so their operands are staged through LDS with
-// samples as rows and each block accumulates a private partial that a second kernel sums.
+// Split precision.  Every matrix operand v is held as two FP16 parts scaled by a power of
+// two, v 2^e = hi + lo with hi = fp16(v 2^e) and lo = fp16(v 2^e - hi), and a product is
+// taken as hi*hi' + hi*lo' + lo*hi' (three v_mfma_f32_16x16x32_f16 into one FP32
+// accumulator).  The dropped lo*lo' term and the rounding of lo leave a relative error near
+// 2^-22 per product.  The power of two keeps operands inside the FP16 normal range: weight
+// matrices use one exponent each (largest entry just under 2^14); an activation column (one
+// sample) uses an exponent from a bound on its magnitude that every wave can evaluate on
+// its own (infinity norms of the weights times the sample's input or upstream gradient).
+// Accumulators are brought back to true scale with v_ldexp, which is exact.
+//
+// Layout.  A 16x16 accumulator tile holds 16 hidden units (rows) x 16 samples (columns);
+// lane (q = lane/16, j = lane%16) owns rows 4q..4q+3 of column j.  A K-step of 32 reads
+// the lane's 8 operand slots (q, e) as logical index k(kk, q, e) = 32 kk + 4 q + e (e < 4)
+// or 32 kk + 16 + 4 q + (e - 4) (e >= 4), so two consecutive row tiles of one layer's
+// output are the next layer's B operand without any data movement.  Weight rows are
+// stored with their columns in that slot order ("phys" order), so an A operand is one
+// 16-byte read per part.
+//
+// Forward: each wave owns 16 NC samples and all 128 hidden units; W1 and W2 (both parts)
+// sit in LDS.  Backward: a block's waves own slices of 32 hidden units for the block's
+// 32-sample tiles and keep their rows of W1, W2 or W2^T in registers (two roles, see the
+// backward section); activations are exchanged through LDS.  The weight gradients reduce
+// over samples, so their operands are transposed through LDS into sample-slot order; their
+// accumulators carry a power-of-two frame that only ever decreases (rescaled when a tile
+// needs it), and a sample's operands are scaled so that the product lands in that frame.
 #include <string.h>
 
 #include "dvgo_internal.h"
@@ -18,21 +35,85 @@ using namespace dvgo;
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
 constexpr int H = 128;      // hidden width
-constexpr int KX = 48;      // padded input width: features in columns 0..11, encoding in 12..47
+constexpr int KX = 64;      // padded input width: features 0..11, view encoding 12..47, zeros 48..63
+constexpr int NXIN = 48;    // inputs that can be non-zero
 constexpr int PEW = 36;     // per-ray encoding row (input columns 12..47)
-constexpr int W2S = 132;    // LDS row stride of W2 (floats)
-constexpr int W1S = 52;     // LDS row stride of W1 (forward)
-constexpr int SH = 144;     // LDS row stride of staged [sample][hidden] tiles
-constexpr int XS = 52;      // LDS row stride of staged inputs
-constexpr int FWD_THREADS = 512, FWD_TILE = 128;
-constexpr int BWD_THREADS = 256, BWD_TILE = 64;
+constexpr int RS1 = 72;     // row stride (halves) of a 64-wide operand row
+constexpr int RS2 = 136;    // row stride (halves) of a 128-wide operand row
+constexpr int TS = 40;      // row stride (halves) of a transposed [unit][32 samples] plane
+constexpr int MAXE = 100;   // clamp of scaling exponents
+constexpr int FRAME_NONE = 1 << 20;
 constexpr int MAX_BLOCKS = 256;
 
-__device__ __forceinline__ v4f mfma4(float a, float b, v4f c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+// ---- weight image (written by mlp_prep_kernel into the workspace) ----
+// W2 comes first so that every W2 read of the forward kernel reaches its LDS copy with one
+// base register and a 16-bit immediate offset.
+constexpr int IMG_W2H = 0;
+constexpr int IMG_W2L = IMG_W2H + H * RS2 * 2;
+constexpr int IMG_W1H = IMG_W2L + H * RS2 * 2;   // start of the part the backward kernel stages
+constexpr int IMG_W1L = IMG_W1H + H * RS1 * 2;
+constexpr int IMG_B1 = IMG_W1L + H * RS1 * 2;
+constexpr int IMG_B2 = IMG_B1 + H * 4;
+constexpr int IMG_W3 = IMG_B2 + H * 4;
+constexpr int IMG_B3 = IMG_W3 + 3 * H * 4;
+constexpr int IMG_META = IMG_B3 + 16;
+constexpr int IMG_FWD_END = IMG_META + 48;  // end of the forward kernel's LDS image
+constexpr int IMG_W2TH = IMG_FWD_END;
+constexpr int IMG_W2TL = IMG_W2TH + H * RS2 * 2;
+constexpr int IMG_W1FH = IMG_W2TL + H * RS2 * 2;
+constexpr int IMG_W1FL = IMG_W1FH + 16 * RS2 * 2;
+constexpr int IMG_BYTES = IMG_W1FL + 16 * RS2 * 2;
+static_assert(IMG_W1H % 16 == 0 && IMG_FWD_END % 16 == 0 && IMG_BYTES % 16 == 0, "image alignment");
+
+struct Meta {
+    int sw1, sw2;           // weight exponents of W1 and W2 (W2^T shares sw2, W1F shares sw1)
+    float n1, b1max;        // max_i sum_k |W1[i][k]|, max |b1|
+    float n2t, n3t;         // max_in sum_out |W2[out][in]|, max_h sum_o |W3[o][h]|
+    int pad[6];
+};
+static_assert(sizeof(Meta) == 48, "meta size");
+
+__host__ __device__ constexpr int kidx(int kk, int q, int e) {
+    return 32 * kk + (e < 4 ? 4 * q + e : 16 + 4 * q + (e - 4));
 }
+
+__device__ __forceinline__ v4f mfma16(h8 a, h8 b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// exponent e with |v| 2^e < 2^14 for every |v| <= m
+__device__ __forceinline__ int scale_exp(float m) {
+    int k;
+    frexpf(m, &k);
+    const int e = 14 - k;
+    return e < -MAXE ? -MAXE : (e > MAXE ? MAXE : e);
+}
+
+// exponent k with m < 2^k (FRAME_NONE - style "no constraint" handled by callers for m == 0)
+__device__ __forceinline__ int ceil_exp(float m) {
+    int k;
+    frexpf(m, &k);
+    return k;
+}
+
+__device__ __forceinline__ void split4(const float v[4], float sc, h4 &hi, h4 &lo) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const float t = v[r] * sc;
+        const _Float16 h = (_Float16)t;
+        hi[r] = h;
+        lo[r] = (_Float16)(t - (float)h);
+    }
+}
+
+__device__ __forceinline__ h8 cat(h4 a, h4 b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); }
+
+__device__ __forceinline__ float pow2(int e) { return __builtin_amdgcn_ldexpf(1.f, e); }
+__device__ __forceinline__ float ldx(float v, int e) { return __builtin_amdgcn_ldexpf(v, e); }
 
 struct MlpArgs {
     const float *W1, *b1, *W2, *b2, *W3, *b3;
@@ -43,9 +124,12 @@ struct MlpArgs {
     const float *dirs;
     int S;
     const float *feat;
+    int feat_vec;        // in_feat == 12 and feat 16-byte aligned: rows load as float4
     float *rgb;
-    float *W1p;   // [H][KX] W1 with columns moved to the padded input layout (workspace)
-    float *pe;    // [R][PEW] view encodings (workspace)
+    unsigned char *img;  // weight image (workspace)
+    float *pe;           // [R][PEW] view encodings (workspace)
+    int *tile_ray;       // [ceil(S/32)] ray of the first sample of each 32-sample tile (workspace)
+    int n_tiles;         // ceil(S/32)
     const float *grad_rgb;
     float *grad_feat;
     float *partial;  // [blocks][n_params] (workspace)
@@ -54,35 +138,18 @@ struct MlpArgs {
     int nblocks;
 };
 
-// padded input column k of W1p -> column of W1 (or -1 for padding)
-__device__ __forceinline__ int w1_col(const MlpArgs &a, int k) {
-    if (k < 12) return k < a.in_feat ? k : -1;
+// padded input column k -> column of W1 (or -1 for padding)
+__host__ __device__ __forceinline__ int w1_col(int in_feat, int n_freq, int k) {
+    if (k < 12) return k < in_feat ? k : -1;
     const int p = k - 12;
-    return p < 3 + 6 * a.n_freq ? a.in_feat + p : -1;
+    return p < 3 + 6 * n_freq ? in_feat + p : -1;
 }
 
-__global__ void mlp_prep_kernel(MlpArgs a) {
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    if (tid < H * KX) {
-        const int h = tid / KX, k = tid % KX;
-        const int c = w1_col(a, k);
-        a.W1p[tid] = c >= 0 ? a.W1[h * a.n_in + c] : 0.f;
-    }
-    const int r = tid - H * KX;
-    if (r >= 0 && r < a.n_rays) {
-        const float d[3] = {a.dirs[3 * r], a.dirs[3 * r + 1], a.dirs[3 * r + 2]};
-        float *row = a.pe + (int64_t)r * PEW;
-        for (int i = 0; i < PEW; ++i) row[i] = 0.f;
-        for (int ax = 0; ax < 3; ++ax) row[ax] = d[ax];
-        for (int f = 0; f < a.n_freq; ++f)
-            for (int ax = 0; ax < 3; ++ax) {
-                const float v = ldexpf(d[ax], f);
-                row[3 + 3 * f + ax] = sinf(v);
-                row[3 + 3 * a.n_freq + 3 * f + ax] = cosf(v);
-            }
-    }
-}
+// ------------------------------------------------------------------ preparation
 
+constexpr int TILE = 32;   // samples per wave tile (forward) and per block tile (backward)
+
+// ray of sample s: the last r with offs[r] <= s (rays may be empty)
 __device__ __forceinline__ int find_ray(const int *offs, int R, int s) {
     int lo = 0, hi = R - 1;
     while (lo < hi) {
@@ -92,278 +159,915 @@ __device__ __forceinline__ int find_ray(const int *offs, int R, int s) {
     return lo;
 }
 
-// input element x[s][16 kb + 4 q + r] of this lane's sample
-__device__ __forceinline__ void load_inputs(const MlpArgs &a, int s, bool sv, int q, float xin[3][4]) {
-    int ray = sv ? find_ray(a.offs, a.n_rays, s) : 0;
-    const float *pe = a.pe + (int64_t)ray * PEW;
+// The same search for a sample of the 32-sample tile whose first sample lies on ray r0:
+// every lane of the wave holds w = offs[min(r0 + lane, R)] and the search runs over the
+// 64-entry window with shuffles; a sample beyond the window falls back to find_ray.  All
+// 64 lanes must call it (the shuffles read every lane).
+__device__ __forceinline__ int ray_in_window(const int *offs, int R, int r0, int w, int s) {
+    int lo = 0, hi = 63;
 #pragma unroll
-    for (int kb = 0; kb < 3; ++kb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int k = 16 * kb + 4 * q + r;
-            float v = 0.f;
-            if (sv) {
-                if (k < 12) v = k < a.in_feat ? a.feat[(int64_t)s * a.in_feat + k] : 0.f;
-                else v = pe[k - 12];
-            }
-            xin[kb][r] = v;
-        }
+    for (int it = 0; it < 6; ++it) {
+        const int mid = (lo + hi + 1) >> 1;
+        const int v = __shfl(w, mid, 64);
+        if (v <= s) lo = mid; else hi = mid - 1;
+    }
+    if (lo == 63 && r0 + 64 <= R && offs[r0 + 64] <= s) return find_ray(offs, R, s);
+    return r0 + lo;
 }
 
-// Forward of the three layers for the 16 samples of this wave; returns h1, h2 (post-ReLU)
-// and the pre-sigmoid output z3 (rows 0..2 of acc3 in lanes q == 0).
-template <bool W1_IN_LDS>
-__device__ __forceinline__ void mlp_forward_tile(const MlpArgs &a, const float *W1src, int w1s, const float *W2s,
-                                                 const float xin[3][4], int q, int j, v4f acc1[8], v4f acc2[8],
-                                                 v4f &acc3) {
-#pragma unroll
-    for (int m = 0; m < 8; ++m) acc1[m] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < 3; ++kb) {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const float4 w = *reinterpret_cast<const float4 *>(W1src + (16 * m + j) * w1s + 16 * kb + 4 * q);
-            acc1[m] = mfma4(w.x, xin[kb][0], acc1[m]);
-            acc1[m] = mfma4(w.y, xin[kb][1], acc1[m]);
-            acc1[m] = mfma4(w.z, xin[kb][2], acc1[m]);
-            acc1[m] = mfma4(w.w, xin[kb][3], acc1[m]);
+__device__ __forceinline__ int window_entry(const int *offs, int R, int r0) {
+    const int i = r0 + lane();
+    return offs[i < R ? i : R];
+}
+
+__device__ float block_max(float v, float *red) {
+    // blockDim.x is a multiple of 64 and at most 1024
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if (lane() == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float m = 0.f;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) m = fmaxf(m, red[i]);
+    return m;
+}
+
+__device__ __forceinline__ void put_split(unsigned char *img, int off_h, int off_l, int idx, float v, float sc) {
+    const float t = v * sc;
+    const _Float16 h = (_Float16)t;
+    reinterpret_cast<_Float16 *>(img + off_h)[idx] = h;
+    reinterpret_cast<_Float16 *>(img + off_l)[idx] = (_Float16)(t - (float)h);
+}
+
+// logical index of phys slot p of a 128- or 64-wide operand row
+__device__ __forceinline__ int phys_to_k(int p) { return kidx(p >> 5, (p >> 3) & 3, p & 7); }
+
+constexpr int PREP_THREADS = 256;
+constexpr int PREP_W2_BLOCKS = 8;
+constexpr int PREP_FIXED_BLOCKS = PREP_W2_BLOCKS + 3;
+
+// blocks 0..7: W2 and W2^T planes (16 rows each); block 8: W1 planes, W1F planes, b1, b3,
+// n1, b1max, sw1; block 9: W3, b2, n3t; block 10: n2t, sw2; blocks 11..: view encodings.
+__global__ __launch_bounds__(PREP_THREADS) void mlp_prep_kernel(MlpArgs a) {
+    __shared__ float red[PREP_THREADS / 64];
+    unsigned char *img = a.img;
+    Meta *meta = reinterpret_cast<Meta *>(img + IMG_META);
+    const int tid = threadIdx.x, b = blockIdx.x;
+    if (b < PREP_W2_BLOCKS) {
+        float m = 0.f;
+        for (int i = tid; i < H * H; i += PREP_THREADS) m = fmaxf(m, fabsf(a.W2[i]));
+        const int sw = scale_exp(block_max(m, red));
+        const float sc = pow2(sw);
+        for (int i = tid; i < 16 * RS2; i += PREP_THREADS) {
+            const int row = 16 * b + i / RS2, p = i % RS2;
+            const int k = p < H ? phys_to_k(p) : -1;
+            put_split(img, IMG_W2H, IMG_W2L, row * RS2 + p, k >= 0 ? a.W2[row * H + k] : 0.f, sc);
+            put_split(img, IMG_W2TH, IMG_W2TL, row * RS2 + p, k >= 0 ? a.W2[k * H + row] : 0.f, sc);
         }
-    }
-#pragma unroll
-    for (int m = 0; m < 8; ++m)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc1[m][r] = fmaxf(acc1[m][r] + a.b1[16 * m + 4 * q + r], 0.f);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) acc2[m] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const float4 w = *reinterpret_cast<const float4 *>(W2s + (16 * m + j) * W2S + 16 * t + 4 * q);
-            acc2[m] = mfma4(w.x, acc1[t][0], acc2[m]);
-            acc2[m] = mfma4(w.y, acc1[t][1], acc2[m]);
-            acc2[m] = mfma4(w.z, acc1[t][2], acc2[m]);
-            acc2[m] = mfma4(w.w, acc1[t][3], acc2[m]);
+        if (b == 0 && tid == 0) meta->sw2 = sw;
+    } else if (b == PREP_W2_BLOCKS) {
+        float m = 0.f, rs = 0.f, bm = 0.f;
+        for (int i = tid; i < H * a.n_in; i += PREP_THREADS) m = fmaxf(m, fabsf(a.W1[i]));
+        if (tid < H) {
+            for (int k = 0; k < a.n_in; ++k) rs += fabsf(a.W1[tid * a.n_in + k]);
+            bm = fabsf(a.b1[tid]);
         }
-        // keep the scheduler from hoisting every weight load of the layer (register spills)
-        __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int m = 0; m < 8; ++m)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc2[m][r] = fmaxf(acc2[m][r] + a.b2[16 * m + 4 * q + r], 0.f);
-    acc3 = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float w = j < 3 ? a.W3[j * H + 16 * t + 4 * q + r] : 0.f;
-            acc3 = mfma4(w, acc2[t][r], acc3);
+        const int sw = scale_exp(block_max(m, red));
+        const float n1 = block_max(rs, red);
+        const float b1max = block_max(bm, red);
+        const float sc = pow2(sw);
+        for (int i = tid; i < H * RS1; i += PREP_THREADS) {
+            const int row = i / RS1, p = i % RS1;
+            const int c = p < KX ? w1_col(a.in_feat, a.n_freq, phys_to_k(p)) : -1;
+            put_split(img, IMG_W1H, IMG_W1L, i, c >= 0 ? a.W1[row * a.n_in + c] : 0.f, sc);
+        }
+        // W1F[c][phys over hidden] = W1[hidden][c] for the feature columns c < in_feat
+        for (int i = tid; i < 16 * RS2; i += PREP_THREADS) {
+            const int c = i / RS2, p = i % RS2;
+            const int h = p < H ? phys_to_k(p) : -1;
+            put_split(img, IMG_W1FH, IMG_W1FL, i, (h >= 0 && c < a.in_feat) ? a.W1[h * a.n_in + c] : 0.f, sc);
+        }
+        float *b1 = reinterpret_cast<float *>(img + IMG_B1);
+        float *b3 = reinterpret_cast<float *>(img + IMG_B3);
+        if (tid < H) b1[tid] = a.b1[tid];
+        if (tid < 4) b3[tid] = tid < 3 ? a.b3[tid] : 0.f;
+        if (tid == 0) {
+            meta->sw1 = sw;
+            meta->n1 = n1;
+            meta->b1max = b1max;
+        }
+    } else if (b == PREP_W2_BLOCKS + 1) {
+        float *w3 = reinterpret_cast<float *>(img + IMG_W3);
+        float *b2 = reinterpret_cast<float *>(img + IMG_B2);
+        float cs = 0.f;
+        for (int i = tid; i < 3 * H; i += PREP_THREADS) w3[i] = a.W3[i];
+        if (tid < H) {
+            b2[tid] = a.b2[tid];
+            cs = fabsf(a.W3[tid]) + fabsf(a.W3[H + tid]) + fabsf(a.W3[2 * H + tid]);
+        }
+        const float n3t = block_max(cs, red);
+        if (tid == 0) meta->n3t = n3t;
+    } else if (b == PREP_W2_BLOCKS + 2) {
+        float cs = 0.f;
+        if (tid < H)
+            for (int o = 0; o < H; ++o) cs += fabsf(a.W2[o * H + tid]);
+        const float n2t = block_max(cs, red);
+        if (tid == 0) meta->n2t = n2t;
+    } else if (b >= PREP_FIXED_BLOCKS + (a.n_rays + PREP_THREADS - 1) / PREP_THREADS) {
+        const int t = (b - PREP_FIXED_BLOCKS - (a.n_rays + PREP_THREADS - 1) / PREP_THREADS) * PREP_THREADS + tid;
+        if (t < a.n_tiles) a.tile_ray[t] = find_ray(a.offs, a.n_rays, TILE * t);
+    } else {
+        const int r = (b - PREP_FIXED_BLOCKS) * PREP_THREADS + tid;
+        if (r < a.n_rays) {
+            const float d[3] = {a.dirs[3 * r], a.dirs[3 * r + 1], a.dirs[3 * r + 2]};
+            float *row = a.pe + (int64_t)r * PEW;
+            for (int i = 0; i < PEW; ++i) row[i] = 0.f;
+            for (int ax = 0; ax < 3; ++ax) row[ax] = d[ax];
+            for (int f = 0; f < a.n_freq; ++f)
+                for (int ax = 0; ax < 3; ++ax) {
+                    const float v = ldexpf(d[ax], f);
+                    row[3 + 3 * f + ax] = sinf(v);
+                    row[3 + 3 * a.n_freq + 3 * f + ax] = cosf(v);
+                }
         }
     }
 }
+
+
+// Pointer into a kernel's LDS block at byte offset `off`, with the offset hidden from the
+// optimiser: accesses then share one base register and use the 16-bit immediate offset of
+// ds_read/ds_write instead of one materialised address per constant offset above 64 KB.
+__device__ __forceinline__ unsigned char *lds_region(unsigned char *sm, int off) {
+    asm volatile("" : "+s"(off));
+    return sm + off;
+}
+
+// A lane index the optimiser must treat as new in every loop iteration, so that address
+// arithmetic built from it is recomputed next to its use (and folded into instruction
+// offsets) instead of being hoisted out of the loop into long-lived registers.
+__device__ __forceinline__ int fresh(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+__device__ __forceinline__ float4 feat4(const MlpArgs &a, int s, int c0) {
+    const float *fp = a.feat + (int64_t)s * a.in_feat;
+    if (a.feat_vec) return *reinterpret_cast<const float4 *>(fp + c0);
+    return make_float4(c0 < a.in_feat ? fp[c0] : 0.f, c0 + 1 < a.in_feat ? fp[c0 + 1] : 0.f,
+                       c0 + 2 < a.in_feat ? fp[c0 + 2] : 0.f, c0 + 3 < a.in_feat ? fp[c0 + 3] : 0.f);
+}
+
+// The 8 inputs of operand slot group (kk, q) of a valid sample s on ray `ray`: logical
+// columns k(kk, q, 0..7).  For kk = 0 these are features 4q..4q+3 (view encoding 0..3 when
+// q = 3) and view encoding 4+4q..7+4q; for kk = 1 view encoding 20+4q..23+4q and padding.
+__device__ __forceinline__ void load_x8(const MlpArgs &a, int s, int ray, int kk, int q, float v[8]) {
+    const float *pe = a.pe + (int64_t)ray * PEW;
+    float4 lo, hi;
+    if (kk == 0) {
+        lo = q < 3 ? feat4(a, s, 4 * q) : *reinterpret_cast<const float4 *>(pe);
+        hi = *reinterpret_cast<const float4 *>(pe + 4 + 4 * q);
+    } else {
+        lo = *reinterpret_cast<const float4 *>(pe + 20 + 4 * q);
+        hi = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w;
+    v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
+}
+
+__device__ __forceinline__ void copy_to_lds(unsigned char *dst, const unsigned char *src, int bytes) {
+    for (int i = threadIdx.x * 16; i < bytes; i += blockDim.x * 16)
+        *reinterpret_cast<uint4 *>(dst + i) = *reinterpret_cast<const uint4 *>(src + i);
+}
+
+// ------------------------------------------------------------------ forward
+
+constexpr int FWD_WAVES = 8, FWD_THREADS = 64 * FWD_WAVES;
+constexpr int FWD_NC = 2;                 // 16-sample column tiles per wave tile
+constexpr int FWD_WTILE = 16 * FWD_NC;    // samples per wave tile
+static_assert(FWD_WTILE == TILE, "forward wave tiles are the 32-sample tiles of tile_ray");
 
 __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
-    __shared__ float W2s[H * W2S];
-    __shared__ float W1s[H * W1S];
-    for (int i = threadIdx.x; i < H * H; i += FWD_THREADS) W2s[(i / H) * W2S + (i % H)] = a.W2[i];
-    for (int i = threadIdx.x; i < H * KX; i += FWD_THREADS) W1s[(i / KX) * W1S + (i % KX)] = a.W1p[i];
+    __shared__ __attribute__((aligned(16))) unsigned char sm[IMG_FWD_END];
+    copy_to_lds(sm, a.img, IMG_FWD_END);
     __syncthreads();
-    const int wv = threadIdx.x >> 6, ln = lane(), j = ln & 15, q = ln >> 4;
-    const int ntiles = (a.S + FWD_TILE - 1) / FWD_TILE;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int s = tile * FWD_TILE + wv * 16 + j;
-        const bool sv = s < a.S;
-        float xin[3][4];
-        load_inputs(a, s, sv, q, xin);
-        v4f acc1[8], acc2[8], acc3;
-        mlp_forward_tile<true>(a, W1s, W1S, W2s, xin, q, j, acc1, acc2, acc3);
-        if (q == 0 && sv) {
+    const _Float16 *W2h = reinterpret_cast<const _Float16 *>(sm + IMG_W2H);
+    const _Float16 *W2l = reinterpret_cast<const _Float16 *>(sm + IMG_W2L);
+    const unsigned char *r1 = lds_region(sm, IMG_W1H);
+    const _Float16 *W1h = reinterpret_cast<const _Float16 *>(r1);
+    const _Float16 *W1l = reinterpret_cast<const _Float16 *>(r1 + (IMG_W1L - IMG_W1H));
+    const float *b1 = reinterpret_cast<const float *>(r1 + (IMG_B1 - IMG_W1H));
+    const float *b2 = reinterpret_cast<const float *>(r1 + (IMG_B2 - IMG_W1H));
+    const float *W3 = reinterpret_cast<const float *>(r1 + (IMG_W3 - IMG_W1H));
+    const float *b3 = reinterpret_cast<const float *>(r1 + (IMG_B3 - IMG_W1H));
+    const Meta meta = *reinterpret_cast<const Meta *>(r1 + (IMG_META - IMG_W1H));
+    const int ln = lane(), j = ln & 15, q = ln >> 4;
+    const int nwt = (a.S + FWD_WTILE - 1) / FWD_WTILE;
+    for (int wt = blockIdx.x * FWD_WAVES + (threadIdx.x >> 6); wt < nwt; wt += gridDim.x * FWD_WAVES) {
+        int s[FWD_NC], ex[FWD_NC], e1[FWD_NC];
+        bool sv[FWD_NC];
+        h8 xh[FWD_NC][2], xl[FWD_NC][2];
+        const int r0 = a.tile_ray[wt];
+        const int win = window_entry(a.offs, a.n_rays, r0);
 #pragma unroll
-            for (int r = 0; r < 3; ++r) a.rgb[(int64_t)s * 3 + r] = sigmoidf(acc3[r] + a.b3[r]);
+        for (int c = 0; c < FWD_NC; ++c) {
+            s[c] = wt * FWD_WTILE + 16 * c + j;
+            sv[c] = s[c] < a.S;
+            int ray = ray_in_window(a.offs, a.n_rays, r0, win, s[c]);
+            if (!sv[c]) ray = 0;
+            float xv[2][8], m = 0.f;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                if (sv[c]) load_x8(a, s[c], ray, kk, q, xv[kk]);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    if (!sv[c]) xv[kk][e] = 0.f;
+                    m = fmaxf(m, fabsf(xv[kk][e]));
+                }
+            }
+            m = fmaxf(m, __shfl_xor(m, 16, 64));
+            m = fmaxf(m, __shfl_xor(m, 32, 64));
+            ex[c] = scale_exp(m);
+            e1[c] = scale_exp(meta.n1 * m + meta.b1max);
+            const float sc = pow2(ex[c]);
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                h4 h0, l0, h1, l1;
+                split4(&xv[kk][0], sc, h0, l0);
+                split4(&xv[kk][4], sc, h1, l1);
+                xh[c][kk] = cat(h0, h1);
+                xl[c][kk] = cat(l0, l1);
+            }
         }
+        // layer 1: h1 = relu(W1 x + b1), kept as the split B operand of layer 2
+        h4 hh[FWD_NC][8], hl[FWD_NC][8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            v4f acc[FWD_NC];
+#pragma unroll
+            for (int c = 0; c < FWD_NC; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int o = (16 * m + j) * RS1 + 32 * kk + 8 * q;
+                const h8 ah = *reinterpret_cast<const h8 *>(W1h + o);
+                const h8 al = *reinterpret_cast<const h8 *>(W1l + o);
+#pragma unroll
+                for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(al, xh[c][kk], acc[c]);
+#pragma unroll
+                for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, xl[c][kk], acc[c]);
+#pragma unroll
+                for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, xh[c][kk], acc[c]);
+            }
+            const float4 bb = *reinterpret_cast<const float4 *>(b1 + 16 * m + 4 * q);
+#pragma unroll
+            for (int c = 0; c < FWD_NC; ++c) {
+                const int un = -(meta.sw1 + ex[c]);
+                float v[4] = {fmaxf(ldx(acc[c][0], un) + bb.x, 0.f), fmaxf(ldx(acc[c][1], un) + bb.y, 0.f),
+                              fmaxf(ldx(acc[c][2], un) + bb.z, 0.f), fmaxf(ldx(acc[c][3], un) + bb.w, 0.f)};
+                split4(v, pow2(e1[c]), hh[c][m], hl[c][m]);
+            }
+            // keep the scheduler from hoisting every weight load of the layer (spills)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        // layer 2 and the output layer: z3 = W3 relu(W2 h1 + b2) (+ b3), output rows on VALU
+        float z[FWD_NC][3];
+#pragma unroll
+        for (int c = 0; c < FWD_NC; ++c) z[c][0] = z[c][1] = z[c][2] = 0.f;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            v4f acc[FWD_NC];
+#pragma unroll
+            for (int c = 0; c < FWD_NC; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int o = (16 * m + j) * RS2 + 32 * kk + 8 * q;
+                const h8 ah = *reinterpret_cast<const h8 *>(W2h + o);
+                const h8 al = *reinterpret_cast<const h8 *>(W2l + o);
+#pragma unroll
+                for (int c = 0; c < FWD_NC; ++c) {
+                    const h8 bh = cat(hh[c][2 * kk], hh[c][2 * kk + 1]);
+                    acc[c] = mfma16(al, bh, acc[c]);
+                }
+#pragma unroll
+                for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, cat(hl[c][2 * kk], hl[c][2 * kk + 1]), acc[c]);
+#pragma unroll
+                for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, cat(hh[c][2 * kk], hh[c][2 * kk + 1]), acc[c]);
+            }
+            const float4 bb = *reinterpret_cast<const float4 *>(b2 + 16 * m + 4 * q);
+            const float4 w0 = *reinterpret_cast<const float4 *>(W3 + 16 * m + 4 * q);
+            const float4 w1 = *reinterpret_cast<const float4 *>(W3 + H + 16 * m + 4 * q);
+            const float4 w2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + 16 * m + 4 * q);
+            const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+            const float wv[3][4] = {{w0.x, w0.y, w0.z, w0.w}, {w1.x, w1.y, w1.z, w1.w}, {w2.x, w2.y, w2.z, w2.w}};
+#pragma unroll
+            for (int c = 0; c < FWD_NC; ++c) {
+                const int un = -(meta.sw2 + e1[c]);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const float h2 = fmaxf(ldx(acc[c][r], un) + bv[r], 0.f);
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) z[c][o] += wv[o][r] * h2;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int c = 0; c < FWD_NC; ++c) {
+#pragma unroll
+            for (int o = 0; o < 3; ++o) {
+                z[c][o] += __shfl_xor(z[c][o], 16, 64);
+                z[c][o] += __shfl_xor(z[c][o], 32, 64);
+            }
+            const float zq = q == 0 ? z[c][0] : (q == 1 ? z[c][1] : z[c][2]);
+            if (q < 3 && sv[c]) a.rgb[(int64_t)s[c] * 3 + q] = sigmoidf(zq + b3[q]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ backward
+//
+// Block = 8 waves in two roles that alternate through four block-wide phases per tile of
+// NT = 32 samples.  P waves (0..3) own units 32p..32p+31 of both hidden layers for the
+// forward recompute and hold those rows of W1 and W2 in registers; C waves (4..7) own the
+// same units for the backward chain, hold those rows of W2^T, and stage the inputs of the
+// next tile while the P waves compute.  Per tile t (inputs of t already staged):
+//   phase 1  P: layer 1 -> h1 B operand, h1^T, mask bits C: feature gradient of t-1
+//   phase 2  P: layer 2 -> h2, logit partials            C: dW1 += dz1^T x of t-1; loads of t+1
+//   phase 3  P: dz3, dz2 -> dz2 B operand, dz2^T (frame) C: dz3, exponents, dW3 b2 b3 sums;
+//                                                           inputs of t+1 -> x planes
+//   phase 4  P: dW2 += dz2^T h1                          C: dz1, dfeat partials, dz1^T (frame)
+// Both roles run the same number of barriers per tile, so s_barrier stays matched.
+
+constexpr int BWD_WAVES = 8, BWD_THREADS = 64 * BWD_WAVES;
+constexpr int NT = TILE;  // samples per block tile (two 16-sample column tiles)
+
+// LDS of the backward kernel (bytes); the small image part is staged at offset 0
+constexpr int BS = IMG_FWD_END - IMG_B1;             // b1, b2, W3, b3, meta
+constexpr int BSL(int img_off) { return img_off - IMG_B1; }
+constexpr int XB_BYTES = 2 * NT * RS1 * 2;           // x B operand [NT][RS1] hi, lo
+constexpr int XT_BYTES = 2 * NXIN * TS * 2;          // x^T [NXIN][TS] hi, lo
+constexpr int B_XB0 = BS;                            // two buffers of each (tile parity)
+constexpr int B_XT0 = B_XB0 + 2 * XB_BYTES;
+constexpr int B_HBH = B_XT0 + 2 * XT_BYTES;          // h1 then dz2, B operand [NT][RS2]
+constexpr int B_HBL = B_HBH + NT * RS2 * 2;
+constexpr int B_HTH = B_HBL + NT * RS2 * 2;          // h1^T [H][TS]
+constexpr int B_HTL = B_HTH + H * TS * 2;
+constexpr int B_D2TH = B_HTL + H * TS * 2;           // dz2^T [H][TS] (frame-scaled)
+constexpr int B_D2TL = B_D2TH + H * TS * 2;
+constexpr int B_D1TH = B_D2TL + H * TS * 2;          // dz1^T [H][TS] (frame-scaled)
+constexpr int B_D1TL = B_D1TH + H * TS * 2;
+constexpr int B_Z3P = B_D1TL + H * TS * 2;           // logit partials [4][NT][4] f32
+constexpr int B_DFP = B_Z3P + 4 * NT * 4 * 4;        // dfeat partials [4][NT][16] f32
+constexpr int H2S = 36;                              // row stride (floats) of the h2 plane
+constexpr int B_H2 = B_DFP + 4 * NT * 16 * 4;        // h2 [H][H2S] f32, written by P, read by C
+constexpr int B_MASK = B_H2 + H * H2S * 4;           // h1 > 0 ballots [4][2][2][4] u64
+constexpr int B_XMAX = B_MASK + 4 * 16 * 8;          // max |x| per sample [2][NT]
+constexpr int B_GR = B_XMAX + 2 * NT * 4;            // grad_rgb [2][NT][4]
+constexpr int B_END = B_GR + 2 * NT * 16;
+static_assert(B_END <= 160 * 1024, "backward LDS");
+static_assert(B_XB0 % 16 == 0 && B_HBH % 16 == 0 && B_HTH % 16 == 0 && B_D1TH % 16 == 0 && B_Z3P % 16 == 0,
+              "LDS alignment");
+
+// exponent that moves a gradient column into the accumulator frame F (operand scale e of
+// the other factor); a zero column stays zero for any shift, so the clamp only guards range
+__device__ __forceinline__ int frame_shift(int F, int e) {
+    const int d = F - e;
+    return d < -300 ? -300 : (d > 300 ? 300 : d);
+}
+
+__device__ __forceinline__ h8 lds_h8(const unsigned char *base, int off, int idx) {
+    return *reinterpret_cast<const h8 *>(reinterpret_cast<const _Float16 *>(base + off) + idx);
+}
+
+__device__ __forceinline__ h8 glb_h8(const unsigned char *img, int off, int idx) {
+    return *reinterpret_cast<const h8 *>(reinterpret_cast<const _Float16 *>(img + off) + idx);
+}
+
+// write a split value into a transposed plane [unit][TS]
+__device__ __forceinline__ void put_t(unsigned char *base, int off_h, int off_l, int unit, int col, float t) {
+    const _Float16 h = (_Float16)t;
+    reinterpret_cast<_Float16 *>(base + off_h)[unit * TS + col] = h;
+    reinterpret_cast<_Float16 *>(base + off_l)[unit * TS + col] = (_Float16)(t - (float)h);
+}
+
+__device__ __forceinline__ void store_h4(unsigned char *base, int off, int idx, h4 v) {
+    *reinterpret_cast<h4 *>(reinterpret_cast<_Float16 *>(base + off) + idx) = v;
+}
+
+// Per-sample quantities every wave derives identically from LDS (columns c: sample 16c + j)
+struct SampleExp {
+    int ex[2], e1[2];
+};
+
+__device__ __forceinline__ SampleExp sample_exp(const float *xmax_s, const Meta &meta, int j) {
+    SampleExp r;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const float xm = xmax_s[16 * c + j];
+        r.ex[c] = scale_exp(xm);
+        r.e1[c] = scale_exp(meta.n1 * xm + meta.b1max);
+    }
+    return r;
+}
+
+// Output-layer gradient of this lane's two samples and the exponents that follow from it.
+struct GradExp {
+    float dz3[2][3];
+    int g2[2], g1[2], k2[2], k1[2];
+};
+
+__device__ __forceinline__ GradExp grad_exp(const float *z3p, const float *gr_s, const float *b3, const Meta &meta,
+                                            int j) {
+    GradExp g;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int sl = 16 * c + j;
+        float mx = 0.f;
+#pragma unroll
+        for (int o = 0; o < 3; ++o) {
+            float z = b3[o];
+#pragma unroll
+            for (int ww = 0; ww < 4; ++ww) z += z3p[(ww * NT + sl) * 4 + o];
+            const float y = sigmoidf(z);
+            g.dz3[c][o] = gr_s[sl * 4 + o] * y * (1.f - y);
+            mx = fmaxf(mx, fabsf(g.dz3[c][o]));
+        }
+        // |dz2| <= n3t max|dz3| and |dz1| <= n2t |dz2| (infinity norms of W3^T and W2^T)
+        const float bnd2 = meta.n3t * mx, bnd1 = meta.n2t * bnd2;
+        g.g2[c] = scale_exp(bnd2);
+        g.g1[c] = scale_exp(bnd1);
+        g.k2[c] = bnd2 > 0.f ? ceil_exp(bnd2) : -FRAME_NONE;
+        g.k1[c] = bnd1 > 0.f ? ceil_exp(bnd1) : -FRAME_NONE;
+    }
+    return g;
+}
+
+// smallest frame the tile allows: F <= 14 + (other operand's exponent) - ceil_exp(bound)
+__device__ __forceinline__ int tile_frame(const int other_e[2], const int k[2]) {
+    int f = FRAME_NONE;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) f = min(f, 14 + other_e[c] - k[c]);
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) f = min(f, __shfl_xor(f, o, 64));
+    return f;
+}
+
+template <int N>
+__device__ __forceinline__ void rescale(v4f (&acc)[2][N], int &F, int f) {
+    if (f < F) {
+        const int d = max(f - F, -300);
+#pragma unroll
+        for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+            for (int n = 0; n < N; ++n)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[mp][n][r] = ldx(acc[mp][n][r], d);
+        F = f;
     }
 }
 
 __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
-    __shared__ float W2s[H * W2S];
-    __shared__ float bufA[BWD_TILE * SH];
-    __shared__ float bufB[BWD_TILE * SH];
-    __shared__ float xs[BWD_TILE * XS];
-    __shared__ float dz3s[BWD_TILE * 4];
-    for (int i = threadIdx.x; i < H * H; i += BWD_THREADS) W2s[(i / H) * W2S + (i % H)] = a.W2[i];
-    __syncthreads();
-    const int tid = threadIdx.x;
-    const int wv = tid >> 6, ln = lane(), j = ln & 15, q = ln >> 4;
-    v4f dW2acc[2][8], dW1acc[2][3], dW3acc[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) dW2acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < 3; ++t) dW1acc[i][t] = v4f{0.f, 0.f, 0.f, 0.f};
-        dW3acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
-    }
-    float db_acc = 0.f;   // threads 0..127: b2[tid] (phase 1) and b1[tid] (phase 2) share nothing
-    float db1_acc = 0.f;
-    float db3_acc = 0.f;  // threads 128..130
-    const int ntiles = (a.S + BWD_TILE - 1) / BWD_TILE;
-    const int row = wv * 16 + j;  // this lane's sample row inside the tile
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int s = tile * BWD_TILE + row;
-        const bool sv = s < a.S;
-        float xin[3][4];
-        load_inputs(a, s, sv, q, xin);
-#pragma unroll
-        for (int kb = 0; kb < 3; ++kb)
-            *reinterpret_cast<float4 *>(&xs[row * XS + 16 * kb + 4 * q]) =
-                make_float4(xin[kb][0], xin[kb][1], xin[kb][2], xin[kb][3]);
-        v4f acc1[8], acc2[8], acc3;
-        mlp_forward_tile<false>(a, a.W1p, KX, W2s, xin, q, j, acc1, acc2, acc3);
-        // output layer: dz3 = dL/drgb * y (1 - y) (lanes q == 0 hold rows o = 0..3)
-        float dz3v[4] = {0.f, 0.f, 0.f, 0.f};
-        if (q == 0 && sv) {
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                const float y = sigmoidf(acc3[r] + a.b3[r]);
-                dz3v[r] = a.grad_rgb[(int64_t)s * 3 + r] * y * (1.f - y);
-            }
-        }
-        if (q == 0) *reinterpret_cast<float4 *>(&dz3s[row * 4]) = make_float4(dz3v[0], dz3v[1], dz3v[2], dz3v[3]);
-        // B operand dz3[o = q][s_j] lives in lane (0, j), element q
-        float bq = 0.f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float t = __shfl(dz3v[r], j, 64);
-            if (q == r) bq = t;
-        }
-        // dh2 = W3^T dz3 (one K-step over o), then ReLU mask of layer 2
-        v4f dz2[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const float w = q < 3 ? a.W3[q * H + 16 * m + j] : 0.f;
-            dz2[m] = mfma4(w, bq, v4f{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dz2[m][r] = acc2[m][r] > 0.f ? dz2[m][r] : 0.f;
-        }
-        // dh1 = W2^T dz2: reduction over h' = 16 t + 4 q + r, A = W2[h'][16 m + j]
-        v4f dz1[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) dz1[m] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float *wrow = W2s + (16 * t + 4 * q + r) * W2S + j;
-#pragma unroll
-                for (int m = 0; m < 8; ++m) dz1[m] = mfma4(wrow[16 * m], dz2[t][r], dz1[m]);
-            }
-        }
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) dz1[m][r] = acc1[m][r] > 0.f ? dz1[m][r] : 0.f;
-        // dfeat = W1f^T dz1: rows = feature column c = j (< 12), reduction over h
-        v4f df = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const float w = j < 12 ? a.W1p[(16 * m + 4 * q + r) * KX + j] : 0.f;
-                df = mfma4(w, dz1[m][r], df);
-            }
-        if (sv) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int c = 4 * q + r;
-                if (c < a.in_feat) a.grad_feat[(int64_t)s * a.in_feat + c] = df[r];
-            }
-        }
-        // ---- phase 1: dW2 = sum_s dz2 h1^T, db2 = sum_s dz2
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            *reinterpret_cast<float4 *>(&bufA[row * SH + 16 * m + 4 * q]) =
-                make_float4(dz2[m][0], dz2[m][1], dz2[m][2], dz2[m][3]);
-            *reinterpret_cast<float4 *>(&bufB[row * SH + 16 * m + 4 * q]) =
-                make_float4(acc1[m][0], acc1[m][1], acc1[m][2], acc1[m][3]);
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int ks = 0; ks < BWD_TILE / 4; ++ks) {
-            const float *ra = bufA + (4 * ks + q) * SH + j;
-            const float *rb = bufB + (4 * ks + q) * SH + j;
-            const float a0 = ra[16 * (2 * wv)], a1 = ra[16 * (2 * wv + 1)];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const float bv = rb[16 * t];
-                dW2acc[0][t] = mfma4(a0, bv, dW2acc[0][t]);
-                dW2acc[1][t] = mfma4(a1, bv, dW2acc[1][t]);
-            }
-        }
-        if (tid < H) {
-            float sacc = 0.f;
-            for (int r = 0; r < BWD_TILE; ++r) sacc += bufA[r * SH + tid];
-            db_acc += sacc;
-        }
-        __syncthreads();
-        // ---- phase 2: dW1 = sum_s dz1 x^T, dW3 = sum_s dz3 h2^T, db1, db3
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            *reinterpret_cast<float4 *>(&bufA[row * SH + 16 * m + 4 * q]) =
-                make_float4(dz1[m][0], dz1[m][1], dz1[m][2], dz1[m][3]);
-            *reinterpret_cast<float4 *>(&bufB[row * SH + 16 * m + 4 * q]) =
-                make_float4(acc2[m][0], acc2[m][1], acc2[m][2], acc2[m][3]);
-        }
-        __syncthreads();
-#pragma unroll 2
-        for (int ks = 0; ks < BWD_TILE / 4; ++ks) {
-            const int sr = 4 * ks + q;
-            const float a0 = bufA[sr * SH + 16 * (2 * wv) + j], a1 = bufA[sr * SH + 16 * (2 * wv + 1) + j];
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const float bv = xs[sr * XS + 16 * t + j];
-                dW1acc[0][t] = mfma4(a0, bv, dW1acc[0][t]);
-                dW1acc[1][t] = mfma4(a1, bv, dW1acc[1][t]);
-            }
-            const float a3 = j < 3 ? dz3s[sr * 4 + j] : 0.f;
-            dW3acc[0] = mfma4(a3, bufB[sr * SH + 16 * (2 * wv) + j], dW3acc[0]);
-            dW3acc[1] = mfma4(a3, bufB[sr * SH + 16 * (2 * wv + 1) + j], dW3acc[1]);
-        }
-        if (tid < H) {
-            float sacc = 0.f;
-            for (int r = 0; r < BWD_TILE; ++r) sacc += bufA[r * SH + tid];
-            db1_acc += sacc;
-        } else if (tid < H + 3) {
-            float sacc = 0.f;
-            for (int r = 0; r < BWD_TILE; ++r) sacc += dz3s[r * 4 + (tid - H)];
-            db3_acc += sacc;
-        }
-        __syncthreads();
-    }
-    // ---- write this block's partial gradients in parameter order W1, b1, W2, b2, W3, b3
+    __shared__ __attribute__((aligned(16))) unsigned char sm[B_END];
+    copy_to_lds(sm, a.img + IMG_B1, BS);
+    const int tid = threadIdx.x, ln = lane(), j = ln & 15, q = ln >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const Meta meta = *reinterpret_cast<const Meta *>(a.img + IMG_META);
+    const float *b1 = reinterpret_cast<const float *>(sm + BSL(IMG_B1));
+    const float *b2 = reinterpret_cast<const float *>(sm + BSL(IMG_B2));
+    const float *W3 = reinterpret_cast<const float *>(sm + BSL(IMG_W3));
+    const float *b3 = reinterpret_cast<const float *>(sm + BSL(IMG_B3));
+    unsigned char *rA = lds_region(sm, B_HBH);   // HB, HT, D2T
+    unsigned char *rB = lds_region(sm, B_D1TH);  // D1T, partials, per-sample values
+    float *z3p = reinterpret_cast<float *>(rB + (B_Z3P - B_D1TH));
+    float *dfp = reinterpret_cast<float *>(rB + (B_DFP - B_D1TH));
+    float *xmax_b = reinterpret_cast<float *>(rB + (B_XMAX - B_D1TH));
+    float *gr_b = reinterpret_cast<float *>(rB + (B_GR - B_D1TH));
+    float *h2s = reinterpret_cast<float *>(rB + (B_H2 - B_D1TH));
+    unsigned long long *mask1 = reinterpret_cast<unsigned long long *>(rB + (B_MASK - B_D1TH));
+    const int ntiles = a.n_tiles;
     float *P = a.partial + (int64_t)blockIdx.x * a.n_params;
     float *pW1 = P, *pb1 = pW1 + H * a.n_in, *pW2 = pb1 + H, *pb2 = pW2 + H * H, *pW3 = pb2 + H, *pb3 = pW3 + 3 * H;
+
+    if (wave < 4) {
+        // ================================================================ P waves
+        const int w = wave;
+        h8 w2h[2][4], w2l[2][4], w1h[2][2], w1l[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int m = 2 * wv + i;
+        for (int mp = 0; mp < 2; ++mp) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int hrow = 16 * m + 4 * q + r;
-#pragma unroll
-            for (int t = 0; t < 8; ++t) pW2[hrow * H + 16 * t + j] = dW2acc[i][t][r];
-#pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const int c = w1_col(a, 16 * t + j);
-                if (c >= 0) pW1[hrow * a.n_in + c] = dW1acc[i][t][r];
+            for (int kk = 0; kk < 4; ++kk) {
+                const int o = (32 * w + 16 * mp + j) * RS2 + 32 * kk + 8 * q;
+                w2h[mp][kk] = glb_h8(a.img, IMG_W2H, o);
+                w2l[mp][kk] = glb_h8(a.img, IMG_W2L, o);
             }
-            if (q == 0 && r < 3) pW3[r * H + 16 * (2 * wv + i) + j] = dW3acc[i][r];
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int o = (32 * w + 16 * mp + j) * RS1 + 32 * kk + 8 * q;
+                w1h[mp][kk] = glb_h8(a.img, IMG_W1H, o);
+                w1l[mp][kk] = glb_h8(a.img, IMG_W1L, o);
+            }
         }
-    }
-    if (tid < H) {
-        pb2[tid] = db_acc;
-        pb1[tid] = db1_acc;
-    } else if (tid < H + 3) {
-        pb3[tid - H] = db3_acc;
+        v4f dW2[2][8];
+#pragma unroll
+        for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+            for (int n = 0; n < 8; ++n) dW2[mp][n] = v4f{0.f, 0.f, 0.f, 0.f};
+        int F2 = FRAME_NONE;
+        __syncthreads();  // staged image and the first tile's inputs
+        int it = 0;
+        for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
+            const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
+            const int pb = it & 1;
+            const float *xmax_s = xmax_b + pb * NT;
+            const float *gr_s = gr_b + pb * NT * 4;
+            const int xb = B_XB0 + pb * XB_BYTES;
+            // ---- phase 1: layer 1 for units 32w..; h1 -> B operand, transposed planes, mask bits
+            {
+                const SampleExp se = sample_exp(xmax_s, meta, j);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+                    for (int kk = 0; kk < 2; ++kk) {
+                        const h8 bh = lds_h8(sm, xb, (16 * c + j) * RS1 + 32 * kk + 8 * q);
+                        const h8 bl = lds_h8(sm, xb + NT * RS1 * 2, (16 * c + j) * RS1 + 32 * kk + 8 * q);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w1l[mp][kk], bh, acc[mp]);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w1h[mp][kk], bl, acc[mp]);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w1h[mp][kk], bh, acc[mp]);
+                    }
+                    const int un = -(meta.sw1 + se.ex[c]);
+                    const float sc = pow2(se.e1[c]);
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) {
+                        const float4 bb = *reinterpret_cast<const float4 *>(b1 + 32 * w + 16 * mp + 4 * q);
+                        const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+                        float h1[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            h1[r] = fmaxf(ldx(acc[mp][r], un) + bv[r], 0.f);
+                            // bit 16 q + j: unit 32w + 16mp + 4q + r of sample 16c + j
+                            const unsigned long long bits = __ballot(h1[r] > 0.f);
+                            if (ln == 0) mask1[((w * 2 + mp) * 2 + c) * 4 + r] = bits;
+                        }
+                        h4 hi, lo;
+                        split4(h1, sc, hi, lo);
+                        const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
+                        store_h4(rA, 0, ob, hi);
+                        store_h4(rA, B_HBL - B_HBH, ob, lo);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int u = 32 * w + 16 * mp + 4 * q + r;
+                            reinterpret_cast<_Float16 *>(rA + (B_HTH - B_HBH))[u * TS + 16 * c + j] = hi[r];
+                            reinterpret_cast<_Float16 *>(rA + (B_HTL - B_HBH))[u * TS + 16 * c + j] = lo[r];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __syncthreads();
+            // ---- phase 2: layer 2 for units 32w.., logit partials
+            {
+                const SampleExp se = sample_exp(xmax_s, meta, j);
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const h8 bh = lds_h8(rA, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                        const h8 bl = lds_h8(rA, B_HBL - B_HBH, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2l[mp][kk], bh, acc[mp]);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2h[mp][kk], bl, acc[mp]);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2h[mp][kk], bh, acc[mp]);
+                    }
+                    const int un = -(meta.sw2 + se.e1[c]);
+                    float zp[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) {
+                        const int u0 = 32 * w + 16 * mp + 4 * q;
+                        const float4 bb = *reinterpret_cast<const float4 *>(b2 + u0);
+                        const float4 x0 = *reinterpret_cast<const float4 *>(W3 + u0);
+                        const float4 x1 = *reinterpret_cast<const float4 *>(W3 + H + u0);
+                        const float4 x2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + u0);
+                        const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
+                        const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float h2 = fmaxf(ldx(acc[mp][r], un) + bv[r], 0.f);
+                            h2s[(u0 + r) * H2S + 16 * c + j] = h2;
+#pragma unroll
+                            for (int o = 0; o < 3; ++o) zp[o] += wv[o][r] * h2;
+                        }
+                    }
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) {
+                        zp[o] += __shfl_xor(zp[o], 16, 64);
+                        zp[o] += __shfl_xor(zp[o], 32, 64);
+                    }
+                    const float zq = q == 0 ? zp[0] : (q == 1 ? zp[1] : zp[2]);
+                    if (q < 3) z3p[(w * NT + 16 * c + j) * 4 + q] = zq;
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+            __syncthreads();
+            // ---- phase 3: dz3, dz2 = mask(h2) W3^T dz3 (VALU), dz2 B operand and frame-scaled dz2^T
+            {
+                const SampleExp se = sample_exp(xmax_s, meta, j);
+                const GradExp ge = grad_exp(z3p, gr_s, b3, meta, j);
+                rescale<8>(dW2, F2, tile_frame(se.e1, ge.k2));
+#pragma unroll
+                for (int mp = 0; mp < 2; ++mp) {
+                    const int u0 = 32 * w + 16 * mp + 4 * q;
+                    const float4 x0 = *reinterpret_cast<const float4 *>(W3 + u0);
+                    const float4 x1 = *reinterpret_cast<const float4 *>(W3 + H + u0);
+                    const float4 x2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + u0);
+                    const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        float dz2[4];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const float d = wv[0][r] * ge.dz3[c][0] + wv[1][r] * ge.dz3[c][1] + wv[2][r] * ge.dz3[c][2];
+                            dz2[r] = h2s[(u0 + r) * H2S + 16 * c + j] > 0.f ? d : 0.f;
+                        }
+                        h4 hi, lo;
+                        split4(dz2, pow2(ge.g2[c]), hi, lo);
+                        const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
+                        store_h4(rA, 0, ob, hi);
+                        store_h4(rA, B_HBL - B_HBH, ob, lo);
+                        const int fs = frame_shift(F2, se.e1[c]);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            put_t(rA, B_D2TH - B_HBH, B_D2TL - B_HBH, u0 + r, 16 * c + j, ldx(dz2[r], fs));
+                    }
+                }
+            }
+            __syncthreads();
+            // ---- phase 4: dW2 += dz2^T h1 (K = the tile's 32 samples)
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp) {
+                const int ra = (32 * w + 16 * mp + j) * TS + 8 * q;
+                const h8 ah = lds_h8(rA, B_D2TH - B_HBH, ra), al = lds_h8(rA, B_D2TL - B_HBH, ra);
+#pragma unroll
+                for (int n = 0; n < 8; ++n) {
+                    const int rb = (16 * n + j) * TS + 8 * q;
+                    const h8 bh = lds_h8(rA, B_HTH - B_HBH, rb), bl = lds_h8(rA, B_HTL - B_HBH, rb);
+                    dW2[mp][n] = mfma16(al, bh, dW2[mp][n]);
+                    dW2[mp][n] = mfma16(ah, bl, dW2[mp][n]);
+                    dW2[mp][n] = mfma16(ah, bh, dW2[mp][n]);
+                }
+            }
+            __syncthreads();
+        }
+        // ---- partial gradient of the P role: W2
+        const int u2 = F2 == FRAME_NONE ? 0 : -F2;
+#pragma unroll
+        for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int hrow = 32 * w + 16 * mp + 4 * q + r;
+#pragma unroll
+                for (int n = 0; n < 8; ++n) pW2[hrow * H + 16 * n + j] = ldx(dW2[mp][n][r], u2);
+            }
+    } else {
+        // ================================================================ C waves
+        const int w = wave - 4;
+        const int ct = tid - 256;           // 0..255 within the C role
+        const int xsl = ct >> 3, xg = ct & 7;  // input staging: sample xsl, slot group xg
+        h8 w2th[2][4], w2tl[2][4];
+#pragma unroll
+        for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int o = (32 * w + 16 * mp + j) * RS2 + 32 * kk + 8 * q;
+                w2th[mp][kk] = glb_h8(a.img, IMG_W2TH, o);
+                w2tl[mp][kk] = glb_h8(a.img, IMG_W2TL, o);
+            }
+        const int ofF = j * RS2 + 32 * w + 8 * q;
+        const h8 w1fh = glb_h8(a.img, IMG_W1FH, ofF), w1fl = glb_h8(a.img, IMG_W1FL, ofF);
+        v4f dW1[2][3];
+#pragma unroll
+        for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+            for (int n = 0; n < 3; ++n) dW1[mp][n] = v4f{0.f, 0.f, 0.f, 0.f};
+        // lane-local sums over this lane's samples; reduced over the 16 sample lanes at the end
+        float db1[2][4], db2[2][4], dw3[3][2][4], db3[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                db1[mp][r] = db2[mp][r] = 0.f;
+#pragma unroll
+                for (int o = 0; o < 3; ++o) dw3[o][mp][r] = 0.f;
+            }
+        int F1 = FRAME_NONE;
+        // inputs of a tile: global loads (all lanes take part in the ray search) ...
+        float xv[8], grv = 0.f;
+        auto load_tile = [&](int t) {
+            const int r0 = a.tile_ray[t];
+            const int win = window_entry(a.offs, a.n_rays, r0);
+            const int s = t * NT + xsl;
+            const bool sv = s < a.S;
+            const int ray = ray_in_window(a.offs, a.n_rays, r0, win, s);
+            if (sv) load_x8(a, s, ray, xg >> 2, xg & 3, xv);
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (!sv) xv[e] = 0.f;
+            grv = (sv && xg < 3) ? a.grad_rgb[(int64_t)s * 3 + xg] : 0.f;
+        };
+        // ... and their split into the x planes of buffer pb (x B operand, x^T, max |x|, grad_rgb)
+        auto stage_tile = [&](int pb) {
+            float m = 0.f;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) m = fmaxf(m, fabsf(xv[e]));
+            m = fmaxf(m, __shfl_xor(m, 1, 64));
+            m = fmaxf(m, __shfl_xor(m, 2, 64));
+            m = fmaxf(m, __shfl_xor(m, 4, 64));
+            const float sc = pow2(scale_exp(m));
+            h4 h0, l0, h1, l1;
+            split4(&xv[0], sc, h0, l0);
+            split4(&xv[4], sc, h1, l1);
+            const int xb = B_XB0 + pb * XB_BYTES, xt = B_XT0 + pb * XT_BYTES;
+            *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb) + xsl * RS1 + 8 * xg) = cat(h0, h1);
+            *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb + NT * RS1 * 2) + xsl * RS1 + 8 * xg) =
+                cat(l0, l1);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int k = kidx(xg >> 2, xg & 3, e);
+                if (k < NXIN) put_t(sm, xt, xt + NXIN * TS * 2, k, xsl, xv[e] * sc);
+            }
+            if (xg == 0) xmax_b[pb * NT + xsl] = m;
+            if (xg < 4) gr_b[(pb * NT + xsl) * 4 + xg] = grv;
+        };
+        // feature gradient of a finished tile (partials of the four C waves, fixed order)
+        auto feat_out = [&](int pbase) {
+            for (int i = ct; i < NT * a.in_feat; i += 256) {
+                const int sl = i / a.in_feat, c = i % a.in_feat;
+                const int s = pbase + sl;
+                if (s < a.S)
+                    a.grad_feat[(int64_t)s * a.in_feat + c] = dfp[(0 * NT + sl) * 16 + c] + dfp[(1 * NT + sl) * 16 + c] +
+                                                              dfp[(2 * NT + sl) * 16 + c] + dfp[(3 * NT + sl) * 16 + c];
+            }
+        };
+        // dW1 += dz1^T x of a finished tile (its x^T buffer pb)
+        auto dw1_step = [&](int pb) {
+            const int xt = B_XT0 + pb * XT_BYTES;
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp) {
+                const int ra = (32 * w + 16 * mp + j) * TS + 8 * q;
+                const h8 dh = lds_h8(rB, 0, ra), dl = lds_h8(rB, B_D1TL - B_D1TH, ra);
+#pragma unroll
+                for (int n = 0; n < 3; ++n) {
+                    const int rb = (16 * n + j) * TS + 8 * q;
+                    const h8 bh = lds_h8(sm, xt, rb), bl = lds_h8(sm, xt + NXIN * TS * 2, rb);
+                    dW1[mp][n] = mfma16(dl, bh, dW1[mp][n]);
+                    dW1[mp][n] = mfma16(dh, bl, dW1[mp][n]);
+                    dW1[mp][n] = mfma16(dh, bh, dW1[mp][n]);
+                }
+            }
+        };
+        if (blockIdx.x < ntiles) {
+            load_tile(blockIdx.x);
+            stage_tile(0);
+        }
+        __syncthreads();  // staged image and the first tile's inputs
+        int it = 0, pbase = -1;
+        for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
+            const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
+            const int pb = it & 1;
+            const bool next = tile + (int)gridDim.x < ntiles;
+            // ---- phase 1: feature gradient of the previous tile
+            if (pbase >= 0) feat_out(pbase);
+            __syncthreads();
+            // ---- phase 2: dW1 of the previous tile; loads of the next tile's inputs
+            if (pbase >= 0) dw1_step(pb ^ 1);
+            if (next) load_tile(tile + gridDim.x);
+            __syncthreads();
+            // ---- phase 3: output gradient and exponents of this tile; frame of dW1;
+            //      dW3 += dz3 h2^T, db2 += dz2, db3 += dz3 (VALU, h2 from the P waves);
+            //      the next tile's inputs into the other x buffers
+            const SampleExp se = sample_exp(xmax_b + pb * NT, meta, j);
+            const GradExp ge = grad_exp(z3p, gr_b + pb * NT * 4, b3, meta, j);
+            rescale<3>(dW1, F1, tile_frame(se.ex, ge.k1));
+            if (w == 0 && q == 0) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) db3[o] += ge.dz3[c][o];
+            }
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp) {
+                const int u0 = 32 * w + 16 * mp + 4 * q;
+                const float4 x0 = *reinterpret_cast<const float4 *>(W3 + u0);
+                const float4 x1 = *reinterpret_cast<const float4 *>(W3 + H + u0);
+                const float4 x2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + u0);
+                const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float h2 = h2s[(u0 + r) * H2S + 16 * c + j];
+                        const float d = wv[0][r] * ge.dz3[c][0] + wv[1][r] * ge.dz3[c][1] + wv[2][r] * ge.dz3[c][2];
+                        db2[mp][r] += h2 > 0.f ? d : 0.f;
+#pragma unroll
+                        for (int o = 0; o < 3; ++o) dw3[o][mp][r] += ge.dz3[c][o] * h2;
+                    }
+            }
+            if (next) stage_tile(pb ^ 1);
+            __syncthreads();
+            // ---- phase 4: dz1 = mask(h1) W2^T dz2, dfeat partials, frame-scaled dz1^T
+            {
+                float dz1[2][2][4];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const h8 bh = lds_h8(rA, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                        const h8 bl = lds_h8(rA, B_HBL - B_HBH, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2tl[mp][kk], bh, acc[mp]);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2th[mp][kk], bl, acc[mp]);
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2th[mp][kk], bh, acc[mp]);
+                    }
+                    const int un = -(meta.sw2 + ge.g2[c]);
+                    const int fs = frame_shift(F1, se.ex[c]);
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) {
+                        const int u0 = 32 * w + 16 * mp + 4 * q;
+                        const unsigned long long *mk = mask1 + ((w * 2 + mp) * 2 + c) * 4;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const bool on = (mk[r] >> (16 * q + j)) & 1ull;
+                            dz1[mp][c][r] = on ? ldx(acc[mp][r], un) : 0.f;
+                            db1[mp][r] += dz1[mp][c][r];
+                            put_t(rB, 0, B_D1TL - B_D1TH, u0 + r, 16 * c + j, ldx(dz1[mp][c][r], fs));
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                // dfeat partial over this wave's 32 units: rows = feature 4q + r, column = sample
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    h4 h0, l0, h1v, l1v;
+                    const float sc = pow2(ge.g1[c]);
+                    split4(dz1[0][c], sc, h0, l0);
+                    split4(dz1[1][c], sc, h1v, l1v);
+                    const h8 bh = cat(h0, h1v), bl = cat(l0, l1v);
+                    v4f df = v4f{0.f, 0.f, 0.f, 0.f};
+                    df = mfma16(w1fl, bh, df);
+                    df = mfma16(w1fh, bl, df);
+                    df = mfma16(w1fh, bh, df);
+                    const int un = -(meta.sw1 + ge.g1[c]);
+                    *reinterpret_cast<float4 *>(dfp + (w * NT + 16 * c + j) * 16 + 4 * q) =
+                        make_float4(ldx(df[0], un), ldx(df[1], un), ldx(df[2], un), ldx(df[3], un));
+                }
+            }
+            __syncthreads();
+            pbase = tile * NT;
+        }
+        // ---- the last tile's feature gradient and dW1 (no barrier needed: C-only work)
+        if (pbase >= 0) {
+            feat_out(pbase);
+            dw1_step((it - 1) & 1);
+        }
+        // ---- partial gradients of the C role: W1, b1, W2's neighbours b2, W3, b3
+        const int u1 = F1 == FRAME_NONE ? 0 : -F1;
+#pragma unroll
+        for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int hrow = 32 * w + 16 * mp + 4 * q + r;
+#pragma unroll
+                for (int n = 0; n < 3; ++n) {
+                    const int c = w1_col(a.in_feat, a.n_freq, 16 * n + j);
+                    if (c >= 0) pW1[hrow * a.n_in + c] = ldx(dW1[mp][n][r], u1);
+                }
+                float s1 = db1[mp][r], s2 = db2[mp][r], s3[3] = {dw3[0][mp][r], dw3[1][mp][r], dw3[2][mp][r]};
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) {
+                    s1 += __shfl_xor(s1, o, 64);
+                    s2 += __shfl_xor(s2, o, 64);
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) s3[t] += __shfl_xor(s3[t], o, 64);
+                }
+                if (j == 0) {
+                    pb1[hrow] = s1;
+                    pb2[hrow] = s2;
+#pragma unroll
+                    for (int t = 0; t < 3; ++t) pW3[t * H + hrow] = s3[t];
+                }
+            }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) db3[t] += __shfl_xor(db3[t], o, 64);
+        if (ct < 3) pb3[ct] = db3[ct];
     }
 }
 
@@ -403,14 +1107,16 @@ int check_mlp(const dvgo_color_mlp *m, bool bwd) {
 int n_in_of(const dvgo_color_mlp *m) { return m->in_feat + 3 + 6 * m->n_freq; }
 int n_params_of(const dvgo_color_mlp *m) { return H * n_in_of(m) + H + H * H + H + 3 * H + 3; }
 int bwd_blocks(int64_t S) {
-    int64_t t = (S + BWD_TILE - 1) / BWD_TILE;
+    int64_t t = (S + NT - 1) / NT;
     return (int)(t < MAX_BLOCKS ? (t < 1 ? 1 : t) : MAX_BLOCKS);
 }
 
-size_t ws_layout(const dvgo_color_mlp *m, int32_t R, int64_t S, size_t *off_pe, size_t *off_part) {
-    size_t o = align_up((size_t)H * KX * 4, 256);
+size_t ws_layout(const dvgo_color_mlp *m, int32_t R, int64_t S, size_t *off_pe, size_t *off_tr, size_t *off_part) {
+    size_t o = align_up((size_t)IMG_BYTES, 256);
     *off_pe = o;
     o += align_up((size_t)R * PEW * 4, 256);
+    *off_tr = o;
+    o += align_up((size_t)((S + TILE - 1) / TILE) * 4, 256);
     *off_part = o;
     o += (size_t)bwd_blocks(S) * n_params_of(m) * 4;
     return o;
@@ -423,8 +1129,8 @@ int setup(const dvgo_color_mlp *m, int32_t R, const int32_t *offs, const float *
     if (R < 0 || S < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays or n_samples");
     if (S >= ((int64_t)1 << 31) / 16) return set_error(DVGO_ERR_RANGE, "n_samples too large");
     if (S > 0 && (R == 0 || !offs || !dirs || !feat)) return set_error(DVGO_ERR_NULL, "ray_offsets, dirs or feat is NULL");
-    size_t off_pe, off_part;
-    const size_t need = ws_layout(m, R, S, &off_pe, &off_part);
+    size_t off_pe, off_tr, off_part;
+    const size_t need = ws_layout(m, R, S, &off_pe, &off_tr, &off_part);
     if (!ws || ws_bytes < need) return set_error(DVGO_ERR_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, need);
     if (((uintptr_t)ws & 255) != 0) return set_error(DVGO_ERR_SHAPE, "workspace must be 256-byte aligned");
     memset(&a, 0, sizeof(a));
@@ -439,16 +1145,20 @@ int setup(const dvgo_color_mlp *m, int32_t R, const int32_t *offs, const float *
     a.dirs = dirs;
     a.S = (int)S;
     a.feat = feat;
-    a.W1p = (float *)ws;
+    a.feat_vec = m->in_feat == 12 && ((uintptr_t)feat & 15) == 0;
+    a.img = (unsigned char *)ws;
     a.pe = (float *)((char *)ws + off_pe);
+    a.tile_ray = (int *)((char *)ws + off_tr);
+    a.n_tiles = (int)((S + TILE - 1) / TILE);
     a.partial = (float *)((char *)ws + off_part);
     a.nblocks = bwd_blocks(S);
     return DVGO_OK;
 }
 
 int launch_prep(const MlpArgs &a, hipStream_t st) {
-    const int n = H * KX + a.n_rays;
-    hipLaunchKernelGGL(mlp_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, st, a);
+    const int n = PREP_FIXED_BLOCKS + (a.n_rays + PREP_THREADS - 1) / PREP_THREADS +
+                  (a.n_tiles + PREP_THREADS - 1) / PREP_THREADS;
+    hipLaunchKernelGGL(mlp_prep_kernel, dim3(n), dim3(PREP_THREADS), 0, st, a);
     return check_hip(hipGetLastError(), "mlp_prep_kernel launch");
 }
 
@@ -459,8 +1169,8 @@ extern "C" int dvgo_mlp_workspace_size(const dvgo_color_mlp *m, int32_t n_rays, 
     if (rc) return rc;
     if (!bytes) return set_error(DVGO_ERR_NULL, "bytes is NULL");
     if (n_rays < 0 || n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative size");
-    size_t a, b;
-    *bytes = ws_layout(m, n_rays, n_samples, &a, &b);
+    size_t a, b, c;
+    *bytes = ws_layout(m, n_rays, n_samples, &a, &b, &c);
     return DVGO_OK;
 }
 
@@ -476,8 +1186,9 @@ extern "C" int dvgo_mlp_forward(const dvgo_color_mlp *m, int32_t n_rays, const i
     hipStream_t st = (hipStream_t)stream;
     rc = launch_prep(a, st);
     if (rc) return rc;
-    const int ntiles = (int)((n_samples + FWD_TILE - 1) / FWD_TILE);
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(ntiles < MAX_BLOCKS ? ntiles : MAX_BLOCKS), dim3(FWD_THREADS), 0, st, a);
+    const int64_t nwt = (n_samples + FWD_WTILE - 1) / FWD_WTILE;
+    const int64_t nb = (nwt + FWD_WAVES - 1) / FWD_WAVES;
+    hipLaunchKernelGGL(mlp_fwd_kernel, dim3((int)(nb < MAX_BLOCKS ? nb : MAX_BLOCKS)), dim3(FWD_THREADS), 0, st, a);
     return check_hip(hipGetLastError(), "mlp_fwd_kernel launch");
 }
 

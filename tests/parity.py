@@ -22,14 +22,17 @@ def close(x, y, rtol, floor, name="value", scale=None, skip=None, slack=None):
     elements at a non-differentiable point (a ReLU unit within rounding of its kink) are
     left out of the elementwise check; the normwise check still covers them.  slack
     (optional, per element): an absolute allowance added to the elementwise bound, e.g. the
-    change a gradient sees when a ReLU unit at its kink switches side."""
+    change a gradient sees when a ReLU unit at its kink switches side; its 2-norm is added to
+    the normwise bound as well."""
     x = np.asarray(x, np.float64).ravel()
     y = np.asarray(y, np.float64).ravel()
     assert x.shape == y.shape, f"{name}: shape {x.shape} vs {y.shape}"
     assert np.isfinite(x).all(), f"{name}: non-finite values"
     ny = np.linalg.norm(y)
     err = np.linalg.norm(x - y)
-    assert err <= rtol * ny + 1e-30, f"{name}: normwise error {err / max(ny, 1e-300):.3e} > {rtol}"
+    # a slack (an ambiguous kink decision) may move the result by up to |slack| per element
+    ns = np.linalg.norm(np.asarray(slack, np.float64)) if slack is not None else 0.0
+    assert err <= rtol * ny + ns + 1e-30, f"{name}: normwise error {err / max(ny, 1e-300):.3e} > {rtol}"
     if y.size:
         bound = rtol * np.maximum(np.abs(y), floor * np.abs(y).max())
         if scale is not None:

@@ -216,11 +216,23 @@ def test_config4_finite_differences(pkg):
     loss.backward()
     gd = dens.grad.cpu().numpy()
     gfg = fgrid.grad.cpu().numpy()
+    # 128 entries of each grid at vertices of cells that samples fall in (chosen from the
+    # inputs alone: a random sample, one of its 8 cell corners, a random channel)
     rng = np.random.default_rng(60)
-    # entries with a non-zero GPU gradient, 128 of each grid
-    di = rng.choice(np.flatnonzero(gd.ravel()), 128, replace=False)
-    fi = rng.choice(np.flatnonzero(gfg.ravel()), 128, replace=False)
-    fd, an, gp = [], [], []
+    u = (smp.xyz.astype(np.float64) + 1.0) / 2.0 * (n - 1)
+    cell = np.minimum(np.floor(np.clip(u, 0, n - 1)).astype(np.int64), n - 2)
+
+    def pick(C, count):
+        out = set()
+        while len(out) < count:
+            k = int(rng.integers(S))
+            v = cell[k] + rng.integers(0, 2, 3)
+            out.add(int(((v[0] * n + v[1]) * n + v[2]) * C + rng.integers(C)))
+        return np.array(sorted(out))
+
+    di = pick(1, 128)
+    fi = pick(wl.feat.data.shape[-1], 128)
+    fd, an, gp, curv = [], [], [], []
     eps = np.float32(1e-4)
     for grid, flat, gpu in ((wl.density, di, gd), (wl.feat, fi, gfg)):
         C = grid.data.shape[-1]
@@ -239,7 +251,10 @@ def test_config4_finite_differences(pkg):
             lo_v = float(data[idx])
             lm = _partial_loss(wl, sub, rays, shift, R)
             data[idx] = old
+            l0 = _partial_loss(wl, sub, rays, shift, R)
             fd.append((lp - lm) / (hi_v - lo_v))
+            # one-sided slopes: they differ by O(eps) unless a ReLU kink lies inside the step
+            curv.append(abs((lp - l0) / (hi_v - float(old)) - (l0 - lm) / (float(old) - lo_v)))
             gp.append(gpu.ravel()[idx])
             # analytic oracle gradient from the touching rays only
             feat_o = oracle.gather(wl.feat, sub.xyz)
@@ -253,9 +268,15 @@ def test_config4_finite_differences(pkg):
             else:
                 gfo, _, _ = oracle.mlp_backward(wl.mlp, sub.ray_offsets, wl.rays.dirs[rays], feat_o, og["grad_srgb"])
                 an.append(oracle.scatter(wl.feat, sub.xyz, gfo).ravel()[idx])
-    fd, an, gp = np.array(fd), np.array(an), np.array(gp)
+    fd, an, gp, curv = np.array(fd), np.array(an), np.array(gp), np.array(curv)
+    # An entry whose +-eps step crosses a ReLU kink of the colour head has no central
+    # difference to compare with (the loss is not differentiable there); leave it out of the
+    # finite-difference checks and keep the analytic comparison for every entry.
+    smooth = curv <= 1e-3 * (np.abs(fd) + 1e-2 * np.abs(fd).max())
+    say("FD entries across a kink:", int((~smooth).sum()), "of", len(fd))
+    assert smooth.sum() >= 0.9 * len(fd)
     # the oracle's analytic gradient agrees with its own finite differences
-    close(an, fd, rtol=1e-4, floor=1e-2, name="oracle analytic vs FD")
+    close(an[smooth], fd[smooth], rtol=1e-4, floor=1e-2, name="oracle analytic vs FD")
     close(gp[:128], an[:128], **GRAD, name="GPU vs oracle, density")
     close(gp[128:], an[128:], **GRAD, name="GPU vs oracle, features")
-    close(gp, fd, rtol=2e-4, floor=1e-2, name="GPU vs FD")
+    close(gp[smooth], fd[smooth], rtol=2e-4, floor=1e-2, name="GPU vs FD")
