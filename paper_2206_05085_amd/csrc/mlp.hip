@@ -419,9 +419,9 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
             const float4 bb = *reinterpret_cast<const float4 *>(b1 + 16 * m + 4 * q);
 #pragma unroll
             for (int c = 0; c < FWD_NC; ++c) {
-                const int un = -(meta.sw1 + ex[c]);
-                float v[4] = {fmaxf(ldx(acc[c][0], un) + bb.x, 0.f), fmaxf(ldx(acc[c][1], un) + bb.y, 0.f),
-                              fmaxf(ldx(acc[c][2], un) + bb.z, 0.f), fmaxf(ldx(acc[c][3], un) + bb.w, 0.f)};
+                const float un = pow2(-(meta.sw1 + ex[c]));
+                float v[4] = {fmaxf(fmaf(acc[c][0], un, bb.x), 0.f), fmaxf(fmaf(acc[c][1], un, bb.y), 0.f),
+                              fmaxf(fmaf(acc[c][2], un, bb.z), 0.f), fmaxf(fmaf(acc[c][3], un, bb.w), 0.f)};
                 split4(v, pow2(e1[c]), hh[c][m], hl[c][m]);
             }
             // keep the scheduler from hoisting every weight load of the layer (spills)
@@ -459,10 +459,10 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
             const float wv[3][4] = {{w0.x, w0.y, w0.z, w0.w}, {w1.x, w1.y, w1.z, w1.w}, {w2.x, w2.y, w2.z, w2.w}};
 #pragma unroll
             for (int c = 0; c < FWD_NC; ++c) {
-                const int un = -(meta.sw2 + e1[c]);
+                const float un = pow2(-(meta.sw2 + e1[c]));
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const float h2 = fmaxf(ldx(acc[c][r], un) + bv[r], 0.f);
+                    const float h2 = fmaxf(fmaf(acc[c][r], un, bv[r]), 0.f);
 #pragma unroll
                     for (int o = 0; o < 3; ++o) z[c][o] += wv[o][r] * h2;
                 }
@@ -484,17 +484,17 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
 
 // ------------------------------------------------------------------ backward
 //
-// Block = 8 waves in two roles that alternate through four block-wide phases per tile of
-// NT = 32 samples.  P waves (0..3) own units 32p..32p+31 of both hidden layers for the
-// forward recompute and hold those rows of W1 and W2 in registers; C waves (4..7) own the
-// same units for the backward chain, hold those rows of W2^T, and stage the inputs of the
-// next tile while the P waves compute.  Per tile t (inputs of t already staged):
-//   phase 1  P: layer 1 -> h1 B operand, h1^T, mask bits C: feature gradient of t-1
-//   phase 2  P: layer 2 -> h2, logit partials            C: dW1 += dz1^T x of t-1; loads of t+1
-//   phase 3  P: dz3, dz2 -> dz2 B operand, dz2^T (frame) C: dz3, exponents, dW3 b2 b3 sums;
-//                                                           inputs of t+1 -> x planes
-//   phase 4  P: dW2 += dz2^T h1                          C: dz1, dfeat partials, dz1^T (frame)
-// Both roles run the same number of barriers per tile, so s_barrier stays matched.
+// Block = 8 waves in two roles.  P waves (0..3) own units 32p..32p+31 of both hidden
+// layers for the forward recompute and hold those rows of W1 and W2 in registers; C waves
+// (4..7) own the same units for the backward chain and hold those rows of W2^T.  The C
+// waves run one tile behind, so every phase pairs P and C work on the same SIMDs.  Phases
+// of iteration t (block-wide barriers between them; the inputs of t are already staged):
+//   A  P: layer 1 of t -> h1 B operand, h1^T, mask bits    C: dz1, dfeat partials, dz1^T of t-1
+//   B  P: layer 2 of t -> h2, logit partials                C: dW1 += dz1^T x of t-1; loads of t+1
+//   C  P: dz3, dz2 of t -> dz2 B operand, dz2^T (frame)     C: dz3, exponents, dW3 b2 b3 sums of t
+//   D  P: dW2 += dz2^T h1 of t                              C: feature gradient of t-1; stage t+1
+// After the last tile one more A/B pair finishes the C side.  Both roles run the same
+// number of barriers, so s_barrier stays matched.
 
 constexpr int BWD_WAVES = 8, BWD_THREADS = 64 * BWD_WAVES;
 constexpr int NT = TILE;  // samples per block tile (two 16-sample column tiles)
@@ -504,26 +504,28 @@ constexpr int BS = IMG_FWD_END - IMG_B1;             // b1, b2, W3, b3, meta
 constexpr int BSL(int img_off) { return img_off - IMG_B1; }
 constexpr int XB_BYTES = 2 * NT * RS1 * 2;           // x B operand [NT][RS1] hi, lo
 constexpr int XT_BYTES = 2 * NXIN * TS * 2;          // x^T [NXIN][TS] hi, lo
-constexpr int B_XB0 = BS;                            // two buffers of each (tile parity)
+constexpr int HB_BYTES = 2 * NT * RS2 * 2;           // h1, later dz2, B operand [NT][RS2] hi, lo
+constexpr int B_XB0 = BS;                            // two buffers each (tile parity)
 constexpr int B_XT0 = B_XB0 + 2 * XB_BYTES;
-constexpr int B_HBH = B_XT0 + 2 * XT_BYTES;          // h1 then dz2, B operand [NT][RS2]
-constexpr int B_HBL = B_HBH + NT * RS2 * 2;
-constexpr int B_HTH = B_HBL + NT * RS2 * 2;          // h1^T [H][TS]
+constexpr int B_HB0 = B_XT0 + 2 * XT_BYTES;
+constexpr int B_HTH = B_HB0 + 2 * HB_BYTES;          // h1^T [H][TS]
 constexpr int B_HTL = B_HTH + H * TS * 2;
 constexpr int B_D2TH = B_HTL + H * TS * 2;           // dz2^T [H][TS] (frame-scaled)
 constexpr int B_D2TL = B_D2TH + H * TS * 2;
 constexpr int B_D1TH = B_D2TL + H * TS * 2;          // dz1^T [H][TS] (frame-scaled)
 constexpr int B_D1TL = B_D1TH + H * TS * 2;
 constexpr int B_Z3P = B_D1TL + H * TS * 2;           // logit partials [4][NT][4] f32
-constexpr int B_DFP = B_Z3P + 4 * NT * 4 * 4;        // dfeat partials [4][NT][16] f32
+constexpr int DFS = 12;                              // row of dfeat partials (features)
+constexpr int B_DFP = B_Z3P + 4 * NT * 4 * 4;        // dfeat partials [4][NT][DFS] f32
 constexpr int H2S = 36;                              // row stride (floats) of the h2 plane
-constexpr int B_H2 = B_DFP + 4 * NT * 16 * 4;        // h2 [H][H2S] f32, written by P, read by C
-constexpr int B_MASK = B_H2 + H * H2S * 4;           // h1 > 0 ballots [4][2][2][4] u64
-constexpr int B_XMAX = B_MASK + 4 * 16 * 8;          // max |x| per sample [2][NT]
+constexpr int B_H2 = B_DFP + 4 * NT * DFS * 4;       // h2 [H][H2S] f32, written by P, read by C
+constexpr int B_MASK = B_H2 + H * H2S * 4;           // h1 > 0 ballots [2][4][2][2][4] u64
+constexpr int B_XMAX = B_MASK + 2 * 4 * 16 * 8;      // max |x| per sample [2][NT]
 constexpr int B_GR = B_XMAX + 2 * NT * 4;            // grad_rgb [2][NT][4]
 constexpr int B_END = B_GR + 2 * NT * 16;
 static_assert(B_END <= 160 * 1024, "backward LDS");
-static_assert(B_XB0 % 16 == 0 && B_HBH % 16 == 0 && B_HTH % 16 == 0 && B_D1TH % 16 == 0 && B_Z3P % 16 == 0,
+static_assert(B_XB0 % 16 == 0 && B_HB0 % 16 == 0 && B_HTH % 16 == 0 && B_D1TH % 16 == 0 && B_Z3P % 16 == 0 &&
+                  B_DFP % 16 == 0 && B_MASK % 8 == 0,
               "LDS alignment");
 
 // exponent that moves a gradient column into the accumulator frame F (operand scale e of
@@ -634,14 +636,14 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     const float *b2 = reinterpret_cast<const float *>(sm + BSL(IMG_B2));
     const float *W3 = reinterpret_cast<const float *>(sm + BSL(IMG_W3));
     const float *b3 = reinterpret_cast<const float *>(sm + BSL(IMG_B3));
-    unsigned char *rA = lds_region(sm, B_HBH);   // HB, HT, D2T
-    unsigned char *rB = lds_region(sm, B_D1TH);  // D1T, partials, per-sample values
-    float *z3p = reinterpret_cast<float *>(rB + (B_Z3P - B_D1TH));
-    float *dfp = reinterpret_cast<float *>(rB + (B_DFP - B_D1TH));
-    float *xmax_b = reinterpret_cast<float *>(rB + (B_XMAX - B_D1TH));
-    float *gr_b = reinterpret_cast<float *>(rB + (B_GR - B_D1TH));
-    float *h2s = reinterpret_cast<float *>(rB + (B_H2 - B_D1TH));
-    unsigned long long *mask1 = reinterpret_cast<unsigned long long *>(rB + (B_MASK - B_D1TH));
+    unsigned char *rA = lds_region(sm, B_HTH);   // HT, D2T, D1T
+    unsigned char *rB = lds_region(sm, B_Z3P);   // partials, h2, masks, per-sample values
+    float *z3p = reinterpret_cast<float *>(rB);
+    float *dfp = reinterpret_cast<float *>(rB + (B_DFP - B_Z3P));
+    float *h2s = reinterpret_cast<float *>(rB + (B_H2 - B_Z3P));
+    unsigned long long *mask_b = reinterpret_cast<unsigned long long *>(rB + (B_MASK - B_Z3P));
+    float *xmax_b = reinterpret_cast<float *>(rB + (B_XMAX - B_Z3P));
+    float *gr_b = reinterpret_cast<float *>(rB + (B_GR - B_Z3P));
     const int ntiles = a.n_tiles;
     float *P = a.partial + (int64_t)blockIdx.x * a.n_params;
     float *pW1 = P, *pb1 = pW1 + H * a.n_in, *pW2 = pb1 + H, *pb2 = pW2 + H * H, *pW3 = pb2 + H, *pb3 = pW3 + 3 * H;
@@ -679,24 +681,40 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             const float *xmax_s = xmax_b + pb * NT;
             const float *gr_s = gr_b + pb * NT * 4;
             const int xb = B_XB0 + pb * XB_BYTES;
-            // ---- phase 1: layer 1 for units 32w..; h1 -> B operand, transposed planes, mask bits
+            unsigned char *hb = lds_region(sm, B_HB0 + pb * HB_BYTES);
+            unsigned long long *mask1 = mask_b + pb * 64;
+            // ---- A: layer 1 for units 32w..; h1 -> B operand, transposed planes, mask bits
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
+                v4f acc[2][2];  // [c][mp]
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    h8 bh[2], bl[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        bh[c] = lds_h8(sm, xb, (16 * c + j) * RS1 + 32 * kk + 8 * q);
+                        bl[c] = lds_h8(sm, xb + NT * RS1 * 2, (16 * c + j) * RS1 + 32 * kk + 8 * q);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1l[mp][kk], bh[c], acc[c][mp]);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1h[mp][kk], bl[c], acc[c][mp]);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1h[mp][kk], bh[c], acc[c][mp]);
+                }
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-                    for (int kk = 0; kk < 2; ++kk) {
-                        const h8 bh = lds_h8(sm, xb, (16 * c + j) * RS1 + 32 * kk + 8 * q);
-                        const h8 bl = lds_h8(sm, xb + NT * RS1 * 2, (16 * c + j) * RS1 + 32 * kk + 8 * q);
-#pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w1l[mp][kk], bh, acc[mp]);
-#pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w1h[mp][kk], bl, acc[mp]);
-#pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w1h[mp][kk], bh, acc[mp]);
-                    }
-                    const int un = -(meta.sw1 + se.ex[c]);
+                    const float un = pow2(-(meta.sw1 + se.ex[c]));
                     const float sc = pow2(se.e1[c]);
 #pragma unroll
                     for (int mp = 0; mp < 2; ++mp) {
@@ -705,7 +723,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         float h1[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            h1[r] = fmaxf(ldx(acc[mp][r], un) + bv[r], 0.f);
+                            h1[r] = fmaxf(fmaf(acc[c][mp][r], un, bv[r]), 0.f);
                             // bit 16 q + j: unit 32w + 16mp + 4q + r of sample 16c + j
                             const unsigned long long bits = __ballot(h1[r] > 0.f);
                             if (ln == 0) mask1[((w * 2 + mp) * 2 + c) * 4 + r] = bits;
@@ -713,37 +731,50 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         h4 hi, lo;
                         split4(h1, sc, hi, lo);
                         const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
-                        store_h4(rA, 0, ob, hi);
-                        store_h4(rA, B_HBL - B_HBH, ob, lo);
+                        store_h4(hb, 0, ob, hi);
+                        store_h4(hb, NT * RS2 * 2, ob, lo);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int u = 32 * w + 16 * mp + 4 * q + r;
-                            reinterpret_cast<_Float16 *>(rA + (B_HTH - B_HBH))[u * TS + 16 * c + j] = hi[r];
-                            reinterpret_cast<_Float16 *>(rA + (B_HTL - B_HBH))[u * TS + 16 * c + j] = lo[r];
+                            reinterpret_cast<_Float16 *>(rA)[u * TS + 16 * c + j] = hi[r];
+                            reinterpret_cast<_Float16 *>(rA + (B_HTL - B_HTH))[u * TS + 16 * c + j] = lo[r];
                         }
                     }
-                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
             __syncthreads();
-            // ---- phase 2: layer 2 for units 32w.., logit partials
+            // ---- B: layer 2 for units 32w.., logit partials
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
+                v4f acc[2][2];  // [c][mp]
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    h8 bh[2], bl[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        bh[c] = lds_h8(hb, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                        bl[c] = lds_h8(hb, NT * RS2 * 2, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2l[mp][kk], bh[c], acc[c][mp]);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2h[mp][kk], bl[c], acc[c][mp]);
+#pragma unroll
+                    for (int c = 0; c < 2; ++c)
+#pragma unroll
+                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2h[mp][kk], bh[c], acc[c][mp]);
+                }
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const h8 bh = lds_h8(rA, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
-                        const h8 bl = lds_h8(rA, B_HBL - B_HBH, (16 * c + j) * RS2 + 32 * kk + 8 * q);
-#pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2l[mp][kk], bh, acc[mp]);
-#pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2h[mp][kk], bl, acc[mp]);
-#pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2h[mp][kk], bh, acc[mp]);
-                    }
-                    const int un = -(meta.sw2 + se.e1[c]);
+                    const float un = pow2(-(meta.sw2 + se.e1[c]));
                     float zp[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                     for (int mp = 0; mp < 2; ++mp) {
@@ -756,7 +787,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const float h2 = fmaxf(ldx(acc[mp][r], un) + bv[r], 0.f);
+                            const float h2 = fmaxf(fmaf(acc[c][mp][r], un, bv[r]), 0.f);
                             h2s[(u0 + r) * H2S + 16 * c + j] = h2;
 #pragma unroll
                             for (int o = 0; o < 3; ++o) zp[o] += wv[o][r] * h2;
@@ -769,11 +800,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     }
                     const float zq = q == 0 ? zp[0] : (q == 1 ? zp[1] : zp[2]);
                     if (q < 3) z3p[(w * NT + 16 * c + j) * 4 + q] = zq;
-                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
             __syncthreads();
-            // ---- phase 3: dz3, dz2 = mask(h2) W3^T dz3 (VALU), dz2 B operand and frame-scaled dz2^T
+            // ---- C: dz3, dz2 = mask(h2) W3^T dz3 (VALU), dz2 B operand and frame-scaled dz2^T
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
                 const GradExp ge = grad_exp(z3p, gr_s, b3, meta, j);
@@ -796,25 +826,25 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         h4 hi, lo;
                         split4(dz2, pow2(ge.g2[c]), hi, lo);
                         const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
-                        store_h4(rA, 0, ob, hi);
-                        store_h4(rA, B_HBL - B_HBH, ob, lo);
-                        const int fs = frame_shift(F2, se.e1[c]);
+                        store_h4(hb, 0, ob, hi);
+                        store_h4(hb, NT * RS2 * 2, ob, lo);
+                        const int fs = frame_shift(F2, se.e1[c]);  // exact for any shift; 0 stays 0
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            put_t(rA, B_D2TH - B_HBH, B_D2TL - B_HBH, u0 + r, 16 * c + j, ldx(dz2[r], fs));
+                            put_t(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2[r], fs));
                     }
                 }
             }
             __syncthreads();
-            // ---- phase 4: dW2 += dz2^T h1 (K = the tile's 32 samples)
+            // ---- D: dW2 += dz2^T h1 (K = the tile's 32 samples)
 #pragma unroll
             for (int mp = 0; mp < 2; ++mp) {
                 const int ra = (32 * w + 16 * mp + j) * TS + 8 * q;
-                const h8 ah = lds_h8(rA, B_D2TH - B_HBH, ra), al = lds_h8(rA, B_D2TL - B_HBH, ra);
+                const h8 ah = lds_h8(rA, B_D2TH - B_HTH, ra), al = lds_h8(rA, B_D2TL - B_HTH, ra);
 #pragma unroll
                 for (int n = 0; n < 8; ++n) {
                     const int rb = (16 * n + j) * TS + 8 * q;
-                    const h8 bh = lds_h8(rA, B_HTH - B_HBH, rb), bl = lds_h8(rA, B_HTL - B_HBH, rb);
+                    const h8 bh = lds_h8(rA, 0, rb), bl = lds_h8(rA, B_HTL - B_HTH, rb);
                     dW2[mp][n] = mfma16(al, bh, dW2[mp][n]);
                     dW2[mp][n] = mfma16(ah, bl, dW2[mp][n]);
                     dW2[mp][n] = mfma16(ah, bh, dW2[mp][n]);
@@ -822,6 +852,9 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             }
             __syncthreads();
         }
+        // the C side's last A/B pair
+        __syncthreads();
+        __syncthreads();
         // ---- partial gradient of the P role: W2
         const int u2 = F2 == FRAME_NONE ? 0 : -F2;
 #pragma unroll
@@ -835,7 +868,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     } else {
         // ================================================================ C waves
         const int w = wave - 4;
-        const int ct = tid - 256;           // 0..255 within the C role
+        const int ct = tid - 256;              // 0..255 within the C role
         const int xsl = ct >> 3, xg = ct & 7;  // input staging: sample xsl, slot group xg
         h8 w2th[2][4], w2tl[2][4];
 #pragma unroll
@@ -864,19 +897,20 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 for (int o = 0; o < 3; ++o) dw3[o][mp][r] = 0.f;
             }
         int F1 = FRAME_NONE;
-        // inputs of a tile: global loads (all lanes take part in the ray search) ...
+        // inputs of a tile: global loads, in three steps spread over phases so that their
+        // latency overlaps other work (ray window; ray search and feature loads; staging)
         float xv[8], grv = 0.f;
-        auto load_tile = [&](int t) {
-            const int r0 = a.tile_ray[t];
-            const int win = window_entry(a.offs, a.n_rays, r0);
+        auto load_tile = [&](int t, int r0, int win) {
             const int s = t * NT + xsl;
             const bool sv = s < a.S;
-            const int ray = ray_in_window(a.offs, a.n_rays, r0, win, s);
-            if (sv) load_x8(a, s, ray, xg >> 2, xg & 3, xv);
+            const int ray = ray_in_window(a.offs, a.n_rays, r0, win, s);  // all lanes take part
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if (!sv) xv[e] = 0.f;
-            grv = (sv && xg < 3) ? a.grad_rgb[(int64_t)s * 3 + xg] : 0.f;
+            for (int e = 0; e < 8; ++e) xv[e] = 0.f;
+            grv = 0.f;
+            if (sv) {
+                load_x8(a, s, ray, xg >> 2, xg & 3, xv);
+                if (xg < 3) grv = a.grad_rgb[(int64_t)s * 3 + xg];
+            }
         };
         // ... and their split into the x planes of buffer pb (x B operand, x^T, max |x|, grad_rgb)
         auto stage_tile = [&](int pb) {
@@ -908,8 +942,9 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 const int sl = i / a.in_feat, c = i % a.in_feat;
                 const int s = pbase + sl;
                 if (s < a.S)
-                    a.grad_feat[(int64_t)s * a.in_feat + c] = dfp[(0 * NT + sl) * 16 + c] + dfp[(1 * NT + sl) * 16 + c] +
-                                                              dfp[(2 * NT + sl) * 16 + c] + dfp[(3 * NT + sl) * 16 + c];
+                    a.grad_feat[(int64_t)s * a.in_feat + c] = dfp[(0 * NT + sl) * DFS + c] +
+                                                              dfp[(1 * NT + sl) * DFS + c] +
+                                                              dfp[(2 * NT + sl) * DFS + c] + dfp[(3 * NT + sl) * DFS + c];
             }
         };
         // dW1 += dz1^T x of a finished tile (its x^T buffer pb)
@@ -918,7 +953,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
 #pragma unroll
             for (int mp = 0; mp < 2; ++mp) {
                 const int ra = (32 * w + 16 * mp + j) * TS + 8 * q;
-                const h8 dh = lds_h8(rB, 0, ra), dl = lds_h8(rB, B_D1TL - B_D1TH, ra);
+                const h8 dh = lds_h8(rA, B_D1TH - B_HTH, ra), dl = lds_h8(rA, B_D1TL - B_HTH, ra);
 #pragma unroll
                 for (int n = 0; n < 3; ++n) {
                     const int rb = (16 * n + j) * TS + 8 * q;
@@ -929,114 +964,149 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
             }
         };
+        // dz1 = mask(h1) W2^T dz2 of a tile (buffers of parity pb, exponents g2/g1/ex of that
+        // tile), dfeat partials, frame-scaled dz1^T
+        auto dz1_step = [&](int pb, const int g2[2], const int g1[2], const int ex[2]) {
+            const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
+            const unsigned char *hb = lds_region(sm, B_HB0 + pb * HB_BYTES);
+            const unsigned long long *mask1 = mask_b + pb * 64;
+            float dz1[2][2][4];
+            v4f acc[2][2];  // [c][mp]
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int mp = 0; mp < 2; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                h8 bh[2], bl[2];
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    bh[c] = lds_h8(hb, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                    bl[c] = lds_h8(hb, NT * RS2 * 2, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                }
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2tl[mp][kk], bh[c], acc[c][mp]);
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2th[mp][kk], bl[c], acc[c][mp]);
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2th[mp][kk], bh[c], acc[c][mp]);
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const float un = pow2(-(meta.sw2 + g2[c]));
+                const int fs = frame_shift(F1, ex[c]);  // exact for any shift; 0 stays 0
+#pragma unroll
+                for (int mp = 0; mp < 2; ++mp) {
+                    const int u0 = 32 * w + 16 * mp + 4 * q;
+                    const unsigned long long *mk = mask1 + ((w * 2 + mp) * 2 + c) * 4;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        // lane 16q + j of the ballot is this lane's unit and sample
+                        const bool on = __builtin_amdgcn_inverse_ballot_w64(mk[r]);
+                        dz1[mp][c][r] = on ? acc[c][mp][r] * un : 0.f;
+                        db1[mp][r] += dz1[mp][c][r];
+                        put_t(rA, B_D1TH - B_HTH, B_D1TL - B_HTH, u0 + r, 16 * c + j, ldx(dz1[mp][c][r], fs));
+                    }
+                }
+            }
+            // dfeat partial over this wave's 32 units: rows = feature 4q + r, column = sample
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                h4 h0, l0, h1v, l1v;
+                const float sc = pow2(g1[c]);
+                split4(dz1[0][c], sc, h0, l0);
+                split4(dz1[1][c], sc, h1v, l1v);
+                const h8 bh = cat(h0, h1v), bl = cat(l0, l1v);
+                v4f df = v4f{0.f, 0.f, 0.f, 0.f};
+                df = mfma16(w1fl, bh, df);
+                df = mfma16(w1fh, bl, df);
+                df = mfma16(w1fh, bh, df);
+                const float un = pow2(-(meta.sw1 + g1[c]));
+                if (q < DFS / 4)
+                    *reinterpret_cast<float4 *>(dfp + (w * NT + 16 * c + j) * DFS + 4 * q) =
+                        make_float4(df[0] * un, df[1] * un, df[2] * un, df[3] * un);
+            }
+        };
         if (blockIdx.x < ntiles) {
-            load_tile(blockIdx.x);
+            const int r0 = a.tile_ray[blockIdx.x];
+            load_tile(blockIdx.x, r0, window_entry(a.offs, a.n_rays, r0));
             stage_tile(0);
         }
         __syncthreads();  // staged image and the first tile's inputs
         int it = 0, pbase = -1;
+        int pg2[2] = {0, 0}, pg1[2] = {0, 0}, pex[2] = {0, 0};  // exponents of the previous tile
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
             const int pb = it & 1;
             const bool next = tile + (int)gridDim.x < ntiles;
-            // ---- phase 1: feature gradient of the previous tile
-            if (pbase >= 0) feat_out(pbase);
+            // ---- A: dz1 of the previous tile; ray window of the next tile
+            const int r0n = next ? a.tile_ray[tile + gridDim.x] : 0;
+            if (pbase >= 0) dz1_step(pb ^ 1, pg2, pg1, pex);
+            const int winn = next ? window_entry(a.offs, a.n_rays, r0n) : 0;
             __syncthreads();
-            // ---- phase 2: dW1 of the previous tile; loads of the next tile's inputs
+            // ---- B: dW1 of the previous tile; loads of the next tile's inputs
+            if (next) load_tile(tile + gridDim.x, r0n, winn);
             if (pbase >= 0) dw1_step(pb ^ 1);
-            if (next) load_tile(tile + gridDim.x);
             __syncthreads();
-            // ---- phase 3: output gradient and exponents of this tile; frame of dW1;
-            //      dW3 += dz3 h2^T, db2 += dz2, db3 += dz3 (VALU, h2 from the P waves);
-            //      the next tile's inputs into the other x buffers
-            const SampleExp se = sample_exp(xmax_b + pb * NT, meta, j);
-            const GradExp ge = grad_exp(z3p, gr_b + pb * NT * 4, b3, meta, j);
-            rescale<3>(dW1, F1, tile_frame(se.ex, ge.k1));
-            if (w == 0 && q == 0) {
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int o = 0; o < 3; ++o) db3[o] += ge.dz3[c][o];
-            }
-#pragma unroll
-            for (int mp = 0; mp < 2; ++mp) {
-                const int u0 = 32 * w + 16 * mp + 4 * q;
-                const float4 x0 = *reinterpret_cast<const float4 *>(W3 + u0);
-                const float4 x1 = *reinterpret_cast<const float4 *>(W3 + H + u0);
-                const float4 x2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + u0);
-                const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
-#pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const float h2 = h2s[(u0 + r) * H2S + 16 * c + j];
-                        const float d = wv[0][r] * ge.dz3[c][0] + wv[1][r] * ge.dz3[c][1] + wv[2][r] * ge.dz3[c][2];
-                        db2[mp][r] += h2 > 0.f ? d : 0.f;
-#pragma unroll
-                        for (int o = 0; o < 3; ++o) dw3[o][mp][r] += ge.dz3[c][o] * h2;
-                    }
-            }
-            if (next) stage_tile(pb ^ 1);
-            __syncthreads();
-            // ---- phase 4: dz1 = mask(h1) W2^T dz2, dfeat partials, frame-scaled dz1^T
+            // ---- C: output gradient and exponents of this tile; frame of dW1;
+            //      dW3 += dz3 h2^T, db2 += dz2, db3 += dz3 (VALU, h2 from the P waves)
             {
-                float dz1[2][2][4];
+                const SampleExp se = sample_exp(xmax_b + pb * NT, meta, j);
+                const GradExp ge = grad_exp(z3p, gr_b + pb * NT * 4, b3, meta, j);
+                rescale<3>(dW1, F1, tile_frame(se.ex, ge.k1));
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+                    pg2[c] = ge.g2[c];
+                    pg1[c] = ge.g1[c];
+                    pex[c] = se.ex[c];
+                }
+                if (w == 0 && q == 0) {
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const h8 bh = lds_h8(rA, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
-                        const h8 bl = lds_h8(rA, B_HBL - B_HBH, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                    for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2tl[mp][kk], bh, acc[mp]);
+                        for (int o = 0; o < 3; ++o) db3[o] += ge.dz3[c][o];
+                }
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2th[mp][kk], bl, acc[mp]);
+                for (int mp = 0; mp < 2; ++mp) {
+                    const int u0 = 32 * w + 16 * mp + 4 * q;
+                    const float4 x0 = *reinterpret_cast<const float4 *>(W3 + u0);
+                    const float4 x1 = *reinterpret_cast<const float4 *>(W3 + H + u0);
+                    const float4 x2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + u0);
+                    const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[mp] = mfma16(w2th[mp][kk], bh, acc[mp]);
-                    }
-                    const int un = -(meta.sw2 + ge.g2[c]);
-                    const int fs = frame_shift(F1, se.ex[c]);
-#pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) {
-                        const int u0 = 32 * w + 16 * mp + 4 * q;
-                        const unsigned long long *mk = mask1 + ((w * 2 + mp) * 2 + c) * 4;
+                    for (int c = 0; c < 2; ++c)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const bool on = (mk[r] >> (16 * q + j)) & 1ull;
-                            dz1[mp][c][r] = on ? ldx(acc[mp][r], un) : 0.f;
-                            db1[mp][r] += dz1[mp][c][r];
-                            put_t(rB, 0, B_D1TL - B_D1TH, u0 + r, 16 * c + j, ldx(dz1[mp][c][r], fs));
-                        }
-                    }
-                    __builtin_amdgcn_sched_barrier(0);
-                }
-                // dfeat partial over this wave's 32 units: rows = feature 4q + r, column = sample
+                            const float h2 = h2s[(u0 + r) * H2S + 16 * c + j];
+                            const float d = wv[0][r] * ge.dz3[c][0] + wv[1][r] * ge.dz3[c][1] + wv[2][r] * ge.dz3[c][2];
+                            db2[mp][r] += h2 > 0.f ? d : 0.f;
 #pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    h4 h0, l0, h1v, l1v;
-                    const float sc = pow2(ge.g1[c]);
-                    split4(dz1[0][c], sc, h0, l0);
-                    split4(dz1[1][c], sc, h1v, l1v);
-                    const h8 bh = cat(h0, h1v), bl = cat(l0, l1v);
-                    v4f df = v4f{0.f, 0.f, 0.f, 0.f};
-                    df = mfma16(w1fl, bh, df);
-                    df = mfma16(w1fh, bl, df);
-                    df = mfma16(w1fh, bh, df);
-                    const int un = -(meta.sw1 + ge.g1[c]);
-                    *reinterpret_cast<float4 *>(dfp + (w * NT + 16 * c + j) * 16 + 4 * q) =
-                        make_float4(ldx(df[0], un), ldx(df[1], un), ldx(df[2], un), ldx(df[3], un));
+                            for (int o = 0; o < 3; ++o) dw3[o][mp][r] += ge.dz3[c][o] * h2;
+                        }
                 }
             }
+            __syncthreads();
+            // ---- D: feature gradient of the previous tile; the next tile's inputs -> x planes
+            if (pbase >= 0) feat_out(pbase);
+            if (next) stage_tile(pb ^ 1);
             __syncthreads();
             pbase = tile * NT;
         }
-        // ---- the last tile's feature gradient and dW1 (no barrier needed: C-only work)
+        // ---- the last tile: A (dz1), B (dW1 and the feature gradient)
+        if (pbase >= 0) dz1_step((it - 1) & 1, pg2, pg1, pex);
+        __syncthreads();
         if (pbase >= 0) {
-            feat_out(pbase);
             dw1_step((it - 1) & 1);
+            feat_out(pbase);
         }
-        // ---- partial gradients of the C role: W1, b1, W2's neighbours b2, W3, b3
+        __syncthreads();
+        // ---- partial gradients of the C role: W1, b1, b2, W3, b3
         const int u1 = F1 == FRAME_NONE ? 0 : -F1;
 #pragma unroll
         for (int mp = 0; mp < 2; ++mp)
