@@ -28,6 +28,35 @@ FP16_PEAK_TFLOPS = 2500.0   # dense FP16 matrix peak of MI355X
 H, C_IN, N_IN = 128, 12, 39   # MLP widths: hidden, feature channels, input columns (12 + 27)
 
 
+TRAFFIC_FILES = {"mlp_bwd": ("profiles/mlp_bwd_config2_hbm_traffic.md", ["paper_2206_05085_amd/csrc/mlp.hip",
+                                                                       "paper_2206_05085_amd/csrc/dvgo_internal.h"])}
+
+
+def measured_traffic(stage):
+    """HBM bytes per launch of the stage's main kernel from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for a plain copy), or
+    None when there is none or the kernel sources changed since the counters were taken."""
+    import hashlib
+    spec = TRAFFIC_FILES.get(stage)
+    root = os.path.dirname(os.path.abspath(__file__))
+    if spec is None or not os.path.exists(os.path.join(root, spec[0])):
+        return None
+    h = hashlib.sha256()
+    for f in spec[1]:
+        h.update(open(os.path.join(root, f), "rb").read())
+    vals = {}
+    for line in open(os.path.join(root, spec[0])):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    try:
+        return int(float(vals["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def mlp_flops_per_sample(backward: bool) -> float:
     """Algorithmic FLOPs of the colour MLP per sample (multiply-add = 2 FLOPs)."""
     fwd = 2 * (N_IN * H + H * H + H * 3)
@@ -314,6 +343,8 @@ def main():
     ap.add_argument("--no-proposal", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=1500)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="end with a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
@@ -408,7 +439,7 @@ def main():
         # the colour MLP runs on FP16 matrix cores with split (hi + lo) operands: three FP16
         # products per FP32-grade product, so FP16_PEAK / 3 is the ceiling of this formulation
         roof = {"kernel": dom, "bound": "mfma", "achieved": round(ach, 2), "peak": FP16_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(ach / FP16_PEAK_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(ach / FP16_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom),
                 "algorithmic": f"{fl / S:.0f} FLOP/sample x {S} samples",
                 "mfma_dtype": "f16 (split hi/lo, 3 products)",
                 "frac_of_split_ceiling": round(ach / (FP16_PEAK_TFLOPS / 3), 4)}
@@ -443,6 +474,14 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_rays)
+    if args.calib_copy_mib > 0:
+        # a plain copy of known size for the FETCH_SIZE / WRITE_SIZE calibration: reads and writes
+        # exactly calib_copy_mib MiB (one torch copy kernel), the last dispatch of the process
+        src = torch.ones(args.calib_copy_mib * 2**18, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
     print(json.dumps(out), flush=True)
 
 

@@ -201,61 +201,86 @@ __device__ __forceinline__ void put_split(unsigned char *img, int off_h, int off
 // logical index of phys slot p of a 128- or 64-wide operand row
 __device__ __forceinline__ int phys_to_k(int p) { return kidx(p >> 5, (p >> 3) & 3, p & 7); }
 
-constexpr int PREP_THREADS = 256;
-constexpr int PREP_W2_BLOCKS = 8;
-constexpr int PREP_FIXED_BLOCKS = PREP_W2_BLOCKS + 3;
+constexpr int PREP_THREADS = 512;
+constexpr int PREP_W2_BLOCKS = 16;  // 8 rows of W2 and of W2^T each
+constexpr int PREP_W1_BLOCKS = 4;   // 32 rows of W1 each (block 0 of them also W1F, b1, b3)
+constexpr int PREP_FIXED_BLOCKS = PREP_W2_BLOCKS + PREP_W1_BLOCKS + 1;
 
-// blocks 0..7: W2 and W2^T planes (16 rows each); block 8: W1 planes, W1F planes, b1, b3,
-// n1, b1max, sw1; block 9: W3, b2, n3t; block 10: n2t, sw2; blocks 11..: view encodings.
+// blocks [0, 16): W2 and W2^T planes; every one of them also reduces max|W2| and the column
+// sums of |W2| from the same loads (block 0 stores sw2 and n2t).  Blocks [16, 20): W1 planes,
+// max|W1| and the row sums of |W1| (block 16 stores sw1, n1, b1max and writes W1F, b1, b3).
+// Block 20: W3, b2, n3t.  Then view encodings (one ray per thread) and tile start rays.
 __global__ __launch_bounds__(PREP_THREADS) void mlp_prep_kernel(MlpArgs a) {
     __shared__ float red[PREP_THREADS / 64];
+    __shared__ float sums[PREP_THREADS];
     unsigned char *img = a.img;
     Meta *meta = reinterpret_cast<Meta *>(img + IMG_META);
     const int tid = threadIdx.x, b = blockIdx.x;
+    const int pe_blocks = (a.n_rays + PREP_THREADS - 1) / PREP_THREADS;
     if (b < PREP_W2_BLOCKS) {
-        float m = 0.f;
-        for (int i = tid; i < H * H; i += PREP_THREADS) m = fmaxf(m, fabsf(a.W2[i]));
-        const int sw = scale_exp(block_max(m, red));
+        // element i = tid + 512 k sits in column tid % 128 (512 is a multiple of H)
+        float m = 0.f, cs = 0.f;
+#pragma unroll 8
+        for (int i = tid; i < H * H; i += PREP_THREADS) {
+            const float v = fabsf(a.W2[i]);
+            m = fmaxf(m, v);
+            cs += v;
+        }
+        sums[tid] = cs;
+        const int sw = scale_exp(block_max(m, red));  // its barriers also order the sums
+        float n2t = 0.f;
+        if (b == 0) {
+            const float col = tid < H ? sums[tid] + sums[tid + H] + sums[tid + 2 * H] + sums[tid + 3 * H] : 0.f;
+            n2t = block_max(col, red);
+        }
         const float sc = pow2(sw);
-        for (int i = tid; i < 16 * RS2; i += PREP_THREADS) {
-            const int row = 16 * b + i / RS2, p = i % RS2;
+        for (int i = tid; i < 8 * RS2; i += PREP_THREADS) {
+            const int row = 8 * b + i / RS2, p = i % RS2;
             const int k = p < H ? phys_to_k(p) : -1;
             put_split(img, IMG_W2H, IMG_W2L, row * RS2 + p, k >= 0 ? a.W2[row * H + k] : 0.f, sc);
             put_split(img, IMG_W2TH, IMG_W2TL, row * RS2 + p, k >= 0 ? a.W2[k * H + row] : 0.f, sc);
         }
-        if (b == 0 && tid == 0) meta->sw2 = sw;
-    } else if (b == PREP_W2_BLOCKS) {
-        float m = 0.f, rs = 0.f, bm = 0.f;
-        for (int i = tid; i < H * a.n_in; i += PREP_THREADS) m = fmaxf(m, fabsf(a.W1[i]));
-        if (tid < H) {
-            for (int k = 0; k < a.n_in; ++k) rs += fabsf(a.W1[tid * a.n_in + k]);
-            bm = fabsf(a.b1[tid]);
+        if (b == 0 && tid == 0) {
+            meta->sw2 = sw;
+            meta->n2t = n2t;
+        }
+    } else if (b < PREP_W2_BLOCKS + PREP_W1_BLOCKS) {
+        const int wb = b - PREP_W2_BLOCKS;
+        if (tid < H) sums[tid] = 0.f;
+        __syncthreads();
+        float m = 0.f;
+        for (int i = tid; i < H * a.n_in; i += PREP_THREADS) {
+            const float v = fabsf(a.W1[i]);
+            m = fmaxf(m, v);
+            atomicAdd(&sums[i / a.n_in], v);
         }
         const int sw = scale_exp(block_max(m, red));
-        const float n1 = block_max(rs, red);
-        const float b1max = block_max(bm, red);
         const float sc = pow2(sw);
-        for (int i = tid; i < H * RS1; i += PREP_THREADS) {
-            const int row = i / RS1, p = i % RS1;
+        for (int i = tid; i < 32 * RS1; i += PREP_THREADS) {
+            const int row = 32 * wb + i / RS1, p = i % RS1;
             const int c = p < KX ? w1_col(a.in_feat, a.n_freq, phys_to_k(p)) : -1;
-            put_split(img, IMG_W1H, IMG_W1L, i, c >= 0 ? a.W1[row * a.n_in + c] : 0.f, sc);
+            put_split(img, IMG_W1H, IMG_W1L, row * RS1 + p, c >= 0 ? a.W1[row * a.n_in + c] : 0.f, sc);
         }
-        // W1F[c][phys over hidden] = W1[hidden][c] for the feature columns c < in_feat
-        for (int i = tid; i < 16 * RS2; i += PREP_THREADS) {
-            const int c = i / RS2, p = i % RS2;
-            const int h = p < H ? phys_to_k(p) : -1;
-            put_split(img, IMG_W1FH, IMG_W1FL, i, (h >= 0 && c < a.in_feat) ? a.W1[h * a.n_in + c] : 0.f, sc);
+        if (wb == 0) {
+            const float n1 = block_max(tid < H ? sums[tid] : 0.f, red);
+            const float b1max = block_max(tid < H ? fabsf(a.b1[tid]) : 0.f, red);
+            // W1F[c][phys over hidden] = W1[hidden][c] for the feature columns c < in_feat
+            for (int i = tid; i < 16 * RS2; i += PREP_THREADS) {
+                const int c = i / RS2, p = i % RS2;
+                const int h = p < H ? phys_to_k(p) : -1;
+                put_split(img, IMG_W1FH, IMG_W1FL, i, (h >= 0 && c < a.in_feat) ? a.W1[h * a.n_in + c] : 0.f, sc);
+            }
+            float *b1 = reinterpret_cast<float *>(img + IMG_B1);
+            float *b3 = reinterpret_cast<float *>(img + IMG_B3);
+            if (tid < H) b1[tid] = a.b1[tid];
+            if (tid < 4) b3[tid] = tid < 3 ? a.b3[tid] : 0.f;
+            if (tid == 0) {
+                meta->sw1 = sw;
+                meta->n1 = n1;
+                meta->b1max = b1max;
+            }
         }
-        float *b1 = reinterpret_cast<float *>(img + IMG_B1);
-        float *b3 = reinterpret_cast<float *>(img + IMG_B3);
-        if (tid < H) b1[tid] = a.b1[tid];
-        if (tid < 4) b3[tid] = tid < 3 ? a.b3[tid] : 0.f;
-        if (tid == 0) {
-            meta->sw1 = sw;
-            meta->n1 = n1;
-            meta->b1max = b1max;
-        }
-    } else if (b == PREP_W2_BLOCKS + 1) {
+    } else if (b == PREP_FIXED_BLOCKS - 1) {
         float *w3 = reinterpret_cast<float *>(img + IMG_W3);
         float *b2 = reinterpret_cast<float *>(img + IMG_B2);
         float cs = 0.f;
@@ -266,14 +291,8 @@ __global__ __launch_bounds__(PREP_THREADS) void mlp_prep_kernel(MlpArgs a) {
         }
         const float n3t = block_max(cs, red);
         if (tid == 0) meta->n3t = n3t;
-    } else if (b == PREP_W2_BLOCKS + 2) {
-        float cs = 0.f;
-        if (tid < H)
-            for (int o = 0; o < H; ++o) cs += fabsf(a.W2[o * H + tid]);
-        const float n2t = block_max(cs, red);
-        if (tid == 0) meta->n2t = n2t;
-    } else if (b >= PREP_FIXED_BLOCKS + (a.n_rays + PREP_THREADS - 1) / PREP_THREADS) {
-        const int t = (b - PREP_FIXED_BLOCKS - (a.n_rays + PREP_THREADS - 1) / PREP_THREADS) * PREP_THREADS + tid;
+    } else if (b >= PREP_FIXED_BLOCKS + pe_blocks) {
+        const int t = (b - PREP_FIXED_BLOCKS - pe_blocks) * PREP_THREADS + tid;
         if (t < a.n_tiles) a.tile_ray[t] = find_ray(a.offs, a.n_rays, TILE * t);
     } else {
         const int r = (b - PREP_FIXED_BLOCKS) * PREP_THREADS + tid;
@@ -291,7 +310,6 @@ __global__ __launch_bounds__(PREP_THREADS) void mlp_prep_kernel(MlpArgs a) {
         }
     }
 }
-
 
 // Pointer into a kernel's LDS block at byte offset `off`, with the offset hidden from the
 // optimiser: accesses then share one base register and use the 16-bit immediate offset of
@@ -1141,12 +1159,23 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     }
 }
 
-// gradient += sum of the per-block partials
-__global__ void mlp_reduce_kernel(MlpArgs a) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= a.n_params) return;
+// gradient += sum of the per-block partials: 64 parameters per block, the four waves sum
+// interleaved quarters of the partials and are combined in a fixed order
+constexpr int RED_THREADS = 256;
+
+__global__ __launch_bounds__(RED_THREADS) void mlp_reduce_kernel(MlpArgs a) {
+    __shared__ float part[RED_THREADS / 64][64];
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int i = blockIdx.x * 64 + l;
     float acc = 0.f;
-    for (int b = 0; b < a.nblocks; ++b) acc += a.partial[(int64_t)b * a.n_params + i];
+    if (i < a.n_params) {
+#pragma unroll 8
+        for (int b = wv; b < a.nblocks; b += RED_THREADS / 64) acc += a.partial[(int64_t)b * a.n_params + i];
+    }
+    part[wv][l] = acc;
+    __syncthreads();
+    if (wv != 0 || i >= a.n_params) return;
+    acc = (part[0][l] + part[1][l]) + (part[2][l] + part[3][l]);
     const int nW1 = H * a.n_in;
     int k = i;
     if (k < nW1) { a.gW1[k] += acc; return; }
@@ -1278,6 +1307,6 @@ extern "C" int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const 
     hipLaunchKernelGGL(mlp_bwd_kernel, dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     rc = check_hip(hipGetLastError(), "mlp_bwd_kernel launch");
     if (rc) return rc;
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((a.n_params + 255) / 256), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((a.n_params + 63) / 64), dim3(RED_THREADS), 0, st, a);
     return check_hip(hipGetLastError(), "mlp_reduce_kernel launch");
 }
