@@ -16,6 +16,10 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
 * Adam: pinned against torch.optim.Adam in float64; skip rule checked bitwise.
 * proposal network: pinned against torch float64 with bfloat16-rounded operands;
   softmax/CE gradient closed form; resample closed forms (uniform and one-hot).
+* total variation (Huber to the six axis neighbours, dense and sparse gradient modes):
+  pinned (constant field, linear-ramp and saturated-spike closed forms, finite
+  differences of the loss, 2-homogeneity of the quadratic regime, the sparse rule).
+  The Huber threshold is unstated in the paper; it is an argument.
 * the alpha activation itself (the paper names it but never writes it): parity
   unpinned beyond its defining identity alpha(raw=0, delta_ref) = alpha_init.
 """
@@ -72,6 +76,7 @@ def lib():
         L.orc_act_shift.argtypes = [C.c_double, C.c_double]
         L.orc_loss_head.restype = C.c_double
         L.orc_prop_backward.restype = C.c_double
+        L.orc_tv.restype = C.c_double
         _lib = L
     return _lib
 
@@ -447,3 +452,16 @@ def softmax_entropy(logits):
     H = np.zeros(R)
     lib().orc_softmax_entropy(C.c_int32(R), C.c_int32(B), _ptr(lg), _ptr(p), _ptr(H))
     return p, H
+
+
+def tv(grid, weight, delta, dense=True, grad=None):
+    """Total-variation loss and gradient of a grid (orc_tv): returns (L, grad_in + dL/dv) where
+    the gradient is added at every vertex (dense) or only where some channel of grad_in is
+    non-zero.  grid: synth.Grid (data [nx,ny,nz,C] float32); grad: float64 array of the
+    same shape, or None (zeros)."""
+    keep = _Keep()
+    g = grid_struct(grid, keep)
+    out = np.zeros(grid.data.shape, np.float64) if grad is None else np.array(grad, np.float64, copy=True)
+    out = np.ascontiguousarray(out)
+    L = lib().orc_tv(C.byref(g), C.c_double(weight), C.c_double(delta), C.c_int32(1 if dense else 0), _ptr(out))
+    return float(L), out

@@ -982,3 +982,46 @@ void orc_softmax_entropy(int32_t R, int32_t B, const double *logits, double *pro
         H[r] = h;
     }
 }
+
+/* -------------------------------------------------------------- total variation */
+
+/* Total-variation regulariser of a grid (section 2, efficient TV loss): for every vertex p
+ * and channel c, the Huber penalty of the difference to each of its (up to six) axis
+ * neighbours n,
+ *     L = weight / (N C) * sum_p sum_c sum_n huber(v[p][c] - v[n][c]),
+ * N = number of vertices, C = channels, huber(x) = x^2/2 for |x| <= delta, else
+ * delta (|x| - delta/2).  Every neighbour pair appears from both of its ends, so
+ *     dL/dv[p][c] = 2 weight / (N C) * sum_n clamp(v[p][c] - v[n][c], -delta, delta).
+ * grad ([N][cs], FP64) receives += dL/dv at every vertex (dense != 0) or only at the
+ * vertices where some channel of the incoming grad is non-zero (sparse).  Returns L. */
+double orc_tv(const orc_grid *g, double weight, double delta, int32_t dense, double *grad)
+{
+    const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2], N = nx * ny * nz;
+    const double scale = weight / ((double)N * g->C);
+    double loss = 0.0;
+    for (int64_t x = 0; x < nx; ++x)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t z = 0; z < nz; ++z) {
+                const int64_t i = (x * ny + y) * nz + z;
+                int touched = dense;
+                if (grad)
+                    for (int c = 0; c < g->C && !touched; ++c) touched = grad[i * g->cs + c] != 0.0;
+                const int64_t nb[6][3] = {{x - 1, y, z}, {x + 1, y, z}, {x, y - 1, z},
+                                          {x, y + 1, z}, {x, y, z - 1}, {x, y, z + 1}};
+                for (int c = 0; c < g->C; ++c) {
+                    const double v = g->data[i * g->cs + c];
+                    double d_sum = 0.0;
+                    for (int k = 0; k < 6; ++k) {
+                        if (nb[k][0] < 0 || nb[k][0] >= nx || nb[k][1] < 0 || nb[k][1] >= ny || nb[k][2] < 0 ||
+                            nb[k][2] >= nz)
+                            continue;
+                        const int64_t j = (nb[k][0] * ny + nb[k][1]) * nz + nb[k][2];
+                        const double d = v - (double)g->data[j * g->cs + c];
+                        loss += fabs(d) <= delta ? 0.5 * d * d : delta * (fabs(d) - 0.5 * delta);
+                        d_sum += d < -delta ? -delta : (d > delta ? delta : d);
+                    }
+                    if (grad && touched) grad[i * g->cs + c] += 2.0 * scale * d_sum;
+                }
+            }
+    return scale * loss;
+}
