@@ -331,6 +331,44 @@ def ragged_leg(R=8192, steps=20, log=None):
             "buckets": len(buckets)}
 
 
+def tv_leg(ops, st, torch, reps=20):
+    """Total-variation gradient on the step's grids (section 2): dense over all vertices, and
+    sparse over the vertices an eager backward touched.  Weights 1e-5 (density) and 1e-6
+    (features) as in section 5.3; Huber threshold 1.0 (the paper does not give one).
+    Compulsory bytes: dense 12 B per element (value, gradient in and out); sparse 4 B per
+    element (gradient test) + 8 B per element of a touched vertex."""
+    st.forward()
+    st.backward()          # leaves the step's gradients in the grid .grad buffers
+    torch.cuda.synchronize()
+    res = {"delta": 1.0, "weights": {"density": 1e-5, "feat": 1e-6}}
+    for name, w in (("density", 1e-5), ("feat", 1e-6)):
+        g = st.grid(name)
+        N = g.data.shape[0] * g.data.shape[1] * g.data.shape[2]
+        Cc = g.data.shape[3]
+        touched = int((g.grad.reshape(N, Cc) != 0).any(dim=1).sum().item())
+        snapshot = g.grad.clone()
+        for dense in (True, False):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ops.tv_add_grad(g, w, 1.0, dense)
+            e0.record()
+            for _ in range(reps):
+                ops.tv_add_grad(g, w, 1.0, dense)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            by = 12 * N * Cc if dense else 4 * N * Cc + 8 * touched * Cc
+            gbs = by / (ms * 1e-3) / 1e9
+            res[f"{name}_{'dense' if dense else 'sparse'}"] = {
+                "ms": round(ms, 4), "bytes": by, "GB/s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+            g.grad.copy_(snapshot)
+        res[f"{name}_touched_vertices"] = touched
+        res[f"{name}_vertices"] = N
+    for d in (st.density, st.feat, st.mlp_flat):
+        d["g"].zero_()
+    torch.cuda.synchronize()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,6 +381,7 @@ def main():
     ap.add_argument("--no-proposal", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=1500)
+    ap.add_argument("--no-tv", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="end with a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -463,6 +502,9 @@ def main():
                       "rays": R, "live_samples": S, "graph": use_graph, "parallelism": "single GPU"},
            "roofline": roof, "roofline_render": roof_render,
            "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()}, "loss": loss, "wall_s": round(wall, 3)}
+    if not args.no_tv:
+        print("[bench] total-variation gradients", file=sys.stderr, flush=True)
+        out["tv"] = tv_leg(ops, st, torch)
     if not args.no_ragged:
         print("[bench] ragged unbounded batch: schedules", file=sys.stderr, flush=True)
         out["ragged"] = ragged_leg(log=True)

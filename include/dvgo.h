@@ -188,6 +188,20 @@ int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, int64_t n_s
                          const float *s_mid, const float *s_len, float *loss, const float *grad_loss, float *grad_w,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* Total-variation regulariser of a grid, gradient only (section 2, efficient TV loss: the
+ * loss itself is not formed; its gradient is added into the grid gradient between the
+ * backward pass and the optimiser step).  Loss read as
+ *     L = weight / (N C) * sum_p sum_c sum_n huber_delta(v[p][c] - v[n][c])
+ * over vertices p (N of them), channels c < channels (C) and the up to six axis neighbours
+ * n of p; so g->grad[p][c] += 2 weight / (N C) * sum_n clamp(v[p][c] - v[n][c], -delta, delta).
+ * dense != 0: every vertex; dense == 0 (the paper's mode after its first 10k iterations):
+ * only vertices where some channel of the incoming g->grad is non-zero.  g->data is read,
+ * g->grad is read and updated in place (padding channels untouched).  The Huber threshold
+ * is not given in the paper: delta > 0 is an argument.  Errors: DVGO_ERR_NULL,
+ * DVGO_ERR_SHAPE (dimensions < 2, bad channels, misaligned float4 rows), DVGO_ERR_RANGE
+ * (delta <= 0). */
+int dvgo_tv_add_grad(const dvgo_grid *g, float weight, float delta, int32_t dense, void *stream);
+
 /* Fused Adam over n float32 elements (section 3, re-implemented Adam): with 1-based step t,
  * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2; p -= lr * (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).
  * t is `step`, or, when step_dev is not NULL, the int32 at step_dev read by the kernel (so a

@@ -454,14 +454,17 @@ def softmax_entropy(logits):
     return p, H
 
 
-def tv(grid, weight, delta, dense=True, grad=None):
+def tv(grid, weight, delta, dense=True, grad=None, want_mag=False):
     """Total-variation loss and gradient of a grid (orc_tv): returns (L, grad_in + dL/dv) where
     the gradient is added at every vertex (dense) or only where some channel of grad_in is
     non-zero.  grid: synth.Grid (data [nx,ny,nz,C] float32); grad: float64 array of the
-    same shape, or None (zeros)."""
+    same shape, or None (zeros).  want_mag: also return the per-element magnitude the
+    gradient sum is conditioned on."""
     keep = _Keep()
     g = grid_struct(grid, keep)
     out = np.zeros(grid.data.shape, np.float64) if grad is None else np.array(grad, np.float64, copy=True)
     out = np.ascontiguousarray(out)
-    L = lib().orc_tv(C.byref(g), C.c_double(weight), C.c_double(delta), C.c_int32(1 if dense else 0), _ptr(out))
-    return float(L), out
+    mag = np.zeros(grid.data.shape, np.float64) if want_mag else None
+    L = lib().orc_tv(C.byref(g), C.c_double(weight), C.c_double(delta), C.c_int32(1 if dense else 0), _ptr(out),
+                     _ptr(mag) if want_mag else None)
+    return (float(L), out, mag) if want_mag else (float(L), out)

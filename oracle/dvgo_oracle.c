@@ -993,8 +993,10 @@ void orc_softmax_entropy(int32_t R, int32_t B, const double *logits, double *pro
  * delta (|x| - delta/2).  Every neighbour pair appears from both of its ends, so
  *     dL/dv[p][c] = 2 weight / (N C) * sum_n clamp(v[p][c] - v[n][c], -delta, delta).
  * grad ([N][cs], FP64) receives += dL/dv at every vertex (dense != 0) or only at the
- * vertices where some channel of the incoming grad is non-zero (sparse).  Returns L. */
-double orc_tv(const orc_grid *g, double weight, double delta, int32_t dense, double *grad)
+ * vertices where some channel of the incoming grad is non-zero (sparse).  mag (optional,
+ * [N][cs]) receives 2 weight / (N C) * sum_n |clamp(...)|, the magnitude a float evaluation
+ * of the sum is conditioned on.  Returns L. */
+double orc_tv(const orc_grid *g, double weight, double delta, int32_t dense, double *grad, double *mag)
 {
     const int64_t nx = g->n[0], ny = g->n[1], nz = g->n[2], N = nx * ny * nz;
     const double scale = weight / ((double)N * g->C);
@@ -1010,7 +1012,7 @@ double orc_tv(const orc_grid *g, double weight, double delta, int32_t dense, dou
                                           {x, y + 1, z}, {x, y, z - 1}, {x, y, z + 1}};
                 for (int c = 0; c < g->C; ++c) {
                     const double v = g->data[i * g->cs + c];
-                    double d_sum = 0.0;
+                    double d_sum = 0.0, d_abs = 0.0;
                     for (int k = 0; k < 6; ++k) {
                         if (nb[k][0] < 0 || nb[k][0] >= nx || nb[k][1] < 0 || nb[k][1] >= ny || nb[k][2] < 0 ||
                             nb[k][2] >= nz)
@@ -1018,9 +1020,12 @@ double orc_tv(const orc_grid *g, double weight, double delta, int32_t dense, dou
                         const int64_t j = (nb[k][0] * ny + nb[k][1]) * nz + nb[k][2];
                         const double d = v - (double)g->data[j * g->cs + c];
                         loss += fabs(d) <= delta ? 0.5 * d * d : delta * (fabs(d) - 0.5 * delta);
-                        d_sum += d < -delta ? -delta : (d > delta ? delta : d);
+                        const double cl = d < -delta ? -delta : (d > delta ? delta : d);
+                        d_sum += cl;
+                        d_abs += fabs(cl);
                     }
                     if (grad && touched) grad[i * g->cs + c] += 2.0 * scale * d_sum;
+                    if (mag) mag[i * g->cs + c] = 2.0 * scale * d_abs;
                 }
             }
     return scale * loss;

@@ -76,6 +76,7 @@ SIGNATURES = {
     "dvgo_counter_add": (C.c_int, [VP, _I32, VP]),
     "dvgo_grid_gather": (C.c_int, [_PG, _I64, VP, VP, VP]),
     "dvgo_grid_scatter": (C.c_int, [_PG, _I64, VP, VP, VP]),
+    "dvgo_tv_add_grad": (C.c_int, [_PG, _F, _F, _I32, VP]),
     "dvgo_alpha": (C.c_int, [_PG, _I64, VP, VP, _F, VP, VP]),
     "dvgo_mlp_workspace_size": (C.c_int, [_PM, _I32, _I64, _SZP]),
     "dvgo_mlp_forward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, C.c_size_t, VP]),

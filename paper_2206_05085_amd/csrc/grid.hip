@@ -352,3 +352,119 @@ extern "C" int dvgo_loss_head(int32_t n_rays, const float *rgb, const float *tar
                        dist_weight, loss, grad_rgb, grad_dist);
     return check_hip(hipGetLastError(), "loss_head_kernel launch");
 }
+
+// ------------------------------------------------------------------ total variation
+//
+// Gradient of the grid's total-variation regulariser (section 2, efficient TV loss), added
+// straight into the gradient: for vertex p and channel c,
+//     grad[p][c] += coef * sum over the (up to six) axis neighbours n of clamp(v[p][c] - v[n][c], -delta, delta)
+// with coef = 2 weight / (N C).  Vector path (channels == ch_stride, a multiple of 4): G =
+// channels / 4 lanes per vertex, each owning one float4 of the row, so every load of a wave
+// is contiguous; floor(64 / G) vertices per wave.  Scalar path: one lane per vertex, channel
+// loop.  Blocks are renumbered so that each XCD (blocks are dealt to the 8 XCDs round-robin)
+// walks one contiguous slab of the grid and finds the x and y neighbour planes in its own L2.
+// In sparse mode a vertex is updated only if some channel of its incoming gradient is
+// non-zero; a lane reads and writes only its own vertex's gradient, so the test never sees
+// another lane's update.
+namespace {
+
+constexpr int TV_BLOCK = 256, N_XCD = 8;
+
+__device__ __forceinline__ int64_t xcd_block(int nblocks) {
+    // hardware block b runs on XCD b % 8; give XCD k the logical range [k q, (k+1) q)
+    const int q = (nblocks + N_XCD - 1) / N_XCD;
+    return (int64_t)(blockIdx.x % N_XCD) * q + blockIdx.x / N_XCD;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(TV_BLOCK) void tv_kernel(DevGrid g, float coef, float delta, int dense, int64_t nvert,
+                                                     int nblocks) {
+    const int64_t lb = xcd_block(nblocks);
+    if (lb >= nblocks) return;  // whole block: padding of the renumbering
+    const int G = VEC ? g.C / 4 : 1;            // lanes per vertex
+    const int vpw = 64 / G;                     // vertices per wave
+    const int ln = lane(), vl = ln / G, grp = ln - vl * G;
+    const int64_t wave = lb * (TV_BLOCK / 64) + (threadIdx.x >> 6);
+    const int64_t i = wave * vpw + vl;
+    const bool live = vl < vpw && i < nvert;
+    const int nz = g.n[2], ny = g.n[1], nx = g.n[0];
+    const int z = live ? (int)(i % nz) : 0;
+    const int64_t t = live ? i / nz : 0;
+    const int y = (int)(t % ny), x = (int)(t / ny);
+    const int64_t base = i * g.cs + 4 * grp;
+    if (VEC) {
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (live) q = *reinterpret_cast<const float4 *>(g.grad + base);
+        if (!dense) {
+            const bool nonzero = live && ((q.x != 0.f) | (q.y != 0.f) | (q.z != 0.f) | (q.w != 0.f));
+            const unsigned long long b = __ballot(nonzero);  // every lane takes part
+            const unsigned long long mine = ((1ull << G) - 1) << (vl * G);
+            if (!(b & mine)) return;
+        }
+        if (!live) return;
+        const float4 v = *reinterpret_cast<const float4 *>(g.data + base);
+        const int64_t off[6] = {-(int64_t)g.sx, (int64_t)g.sx, -(int64_t)g.sy, (int64_t)g.sy, -(int64_t)g.cs,
+                                (int64_t)g.cs};
+        const bool ok[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < nz - 1};
+        float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            if (!ok[k]) continue;
+            const float4 u = *reinterpret_cast<const float4 *>(g.data + base + off[k]);
+            sum.x += fminf(fmaxf(v.x - u.x, -delta), delta);
+            sum.y += fminf(fmaxf(v.y - u.y, -delta), delta);
+            sum.z += fminf(fmaxf(v.z - u.z, -delta), delta);
+            sum.w += fminf(fmaxf(v.w - u.w, -delta), delta);
+        }
+        q.x += coef * sum.x;
+        q.y += coef * sum.y;
+        q.z += coef * sum.z;
+        q.w += coef * sum.w;
+        *reinterpret_cast<float4 *>(g.grad + base) = q;
+    } else {
+        if (!live) return;
+        float *gp = g.grad + i * g.cs;
+        const float *vp = g.data + i * g.cs;
+        if (!dense) {
+            bool any = false;
+            for (int c = 0; c < g.C; ++c) any |= gp[c] != 0.f;
+            if (!any) return;
+        }
+        const int64_t off[6] = {-(int64_t)g.sx, (int64_t)g.sx, -(int64_t)g.sy, (int64_t)g.sy, -(int64_t)g.cs,
+                                (int64_t)g.cs};
+        const bool ok[6] = {x > 0, x < nx - 1, y > 0, y < ny - 1, z > 0, z < nz - 1};
+        for (int c = 0; c < g.C; ++c) {
+            const float v = vp[c];
+            float sum = 0.f;
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+                if (ok[k]) sum += fminf(fmaxf(v - vp[off[k] + c], -delta), delta);
+            gp[c] += coef * sum;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" int dvgo_tv_add_grad(const dvgo_grid *g, float weight, float delta, int32_t dense, void *stream) {
+    DevGrid dg;
+    int rc = make_dev_grid(g, "grid", &dg, true);
+    if (rc) return rc;
+    if (!(delta > 0.f)) return set_error(DVGO_ERR_RANGE, "delta must be > 0");
+    const int64_t nvert = (int64_t)g->nx * g->ny * g->nz;
+    const bool vec = g->channels == g->ch_stride && (g->ch_stride & 3) == 0;
+    if (vec && (((uintptr_t)g->data | (uintptr_t)g->grad) & 15))
+        return set_error(DVGO_ERR_SHAPE, "grid data and grad must be 16-byte aligned when ch_stride is a multiple of 4");
+    const float coef = (float)(2.0 * (double)weight / ((double)nvert * g->channels));
+    const int vpw = vec ? 64 / (g->ch_stride / 4) : 64;
+    const int64_t waves = (nvert + vpw - 1) / vpw;
+    const int nblocks = (int)((waves + TV_BLOCK / 64 - 1) / (TV_BLOCK / 64));
+    const int launched = (nblocks + N_XCD - 1) / N_XCD * N_XCD;
+    if (vec)
+        hipLaunchKernelGGL(tv_kernel<true>, dim3(launched), dim3(TV_BLOCK), 0, (hipStream_t)stream, dg, coef, delta,
+                           dense ? 1 : 0, nvert, nblocks);
+    else
+        hipLaunchKernelGGL(tv_kernel<false>, dim3(launched), dim3(TV_BLOCK), 0, (hipStream_t)stream, dg, coef, delta,
+                           dense ? 1 : 0, nvert, nblocks);
+    return check_hip(hipGetLastError(), "tv_kernel launch");
+}

@@ -15,7 +15,7 @@ from ._lib import COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, ColorMLP, Grid, Proposa
 
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
-           "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather",
+           "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
            "grid_scatter", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
            "COLOR_GRID", "COLOR_SAMPLES"]
 
@@ -324,6 +324,15 @@ def grid_scatter(grid: DeviceGrid, xyz, grad_out):
     _chk(xyz, "xyz", numel=3 * S)
     _chk(grad_out, "grad_out", numel=S * g.channels)
     call("dvgo_grid_scatter", ctypes.byref(g), S, _p(xyz), _p(grad_out), _stream())
+
+
+def tv_add_grad(grid: DeviceGrid, weight: float, delta: float = 1.0, dense: bool = True):
+    """grid.grad += gradient of the total-variation regulariser (Huber to the six axis
+    neighbours, mean over vertices and channels, scaled by weight); dense=False updates only
+    vertices whose incoming gradient is non-zero."""
+    import ctypes
+    g = grid.struct(need_grad=True)
+    call("dvgo_tv_add_grad", ctypes.byref(g), float(weight), float(delta), 1 if dense else 0, _stream())
 
 
 def alpha(density: DeviceGrid, xyz, delta, act_shift_: float, out=None):

@@ -22,9 +22,11 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 device="cuda"):
+                 tv=None, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
-        color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU."""
+        color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
+        tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
+        term, added into the grid gradients after the backward pass."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -33,6 +35,7 @@ class TrainStep:
         self.grid_mode = color is not None
         self.shift = ops.act_shift() if act_shift is None else act_shift
         self.halt_T, self.bg, self.lam = halt_T, tuple(bg), dist_weight
+        self.tv = None if tv is None else (float(tv[0]), float(tv[1]), float(tv[2]), bool(tv[3]))
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
         self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
         self.density = self._param(dev(density))
@@ -123,6 +126,11 @@ class TrainStep:
             ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
                              ws=self.mlp_ws)
             ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+        if self.tv is not None:
+            # total-variation gradients go straight into the grid gradients before Adam (section 2)
+            w_density, w_other, delta, dense = self.tv
+            ops.tv_add_grad(self.grid("density"), w_density, delta, dense)
+            ops.tv_add_grad(self.grid("color" if self.grid_mode else "feat"), w_other, delta, dense)
 
     def optimise(self):
         ops.counter_add(self.t_dev, 1)

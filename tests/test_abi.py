@@ -122,6 +122,19 @@ def test_validation_errors(L):
     rr.origins = rr.dirs = rr.t_near = rr.t_far = 64
     assert lib.dvgo_resample_offsets(C.byref(rr), 64, 3.0, 300, 256, 64, None) == -3  # n_fine > 256
     assert lib.dvgo_histogram(4, 64, 64, 64, 32, 1e-4, 64, None) == -7
+    # total variation: NULL grid, missing gradient, delta <= 0, misaligned float4 rows
+    assert lib.dvgo_tv_add_grad(None, 1.0, 1.0, 1, None) == -1
+    t = L.Grid()
+    t.struct_size = C.sizeof(L.Grid)
+    t.nx, t.ny, t.nz, t.channels, t.ch_stride = 4, 4, 4, 12, 12
+    t.xyz_min[:] = [-1, -1, -1]
+    t.xyz_max[:] = [1, 1, 1]
+    t.data = 64
+    assert lib.dvgo_tv_add_grad(C.byref(t), 1.0, 1.0, 1, None) == -1      # grad is NULL
+    t.grad = 64
+    assert lib.dvgo_tv_add_grad(C.byref(t), 1.0, 0.0, 1, None) == -3
+    t.grad = 68
+    assert lib.dvgo_tv_add_grad(C.byref(t), 1.0, 1.0, 1, None) == -2
     # sizes
     assert lib.dvgo_render_state_size(8192, 10 ** 6, C.byref(out)) == 0 and out.value > 0
     assert lib.dvgo_render_state_size(-1, 0, C.byref(out)) == -2
