@@ -112,6 +112,10 @@ __device__ __forceinline__ void split4(const float v[4], float sc, h4 &hi, h4 &l
 
 __device__ __forceinline__ h8 cat(h4 a, h4 b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); }
 
+// logistic function with the hardware exponential and reciprocal (about 1e-7 relative; the
+// limits are exact: 1/(1 + inf) = 0 and 1/(1 + 0) = 1)
+__device__ __forceinline__ float fast_sigmoid(float z) { return __fdividef(1.f, 1.f + __expf(-z)); }
+
 __device__ __forceinline__ float pow2(int e) { return __builtin_amdgcn_ldexpf(1.f, e); }
 __device__ __forceinline__ float ldx(float v, int e) { return __builtin_amdgcn_ldexpf(v, e); }
 
@@ -495,7 +499,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
                 z[c][o] += __shfl_xor(z[c][o], 32, 64);
             }
             const float zq = q == 0 ? z[c][0] : (q == 1 ? z[c][1] : z[c][2]);
-            if (q < 3 && sv[c]) a.rgb[(int64_t)s[c] * 3 + q] = sigmoidf(zq + b3[q]);
+            if (q < 3 && sv[c]) a.rgb[(int64_t)s[c] * 3 + q] = fast_sigmoid(zq + b3[q]);
         }
     }
 }
@@ -606,7 +610,7 @@ __device__ __forceinline__ GradExp grad_exp(const float *z3p, const float *gr_s,
             float z = b3[o];
 #pragma unroll
             for (int ww = 0; ww < 4; ++ww) z += z3p[(ww * NT + sl) * 4 + o];
-            const float y = sigmoidf(z);
+            const float y = fast_sigmoid(z);
             g.dz3[c][o] = gr_s[sl * 4 + o] * y * (1.f - y);
             mx = fmaxf(mx, fabsf(g.dz3[c][o]));
         }
@@ -627,7 +631,8 @@ __device__ __forceinline__ int tile_frame(const int other_e[2], const int k[2]) 
     for (int c = 0; c < 2; ++c) f = min(f, 14 + other_e[c] - k[c]);
 #pragma unroll
     for (int o = 1; o < 16; o <<= 1) f = min(f, __shfl_xor(f, o, 64));
-    return f;
+    // every lane holds the same value: make it scalar so the (rare) rescale is a real branch
+    return __builtin_amdgcn_readfirstlane(f);
 }
 
 template <int N>
