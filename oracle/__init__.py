@@ -20,6 +20,12 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
   pinned (constant field, linear-ramp and saturated-spike closed forms, finite
   differences of the loss, 2-homogeneity of the quadratic regime, the sparse rule).
   The Huber threshold is unstated in the paper; it is an argument.
+* sample producer (box clipping, candidate placement, nearest-vertex mask compaction; its
+  integer decisions are taken in float32): pinned (axis-aligned closed forms, misses,
+  float64 slab geometry and counts, the cap, brute-force mask selection).
+* occupancy mask update (alpha threshold, 27-neighbour dilation, deactivation only):
+  pinned (numpy brute force, a single dense vertex, the alpha_init identity, idempotence
+  and monotonicity).
 * the alpha activation itself (the paper names it but never writes it): parity
   unpinned beyond its defining identity alpha(raw=0, delta_ref) = alpha_init.
 """
@@ -468,3 +474,40 @@ def tv(grid, weight, delta, dense=True, grad=None, want_mag=False):
     L = lib().orc_tv(C.byref(g), C.c_double(weight), C.c_double(delta), C.c_int32(1 if dense else 0), _ptr(out),
                      _ptr(mag) if want_mag else None)
     return (float(L), out, mag) if want_mag else (float(L), out)
+
+
+def occupancy_update(density, act_shift, delta, alpha_thr, mask=None):
+    """Occupancy mask update (orc_occupancy_update): returns the new uint8 mask [nx,ny,nz].
+    density: synth.Grid with one channel; mask: the current mask (None = all active)."""
+    keep = _Keep()
+    g = grid_struct(density, keep)
+    out = np.ones(density.data.shape[:3], np.uint8) if mask is None else np.array(mask, np.uint8, copy=True)
+    out = np.ascontiguousarray(out)
+    lib().orc_occupancy_update(C.byref(g), C.c_double(act_shift), C.c_double(delta), C.c_double(alpha_thr),
+                               _ptr(out))
+    return out
+
+
+def sample_rays(origins, dirs, bmin, bmax, near, step, voxel, max_per_ray, mask=None):
+    """Parsimonious box sampling with occupancy compaction (orc_sample_rays).  Returns a dict
+    with ray_offsets [R+1] int32, t_near/t_far [R], xyz [S,3], delta, s_mid, s_len [S]
+    (float32: these are the float32 decisions and values the sampler defines)."""
+    o = _c(origins, np.float32).reshape(-1, 3)
+    d = _c(dirs, np.float32).reshape(-1, 3)
+    R = o.shape[0]
+    lo = _c(bmin, np.float32).reshape(3)
+    hi = _c(bmax, np.float32).reshape(3)
+    m = None if mask is None else _c(mask, np.uint8)
+    shape = np.zeros(3, np.int32) if m is None else np.array(m.shape, np.int32)
+    offs = np.zeros(R + 1, np.int32)
+    tn = np.zeros(R, np.float32)
+    tf = np.zeros(R, np.float32)
+    L = lib()
+    L.orc_sample_rays.restype = C.c_int64
+    args = (C.c_int32(R), _ptr(o), _ptr(d), _ptr(lo), _ptr(hi), C.c_float(near), C.c_float(step), C.c_float(voxel),
+            C.c_int32(max_per_ray), _ptr(m), _ptr(shape), _ptr(offs), _ptr(tn), _ptr(tf))
+    S = int(L.orc_sample_rays(*args, None, None, None, None))
+    xyz = np.zeros((S, 3), np.float32)
+    dl, sm, sl = (np.zeros(S, np.float32) for _ in range(3))
+    L.orc_sample_rays(*args, _ptr(xyz), _ptr(dl), _ptr(sm), _ptr(sl))
+    return dict(ray_offsets=offs, t_near=tn, t_far=tf, xyz=xyz, delta=dl, s_mid=sm, s_len=sl)

@@ -1030,3 +1030,135 @@ double orc_tv(const orc_grid *g, double weight, double delta, int32_t dense, dou
             }
     return scale * loss;
 }
+
+/* ------------------------------------------------------------------ sample producer */
+
+/* Occupancy mask update.  Section 1: as training goes on, a mask gradually switches off
+ * space of low density so that most point queries can be skipped.  Readings: a vertex is
+ * dense when the alpha of its own density logit at the sampling step reaches alpha_thr
+ * (alpha = 1 - exp(-softplus(raw + b) delta), the activation of section 5.4); a vertex stays
+ * active only if it was active and some vertex of its 3x3x3 neighbourhood (clipped at the
+ * grid faces) is dense.  The active set therefore only shrinks, and because of the one-vertex
+ * dilation every cell that touches a dense vertex has all its eight vertices active.
+ * mask: [nx][ny][nz] bytes, non-zero = active; rewritten as 0/1.  Double precision, straight
+ * from the definition (expm1 keeps small alphas exact). */
+void orc_occupancy_update(const orc_grid *dens, double act_shift, double delta, double alpha_thr, uint8_t *mask)
+{
+    const int64_t nx = dens->n[0], ny = dens->n[1], nz = dens->n[2], N = nx * ny * nz;
+    uint8_t *is_dense = (uint8_t *)malloc((size_t)N);
+    for (int64_t i = 0; i < N; ++i) {
+        const double sigma = softplus((double)dens->data[i * dens->cs] + act_shift);
+        const double alpha = -expm1(-sigma * delta);
+        is_dense[i] = alpha >= alpha_thr;
+    }
+    for (int64_t x = 0; x < nx; ++x)
+        for (int64_t y = 0; y < ny; ++y)
+            for (int64_t z = 0; z < nz; ++z) {
+                const int64_t i = (x * ny + y) * nz + z;
+                int near_dense = 0;
+                for (int64_t a = x - 1; a <= x + 1; ++a)
+                    for (int64_t b = y - 1; b <= y + 1; ++b)
+                        for (int64_t c = z - 1; c <= z + 1; ++c)
+                            if (a >= 0 && a < nx && b >= 0 && b < ny && c >= 0 && c < nz)
+                                near_dense |= is_dense[(a * ny + b) * nz + c];
+                mask[i] = (mask[i] != 0) && near_dense;
+            }
+    free(is_dense);
+}
+
+/* Ray/box clip of one ray by the slab method; returns the number of candidate samples.
+ * Every step is one float32 operation rounded on its own (see orc_sample_rays). */
+static int32_t clip_and_count(const float *o, const float *d, const float *bmin, const float *bmax, float near,
+                              float step, int32_t max_per_ray, float *t_near, float *t_exit)
+{
+    float enter = -INFINITY, leave = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        float lo, hi;
+        if (d[a] != 0.0f) {
+            const float t0 = (bmin[a] - o[a]) / d[a];
+            const float t1 = (bmax[a] - o[a]) / d[a];
+            lo = t0 < t1 ? t0 : t1;
+            hi = t0 < t1 ? t1 : t0;
+        } else if (bmin[a] <= o[a] && o[a] <= bmax[a]) {
+            lo = -INFINITY;
+            hi = INFINITY;
+        } else {
+            lo = INFINITY;
+            hi = -INFINITY;
+        }
+        if (lo > enter) enter = lo;
+        if (hi < leave) leave = hi;
+    }
+    const float tn = enter > near ? enter : near;
+    *t_near = tn;
+    *t_exit = leave;
+    if (!(leave > tn)) return 0;
+    /* samples at t_k = t_near + (k + 1/2) step for every k >= 0 with t_k < t_exit */
+    const float c = (leave - tn) / step - 0.5f;
+    if (!(c > 0.0f)) return 0;
+    if (c > (float)max_per_ray) return max_per_ray;
+    return (int32_t)ceilf(c);
+}
+
+/* Nearest vertex of point x on the occupancy grid (clamped to the grid). */
+static int64_t nearest_vertex(const float *x, const float *bmin, const float *bmax, const int32_t *n)
+{
+    int64_t idx[3];
+    for (int a = 0; a < 3; ++a) {
+        const float sc = (float)(n[a] - 1) / (bmax[a] - bmin[a]);
+        const float u = (x[a] - bmin[a]) * sc;
+        if (!(u >= 0.0f)) idx[a] = 0;
+        else if (u >= (float)(n[a] - 1)) idx[a] = n[a] - 1;
+        else idx[a] = (int64_t)rintf(u);
+    }
+    return (idx[0] * n[1] + idx[1]) * n[2] + idx[2];
+}
+
+/* Parsimonious sampling with occupancy compaction.  Section 3 (re-implemented rendering
+ * utilities): points are placed only where the ray crosses the scene box (bounded scenes);
+ * section 1: points in switched-off space are skipped.  Readings, all taken in float32 with
+ * each operation rounded on its own (round to nearest even), because these decisions produce
+ * integers (sample counts, offsets):
+ *   - the ray's box interval by the slab method, per axis (bmin - o)/d and (bmax - o)/d
+ *     (an axis with d = 0 is unbounded if o lies within its slab, else empty); t_near is the
+ *     larger of the entry and `near`; the ray misses when the exit is not beyond t_near;
+ *   - candidate k (k = 0, 1, ...) is the interval [t_near + k step, t_near + (k+1) step] at its
+ *     midpoint t_k = fma(k + 1/2, step, t_near); candidates run while t_k < t_exit, i.e.
+ *     n = ceil((t_exit - t_near)/step - 1/2), capped at max_per_ray;
+ *   - its point is x = fma(t_k, d, o) per axis; it is kept when the occupancy mask is set at
+ *     the nearest vertex, u = (x - bmin) (n_a - 1)/(bmax - bmin) rounded to nearest even and
+ *     clamped to the grid (mask NULL keeps every candidate);
+ *   - a kept candidate carries delta = step / voxel, s_mid = (k + 1/2)/n, s_len = 1/n: s is
+ *     linear in t over the n candidate intervals of the unmasked ray.
+ * Rays are laid out in order, each ray's samples in increasing k.  Writes ray_offsets [R+1],
+ * t_near and t_far [R] (the box interval; both 0 for a ray that misses), and, when xyz is not
+ * NULL, the samples (arrays sized by the return value, the total).  Returns the total. */
+int64_t orc_sample_rays(int32_t R, const float *o, const float *d, const float *bmin, const float *bmax, float near,
+                        float step, float voxel, int32_t max_per_ray, const uint8_t *mask, const int32_t *mshape,
+                        int32_t *offs, float *t_near, float *t_far, float *xyz, float *delta, float *s_mid,
+                        float *s_len)
+{
+    int64_t total = 0;
+    offs[0] = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        float tn, te;
+        const int32_t n = clip_and_count(o + 3 * r, d + 3 * r, bmin, bmax, near, step, max_per_ray, &tn, &te);
+        t_near[r] = te > tn ? tn : 0.0f;
+        t_far[r] = te > tn ? te : 0.0f;
+        for (int32_t k = 0; k < n; ++k) {
+            const float t = fmaf((float)k + 0.5f, step, tn);
+            float x[3];
+            for (int a = 0; a < 3; ++a) x[a] = fmaf(t, d[3 * r + a], o[3 * r + a]);
+            if (mask && !mask[nearest_vertex(x, bmin, bmax, mshape)]) continue;
+            if (xyz) {
+                for (int a = 0; a < 3; ++a) xyz[3 * total + a] = x[a];
+                delta[total] = step / voxel;
+                s_mid[total] = ((float)k + 0.5f) / (float)n;
+                s_len[total] = 1.0f / (float)n;
+            }
+            ++total;
+        }
+        offs[r + 1] = (int32_t)total;
+    }
+    return total;
+}
