@@ -369,6 +369,63 @@ def tv_leg(ops, st, torch, reps=20):
     return res
 
 
+def sampler_leg(ops, torch, wl, steps=20, reps=20):
+    """GPU sample producer on the step's scene (sections 1 and 3): occupancy update of the
+    160^3 density (alpha >= 1e-3 at a half-voxel step, 27-neighbour dilation), then box
+    clipping + compaction of the step's rays at a half-voxel step through that mask, then
+    training steps (graph replays) on the produced batch.  Compulsory bytes: occupancy 4 B of
+    density + 2 B of mask per vertex; producer 24 B per ray + 24 B per emitted sample (mask
+    lookups hit L2)."""
+    from paper_2206_05085_amd.step import TrainStep
+    st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                   mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight)
+    nx, ny, nz = wl.density.data.shape[:3]
+    N = nx * ny * nz
+    voxel = wl.density.voxel_size()
+    mask = torch.ones(N, dtype=torch.uint8, device="cuda")
+
+    def timed(f, n):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    occ_ms = timed(lambda: st.update_occupancy(mask, 1e-3, 0.5), reps)   # idempotent on a fixed density
+    active = float(mask.float().mean().item())
+    og = torch.as_tensor(wl.rays.origins).cuda().contiguous()
+    dg = torch.as_tensor(wl.rays.dirs).cuda().contiguous()
+    R = og.shape[0]
+    res = {"occupancy": {"grid": [nx, ny, nz], "alpha_thr": 1e-3, "delta": 0.5, "active_fraction": round(active, 4),
+                         "ms": round(occ_ms, 4), "GB/s": round(6 * N / (occ_ms * 1e-3) / 1e9, 1)}}
+    for name, m in (("unmasked", None), ("masked", mask.view(nx, ny, nz))):
+        spec = ops.SamplerSpec(wl.density.xyz_min, wl.density.xyz_max, 0.5 * voxel, voxel, 0.0, 4096, m)
+        offs = ops.sample_count(spec, og, dg)
+        S = int(offs[-1].item())
+        out = ops.sample_emit(spec, og, dg, offs, S)
+
+        def produce():
+            ops.sample_count(spec, og, dg, ray_offsets=offs)
+            ops.sample_emit(spec, og, dg, offs, S, out=out)
+        ms = timed(produce, reps)
+        res[name] = {"rays": R, "samples": S, "ms": round(ms, 4), "samples_per_s": round(S / (ms * 1e-3), 1),
+                     "GB/s": round((24 * R + 24 * S) / (ms * 1e-3) / 1e9, 1)}
+        if m is not None:
+            st.bind(out, dg, wl.target)
+            g = st.capture(warmup=1)
+            step_ms = timed(g.replay, steps)
+            res[name]["step_ms_graph"] = round(step_ms, 4)
+            res[name]["step_samples_per_s"] = round(S / (step_ms * 1e-3), 1)
+            res[name]["produce_plus_step_ms"] = round(step_ms + ms, 4)
+    res["workload"] = (f"{R} pinhole rays through the 160^3 blob scene, step 0.5 voxel, occupancy from the density "
+                       f"(alpha >= 1e-3 at 0.5 voxel)")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,6 +439,7 @@ def main():
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=1500)
     ap.add_argument("--no-tv", action="store_true")
+    ap.add_argument("--no-sampler", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="end with a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -505,6 +563,9 @@ def main():
     if not args.no_tv:
         print("[bench] total-variation gradients", file=sys.stderr, flush=True)
         out["tv"] = tv_leg(ops, st, torch)
+    if not args.no_sampler:
+        print("[bench] GPU sample producer + occupancy mask", file=sys.stderr, flush=True)
+        out["sampler"] = sampler_leg(ops, torch, wl)
     if not args.no_ragged:
         print("[bench] ragged unbounded batch: schedules", file=sys.stderr, flush=True)
         out["ragged"] = ragged_leg(log=True)

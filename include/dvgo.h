@@ -331,6 +331,64 @@ int dvgo_resample(const dvgo_rays *rays, const float *prob, const float *entropy
                   const int32_t *ray_offsets, int32_t n_fine, int32_t n_plain, float voxel, float *xyz, float *delta,
                   float *s_mid, float *s_len, void *stream);
 
+/* ------------------------------------------------------------------ sample producer
+ * Builds the ragged batch on the device from rays: points are placed only where a ray
+ * crosses the scene box (section 3, re-implemented rendering utilities; bounded scenes), and
+ * points in space switched off by the occupancy mask are skipped (section 1).
+ *
+ * Definition (every step one float32 operation rounded to nearest even, no fused forms
+ * except the two fma below; any IEEE float32 evaluation of these steps gives the same
+ * integers):
+ *   box interval: per axis t0 = (xyz_min - o)/d, t1 = (xyz_max - o)/d, [min, max] of the two
+ *     (an axis with d == 0 is unbounded if xyz_min <= o <= xyz_max, else empty); t_exit = the
+ *     smallest upper end, t_near = max(largest lower end, near); the ray misses unless
+ *     t_exit > t_near;
+ *   candidates: n = ceil((t_exit - t_near)/step - 0.5) (0 if that is not positive), capped at
+ *     max_per_ray; candidate k = 0..n-1 is the interval [t_near + k step, t_near + (k+1) step]
+ *     at its midpoint t_k = fma(k + 0.5, step, t_near), point x = fma(t_k, d, o) per axis;
+ *   mask: candidate kept iff mask[i][j][l] != 0 at the nearest vertex, per axis
+ *     u = (x - xyz_min) * ((mask_shape - 1)/(xyz_max - xyz_min)), rounded to nearest even,
+ *     clamped to [0, mask_shape - 1] (u < 0 or NaN -> 0);
+ *   kept candidate: xyz = x, delta = step/voxel, s_mid = (k + 0.5)/n, s_len = 1/n (s linear in
+ *     t over the ray's n candidate intervals); rays in order, each ray's samples by k.
+ * Directions should be unit vectors for `step` to be a distance (not checked). */
+typedef struct dvgo_sampler {
+    uint32_t struct_size;
+    float xyz_min[3];       /* scene box; also the box of the mask's vertex grid */
+    float xyz_max[3];
+    float near;             /* samples start at t >= near (finite) */
+    float step;             /* spacing of candidates along t (> 0) */
+    float voxel;            /* world size of a voxel (> 0): every sample's delta = step / voxel */
+    int32_t max_per_ray;    /* 1 .. 2^20; max_per_ray * n_rays must be < 2^31 */
+    int32_t mask_shape[3];  /* vertex grid of the mask, entries >= 1, product < 2^31 */
+    const uint8_t *mask;    /* [nx][ny][nz] bytes, non-zero = active; NULL = every point active */
+} dvgo_sampler;
+
+/* Counts kept samples per ray and writes ray_offsets [n_rays+1] (exclusive prefix, int32;
+ * ray_offsets[n_rays] = total, which the caller reads to size the emit outputs).  t_near,
+ * t_far [n_rays] (each may be NULL) receive the box interval, (0, 0) for a ray that misses.
+ * origins, dirs [n_rays,3]. */
+int dvgo_sample_count(const dvgo_sampler *sp, int32_t n_rays, const float *origins, const float *dirs,
+                      int32_t *ray_offsets, float *t_near, float *t_far, void *stream);
+
+/* Writes the kept samples of the batch laid out by dvgo_sample_count (same sampler, rays and
+ * mask contents): xyz [capacity,3], delta, s_mid, s_len [capacity].  Samples whose index
+ * falls outside [0, capacity) are dropped, never written. */
+int dvgo_sample_emit(const dvgo_sampler *sp, int32_t n_rays, const float *origins, const float *dirs,
+                     const int32_t *ray_offsets, int64_t capacity, float *xyz, float *delta, float *s_mid,
+                     float *s_len, void *stream);
+
+/* Occupancy mask update (section 1: low-density space is switched off as training goes
+ * on).  A vertex is dense when the alpha of its own density logit at the sampling step,
+ * 1 - exp(-softplus(raw + act_shift) * delta), is at least alpha_thr; mask[v] (bytes over the
+ * density grid's vertices [nx][ny][nz]) becomes 1 iff it was non-zero and some vertex of its
+ * 3x3x3 neighbourhood (clipped at the faces) is dense, else 0.  The active set only shrinks;
+ * the dilation keeps all eight vertices of every cell that touches a dense vertex active.
+ * The alpha test is evaluated as raw >= (the smallest float32 logit that passes it).
+ * Needs delta > 0, 0 <= alpha_thr < 1; uses channel 0 of the density grid. */
+int dvgo_occupancy_update(const dvgo_grid *density, float act_shift, float delta, float alpha_thr, uint8_t *mask,
+                          void *stream);
+
 #ifdef __cplusplus
 }
 #endif

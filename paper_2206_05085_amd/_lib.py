@@ -57,8 +57,14 @@ class Proposal(C.Structure):
                 ("W", VP * 4), ("b", VP * 4), ("gW", VP * 4), ("gb", VP * 4)]
 
 
+class Sampler(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("xyz_min", C.c_float * 3), ("xyz_max", C.c_float * 3),
+                ("near", C.c_float), ("step", C.c_float), ("voxel", C.c_float), ("max_per_ray", C.c_int32),
+                ("mask_shape", C.c_int32 * 3), ("mask", VP)]
+
+
 _I32, _I64, _F, _SZP = C.c_int32, C.c_int64, C.c_float, C.POINTER(C.c_size_t)
-_PR, _PQ = C.POINTER(Rays), C.POINTER(Proposal)
+_PR, _PQ, _PSM = C.POINTER(Rays), C.POINTER(Proposal), C.POINTER(Sampler)
 _PG, _PS, _PP, _PM = C.POINTER(Grid), C.POINTER(Samples), C.POINTER(RenderParams), C.POINTER(ColorMLP)
 
 SIGNATURES = {
@@ -89,6 +95,9 @@ SIGNATURES = {
     "dvgo_histogram": (C.c_int, [_I32, VP, VP, VP, _I32, _F, VP, VP]),
     "dvgo_resample_offsets": (C.c_int, [_PR, VP, _F, _I32, _I32, VP, VP]),
     "dvgo_resample": (C.c_int, [_PR, VP, VP, _F, VP, _I32, _I32, _F, VP, VP, VP, VP, VP]),
+    "dvgo_sample_count": (C.c_int, [_PSM, _I32, VP, VP, VP, VP, VP, VP]),
+    "dvgo_sample_emit": (C.c_int, [_PSM, _I32, VP, VP, VP, _I64, VP, VP, VP, VP, VP]),
+    "dvgo_occupancy_update": (C.c_int, [_PG, _F, _F, _F, VP, VP]),
 }
 
 _lib = None

@@ -11,12 +11,14 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, ColorMLP, Grid, Proposal, Rays, RenderParams, Samples, call
+from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, ColorMLP, Grid, Proposal, Rays, RenderParams, Sampler, Samples,
+                   call)
 
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
            "grid_scatter", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
+           "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
            "COLOR_GRID", "COLOR_SAMPLES"]
 
 
@@ -540,3 +542,85 @@ def resample(rays: RayBatch, prob, entropy, tau, ray_offsets, n_samples, voxel, 
     call("dvgo_resample", ctypes.byref(r), _p(prob), _p(entropy), tau, _p(ray_offsets), n_fine, n_plain, voxel,
          _p(xyz), _p(dl), _p(sm), _p(sl), _stream())
     return SampleBatch(ray_offsets, xyz, dl, sm, sl, R, int(n_samples))
+
+
+# ------------------------------------------------------------------ sample producer
+
+
+@dataclass
+class SamplerSpec:
+    """Scene box, spacing and occupancy mask of the sample producer (dvgo_sampler)."""
+    xyz_min: Sequence[float]
+    xyz_max: Sequence[float]
+    step: float
+    voxel: float
+    near: float = 0.0
+    max_per_ray: int = 4096
+    mask: Optional[torch.Tensor] = None  # uint8 [nx, ny, nz] on the GPU, or None (all active)
+
+    def struct(self) -> Sampler:
+        sp = Sampler()
+        sp.struct_size = C_size(Sampler)
+        sp.xyz_min[:] = [float(v) for v in self.xyz_min]
+        sp.xyz_max[:] = [float(v) for v in self.xyz_max]
+        sp.near, sp.step, sp.voxel = float(self.near), float(self.step), float(self.voxel)
+        sp.max_per_ray = int(self.max_per_ray)
+        if self.mask is not None:
+            _chk(self.mask, "mask", torch.uint8)
+            if self.mask.dim() != 3:
+                raise ValueError("mask must be [nx, ny, nz]")
+            sp.mask_shape[:] = list(self.mask.shape)
+            sp.mask = _p(self.mask)
+        return sp
+
+
+def _rays(origins, dirs):
+    _chk(origins, "origins", last=3)
+    R = origins.numel() // 3
+    _chk(dirs, "dirs", numel=3 * R)
+    return R
+
+
+def sample_count(spec: SamplerSpec, origins, dirs, ray_offsets=None, t_near=None, t_far=None):
+    """Kept samples per ray as ray_offsets [R+1] (int32, exclusive prefix); optional box interval."""
+    R = _rays(origins, dirs)
+    dev = origins.device
+    if ray_offsets is None:
+        ray_offsets = torch.empty(R + 1, dtype=torch.int32, device=dev)
+    _chk(ray_offsets, "ray_offsets", torch.int32, R + 1)
+    for name, t in (("t_near", t_near), ("t_far", t_far)):
+        if t is not None:
+            _chk(t, name, numel=R)
+    call("dvgo_sample_count", spec.struct(), R, _p(origins), _p(dirs), _p(ray_offsets), _p(t_near), _p(t_far),
+         _stream())
+    return ray_offsets
+
+
+def sample_emit(spec: SamplerSpec, origins, dirs, ray_offsets, n_samples: int, out=None) -> SampleBatch:
+    """Fills the batch laid out by sample_count; n_samples = ray_offsets[R] (the capacity)."""
+    R = _rays(origins, dirs)
+    dev = origins.device
+    _chk(ray_offsets, "ray_offsets", torch.int32, R + 1)
+    if out is None:
+        out = SampleBatch(ray_offsets, torch.empty(n_samples, 3, device=dev), torch.empty(n_samples, device=dev),
+                          torch.empty(n_samples, device=dev), torch.empty(n_samples, device=dev), R, n_samples)
+    for name in ("xyz", "delta", "s_mid", "s_len"):
+        _chk(getattr(out, name), name, numel=n_samples * (3 if name == "xyz" else 1))
+    call("dvgo_sample_emit", spec.struct(), R, _p(origins), _p(dirs), _p(ray_offsets), int(n_samples), _p(out.xyz),
+         _p(out.delta), _p(out.s_mid), _p(out.s_len), _stream())
+    return out
+
+
+def sample_rays(spec: SamplerSpec, origins, dirs) -> SampleBatch:
+    """Count, read the total (one 4-byte device-to-host copy, which synchronises), emit."""
+    offs = sample_count(spec, origins, dirs)
+    total = int(offs[-1].item())
+    return sample_emit(spec, origins, dirs, offs, total)
+
+
+def occupancy_update(density: DeviceGrid, act_shift_: float, delta: float, alpha_thr: float, mask):
+    """In place: mask &= 27-neighbour dilation of (alpha of the vertex logit at step delta >= alpha_thr)."""
+    g = density.struct()
+    _chk(mask, "mask", torch.uint8, g.nx * g.ny * g.nz)
+    call("dvgo_occupancy_update", g, float(act_shift_), float(delta), float(alpha_thr), _p(mask), _stream())
+    return mask

@@ -86,6 +86,18 @@ class TrainStep:
             self.mlp_ws = torch.empty(max(ops.mlp_workspace_size(self.mlp, R, S), 1), dtype=torch.uint8, device=d)
         return self
 
+    def bind_rays(self, spec: ops.SamplerSpec, origins, dirs, target):
+        """Produce the batch on the GPU from rays (box clipping + occupancy compaction with
+        spec.mask) and bind it.  Reads the sample total back to the host (one small copy)."""
+        o = torch.as_tensor(origins).to(self.device, torch.float32).contiguous()
+        d = torch.as_tensor(dirs).to(self.device, torch.float32).contiguous()
+        return self.bind(ops.sample_rays(spec, o, d), d, target)
+
+    def update_occupancy(self, mask, alpha_thr: float = 1e-3, delta: float = 0.5):
+        """Switch off mask vertices whose 3x3x3 neighbourhood has no density logit with alpha
+        >= alpha_thr at a step of delta voxels (mask: uint8 over the density grid, in place)."""
+        return ops.occupancy_update(self.grid("density"), self.shift, delta, alpha_thr, mask)
+
     def tune(self, longest_first: bool = True):
         """Pick the render kernels' launch shape with the library's autotuner (on the bound
         batch; call outside graph capture).  Returns (Schedule, ms of render fwd + bwd)."""

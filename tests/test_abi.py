@@ -42,14 +42,15 @@ def test_abi_version(L):
 def test_struct_layouts_match_header(L, tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "dvgo.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dvgo_grid), sizeof(dvgo_samples),'
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(dvgo_grid), sizeof(dvgo_samples),'
                    'sizeof(dvgo_render_params), sizeof(dvgo_color_mlp), offsetof(dvgo_grid, data),'
-                   'offsetof(dvgo_color_mlp, gW1));return 0;}\n')
+                   'offsetof(dvgo_color_mlp, gW1), sizeof(dvgo_sampler), offsetof(dvgo_sampler, mask));'
+                   'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(L.Grid), C.sizeof(L.Samples), C.sizeof(L.RenderParams), C.sizeof(L.ColorMLP),
-            L.Grid.data.offset, L.ColorMLP.gW1.offset]
+            L.Grid.data.offset, L.ColorMLP.gW1.offset, C.sizeof(L.Sampler), L.Sampler.mask.offset]
     assert got == want
 
 
@@ -135,6 +136,39 @@ def test_validation_errors(L):
     assert lib.dvgo_tv_add_grad(C.byref(t), 1.0, 0.0, 1, None) == -3
     t.grad = 68
     assert lib.dvgo_tv_add_grad(C.byref(t), 1.0, 1.0, 1, None) == -2
+    # sample producer: NULL sampler, struct size, bad box, step, cap, int32 overflow, capacity
+    assert lib.dvgo_sample_count(None, 4, 64, 64, 64, None, None, None) == -1
+    sp = L.Sampler()
+    sp.struct_size = 5
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -8
+    sp.struct_size = C.sizeof(L.Sampler)
+    sp.xyz_min[:] = [-1, -1, -1]
+    sp.xyz_max[:] = [1, 1, -1]
+    sp.step, sp.voxel, sp.max_per_ray = 0.01, 0.02, 512
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -2
+    sp.xyz_max[:] = [1, 1, 1]
+    assert lib.dvgo_sample_count(C.byref(sp), 4, None, 64, 64, None, None, None) == -1
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, None, None, None, None) == -1
+    sp.step = 0.0
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -3
+    sp.step, sp.max_per_ray = 0.01, 0
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -3
+    sp.max_per_ray = 1 << 20
+    assert lib.dvgo_sample_count(C.byref(sp), 4096, 64, 64, 64, None, None, None) == -3
+    assert "2^31" in _err(L)
+    sp.max_per_ray = 512
+    sp.mask = 64
+    sp.mask_shape[:] = [4, 0, 4]
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -2
+    sp.mask_shape[:] = [4, 4, 4]
+    assert lib.dvgo_sample_emit(C.byref(sp), 4, 64, 64, 64, -1, 64, 64, 64, 64, None) == -2
+    assert lib.dvgo_sample_emit(C.byref(sp), 4, 64, 64, 64, 10, None, 64, 64, 64, None) == -1
+    # occupancy update: NULL mask, delta, threshold range
+    assert lib.dvgo_occupancy_update(C.byref(t), -8.5, 0.5, 1e-3, None, None) == -1
+    t.ch_stride, t.channels = 1, 1
+    assert lib.dvgo_occupancy_update(C.byref(t), -8.5, 0.0, 1e-3, 64, None) == -3
+    assert lib.dvgo_occupancy_update(C.byref(t), -8.5, 0.5, 1.0, 64, None) == -3
+    assert lib.dvgo_occupancy_update(C.byref(t), -8.5, 0.5, -0.1, 64, None) == -3
     # sizes
     assert lib.dvgo_render_state_size(8192, 10 ** 6, C.byref(out)) == 0 and out.value > 0
     assert lib.dvgo_render_state_size(-1, 0, C.byref(out)) == -2
