@@ -8,6 +8,9 @@ and wraps it with numpy.  It shares nothing with the HIP library.
 Parity status per function (pins live in ``tests/test_oracle_*.py``):
 
 * gather / scatter: pinned (linear-field reproduction, vertex values, adjoint identity).
+  Through the unbounded-scene contraction (Eq. 4, p = inf and 2): pinned (identity-field
+  reproduction of an independent Eq. 4, its radius law and direction, continuity at the unit
+  sphere, the limit radius, the plain lookup inside, the warped adjoint identity).
 * distortion (Eq. 1) and its gradient: pinned (closed forms, the paper's O(N) rewrite,
   2-homogeneity, shift and reflection invariance, Euler identity, finite differences).
 * render forward / backward: pinned (closed-form constant-density ray, invariants,
@@ -60,7 +63,7 @@ def build_lib(force: bool = True) -> str:
 
 class OrcGrid(C.Structure):
     _fields_ = [("data", VP), ("n", C.c_int32 * 3), ("cs", C.c_int32), ("C", C.c_int32),
-                ("bmin", C.c_float * 3), ("bmax", C.c_float * 3)]
+                ("bmin", C.c_float * 3), ("bmax", C.c_float * 3), ("warp", C.c_int32), ("wb", C.c_double)]
 
 
 class OrcMLP(C.Structure):
@@ -118,6 +121,8 @@ def grid_struct(grid, keep):
     g.C = int(data.shape[3])
     g.bmin[:] = [float(v) for v in grid.xyz_min]
     g.bmax[:] = [float(v) for v in grid.xyz_max]
+    g.warp = int(getattr(grid, "warp", 0))
+    g.wb = float(getattr(grid, "warp_b", 1.0))
     return g
 
 

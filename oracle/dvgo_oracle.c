@@ -31,6 +31,8 @@ typedef struct {
     int32_t cs;          /* floats per vertex */
     int32_t C;           /* channels used */
     float bmin[3], bmax[3];
+    int32_t warp;        /* 0: points index the box directly; 1, 2: Eq. 4 contraction, p = inf, 2 */
+    double wb;           /* b of Eq. 4 */
 } orc_grid;
 
 int orc_version(void) { return ORC_VERSION; }
@@ -54,17 +56,38 @@ static double sigmoid(double z)
 
 /* ------------------------------------------------------------------ interpolation */
 
+/* Eq. 4, the parameterisation of unbounded scenes (section 5.5): a point inside the unit
+ * p-ball is kept; a point outside is moved along its own direction to the radius
+ * 1 + b - b/||x||_p, so all of space lands inside the p-ball of radius 1 + b, which the
+ * grid's box [-1-b, 1+b]^3 covers.  p = inf (warp 1) or p = 2 (warp 2). */
+static void contract(int32_t warp, double b, const double x[3], double out[3])
+{
+    double n;
+    if (warp == 1) {
+        n = fabs(x[0]);
+        if (fabs(x[1]) > n) n = fabs(x[1]);
+        if (fabs(x[2]) > n) n = fabs(x[2]);
+    } else {
+        n = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    }
+    const double s = n <= 1.0 ? 1.0 : (1.0 + b - b / n) / n;
+    for (int a = 0; a < 3; ++a) out[a] = x[a] * s;
+}
+
 /* Trilinear interpolation on a vertex grid whose corner vertices sit on the box corners
  * (the paper queries its grids through a library routine, section 4; reading: vertex i is
  * at bmin + i (bmax - bmin)/(n - 1)).  A coordinate is clamped to the box, and a point on
- * the upper face uses the last cell with fraction 1.  Corner c = 4 dx + 2 dy + dz. */
+ * the upper face uses the last cell with fraction 1.  Corner c = 4 dx + 2 dy + dz.  A grid
+ * with a warp is addressed at the contracted point (Eq. 4) instead of the point itself. */
 static void corners(const orc_grid *g, const float *p, int64_t idx[8], double wt[8])
 {
     int64_t i0[3];
     double f[3];
+    double x[3] = {p[0], p[1], p[2]};
+    if (g->warp) contract(g->warp, g->wb, x, x);
     for (int a = 0; a < 3; ++a) {
         double lo = g->bmin[a], hi = g->bmax[a];
-        double u = ((double)p[a] - lo) / (hi - lo) * (double)(g->n[a] - 1);
+        double u = (x[a] - lo) / (hi - lo) * (double)(g->n[a] - 1);
         if (!(u > 0.0)) u = 0.0; /* also maps NaN to 0 */
         if (u > g->n[a] - 1) u = g->n[a] - 1;
         int64_t i = (int64_t)floor(u);

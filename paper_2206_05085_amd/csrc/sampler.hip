@@ -193,25 +193,42 @@ __global__ __launch_bounds__(256) void sample_emit_kernel(SamplerArgs a, int R, 
 }
 
 // mask[v] = mask[v] && (some vertex of the 3x3x3 neighbourhood has raw >= thr); thr is the
-// smallest float32 logit whose alpha at the sampling step reaches the alpha threshold
+// smallest float32 logit whose alpha at the sampling step reaches the alpha threshold.  A
+// thread owns OCC_Z consecutive z vertices of one (x, y) column: it ORs the dense test over
+// the 3x3 (x, y) neighbours for z0-1 .. z0+OCC_Z, then each output ORs three of those.
+constexpr int OCC_Z = 4;
+
 __global__ __launch_bounds__(256) void occupancy_kernel(const float *raw, int cs, int nx, int ny, int nz, float thr,
                                                         uint8_t *mask) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t N = (int64_t)nx * ny * nz;
-    if (v >= N) return;
-    const int z = (int)(v % nz);
-    const int y = (int)((v / nz) % ny);
-    const int x = (int)(v / ((int64_t)ny * nz));
-    bool active = mask[v] != 0;
-    if (active) {
-        bool near_dense = false;
-        for (int a = x > 0 ? x - 1 : 0; a <= (x + 1 < nx ? x + 1 : nx - 1); ++a)
-            for (int b = y > 0 ? y - 1 : 0; b <= (y + 1 < ny ? y + 1 : ny - 1); ++b)
-                for (int c = z > 0 ? z - 1 : 0; c <= (z + 1 < nz ? z + 1 : nz - 1); ++c)
-                    near_dense |= raw[(((int64_t)a * ny + b) * nz + c) * cs] >= thr;
-        active = near_dense;
+    const int nq = (nz + OCC_Z - 1) / OCC_Z;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nx * ny * nq) return;
+    const int q = t % nq;
+    const int y = (t / nq) % ny;
+    const int x = t / (nq * ny);
+    const int z0 = q * OCC_Z;
+    const int64_t row = ((int64_t)x * ny + y) * nz;
+    uint8_t m[OCC_Z];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < OCC_Z; ++j) {
+        m[j] = z0 + j < nz ? mask[row + z0 + j] : 0;
+        any |= m[j] != 0;
     }
-    mask[v] = active ? 1 : 0;
+    if (!any) return;  // already 0 everywhere: nothing to switch off
+    bool col[OCC_Z + 2] = {};
+    for (int a = x > 0 ? x - 1 : 0; a <= (x + 1 < nx ? x + 1 : nx - 1); ++a)
+        for (int b = y > 0 ? y - 1 : 0; b <= (y + 1 < ny ? y + 1 : ny - 1); ++b) {
+            const float *p = raw + ((int64_t)a * ny + b) * nz * cs;
+#pragma unroll
+            for (int i = 0; i < OCC_Z + 2; ++i) {
+                const int z = z0 - 1 + i;
+                if (z >= 0 && z < nz) col[i] |= p[(int64_t)z * cs] >= thr;
+            }
+        }
+#pragma unroll
+    for (int j = 0; j < OCC_Z; ++j)
+        if (z0 + j < nz) mask[row + z0 + j] = (m[j] != 0 && (col[j] || col[j + 1] || col[j + 2])) ? 1 : 0;
 }
 
 int make_sampler(const dvgo_sampler *sp, int32_t n_rays, const float *org, const float *dir, SamplerArgs &a) {
@@ -306,8 +323,8 @@ extern "C" int dvgo_occupancy_update(const dvgo_grid *density, float act_shift, 
     if (!(alpha_thr >= 0.f && alpha_thr < 1.f)) return set_error(DVGO_ERR_RANGE, "alpha_thr must be in [0, 1)");
     if (!std::isfinite(act_shift)) return set_error(DVGO_ERR_RANGE, "act_shift must be finite");
     const float thr = logit_threshold(act_shift, delta, alpha_thr);
-    const int64_t N = (int64_t)dg.n[0] * dg.n[1] * dg.n[2];
-    hipLaunchKernelGGL(occupancy_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+    const int64_t threads = (int64_t)dg.n[0] * dg.n[1] * ((dg.n[2] + OCC_Z - 1) / OCC_Z);
+    hipLaunchKernelGGL(occupancy_kernel, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
                        dg.data, dg.cs, dg.n[0], dg.n[1], dg.n[2], thr, mask);
     return check_hip(hipGetLastError(), "occupancy_kernel launch");
 }

@@ -42,11 +42,15 @@ class Grid:
     """Dense vertex grid, channel-last: ``data[nx, ny, nz, C]`` (float32, C-contiguous).
 
     Vertices sit on the box corners: vertex i along an axis is at
-    ``xyz_min + i * (xyz_max - xyz_min) / (n - 1)``.
+    ``xyz_min + i * (xyz_max - xyz_min) / (n - 1)``.  ``warp`` says how points address
+    the box: 0 directly, 1 / 2 through the unbounded-scene contraction (Eq. 4) with
+    p = inf / 2 and parameter ``warp_b``.
     """
     data: np.ndarray
     xyz_min: np.ndarray
     xyz_max: np.ndarray
+    warp: int = 0
+    warp_b: float = 1.0
 
     @property
     def shape(self):
