@@ -266,7 +266,7 @@ def ragged_leg(R=8192, steps=20, log=None):
     smp = wl.samples
     S = smp.n_samples
     st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
-                   mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight)
+                   mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight, warp=(wl.density.warp, wl.density.warp_b))
     b = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
     st.bind(b, wl.rays.dirs, wl.target)
     st.forward()
@@ -303,6 +303,16 @@ def ragged_leg(R=8192, steps=20, log=None):
     ms_bucket = time_render(buckets)
     tuned, ms_tune = st.tune(longest_first=True)
     ms_tuned = time_render([tuned])
+    # the same samples contracted on the host and looked up on plain grids: the cost of the
+    # in-kernel contraction (Eq. 4) in the density lookups of render forward + backward
+    b_world = b
+    b = ops.SampleBatch.from_arrays(smp.ray_offsets, synth.scenes._contract_inf(smp.xyz.astype(np.float64)),
+                                    smp.delta, smp.s_mid, smp.s_len)
+    warp_saved = st.warp
+    st.warp = (0, 1.0)
+    ms_host_contracted = time_render([tuned])
+    st.warp = warp_saved
+    b = b_world
     say("render fwd+bwd ms: batch order %.3f, per-bucket %.3f, tuned %.3f (wpb %d, grid %d)"
         % (ms_plain, ms_bucket, ms_tuned, tuned.waves_per_block, tuned.grid_waves))
     st.density["g"].zero_()
@@ -319,7 +329,7 @@ def ragged_leg(R=8192, steps=20, log=None):
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / steps
     lens = smp.lengths()
-    return {"workload": f"320^3 contracted grids, {R} rays, lognormal lengths 32-1024 (S={S}, max {lens.max()})",
+    return {"workload": f"320^3 grids addressed through Eq. 4 (p = inf, b = 1), {R} rays, lognormal lengths 32-1024 (S={S}, max {lens.max()})",
             "render_fwd_bwd_ms": {"one_wave_per_ray_batch_order": round(ms_plain, 4),
                                   "per_length_bucket_launches": round(ms_bucket, 4),
                                   "autotuned_persistent_longest_first": round(ms_tuned, 4)},
@@ -327,6 +337,8 @@ def ragged_leg(R=8192, steps=20, log=None):
                                      "per_length_bucket_launches": round(S / (ms_bucket * 1e-3), 1),
                                      "autotuned_persistent_longest_first": round(S / (ms_tuned * 1e-3), 1)},
             "tuned_shape": {"waves_per_block": tuned.waves_per_block, "grid_waves": tuned.grid_waves},
+            "contraction": {"in_kernel_eq4_p_inf_ms": round(ms_tuned, 4),
+                            "host_contracted_points_ms": round(ms_host_contracted, 4)},
             "step_ms_graph": round(ms_step, 4), "step_samples_per_s": round(S / (ms_step * 1e-3), 1),
             "buckets": len(buckets)}
 

@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DVGO_ABI_VERSION 1
+#define DVGO_ABI_VERSION 2
 
 enum {
     DVGO_OK = 0,
@@ -53,12 +53,21 @@ enum {
 
 enum { DVGO_COLOR_GRID = 0, DVGO_COLOR_SAMPLES = 1, DVGO_COLOR_NONE = 2 };
 
+/* How points address a grid's box (dvgo_grid.warp).  NONE: directly.  CONTRACT_INF /
+ * CONTRACT_L2: through the unbounded-scene contraction of Eq. 4 (section 5.4), p = inf / 2. */
+enum { DVGO_WARP_NONE = 0, DVGO_WARP_CONTRACT_INF = 1, DVGO_WARP_CONTRACT_L2 = 2 };
+
 /* Dense vertex grid, channel-last: value (i,j,k,c) at data[((i*ny + j)*nz + k)*ch_stride + c].
  * Vertex i along x sits at xyz_min[0] + i*(xyz_max[0]-xyz_min[0])/(nx-1) (vertices on the box
  * corners).  A query point is clamped to the box; trilinear weights use the enclosing cell.
  * Requirements: nx,ny,nz >= 2; 1 <= channels <= ch_stride <= 16; xyz_max > xyz_min;
  * nx*ny*nz*ch_stride < 2^31.  `grad` (same layout) receives += in backward calls; it may be
- * NULL where a call does not write it. */
+ * NULL where a call does not write it.
+ * warp (DVGO_WARP_*) and warp_b: with a contraction, every lookup of this grid (gather,
+ * scatter, the renderer's density and colour lookups, alpha, the proposal's coarse pass)
+ * addresses the box at x' = x if ||x||_p <= 1, else (1 + b - b/||x||_p) x/||x||_p (Eq. 4,
+ * b = warp_b > 0), computed in double; the paper's box for it is [-1-b, 1+b]^3 (any box is
+ * accepted; points outside it clamp as usual).  Points (xyz) stay in world coordinates. */
 typedef struct dvgo_grid {
     uint32_t struct_size;
     int32_t nx, ny, nz;
@@ -68,6 +77,8 @@ typedef struct dvgo_grid {
     float xyz_max[3];
     const float *data;
     float *grad;
+    int32_t warp;
+    float warp_b;
 } dvgo_grid;
 
 /* Flattened ragged batch of samples (point queries) along rays.

@@ -9,13 +9,14 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdvgo.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 VP = C.c_void_p
 OK = 0
 ERRORS = {-1: "ERR_NULL", -2: "ERR_SHAPE", -3: "ERR_RANGE", -5: "ERR_WORKSPACE", -6: "ERR_HIP",
           -7: "ERR_UNSUPPORTED", -8: "ERR_ABI"}
 COLOR_GRID, COLOR_SAMPLES, COLOR_NONE = 0, 1, 2
+WARP_NONE, WARP_CONTRACT_INF, WARP_CONTRACT_L2 = 0, 1, 2
 
 
 class DvgoError(RuntimeError):
@@ -27,7 +28,7 @@ class DvgoError(RuntimeError):
 class Grid(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("channels", C.c_int32), ("ch_stride", C.c_int32), ("xyz_min", C.c_float * 3),
-                ("xyz_max", C.c_float * 3), ("data", VP), ("grad", VP)]
+                ("xyz_max", C.c_float * 3), ("data", VP), ("grad", VP), ("warp", C.c_int32), ("warp_b", C.c_float)]
 
 
 class Samples(C.Structure):

@@ -80,6 +80,9 @@ struct DevGrid {
     int C;   // channels used
     int sx, sy;  // strides (floats) of x and y; z stride is cs
     float s_hi[3], s_lo[3], o_hi[3], o_lo[3];
+    int warp;              // DVGO_WARP_*: 0 = points index the box directly
+    double wb;             // b of Eq. 4
+    double s_d[3], o_d[3]; // the index map u = x*s + o in double, for warped points
 };
 
 struct Tri {
@@ -110,12 +113,52 @@ __device__ __forceinline__ void axis_coord(float x, float shi, float slo, float 
     else { i0 = (int)fl; f = fr; }
 }
 
+// Cell index and fraction of a point addressed through the unbounded-scene contraction
+// (Eq. 4, p = inf or 2).  The contraction and the index map run in double, so the fraction
+// is accurate to float32 although the contracted point is a derived value; the clamping
+// matches axis_coord.
+__device__ __forceinline__ void warped_coords(const DevGrid &g, float x, float y, float z, int (&i)[3],
+                                              float (&f)[3]) {
+    double p[3] = {(double)x, (double)y, (double)z};
+    double n;
+    if (g.warp == DVGO_WARP_CONTRACT_INF) {
+        n = fabs(p[0]);
+        n = fabs(p[1]) > n ? fabs(p[1]) : n;
+        n = fabs(p[2]) > n ? fabs(p[2]) : n;
+    } else {
+        n = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    }
+    const double s = n > 1.0 ? (1.0 + g.wb - g.wb / n) / n : 1.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double u = p[a] * s * g.s_d[a] + g.o_d[a];
+        const double fl = floor(u);
+        if (!(fl >= 0.0)) { i[a] = 0; f[a] = 0.f; }              // below the box (or NaN)
+        else if (fl > (double)(g.n[a] - 2)) { i[a] = g.n[a] - 2; f[a] = 1.f; }
+        else { i[a] = (int)fl; f[a] = (float)(u - fl); }
+    }
+}
+
+// W: the kernel was built for grids with a warp (the double-precision contraction path costs
+// registers, so kernels for plain grids leave it out).
+template <bool W>
+__device__ __forceinline__ void grid_coords(const DevGrid &g, float x, float y, float z, int (&i)[3], float (&f)[3]) {
+    if (W && g.warp) {
+        warped_coords(g, x, y, z, i, f);
+        return;
+    }
+    axis_coord(x, g.s_hi[0], g.s_lo[0], g.o_hi[0], g.o_lo[0], g.n[0], i[0], f[0]);
+    axis_coord(y, g.s_hi[1], g.s_lo[1], g.o_hi[1], g.o_lo[1], g.n[1], i[1], f[1]);
+    axis_coord(z, g.s_hi[2], g.s_lo[2], g.o_hi[2], g.o_lo[2], g.n[2], i[2], f[2]);
+}
+
+template <bool W = false>
 __device__ __forceinline__ Tri trilinear(const DevGrid &g, float x, float y, float z) {
-    int ix, iy, iz;
-    float fx, fy, fz;
-    axis_coord(x, g.s_hi[0], g.s_lo[0], g.o_hi[0], g.o_lo[0], g.n[0], ix, fx);
-    axis_coord(y, g.s_hi[1], g.s_lo[1], g.o_hi[1], g.o_lo[1], g.n[1], iy, fy);
-    axis_coord(z, g.s_hi[2], g.s_lo[2], g.o_hi[2], g.o_lo[2], g.n[2], iz, fz);
+    int i[3];
+    float fr[3];
+    grid_coords<W>(g, x, y, z, i, fr);
+    const int ix = i[0], iy = i[1], iz = i[2];
+    const float fx = fr[0], fy = fr[1], fz = fr[2];
     Tri t;
     t.base = ix * g.sx + iy * g.sy + iz * g.cs;
     const float wx[2] = {1.f - fx, fx}, wy[2] = {1.f - fy, fy}, wz[2] = {1.f - fz, fz};
@@ -131,12 +174,12 @@ struct Cell {
     float fx, fy, fz;
 };
 
+template <bool W = false>
 __device__ __forceinline__ Cell cell_of(const DevGrid &g, float x, float y, float z) {
-    Cell c;
-    axis_coord(x, g.s_hi[0], g.s_lo[0], g.o_hi[0], g.o_lo[0], g.n[0], c.ix, c.fx);
-    axis_coord(y, g.s_hi[1], g.s_lo[1], g.o_hi[1], g.o_lo[1], g.n[1], c.iy, c.fy);
-    axis_coord(z, g.s_hi[2], g.s_lo[2], g.o_hi[2], g.o_lo[2], g.n[2], c.iz, c.fz);
-    return c;
+    int i[3];
+    float fr[3];
+    grid_coords<W>(g, x, y, z, i, fr);
+    return Cell{i[0], i[1], i[2], fr[0], fr[1], fr[2]};
 }
 
 __device__ __forceinline__ float corner_weight(const Cell &c, int dx, int dy, int dz) {

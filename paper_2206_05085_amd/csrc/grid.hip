@@ -51,7 +51,15 @@ int make_dev_grid(const dvgo_grid *g, const char *name, DevGrid *out, bool need_
         out->s_lo[a] = (float)(s - (double)out->s_hi[a]);
         out->o_hi[a] = (float)o;
         out->o_lo[a] = (float)(o - (double)out->o_hi[a]);
+        out->s_d[a] = s;
+        out->o_d[a] = o;
     }
+    if (g->warp != DVGO_WARP_NONE && g->warp != DVGO_WARP_CONTRACT_INF && g->warp != DVGO_WARP_CONTRACT_L2)
+        return set_error(DVGO_ERR_UNSUPPORTED, "%s: unknown warp %d", name, g->warp);
+    if (g->warp != DVGO_WARP_NONE && !(g->warp_b > 0.f && g->warp_b < 1e30f))
+        return set_error(DVGO_ERR_RANGE, "%s: the contraction's b must be positive and finite", name);
+    out->warp = g->warp;
+    out->wb = g->warp_b;
     return DVGO_OK;
 }
 
@@ -69,10 +77,11 @@ int grid_blocks(int64_t work, int per_block = kBlock) {
     return (int)(b < 1 ? 1 : b);
 }
 
+template <bool W>
 __global__ __launch_bounds__(kBlock) void gather_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
                                                         float *__restrict__ out) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < S; k += (int64_t)gridDim.x * kBlock) {
-        const Tri t = trilinear(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+        const Tri t = trilinear<W>(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
         float acc[16];
 #pragma unroll
         for (int ch = 0; ch < 16; ++ch) acc[ch] = 0.f;
@@ -108,7 +117,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(DevGrid g, int64_t S, co
 
 // One lane per sample, 64 consecutive samples per wave: consecutive samples lie along a
 // ray, so contributions to shared vertices are summed in the wave before the atomics.
-template <int NC>
+template <int NC, bool W>
 __global__ __launch_bounds__(kBlock) void scatter_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
                                                          const float *__restrict__ gout) {
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
@@ -121,7 +130,7 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(DevGrid g, int64_t S, c
 #pragma unroll
         for (int ch = 0; ch < NC; ++ch) v[ch] = 0.f;
         if (valid) {
-            cl = cell_of(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+            cl = cell_of<W>(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch)
                 if (ch < g.C) v[ch] = gout[k * g.C + ch];
@@ -135,15 +144,20 @@ void launch_scatter(const DevGrid &dg, int64_t S, const float *xyz, const float 
     int64_t waves = (S + 63) / 64;
     int64_t blocks = (waves + 3) / 4;
     if (blocks > 256 * 16) blocks = 256 * 16;
-    hipLaunchKernelGGL(scatter_kernel<NC>, dim3((unsigned)blocks), dim3(kBlock), scatter_lds_bytes(NC, kBlock), st, dg,
-                       S, xyz, gout);
+    if (dg.warp)
+        hipLaunchKernelGGL((scatter_kernel<NC, true>), dim3((unsigned)blocks), dim3(kBlock),
+                           scatter_lds_bytes(NC, kBlock), st, dg, S, xyz, gout);
+    else
+        hipLaunchKernelGGL((scatter_kernel<NC, false>), dim3((unsigned)blocks), dim3(kBlock),
+                           scatter_lds_bytes(NC, kBlock), st, dg, S, xyz, gout);
 }
 
+template <bool W>
 __global__ __launch_bounds__(kBlock) void alpha_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
                                                        const float *__restrict__ delta, float shift,
                                                        float *__restrict__ alpha) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < S; k += (int64_t)gridDim.x * kBlock) {
-        const Tri t = trilinear(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+        const Tri t = trilinear<W>(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
         const float raw = interp_ch(g, t, 0);
         alpha[k] = -expm1f(-softplusf(raw + shift) * delta[k]);
     }
@@ -254,8 +268,12 @@ extern "C" int dvgo_grid_gather(const dvgo_grid *g, int64_t n_samples, const flo
     if (!xyz || !out) return set_error(DVGO_ERR_NULL, "xyz or out is NULL");
     if ((g->ch_stride & 3) == 0 && ((uintptr_t)g->data & 15))
         return set_error(DVGO_ERR_SHAPE, "grid data must be 16-byte aligned when ch_stride is a multiple of 4");
-    hipLaunchKernelGGL(gather_kernel, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream, dg,
-                       n_samples, xyz, out);
+    if (dg.warp)
+        hipLaunchKernelGGL(gather_kernel<true>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream,
+                           dg, n_samples, xyz, out);
+    else
+        hipLaunchKernelGGL(gather_kernel<false>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream,
+                           dg, n_samples, xyz, out);
     return check_hip(hipGetLastError(), "gather_kernel launch");
 }
 
@@ -286,8 +304,12 @@ extern "C" int dvgo_alpha(const dvgo_grid *density, int64_t n_samples, const flo
     if (n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_samples");
     if (n_samples == 0) return DVGO_OK;
     if (!xyz || !delta || !alpha) return set_error(DVGO_ERR_NULL, "xyz, delta or alpha is NULL");
-    hipLaunchKernelGGL(alpha_kernel, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream, dg,
-                       n_samples, xyz, delta, act_shift, alpha);
+    if (dg.warp)
+        hipLaunchKernelGGL(alpha_kernel<true>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream, dg,
+                           n_samples, xyz, delta, act_shift, alpha);
+    else
+        hipLaunchKernelGGL(alpha_kernel<false>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream,
+                           dg, n_samples, xyz, delta, act_shift, alpha);
     return check_hip(hipGetLastError(), "alpha_kernel launch");
 }
 

@@ -315,7 +315,7 @@ __global__ __launch_bounds__(256) void coarse_kernel(RayArgs ra, DevGrid g, floa
         const float px = (float)((double)ra.o[3 * r] + t * (double)ra.d[3 * r]);
         const float py = (float)((double)ra.o[3 * r + 1] + t * (double)ra.d[3 * r + 1]);
         const float pz = (float)((double)ra.o[3 * r + 2] + t * (double)ra.d[3 * r + 2]);
-        const float raw = interp_ch(g, trilinear(g, px, py, pz), 0);
+        const float raw = interp_ch(g, trilinear<true>(g, px, py, pz), 0);
         const float delta = (float)(((double)b - (double)a) / NB / (double)voxel);
         x = softplusf(raw + shift) * delta;
         alpha = -expm1f(-x);

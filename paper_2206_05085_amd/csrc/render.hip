@@ -72,13 +72,13 @@ __device__ __forceinline__ void zero_sample(SampleIn &s) {
     s.cc = s.cd;
 }
 
-template <int MODE>
+template <int MODE, bool WARP>
 __device__ __forceinline__ void load_sample(const RenderArgs &a, int k, bool has_next, SampleIn &s) {
     const float px = a.xyz[3 * k], py = a.xyz[3 * k + 1], pz = a.xyz[3 * k + 2];
-    s.cd = cell_of(a.dens, px, py, pz);
+    s.cd = cell_of<WARP>(a.dens, px, py, pz);
     s.raw = interp_ch(a.dens, tri_from_cell(a.dens, s.cd), 0);
     if (MODE == DVGO_COLOR_GRID) {
-        s.cc = cell_of(a.col, px, py, pz);
+        s.cc = cell_of<WARP>(a.col, px, py, pz);
         const Tri tc = tri_from_cell(a.col, s.cc);
         s.c0 = interp_ch(a.col, tc, 0);
         s.c1 = interp_ch(a.col, tc, 1);
@@ -98,7 +98,7 @@ __device__ __forceinline__ void load_sample(const RenderArgs &a, int k, bool has
     s.mn = has_next ? a.s_mid[k + 1] : 0.f;
 }
 
-template <int MODE>
+template <int MODE, bool WARP>
 __device__ __forceinline__ void render_fwd_ray(const RenderArgs &a, int r) {
     const int ln = lane();
     const int beg = a.offs[r], end = a.offs[r + 1];
@@ -113,7 +113,7 @@ __device__ __forceinline__ void render_fwd_ray(const RenderArgs &a, int r) {
         const bool valid = k < end;
         const bool has_next = k + 1 < end;
         SampleIn s;
-        if (valid) load_sample<MODE>(a, k, has_next, s);
+        if (valid) load_sample<MODE, WARP>(a, k, has_next, s);
         else zero_sample(s);
         const float xi = wave_incl(s.x);
         const float T = expf(-(L + wave_excl(xi)));
@@ -160,12 +160,12 @@ __device__ __forceinline__ void render_fwd_ray(const RenderArgs &a, int r) {
     }
 }
 
-template <int MODE>
+template <int MODE, bool WARP>
 __global__ __launch_bounds__(1024) void render_fwd_kernel(RenderArgs a) {
-    FOR_EACH_RAY(a, r) render_fwd_ray<MODE>(a, r);
+    FOR_EACH_RAY(a, r) render_fwd_ray<MODE, WARP>(a, r);
 }
 
-template <int MODE>
+template <int MODE, bool WARP>
 __device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
     const int ln = lane();
     const int beg = a.offs[r], end = a.offs[r + 1];
@@ -192,7 +192,7 @@ __device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
         const bool valid = k < hend;
         const bool has_next = k + 1 < hend;
         SampleIn s;
-        if (valid) load_sample<MODE>(a, k, has_next, s);
+        if (valid) load_sample<MODE, WARP>(a, k, has_next, s);
         else zero_sample(s);
         const float xi = wave_incl(s.x);
         const float T = expf(-(cp.x + wave_excl(xi)));
@@ -226,9 +226,9 @@ __device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
     }
 }
 
-template <int MODE>
+template <int MODE, bool WARP>
 __global__ __launch_bounds__(1024) void render_bwd_kernel(RenderArgs a) {
-    FOR_EACH_RAY(a, r) render_bwd_ray<MODE>(a, r);
+    FOR_EACH_RAY(a, r) render_bwd_ray<MODE, WARP>(a, r);
 }
 
 // Standalone distortion loss on given weights; forward sweep, then (if requested) a
@@ -359,23 +359,41 @@ Launch launch_shape(const dvgo_render_params *p, int n_list) {
     return Launch{dim3((waves + wpb - 1) / wpb), dim3(64 * wpb)};
 }
 
+// kernels with the contraction path only where a grid of the call has a warp
+bool any_warp(const dvgo_render_params *p, const RenderArgs &a) {
+    return a.dens.warp || (p->color_mode == DVGO_COLOR_GRID && a.col.warp);
+}
+
+template <bool W>
+void launch_fwd_w(const dvgo_render_params *p, const Launch &L, const RenderArgs &a, hipStream_t st) {
+    if (p->color_mode == DVGO_COLOR_GRID)
+        hipLaunchKernelGGL((render_fwd_kernel<DVGO_COLOR_GRID, W>), L.grid, L.block, 0, st, a);
+    else if (p->color_mode == DVGO_COLOR_SAMPLES)
+        hipLaunchKernelGGL((render_fwd_kernel<DVGO_COLOR_SAMPLES, W>), L.grid, L.block, 0, st, a);
+    else
+        hipLaunchKernelGGL((render_fwd_kernel<DVGO_COLOR_NONE, W>), L.grid, L.block, 0, st, a);
+}
+
+template <bool W>
+void launch_bwd_w(const dvgo_render_params *p, const Launch &L, const RenderArgs &a, hipStream_t st) {
+    if (p->color_mode == DVGO_COLOR_GRID)
+        hipLaunchKernelGGL((render_bwd_kernel<DVGO_COLOR_GRID, W>), L.grid, L.block, scatter_lds_bytes(3, L.block.x),
+                           st, a);
+    else
+        hipLaunchKernelGGL((render_bwd_kernel<DVGO_COLOR_SAMPLES, W>), L.grid, L.block, 0, st, a);
+}
+
 int launch_fwd(const dvgo_render_params *p, const RenderArgs &a, hipStream_t st) {
     const Launch L = launch_shape(p, a.n_list);
-    if (p->color_mode == DVGO_COLOR_GRID)
-        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_GRID>, L.grid, L.block, 0, st, a);
-    else if (p->color_mode == DVGO_COLOR_SAMPLES)
-        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_SAMPLES>, L.grid, L.block, 0, st, a);
-    else
-        hipLaunchKernelGGL(render_fwd_kernel<DVGO_COLOR_NONE>, L.grid, L.block, 0, st, a);
+    if (any_warp(p, a)) launch_fwd_w<true>(p, L, a, st);
+    else launch_fwd_w<false>(p, L, a, st);
     return check_hip(hipGetLastError(), "render_fwd_kernel launch");
 }
 
 int launch_bwd(const dvgo_render_params *p, const RenderArgs &a, hipStream_t st) {
     const Launch L = launch_shape(p, a.n_list);
-    if (p->color_mode == DVGO_COLOR_GRID)
-        hipLaunchKernelGGL(render_bwd_kernel<DVGO_COLOR_GRID>, L.grid, L.block, scatter_lds_bytes(3, L.block.x), st, a);
-    else
-        hipLaunchKernelGGL(render_bwd_kernel<DVGO_COLOR_SAMPLES>, L.grid, L.block, 0, st, a);
+    if (any_warp(p, a)) launch_bwd_w<true>(p, L, a, st);
+    else launch_bwd_w<false>(p, L, a, st);
     return check_hip(hipGetLastError(), "render_bwd_kernel launch");
 }
 

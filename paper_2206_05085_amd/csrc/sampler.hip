@@ -121,7 +121,10 @@ __global__ __launch_bounds__(256) void sample_count_kernel(SamplerArgs a, int R,
     }
 }
 
-// offs[1..R] (counts) -> inclusive prefix sums in place; offs[0] = 0.  One block.
+// offs[1..R] (counts) -> inclusive prefix sums in place; offs[0] = 0.  One block; each pass
+// covers SCAN_E consecutive entries per thread (all loads issued before the block scan).
+constexpr int SCAN_E = 8;
+
 __global__ __launch_bounds__(1024) void offsets_scan_kernel(int R, int *offs) {
     __shared__ int wsum[16];
     __shared__ int carry;
@@ -130,28 +133,36 @@ __global__ __launch_bounds__(1024) void offsets_scan_kernel(int R, int *offs) {
         offs[0] = 0;
     }
     __syncthreads();
-    for (int base = 0; base < R; base += 1024) {
-        const int r = base + threadIdx.x;
-        int v = r < R ? offs[r + 1] : 0;
+    for (int base = 0; base < R; base += 1024 * SCAN_E) {
+        const int r0 = base + threadIdx.x * SCAN_E;
+        int v[SCAN_E];
+#pragma unroll
+        for (int e = 0; e < SCAN_E; ++e) v[e] = r0 + e < R ? offs[r0 + e + 1] : 0;
+#pragma unroll
+        for (int e = 1; e < SCAN_E; ++e) v[e] += v[e - 1];
+        int t = v[SCAN_E - 1];
 #pragma unroll
         for (int s = 1; s < 64; s <<= 1) {
-            const int t = __shfl_up(v, s, 64);
-            if (lane() >= s) v += t;
+            const int u = __shfl_up(t, s, 64);
+            if (lane() >= s) t += u;
         }
-        if (lane() == 63) wsum[threadIdx.x >> 6] = v;
+        if (lane() == 63) wsum[threadIdx.x >> 6] = t;
         __syncthreads();
         if (threadIdx.x < 16) {
             int w = wsum[threadIdx.x];
 #pragma unroll
             for (int s = 1; s < 16; s <<= 1) {
-                const int t = __shfl_up(w, s, 16);
-                if ((int)threadIdx.x >= s) w += t;
+                const int u = __shfl_up(w, s, 16);
+                if ((int)threadIdx.x >= s) w += u;
             }
             wsum[threadIdx.x] = w;
         }
         __syncthreads();
-        const int below = (threadIdx.x >> 6) ? wsum[(threadIdx.x >> 6) - 1] : 0;
-        if (r < R) offs[r + 1] = carry + below + v;
+        // entries before this thread's run: carry + earlier waves + earlier lanes of this wave
+        const int before = carry + ((threadIdx.x >> 6) ? wsum[(threadIdx.x >> 6) - 1] : 0) + t - v[SCAN_E - 1];
+#pragma unroll
+        for (int e = 0; e < SCAN_E; ++e)
+            if (r0 + e < R) offs[r0 + e + 1] = before + v[e];
         __syncthreads();
         if (threadIdx.x == 0) carry += wsum[15];
         __syncthreads();

@@ -11,15 +11,15 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, ColorMLP, Grid, Proposal, Rays, RenderParams, Sampler, Samples,
-                   call)
+from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, WARP_CONTRACT_INF, WARP_CONTRACT_L2, WARP_NONE, ColorMLP, Grid,
+                   Proposal, Rays, RenderParams, Sampler, Samples, call)
 
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
            "grid_scatter", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
            "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
-           "COLOR_GRID", "COLOR_SAMPLES"]
+           "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2"]
 
 
 def _stream():
@@ -93,6 +93,8 @@ class DeviceGrid:
     xyz_max: Sequence[float]
     grad: Optional[torch.Tensor] = None
     channels: Optional[int] = None
+    warp: int = 0          # WARP_NONE, WARP_CONTRACT_INF or WARP_CONTRACT_L2 (Eq. 4)
+    warp_b: float = 1.0
 
     def struct(self, need_grad=False) -> Grid:
         _chk(self.data, "grid data")
@@ -112,6 +114,8 @@ class DeviceGrid:
         g.xyz_max[:] = [float(v) for v in self.xyz_max]
         g.data = _p(self.data)
         g.grad = _p(self.grad)
+        g.warp = int(self.warp)
+        g.warp_b = float(self.warp_b)
         return g
 
 

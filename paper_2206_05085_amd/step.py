@@ -22,11 +22,13 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 tv=None, device="cuda"):
+                 tv=None, warp=None, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
         tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
-        term, added into the grid gradients after the backward pass."""
+        term, added into the grid gradients after the backward pass.  warp: optional (mode, b):
+        every grid is addressed through the Eq. 4 contraction (ops.WARP_CONTRACT_INF or
+        ops.WARP_CONTRACT_L2) and the batch holds world points."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -36,6 +38,7 @@ class TrainStep:
         self.shift = ops.act_shift() if act_shift is None else act_shift
         self.halt_T, self.bg, self.lam = halt_T, tuple(bg), dist_weight
         self.tv = None if tv is None else (float(tv[0]), float(tv[1]), float(tv[2]), bool(tv[3]))
+        self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
         self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
         self.density = self._param(dev(density))
@@ -63,7 +66,7 @@ class TrainStep:
     def grid(self, which) -> ops.DeviceGrid:
         d = getattr(self, which)
         return ops.DeviceGrid(d["p"], self.box[0], self.box[1], grad=d["g"],
-                              channels=3 if which == "color" else None)
+                              channels=3 if which == "color" else None, warp=self.warp[0], warp_b=self.warp[1])
 
     def bind(self, batch: ops.SampleBatch, dirs, target):
         """Attach a sample batch (already on the GPU) and allocate every per-batch buffer."""

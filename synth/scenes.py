@@ -265,13 +265,14 @@ def _contract_inf(x, b=1.0):
     return x * scale
 
 
-def disparity_samples(rng, o, d, lengths, voxel, t_near=0.05, t_far=1e3, jitter=0.4):
+def disparity_samples(rng, o, d, lengths, voxel, t_near=0.05, t_far=1e3, jitter=0.4, contract=True):
     """Ragged unbounded-scene batch: s linear in disparity on [t_near, t_far].
 
     Ray r gets ``lengths[r]`` intervals with boundaries s_0 = 0, s_n = 1 and interior
     boundaries (j + U(-jitter, jitter)) / n, so interval lengths are non-uniform.
-    Points are contracted with Eq. 4 (p = inf, b = 1); delta is the contracted length of
-    the interval divided by the voxel size, as the step is measured in contracted space.
+    delta is the contracted length (Eq. 4, p = inf, b = 1) of the interval divided by the
+    voxel size, as the step is measured in contracted space.  The points are the contracted
+    midpoints (contract=True) or the world midpoints, for grids that contract them on lookup.
     """
     R = o.shape[0]
     n = lengths.astype(np.int64)
@@ -297,7 +298,8 @@ def disparity_samples(rng, o, d, lengths, voxel, t_near=0.05, t_far=1e3, jitter=
 
     oo = o[ray]
     dd = d[ray]
-    xm = _contract_inf(oo + t_of(s_mid)[:, None] * dd)
+    xw = oo + t_of(s_mid)[:, None] * dd
+    xm = _contract_inf(xw) if contract else xw
     xl = _contract_inf(oo + t_of(left)[:, None] * dd)
     xr = _contract_inf(oo + t_of(right)[:, None] * dd)
     delta = np.linalg.norm(xr - xl, axis=1) / voxel
@@ -375,18 +377,24 @@ def config2(R=8192, N=256, n=160, C=12, lo=0.2, hi=1.0, mlp_bias_std=0.0) -> Wor
     return Workload("config2", dens, None, feat, mlp, rays, smp, tgt)
 
 
-def config3(R=8192, n=320, C=12, median=256, sigma=0.6, lmin=32, lmax=1024) -> Workload:
-    """Unbounded, ragged: contracted [-2,2]^3 grids of 320^3, lognormal ray lengths in [32,1024]."""
+def config3(R=8192, n=320, C=12, median=256, sigma=0.6, lmin=32, lmax=1024, contract_on_host=False) -> Workload:
+    """Unbounded, ragged: [-2,2]^3 grids of 320^3 addressed through the Eq. 4 contraction
+    (p = inf, b = 1), lognormal ray lengths in [32,1024].  Points are world points and the
+    grids carry the contraction (warp 1), unless contract_on_host: then the points are
+    contracted here and the grids take them directly."""
     c = 3
     b = 1.0
     lo, hi = -1.0 - b, 1.0 + b
     dens = blob_density(_rng(c, 0), n, lo, hi)
     feat = normal_grid(_rng(c, 1), n, C, lo, hi)
+    if not contract_on_host:
+        for g in (dens, feat):
+            g.warp, g.warp_b = 1, b
     mlp = mlp_weights(_rng(c, 2), C)
     o, d = rays_into_ball(_rng(c, 3), R)
     r4 = _rng(c, 4)
     lengths = np.clip(np.round(r4.lognormal(np.log(median), sigma, size=R)), lmin, lmax).astype(np.int64)
-    smp = disparity_samples(r4, o, d, lengths, dens.voxel_size())
+    smp = disparity_samples(r4, o, d, lengths, dens.voxel_size(), contract=contract_on_host)
     rays = Rays(o.astype(F32), d.astype(F32), np.full(R, 0.05, F32), np.full(R, 1e3, F32), np.ones(R, bool))
     tgt = _rng(c, 5).random((R, 3)).astype(F32)
     return Workload("config3", dens, None, feat, mlp, rays, smp, tgt)

@@ -34,7 +34,7 @@ def T(a, dt=torch.float32):
 def dgrid(ops, g: synth.Grid, grad=False, channels=None):
     data = T(g.data)
     return ops.DeviceGrid(data, g.xyz_min, g.xyz_max, grad=torch.zeros_like(data) if grad else None,
-                          channels=channels)
+                          channels=channels, warp=g.warp, warp_b=g.warp_b)
 
 
 def dbatch(ops, s: synth.Samples):
@@ -137,9 +137,22 @@ def test_render_sample_mode_config2_grid(dv):
 
 
 def test_render_ragged_unbounded_config3(dv):
+    # world points, grids addressed through Eq. 4 (p = inf, b = 1) inside the kernels
     wl = synth.config3(R=96)
-    say("render sample-colour, 320^3 contracted, 96 lognormal rays, S =", wl.samples.n_samples)
+    assert wl.density.warp == 1
+    say("render sample-colour, 320^3 through Eq. 4 p=inf, 96 lognormal rays, S =", wl.samples.n_samples)
     _check_render(dv, wl, wl.samples, "samples", seed=2)
+
+
+def test_render_ragged_unbounded_l2_contraction(dv):
+    # the same rays through the p = 2 contraction, with a grid-colour field
+    wl = synth.config3(R=64, n=48)
+    rng = np.random.default_rng(6)
+    wl.color = synth.Grid(rng.random((48, 48, 48, 3)).astype(np.float32), wl.density.xyz_min, wl.density.xyz_max,
+                          warp=2, warp_b=1.0)
+    wl.density.warp = 2
+    say("render grid-colour, 48^3 through Eq. 4 p=2, 64 rays, S =", wl.samples.n_samples)
+    _check_render(dv, wl, wl.samples, "grid", seed=3)
 
 
 def test_render_edge_cases(dv):
@@ -203,6 +216,27 @@ def test_gather_scatter(dv, C):
     # an interpolated value is a sum of 8 weighted vertex values that may cancel: its
     # float32 error is relative to sum_c w_c |G_c|, the gather of |G|
     absg = synth.Grid(np.abs(g.data), g.xyz_min, g.xyz_max)
+    close(out.cpu().numpy(), oracle.gather(g, xyz), **FWD, name="gather", scale=oracle.gather(absg, xyz))
+    close(dg.grad.cpu().numpy(), oracle.scatter(g, xyz, y.astype(np.float64)), **GRAD, name="scatter")
+
+
+@pytest.mark.parametrize("warp,b,C", [(1, 1.0, 12), (2, 1.0, 12), (1, 0.5, 1), (2, 3.0, 3)])
+def test_gather_scatter_contracted(dv, warp, b, C):
+    # world points from 0.1 to 1e4 away from the origin, looked up through Eq. 4
+    rng = np.random.default_rng(20 + C)
+    g = synth.normal_grid(rng, 40, C, -1.0 - b, 1.0 + b)
+    g.warp, g.warp_b = warp, b
+    S = 6000
+    d = rng.standard_normal((S, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    xyz = (d * 10.0 ** rng.uniform(-1.0, 4.0, S)[:, None]).astype(np.float32)
+    y = rng.standard_normal((S, C)).astype(np.float32)
+    say("gather/scatter through Eq. 4, p =", "inf" if warp == 1 else 2, "b =", b, "C =", C)
+    dg = dgrid(dv, g, grad=True)
+    out = dv.grid_gather(dg, T(xyz))
+    dv.grid_scatter(dg, T(xyz), T(y))
+    torch.cuda.synchronize()
+    absg = synth.Grid(np.abs(g.data), g.xyz_min, g.xyz_max, warp=warp, warp_b=b)
     close(out.cpu().numpy(), oracle.gather(g, xyz), **FWD, name="gather", scale=oracle.gather(absg, xyz))
     close(dg.grad.cpu().numpy(), oracle.scatter(g, xyz, y.astype(np.float64)), **GRAD, name="scatter")
 

@@ -133,6 +133,17 @@ def test_capacity_bounds_writes(dv):
     assert (out.s_mid[cap:] == 7.0).all() and (out.s_len[cap:] == 7.0).all()
 
 
+def test_many_rays_multi_pass_offsets(dv):
+    # more rays than one pass of the prefix sum (8192 per pass), with a mask
+    rng = np.random.default_rng(104)
+    rays = synth.scenes.rays_at_box(rng, 20001)
+    mask = (rng.random((9, 9, 9)) < 0.5).astype(np.uint8)
+    say("20001 rays, three prefix-sum passes")
+    got = _gpu(dv, rays.origins, rays.dirs, 0.1, 0.1, mask=mask)
+    want = oracle.sample_rays(rays.origins, rays.dirs, BOX[0], BOX[1], 0.0, 0.1, 0.1, 4096, mask)
+    _same(got, want)
+
+
 def test_no_rays(dv):
     spec = dv.SamplerSpec(BOX[0], BOX[1], 0.02, 0.02)
     e = torch.empty(0, 3, device="cuda")

@@ -48,7 +48,8 @@ def test_schedule_builder(ops):
 def _run(ops, wl, sched, srgb, GC, GD):
     smp = wl.samples
     b = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
-    d = ops.DeviceGrid(T(wl.density.data), wl.density.xyz_min, wl.density.xyz_max)
+    d = ops.DeviceGrid(T(wl.density.data), wl.density.xyz_min, wl.density.xyz_max, warp=wl.density.warp,
+                   warp_b=wl.density.warp_b)
     d.grad = torch.zeros_like(d.data)
     shift = ops.act_shift()
     outs = []
@@ -89,13 +90,15 @@ def test_schedules_agree(ops):
     buck = _run(ops, wl, lists, srgb, GC, GD)
     tuned, ms = ops.render_autotune(ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid,
                                                                 smp.s_len),
-                                    ops.DeviceGrid(T(wl.density.data), wl.density.xyz_min, wl.density.xyz_max),
+                                    ops.DeviceGrid(T(wl.density.data), wl.density.xyz_min, wl.density.xyz_max, warp=wl.density.warp,
+                   warp_b=wl.density.warp_b),
                                     None, srgb, act_shift_=ops.act_shift(), ray_list=order)
     say("autotuned:", tuned.waves_per_block, tuned.grid_waves, f"{ms:.3f} ms")
     assert 1 <= tuned.waves_per_block <= 16 and tuned.grid_waves >= 0 and ms > 0
     again, ms2 = ops.render_autotune(ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid,
                                                                  smp.s_len),
-                                     ops.DeviceGrid(T(wl.density.data), wl.density.xyz_min, wl.density.xyz_max),
+                                     ops.DeviceGrid(T(wl.density.data), wl.density.xyz_min, wl.density.xyz_max, warp=wl.density.warp,
+                   warp_b=wl.density.warp_b),
                                      None, srgb, act_shift_=ops.act_shift(), ray_list=order)
     assert (again.waves_per_block, again.grid_waves, ms2) == (tuned.waves_per_block, tuned.grid_waves, ms)  # cached
     tun = _run(ops, wl, tuned, srgb, GC, GD)
