@@ -26,6 +26,10 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
 * sample producer (box clipping, candidate placement, nearest-vertex mask compaction; its
   integer decisions are taken in float32): pinned (axis-aligned closed forms, misses,
   float64 slab geometry and counts, the cap, brute-force mask selection).
+* forward-facing NDC plane sampler: pinned (the paper's 2D - 1 points at s = 0.5, the
+  central ray's plane depths, every point is the NDC projection of a world point on its ray
+  (independent float64 projection), float64 brute force of the image-axis box test, rays that
+  never reach the near plane, masks).
 * occupancy mask update (alpha threshold, 27-neighbour dilation, deactivation only):
   pinned (numpy brute force, a single dense vertex, the alpha_init identity, idempotence
   and monotonicity).
@@ -516,3 +520,25 @@ def sample_rays(origins, dirs, bmin, bmax, near, step, voxel, max_per_ray, mask=
     dl, sm, sl = (np.zeros(S, np.float32) for _ in range(3))
     L.orc_sample_rays(*args, _ptr(xyz), _ptr(dl), _ptr(sm), _ptr(sl))
     return dict(ray_offsets=offs, t_near=tn, t_far=tf, xyz=xyz, delta=dl, s_mid=sm, s_len=sl)
+
+
+def sample_ndc(origins, dirs, bmin, bmax, fx, fy, near, planes, step, max_per_ray=4096, mask=None):
+    """Forward-facing NDC plane sampling (orc_sample_ndc).  Returns a dict with ray_offsets
+    [R+1] int32 and the float32 samples xyz [S,3] (NDC points), delta, s_mid, s_len."""
+    o = _c(origins, np.float32).reshape(-1, 3)
+    d = _c(dirs, np.float32).reshape(-1, 3)
+    R = o.shape[0]
+    lo = _c(bmin, np.float32).reshape(3)
+    hi = _c(bmax, np.float32).reshape(3)
+    m = None if mask is None else _c(mask, np.uint8)
+    shape = np.zeros(3, np.int32) if m is None else np.array(m.shape, np.int32)
+    offs = np.zeros(R + 1, np.int32)
+    L = lib()
+    L.orc_sample_ndc.restype = C.c_int64
+    args = (C.c_int32(R), _ptr(o), _ptr(d), _ptr(lo), _ptr(hi), C.c_float(fx), C.c_float(fy), C.c_float(near),
+            C.c_int32(planes), C.c_float(step), C.c_int32(max_per_ray), _ptr(m), _ptr(shape), _ptr(offs))
+    S = int(L.orc_sample_ndc(*args, None, None, None, None))
+    xyz = np.zeros((S, 3), np.float32)
+    dl, sm, sl = (np.zeros(S, np.float32) for _ in range(3))
+    L.orc_sample_ndc(*args, _ptr(xyz), _ptr(dl), _ptr(sm), _ptr(sl))
+    return dict(ray_offsets=offs, xyz=xyz, delta=dl, s_mid=sm, s_len=sl)

@@ -1185,3 +1185,64 @@ int64_t orc_sample_rays(int32_t R, const float *o, const float *d, const float *
     }
     return total;
 }
+
+/* Forward-facing sampling (section 5.3): rays of a forward-facing capture are warped with
+ * NeRF's normalised device coordinates to a bounded volume holding D planes at fixed depths
+ * (a multiplane-image-like grid), and every ray is traced from the first plane to the last
+ * with a step of s planes, which gives 2D - 1 points at s = 0.5.  Readings, all decided in
+ * float32 with each operation rounded on its own:
+ *   - camera space looks down -z; fx = 2 focal / W, fy = 2 focal / H, near = the near plane;
+ *     a ray with d_z >= 0 never crosses it and gets no samples;
+ *   - the origin moves to the near plane, t0 = -(near + o_z)/d_z, o <- fma(t0, d, o); the NDC
+ *     origin is (-fx (o_x/o_z), -fy (o_y/o_z), 1 + (2 near)/o_z) and the NDC direction
+ *     (-fx (d_x/d_z - o_x/o_z), -fy (d_y/d_z - o_y/o_z), -(2 near)/o_z), so NDC depth runs
+ *     from -1 (near plane) to 1 (infinity) over t' in [0, 1];
+ *   - the planes sit at NDC depth -1 + 2 p/(D - 1), p = 0 .. D - 1; sample j (j = 0 .. J,
+ *     J = floor((D - 1)/s), capped at max_per_ray candidates) is at plane coordinate j s,
+ *     t' = (j s)/(D - 1), point fma(t', d', o') per axis; it owns the interval of one step
+ *     around it: delta = s (planes are one voxel apart along depth), s_mid = (j + 1/2)/(J + 1),
+ *     s_len = 1/(J + 1);
+ *   - a sample is kept when its point lies in the box across the image axes (bmin <= x' <= bmax
+ *     for x and y; depth is inside by construction, and the first and last planes sit on the
+ *     box faces, where a rounding must not drop them) and the mask (if any) is set at its
+ *     nearest vertex, as in orc_sample_rays.
+ * Writes ray_offsets [R+1] and, when xyz is not NULL, the samples.  Returns the total. */
+int64_t orc_sample_ndc(int32_t R, const float *o, const float *d, const float *bmin, const float *bmax, float fx,
+                       float fy, float near, int32_t planes, float step, int32_t max_per_ray, const uint8_t *mask,
+                       const int32_t *mshape, int32_t *offs, float *xyz, float *delta, float *s_mid, float *s_len)
+{
+    int64_t total = 0;
+    offs[0] = 0;
+    const float span = (float)(planes - 1);
+    const float jmax = floorf(span / step);
+    const int32_t n = jmax + 1.0f > (float)max_per_ray ? max_per_ray : (int32_t)jmax + 1;
+    for (int32_t r = 0; r < R; ++r) {
+        const float *ro = o + 3 * r, *rd = d + 3 * r;
+        if (rd[2] < 0.0f) {
+            const float t0 = -(near + ro[2]) / rd[2];
+            float p[3];
+            for (int a = 0; a < 3; ++a) p[a] = fmaf(t0, rd[a], ro[a]);
+            const float qx = p[0] / p[2], qy = p[1] / p[2];
+            const float on[3] = {-(fx * qx), -(fy * qy), 1.0f + (2.0f * near) / p[2]};
+            const float dn[3] = {-(fx * (rd[0] / rd[2] - qx)), -(fy * (rd[1] / rd[2] - qy)), -((2.0f * near) / p[2])};
+            for (int32_t j = 0; j < n; ++j) {
+                const float t = ((float)j * step) / span;
+                float x[3];
+                int inside = 1;
+                for (int a = 0; a < 3; ++a) x[a] = fmaf(t, dn[a], on[a]);
+                for (int a = 0; a < 2; ++a) inside &= bmin[a] <= x[a] && x[a] <= bmax[a];
+                if (!inside) continue;
+                if (mask && !mask[nearest_vertex(x, bmin, bmax, mshape)]) continue;
+                if (xyz) {
+                    for (int a = 0; a < 3; ++a) xyz[3 * total + a] = x[a];
+                    delta[total] = step;
+                    s_mid[total] = ((float)j + 0.5f) / (float)n;
+                    s_len[total] = 1.0f / (float)n;
+                }
+                ++total;
+            }
+        }
+        offs[r + 1] = (int32_t)total;
+    }
+    return total;
+}

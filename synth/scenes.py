@@ -214,6 +214,27 @@ def pinhole_rays(rng, R, n_cams=100, radius=4.0, H=800, W=800, fov_deg=40.0,
     return _finish_rays(cams[cid], d, bmin, bmax)
 
 
+def forward_facing_rays(rng, R, n_cams=20, W=1008, H=756, focal=815.0, spread=0.15, tilt_deg=3.0):
+    """Random pixels of n_cams pinhole cameras of a forward-facing capture, in the reference
+    camera's frame (looking down -z): centres jittered in the z = 0 plane by +-spread, small
+    random tilts.  Returns float32 origins and unit directions."""
+    cams = np.zeros((n_cams, 3))
+    cams[:, :2] = rng.uniform(-spread, spread, (n_cams, 2))
+    ang = np.deg2rad(rng.uniform(-tilt_deg, tilt_deg, (n_cams, 2)))
+    cid = rng.integers(0, n_cams, size=R)
+    px = rng.integers(0, W, size=R) + 0.5
+    py = rng.integers(0, H, size=R) + 0.5
+    dc = np.stack([(px - 0.5 * W) / focal, -(py - 0.5 * H) / focal, -np.ones(R)], axis=1)
+    ax, ay = ang[cid, 0], ang[cid, 1]
+    # tilt about x then y
+    y1 = dc[:, 1] * np.cos(ax) - dc[:, 2] * np.sin(ax)
+    z1 = dc[:, 1] * np.sin(ax) + dc[:, 2] * np.cos(ax)
+    x2 = dc[:, 0] * np.cos(ay) + z1 * np.sin(ay)
+    z2 = -dc[:, 0] * np.sin(ay) + z1 * np.cos(ay)
+    d = _unit(np.stack([x2, y1, z2], axis=1))
+    return cams[cid].astype(F32), d.astype(F32)
+
+
 def rays_into_ball(rng, R, radius=0.9):
     """Origins on a small sphere inside the unit ball, aimed at uniform points of the ball."""
     o = radius * _sphere(rng, R)
