@@ -438,6 +438,56 @@ def sampler_leg(ops, torch, wl, steps=20, reps=20):
     return res
 
 
+def ff_leg(ops, torch, steps=10, reps=20):
+    """Forward-facing scene on the GPU (section 5.3): 256 planes of 384 x 384 in NDC, occupancy
+    from the density at the 1-plane step (alpha >= 1e-3), NDC plane sampling of 8192 rays at a
+    step of one plane (the paper's setting) through that mask, then graph-replayed training steps
+    on the produced batch."""
+    import synth
+    from paper_2206_05085_amd.step import TrainStep
+    wl = synth.config6()
+    fx, fy, planes = wl.extra["ndc"]
+    nx, ny, nz = wl.density.data.shape[:3]
+    st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                   mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight)
+    del wl.feat
+    mask = torch.ones(nx * ny * nz, dtype=torch.uint8, device="cuda")
+
+    def timed(f, n):
+        f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    occ_ms = timed(lambda: st.update_occupancy(mask, 1e-3, 1.0), reps)
+    og = torch.as_tensor(wl.rays.origins).cuda().contiguous()
+    dg = torch.as_tensor(wl.rays.dirs).cuda().contiguous()
+    spec = ops.SamplerSpec(wl.density.xyz_min, wl.density.xyz_max, 1.0, near=1.0, mask=mask.view(nx, ny, nz),
+                           ndc=(fx, fy, planes))
+    offs = ops.sample_count(spec, og, dg)
+    S = int(offs[-1].item())
+    batch = ops.sample_emit(spec, og, dg, offs, S)
+
+    def produce():
+        ops.sample_count(spec, og, dg, ray_offsets=offs)
+        ops.sample_emit(spec, og, dg, offs, S, out=batch)
+    prod_ms = timed(produce, reps)
+    st.bind(batch, dg, wl.target)
+    g = st.capture(warmup=1)
+    step_ms = timed(g.replay, steps)
+    R = og.shape[0]
+    return {"workload": f"{nx}x{ny}x{nz} NDC volume (density + 12-ch features + MLP), {R} forward-facing rays, "
+                        f"step 1 plane, occupancy alpha >= 1e-3",
+            "active_fraction": round(float(mask.float().mean().item()), 4), "occupancy_ms": round(occ_ms, 4),
+            "samples": S, "candidates": R * planes, "producer_ms": round(prod_ms, 4),
+            "step_ms_graph": round(step_ms, 4), "step_samples_per_s": round(S / (step_ms * 1e-3), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -452,6 +502,7 @@ def main():
     ap.add_argument("--proposal-steps", type=int, default=1500)
     ap.add_argument("--no-tv", action="store_true")
     ap.add_argument("--no-sampler", action="store_true")
+    ap.add_argument("--no-ff", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="end with a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -578,6 +629,10 @@ def main():
     if not args.no_sampler:
         print("[bench] GPU sample producer + occupancy mask", file=sys.stderr, flush=True)
         out["sampler"] = sampler_leg(ops, torch, wl)
+    if not args.no_ff:
+        print("[bench] forward-facing NDC volume: occupancy, plane sampling, step", file=sys.stderr, flush=True)
+        out["forward_facing"] = ff_leg(ops, torch)
+        torch.cuda.empty_cache()
     if not args.no_ragged:
         print("[bench] ragged unbounded batch: schedules", file=sys.stderr, flush=True)
         out["ragged"] = ragged_leg(log=True)

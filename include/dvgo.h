@@ -344,12 +344,13 @@ int dvgo_resample(const dvgo_rays *rays, const float *prob, const float *entropy
 
 /* ------------------------------------------------------------------ sample producer
  * Builds the ragged batch on the device from rays: points are placed only where a ray
- * crosses the scene box (section 3, re-implemented rendering utilities; bounded scenes), and
- * points in space switched off by the occupancy mask are skipped (section 1).
+ * crosses the scene box (DVGO_SAMPLE_BOX: section 3, re-implemented rendering utilities;
+ * bounded scenes) or on the planes of a forward-facing volume in normalised device
+ * coordinates (DVGO_SAMPLE_NDC: section 5.3), and points in space switched off by the
+ * occupancy mask are skipped (section 1).
  *
- * Definition (every step one float32 operation rounded to nearest even, no fused forms
- * except the two fma below; any IEEE float32 evaluation of these steps gives the same
- * integers):
+ * Box mode (every step one float32 operation rounded to nearest even, no fused forms except
+ * the two fma below; any IEEE float32 evaluation of these steps gives the same integers):
  *   box interval: per axis t0 = (xyz_min - o)/d, t1 = (xyz_max - o)/d, [min, max] of the two
  *     (an axis with d == 0 is unbounded if xyz_min <= o <= xyz_max, else empty); t_exit = the
  *     smallest upper end, t_near = max(largest lower end, near); the ray misses unless
@@ -362,9 +363,23 @@ int dvgo_resample(const dvgo_rays *rays, const float *prob, const float *entropy
  *     clamped to [0, mask_shape - 1] (u < 0 or NaN -> 0);
  *   kept candidate: xyz = x, delta = step/voxel, s_mid = (k + 0.5)/n, s_len = 1/n (s linear in
  *     t over the ray's n candidate intervals); rays in order, each ray's samples by k.
- * Directions should be unit vectors for `step` to be a distance (not checked). */
+ * Directions should be unit vectors for `step` to be a distance (not checked).
+ * NDC mode (same float32 rules; rays in the reference camera's frame, looking down -z):
+ *   a ray with d_z >= 0 gets no samples; t0 = -(near + o_z)/d_z, p = fma(t0, d, o) per axis;
+ *     NDC origin o' = (-(ndc_fx (p_x/p_z)), -(ndc_fy (p_y/p_z)), 1 + (2 near)/p_z), NDC
+ *     direction d' = (-(ndc_fx (d_x/d_z - p_x/p_z)), -(ndc_fy (d_y/d_z - p_y/p_z)),
+ *     -((2 near)/p_z)), with ndc_fx = 2 focal/W, ndc_fy = 2 focal/H;
+ *   candidates: n = min(floor((ndc_planes - 1)/step) + 1, max_per_ray) for every such ray
+ *     (2 ndc_planes - 1 at step 0.5); candidate j at t' = (j step)/(ndc_planes - 1), point
+ *     x = fma(t', d', o') per axis; kept iff xyz_min <= x <= xyz_max on the x and y axes (depth
+ *     runs between the first and last planes by construction) and the mask keeps it (as above);
+ *   kept candidate: xyz = x (NDC), delta = step (planes), s_mid = (j + 0.5)/n, s_len = 1/n;
+ *     t_near, t_far outputs: (0, 1) for rays with samples, else (0, 0); `voxel` is unused. */
+enum { DVGO_SAMPLE_BOX = 0, DVGO_SAMPLE_NDC = 1 };
+
 typedef struct dvgo_sampler {
     uint32_t struct_size;
+    int32_t mode;           /* DVGO_SAMPLE_BOX or DVGO_SAMPLE_NDC */
     float xyz_min[3];       /* scene box; also the box of the mask's vertex grid */
     float xyz_max[3];
     float near;             /* samples start at t >= near (finite) */
@@ -373,6 +388,8 @@ typedef struct dvgo_sampler {
     int32_t max_per_ray;    /* 1 .. 2^20; max_per_ray * n_rays must be < 2^31 */
     int32_t mask_shape[3];  /* vertex grid of the mask, entries >= 1, product < 2^31 */
     const uint8_t *mask;    /* [nx][ny][nz] bytes, non-zero = active; NULL = every point active */
+    float ndc_fx, ndc_fy;   /* NDC mode: 2 focal / W, 2 focal / H (> 0) */
+    int32_t ndc_planes;     /* NDC mode: number of planes D (>= 2); near must be > 0 */
 } dvgo_sampler;
 
 /* Counts kept samples per ray and writes ray_offsets [n_rays+1] (exclusive prefix, int32;

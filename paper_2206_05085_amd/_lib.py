@@ -17,6 +17,7 @@ ERRORS = {-1: "ERR_NULL", -2: "ERR_SHAPE", -3: "ERR_RANGE", -5: "ERR_WORKSPACE",
           -7: "ERR_UNSUPPORTED", -8: "ERR_ABI"}
 COLOR_GRID, COLOR_SAMPLES, COLOR_NONE = 0, 1, 2
 WARP_NONE, WARP_CONTRACT_INF, WARP_CONTRACT_L2 = 0, 1, 2
+SAMPLE_BOX, SAMPLE_NDC = 0, 1
 
 
 class DvgoError(RuntimeError):
@@ -59,9 +60,10 @@ class Proposal(C.Structure):
 
 
 class Sampler(C.Structure):
-    _fields_ = [("struct_size", C.c_uint32), ("xyz_min", C.c_float * 3), ("xyz_max", C.c_float * 3),
-                ("near", C.c_float), ("step", C.c_float), ("voxel", C.c_float), ("max_per_ray", C.c_int32),
-                ("mask_shape", C.c_int32 * 3), ("mask", VP)]
+    _fields_ = [("struct_size", C.c_uint32), ("mode", C.c_int32), ("xyz_min", C.c_float * 3),
+                ("xyz_max", C.c_float * 3), ("near", C.c_float), ("step", C.c_float), ("voxel", C.c_float),
+                ("max_per_ray", C.c_int32), ("mask_shape", C.c_int32 * 3), ("mask", VP), ("ndc_fx", C.c_float),
+                ("ndc_fy", C.c_float), ("ndc_planes", C.c_int32)]
 
 
 _I32, _I64, _F, _SZP = C.c_int32, C.c_int64, C.c_float, C.POINTER(C.c_size_t)

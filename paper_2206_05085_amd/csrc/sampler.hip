@@ -1,5 +1,6 @@
 // Sample producer: parsimonious sampling inside the scene box (section 3, re-implemented
-// rendering utilities) with occupancy compaction (section 1), and the occupancy mask update.
+// rendering utilities) or along forward-facing rays warped to normalised device coordinates
+// (section 5.3), with occupancy compaction (section 1), and the occupancy mask update.
 //
 // The producer runs in two passes over the same per-ray arithmetic: a count pass (one wave
 // per ray, candidates in chunks of 64 lanes, a ballot per chunk), a one-block prefix sum that
@@ -23,10 +24,20 @@ constexpr int kMaxPerRay = 1 << 20;
 struct SamplerArgs {
     float bmin[3], bmax[3];
     float near, step;
-    float delta;       // step / voxel, every sample's alpha interval
+    float delta;       // every sample's alpha interval: step / voxel (box), step (NDC planes)
     int max_per_ray;
     int mn[3];         // mask vertex grid
     const uint8_t *mask;
+    float fx, fy;      // NDC: 2 focal / W, 2 focal / H
+    float span;        // NDC: planes - 1
+    int n_ndc;         // NDC: candidates per ray, min(floor(span / step) + 1, max_per_ray)
+};
+
+// Per-ray plan: the number of candidates and what places them.
+struct RayPlan {
+    int n;
+    float tn, te;            // box mode: interval along t
+    float on[3], dn[3];      // NDC mode: origin and direction of the warped ray
 };
 
 // Box interval of one ray by the slab method; returns the number of candidates.
@@ -62,13 +73,9 @@ __device__ __forceinline__ int clip_ray(const SamplerArgs &a, const float (&o)[3
     return (int)__builtin_ceilf(c);
 }
 
-// Point of candidate k and whether the mask keeps it (nearest vertex, clamped to the grid).
-__device__ __forceinline__ bool candidate(const SamplerArgs &a, const float (&o)[3], const float (&d)[3], float tn,
-                                          int k, float (&x)[3]) {
+// Whether the mask keeps point x (nearest vertex, clamped to the grid).
+__device__ __forceinline__ bool mask_keeps(const SamplerArgs &a, const float (&x)[3]) {
 #pragma clang fp contract(off)
-    const float t = __builtin_fmaf((float)k + 0.5f, a.step, tn);
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) x[ax] = __builtin_fmaf(t, d[ax], o[ax]);
     if (!a.mask) return true;
     int idx[3];
 #pragma unroll
@@ -80,6 +87,61 @@ __device__ __forceinline__ bool candidate(const SamplerArgs &a, const float (&o)
         else idx[ax] = (int)__builtin_rintf(u);
     }
     return a.mask[((int64_t)idx[0] * a.mn[1] + idx[1]) * a.mn[2] + idx[2]] != 0;
+}
+
+// NeRF's normalised device coordinates of a forward-facing ray (camera looking down -z):
+// the origin moves to the near plane, then origin and direction are warped so that NDC
+// depth runs from -1 (near plane) to 1 (infinity) over t' in [0, 1].
+__device__ __forceinline__ bool ndc_ray(const SamplerArgs &a, const float (&o)[3], const float (&d)[3],
+                                        float (&on)[3], float (&dn)[3]) {
+#pragma clang fp contract(off)
+    if (!(d[2] < 0.0f)) return false;  // never crosses the near plane in front of the camera
+    const float t0 = -(a.near + o[2]) / d[2];
+    float p[3];
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) p[ax] = __builtin_fmaf(t0, d[ax], o[ax]);
+    const float qx = p[0] / p[2], qy = p[1] / p[2];
+    const float nz = (2.0f * a.near) / p[2];
+    on[0] = -(a.fx * qx);
+    on[1] = -(a.fy * qy);
+    on[2] = 1.0f + nz;
+    dn[0] = -(a.fx * (d[0] / d[2] - qx));
+    dn[1] = -(a.fy * (d[1] / d[2] - qy));
+    dn[2] = -nz;
+    return true;
+}
+
+template <int MODE>
+__device__ __forceinline__ RayPlan plan_ray(const SamplerArgs &a, const float (&o)[3], const float (&d)[3]) {
+    RayPlan p;
+    if (MODE == DVGO_SAMPLE_BOX) {
+        p.n = clip_ray(a, o, d, p.tn, p.te);
+    } else {
+        p.tn = 0.0f;
+        p.te = ndc_ray(a, o, d, p.on, p.dn) ? 1.0f : 0.0f;
+        p.n = p.te > 0.0f ? a.n_ndc : 0;
+    }
+    return p;
+}
+
+// Point of candidate k of a ray and whether it is kept.
+template <int MODE>
+__device__ __forceinline__ bool candidate(const SamplerArgs &a, const RayPlan &p, const float (&o)[3],
+                                          const float (&d)[3], int k, float (&x)[3]) {
+#pragma clang fp contract(off)
+    if (MODE == DVGO_SAMPLE_BOX) {
+        // the midpoint of the k-th step after t_near
+        const float t = __builtin_fmaf((float)k + 0.5f, a.step, p.tn);
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) x[ax] = __builtin_fmaf(t, d[ax], o[ax]);
+    } else {
+        // plane coordinate k step; dropped outside the box across the image axes
+        const float t = ((float)k * a.step) / a.span;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) x[ax] = __builtin_fmaf(t, p.dn[ax], p.on[ax]);
+        if (!(a.bmin[0] <= x[0] && x[0] <= a.bmax[0] && a.bmin[1] <= x[1] && x[1] <= a.bmax[1])) return false;
+    }
+    return mask_keeps(a, x);
 }
 
 __device__ __forceinline__ int wave_ray() {
@@ -94,30 +156,31 @@ __device__ __forceinline__ void load_ray(const float *org, const float *dir, int
     }
 }
 
-// kept candidates per ray -> offs[r + 1]; the box interval -> t_near / t_far (0, 0 on a miss)
+// kept candidates per ray -> offs[r + 1]; the ray's parameter interval -> t_near / t_far
+// (0, 0 when it has none)
+template <int MODE>
 __global__ __launch_bounds__(256) void sample_count_kernel(SamplerArgs a, int R, const float *org, const float *dir,
                                                            int *offs, float *t_near, float *t_far) {
     const int r = wave_ray();
     if (r >= R) return;
     float o[3], d[3];
     load_ray(org, dir, r, o, d);
-    float tn, te;
-    const int n = clip_ray(a, o, d, tn, te);
-    int cnt = n;
-    if (a.mask) {
+    const RayPlan p = plan_ray<MODE>(a, o, d);
+    int cnt = p.n;
+    if (a.mask || MODE == DVGO_SAMPLE_NDC) {
         cnt = 0;
-        for (int k0 = 0; k0 < n; k0 += 64) {
+        for (int k0 = 0; k0 < p.n; k0 += 64) {
             const int k = k0 + lane();
             float x[3];
-            const bool live = k < n && candidate(a, o, d, tn, k, x);
+            const bool live = k < p.n && candidate<MODE>(a, p, o, d, k, x);
             cnt += __popcll(__ballot(live));
         }
     }
     if (lane() == 0) {
         offs[r + 1] = cnt;
-        const bool hit = te > tn;
-        if (t_near) t_near[r] = hit ? tn : 0.0f;
-        if (t_far) t_far[r] = hit ? te : 0.0f;
+        const bool hit = p.te > p.tn;
+        if (t_near) t_near[r] = hit ? p.tn : 0.0f;
+        if (t_far) t_far[r] = hit ? p.te : 0.0f;
     }
 }
 
@@ -171,6 +234,7 @@ __global__ __launch_bounds__(1024) void offsets_scan_kernel(int R, int *offs) {
 
 // kept candidates of ray r at offs[r] + (kept candidates before them); indices outside
 // [0, capacity) are not written
+template <int MODE>
 __global__ __launch_bounds__(256) void sample_emit_kernel(SamplerArgs a, int R, const float *org, const float *dir,
                                                           const int *offs, int64_t capacity, float *xyz,
                                                           float *delta, float *s_mid, float *s_len) {
@@ -178,8 +242,8 @@ __global__ __launch_bounds__(256) void sample_emit_kernel(SamplerArgs a, int R, 
     if (r >= R) return;
     float o[3], d[3];
     load_ray(org, dir, r, o, d);
-    float tn, te;
-    const int n = clip_ray(a, o, d, tn, te);
+    const RayPlan p = plan_ray<MODE>(a, o, d);
+    const int n = p.n;
     if (n == 0) return;
     const float fn = (float)n;
     const float sl = 1.0f / fn;
@@ -187,7 +251,7 @@ __global__ __launch_bounds__(256) void sample_emit_kernel(SamplerArgs a, int R, 
     for (int k0 = 0; k0 < n; k0 += 64) {
         const int k = k0 + lane();
         float x[3];
-        const bool live = k < n && candidate(a, o, d, tn, k, x);
+        const bool live = k < n && candidate<MODE>(a, p, o, d, k, x);
         const uint64_t b = __ballot(live);
         const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0));
         const int64_t i = pos + below;
@@ -274,6 +338,22 @@ int make_sampler(const dvgo_sampler *sp, int32_t n_rays, const float *org, const
     a.step = sp->step;
     a.delta = sp->step / sp->voxel;
     a.max_per_ray = sp->max_per_ray;
+    a.fx = a.fy = a.span = 0.0f;
+    a.n_ndc = 0;
+    if (sp->mode == DVGO_SAMPLE_NDC) {
+        if (!(sp->near > 0.f)) return set_error(DVGO_ERR_RANGE, "NDC sampling needs near > 0");
+        if (!(sp->ndc_fx > 0.f) || !(sp->ndc_fy > 0.f) || !std::isfinite(sp->ndc_fx) || !std::isfinite(sp->ndc_fy))
+            return set_error(DVGO_ERR_RANGE, "NDC sampling needs positive finite ndc_fx, ndc_fy");
+        if (sp->ndc_planes < 2) return set_error(DVGO_ERR_SHAPE, "NDC sampling needs ndc_planes >= 2");
+        a.fx = sp->ndc_fx;
+        a.fy = sp->ndc_fy;
+        a.span = (float)(sp->ndc_planes - 1);
+        const float jmax = std::floor(a.span / sp->step);
+        a.n_ndc = jmax + 1.0f > (float)sp->max_per_ray ? sp->max_per_ray : (int)jmax + 1;
+        a.delta = sp->step;
+    } else if (sp->mode != DVGO_SAMPLE_BOX) {
+        return set_error(DVGO_ERR_UNSUPPORTED, "unknown sampler mode %d", sp->mode);
+    }
     return DVGO_OK;
 }
 
@@ -299,8 +379,14 @@ extern "C" int dvgo_sample_count(const dvgo_sampler *sp, int32_t n_rays, const f
     if (rc) return rc;
     if (!ray_offsets) return set_error(DVGO_ERR_NULL, "ray_offsets is NULL");
     if (n_rays > 0) {
-        hipLaunchKernelGGL(sample_count_kernel, dim3(ray_blocks(n_rays)), dim3(64 * kWavesPerBlock), 0,
-                           (hipStream_t)stream, a, n_rays, origins, dirs, ray_offsets, t_near, t_far);
+        if (sp->mode == DVGO_SAMPLE_NDC)
+            hipLaunchKernelGGL(sample_count_kernel<DVGO_SAMPLE_NDC>, dim3(ray_blocks(n_rays)),
+                               dim3(64 * kWavesPerBlock), 0, (hipStream_t)stream, a, n_rays, origins, dirs,
+                               ray_offsets, t_near, t_far);
+        else
+            hipLaunchKernelGGL(sample_count_kernel<DVGO_SAMPLE_BOX>, dim3(ray_blocks(n_rays)),
+                               dim3(64 * kWavesPerBlock), 0, (hipStream_t)stream, a, n_rays, origins, dirs,
+                               ray_offsets, t_near, t_far);
         rc = check_hip(hipGetLastError(), "sample_count_kernel launch");
         if (rc) return rc;
     }
@@ -318,9 +404,14 @@ extern "C" int dvgo_sample_emit(const dvgo_sampler *sp, int32_t n_rays, const fl
     if (n_rays == 0 || capacity == 0) return DVGO_OK;
     if (!ray_offsets || !xyz || !delta || !s_mid || !s_len)
         return set_error(DVGO_ERR_NULL, "ray_offsets or an output array is NULL");
-    hipLaunchKernelGGL(sample_emit_kernel, dim3(ray_blocks(n_rays)), dim3(64 * kWavesPerBlock), 0,
-                       (hipStream_t)stream, a, n_rays, origins, dirs, ray_offsets, capacity, xyz, delta, s_mid,
-                       s_len);
+    if (sp->mode == DVGO_SAMPLE_NDC)
+        hipLaunchKernelGGL(sample_emit_kernel<DVGO_SAMPLE_NDC>, dim3(ray_blocks(n_rays)), dim3(64 * kWavesPerBlock),
+                           0, (hipStream_t)stream, a, n_rays, origins, dirs, ray_offsets, capacity, xyz, delta, s_mid,
+                           s_len);
+    else
+        hipLaunchKernelGGL(sample_emit_kernel<DVGO_SAMPLE_BOX>, dim3(ray_blocks(n_rays)), dim3(64 * kWavesPerBlock),
+                           0, (hipStream_t)stream, a, n_rays, origins, dirs, ray_offsets, capacity, xyz, delta, s_mid,
+                           s_len);
     return check_hip(hipGetLastError(), "sample_emit_kernel launch");
 }
 

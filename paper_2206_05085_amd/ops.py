@@ -553,18 +553,24 @@ def resample(rays: RayBatch, prob, entropy, tau, ray_offsets, n_samples, voxel, 
 
 @dataclass
 class SamplerSpec:
-    """Scene box, spacing and occupancy mask of the sample producer (dvgo_sampler)."""
+    """Scene box, spacing and occupancy mask of the sample producer (dvgo_sampler).  Box mode
+    (default): step and voxel in world units.  NDC mode (ndc = (fx, fy, planes), fx = 2 focal / W,
+    fy = 2 focal / H): step in planes, near = the camera's near plane, voxel unused."""
     xyz_min: Sequence[float]
     xyz_max: Sequence[float]
     step: float
-    voxel: float
+    voxel: float = 1.0
     near: float = 0.0
     max_per_ray: int = 4096
     mask: Optional[torch.Tensor] = None  # uint8 [nx, ny, nz] on the GPU, or None (all active)
+    ndc: Optional[tuple] = None
 
     def struct(self) -> Sampler:
         sp = Sampler()
         sp.struct_size = C_size(Sampler)
+        if self.ndc is not None:
+            sp.mode = _lib.SAMPLE_NDC
+            sp.ndc_fx, sp.ndc_fy, sp.ndc_planes = float(self.ndc[0]), float(self.ndc[1]), int(self.ndc[2])
         sp.xyz_min[:] = [float(v) for v in self.xyz_min]
         sp.xyz_max[:] = [float(v) for v in self.xyz_max]
         sp.near, sp.step, sp.voxel = float(self.near), float(self.step), float(self.voxel)

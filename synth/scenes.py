@@ -129,17 +129,22 @@ def _axis(n, lo, hi):
     return lo + (hi - lo) * np.arange(n, dtype=np.float64) / (n - 1)
 
 
+def _shape3(n):
+    return (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+
+
 def blob_density(rng, n, xyz_min=-1.0, xyz_max=1.0, n_blobs=8, center_box=0.6, return_blobs=False):
     """Density logits N(0,1) + sum of Gaussian blobs (amplitude U[6,14], sigma U[0.05,0.2]).
-    With return_blobs, also returns the blob term alone ([n,n,n] float32)."""
+    n: vertices per axis, or a 3-tuple.  With return_blobs, also returns the blob term alone."""
     lo = np.full(3, xyz_min, np.float64)
     hi = np.full(3, xyz_max, np.float64)
-    base = rng.standard_normal((n, n, n), dtype=np.float32)
+    shp = _shape3(n)
+    base = rng.standard_normal(shp, dtype=np.float32)
     mu = rng.uniform(-center_box, center_box, size=(n_blobs, 3))
     sd = rng.uniform(0.05, 0.2, size=n_blobs)
     amp = rng.uniform(6.0, 14.0, size=n_blobs)
-    axes = [_axis(n, lo[a], hi[a]) for a in range(3)]
-    acc = np.zeros((n, n, n), np.float32)
+    axes = [_axis(shp[a], lo[a], hi[a]) for a in range(3)]
+    acc = np.zeros(shp, np.float32)
     for b in range(n_blobs):
         g = [np.exp(-(axes[a] - mu[b, a]) ** 2 / (2 * sd[b] ** 2)).astype(F32) for a in range(3)]
         acc += F32(amp[b]) * (g[0][:, None, None] * g[1][None, :, None] * g[2][None, None, :])
@@ -149,7 +154,7 @@ def blob_density(rng, n, xyz_min=-1.0, xyz_max=1.0, n_blobs=8, center_box=0.6, r
 
 
 def normal_grid(rng, n, C, xyz_min=-1.0, xyz_max=1.0) -> Grid:
-    data = rng.standard_normal((n, n, n, C), dtype=np.float32)
+    data = rng.standard_normal(_shape3(n) + (C,), dtype=np.float32)
     return Grid(data, np.full(3, xyz_min, F32), np.full(3, xyz_max, F32))
 
 
@@ -428,6 +433,23 @@ def config4(R=16384, N=512, n=160, C=12) -> Workload:
     smp = uniform_samples(rays, N, w2.density.voxel_size())
     tgt = _rng(4, 5).random((R, 3)).astype(F32)
     return Workload("config4", w2.density, None, w2.feat, w2.mlp, rays, smp, tgt)
+
+
+def config6(R=8192, shape=(384, 384, 256), C=12, W=1008, H=756, focal=815.0) -> Workload:
+    """Forward-facing (section 5.3): a multiplane-image-like volume of 256 planes of 384 x 384 in
+    normalised device coordinates [-1,1]^3 (density + 12-channel features + colour MLP), and the
+    rays of 20 forward-facing pinhole cameras (W x H, focal) in the reference camera's frame.
+    The batch is made on the GPU by the NDC sampler (samples is None here)."""
+    c = 6
+    dens = blob_density(_rng(c, 0), shape)
+    feat = normal_grid(_rng(c, 1), shape, C)
+    mlp = mlp_weights(_rng(c, 2), C)
+    o, d = forward_facing_rays(_rng(c, 3), R, W=W, H=H, focal=focal)
+    rays = Rays(o, d, np.zeros(R, F32), np.zeros(R, F32), np.ones(R, bool))
+    tgt = _rng(c, 5).random((R, 3)).astype(F32)
+    wl = Workload("config6", dens, None, feat, mlp, rays, None, tgt)
+    wl.extra["ndc"] = (2.0 * focal / W, 2.0 * focal / H, shape[2])
+    return wl
 
 
 def clear_free_space(density: Grid, blobs, keep_above=1.0, empty=-20.0) -> Grid:

@@ -163,6 +163,17 @@ def test_validation_errors(L):
     sp.mask_shape[:] = [4, 4, 4]
     assert lib.dvgo_sample_emit(C.byref(sp), 4, 64, 64, 64, -1, 64, 64, 64, 64, None) == -2
     assert lib.dvgo_sample_emit(C.byref(sp), 4, 64, 64, 64, 10, None, 64, 64, 64, None) == -1
+    # NDC mode: unknown mode, near <= 0, focal scale <= 0, fewer than two planes
+    sp.mask = None
+    sp.mode = 7
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -7
+    sp.mode = L.SAMPLE_NDC
+    sp.near, sp.ndc_fx, sp.ndc_fy, sp.ndc_planes = 0.0, 1.6, 2.1, 256
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -3
+    sp.near, sp.ndc_fx = 1.0, 0.0
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -3
+    sp.ndc_fx, sp.ndc_planes = 1.6, 1
+    assert lib.dvgo_sample_count(C.byref(sp), 4, 64, 64, 64, None, None, None) == -2
     # occupancy update: NULL mask, delta, threshold range
     assert lib.dvgo_occupancy_update(C.byref(t), -8.5, 0.5, 1e-3, None, None) == -1
     t.ch_stride, t.channels = 1, 1

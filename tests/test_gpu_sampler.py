@@ -144,6 +144,63 @@ def test_many_rays_multi_pass_offsets(dv):
     _same(got, want)
 
 
+# ------------------------------------------------------------------ forward-facing (NDC)
+
+FF = dict(W=1008, H=756, focal=815.0)
+FX, FY = 2 * FF["focal"] / FF["W"], 2 * FF["focal"] / FF["H"]
+
+
+def _gpu_ndc(dv, o, d, planes, step, near=1.0, cap=4096, mask=None):
+    spec = dv.SamplerSpec(BOX[0], BOX[1], step, near=near, max_per_ray=cap,
+                          mask=None if mask is None else T(mask, torch.uint8), ndc=(FX, FY, planes))
+    R = len(o)
+    og, dg = T(o), T(d)
+    tn = torch.empty(R, device="cuda")
+    tf = torch.empty(R, device="cuda")
+    offs = dv.sample_count(spec, og, dg, t_near=tn, t_far=tf)
+    S = int(offs[-1].item())
+    b = dv.sample_emit(spec, og, dg, offs, S)
+    torch.cuda.synchronize()
+    n = np.diff(offs.cpu().numpy())
+    assert (tf.cpu().numpy()[n > 0] == 1.0).all() and not tn.cpu().numpy().any()
+    return dict(ray_offsets=offs.cpu().numpy(), xyz=b.xyz.cpu().numpy(), delta=b.delta.cpu().numpy(),
+                s_mid=b.s_mid.cpu().numpy(), s_len=b.s_len.cpu().numpy())
+
+
+@pytest.mark.parametrize("planes,step,masked", [(8, 0.5, False), (64, 0.5, True), (33, 0.75, True),
+                                                (256, 1.0, False)])
+def test_ndc_rays(dv, planes, step, masked):
+    rng = np.random.default_rng(105)
+    o, d = synth.scenes.forward_facing_rays(rng, 2000, spread=0.3, tilt_deg=6.0, **FF)
+    d[:3] = np.float32([[0, 0, 1], [1, 0, 0], [0, 0, -1]])      # backwards, sideways, central
+    mask = (rng.random((24, 20, planes)) < 0.5).astype(np.uint8) if masked else None
+    say("NDC rays, planes", planes, "step", step, "masked", masked)
+    got = _gpu_ndc(dv, o, d, planes, step, mask=mask)
+    want = oracle.sample_ndc(o, d, BOX[0], BOX[1], FX, FY, 1.0, planes, step, 4096, mask)
+    _same(got, want, keys=("ray_offsets", "xyz", "delta", "s_mid", "s_len"))
+    n = np.diff(want["ray_offsets"])
+    assert n[0] == 0 and n[1] == 0
+    if not masked:
+        assert n[2] == int(np.floor((planes - 1) / step)) + 1
+
+
+def test_ndc_full_size_mpi(dv):
+    # section 5.3's volume: 256 planes of 384 x 384, step 1 plane; 8192 rays, a mask with blobs
+    rng = np.random.default_rng(106)
+    o, d = synth.scenes.forward_facing_rays(rng, 8192, **FF)
+    shape = (384, 384, 256)
+    mask = np.zeros(shape, np.uint8)
+    for _ in range(40):
+        c = rng.integers(0, shape)
+        r = rng.integers(8, 40, 3)
+        mask[max(c[0] - r[0], 0):c[0] + r[0], max(c[1] - r[1], 0):c[1] + r[1], max(c[2] - r[2], 0):c[2] + r[2]] = 1
+    say("NDC full size 384x384x256, 8192 rays, mask active", round(float(mask.mean()), 3))
+    got = _gpu_ndc(dv, o, d, 256, 1.0, mask=mask)
+    want = oracle.sample_ndc(o, d, BOX[0], BOX[1], FX, FY, 1.0, 256, 1.0, 4096, mask)
+    _same(got, want, keys=("ray_offsets", "xyz", "delta", "s_mid", "s_len"))
+    assert want["ray_offsets"][-1] > 8192 * 5
+
+
 def test_no_rays(dv):
     spec = dv.SamplerSpec(BOX[0], BOX[1], 0.02, 0.02)
     e = torch.empty(0, 3, device="cuda")
