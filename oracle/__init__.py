@@ -15,7 +15,10 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
   2-homogeneity, shift and reflection invariance, Euler identity, finite differences).
 * render forward / backward: pinned (closed-form constant-density ray, invariants,
   the alpha_init identity, halting rule, finite differences of the oracle's forward).
-* colour MLP: pinned against torch float64 Linear/ReLU/Sigmoid and autograd.
+* colour MLP: pinned against torch float64 Linear/ReLU/Sigmoid and autograd.  Its cheaper
+  mode (matrix-product operands rounded to FP16 significands): pinned against a torch float64
+  head with the same operands rounded by numpy's float16 conversion (straight-through values,
+  rounded product-output gradients), and within a few 2^-11 of the exact head.
 * Adam: pinned against torch.optim.Adam in float64; skip rule checked bitwise.
 * proposal network: pinned against torch float64 with bfloat16-rounded operands;
   softmax/CE gradient closed form; resample closed forms (uniform and one-hot).
@@ -72,7 +75,7 @@ class OrcGrid(C.Structure):
 
 class OrcMLP(C.Structure):
     _fields_ = [("W1", VP), ("b1", VP), ("W2", VP), ("b2", VP), ("W3", VP), ("b3", VP),
-                ("C", C.c_int32), ("F", C.c_int32), ("H", C.c_int32)]
+                ("C", C.c_int32), ("F", C.c_int32), ("H", C.c_int32), ("half", C.c_int32)]
 
 
 class OrcProp(C.Structure):
@@ -272,8 +275,9 @@ def loss_head(rgb, target, D, lam):
     return float(L), GC, GD
 
 
-def _mlp_struct(mlp, keep, C_feat, F):
+def _mlp_struct(mlp, keep, C_feat, F, half=False):
     P = OrcMLP()
+    P.half = 1 if half else 0
     W1, W2, W3 = [keep(_c(w, np.float32)) for w in mlp.W]
     b1, b2, b3 = [keep(_c(b, np.float32)) for b in mlp.b]
     P.W1, P.b1, P.W2, P.b2, P.W3, P.b3 = [a.ctypes.data for a in (W1, b1, W2, b2, W3, b3)]
@@ -281,10 +285,12 @@ def _mlp_struct(mlp, keep, C_feat, F):
     return P
 
 
-def mlp_forward(mlp, offs, dirs, feat, F=4):
+def mlp_forward(mlp, offs, dirs, feat, F=4, half=False):
+    """Colour head forward (orc_mlp_forward); half: matrix-product operands rounded to FP16
+    significands, as the cheaper colour head computes them."""
     keep = _Keep()
     feat = keep(_c(feat, np.float64))
-    P = _mlp_struct(mlp, keep, feat.shape[1], F)
+    P = _mlp_struct(mlp, keep, feat.shape[1], F, half)
     offs = keep(_c(offs, np.int32))
     dirs = keep(_c(dirs, np.float32))
     R = offs.shape[0] - 1
@@ -325,11 +331,11 @@ def mlp_kink_slack(mlp, offs, dirs, feat, grad_rgb, thr=1e-5, F=4):
     return sf, W, b
 
 
-def mlp_backward(mlp, offs, dirs, feat, grad_rgb, F=4):
-    """Returns (grad_feat [S,C], [gW1, gW2, gW3], [gb1, gb2, gb3])."""
+def mlp_backward(mlp, offs, dirs, feat, grad_rgb, F=4, half=False):
+    """Returns (grad_feat [S,C], [gW1, gW2, gW3], [gb1, gb2, gb3]); half as in mlp_forward."""
     keep = _Keep()
     feat = keep(_c(feat, np.float64))
-    P = _mlp_struct(mlp, keep, feat.shape[1], F)
+    P = _mlp_struct(mlp, keep, feat.shape[1], F, half)
     offs = keep(_c(offs, np.int32))
     dirs = keep(_c(dirs, np.float32))
     gr = keep(_c(grad_rgb, np.float64))
@@ -542,3 +548,11 @@ def sample_ndc(origins, dirs, bmin, bmax, fx, fy, near, planes, step, max_per_ra
     dl, sm, sl = (np.zeros(S, np.float32) for _ in range(3))
     L.orc_sample_ndc(*args, _ptr(xyz), _ptr(dl), _ptr(sm), _ptr(sl))
     return dict(ray_offsets=offs, xyz=xyz, delta=dl, s_mid=sm, s_len=sl)
+
+
+def r16_round(x):
+    """Round to 11 significant bits, to nearest even (the FP16 operands of the cheaper head)."""
+    a = _c(x, np.float64)
+    out = np.zeros_like(a)
+    lib().orc_r16_round(C.c_int64(a.size), _ptr(a), _ptr(out))
+    return out

@@ -56,7 +56,7 @@ static double sigmoid(double z)
 
 /* ------------------------------------------------------------------ interpolation */
 
-/* Eq. 4, the parameterisation of unbounded scenes (section 5.5): a point inside the unit
+/* Eq. 4, the parameterisation of unbounded scenes (section 5.4): a point inside the unit
  * p-ball is kept; a point outside is moved along its own direction to the radius
  * 1 + b - b/||x||_p, so all of space lands inside the p-ball of radius 1 + b, which the
  * grid's box [-1-b, 1+b]^3 covers.  p = inf (warp 1) or p = 2 (warp 2). */
@@ -411,11 +411,28 @@ static void view_pe(const float *d, int F, double *pe)
         }
 }
 
-/* Hybrid colour head: input [feat(C), PE(d)], two hidden ReLU layers of H, sigmoid RGB. */
+/* Hybrid colour head: input [feat(C), PE(d)], two hidden ReLU layers of H, sigmoid RGB.
+ * half != 0: the cheaper colour head, whose matrix products take each operand rounded to an
+ * FP16 significand (see r16); exact double otherwise. */
 typedef struct {
     const float *W1, *b1, *W2, *b2, *W3, *b3;  /* [H][C+3+6F], [H], [H][H], [H], [3][H], [3] */
     int32_t C, F, H;
+    int32_t half;
 } orc_mlp;
+
+/* v rounded to 11 significant bits, to nearest even: the value an FP16 operand carries after
+ * an exact power-of-two scaling into the FP16 normal range (the range itself is not modelled). */
+static double r16(double v)
+{
+    if (v == 0.0 || !isfinite(v)) return v;
+    int e;
+    const double m = frexp(v, &e);  /* v = m 2^e, 1/2 <= |m| < 1 */
+    return ldexp(nearbyint(ldexp(m, 11)), e - 11);
+}
+
+/* An operand of one of the head's matrix products (layers 1 and 2, the back-propagation
+ * through W2 and W1, the gradients of W2 and W1). */
+static double opnd(const orc_mlp *P, double v) { return P->half ? r16(v) : v; }
 
 static int64_t find_ray(int32_t R, const int32_t *offs, int64_t k)
 {
@@ -432,13 +449,13 @@ static void mlp_fwd_one(const orc_mlp *P, const double *x, double *z1, double *h
     int I = P->C + 3 + 6 * P->F, H = P->H;
     for (int i = 0; i < H; ++i) {
         double s = P->b1[i];
-        for (int j = 0; j < I; ++j) s += (double)P->W1[i * I + j] * x[j];
+        for (int j = 0; j < I; ++j) s += opnd(P, P->W1[i * I + j]) * opnd(P, x[j]);
         z1[i] = s;
         h1[i] = s > 0 ? s : 0.0;
     }
     for (int i = 0; i < H; ++i) {
         double s = P->b2[i];
-        for (int j = 0; j < H; ++j) s += (double)P->W2[i * H + j] * h1[j];
+        for (int j = 0; j < H; ++j) s += opnd(P, P->W2[i * H + j]) * opnd(P, h1[j]);
         z2[i] = s;
         h2[i] = s > 0 ? s : 0.0;
     }
@@ -498,20 +515,20 @@ static void mlp_backward_range(const orc_mlp *P, int32_t R, const int32_t *offs,
         }
         for (int i = 0; i < H; ++i) {
             gb2[i] += d2[i];
-            for (int j = 0; j < H; ++j) gW2[i * H + j] += d2[i] * h1[j];
+            for (int j = 0; j < H; ++j) gW2[i * H + j] += opnd(P, d2[i]) * opnd(P, h1[j]);
         }
         for (int j = 0; j < H; ++j) {
             double s = 0.0;
-            for (int i = 0; i < H; ++i) s += (double)P->W2[i * H + j] * d2[i];
+            for (int i = 0; i < H; ++i) s += opnd(P, P->W2[i * H + j]) * opnd(P, d2[i]);
             d1[j] = z1[j] > 0 ? s : 0.0;
         }
         for (int i = 0; i < H; ++i) {
             gb1[i] += d1[i];
-            for (int j = 0; j < I; ++j) gW1[i * I + j] += d1[i] * x[j];
+            for (int j = 0; j < I; ++j) gW1[i * I + j] += opnd(P, d1[i]) * opnd(P, x[j]);
         }
         for (int c = 0; c < P->C; ++c) {
             double s = 0.0;
-            for (int i = 0; i < H; ++i) s += (double)P->W1[i * I + c] * d1[i];
+            for (int i = 0; i < H; ++i) s += opnd(P, P->W1[i * I + c]) * opnd(P, d1[i]);
             grad_feat[k * P->C + c] = s;
         }
     }
@@ -718,6 +735,11 @@ static double bf16(double x)
     u &= 0xffff0000u;
     memcpy(&f, &u, 4);
     return (double)f;
+}
+
+void orc_r16_round(int64_t n, const double *in, double *out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = r16(in[i]);
 }
 
 void orc_bf16_round(int64_t n, const double *in, double *out)

@@ -50,6 +50,75 @@ def test_mlp_matches_torch(orc):
         np.testing.assert_allclose(a, t.grad.numpy(), rtol=1e-10, atol=1e-13)
 
 
+def _h(t):
+    """FP16 significand rounding by numpy's float64 -> float16 conversion (scale into [1, 2),
+    convert, scale back).  numpy converts directly; torch's float64 -> half path rounds through
+    float32 first (double rounding near ties), so it cannot serve as the reference."""
+    t = np.asarray(t.detach().numpy() if isinstance(t, torch.Tensor) else t, dtype=np.float64)
+    m, e = np.frexp(t)
+    return torch.as_tensor(np.ldexp((2.0 * m).astype(np.float16).astype(np.float64), e - 1))
+
+
+def test_r16_matches_torch_half(orc):
+    rng = np.random.default_rng(44)
+    x = np.concatenate([rng.standard_normal(2000) * 10.0 ** rng.integers(-12, 12, 2000),
+                        [0.0, 1.0, 1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11, -(1 + 2.0 ** -10 + 2.0 ** -11)]])
+    np.testing.assert_array_equal(orc.r16_round(x), _h(x).numpy())
+    # ties go to even: 1 + 2^-11 -> 1, 1 + 3 * 2^-11 -> 1 + 2^-9
+    assert orc.r16_round([1 + 2.0 ** -11])[0] == 1.0 and orc.r16_round([1 + 3 * 2.0 ** -11])[0] == 1 + 2.0 ** -9
+
+
+def _torch_mlp_half(mlp, feat, dirs_per_sample, F=4):
+    """The cheaper colour head in torch float64: every matrix-product operand rounded to an FP16
+    significand (weights and activations in the forward, the back-propagated gradients at the
+    product outputs), biases, the output layer and activations exact."""
+    class RoundGrad(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, t):
+            return t.clone()
+
+        @staticmethod
+        def backward(ctx, g):
+            return _h(g)
+
+    def rnd(t):  # rounded value, identity gradient
+        return t + (_h(t.detach()) - t.detach())
+    W = [torch.tensor(w, dtype=torch.float64, requires_grad=True) for w in mlp.W]
+    b = [torch.tensor(v, dtype=torch.float64, requires_grad=True) for v in mlp.b]
+    f = torch.tensor(feat, dtype=torch.float64, requires_grad=True)
+    x = torch.cat([f, _pe(dirs_per_sample, F)], dim=-1)
+    m1 = RoundGrad.apply(rnd(x) @ rnd(W[0]).T)
+    h1 = torch.relu(m1 + b[0])
+    m2 = RoundGrad.apply(rnd(h1) @ rnd(W[1]).T)
+    h2 = torch.relu(m2 + b[1])
+    rgb = torch.sigmoid(torch.nn.functional.linear(h2, W[2], b[2]))
+    return rgb, f, W, b
+
+
+def test_half_mlp_matches_torch(orc):
+    rng = np.random.default_rng(43)
+    mlp = synth.mlp_weights(rng, bias_std=0.3)
+    offs = np.array([0, 7, 7, 20, 41], np.int32)
+    S = int(offs[-1])
+    dirs = synth.scenes._unit(rng.standard_normal((4, 3))).astype(np.float32)
+    feat = rng.standard_normal((S, 12))
+    rgb = orc.mlp_forward(mlp, offs, dirs, feat, half=True)
+    ray_of = np.repeat(np.arange(4), np.diff(offs))
+    trgb, f, W, b = _torch_mlp_half(mlp, feat, dirs[ray_of].astype(np.float64))
+    np.testing.assert_allclose(rgb, trgb.detach().numpy(), rtol=1e-12, atol=1e-14)
+    g = rng.standard_normal((S, 3))
+    (trgb * torch.tensor(g)).sum().backward()
+    gf, gW, gb = orc.mlp_backward(mlp, offs, dirs, feat, g, half=True)
+    np.testing.assert_allclose(gf, f.grad.numpy(), rtol=1e-10, atol=1e-13)
+    for a, t in zip(gW + gb, W + b):
+        np.testing.assert_allclose(a, t.grad.numpy(), rtol=1e-10, atol=1e-13)
+    # and it stays within FP16 rounding of the exact head (normwise, a few units of 2^-11)
+    exact = orc.mlp_forward(mlp, offs, dirs, feat)
+    assert np.linalg.norm(rgb - exact) <= 4 * 2.0 ** -11 * np.linalg.norm(exact)
+    egf = orc.mlp_backward(mlp, offs, dirs, feat, g)[0]
+    assert 0 < np.linalg.norm(gf - egf) <= 20 * 2.0 ** -11 * np.linalg.norm(egf)
+
+
 def test_adam_matches_torch_and_skips_zero(orc):
     rng = np.random.default_rng(41)
     n = 1000
