@@ -488,6 +488,43 @@ def ff_leg(ops, torch, steps=10, reps=20):
             "step_ms_graph": round(step_ms, 4), "step_samples_per_s": round(S / (step_ms * 1e-3), 1)}
 
 
+def f16_head_leg(ops, torch, wl, batch, steps=30):
+    """The cheaper colour head (FP16 matrix operands, one product per product) in the same
+    config-2 step: colour-head stage times and the graph-replayed step.  Reduced precision by
+    design (its own tolerance), so it is reported beside the FP32-grade headline, not as it."""
+    from paper_2206_05085_amd.step import TrainStep
+    st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                   mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight, mlp_precision=ops.MLP_F16)
+    st.bind(batch, wl.rays.dirs, wl.target)
+
+    def timed(f, n):
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    st.forward()
+    st.backward()
+    fwd = timed(lambda: ops.mlp_forward(st.mlp, batch.ray_offsets, st.dirs, st.feat_s, rgb=st.rgb_s, ws=st.mlp_ws), 10)
+    bwd = timed(lambda: ops.mlp_backward(st.mlp, batch.ray_offsets, st.dirs, st.feat_s, st.g_rgb_s,
+                                         grad_feat=st.g_feat_s, ws=st.mlp_ws), 10)
+    for d in (st.density, st.feat, st.mlp_flat):
+        d["g"].zero_()
+    g = st.capture(warmup=1)
+    step = timed(g.replay, steps)
+    S = batch.n_samples
+    return {"mlp_fwd_ms": round(fwd, 4), "mlp_bwd_ms": round(bwd, 4), "step_ms_graph": round(step, 4),
+            "step_samples_per_s": round(S / (step * 1e-3), 1),
+            "mlp_bwd_tflops_algorithmic": round(S * mlp_flops_per_sample(True) / (bwd * 1e-3) / 1e12, 2),
+            "precision": "FP16 matrix operands (11-bit significands), FP32 accumulation"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -503,6 +540,7 @@ def main():
     ap.add_argument("--no-tv", action="store_true")
     ap.add_argument("--no-sampler", action="store_true")
     ap.add_argument("--no-ff", action="store_true")
+    ap.add_argument("--no-f16", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="end with a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -626,6 +664,9 @@ def main():
     if not args.no_tv:
         print("[bench] total-variation gradients", file=sys.stderr, flush=True)
         out["tv"] = tv_leg(ops, st, torch)
+    if not args.no_f16:
+        print("[bench] cheaper colour head (FP16 operands)", file=sys.stderr, flush=True)
+        out["cheaper_colour_head"] = f16_head_leg(ops, torch, wl, batch)
     if not args.no_sampler:
         print("[bench] GPU sample producer + occupancy mask", file=sys.stderr, flush=True)
         out["sampler"] = sampler_leg(ops, torch, wl)

@@ -127,7 +127,15 @@ typedef struct dvgo_render_params {
  * unit direction d: [d, sin(2^0 d) .. sin(2^(F-1) d), cos(2^0 d) .. cos(2^(F-1) d)], each block
  * in x,y,z order.  Weights are row-major [out][in] (W1 [H][in_feat+3+6F], W2 [H][H],
  * W3 [3][H]); the g* pointers receive += in dvgo_mlp_backward.
- * Supported: in_feat <= 12, n_freq <= 4 (so the input fits 48 columns), hidden = 128. */
+ * Supported: in_feat <= 12, n_freq <= 4 (so the input fits 48 columns), hidden = 128.
+ * precision: DVGO_MLP_SPLIT_F16 (default, FP32-grade: every matrix-core operand is split into two
+ * FP16 parts and a product takes three FP16 products) or DVGO_MLP_F16 (the cheaper colour head:
+ * every matrix-core operand is one FP16 value after the same power-of-two scaling, i.e. rounded
+ * to 11 significant bits, products accumulated in FP32).  In both modes the layer-1/2 products,
+ * the weight gradients of W1/W2 and the back-propagation through W2 and W1 run on matrix cores;
+ * biases, the output layer, its gradients and all activations stay in FP32. */
+enum { DVGO_MLP_SPLIT_F16 = 0, DVGO_MLP_F16 = 1 };
+
 typedef struct dvgo_color_mlp {
     uint32_t struct_size;
     int32_t in_feat;
@@ -135,6 +143,7 @@ typedef struct dvgo_color_mlp {
     int32_t hidden;
     const float *W1, *b1, *W2, *b2, *W3, *b3;
     float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
+    int32_t precision;
 } dvgo_color_mlp;
 
 int dvgo_abi_version(void);

@@ -18,6 +18,7 @@ ERRORS = {-1: "ERR_NULL", -2: "ERR_SHAPE", -3: "ERR_RANGE", -5: "ERR_WORKSPACE",
 COLOR_GRID, COLOR_SAMPLES, COLOR_NONE = 0, 1, 2
 WARP_NONE, WARP_CONTRACT_INF, WARP_CONTRACT_L2 = 0, 1, 2
 SAMPLE_BOX, SAMPLE_NDC = 0, 1
+MLP_SPLIT_F16, MLP_F16 = 0, 1
 
 
 class DvgoError(RuntimeError):
@@ -46,7 +47,8 @@ class RenderParams(C.Structure):
 class ColorMLP(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("in_feat", C.c_int32), ("n_freq", C.c_int32), ("hidden", C.c_int32),
                 ("W1", VP), ("b1", VP), ("W2", VP), ("b2", VP), ("W3", VP), ("b3", VP),
-                ("gW1", VP), ("gb1", VP), ("gW2", VP), ("gb2", VP), ("gW3", VP), ("gb3", VP)]
+                ("gW1", VP), ("gb1", VP), ("gW2", VP), ("gb2", VP), ("gW3", VP), ("gb3", VP),
+                ("precision", C.c_int32)]
 
 
 class Rays(C.Structure):

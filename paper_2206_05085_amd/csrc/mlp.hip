@@ -367,6 +367,7 @@ constexpr int FWD_NC = 2;                 // 16-sample column tiles per wave til
 constexpr int FWD_WTILE = 16 * FWD_NC;    // samples per wave tile
 static_assert(FWD_WTILE == TILE, "forward wave tiles are the 32-sample tiles of tile_ray");
 
+template <bool SPLIT>
 __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char sm[IMG_FWD_END];
     copy_to_lds(sm, a.img, IMG_FWD_END);
@@ -431,10 +432,12 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
                 const int o = (16 * m + j) * RS1 + 32 * kk + 8 * q;
                 const h8 ah = *reinterpret_cast<const h8 *>(W1h + o);
                 const h8 al = *reinterpret_cast<const h8 *>(W1l + o);
+                if (SPLIT) {
 #pragma unroll
-                for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(al, xh[c][kk], acc[c]);
+                    for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(al, xh[c][kk], acc[c]);
 #pragma unroll
-                for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, xl[c][kk], acc[c]);
+                    for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, xl[c][kk], acc[c]);
+                }
 #pragma unroll
                 for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, xh[c][kk], acc[c]);
             }
@@ -463,13 +466,16 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
                 const int o = (16 * m + j) * RS2 + 32 * kk + 8 * q;
                 const h8 ah = *reinterpret_cast<const h8 *>(W2h + o);
                 const h8 al = *reinterpret_cast<const h8 *>(W2l + o);
+                if (SPLIT) {
 #pragma unroll
-                for (int c = 0; c < FWD_NC; ++c) {
-                    const h8 bh = cat(hh[c][2 * kk], hh[c][2 * kk + 1]);
-                    acc[c] = mfma16(al, bh, acc[c]);
+                    for (int c = 0; c < FWD_NC; ++c) {
+                        const h8 bh = cat(hh[c][2 * kk], hh[c][2 * kk + 1]);
+                        acc[c] = mfma16(al, bh, acc[c]);
+                    }
+#pragma unroll
+                    for (int c = 0; c < FWD_NC; ++c)
+                        acc[c] = mfma16(ah, cat(hl[c][2 * kk], hl[c][2 * kk + 1]), acc[c]);
                 }
-#pragma unroll
-                for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, cat(hl[c][2 * kk], hl[c][2 * kk + 1]), acc[c]);
 #pragma unroll
                 for (int c = 0; c < FWD_NC; ++c) acc[c] = mfma16(ah, cat(hh[c][2 * kk], hh[c][2 * kk + 1]), acc[c]);
             }
@@ -565,11 +571,12 @@ __device__ __forceinline__ h8 glb_h8(const unsigned char *img, int off, int idx)
     return *reinterpret_cast<const h8 *>(reinterpret_cast<const _Float16 *>(img + off) + idx);
 }
 
-// write a split value into a transposed plane [unit][TS]
+// write a split value into a transposed plane [unit][TS] (the lo plane only in split mode)
+template <bool SPLIT>
 __device__ __forceinline__ void put_t(unsigned char *base, int off_h, int off_l, int unit, int col, float t) {
     const _Float16 h = (_Float16)t;
     reinterpret_cast<_Float16 *>(base + off_h)[unit * TS + col] = h;
-    reinterpret_cast<_Float16 *>(base + off_l)[unit * TS + col] = (_Float16)(t - (float)h);
+    if (SPLIT) reinterpret_cast<_Float16 *>(base + off_l)[unit * TS + col] = (_Float16)(t - (float)h);
 }
 
 __device__ __forceinline__ void store_h4(unsigned char *base, int off, int idx, h4 v) {
@@ -649,6 +656,7 @@ __device__ __forceinline__ void rescale(v4f (&acc)[2][N], int &F, int f) {
     }
 }
 
+template <bool SPLIT>
 __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char sm[B_END];
     copy_to_lds(sm, a.img + IMG_B1, BS);
@@ -722,14 +730,16 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         bh[c] = lds_h8(sm, xb, (16 * c + j) * RS1 + 32 * kk + 8 * q);
                         bl[c] = lds_h8(sm, xb + NT * RS1 * 2, (16 * c + j) * RS1 + 32 * kk + 8 * q);
                     }
+                    if (SPLIT) {
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                        for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1l[mp][kk], bh[c], acc[c][mp]);
+                            for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1l[mp][kk], bh[c], acc[c][mp]);
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                        for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1h[mp][kk], bl[c], acc[c][mp]);
+                            for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1h[mp][kk], bl[c], acc[c][mp]);
+                    }
 #pragma unroll
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -755,12 +765,12 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         split4(h1, sc, hi, lo);
                         const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
                         store_h4(hb, 0, ob, hi);
-                        store_h4(hb, NT * RS2 * 2, ob, lo);
+                        if (SPLIT) store_h4(hb, NT * RS2 * 2, ob, lo);
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int u = 32 * w + 16 * mp + 4 * q + r;
                             reinterpret_cast<_Float16 *>(rA)[u * TS + 16 * c + j] = hi[r];
-                            reinterpret_cast<_Float16 *>(rA + (B_HTL - B_HTH))[u * TS + 16 * c + j] = lo[r];
+                            if (SPLIT) reinterpret_cast<_Float16 *>(rA + (B_HTL - B_HTH))[u * TS + 16 * c + j] = lo[r];
                         }
                     }
                 }
@@ -782,14 +792,16 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         bh[c] = lds_h8(hb, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
                         bl[c] = lds_h8(hb, NT * RS2 * 2, (16 * c + j) * RS2 + 32 * kk + 8 * q);
                     }
+                    if (SPLIT) {
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                        for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2l[mp][kk], bh[c], acc[c][mp]);
+                            for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2l[mp][kk], bh[c], acc[c][mp]);
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                        for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2h[mp][kk], bl[c], acc[c][mp]);
+                            for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2h[mp][kk], bl[c], acc[c][mp]);
+                    }
 #pragma unroll
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -850,11 +862,11 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         split4(dz2, pow2(ge.g2[c]), hi, lo);
                         const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
                         store_h4(hb, 0, ob, hi);
-                        store_h4(hb, NT * RS2 * 2, ob, lo);
+                        if (SPLIT) store_h4(hb, NT * RS2 * 2, ob, lo);
                         const int fs = frame_shift(F2, se.e1[c]);  // exact for any shift; 0 stays 0
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            put_t(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2[r], fs));
+                            put_t<SPLIT>(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2[r], fs));
                     }
                 }
             }
@@ -868,8 +880,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 for (int n = 0; n < 8; ++n) {
                     const int rb = (16 * n + j) * TS + 8 * q;
                     const h8 bh = lds_h8(rA, 0, rb), bl = lds_h8(rA, B_HTL - B_HTH, rb);
-                    dW2[mp][n] = mfma16(al, bh, dW2[mp][n]);
-                    dW2[mp][n] = mfma16(ah, bl, dW2[mp][n]);
+                    if (SPLIT) {
+                        dW2[mp][n] = mfma16(al, bh, dW2[mp][n]);
+                        dW2[mp][n] = mfma16(ah, bl, dW2[mp][n]);
+                    }
                     dW2[mp][n] = mfma16(ah, bh, dW2[mp][n]);
                 }
             }
@@ -949,12 +963,13 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             split4(&xv[4], sc, h1, l1);
             const int xb = B_XB0 + pb * XB_BYTES, xt = B_XT0 + pb * XT_BYTES;
             *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb) + xsl * RS1 + 8 * xg) = cat(h0, h1);
-            *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb + NT * RS1 * 2) + xsl * RS1 + 8 * xg) =
-                cat(l0, l1);
+            if (SPLIT)
+                *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb + NT * RS1 * 2) + xsl * RS1 + 8 * xg) =
+                    cat(l0, l1);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int k = kidx(xg >> 2, xg & 3, e);
-                if (k < NXIN) put_t(sm, xt, xt + NXIN * TS * 2, k, xsl, xv[e] * sc);
+                if (k < NXIN) put_t<SPLIT>(sm, xt, xt + NXIN * TS * 2, k, xsl, xv[e] * sc);
             }
             if (xg == 0) xmax_b[pb * NT + xsl] = m;
             if (xg < 4) gr_b[(pb * NT + xsl) * 4 + xg] = grv;
@@ -981,8 +996,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 for (int n = 0; n < 3; ++n) {
                     const int rb = (16 * n + j) * TS + 8 * q;
                     const h8 bh = lds_h8(sm, xt, rb), bl = lds_h8(sm, xt + NXIN * TS * 2, rb);
-                    dW1[mp][n] = mfma16(dl, bh, dW1[mp][n]);
-                    dW1[mp][n] = mfma16(dh, bl, dW1[mp][n]);
+                    if (SPLIT) {
+                        dW1[mp][n] = mfma16(dl, bh, dW1[mp][n]);
+                        dW1[mp][n] = mfma16(dh, bl, dW1[mp][n]);
+                    }
                     dW1[mp][n] = mfma16(dh, bh, dW1[mp][n]);
                 }
             }
@@ -1007,14 +1024,16 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     bh[c] = lds_h8(hb, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
                     bl[c] = lds_h8(hb, NT * RS2 * 2, (16 * c + j) * RS2 + 32 * kk + 8 * q);
                 }
+                if (SPLIT) {
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
+                    for (int c = 0; c < 2; ++c)
 #pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2tl[mp][kk], bh[c], acc[c][mp]);
+                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2tl[mp][kk], bh[c], acc[c][mp]);
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
+                    for (int c = 0; c < 2; ++c)
 #pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2th[mp][kk], bl[c], acc[c][mp]);
+                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2th[mp][kk], bl[c], acc[c][mp]);
+                }
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -1034,7 +1053,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         const bool on = __builtin_amdgcn_inverse_ballot_w64(mk[r]);
                         dz1[mp][c][r] = on ? acc[c][mp][r] * un : 0.f;
                         db1[mp][r] += dz1[mp][c][r];
-                        put_t(rA, B_D1TH - B_HTH, B_D1TL - B_HTH, u0 + r, 16 * c + j, ldx(dz1[mp][c][r], fs));
+                        put_t<SPLIT>(rA, B_D1TH - B_HTH, B_D1TL - B_HTH, u0 + r, 16 * c + j, ldx(dz1[mp][c][r], fs));
                     }
                 }
             }
@@ -1047,8 +1066,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 split4(dz1[1][c], sc, h1v, l1v);
                 const h8 bh = cat(h0, h1v), bl = cat(l0, l1v);
                 v4f df = v4f{0.f, 0.f, 0.f, 0.f};
-                df = mfma16(w1fl, bh, df);
-                df = mfma16(w1fh, bl, df);
+                if (SPLIT) {
+                    df = mfma16(w1fl, bh, df);
+                    df = mfma16(w1fh, bl, df);
+                }
                 df = mfma16(w1fh, bh, df);
                 const float un = pow2(-(meta.sw1 + g1[c]));
                 if (q < DFS / 4)
@@ -1201,6 +1222,8 @@ int check_mlp(const dvgo_color_mlp *m, bool bwd) {
     if (m->struct_size != sizeof(dvgo_color_mlp)) return set_error(DVGO_ERR_ABI, "dvgo_color_mlp.struct_size mismatch");
     if (m->hidden != H) return set_error(DVGO_ERR_UNSUPPORTED, "hidden must be %d", H);
     if (m->in_feat < 1 || m->in_feat > 12) return set_error(DVGO_ERR_UNSUPPORTED, "in_feat must be in [1, 12]");
+    if (m->precision != DVGO_MLP_SPLIT_F16 && m->precision != DVGO_MLP_F16)
+        return set_error(DVGO_ERR_UNSUPPORTED, "unknown precision %d", m->precision);
     if (m->n_freq < 0 || m->n_freq > 4) return set_error(DVGO_ERR_UNSUPPORTED, "n_freq must be in [0, 4]");
     if (!m->W1 || !m->b1 || !m->W2 || !m->b2 || !m->W3 || !m->b3) return set_error(DVGO_ERR_NULL, "a weight is NULL");
     if (bwd && (!m->gW1 || !m->gb1 || !m->gW2 || !m->gb2 || !m->gW3 || !m->gb3))
@@ -1292,7 +1315,9 @@ extern "C" int dvgo_mlp_forward(const dvgo_color_mlp *m, int32_t n_rays, const i
     if (rc) return rc;
     const int64_t nwt = (n_samples + FWD_WTILE - 1) / FWD_WTILE;
     const int64_t nb = (nwt + FWD_WAVES - 1) / FWD_WAVES;
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3((int)(nb < MAX_BLOCKS ? nb : MAX_BLOCKS)), dim3(FWD_THREADS), 0, st, a);
+    const dim3 grid((int)(nb < MAX_BLOCKS ? nb : MAX_BLOCKS));
+    if (m->precision == DVGO_MLP_F16) hipLaunchKernelGGL(mlp_fwd_kernel<false>, grid, dim3(FWD_THREADS), 0, st, a);
+    else hipLaunchKernelGGL(mlp_fwd_kernel<true>, grid, dim3(FWD_THREADS), 0, st, a);
     return check_hip(hipGetLastError(), "mlp_fwd_kernel launch");
 }
 
@@ -1309,7 +1334,10 @@ extern "C" int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const 
     hipStream_t st = (hipStream_t)stream;
     rc = launch_prep(a, st);
     if (rc) return rc;
-    hipLaunchKernelGGL(mlp_bwd_kernel, dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
+    if (m->precision == DVGO_MLP_F16)
+        hipLaunchKernelGGL(mlp_bwd_kernel<false>, dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
+    else
+        hipLaunchKernelGGL(mlp_bwd_kernel<true>, dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     rc = check_hip(hipGetLastError(), "mlp_bwd_kernel launch");
     if (rc) return rc;
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((a.n_params + 63) / 64), dim3(RED_THREADS), 0, st, a);

@@ -11,7 +11,7 @@ from typing import Optional, Sequence
 import torch
 
 from . import _lib
-from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, WARP_CONTRACT_INF, WARP_CONTRACT_L2, WARP_NONE, ColorMLP, Grid,
+from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16, WARP_CONTRACT_INF, WARP_CONTRACT_L2, WARP_NONE, ColorMLP, Grid,
                    Proposal, Rays, RenderParams, Sampler, Samples, call)
 
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
@@ -19,7 +19,8 @@ __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "r
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
            "grid_scatter", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
            "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
-           "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2"]
+           "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2",
+           "MLP_SPLIT_F16", "MLP_F16"]
 
 
 def _stream():
@@ -128,6 +129,7 @@ class MLPParams:
     gb: Optional[list] = None
     in_feat: int = 12
     n_freq: int = 4
+    precision: int = 0   # MLP_SPLIT_F16 (FP32-grade) or MLP_F16 (one FP16 product per product)
 
     def struct(self, need_grad=False) -> ColorMLP:
         for i, (w, b) in enumerate(zip(self.W, self.b)):
@@ -136,6 +138,7 @@ class MLPParams:
         m = ColorMLP()
         m.struct_size = C_size(ColorMLP)
         m.in_feat, m.n_freq, m.hidden = self.in_feat, self.n_freq, int(self.W[1].shape[0])
+        m.precision = int(self.precision)
         m.W1, m.W2, m.W3 = [_p(w) for w in self.W]
         m.b1, m.b2, m.b3 = [_p(b) for b in self.b]
         if self.gW is not None:

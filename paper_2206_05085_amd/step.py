@@ -22,13 +22,14 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 tv=None, warp=None, device="cuda"):
+                 tv=None, warp=None, mlp_precision=0, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
         tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
         term, added into the grid gradients after the backward pass.  warp: optional (mode, b):
         every grid is addressed through the Eq. 4 contraction (ops.WARP_CONTRACT_INF or
-        ops.WARP_CONTRACT_L2) and the batch holds world points."""
+        ops.WARP_CONTRACT_L2) and the batch holds world points.  mlp_precision: ops.MLP_SPLIT_F16
+        (FP32-grade colour head) or ops.MLP_F16 (the cheaper head, FP16 matrix operands)."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -55,7 +56,7 @@ class TrainStep:
                 gviews.append(self.mlp_flat["g"][o:o + t.numel()].view(t.shape))
                 o += t.numel()
             self.mlp = ops.MLPParams(views[:3], views[3:], gviews[:3], gviews[3:], in_feat=int(self.feat["p"].shape[-1]),
-                                     n_freq=n_freq)
+                                     n_freq=n_freq, precision=mlp_precision)
         self.batch = None
         self.schedule = None
 

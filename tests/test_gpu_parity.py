@@ -280,7 +280,15 @@ def test_alpha(dv):
 # ----------------------------------------------------------------------- MLP
 
 
-def _mlp_case(dv, S_lengths, seed, bias_std=0.3):
+# The cheaper colour head (FP16 matrix operands) against the oracle head that rounds the same
+# operands: they differ by FP32-vs-FP64 accumulation and by an operand that rounds to the
+# neighbouring FP16 value when the two accumulations straddle a rounding boundary (one
+# 2^-11-relative change of one term among 128): rtol 1e-4 forward, 1e-3 gradients.
+FWD16 = dict(rtol=1e-4, floor=1e-3)
+GRAD16 = dict(rtol=1e-3, floor=1e-2)
+
+
+def _mlp_case(dv, S_lengths, seed, bias_std=0.3, half=False):
     rng = np.random.default_rng(seed)
     mlp = synth.mlp_weights(rng, bias_std=bias_std)
     offs = np.concatenate([[0], np.cumsum(S_lengths)]).astype(np.int32)
@@ -293,20 +301,28 @@ def _mlp_case(dv, S_lengths, seed, bias_std=0.3):
     b = [T(v) for v in mlp.b]
     gW = [torch.zeros_like(w) for w in W]
     gb = [torch.zeros_like(v) for v in b]
-    P = dv.MLPParams(W, b, gW, gb)
+    P = dv.MLPParams(W, b, gW, gb, precision=dv.MLP_F16 if half else dv.MLP_SPLIT_F16)
     rgb = dv.mlp_forward(P, T(offs, torch.int32), T(dirs), T(feat))
     gf = dv.mlp_backward(P, T(offs, torch.int32), T(dirs), T(feat), T(grgb))
     torch.cuda.synchronize()
-    ref = oracle.mlp_forward(mlp, offs, dirs, feat.astype(np.float64))
-    rgf, rgW, rgb_ = oracle.mlp_backward(mlp, offs, dirs, feat.astype(np.float64), grgb.astype(np.float64))
+    f64, g64 = feat.astype(np.float64), grgb.astype(np.float64)
+    ref = oracle.mlp_forward(mlp, offs, dirs, f64, half=half)
+    rgf, rgW, rgb_ = oracle.mlp_backward(mlp, offs, dirs, f64, g64, half=half)
     # A hidden unit whose pre-activation lies within rounding of its ReLU kink may take
     # either side; the oracle bounds how far each gradient moves when it switches.
-    sf, sW, sb = oracle.mlp_kink_slack(mlp, offs, dirs, feat.astype(np.float64), grgb.astype(np.float64))
-    close(rgb.cpu().numpy(), ref, **FWD, name="mlp rgb")
-    close(gf.cpu().numpy(), rgf, **GRAD, name="mlp d feat", slack=sf)
+    sf, sW, sb = oracle.mlp_kink_slack(mlp, offs, dirs, f64, g64, thr=1e-4 if half else 1e-5)
+    fw, gr = (FWD16, GRAD16) if half else (FWD, GRAD)
+    close(rgb.cpu().numpy(), ref, **fw, name="mlp rgb")
+    close(gf.cpu().numpy(), rgf, **gr, name="mlp d feat", slack=sf)
     for i in range(3):
-        close(gW[i].cpu().numpy(), rgW[i], **GRAD, name=f"mlp dW{i + 1}", slack=sW[i])
-        close(gb[i].cpu().numpy(), rgb_[i], **GRAD, name=f"mlp db{i + 1}", slack=sb[i])
+        close(gW[i].cpu().numpy(), rgW[i], **gr, name=f"mlp dW{i + 1}", slack=sW[i])
+        close(gb[i].cpu().numpy(), rgb_[i], **gr, name=f"mlp db{i + 1}", slack=sb[i])
+    if half:
+        # and the cheaper head stays within FP16 rounding of the exact one
+        exact = oracle.mlp_forward(mlp, offs, dirs, f64)
+        assert np.linalg.norm(rgb.cpu().numpy() - exact) <= 4 * 2.0 ** -11 * np.linalg.norm(exact)
+        egf = oracle.mlp_backward(mlp, offs, dirs, f64, g64)[0]
+        assert np.linalg.norm(gf.cpu().numpy() - egf) <= 20 * 2.0 ** -11 * np.linalg.norm(egf)
 
 
 def test_mlp_small_ragged(dv):
@@ -317,6 +333,16 @@ def test_mlp_small_ragged(dv):
 def test_mlp_multi_block(dv):
     say("mlp ~40k samples")
     _mlp_case(dv, list(np.random.default_rng(21).integers(0, 300, 256)), seed=22)
+
+
+def test_mlp_f16_small_ragged(dv):
+    say("mlp FP16 head, 300 samples (ragged, partial tiles)")
+    _mlp_case(dv, [0, 5, 1, 64, 100, 0, 130], seed=23, half=True)
+
+
+def test_mlp_f16_multi_block(dv):
+    say("mlp FP16 head, ~40k samples")
+    _mlp_case(dv, list(np.random.default_rng(24).integers(0, 300, 256)), seed=25, half=True)
 
 
 # ---------------------------------------------------------------------- Adam
