@@ -311,12 +311,12 @@ def mlp_margin(mlp, offs, dirs, feat, F=4):
     return out
 
 
-def mlp_kink_slack(mlp, offs, dirs, feat, grad_rgb, thr=1e-5, F=4):
+def mlp_kink_slack(mlp, offs, dirs, feat, grad_rgb, thr=1e-5, F=4, half=False):
     """Per-element slack of the colour-head gradients at ReLU kinks (see orc_mlp_kink_slack).
     Returns (slack_feat [S,C], [W1, W2, W3] slacks, [b1, b2, b3] slacks)."""
     keep = _Keep()
     feat = keep(_c(feat, np.float64))
-    P = _mlp_struct(mlp, keep, feat.shape[1], F)
+    P = _mlp_struct(mlp, keep, feat.shape[1], F, half)
     offs = keep(_c(offs, np.int32))
     dirs = keep(_c(dirs, np.float32))
     gr = keep(_c(grad_rgb, np.float64))
@@ -556,3 +556,23 @@ def r16_round(x):
     out = np.zeros_like(a)
     lib().orc_r16_round(C.c_int64(a.size), _ptr(a), _ptr(out))
     return out
+
+
+def mlp_magnitudes(mlp, offs, dirs, feat, grad_rgb, F=4, half=False):
+    """Conditioning magnitudes of the colour head's outputs (orc_mlp_magnitudes): returns
+    (mag_rgb [S,3], mag_feat [S,C], [W1, W2, W3] magnitudes, [b1, b2, b3] magnitudes)."""
+    keep = _Keep()
+    feat = keep(_c(feat, np.float64))
+    P = _mlp_struct(mlp, keep, feat.shape[1], F, half)
+    offs = keep(_c(offs, np.int32))
+    dirs = keep(_c(dirs, np.float32))
+    gr = keep(_c(grad_rgb, np.float64))
+    sizes = [mlp.W[0].size, mlp.b[0].size, mlp.W[1].size, mlp.b[1].size, mlp.W[2].size, mlp.b[2].size]
+    mr = np.zeros((feat.shape[0], 3))
+    mf = np.zeros_like(feat)
+    mp = np.zeros(sum(sizes))
+    lib().orc_mlp_magnitudes(C.byref(P), C.c_int32(offs.shape[0] - 1), _ptr(offs), _ptr(dirs), _ptr(feat), _ptr(gr),
+                             _ptr(mr), _ptr(mf), _ptr(mp))
+    parts = np.split(mp, np.cumsum(sizes)[:-1])
+    W = [parts[0].reshape(mlp.W[0].shape), parts[2].reshape(mlp.W[1].shape), parts[4].reshape(mlp.W[2].shape)]
+    return mr, mf, W, [parts[1], parts[3], parts[5]]

@@ -630,7 +630,7 @@ static void mlp_sample_grads(const orc_mlp *P, const double *x, const double *g,
  * absolute change of each gradient when that unit's mask is inverted, summed over such
  * units.  Either mask is a valid (sub)gradient there, so a float32 evaluation may land on
  * either side.  slack_feat [S,C] and slack_par [n_params] (W1, b1, W2, b2, W3, b3) are
- * accumulated (+=). */
+ * accumulated (+=).  With P->half the pre-activations are those of the cheaper head. */
 void orc_mlp_kink_slack(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
                         const double *grad_rgb, double thr, double *slack_feat, double *slack_par)
 {
@@ -650,13 +650,21 @@ void orc_mlp_kink_slack(const orc_mlp *P, int32_t R, const int32_t *offs, const 
                 if (layer == 1) {
                     z = P->b1[i];
                     mag = fabs((double)P->b1[i]);
-                    for (int j = 0; j < I; ++j) { z += (double)P->W1[i * I + j] * x[j]; mag += fabs((double)P->W1[i * I + j] * x[j]); }
+                    for (int j = 0; j < I; ++j) {
+                        const double t = opnd(P, P->W1[i * I + j]) * opnd(P, x[j]);
+                        z += t;
+                        mag += fabs(t);
+                    }
                     z1[i] = z;
                     h1[i] = z > 0 ? z : 0.0;
                 } else {
                     z = P->b2[i];
                     mag = fabs((double)P->b2[i]);
-                    for (int j = 0; j < H; ++j) { z += (double)P->W2[i * H + j] * h1[j]; mag += fabs((double)P->W2[i * H + j] * h1[j]); }
+                    for (int j = 0; j < H; ++j) {
+                        const double t = opnd(P, P->W2[i * H + j]) * opnd(P, h1[j]);
+                        z += t;
+                        mag += fabs(t);
+                    }
                 }
                 if (!(mag > 0 && fabs(z) < thr * mag)) continue;
                 if (!computed) { mlp_sample_grads(P, x, grad_rgb + 3 * k, 0, 0, a); computed = 1; }
@@ -666,6 +674,76 @@ void orc_mlp_kink_slack(const orc_mlp *P, int32_t R, const int32_t *offs, const 
             }
     }
     free(x); free(a); free(b); free(z1); free(h1);
+}
+
+/* Magnitudes the colour head's outputs are conditioned on: the forward and backward passes
+ * re-run with every weight, activation and gradient replaced by its absolute value (ReLU masks
+ * and the sigmoid slope taken from the true evaluation).  A relative perturbation e of every
+ * matrix operand moves each output by at most a small multiple of e times its magnitude, to
+ * first order; a cancelling output (|y| much smaller than its magnitude) is sensitive in
+ * proportion.  Writes mag_rgb [S,3] and mag_feat [S,C]; accumulates mag_par [n_params] (W1,
+ * b1, W2, b2, W3, b3 order) with += .  Operands are those of P (P->half rounds them). */
+void orc_mlp_magnitudes(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
+                        const double *grad_rgb, double *mag_rgb, double *mag_feat, double *mag_par)
+{
+    int64_t S = offs[R];
+    int I = P->C + 3 + 6 * P->F, H = P->H;
+    double *gW1 = mag_par, *gb1 = gW1 + (int64_t)H * I, *gW2 = gb1 + H, *gb2 = gW2 + (int64_t)H * H, *gW3 = gb2 + H,
+           *gb3 = gW3 + 3 * H;
+    double *x = malloc(sizeof(double) * I), *ax = malloc(sizeof(double) * I);
+    double *z1 = malloc(sizeof(double) * H), *h1 = malloc(sizeof(double) * H);
+    double *z2 = malloc(sizeof(double) * H), *h2 = malloc(sizeof(double) * H);
+    double *A1 = malloc(sizeof(double) * H), *A2 = malloc(sizeof(double) * H);
+    double *D1 = malloc(sizeof(double) * H), *D2 = malloc(sizeof(double) * H);
+    double rgb[3], D3[3];
+    for (int64_t k = 0; k < S; ++k) {
+        int64_t r = find_ray(R, offs, k);
+        for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
+        view_pe(dirs + 3 * r, P->F, x + P->C);
+        mlp_fwd_one(P, x, z1, h1, z2, h2, rgb);
+        for (int j = 0; j < I; ++j) ax[j] = fabs(opnd(P, x[j]));
+        for (int i = 0; i < H; ++i) {
+            double a = fabs((double)P->b1[i]);
+            for (int j = 0; j < I; ++j) a += fabs(opnd(P, P->W1[i * I + j])) * ax[j];
+            A1[i] = z1[i] > 0 ? a : 0.0;
+        }
+        for (int i = 0; i < H; ++i) {
+            double a = fabs((double)P->b2[i]);
+            for (int j = 0; j < H; ++j) a += fabs(opnd(P, P->W2[i * H + j])) * A1[j];
+            A2[i] = z2[i] > 0 ? a : 0.0;
+        }
+        for (int o = 0; o < 3; ++o) {
+            double a = fabs((double)P->b3[o]);
+            for (int j = 0; j < H; ++j) a += fabs((double)P->W3[o * H + j]) * A2[j];
+            const double slope = rgb[o] * (1.0 - rgb[o]);
+            mag_rgb[3 * k + o] = slope * a;
+            D3[o] = fabs(grad_rgb[3 * k + o]) * slope;
+            gb3[o] += D3[o];
+            for (int j = 0; j < H; ++j) gW3[o * H + j] += D3[o] * A2[j];
+        }
+        for (int j = 0; j < H; ++j) {
+            double t = 0.0;
+            for (int o = 0; o < 3; ++o) t += fabs((double)P->W3[o * H + j]) * D3[o];
+            D2[j] = z2[j] > 0 ? t : 0.0;
+            gb2[j] += D2[j];
+        }
+        for (int i = 0; i < H; ++i)
+            for (int j = 0; j < H; ++j) gW2[i * H + j] += D2[i] * A1[j];
+        for (int j = 0; j < H; ++j) {
+            double t = 0.0;
+            for (int i = 0; i < H; ++i) t += fabs(opnd(P, P->W2[i * H + j])) * D2[i];
+            D1[j] = z1[j] > 0 ? t : 0.0;
+            gb1[j] += D1[j];
+        }
+        for (int i = 0; i < H; ++i)
+            for (int j = 0; j < I; ++j) gW1[i * I + j] += D1[i] * ax[j];
+        for (int c = 0; c < P->C; ++c) {
+            double t = 0.0;
+            for (int i = 0; i < H; ++i) t += fabs(opnd(P, P->W1[i * I + c])) * D1[i];
+            mag_feat[k * P->C + c] = t;
+        }
+    }
+    free(x); free(ax); free(z1); free(h1); free(z2); free(h2); free(A1); free(A2); free(D1); free(D2);
 }
 
 /* Backward of the colour head for upstream grad_rgb [S,3]: writes grad_feat [S,C] and

@@ -15,7 +15,7 @@ FWD = dict(rtol=1e-5, floor=1e-3)
 GRAD = dict(rtol=1e-4, floor=1e-2)
 
 
-def close(x, y, rtol, floor, name="value", scale=None, skip=None, slack=None):
+def close(x, y, rtol, floor, name="value", scale=None, skip=None, slack=None, elem_rtol=None):
     """scale (optional, per element): the magnitude the result is conditioned on, e.g.
     sum_c w_c |G_c| for an interpolated value whose terms cancel; the elementwise bound
     then uses max(|y_i|, floor * ||y||_inf, scale_i).  skip (optional boolean mask):
@@ -23,7 +23,8 @@ def close(x, y, rtol, floor, name="value", scale=None, skip=None, slack=None):
     left out of the elementwise check; the normwise check still covers them.  slack
     (optional, per element): an absolute allowance added to the elementwise bound, e.g. the
     change a gradient sees when a ReLU unit at its kink switches side; its 2-norm is added to
-    the normwise bound as well."""
+    the normwise bound as well.  elem_rtol (optional): a separate relative bound for the
+    elementwise check (the normwise check keeps rtol)."""
     x = np.asarray(x, np.float64).ravel()
     y = np.asarray(y, np.float64).ravel()
     assert x.shape == y.shape, f"{name}: shape {x.shape} vs {y.shape}"
@@ -34,16 +35,18 @@ def close(x, y, rtol, floor, name="value", scale=None, skip=None, slack=None):
     ns = np.linalg.norm(np.asarray(slack, np.float64)) if slack is not None else 0.0
     assert err <= rtol * ny + ns + 1e-30, f"{name}: normwise error {err / max(ny, 1e-300):.3e} > {rtol}"
     if y.size:
-        bound = rtol * np.maximum(np.abs(y), floor * np.abs(y).max())
+        er = rtol if elem_rtol is None else elem_rtol
+        bound = er * np.maximum(np.abs(y), floor * np.abs(y).max())
         if scale is not None:
-            bound = np.maximum(bound, rtol * np.asarray(scale, np.float64).ravel())
+            bound = np.maximum(bound, er * np.asarray(scale, np.float64).ravel())
         bad = np.abs(x - y) > bound + 1e-30
         if slack is not None:
             bad &= np.abs(x - y) > bound + np.asarray(slack, np.float64).ravel()
         if skip is not None:
             bad &= ~np.asarray(skip, bool).ravel()
         if bad.any():
-            i = np.argmax(np.abs(x - y) - bound)
+            excess = np.abs(x - y) - bound - (0.0 if slack is None else np.asarray(slack, np.float64).ravel())
+            i = np.argmax(np.where(bad, excess, -np.inf))
             raise AssertionError(f"{name}: {bad.sum()} of {y.size} elements out of bound; worst at {i}: "
                                  f"gpu {x[i]:.9g} oracle {y[i]:.9g} bound {bound[i]:.3g}")
     return err / max(ny, 1e-300)

@@ -119,6 +119,33 @@ def test_half_mlp_matches_torch(orc):
     assert 0 < np.linalg.norm(gf - egf) <= 20 * 2.0 ** -11 * np.linalg.norm(egf)
 
 
+@pytest.mark.parametrize("half", [False, True])
+def test_mlp_magnitudes(orc, half):
+    # an upper bound of every output's absolute value, and equal to it when nothing cancels:
+    # non-negative weights, inputs and output gradients (the view encoding is made positive by
+    # a direction with all components in (0, pi/16), so every sine and cosine is positive)
+    rng = np.random.default_rng(45)
+    mlp = synth.mlp_weights(rng, bias_std=0.3)
+    offs = np.array([0, 9, 9, 30], np.int32)
+    S = int(offs[-1])
+    dirs = synth.scenes._unit(rng.standard_normal((3, 3))).astype(np.float32)
+    feat = rng.standard_normal((S, 12))
+    g = rng.standard_normal((S, 3))
+    mr, mf, mW, mb = orc.mlp_magnitudes(mlp, offs, dirs, feat, g, half=half)
+    gf, gW, gb = orc.mlp_backward(mlp, offs, dirs, feat, g, half=half)
+    assert (mf >= np.abs(gf) * (1 - 1e-12)).all()
+    for m, v in zip(mW + mb, gW + gb):
+        assert (m >= np.abs(v) * (1 - 1e-12)).all()
+    pos = synth.MLPWeights([np.abs(w) for w in mlp.W], [np.abs(b) for b in mlp.b])
+    dpos = np.full((3, 3), 0.15, np.float32)
+    mr, mf, mW, mb = orc.mlp_magnitudes(pos, offs, dpos, np.abs(feat), np.abs(g), half=half)
+    gf, gW, gb = orc.mlp_backward(pos, offs, dpos, np.abs(feat), np.abs(g), half=half)
+    np.testing.assert_allclose(mf, gf, rtol=1e-12)
+    for m, v in zip(mW + mb, gW + gb):
+        np.testing.assert_allclose(m, v, rtol=1e-12, atol=1e-300)
+    assert (mr >= 0).all() and np.isfinite(mr).all()
+
+
 def test_adam_matches_torch_and_skips_zero(orc):
     rng = np.random.default_rng(41)
     n = 1000
