@@ -520,7 +520,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
 //   A  P: layer 1 of t -> h1 B operand, h1^T, mask bits    C: dz1, dfeat partials, dz1^T of t-1
 //   B  P: layer 2 of t -> h2, logit partials                C: dW1 += dz1^T x of t-1; loads of t+1
 //   C  P: dz3, dz2 of t -> dz2 B operand, dz2^T (frame)     C: dz3, exponents, dW3 b2 b3 sums of t
-//   D  P: dW2 += dz2^T h1 of t                              C: feature gradient of t-1; stage t+1
+//   D  P: dW2 += dz2^T h1 of t; feature gradient of t-1     C: stage t+1
 // After the last tile one more A/B pair finishes the C side.  Both roles run the same
 // number of barriers, so s_barrier stays matched.
 
@@ -581,6 +581,18 @@ __device__ __forceinline__ void put_t(unsigned char *base, int off_h, int off_l,
 
 __device__ __forceinline__ void store_h4(unsigned char *base, int off, int idx, h4 v) {
     *reinterpret_cast<h4 *>(reinterpret_cast<_Float16 *>(base + off) + idx) = v;
+}
+
+// Feature gradient of a finished tile: the partials of the four C waves, summed in a fixed
+// order; t = the calling thread's index within its 256-thread role.
+__device__ __forceinline__ void feat_grad_out(const MlpArgs &a, const float *dfp, int pbase, int t) {
+    for (int i = t; i < NT * a.in_feat; i += 256) {
+        const int sl = i / a.in_feat, c = i % a.in_feat;
+        const int s = pbase + sl;
+        if (s < a.S)
+            a.grad_feat[(int64_t)s * a.in_feat + c] = dfp[(0 * NT + sl) * DFS + c] + dfp[(1 * NT + sl) * DFS + c] +
+                                                      dfp[(2 * NT + sl) * DFS + c] + dfp[(3 * NT + sl) * DFS + c];
+    }
 }
 
 // Per-sample quantities every wave derives identically from LDS (columns c: sample 16c + j)
@@ -887,6 +899,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     dW2[mp][n] = mfma16(ah, bh, dW2[mp][n]);
                 }
             }
+            // feature gradient of the previous tile (its partials came from the C waves' phase A)
+            if (it > 0) feat_grad_out(a, dfp, (tile - (int)gridDim.x) * NT, tid);
             __syncthreads();
         }
         // the C side's last A/B pair
@@ -973,17 +987,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             }
             if (xg == 0) xmax_b[pb * NT + xsl] = m;
             if (xg < 4) gr_b[(pb * NT + xsl) * 4 + xg] = grv;
-        };
-        // feature gradient of a finished tile (partials of the four C waves, fixed order)
-        auto feat_out = [&](int pbase) {
-            for (int i = ct; i < NT * a.in_feat; i += 256) {
-                const int sl = i / a.in_feat, c = i % a.in_feat;
-                const int s = pbase + sl;
-                if (s < a.S)
-                    a.grad_feat[(int64_t)s * a.in_feat + c] = dfp[(0 * NT + sl) * DFS + c] +
-                                                              dfp[(1 * NT + sl) * DFS + c] +
-                                                              dfp[(2 * NT + sl) * DFS + c] + dfp[(3 * NT + sl) * DFS + c];
-            }
         };
         // dW1 += dz1^T x of a finished tile (its x^T buffer pb)
         auto dw1_step = [&](int pb) {
@@ -1136,8 +1139,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
             }
             __syncthreads();
-            // ---- D: feature gradient of the previous tile; the next tile's inputs -> x planes
-            if (pbase >= 0) feat_out(pbase);
+            // ---- D: the next tile's inputs -> x planes (the P waves write the previous tile's
+            //      feature gradient meanwhile)
             if (next) stage_tile(pb ^ 1);
             __syncthreads();
             pbase = tile * NT;
@@ -1147,7 +1150,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         __syncthreads();
         if (pbase >= 0) {
             dw1_step((it - 1) & 1);
-            feat_out(pbase);
+            feat_grad_out(a, dfp, pbase, ct);
         }
         __syncthreads();
         // ---- partial gradients of the C role: W1, b1, b2, W3, b3
