@@ -577,8 +577,11 @@ def main():
                                                  out=(st.rgb, st.T, st.dist), state=st.state),
         "loss": lambda: ops.loss_head(st.rgb, st.target, st.dist, st.lam, loss=st.loss, grad_rgb=st.g_rgb,
                                       grad_dist=st.g_dist),
+        "bin": lambda: ops.bin_samples(st.grid("density"), batch.xyz, ws=st.bin_ws),
         "render_bwd": lambda: ops.render_backward(batch, st.grid("density"), None, st.rgb_s, st.T, st.state, st.g_rgb,
-                                                  st.g_dist, None, act_shift_=st.shift, grad_sample_rgb=st.g_rgb_s),
+                                                  st.g_dist, None, act_shift_=st.shift, grad_sample_rgb=st.g_rgb_s,
+                                                  grad_sample_density=st.g_raw),
+        "scatter_density": lambda: ops.grid_scatter_binned(st.grid("density"), batch.xyz, st.g_raw, st.bin_ws),
         "mlp_bwd": lambda: ops.mlp_backward(st.mlp, batch.ray_offsets, st.dirs, st.feat_s, st.g_rgb_s,
                                             grad_feat=st.g_feat_s, ws=st.mlp_ws),
         "scatter": lambda: ops.grid_scatter(st.grid("feat"), batch.xyz, st.g_feat_s),
@@ -627,7 +630,8 @@ def main():
 
     # ---- roofline of the dominant stage
     U = unique_vertices(smp.xyz, n, lo, hi)
-    b_render = {"render_fwd": S * 36 + U * 4 + R * 24, "render_bwd": S * 48 + U * 12 + R * 24}
+    b_render = {"render_fwd": S * 36 + U * 4 + R * 24, "render_bwd": S * 52 + U * 4 + R * 24,
+                "scatter_density": S * 20 + U * 8}
     mlp_bwd_flops = S * mlp_flops_per_sample(True)
     mlp_fwd_flops = S * mlp_flops_per_sample(False)
     dom = max(stage_ms, key=stage_ms.get)
@@ -646,9 +650,10 @@ def main():
         ach = by / (stage_ms[dom] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
-    rt = stage_ms["render_fwd"] + stage_ms["render_bwd"]
-    r_bytes = b_render["render_fwd"] + b_render["render_bwd"]
-    roof_render = {"kernels": "render_fwd + render_bwd (density gather, alpha, compositing, distortion, scatter)",
+    rt = stage_ms["render_fwd"] + stage_ms["render_bwd"] + stage_ms["scatter_density"]
+    r_bytes = b_render["render_fwd"] + b_render["render_bwd"] + b_render["scatter_density"]
+    roof_render = {"kernels": "render_fwd + render_bwd + scatter_density (density gather, alpha, compositing, "
+                              "distortion, per-sample density gradient, brick scatter)",
                    "bound": "hbm", "achieved": round(r_bytes / (rt * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(r_bytes / (rt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                    "algorithmic_bytes": int(r_bytes), "unique_density_vertices": U}

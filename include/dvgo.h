@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DVGO_ABI_VERSION 2
+#define DVGO_ABI_VERSION 3
 
 enum {
     DVGO_OK = 0,
@@ -173,11 +173,15 @@ int dvgo_render_forward(const dvgo_render_params *p, const dvgo_samples *s, cons
  * Writes: density->grad += dL/d(density values); in grid mode color->grad += dL/d(colour
  * values); in sample mode grad_sample_rgb [S,3] = dL/dc (overwritten; zero for halted
  * samples).  The derivative of the distortion term follows Eq. 3 (its third sum read as
- * w_i m_i) plus the derivative of Eq. 1's second term, (2/3) w_k s_len_k. */
+ * w_i m_i) plus the derivative of Eq. 1's second term, (2/3) w_k s_len_k.
+ * grad_sample_density [S] (may be NULL): when given, the kernel writes dL/d(raw_k), the
+ * gradient with respect to each sample's interpolated density logit (zero for halted
+ * samples), INSTEAD of adding into density->grad (which may then be NULL); the caller
+ * scatters it, e.g. with dvgo_grid_scatter_binned. */
 int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
                          const dvgo_grid *color, const float *sample_rgb, const float *T_final, const void *state,
                          size_t state_bytes, const float *grad_rgb, const float *grad_dist, const float *grad_T,
-                         float *grad_sample_rgb, void *stream);
+                         float *grad_sample_rgb, float *grad_sample_density, void *stream);
 
 /* Schedule of a ragged batch: order [R] = the rays sorted by decreasing number of 64-sample
  * chunks (ceil(length/64), lengths above 63 chunks share the last class; order within a
@@ -243,6 +247,20 @@ int dvgo_grid_gather(const dvgo_grid *g, int64_t n_samples, const float *xyz, fl
 /* Adjoint of dvgo_grid_gather: g->grad += scatter of grad_out [S, channels]. */
 int dvgo_grid_scatter(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
                       void *stream);
+
+/* Brick-binned scatter (the same sum as dvgo_grid_scatter, organised for few, coalesced global
+ * atomics).  dvgo_bin_samples sorts the samples by the 8^3-cell brick of the grid that holds
+ * their cell (a counting sort into the caller's workspace of dvgo_bin_workspace_size bytes,
+ * 256-byte aligned); dvgo_grid_scatter_binned then adds grad->g += trilinear^T(grad_out) brick
+ * by brick, accumulating each brick in on-chip memory first.  The workspace must hold the bins
+ * of the same grid geometry (shape, box, warp) and the same xyz; grids with equal geometry can
+ * share one binning.  Bins depend only on the points, so one binning serves every scatter of a
+ * step. */
+int dvgo_bin_workspace_size(const dvgo_grid *g, int64_t n_samples, size_t *bytes);
+int dvgo_bin_samples(const dvgo_grid *g, int64_t n_samples, const float *xyz, void *ws, size_t ws_bytes,
+                     void *stream);
+int dvgo_grid_scatter_binned(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
+                             const void *ws, size_t ws_bytes, void *stream);
 
 /* Per-sample alpha of the density path only (trilinear, softplus shift, 1 - exp(-sigma delta)):
  * alpha [S].  Used for the coarse samples of the proposal stage. */

@@ -9,7 +9,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdvgo.so")
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 VP = C.c_void_p
 OK = 0
@@ -77,7 +77,7 @@ SIGNATURES = {
     "dvgo_last_error": (C.c_char_p, []),
     "dvgo_render_state_size": (C.c_int, [_I32, _I64, _SZP]),
     "dvgo_render_forward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
-    "dvgo_render_backward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, C.c_size_t, VP, VP, VP, VP, VP]),
+    "dvgo_render_backward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, C.c_size_t, VP, VP, VP, VP, VP, VP]),
     "dvgo_ray_schedule": (C.c_int, [_I32, VP, VP, VP, VP]),
     "dvgo_render_autotune": (C.c_int, [_PP, _PS, _PG, _PG, VP, C.POINTER(_I32), C.POINTER(_I32),
                                        C.POINTER(C.c_float), VP]),
@@ -87,6 +87,9 @@ SIGNATURES = {
     "dvgo_counter_add": (C.c_int, [VP, _I32, VP]),
     "dvgo_grid_gather": (C.c_int, [_PG, _I64, VP, VP, VP]),
     "dvgo_grid_scatter": (C.c_int, [_PG, _I64, VP, VP, VP]),
+    "dvgo_bin_workspace_size": (C.c_int, [_PG, _I64, _SZP]),
+    "dvgo_bin_samples": (C.c_int, [_PG, _I64, VP, VP, C.c_size_t, VP]),
+    "dvgo_grid_scatter_binned": (C.c_int, [_PG, _I64, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_tv_add_grad": (C.c_int, [_PG, _F, _F, _I32, VP]),
     "dvgo_alpha": (C.c_int, [_PG, _I64, VP, VP, _F, VP, VP]),
     "dvgo_mlp_workspace_size": (C.c_int, [_PM, _I32, _I64, _SZP]),

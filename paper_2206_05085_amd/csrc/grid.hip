@@ -490,3 +490,299 @@ extern "C" int dvgo_tv_add_grad(const dvgo_grid *g, float weight, float delta, i
                            dense ? 1 : 0, nvert, nblocks);
     return check_hip(hipGetLastError(), "tv_kernel launch");
 }
+
+// ------------------------------------------------------------------ brick-binned scatter
+//
+// The scatter of per-sample values into a grid, re-organised so that the global atomics are
+// few and coalesced.  Samples are binned by the 8^3-cell brick that holds their cell (a
+// counting sort: counts, an exclusive prefix, placement); then one block per brick adds its
+// samples' trilinear contributions into a 9^3-vertex LDS tile with LDS atomics and flushes the
+// tile with one global atomic per touched vertex channel, consecutive lanes on consecutive
+// addresses.  Consecutive samples lie along one ray and share a brick, so the counting passes
+// aggregate each run of equal bricks in the wave into one atomic.
+
+namespace {
+
+constexpr int BRICK = 8;            // cells per brick edge
+constexpr int BV = BRICK + 1;       // vertices per brick edge
+constexpr int BIN_WAVES = 4;
+
+struct BinGeom {
+    int nb[3];  // bricks per axis
+    int n;      // bricks
+};
+
+BinGeom bin_geom(const DevGrid &g) {
+    BinGeom b;
+    b.n = 1;
+    for (int a = 0; a < 3; ++a) {
+        b.nb[a] = (g.n[a] - 1 + BRICK - 1) / BRICK;
+        b.n *= b.nb[a];
+    }
+    return b;
+}
+
+__device__ __forceinline__ int brick_of(const BinGeom &b, const Cell &c) {
+    return ((c.ix / BRICK) * b.nb[1] + c.iy / BRICK) * b.nb[2] + c.iz / BRICK;
+}
+
+struct BinWs {
+    int *offs;    // [n + 1] first slot of each brick in perm
+    int *cursor;  // [n] counts, then placement cursors
+    int *perm;    // [S] sample indices grouped by brick
+};
+
+size_t bin_bytes(int nb, int64_t S, size_t *o_cursor, size_t *o_perm) {
+    size_t o = align_up((size_t)(nb + 1) * 4, 256);
+    *o_cursor = o;
+    o += align_up((size_t)nb * 4, 256);
+    *o_perm = o;
+    o += (size_t)S * 4;
+    return o;
+}
+
+__global__ __launch_bounds__(256) void bin_zero_kernel(int *p, int n) {
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
+}
+
+// Runs of equal keys among the lanes of a wave: the head of each run (key >= 0) learns the run
+// length; every lane learns its run's head.
+struct Run {
+    bool head;
+    int len, head_lane;
+};
+
+__device__ __forceinline__ Run wave_runs(int key) {
+    const int ln = lane();
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = key >= 0 && (ln == 0 || prev != key);
+    const bool start = ln == 0 || prev != key;  // a run boundary (invalid lanes start runs too)
+    const unsigned long long starts = __ballot(start);
+    const unsigned long long after = ln == 63 ? 0ull : starts & (~0ull << (ln + 1));
+    const int next = after ? __ffsll((long long)after) - 1 : 64;
+    const unsigned long long upto = starts & (ln == 63 ? ~0ull : ((2ull << ln) - 1));
+    Run r;
+    r.head = head;
+    r.len = next - ln;
+    r.head_lane = 63 - __clzll((long long)upto);
+    return r;
+}
+
+template <bool W>
+__global__ __launch_bounds__(64 * BIN_WAVES) void bin_count_kernel(DevGrid g, BinGeom bg, int64_t S,
+                                                                 const float *__restrict__ xyz, int *cnt) {
+    const int64_t nwaves = (int64_t)gridDim.x * BIN_WAVES;
+    for (int64_t base = (int64_t)(blockIdx.x * BIN_WAVES + (threadIdx.x >> 6)) * 64; base < S; base += nwaves * 64) {
+        const int64_t k = base + lane();
+        int key = -1;
+        if (k < S) key = brick_of(bg, cell_of<W>(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]));
+        const Run run = wave_runs(key);
+        if (run.head) atomicAdd(&cnt[key], run.len);
+    }
+}
+
+// offs = exclusive prefix of cnt (one block); cnt is reset to zero for the placement cursors
+__global__ __launch_bounds__(1024) void bin_scan_kernel(int n, int *cnt, int *offs) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int c = i < n ? cnt[i] : 0;
+        int v = c;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(v, d, 64);
+            if (lane() >= d) v += t;
+        }
+        if (lane() == 63) wsum[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            int w = wsum[threadIdx.x];
+#pragma unroll
+            for (int d = 1; d < 16; d <<= 1) {
+                const int t = __shfl_up(w, d, 16);
+                if ((int)threadIdx.x >= d) w += t;
+            }
+            wsum[threadIdx.x] = w;
+        }
+        __syncthreads();
+        const int below = (threadIdx.x >> 6) ? wsum[(threadIdx.x >> 6) - 1] : 0;
+        if (i < n) {
+            offs[i] = carry + below + v - c;
+            cnt[i] = 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            carry += wsum[15];
+            if (base + 1024 >= n) offs[n] = carry;
+        }
+        __syncthreads();
+    }
+    if (n == 0 && threadIdx.x == 0) offs[0] = 0;
+}
+
+template <bool W>
+__global__ __launch_bounds__(64 * BIN_WAVES) void bin_place_kernel(DevGrid g, BinGeom bg, int64_t S,
+                                                                 const float *__restrict__ xyz, const int *offs,
+                                                                 int *cursor, int *perm) {
+    const int64_t nwaves = (int64_t)gridDim.x * BIN_WAVES;
+    for (int64_t base = (int64_t)(blockIdx.x * BIN_WAVES + (threadIdx.x >> 6)) * 64; base < S; base += nwaves * 64) {
+        const int64_t k = base + lane();
+        int key = -1;
+        if (k < S) key = brick_of(bg, cell_of<W>(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]));
+        const Run run = wave_runs(key);
+        int start = 0;
+        if (run.head) start = atomicAdd(&cursor[key], run.len);
+        start = __shfl(start, run.head_lane, 64);
+        if (key >= 0) perm[offs[key] + start + (lane() - run.head_lane)] = (int)k;
+    }
+}
+
+// One block per brick: LDS tile of BV^3 vertices x NC channels, channel-major with a padded
+// plane (TPL floats) so that the lanes of one LDS atomic, which hold different vertices of
+// one channel, spread over the banks.  Thread = (sample, corner).
+constexpr int TPL = BV * BV * BV + 8;  // 737: odd stride between channel planes
+
+template <int NC, bool W>
+__global__ __launch_bounds__(256) void brick_scatter_kernel(DevGrid g, BinGeom bg, const float *__restrict__ xyz,
+                                                            const float *__restrict__ vals, const int *offs,
+                                                            const int *perm) {
+    __shared__ float tile[TPL * NC];
+    const int b = blockIdx.x;
+    const int beg = offs[b], end = offs[b + 1];
+    if (beg == end) return;
+    const int bz = b % bg.nb[2], by = (b / bg.nb[2]) % bg.nb[1], bx = b / (bg.nb[2] * bg.nb[1]);
+    const int x0 = bx * BRICK, y0 = by * BRICK, z0 = bz * BRICK;
+    for (int i = threadIdx.x; i < TPL * NC; i += 256) tile[i] = 0.f;
+    __syncthreads();
+    // thread = sample: every sample of the brick has its loads in flight at once
+    for (int i = beg + threadIdx.x; i < end; i += 256) {
+        const int s = perm[i];
+        const Cell c = cell_of<W>(g, xyz[3 * (int64_t)s], xyz[3 * (int64_t)s + 1], xyz[3 * (int64_t)s + 2]);
+        const float *src = vals + (int64_t)s * g.C;
+        float val[NC];
+#pragma unroll
+        for (int ch = 0; ch < NC; ++ch) val[ch] = ch < g.C ? src[ch] : 0.f;
+        const int v0 = ((c.ix - x0) * BV + (c.iy - y0)) * BV + (c.iz - z0);
+#pragma unroll
+        for (int corner = 0; corner < 8; ++corner) {
+            const int dx = (corner >> 2) & 1, dy = (corner >> 1) & 1, dz = corner & 1;
+            const float w = corner_weight(c, dx, dy, dz);
+            const int v = v0 + (dx * BV + dy) * BV + dz;
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch)
+                if (ch < g.C) atomicAdd(&tile[ch * TPL + v], w * val[ch]);
+        }
+    }
+    __syncthreads();
+    // flush in memory order (channel fastest) so consecutive lanes hit consecutive addresses
+    for (int i = threadIdx.x; i < BV * BV * BV * NC; i += 256) {
+        const int v = i / NC, ch = i - v * NC;
+        const float t = tile[ch * TPL + v];
+        if (t == 0.f) continue;
+        const int lz = v % BV, ly = (v / BV) % BV, lx = v / (BV * BV);
+        const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+        if (gx < g.n[0] && gy < g.n[1] && gz < g.n[2])
+            unsafeAtomicAdd(g.grad + (int64_t)gx * g.sx + (int64_t)gy * g.sy + (int64_t)gz * g.cs + ch, t);
+    }
+}
+
+template <int NC>
+void launch_brick_scatter(const DevGrid &dg, const BinGeom &bg, const float *xyz, const float *vals, const BinWs &w,
+                          hipStream_t st) {
+    if (dg.warp)
+        hipLaunchKernelGGL((brick_scatter_kernel<NC, true>), dim3(bg.n), dim3(256), 0, st, dg, bg, xyz, vals, w.offs,
+                           w.perm);
+    else
+        hipLaunchKernelGGL((brick_scatter_kernel<NC, false>), dim3(bg.n), dim3(256), 0, st, dg, bg, xyz, vals,
+                           w.offs, w.perm);
+}
+
+int bin_setup(const dvgo_grid *g, int64_t S, const void *ws, size_t ws_bytes, DevGrid &dg, BinGeom &bg, BinWs &w,
+              bool need_grad) {
+    int rc = make_dev_grid(g, "grid", &dg, need_grad);
+    if (rc) return rc;
+    if (S < 0) return set_error(DVGO_ERR_SHAPE, "negative n_samples");
+    if (S >= ((int64_t)1 << 31)) return set_error(DVGO_ERR_RANGE, "n_samples must be below 2^31");
+    bg = bin_geom(dg);
+    size_t oc, op;
+    const size_t need = bin_bytes(bg.n, S, &oc, &op);
+    if (!ws || ws_bytes < need) return set_error(DVGO_ERR_WORKSPACE, "bin workspace too small (%zu < %zu)", ws_bytes, need);
+    if (((uintptr_t)ws & 255) != 0) return set_error(DVGO_ERR_SHAPE, "bin workspace must be 256-byte aligned");
+    w.offs = (int *)ws;
+    w.cursor = (int *)((char *)ws + oc);
+    w.perm = (int *)((char *)ws + op);
+    return DVGO_OK;
+}
+
+int bin_blocks(int64_t S) {
+    const int64_t b = (S + 64 * BIN_WAVES - 1) / (64 * BIN_WAVES);
+    return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+}  // namespace
+
+extern "C" int dvgo_bin_workspace_size(const dvgo_grid *g, int64_t n_samples, size_t *bytes) {
+    DevGrid dg;
+    int rc = make_dev_grid(g, "grid", &dg, false);
+    if (rc) return rc;
+    if (!bytes) return set_error(DVGO_ERR_NULL, "bytes is NULL");
+    if (n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_samples");
+    size_t a, b;
+    *bytes = bin_bytes(bin_geom(dg).n, n_samples, &a, &b);
+    return DVGO_OK;
+}
+
+extern "C" int dvgo_bin_samples(const dvgo_grid *g, int64_t n_samples, const float *xyz, void *ws, size_t ws_bytes,
+                                void *stream) {
+    DevGrid dg;
+    BinGeom bg;
+    BinWs w;
+    int rc = bin_setup(g, n_samples, ws, ws_bytes, dg, bg, w, false);
+    if (rc) return rc;
+    if (n_samples > 0 && !xyz) return set_error(DVGO_ERR_NULL, "xyz is NULL");
+    const hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(bin_zero_kernel, dim3((bg.n + 255) / 256 < 1024 ? (bg.n + 255) / 256 : 1024), dim3(256), 0, st,
+                       w.cursor, bg.n);
+    const int nb = bin_blocks(n_samples);
+    if (n_samples > 0) {
+        if (dg.warp)
+            hipLaunchKernelGGL(bin_count_kernel<true>, dim3(nb), dim3(64 * BIN_WAVES), 0, st, dg, bg, n_samples, xyz,
+                               w.cursor);
+        else
+            hipLaunchKernelGGL(bin_count_kernel<false>, dim3(nb), dim3(64 * BIN_WAVES), 0, st, dg, bg, n_samples, xyz,
+                               w.cursor);
+    }
+    hipLaunchKernelGGL(bin_scan_kernel, dim3(1), dim3(1024), 0, st, bg.n, w.cursor, w.offs);
+    if (n_samples > 0) {
+        if (dg.warp)
+            hipLaunchKernelGGL(bin_place_kernel<true>, dim3(nb), dim3(64 * BIN_WAVES), 0, st, dg, bg, n_samples, xyz,
+                               w.offs, w.cursor, w.perm);
+        else
+            hipLaunchKernelGGL(bin_place_kernel<false>, dim3(nb), dim3(64 * BIN_WAVES), 0, st, dg, bg, n_samples, xyz,
+                               w.offs, w.cursor, w.perm);
+    }
+    return check_hip(hipGetLastError(), "bin kernels launch");
+}
+
+extern "C" int dvgo_grid_scatter_binned(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
+                                        const void *ws, size_t ws_bytes, void *stream) {
+    DevGrid dg;
+    BinGeom bg;
+    BinWs w;
+    int rc = bin_setup(g, n_samples, ws, ws_bytes, dg, bg, w, true);
+    if (rc) return rc;
+    if (n_samples == 0) return DVGO_OK;
+    if (!xyz || !grad_out) return set_error(DVGO_ERR_NULL, "xyz or grad_out is NULL");
+    const hipStream_t st = (hipStream_t)stream;
+    const int C = g->channels;
+    if (C == 1) launch_brick_scatter<1>(dg, bg, xyz, grad_out, w, st);
+    else if (C <= 3) launch_brick_scatter<3>(dg, bg, xyz, grad_out, w, st);
+    else if (C <= 4) launch_brick_scatter<4>(dg, bg, xyz, grad_out, w, st);
+    else if (C <= 8) launch_brick_scatter<8>(dg, bg, xyz, grad_out, w, st);
+    else if (C <= 12) launch_brick_scatter<12>(dg, bg, xyz, grad_out, w, st);
+    else launch_brick_scatter<16>(dg, bg, xyz, grad_out, w, st);
+    return check_hip(hipGetLastError(), "brick_scatter_kernel launch");
+}

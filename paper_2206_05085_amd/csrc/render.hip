@@ -48,6 +48,7 @@ struct RenderArgs {
     // backward
     const float *T_in, *grad_rgb, *grad_dist, *grad_T;
     float *grad_srgb;
+    float *grad_raw;  // per-sample density-logit gradient (written instead of the density scatter)
     // schedule: rays ray_list[0..n_list) (identity when NULL), taken by the waves of the grid
     // in turn (wave i handles entries i, i + n_waves, ...)
     const int *ray_list;
@@ -182,6 +183,8 @@ __device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
             a.grad_srgb[3 * k + 2] = 0.f;
         }
     }
+    if (a.grad_raw)
+        for (int k = hend + ln; k < end; k += 64) a.grad_raw[k] = 0.f;
     if (hend <= beg) return;
     const int nch = (hend - beg + 63) / 64;
     const float b = a.act_shift;
@@ -210,8 +213,12 @@ __device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
         const float gwr = wave_incl_rev(g * w);
         const float Sk = Scar + wave_excl_rev(gwr);
         const float draw = valid ? (Tn * g - Sk) * s.delta * sigmoidf(s.raw + b) : 0.f;
-        const float dd[1] = {draw};
-        scatter_wave<1>(a.dens, valid, s.cd, dd);
+        if (a.grad_raw) {
+            if (valid) a.grad_raw[k] = draw;
+        } else {
+            const float dd[1] = {draw};
+            scatter_wave<1>(a.dens, valid, s.cd, dd);
+        }
         if (MODE == DVGO_COLOR_GRID) {
             const float dc[3] = {w * g0, w * g1, w * g2};
             scatter_wave<3>(a.col, valid, s.cc, dc);
@@ -300,7 +307,8 @@ int check_samples(const dvgo_samples *s) {
 }
 
 int fill_render_args(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
-                     const dvgo_grid *color, const float *sample_rgb, bool bwd, RenderArgs &a) {
+                     const dvgo_grid *color, const float *sample_rgb, bool bwd, RenderArgs &a,
+                     bool density_grad = true) {
     if (!p) return set_error(DVGO_ERR_NULL, "params is NULL");
     if (p->struct_size != sizeof(dvgo_render_params))
         return set_error(DVGO_ERR_ABI, "dvgo_render_params.struct_size mismatch");
@@ -312,7 +320,7 @@ int fill_render_args(const dvgo_render_params *p, const dvgo_samples *s, const d
         return set_error(DVGO_ERR_UNSUPPORTED, "DVGO_COLOR_NONE is forward only");
     if (!(p->halt_T >= 0.f && p->halt_T < 1.f)) return set_error(DVGO_ERR_RANGE, "halt_T must be in [0, 1)");
     memset(&a, 0, sizeof(a));
-    rc = make_dev_grid(density, "density", &a.dens, bwd);
+    rc = make_dev_grid(density, "density", &a.dens, bwd && density_grad);
     if (rc) return rc;
     if (p->color_mode == DVGO_COLOR_GRID) {
         if (!color) return set_error(DVGO_ERR_NULL, "color grid is NULL in DVGO_COLOR_GRID mode");
@@ -440,9 +448,9 @@ extern "C" int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samp
                                     const dvgo_grid *color, const float *sample_rgb, const float *T_final,
                                     const void *state, size_t state_bytes_, const float *grad_rgb,
                                     const float *grad_dist, const float *grad_T, float *grad_sample_rgb,
-                                    void *stream) {
+                                    float *grad_sample_density, void *stream) {
     RenderArgs a;
-    int rc = fill_render_args(p, s, density, color, sample_rgb, true, a);
+    int rc = fill_render_args(p, s, density, color, sample_rgb, true, a, grad_sample_density == nullptr);
     if (rc) return rc;
     if (s->n_rays == 0) return DVGO_OK;
     if (!T_final || !state || !grad_rgb) return set_error(DVGO_ERR_NULL, "T_final, state or grad_rgb is NULL");
@@ -455,6 +463,7 @@ extern "C" int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samp
     a.grad_dist = p->want_dist ? grad_dist : nullptr;
     a.grad_T = grad_T;
     a.grad_srgb = grad_sample_rgb;
+    a.grad_raw = grad_sample_density;
     split_state(const_cast<void *>(state), s->n_rays, &a.halt_idx, &a.ckpt);
     if (a.n_list == 0) return DVGO_OK;
     return launch_bwd(p, a, (hipStream_t)stream);

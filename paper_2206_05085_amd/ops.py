@@ -17,7 +17,7 @@ from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
-           "grid_scatter", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
+           "grid_scatter", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
            "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
            "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2",
            "MLP_SPLIT_F16", "MLP_F16"]
@@ -251,8 +251,10 @@ def render_forward(batch: SampleBatch, density: DeviceGrid, color: Optional[Devi
 def render_backward(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid], sample_rgb, T_final,
                     state, grad_rgb, grad_dist=None, grad_T=None, *, act_shift_: float, halt_T: float = 0.0,
                     bg=(1.0, 1.0, 1.0), want_dist: bool = True, grad_sample_rgb=None,
-                    schedule: Optional[Schedule] = None):
-    """Accumulates into density.grad (and color.grad); returns grad_sample_rgb (sample mode)."""
+                    schedule: Optional[Schedule] = None, grad_sample_density=None):
+    """Accumulates into density.grad (and color.grad); returns grad_sample_rgb (sample mode).
+    With grad_sample_density [S], the per-sample density-logit gradient is written there
+    instead of being added into density.grad."""
     import ctypes
     mode = COLOR_GRID if color is not None else COLOR_SAMPLES
     R, S = batch.n_rays, batch.n_samples
@@ -265,11 +267,13 @@ def render_backward(batch: SampleBatch, density: DeviceGrid, color: Optional[Dev
         grad_sample_rgb = torch.empty(S, 3, device=batch.xyz.device)
     p = _params(act_shift_, halt_T, bg, mode, want_dist, schedule)
     s = batch.struct()
-    gd = density.struct(need_grad=True)
+    if grad_sample_density is not None:
+        _chk(grad_sample_density, "grad_sample_density", numel=S)
+    gd = density.struct(need_grad=grad_sample_density is None)
     gc = color.struct(need_grad=True) if color is not None else None
     call("dvgo_render_backward", ctypes.byref(p), ctypes.byref(s), ctypes.byref(gd),
          ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), _p(T_final), _p(state), state.numel(),
-         _p(grad_rgb), _p(grad_dist), _p(grad_T), _p(grad_sample_rgb), _stream())
+         _p(grad_rgb), _p(grad_dist), _p(grad_T), _p(grad_sample_rgb), _p(grad_sample_density), _stream())
     return grad_sample_rgb
 
 
@@ -333,6 +337,34 @@ def grid_scatter(grid: DeviceGrid, xyz, grad_out):
     _chk(xyz, "xyz", numel=3 * S)
     _chk(grad_out, "grad_out", numel=S * g.channels)
     call("dvgo_grid_scatter", ctypes.byref(g), S, _p(xyz), _p(grad_out), _stream())
+
+
+def bin_workspace_size(grid: DeviceGrid, n_samples: int) -> int:
+    return _size("dvgo_bin_workspace_size", ctypes_byref(grid.struct()), int(n_samples))
+
+
+def bin_samples(grid: DeviceGrid, xyz, ws=None):
+    """Sort the samples by the grid's 8^3-cell bricks (for grid_scatter_binned); returns ws."""
+    _chk(xyz, "xyz", last=3)
+    S = xyz.numel() // 3
+    if ws is None:
+        ws = torch.empty(max(bin_workspace_size(grid, S), 1), dtype=torch.uint8, device=xyz.device)
+    call("dvgo_bin_samples", ctypes_byref(grid.struct()), S, _p(xyz), _p(ws), ws.numel(), _stream())
+    return ws
+
+
+def grid_scatter_binned(grid: DeviceGrid, xyz, grad_out, ws):
+    """grid.grad += trilinear^T(grad_out), brick by brick, with the bins of bin_samples."""
+    _chk(xyz, "xyz", last=3)
+    S = xyz.numel() // 3
+    _chk(grad_out, "grad_out", numel=S * grid.struct().channels)
+    call("dvgo_grid_scatter_binned", ctypes_byref(grid.struct(need_grad=True)), S, _p(xyz), _p(grad_out), _p(ws),
+         ws.numel(), _stream())
+
+
+def ctypes_byref(x):
+    import ctypes
+    return ctypes.byref(x)
 
 
 def tv_add_grad(grid: DeviceGrid, weight: float, delta: float = 1.0, dense: bool = True):

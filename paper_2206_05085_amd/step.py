@@ -22,14 +22,17 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 tv=None, warp=None, mlp_precision=0, device="cuda"):
+                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
         tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
         term, added into the grid gradients after the backward pass.  warp: optional (mode, b):
         every grid is addressed through the Eq. 4 contraction (ops.WARP_CONTRACT_INF or
         ops.WARP_CONTRACT_L2) and the batch holds world points.  mlp_precision: ops.MLP_SPLIT_F16
-        (FP32-grade colour head) or ops.MLP_F16 (the cheaper head, FP16 matrix operands)."""
+        (FP32-grade colour head) or ops.MLP_F16 (the cheaper head, FP16 matrix operands).
+        binned_scatter: the renderer writes per-sample density gradients, which are scattered
+        brick by brick (samples binned once per step) instead of by in-wave aggregated atomics
+        inside the render kernel."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -39,6 +42,7 @@ class TrainStep:
         self.shift = ops.act_shift() if act_shift is None else act_shift
         self.halt_T, self.bg, self.lam = halt_T, tuple(bg), dist_weight
         self.tv = None if tv is None else (float(tv[0]), float(tv[1]), float(tv[2]), bool(tv[3]))
+        self.binned = bool(binned_scatter)
         self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
         self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
@@ -79,6 +83,12 @@ class TrainStep:
         self.rgb, self.T, self.dist = (torch.empty(R, 3, device=d), torch.empty(R, device=d),
                                        torch.empty(R, device=d))
         self.state = torch.empty(ops.render_state_size(R, S), dtype=torch.uint8, device=d)
+        if self.binned:
+            # one binning per step serves every grid of the same geometry
+            self.g_raw = torch.empty(S, device=d)
+            self.bin_ws = torch.empty(max(ops.bin_workspace_size(self.grid("density"), S), 1), dtype=torch.uint8,
+                                      device=d)
+
         self.loss = torch.zeros(1, device=d)
         self.g_rgb, self.g_dist = torch.empty(R, 3, device=d), torch.empty(R, device=d)
         if not self.grid_mode:
@@ -131,16 +141,25 @@ class TrainStep:
 
     def backward(self):
         b = self.batch
+        graw = None
+        if self.binned:
+            ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
+            graw = self.g_raw
         if self.grid_mode:
             ops.render_backward(b, self.grid("density"), self.grid("color"), None, self.T, self.state, self.g_rgb,
                                 self.g_dist, None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg,
-                                schedule=self.schedule)
+                                schedule=self.schedule, grad_sample_density=graw)
         else:
             ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb,
                                 self.g_dist, None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg,
-                                grad_sample_rgb=self.g_rgb_s, schedule=self.schedule)
+                                grad_sample_rgb=self.g_rgb_s, schedule=self.schedule, grad_sample_density=graw)
+        if self.binned:
+            ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
+        if not self.grid_mode:
             ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
                              ws=self.mlp_ws)
+            # the 12-channel feature gradient keeps the in-wave aggregated scatter: its brick
+            # tiles share half their vertices with neighbours, so binning saves no atomics there
             ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
         if self.tv is not None:
             # total-variation gradients go straight into the grid gradients before Adam (section 2)

@@ -241,6 +241,61 @@ def test_gather_scatter_contracted(dv, warp, b, C):
     close(dg.grad.cpu().numpy(), oracle.scatter(g, xyz, y.astype(np.float64)), **GRAD, name="scatter")
 
 
+@pytest.mark.parametrize("n,C,warp", [(24, 1, 0), (17, 3, 0), (40, 12, 0), (33, 12, 1), (9, 16, 0)])
+def test_binned_scatter(dv, n, C, warp):
+    # brick-binned scatter: bins form a permutation; the sum equals the oracle's scatter
+    rng = np.random.default_rng(30 + n + C)
+    g = synth.normal_grid(rng, n, C, -2.0, 2.0) if warp else synth.normal_grid(rng, n, C)
+    g.warp = warp
+    wl = synth.config2(R=64)
+    xyz = wl.samples.xyz
+    if warp:
+        xyz = (xyz * 5.0).astype(np.float32)     # world points far outside the unit cube
+    xyz = np.concatenate([xyz, rng.uniform(-1.2, 1.2, (3000, 3)).astype(np.float32)])
+    S = xyz.shape[0]
+    y = rng.standard_normal((S, C)).astype(np.float32)
+    say("binned scatter n =", n, "C =", C, "warp", warp, "S =", S)
+    dg = dgrid(dv, g, grad=True)
+    ws = dv.bin_samples(dg, T(xyz))
+    dv.grid_scatter_binned(dg, T(xyz), T(y), ws)
+    torch.cuda.synchronize()
+    nb = int(np.prod([(n - 1 + 7) // 8] * 3))
+    raw = ws.cpu().numpy().view(np.int32)
+    offs = raw[:nb + 1]
+    perm_at = ((4 * (nb + 1) + 255) // 256 * 256 + (4 * nb + 255) // 256 * 256) // 4
+    perm = raw[perm_at:perm_at + S]
+    assert offs[0] == 0 and offs[-1] == S and (np.diff(offs) >= 0).all()
+    assert np.array_equal(np.sort(perm), np.arange(S))
+    close(dg.grad.cpu().numpy(), oracle.scatter(g, xyz, y.astype(np.float64)), **GRAD, name="binned scatter")
+
+
+def test_render_backward_per_sample_density(dv):
+    # the per-sample density gradient, scattered brick by brick, equals the oracle's density
+    # gradient; halted samples carry zero
+    wl = synth.config2(R=256)
+    smp = wl.samples
+    rng = np.random.default_rng(31)
+    R, S = smp.n_rays, smp.n_samples
+    shift = float(np.float32(oracle.act_shift()))
+    dens = dgrid(dv, wl.density, grad=True)
+    b = dbatch(dv, smp)
+    srgb = rng.random((S, 3)).astype(np.float32)
+    GC = rng.standard_normal((R, 3)).astype(np.float32)
+    GD = rng.standard_normal(R).astype(np.float32)
+    say("render backward with per-sample density gradient, 256 rays, S =", S)
+    rgb, Tf, D, state = dv.render_forward(b, dens, None, T(srgb), act_shift_=shift)
+    graw = torch.full((S,), 7.0, device="cuda")
+    dv.render_backward(b, dens, None, T(srgb), Tf, state, T(GC), T(GD), None, act_shift_=shift,
+                       grad_sample_density=graw)
+    ws = dv.bin_samples(dens, b.xyz)
+    dv.grid_scatter_binned(dens, b.xyz, graw, ws)
+    torch.cuda.synchronize()
+    assert not (graw == 7.0).any()
+    og = oracle.render_backward(smp, wl.density, GC.astype(np.float64), GD.astype(np.float64), None, srgb=srgb,
+                                shift=shift)
+    close(dens.grad.cpu().numpy(), og["grad_density"], **GRAD, name="grad density (binned)")
+
+
 @pytest.mark.parametrize("pattern", ["rays", "one_cell", "interleaved"])
 def test_scatter_shared_vertices(dv, pattern):
     # the scatter sums contributions to shared vertices inside a wave before the atomics;
