@@ -22,7 +22,7 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, device="cuda"):
+                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, concurrent=True, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
         tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
@@ -32,7 +32,9 @@ class TrainStep:
         (FP32-grade colour head) or ops.MLP_F16 (the cheaper head, FP16 matrix operands).
         binned_scatter: the renderer writes per-sample density gradients, which are scattered
         brick by brick (samples binned once per step) instead of by in-wave aggregated atomics
-        inside the render kernel."""
+        inside the render kernel.  concurrent: in the feature-grid mode, run the binning, the
+        density scatter and the density and MLP Adam updates on a second stream, overlapped with
+        the colour head's backward and the feature scatter (stream-ordered, graph-capturable)."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -43,6 +45,8 @@ class TrainStep:
         self.halt_T, self.bg, self.lam = halt_T, tuple(bg), dist_weight
         self.tv = None if tv is None else (float(tv[0]), float(tv[1]), float(tv[2]), bool(tv[3]))
         self.binned = bool(binned_scatter)
+        self.concurrent = bool(concurrent)
+        self.side = None
         self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
         self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
@@ -178,10 +182,51 @@ class TrainStep:
             ops.grid_adam_step(d["p"], d["g"], d["m"], d["v"], lr=lr, beta1=b1, beta2=b2, eps=self.eps,
                                step_dev=self.t_dev, skip_zero_grad=skip, zero_grad_after=True)
 
+    def _adam(self, name, lr, skip):
+        b1, b2 = self.betas
+        d = getattr(self, name)
+        ops.grid_adam_step(d["p"], d["g"], d["m"], d["v"], lr=lr, beta1=b1, beta2=b2, eps=self.eps,
+                           step_dev=self.t_dev, skip_zero_grad=skip, zero_grad_after=True)
+
     def step(self):
+        if not (self.concurrent and self.binned and not self.grid_mode):
+            self.forward()
+            self.backward()
+            self.optimise()
+            return self.loss
+        # Two streams.  main: forward, render backward, colour-head backward, feature scatter,
+        # feature Adam.  side: binning (needs only the points), then after the render backward
+        # the density scatter (+ TV) and density Adam, then after the colour-head backward the
+        # MLP Adam.  Each buffer has one writer at a time; the side joins main at the end.
+        main = torch.cuda.current_stream()
+        if self.side is None:
+            self.side = torch.cuda.Stream(device=self.device)
+        side = self.side
+        b = self.batch
+        ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
         self.forward()
-        self.backward()
-        self.optimise()
+        ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
+                            None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
+                            schedule=self.schedule, grad_sample_density=self.g_raw)
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
+            if self.tv is not None:
+                ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
+            self._adam("density", self.lr_grid, True)
+        ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
+                         ws=self.mlp_ws)
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            self._adam("mlp_flat", self.lr_mlp, False)
+        ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+        if self.tv is not None:
+            ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
+        self._adam("feat", self.lr_grid, True)
+        main.wait_stream(side)
         return self.loss
 
     # ----------------------------------------------------------- HIP graphs

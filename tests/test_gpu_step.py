@@ -108,6 +108,36 @@ def test_graph_replays_match_eager(pkg):
               name=f"mlp replay {rep}")
 
 
+def test_two_stream_step_matches_sequential(pkg):
+    # the step that overlaps the density scatter and the density / MLP Adam updates on a second
+    # stream takes the same update as the strictly sequential step, eagerly and from a graph
+    ops, _, step = pkg
+    wl = synth.config2(R=256, n=48)
+    say("two-stream step vs sequential, 48^3, 256 rays, TV on")
+    mk = lambda conc: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                                     mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight,
+                                     tv=(1e-3, 1e-4, 1.0, True), concurrent=conc)
+    smp = wl.samples
+    seq, conc, gr = mk(False), mk(True), mk(True)
+    for st in (seq, conc, gr):
+        st.bind(ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len),
+                wl.rays.dirs, wl.target)
+    g = gr.capture(warmup=1)
+    seq.step()
+    conc.step()
+    for rep in range(3):
+        seq.step()
+        conc.step()
+        g.replay()
+        torch.cuda.synchronize()
+        for name in ("density", "feat", "mlp_flat"):
+            ref = getattr(seq, name)["p"].cpu().numpy()
+            for other, tag in ((conc, "eager"), (gr, "graph")):
+                close(getattr(other, name)["p"].cpu().numpy(), ref, rtol=1e-5, floor=1e-3,
+                      name=f"{name} two-stream {tag} step {rep}")
+                assert not getattr(other, name)["g"].any(), f"{name} gradient not cleared ({tag})"
+
+
 def test_autograd_render_and_distortion(pkg):
     ops, ag, _ = pkg
     wl = synth.config1(R=200)
