@@ -287,6 +287,17 @@ int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ra
                       int64_t n_samples, const float *feat, const float *grad_rgb, float *grad_feat, void *ws,
                       size_t ws_bytes, void *stream);
 
+/* dvgo_mlp_backward with the feature gradient scattered straight into the feature grid:
+ * feat_grid->grad += trilinear^T(d loss / d feat) at the points xyz [S,3] (the points the
+ * features were gathered at), instead of writing grad_feat.  The scatter runs inside the
+ * backward kernel while its matrix work proceeds; samples in the same cell as their
+ * predecessor are summed before the atomics.  feat_grid: in_feat channels, no warp (a warped
+ * grid returns DVGO_ERR_UNSUPPORTED; use dvgo_mlp_backward + dvgo_grid_scatter).  Same
+ * workspace and weight-gradient outputs as dvgo_mlp_backward. */
+int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
+                              int64_t n_samples, const float *feat, const float *grad_rgb, const dvgo_grid *feat_grid,
+                              const float *xyz, void *ws, size_t ws_bytes, void *stream);
+
 /* Loss head: loss[0] = (1/(3R)) sum ||rgb_r - target_r||^2 + dist_weight (1/R) sum dist_r
  * (dist may be NULL: no distortion term); grad_rgb [R,3] and grad_dist [R] (may be NULL)
  * receive dloss/drgb and dloss/ddist.  The paper weights the distortion term by 1e-2

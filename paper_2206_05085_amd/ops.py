@@ -17,7 +17,7 @@ from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
-           "grid_scatter", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "loss_head",
+           "grid_scatter", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "mlp_backward_scatter", "loss_head",
            "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
            "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2",
            "MLP_SPLIT_F16", "MLP_F16"]
@@ -428,6 +428,21 @@ def mlp_backward(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, grad_feat=No
     call("dvgo_mlp_backward", ctypes.byref(m), R, _p(ray_offsets), _p(dirs), S, _p(feat), _p(grad_rgb),
          _p(grad_feat), _p(ws), ws.numel(), _stream())
     return grad_feat
+
+
+def mlp_backward_scatter(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, feat_grid: DeviceGrid, xyz, ws=None):
+    """MLP backward (parameter gradients +=) with the feature gradient scattered into
+    feat_grid.grad at xyz inside the kernel (no per-sample feature gradient is written)."""
+    import ctypes
+    R = ray_offsets.numel() - 1
+    S = feat.shape[0]
+    _chk(grad_rgb, "grad_rgb", numel=3 * S)
+    _chk(xyz, "xyz", numel=3 * S)
+    dev = feat.device
+    ws = _mlp_ws(mlp, R, S, ws, dev)
+    call("dvgo_mlp_backward_scatter", ctypes.byref(mlp.struct(need_grad=True)), R, _p(ray_offsets), _p(dirs), S,
+         _p(feat), _p(grad_rgb), ctypes.byref(feat_grid.struct(need_grad=True)), _p(xyz), _p(ws), ws.numel(),
+         _stream())
 
 
 def loss_head(rgb, target, dist, dist_weight, loss=None, grad_rgb=None, grad_dist=None):

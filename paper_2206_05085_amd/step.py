@@ -22,7 +22,8 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, concurrent=True, device="cuda"):
+                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, concurrent=True, fused_scatter=False,
+                 device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
         tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
@@ -34,7 +35,10 @@ class TrainStep:
         brick by brick (samples binned once per step) instead of by in-wave aggregated atomics
         inside the render kernel.  concurrent: in the feature-grid mode, run the binning, the
         density scatter and the density and MLP Adam updates on a second stream, overlapped with
-        the colour head's backward and the feature scatter (stream-ordered, graph-capturable)."""
+        the colour head's backward and the feature scatter (stream-ordered, graph-capturable).
+        fused_scatter: scatter the feature gradient inside the colour head's backward kernel
+        (unwarped feature grids) instead of writing it and scattering it afterwards; saves the
+        per-sample feature-gradient buffer, but measured slower on the config-2 step (off)."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -48,6 +52,7 @@ class TrainStep:
         self.concurrent = bool(concurrent)
         self.side = None
         self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
+        self.fused = bool(fused_scatter) and self.warp[0] == 0
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
         self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
         self.density = self._param(dev(density))
@@ -160,11 +165,7 @@ class TrainStep:
         if self.binned:
             ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
         if not self.grid_mode:
-            ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
-                             ws=self.mlp_ws)
-            # the 12-channel feature gradient keeps the in-wave aggregated scatter: its brick
-            # tiles share half their vertices with neighbours, so binning saves no atomics there
-            ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+            self._mlp_backward_and_scatter()
         if self.tv is not None:
             # total-variation gradients go straight into the grid gradients before Adam (section 2)
             w_density, w_other, delta, dense = self.tv
@@ -181,6 +182,18 @@ class TrainStep:
             d = getattr(self, name)
             ops.grid_adam_step(d["p"], d["g"], d["m"], d["v"], lr=lr, beta1=b1, beta2=b2, eps=self.eps,
                                step_dev=self.t_dev, skip_zero_grad=skip, zero_grad_after=True)
+
+    def _mlp_backward_and_scatter(self):
+        b = self.batch
+        if self.fused:
+            ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
+                                     b.xyz, ws=self.mlp_ws)
+            return
+        ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
+                         ws=self.mlp_ws)
+        # the 12-channel feature gradient keeps the in-wave aggregated scatter: its brick tiles
+        # share half their vertices with neighbours, so binning saves no atomics there
+        ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
 
     def _adam(self, name, lr, skip):
         b1, b2 = self.betas
@@ -217,12 +230,17 @@ class TrainStep:
             if self.tv is not None:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
             self._adam("density", self.lr_grid, True)
-        ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
-                         ws=self.mlp_ws)
+        if self.fused:
+            ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
+                                     b.xyz, ws=self.mlp_ws)
+        else:
+            ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
+                             ws=self.mlp_ws)
         side.wait_stream(main)
         with torch.cuda.stream(side):
             self._adam("mlp_flat", self.lr_mlp, False)
-        ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+        if not self.fused:
+            ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
         if self.tv is not None:
             ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
         self._adam("feat", self.lr_grid, True)

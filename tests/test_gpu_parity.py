@@ -403,6 +403,40 @@ def test_mlp_multi_block(dv):
     _mlp_case(dv, list(np.random.default_rng(21).integers(0, 300, 256)), seed=22)
 
 
+@pytest.mark.parametrize("half", [False, True])
+def test_mlp_backward_fused_scatter(dv, half):
+    # the feature gradient scattered inside the colour head's backward equals the oracle's
+    # scatter of the oracle's feature gradient (parameter gradients as in the unfused call)
+    wl = synth.config2(R=512, n=40)
+    smp = wl.samples
+    rng = np.random.default_rng(26)
+    S, R = smp.n_samples, smp.n_rays
+    feat = oracle.gather(wl.feat, smp.xyz).astype(np.float32)
+    grgb = rng.standard_normal((S, 3)).astype(np.float32)
+    say("mlp backward with fused feature scatter, 40^3x12, S =", S, "half", half)
+    W = [T(w) for w in wl.mlp.W]
+    b = [T(v) for v in wl.mlp.b]
+    gW = [torch.zeros_like(w) for w in W]
+    gb = [torch.zeros_like(v) for v in b]
+    P = dv.MLPParams(W, b, gW, gb, precision=dv.MLP_F16 if half else dv.MLP_SPLIT_F16)
+    fg = dgrid(dv, wl.feat, grad=True)
+    dv.mlp_backward_scatter(P, T(smp.ray_offsets, torch.int32), T(wl.rays.dirs), T(feat), T(grgb), fg, T(smp.xyz))
+    torch.cuda.synchronize()
+    f64, g64 = feat.astype(np.float64), grgb.astype(np.float64)
+    rgf, rgW, rgb_ = oracle.mlp_backward(wl.mlp, smp.ray_offsets, wl.rays.dirs, f64, g64, half=half)
+    want = oracle.scatter(wl.feat, smp.xyz, rgf)
+    sf, sW, sb = oracle.mlp_kink_slack(wl.mlp, smp.ray_offsets, wl.rays.dirs, f64, g64, thr=1e-4 if half else 1e-5,
+                                       half=half)
+    slack = oracle.scatter(wl.feat, smp.xyz, sf)   # every vertex weight is <= 1
+    gr = GRAD16 if half else GRAD
+    scale = None
+    if half:
+        mf = oracle.mlp_magnitudes(wl.mlp, smp.ray_offsets, wl.rays.dirs, f64, g64, half=True)[1]
+        scale = oracle.scatter(wl.feat, smp.xyz, mf)
+    close(fg.grad.cpu().numpy(), want, **gr, name="fused feature-grid gradient", slack=np.abs(slack), scale=scale)
+    close(gW[1].cpu().numpy(), rgW[1], **gr, name="fused dW2", slack=sW[1])
+
+
 def test_mlp_f16_small_ragged(dv):
     say("mlp FP16 head, 300 samples (ragged, partial tiles)")
     _mlp_case(dv, [0, 5, 1, 64, 100, 0, 130], seed=23, half=True)

@@ -108,17 +108,20 @@ def test_graph_replays_match_eager(pkg):
               name=f"mlp replay {rep}")
 
 
-def test_two_stream_step_matches_sequential(pkg):
+@pytest.mark.parametrize("fused", [False, True])
+def test_two_stream_step_matches_sequential(pkg, fused):
     # the step that overlaps the density scatter and the density / MLP Adam updates on a second
-    # stream takes the same update as the strictly sequential step, eagerly and from a graph
+    # stream (with the feature scatter separate or fused into the colour head's backward) takes
+    # the same update as the strictly sequential step, eagerly and from a graph
     ops, _, step = pkg
     wl = synth.config2(R=256, n=48)
-    say("two-stream step vs sequential, 48^3, 256 rays, TV on")
-    mk = lambda conc: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
-                                     mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight,
-                                     tv=(1e-3, 1e-4, 1.0, True), concurrent=conc)
+    say("two-stream step vs sequential, 48^3, 256 rays, TV on, fused feature scatter", fused)
+    mk = lambda conc, fu=False: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max),
+                                               feat=wl.feat.data, mlp=(wl.mlp.W, wl.mlp.b),
+                                               dist_weight=wl.dist_weight, tv=(1e-3, 1e-4, 1.0, True),
+                                               concurrent=conc, fused_scatter=fu)
     smp = wl.samples
-    seq, conc, gr = mk(False), mk(True), mk(True)
+    seq, conc, gr = mk(False), mk(True, fused), mk(True, fused)
     for st in (seq, conc, gr):
         st.bind(ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len),
                 wl.rays.dirs, wl.target)
