@@ -262,6 +262,13 @@ int dvgo_bin_samples(const dvgo_grid *g, int64_t n_samples, const float *xyz, vo
 int dvgo_grid_scatter_binned(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
                              const void *ws, size_t ws_bytes, void *stream);
 
+/* Resampling of a grid to another resolution over the same box (progressive grid scaling, the
+ * "grid scaling schedule" of Table 7's footnote): out [nx][ny][nz][src->ch_stride] (written)
+ * holds at vertex (i, j, k) the trilinear value of src at xyz_min + (i, j, k) (xyz_max -
+ * xyz_min)/(n - 1), each coordinate formed in double and rounded to float32; padding channels
+ * are written as 0.  The lookup is in the grid's own box (a warp of src is not applied). */
+int dvgo_grid_resample(const dvgo_grid *src, int32_t nx, int32_t ny, int32_t nz, float *out, void *stream);
+
 /* Per-sample alpha of the density path only (trilinear, softplus shift, 1 - exp(-sigma delta)):
  * alpha [S].  Used for the coarse samples of the proposal stage. */
 int dvgo_alpha(const dvgo_grid *density, int64_t n_samples, const float *xyz, const float *delta, float act_shift,

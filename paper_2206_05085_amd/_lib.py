@@ -88,6 +88,7 @@ SIGNATURES = {
     "dvgo_grid_gather": (C.c_int, [_PG, _I64, VP, VP, VP]),
     "dvgo_grid_scatter": (C.c_int, [_PG, _I64, VP, VP, VP]),
     "dvgo_bin_workspace_size": (C.c_int, [_PG, _I64, _SZP]),
+    "dvgo_grid_resample": (C.c_int, [_PG, _I32, _I32, _I32, VP, VP]),
     "dvgo_bin_samples": (C.c_int, [_PG, _I64, VP, VP, C.c_size_t, VP]),
     "dvgo_grid_scatter_binned": (C.c_int, [_PG, _I64, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_tv_add_grad": (C.c_int, [_PG, _F, _F, _I32, VP]),

@@ -786,3 +786,46 @@ extern "C" int dvgo_grid_scatter_binned(const dvgo_grid *g, int64_t n_samples, c
     else launch_brick_scatter<16>(dg, bg, xyz, grad_out, w, st);
     return check_hip(hipGetLastError(), "brick_scatter_kernel launch");
 }
+
+// ------------------------------------------------------------------ grid resampling
+
+namespace {
+
+// out vertex (i, j, k) of an (mx, my, mz) grid over the same box = trilinear value of the
+// source at that vertex's position; positions in double, rounded to float32 like any point
+__global__ __launch_bounds__(256) void resample_kernel(DevGrid g, int mx, int my, int mz, double lo0, double lo1,
+                                                       double lo2, double st0, double st1, double st2,
+                                                       float *__restrict__ out) {
+    const int64_t n = (int64_t)mx * my * mz;
+    for (int64_t v = blockIdx.x * (int64_t)256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256) {
+        const int k = (int)(v % mz), j = (int)((v / mz) % my), i = (int)(v / ((int64_t)my * mz));
+        const float x = (float)(lo0 + (double)i * st0), y = (float)(lo1 + (double)j * st1),
+                    z = (float)(lo2 + (double)k * st2);
+        const Tri t = trilinear<false>(g, x, y, z);
+        for (int ch = 0; ch < g.cs; ++ch) out[v * g.cs + ch] = ch < g.C ? interp_ch(g, t, ch) : 0.f;
+    }
+}
+
+}  // namespace
+
+extern "C" int dvgo_grid_resample(const dvgo_grid *src, int32_t nx, int32_t ny, int32_t nz, float *out,
+                                  void *stream) {
+    DevGrid dg;
+    int rc = make_dev_grid(src, "source grid", &dg, false);
+    if (rc) return rc;
+    if (nx < 2 || ny < 2 || nz < 2) return set_error(DVGO_ERR_SHAPE, "every output dimension must be >= 2");
+    if ((int64_t)nx * ny * nz * src->ch_stride >= ((int64_t)1 << 31))
+        return set_error(DVGO_ERR_RANGE, "output grid has >= 2^31 floats");
+    if (!out) return set_error(DVGO_ERR_NULL, "out is NULL");
+    dg.warp = DVGO_WARP_NONE;  // vertices are addressed in the grid's own box
+    const double lo[3] = {src->xyz_min[0], src->xyz_min[1], src->xyz_min[2]};
+    const double hi[3] = {src->xyz_max[0], src->xyz_max[1], src->xyz_max[2]};
+    const int m[3] = {nx, ny, nz};
+    double st[3];
+    for (int a = 0; a < 3; ++a) st[a] = (hi[a] - lo[a]) / (double)(m[a] - 1);
+    const int64_t n = (int64_t)nx * ny * nz;
+    const int64_t blocks = (n + 255) / 256 < 65536 ? (n + 255) / 256 : 65536;
+    hipLaunchKernelGGL(resample_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, dg, nx, ny, nz,
+                       lo[0], lo[1], lo[2], st[0], st[1], st[2], out);
+    return check_hip(hipGetLastError(), "resample_kernel launch");
+}

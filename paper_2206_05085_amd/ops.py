@@ -17,7 +17,7 @@ from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
-           "grid_scatter", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "mlp_backward_scatter", "loss_head",
+           "grid_scatter", "grid_resample", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "mlp_backward_scatter", "loss_head",
            "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
            "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2",
            "MLP_SPLIT_F16", "MLP_F16"]
@@ -337,6 +337,18 @@ def grid_scatter(grid: DeviceGrid, xyz, grad_out):
     _chk(xyz, "xyz", numel=3 * S)
     _chk(grad_out, "grad_out", numel=S * g.channels)
     call("dvgo_grid_scatter", ctypes.byref(g), S, _p(xyz), _p(grad_out), _stream())
+
+
+def grid_resample(grid: DeviceGrid, shape, out=None):
+    """The grid resampled (trilinear) to shape (nx, ny, nz) over the same box: a new
+    [nx, ny, nz, ch_stride] tensor (padding channels 0)."""
+    nx, ny, nz = (int(v) for v in shape)
+    cs = grid.data.shape[3]
+    if out is None:
+        out = torch.empty(nx, ny, nz, cs, device=grid.data.device)
+    _chk(out, "out", numel=nx * ny * nz * cs)
+    call("dvgo_grid_resample", ctypes_byref(grid.struct()), nx, ny, nz, _p(out), _stream())
+    return out
 
 
 def bin_workspace_size(grid: DeviceGrid, n_samples: int) -> int:

@@ -121,6 +121,20 @@ class TrainStep:
         >= alpha_thr at a step of delta voxels (mask: uint8 over the density grid, in place)."""
         return ops.occupancy_update(self.grid("density"), self.shift, delta, alpha_thr, mask)
 
+    def upscale(self, shape):
+        """Progressive grid scaling: resample the density and feature (or colour) grids to
+        shape = (nx, ny, nz) over the same box and restart their Adam moments.  Per-batch
+        buffers that depend on the grid are re-allocated; a captured graph must be captured
+        again."""
+        for name in ("density", "color" if self.grid_mode else "feat"):
+            d = getattr(self, name)
+            new = ops.grid_resample(ops.DeviceGrid(d["p"], self.box[0], self.box[1]), shape)
+            setattr(self, name, self._param(new))
+        if self.batch is not None:
+            self.bind(self.batch, self.dirs, self.target)
+        self.graph = None
+        return self
+
     def tune(self, longest_first: bool = True):
         """Pick the render kernels' launch shape with the library's autotuner (on the bound
         batch; call outside graph capture).  Returns (Schedule, ms of render fwd + bwd)."""

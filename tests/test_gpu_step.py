@@ -141,6 +141,24 @@ def test_two_stream_step_matches_sequential(pkg, fused):
                 assert not getattr(other, name)["g"].any(), f"{name} gradient not cleared ({tag})"
 
 
+def test_upscale_then_step(pkg):
+    # progressive scaling mid-training: 48^3 -> 72^3, moments restarted, the step runs on
+    # eagerly and captured again
+    ops, _, step = pkg
+    wl = synth.config2(R=256, n=48)
+    say("upscale 48^3 -> 72^3 then step")
+    st = make_step(step, wl)
+    st.step()
+    st.upscale((72, 72, 72))
+    assert st.density["p"].shape[:3] == (72, 72, 72) and not st.feat["m"].any()
+    l1 = float(st.step().item())
+    g = st.capture(warmup=0)
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.isfinite(l1) and np.isfinite(float(st.loss.item()))
+    assert not st.density["g"].any() and not st.feat["g"].any()
+
+
 def test_autograd_render_and_distortion(pkg):
     ops, ag, _ = pkg
     wl = synth.config1(R=200)
