@@ -317,9 +317,15 @@ def test_grid_resample(dv, src, dst, C, cs):
     close(got[..., :C], want, **FWD, name="resampled grid", scale=scale)
     assert not got[..., C:].any()
     if src == dst:
-        # float32 vertex positions may sit a rounding off the vertex: the neighbours' share is
-        # bounded by the magnitude of the interpolation
-        close(got[..., :C], data[..., :C], **FWD, name="identity resample", scale=scale)
+        # a float32 vertex position may sit a rounding off its vertex, by du cells along each
+        # axis (float64 below); moving du along an axis changes the value by at most
+        # du * |neighbour - vertex| <= du * 2 max|data|
+        n = np.array(src, np.float64)
+        u = (pts.astype(np.float64) - lo.astype(np.float64)) * (n - 1) / (hi.astype(np.float64) - lo)
+        du = np.abs(u - np.rint(u)).sum(axis=1).reshape(dst + (1,))
+        assert du.max() < 1e-5
+        off = du * 2.0 * np.abs(data[..., :C]).max() / FWD["rtol"]
+        close(got[..., :C], data[..., :C], **FWD, name="identity resample", scale=np.maximum(scale, off))
 
 
 @pytest.mark.parametrize("pattern", ["rays", "one_cell", "interleaved"])

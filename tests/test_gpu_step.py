@@ -135,8 +135,12 @@ def test_two_stream_step_matches_sequential(pkg, fused):
         torch.cuda.synchronize()
         for name in ("density", "feat", "mlp_flat"):
             ref = getattr(seq, name)["p"].cpu().numpy()
+            # the fused feature scatter adds the same terms in another order; Adam normalises
+            # each step's update to at most about lr, so a reordered gradient moves a feature by
+            # a fraction of lr per step (steps so far: 2 + rep)
+            scale = np.full(ref.shape, (2 + rep) * seq.lr_grid) if (fused and name == "feat") else None
             for other, tag in ((conc, "eager"), (gr, "graph")):
-                close(getattr(other, name)["p"].cpu().numpy(), ref, rtol=1e-5, floor=1e-3,
+                close(getattr(other, name)["p"].cpu().numpy(), ref, rtol=1e-5, floor=1e-3, scale=scale,
                       name=f"{name} two-stream {tag} step {rep}")
                 assert not getattr(other, name)["g"].any(), f"{name} gradient not cleared ({tag})"
 
