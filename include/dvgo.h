@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DVGO_ABI_VERSION 3
+#define DVGO_ABI_VERSION 4
 
 enum {
     DVGO_OK = 0,
@@ -133,7 +133,14 @@ typedef struct dvgo_render_params {
  * every matrix-core operand is one FP16 value after the same power-of-two scaling, i.e. rounded
  * to 11 significant bits, products accumulated in FP32).  In both modes the layer-1/2 products,
  * the weight gradients of W1/W2 and the back-propagation through W2 and W1 run on matrix cores;
- * biases, the output layer, its gradients and all activations stay in FP32. */
+ * biases, the output layer, its gradients and all activations stay in FP32.
+ * prepared: 0 = every call first writes its preparation into the workspace (the weights as
+ * scaled FP16 planes, the view encodings of the rays, the first ray of every 32-sample tile).
+ * Nonzero = the workspace already holds that preparation and the call skips it: allowed only
+ * when the last call on this workspace was a dvgo_mlp_forward / dvgo_mlp_backward /
+ * dvgo_mlp_backward_scatter with the same weights (unchanged since), precision, n_rays,
+ * ray_offsets, dirs and n_samples, e.g. the backward that follows the forward of one step.
+ * The library cannot check this; a stale workspace gives wrong results, not an error. */
 enum { DVGO_MLP_SPLIT_F16 = 0, DVGO_MLP_F16 = 1 };
 
 typedef struct dvgo_color_mlp {
@@ -144,6 +151,7 @@ typedef struct dvgo_color_mlp {
     const float *W1, *b1, *W2, *b2, *W3, *b3;
     float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
     int32_t precision;
+    int32_t prepared;
 } dvgo_color_mlp;
 
 int dvgo_abi_version(void);
@@ -308,7 +316,10 @@ int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays, const int
 /* Loss head: loss[0] = (1/(3R)) sum ||rgb_r - target_r||^2 + dist_weight (1/R) sum dist_r
  * (dist may be NULL: no distortion term); grad_rgb [R,3] and grad_dist [R] (may be NULL)
  * receive dloss/drgb and dloss/ddist.  The paper weights the distortion term by 1e-2
- * (sections 5.3, 5.4). */
+ * (sections 5.3, 5.4).  Any of loss, grad_rgb, grad_dist may be NULL (not all three).  With
+ * loss NULL the gradients come from a launch over all rays with no reduction; the loss value
+ * needs a one-block reduction, so a caller can take it on another stream, off the path of the
+ * backward. */
 int dvgo_loss_head(int32_t n_rays, const float *rgb, const float *target, const float *dist, float dist_weight,
                    float *loss, float *grad_rgb, float *grad_dist, void *stream);
 

@@ -9,7 +9,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdvgo.so")
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 VP = C.c_void_p
 OK = 0
@@ -48,7 +48,7 @@ class ColorMLP(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("in_feat", C.c_int32), ("n_freq", C.c_int32), ("hidden", C.c_int32),
                 ("W1", VP), ("b1", VP), ("W2", VP), ("b2", VP), ("W3", VP), ("b3", VP),
                 ("gW1", VP), ("gb1", VP), ("gW2", VP), ("gb2", VP), ("gW3", VP), ("gb3", VP),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("prepared", C.c_int32)]
 
 
 class Rays(C.Structure):

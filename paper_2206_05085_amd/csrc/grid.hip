@@ -191,26 +191,49 @@ __device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, f
 // Streams the four arrays as float4 (the 16-byte-aligned body) with a scalar head/tail.
 // With skip, a float4 group whose four gradients are all zero is not read further and
 // nothing is written; within a partly non-zero group the zero-gradient lanes keep their
-// values bit for bit.
+// values bit for bit.  Each thread takes ADAM_U groups a stride apart per pass and issues
+// all their gradient loads, then all parameter / moment loads, before it computes, so a
+// wave keeps several independent loads in flight instead of one dependent chain.
+constexpr int ADAM_U = 4;
+
 __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, int64_t n4) {
     adam_bias(a);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     const int64_t tid = blockIdx.x * (int64_t)kBlock + threadIdx.x;
     float4 *P = reinterpret_cast<float4 *>(a.p + head), *G = reinterpret_cast<float4 *>(a.g + head);
     float4 *M = reinterpret_cast<float4 *>(a.m + head), *V = reinterpret_cast<float4 *>(a.v + head);
-    for (int64_t i = tid; i < n4; i += stride) {
-        const float4 g = G[i];
-        const bool nz[4] = {g.x != 0.f, g.y != 0.f, g.z != 0.f, g.w != 0.f};
-        if (a.skip && !(nz[0] | nz[1] | nz[2] | nz[3])) continue;
-        float4 p = P[i], m = M[i], v = V[i];
-        if (!a.skip || nz[0]) adam_one(a, g.x, p.x, m.x, v.x);
-        if (!a.skip || nz[1]) adam_one(a, g.y, p.y, m.y, v.y);
-        if (!a.skip || nz[2]) adam_one(a, g.z, p.z, m.z, v.z);
-        if (!a.skip || nz[3]) adam_one(a, g.w, p.w, m.w, v.w);
-        P[i] = p;
-        M[i] = m;
-        V[i] = v;
-        if (a.zero) G[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t i0 = tid; i0 < n4; i0 += ADAM_U * stride) {
+        float4 g[ADAM_U], p[ADAM_U], m[ADAM_U], v[ADAM_U];
+        bool live[ADAM_U];
+#pragma unroll
+        for (int u = 0; u < ADAM_U; ++u) {
+            const int64_t i = i0 + u * stride;
+            g[u] = i < n4 ? G[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < ADAM_U; ++u) {
+            const int64_t i = i0 + u * stride;
+            const bool any = g[u].x != 0.f || g[u].y != 0.f || g[u].z != 0.f || g[u].w != 0.f;
+            live[u] = i < n4 && (!a.skip || any);
+            if (live[u]) {
+                p[u] = P[i];
+                m[u] = M[i];
+                v[u] = V[i];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < ADAM_U; ++u) {
+            if (!live[u]) continue;
+            const int64_t i = i0 + u * stride;
+            if (!a.skip || g[u].x != 0.f) adam_one(a, g[u].x, p[u].x, m[u].x, v[u].x);
+            if (!a.skip || g[u].y != 0.f) adam_one(a, g[u].y, p[u].y, m[u].y, v[u].y);
+            if (!a.skip || g[u].z != 0.f) adam_one(a, g[u].z, p[u].z, m[u].z, v[u].z);
+            if (!a.skip || g[u].w != 0.f) adam_one(a, g[u].w, p[u].w, m[u].w, v[u].w);
+            P[i] = p[u];
+            M[i] = m[u];
+            V[i] = v[u];
+            if (a.zero) G[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
     }
     // scalar head [0, head) and tail [head + 4 n4, n)
     const int64_t tail0 = head + 4 * n4;
@@ -222,6 +245,20 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, 
         adam_one(a, g, a.p[i], a.m[i], a.v[i]);
         if (a.zero) a.g[i] = 0.f;
     }
+}
+
+// gradients only (thread per ray): the same expressions as loss_head_kernel's
+__global__ __launch_bounds__(256) void loss_grad_kernel(int R, const float *__restrict__ rgb,
+                                                        const float *__restrict__ tgt, float lam, float *grad_rgb,
+                                                        float *grad_dist) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= R) return;
+    const float inv3R = 1.f / (3.f * (float)R), invR = 1.f / (float)R;
+    if (grad_rgb) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) grad_rgb[3 * r + ch] = 2.f * (rgb[3 * r + ch] - tgt[3 * r + ch]) * inv3R;
+    }
+    if (grad_dist) grad_dist[r] = lam * invR;
 }
 
 // single block: the loss is written (not accumulated), so no pre-zeroed scalar is needed
@@ -370,6 +407,11 @@ extern "C" int dvgo_loss_head(int32_t n_rays, const float *rgb, const float *tar
     if (n_rays == 0) return DVGO_OK;
     if (!rgb || !target) return set_error(DVGO_ERR_NULL, "rgb or target is NULL");
     if (!loss && !grad_rgb && !grad_dist) return set_error(DVGO_ERR_NULL, "no output requested");
+    if (!loss) {
+        hipLaunchKernelGGL(loss_grad_kernel, dim3((unsigned)((n_rays + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                           n_rays, rgb, target, dist_weight, grad_rgb, grad_dist);
+        return check_hip(hipGetLastError(), "loss_grad_kernel launch");
+    }
     hipLaunchKernelGGL(loss_head_kernel, dim3(1), dim3(1024), 0, (hipStream_t)stream, n_rays, rgb, target, dist,
                        dist_weight, loss, grad_rgb, grad_dist);
     return check_hip(hipGetLastError(), "loss_head_kernel launch");

@@ -1387,8 +1387,10 @@ extern "C" int dvgo_mlp_forward(const dvgo_color_mlp *m, int32_t n_rays, const i
     if (!rgb) return set_error(DVGO_ERR_NULL, "rgb is NULL");
     a.rgb = rgb;
     hipStream_t st = (hipStream_t)stream;
-    rc = launch_prep(a, st);
-    if (rc) return rc;
+    if (!m->prepared) {
+        rc = launch_prep(a, st);
+        if (rc) return rc;
+    }
     const int64_t nwt = (n_samples + FWD_WTILE - 1) / FWD_WTILE;
     const int64_t nb = (nwt + FWD_WAVES - 1) / FWD_WAVES;
     const dim3 grid((int)(nb < MAX_BLOCKS ? nb : MAX_BLOCKS));
@@ -1408,8 +1410,10 @@ extern "C" int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const 
     a.grad_rgb = grad_rgb;
     a.grad_feat = grad_feat;
     hipStream_t st = (hipStream_t)stream;
-    rc = launch_prep(a, st);
-    if (rc) return rc;
+    if (!m->prepared) {
+        rc = launch_prep(a, st);
+        if (rc) return rc;
+    }
     if (m->precision == DVGO_MLP_F16)
         hipLaunchKernelGGL((mlp_bwd_kernel<false, false>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     else
@@ -1438,8 +1442,10 @@ extern "C" int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays
     a.grad_rgb = grad_rgb;
     a.xyz = xyz;
     hipStream_t st = (hipStream_t)stream;
-    rc = launch_prep(a, st);
-    if (rc) return rc;
+    if (!m->prepared) {
+        rc = launch_prep(a, st);
+        if (rc) return rc;
+    }
     if (m->precision == DVGO_MLP_F16)
         hipLaunchKernelGGL((mlp_bwd_kernel<false, true>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     else

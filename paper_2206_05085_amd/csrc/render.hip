@@ -564,12 +564,16 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
     void *state = nullptr;
     const size_t sb = state_bytes(R, S);
     if (hipMalloc(&buf, nf * sizeof(float)) != hipSuccess || hipMalloc(&state, sb) != hipSuccess) {
-        if (buf) hipFree(buf);
+        if (buf) (void)hipFree(buf);
         return set_error(DVGO_ERR_HIP, "autotune scratch allocation failed");
     }
     float *rgb = buf, *T = rgb + 3 * (size_t)R, *dist = T + R, *grgb = dist + R, *gdist = grgb + 3 * (size_t)R,
           *gT = gdist + R, *gden = gT + R, *gcol = gden + n_dens, *gs = gcol + n_col;
-    hipMemsetD32Async((hipDeviceptr_t)grgb, 0x3f800000, 3 * (size_t)R + 2 * (size_t)R, st);  // ones
+    // the first HIP failure below is kept in rc; later steps are skipped, the scratch is freed
+    auto ck = [&rc](hipError_t e, const char *what) {
+        if (!rc && e != hipSuccess) rc = check_hip(e, what);
+    };
+    ck(hipMemsetD32Async((hipDeviceptr_t)grgb, 0x3f800000, 3 * (size_t)R + 2 * (size_t)R, st), "autotune fill");  // ones
     dvgo_grid dg = *density, cg;
     dg.grad = gden;
     if (color) {
@@ -582,7 +586,7 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
     fa.dist = dist;
     fa.sample_w = nullptr;
     split_state(state, R, &fa.halt_idx, &fa.ckpt);
-    rc = fill_render_args(p, s, &dg, color ? &cg : nullptr, sample_rgb, true, ba);
+    if (!rc) rc = fill_render_args(p, s, &dg, color ? &cg : nullptr, sample_rgb, true, ba);
     ba.T_in = T;
     ba.grad_rgb = grgb;
     ba.grad_dist = p->want_dist ? gdist : nullptr;
@@ -590,9 +594,9 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
     ba.grad_srgb = gs;
     ba.halt_idx = fa.halt_idx;
     ba.ckpt = fa.ckpt;
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ck(hipEventCreate(&e0), "autotune event");
+    ck(hipEventCreate(&e1), "autotune event");
     TuneVal best{4, 0, 1e30f};
     const int wpbs[] = {2, 4, 8, 16};
     const int grids[] = {0, 1024, 2048, 4096, 8192, 16384};
@@ -604,24 +608,24 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
             q.grid_waves = grids[gi];
             rc = launch_fwd(&q, fa, st);  // warm-up
             if (!rc) rc = launch_bwd(&q, ba, st);
-            hipEventRecord(e0, st);
+            ck(hipEventRecord(e0, st), "autotune event record");
             for (int rep = 0; rep < 3 && !rc; ++rep) {
                 rc = launch_fwd(&q, fa, st);
                 if (!rc) rc = launch_bwd(&q, ba, st);
             }
-            hipEventRecord(e1, st);
-            hipEventSynchronize(e1);
+            ck(hipEventRecord(e1, st), "autotune event record");
+            ck(hipEventSynchronize(e1), "autotune event wait");
             float t = 0.f;
-            hipEventElapsedTime(&t, e0, e1);
+            ck(hipEventElapsedTime(&t, e0, e1), "autotune event time");
             t /= 3.f;
             if (!rc && t < best.ms) best = TuneVal{wpbs[wi], grids[gi], t};
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipStreamSynchronize(st);
-    hipFree(buf);
-    hipFree(state);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    ck(hipStreamSynchronize(st), "autotune stream wait");  // the scratch is idle before it is freed
+    (void)hipFree(buf);
+    (void)hipFree(state);
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);

@@ -131,7 +131,9 @@ class MLPParams:
     n_freq: int = 4
     precision: int = 0   # MLP_SPLIT_F16 (FP32-grade) or MLP_F16 (one FP16 product per product)
 
-    def struct(self, need_grad=False) -> ColorMLP:
+    def struct(self, need_grad=False, prepared=False) -> ColorMLP:
+        """prepared: the workspace already holds this call's preparation (the previous MLP
+        call on it had the same weights, unchanged since, and the same batch)."""
         for i, (w, b) in enumerate(zip(self.W, self.b)):
             _chk(w, f"W{i + 1}")
             _chk(b, f"b{i + 1}")
@@ -139,6 +141,7 @@ class MLPParams:
         m.struct_size = C_size(ColorMLP)
         m.in_feat, m.n_freq, m.hidden = self.in_feat, self.n_freq, int(self.W[1].shape[0])
         m.precision = int(self.precision)
+        m.prepared = int(bool(prepared))
         m.W1, m.W2, m.W3 = [_p(w) for w in self.W]
         m.b1, m.b2, m.b3 = [_p(b) for b in self.b]
         if self.gW is not None:
@@ -428,46 +431,61 @@ def mlp_forward(mlp: MLPParams, ray_offsets, dirs, feat, rgb=None, ws=None):
     return rgb
 
 
-def mlp_backward(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, grad_feat=None, ws=None):
+def mlp_backward(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, grad_feat=None, ws=None, prepared=False):
+    """prepared=True reuses the preparation a preceding mlp_forward on the same ws wrote
+    (same weights and batch); it needs an explicit ws."""
     import ctypes
+    if prepared and ws is None:
+        raise ValueError("prepared=True needs the workspace of the preceding call")
     R = ray_offsets.numel() - 1
     S = feat.shape[0]
     _chk(grad_rgb, "grad_rgb", numel=3 * S)
     if grad_feat is None:
         grad_feat = torch.empty(S, mlp.in_feat, device=feat.device)
     ws = _mlp_ws(mlp, R, S, ws, feat.device)
-    m = mlp.struct(need_grad=True)
+    m = mlp.struct(need_grad=True, prepared=prepared)
     call("dvgo_mlp_backward", ctypes.byref(m), R, _p(ray_offsets), _p(dirs), S, _p(feat), _p(grad_rgb),
          _p(grad_feat), _p(ws), ws.numel(), _stream())
     return grad_feat
 
 
-def mlp_backward_scatter(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, feat_grid: DeviceGrid, xyz, ws=None):
+def mlp_backward_scatter(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, feat_grid: DeviceGrid, xyz, ws=None,
+                         prepared=False):
     """MLP backward (parameter gradients +=) with the feature gradient scattered into
     feat_grid.grad at xyz inside the kernel (no per-sample feature gradient is written)."""
     import ctypes
+    if prepared and ws is None:
+        raise ValueError("prepared=True needs the workspace of the preceding call")
     R = ray_offsets.numel() - 1
     S = feat.shape[0]
     _chk(grad_rgb, "grad_rgb", numel=3 * S)
     _chk(xyz, "xyz", numel=3 * S)
     dev = feat.device
     ws = _mlp_ws(mlp, R, S, ws, dev)
-    call("dvgo_mlp_backward_scatter", ctypes.byref(mlp.struct(need_grad=True)), R, _p(ray_offsets), _p(dirs), S,
+    call("dvgo_mlp_backward_scatter", ctypes.byref(mlp.struct(need_grad=True, prepared=prepared)), R, _p(ray_offsets), _p(dirs), S,
          _p(feat), _p(grad_rgb), ctypes.byref(feat_grid.struct(need_grad=True)), _p(xyz), _p(ws), ws.numel(),
          _stream())
 
 
-def loss_head(rgb, target, dist, dist_weight, loss=None, grad_rgb=None, grad_dist=None):
+def loss_head(rgb, target, dist, dist_weight, loss=None, grad_rgb=None, grad_dist=None, want_loss=True,
+              want_grad=True):
+    """want_loss / want_grad = False leave that part out (its outputs are then None): the
+    gradients alone take a many-block launch, the loss a one-block reduction."""
     R = rgb.shape[0]
     _chk(rgb, "rgb", numel=3 * R)
     _chk(target, "target", numel=3 * R)
     if dist is not None:
         _chk(dist, "dist", numel=R)
+    if not (want_loss or want_grad):
+        raise ValueError("loss_head: nothing requested")
     dev = rgb.device
-    loss = torch.empty(1, device=dev) if loss is None else loss
-    grad_rgb = torch.empty(R, 3, device=dev) if grad_rgb is None else grad_rgb
-    if grad_dist is None and dist is not None:
-        grad_dist = torch.empty(R, device=dev)
+    loss = (torch.empty(1, device=dev) if loss is None else loss) if want_loss else None
+    if want_grad:
+        grad_rgb = torch.empty(R, 3, device=dev) if grad_rgb is None else grad_rgb
+        if grad_dist is None and dist is not None:
+            grad_dist = torch.empty(R, device=dev)
+    else:
+        grad_rgb = grad_dist = None
     call("dvgo_loss_head", R, _p(rgb), _p(target), _p(dist), dist_weight, _p(loss), _p(grad_rgb), _p(grad_dist),
          _stream())
     return loss, grad_rgb, grad_dist

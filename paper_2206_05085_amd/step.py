@@ -147,20 +147,31 @@ class TrainStep:
         return self.schedule, ms
 
     # --------------------------------------------------------------- stages
-    def forward(self):
+    def forward(self, side=None, gathered=False):
+        """side (optional stream): the loss value is reduced there, off the path of the
+        backward, which needs only the gradients of the loss head.  gathered: the features of
+        the samples are already in feat_s."""
         b = self.batch
         if self.grid_mode:
             ops.render_forward(b, self.grid("density"), self.grid("color"), None, act_shift_=self.shift,
                                halt_T=self.halt_T, bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist),
                                state=self.state, schedule=self.schedule)
         else:
-            ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
+            if not gathered:
+                ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
             ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws)
             ops.render_forward(b, self.grid("density"), None, self.rgb_s, act_shift_=self.shift, halt_T=self.halt_T,
                                bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist), state=self.state,
                                schedule=self.schedule)
-        ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, grad_rgb=self.g_rgb,
-                      grad_dist=self.g_dist)
+        if side is None:
+            ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, grad_rgb=self.g_rgb,
+                          grad_dist=self.g_dist)
+            return
+        ops.loss_head(self.rgb, self.target, self.dist, self.lam, grad_rgb=self.g_rgb, grad_dist=self.g_dist,
+                      want_loss=False)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
 
     def backward(self):
         b = self.batch
@@ -201,10 +212,10 @@ class TrainStep:
         b = self.batch
         if self.fused:
             ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
-                                     b.xyz, ws=self.mlp_ws)
+                                     b.xyz, ws=self.mlp_ws, prepared=True)
             return
         ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
-                         ws=self.mlp_ws)
+                         ws=self.mlp_ws, prepared=True)
         # the 12-channel feature gradient keeps the in-wave aggregated scatter: its brick tiles
         # share half their vertices with neighbours, so binning saves no atomics there
         ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
@@ -221,37 +232,39 @@ class TrainStep:
             self.backward()
             self.optimise()
             return self.loss
-        # Two streams.  main: forward, render backward, colour-head backward, feature scatter,
-        # feature Adam.  side: binning (needs only the points), then after the render backward
-        # the density scatter (+ TV) and density Adam, then after the colour-head backward the
-        # MLP Adam.  Each buffer has one writer at a time; the side joins main at the end.
+        # Two streams.  main: feature gather, colour head, render forward and backward, colour-head
+        # backward, feature scatter, feature Adam.  side: the binning (needs only the points) beside
+        # the colour head's forward, the loss value after the render forward, and after the
+        # colour-head backward the density scatter (+ TV), density Adam and MLP Adam beside the
+        # feature scatter.  The colour-head backward takes nearly all of a CU's LDS and registers,
+        # so nothing is meant to run beside it.  Each buffer has one writer at a time; the side
+        # joins main at the end.
         main = torch.cuda.current_stream()
         if self.side is None:
             self.side = torch.cuda.Stream(device=self.device)
         side = self.side
         b = self.batch
         ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+        ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
         side.wait_stream(main)
         with torch.cuda.stream(side):
             ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
-        self.forward()
+        self.forward(side, gathered=True)
         ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
                             None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
                             schedule=self.schedule, grad_sample_density=self.g_raw)
+        if self.fused:
+            ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
+                                     b.xyz, ws=self.mlp_ws, prepared=True)
+        else:
+            ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
+                             ws=self.mlp_ws, prepared=True)
         side.wait_stream(main)
         with torch.cuda.stream(side):
             ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
             if self.tv is not None:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
             self._adam("density", self.lr_grid, True)
-        if self.fused:
-            ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
-                                     b.xyz, ws=self.mlp_ws)
-        else:
-            ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
-                             ws=self.mlp_ws)
-        side.wait_stream(main)
-        with torch.cuda.stream(side):
             self._adam("mlp_flat", self.lr_mlp, False)
         if not self.fused:
             ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)

@@ -392,9 +392,19 @@ def _mlp_case(dv, S_lengths, seed, bias_std=0.3, half=False):
     gW = [torch.zeros_like(w) for w in W]
     gb = [torch.zeros_like(v) for v in b]
     P = dv.MLPParams(W, b, gW, gb, precision=dv.MLP_F16 if half else dv.MLP_SPLIT_F16)
-    rgb = dv.mlp_forward(P, T(offs, torch.int32), T(dirs), T(feat))
-    gf = dv.mlp_backward(P, T(offs, torch.int32), T(dirs), T(feat), T(grgb))
+    ws = torch.empty(dv.mlp_workspace_size(P, R, S), dtype=torch.uint8, device="cuda")
+    rgb = dv.mlp_forward(P, T(offs, torch.int32), T(dirs), T(feat), ws=ws)
+    # the backward that reuses the forward's preparation (as the training step does) and one
+    # that prepares again on a fresh workspace take identical results
+    gf = dv.mlp_backward(P, T(offs, torch.int32), T(dirs), T(feat), T(grgb), ws=ws, prepared=True)
+    gW2 = [torch.zeros_like(w) for w in W]
+    gb2 = [torch.zeros_like(v) for v in b]
+    P2 = dv.MLPParams(W, b, gW2, gb2, precision=P.precision)
+    gf2 = dv.mlp_backward(P2, T(offs, torch.int32), T(dirs), T(feat), T(grgb))
     torch.cuda.synchronize()
+    assert torch.equal(gf, gf2)
+    for x, y in zip(gW + gb, gW2 + gb2):
+        assert torch.equal(x, y)
     f64, g64 = feat.astype(np.float64), grgb.astype(np.float64)
     ref = oracle.mlp_forward(mlp, offs, dirs, f64, half=half)
     rgf, rgW, rgb_ = oracle.mlp_backward(mlp, offs, dirs, f64, g64, half=half)
@@ -521,3 +531,16 @@ def test_loss_head(dv):
     close(L.cpu().numpy(), [oL], **FWD, name="loss")
     close(gr.cpu().numpy(), oGC, **FWD, name="dL/drgb")
     close(gd.cpu().numpy(), oGD, **FWD, name="dL/dD")
+    # the split the two-stream step uses: gradients alone (many blocks), the loss alone (one block);
+    # the same float32 expressions, so the parts equal the combined call bit for bit
+    for n in (R, 1000, 1):
+        say("loss head parts, R =", n)
+        _, gr2, gd2 = dv.loss_head(T(rgb[:n]), T(tgt[:n]), T(D[:n]), 0.01, want_loss=False)
+        L2, gn, dn = dv.loss_head(T(rgb[:n]), T(tgt[:n]), T(D[:n]), 0.01, want_grad=False)
+        Lc, grc, gdc = dv.loss_head(T(rgb[:n]), T(tgt[:n]), T(D[:n]), 0.01)
+        torch.cuda.synchronize()
+        assert gn is None and dn is None
+        assert torch.equal(gr2, grc) and torch.equal(gd2, gdc) and torch.equal(L2, Lc)
+    _, gr3, gd3 = dv.loss_head(T(rgb), T(tgt), None, 0.01, want_loss=False)
+    torch.cuda.synchronize()
+    assert gd3 is None and torch.equal(gr3, gr)
