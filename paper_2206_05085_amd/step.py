@@ -147,10 +147,10 @@ class TrainStep:
         return self.schedule, ms
 
     # --------------------------------------------------------------- stages
-    def forward(self, side=None, gathered=False):
-        """side (optional stream): the loss value is reduced there, off the path of the
-        backward, which needs only the gradients of the loss head.  gathered: the features of
-        the samples are already in feat_s."""
+    def forward(self, gathered=False, loss_value=True):
+        """gathered: the features of the samples are already in feat_s.  loss_value=False:
+        the loss head writes only the gradients the backward needs (the caller reduces the
+        loss value later, off the backward's path)."""
         b = self.batch
         if self.grid_mode:
             ops.render_forward(b, self.grid("density"), self.grid("color"), None, act_shift_=self.shift,
@@ -163,15 +163,8 @@ class TrainStep:
             ops.render_forward(b, self.grid("density"), None, self.rgb_s, act_shift_=self.shift, halt_T=self.halt_T,
                                bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist), state=self.state,
                                schedule=self.schedule)
-        if side is None:
-            ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, grad_rgb=self.g_rgb,
-                          grad_dist=self.g_dist)
-            return
-        ops.loss_head(self.rgb, self.target, self.dist, self.lam, grad_rgb=self.g_rgb, grad_dist=self.g_dist,
-                      want_loss=False)
-        side.wait_stream(torch.cuda.current_stream())
-        with torch.cuda.stream(side):
-            ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
+        ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, grad_rgb=self.g_rgb,
+                      grad_dist=self.g_dist, want_loss=loss_value)
 
     def backward(self):
         b = self.batch
@@ -233,23 +226,23 @@ class TrainStep:
             self.optimise()
             return self.loss
         # Two streams.  main: feature gather, colour head, render forward and backward, colour-head
-        # backward, feature scatter, feature Adam.  side: the binning (needs only the points) beside
-        # the colour head's forward, the loss value after the render forward, and after the
-        # colour-head backward the density scatter (+ TV), density Adam and MLP Adam beside the
-        # feature scatter.  The colour-head backward takes nearly all of a CU's LDS and registers,
-        # so nothing is meant to run beside it.  Each buffer has one writer at a time; the side
-        # joins main at the end.
+        # backward, feature scatter, feature Adam.  side: the binning (needs only the points) from
+        # the start, and after the colour-head backward the density scatter (+ TV), density Adam,
+        # MLP Adam and the loss value beside the feature scatter.  The colour-head backward takes
+        # nearly all of a CU's LDS and registers, so nothing is meant to run beside it.  Main
+        # hands work to the side once (each hand-over delays main's next kernel in a graph).  Each
+        # buffer has one writer at a time; the side joins main at the end.
         main = torch.cuda.current_stream()
         if self.side is None:
             self.side = torch.cuda.Stream(device=self.device)
         side = self.side
         b = self.batch
-        ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
-        ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
         side.wait_stream(main)
         with torch.cuda.stream(side):
             ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
-        self.forward(side, gathered=True)
+        ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+        ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
+        self.forward(gathered=True, loss_value=False)
         ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
                             None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
                             schedule=self.schedule, grad_sample_density=self.g_raw)
@@ -266,6 +259,7 @@ class TrainStep:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
             self._adam("density", self.lr_grid, True)
             self._adam("mlp_flat", self.lr_mlp, False)
+            ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
         if not self.fused:
             ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
         if self.tv is not None:
