@@ -114,7 +114,7 @@ __device__ __forceinline__ h8 cat(h4 a, h4 b) { return __builtin_shufflevector(a
 
 // logistic function with the hardware exponential and reciprocal (about 1e-7 relative; the
 // limits are exact: 1/(1 + inf) = 0 and 1/(1 + 0) = 1)
-__device__ __forceinline__ float fast_sigmoid(float z) { return __fdividef(1.f, 1.f + __expf(-z)); }
+__device__ __forceinline__ float fast_sigmoid(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 
 __device__ __forceinline__ float pow2(int e) { return __builtin_amdgcn_ldexpf(1.f, e); }
 __device__ __forceinline__ float ldx(float v, int e) { return __builtin_amdgcn_ldexpf(v, e); }
@@ -550,8 +550,8 @@ constexpr int DFS = 12;                              // row of dfeat partials (f
 constexpr int B_DFP = B_Z3P + 4 * NT * 4 * 4;        // dfeat partials [4][NT][DFS] f32
 constexpr int H2S = 36;                              // row stride (floats) of the h2 plane
 constexpr int B_H2 = B_DFP + 4 * NT * DFS * 4;       // h2 [H][H2S] f32, written by P, read by C
-constexpr int B_MASK = B_H2 + H * H2S * 4;           // h1 > 0 ballots [2][4][2][2][4] u64
-constexpr int B_XMAX = B_MASK + 2 * 4 * 16 * 8;      // max |x| per sample [2][NT]
+constexpr int B_MASK = B_H2 + H * H2S * 4;           // h1 > 0 bits per lane [2][4 waves][64 lanes] u16
+constexpr int B_XMAX = B_MASK + 2 * 4 * 64 * 2;      // max |x| per sample [2][NT]
 constexpr int B_GR = B_XMAX + 2 * NT * 4;            // grad_rgb [2][NT][4]
 constexpr int B_END = B_GR + 2 * NT * 16;
 static_assert(B_END <= 160 * 1024, "backward LDS");
@@ -574,12 +574,20 @@ __device__ __forceinline__ h8 glb_h8(const unsigned char *img, int off, int idx)
     return *reinterpret_cast<const h8 *>(reinterpret_cast<const _Float16 *>(img + off) + idx);
 }
 
+// fp16(t - h) for h = fp16(t), in one mixed-precision FMA (t * 1 - h rounded once to fp16);
+// t - h is exact in fp32, so this equals (_Float16)(t - (float)h)
+__device__ __forceinline__ _Float16 lo_part(float t, _Float16 h) {
+    _Float16 r;
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(r) : "v"(t), "v"(h));
+    return r;
+}
+
 // write a split value into a transposed plane [unit][TS] (the lo plane only in split mode)
 template <bool SPLIT>
 __device__ __forceinline__ void put_t(unsigned char *base, int off_h, int off_l, int unit, int col, float t) {
     const _Float16 h = (_Float16)t;
     reinterpret_cast<_Float16 *>(base + off_h)[unit * TS + col] = h;
-    if (SPLIT) reinterpret_cast<_Float16 *>(base + off_l)[unit * TS + col] = (_Float16)(t - (float)h);
+    if (SPLIT) reinterpret_cast<_Float16 *>(base + off_l)[unit * TS + col] = lo_part(t, h);
 }
 
 __device__ __forceinline__ void store_h4(unsigned char *base, int off, int idx, h4 v) {
@@ -753,7 +761,9 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     float *z3p = reinterpret_cast<float *>(rB);
     float *dfp = reinterpret_cast<float *>(rB + (B_DFP - B_Z3P));
     float *h2s = reinterpret_cast<float *>(rB + (B_H2 - B_Z3P));
-    unsigned long long *mask_b = reinterpret_cast<unsigned long long *>(rB + (B_MASK - B_Z3P));
+    // bit (c 2 + mp) 4 + r of lane (j, q) of wave w: h1 > 0 for unit 32w + 16mp + 4q + r, sample
+    // 16c + j; the P wave and the C wave of the same w use the same lane -> (unit, sample) map
+    uint16_t *mask_b = reinterpret_cast<uint16_t *>(rB + (B_MASK - B_Z3P));
     float *xmax_b = reinterpret_cast<float *>(rB + (B_XMAX - B_Z3P));
     float *gr_b = reinterpret_cast<float *>(rB + (B_GR - B_Z3P));
     const int ntiles = a.n_tiles;
@@ -794,11 +804,12 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             const float *gr_s = gr_b + pb * NT * 4;
             const int xb = B_XB0 + pb * XB_BYTES;
             unsigned char *hb = lds_region(sm, B_HB0 + pb * HB_BYTES);
-            unsigned long long *mask1 = mask_b + pb * 64;
+            uint16_t *mask1 = mask_b + pb * 256;
             // ---- A: layer 1 for units 32w..; h1 -> B operand, transposed planes, mask bits
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
                 v4f acc[2][2];  // [c][mp]
+                unsigned mbits = 0;
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -838,9 +849,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             h1[r] = fmaxf(fmaf(acc[c][mp][r], un, bv[r]), 0.f);
-                            // bit 16 q + j: unit 32w + 16mp + 4q + r of sample 16c + j
-                            const unsigned long long bits = __ballot(h1[r] > 0.f);
-                            if (ln == 0) mask1[((w * 2 + mp) * 2 + c) * 4 + r] = bits;
+                            mbits |= (h1[r] > 0.f ? 1u : 0u) << ((c * 2 + mp) * 4 + r);
                         }
                         h4 hi, lo;
                         split4(h1, sc, hi, lo);
@@ -855,6 +864,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         }
                     }
                 }
+                mask1[w * 64 + ln] = (uint16_t)mbits;
             }
             lds_barrier();
             // ---- B: layer 2 for units 32w.., logit partials
@@ -1084,7 +1094,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         auto dz1_step = [&](int pb, const int g2[2], const int g1[2], const int ex[2]) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
             const unsigned char *hb = lds_region(sm, B_HB0 + pb * HB_BYTES);
-            const unsigned long long *mask1 = mask_b + pb * 64;
+            // this lane's h1 > 0 bits, read before the products so the load is long done
+            const unsigned mbits = mask_b[pb * 256 + w * 64 + ln];
             float dz1[2][2][4];
             v4f acc[2][2];  // [c][mp]
 #pragma unroll
@@ -1121,11 +1132,9 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
 #pragma unroll
                 for (int mp = 0; mp < 2; ++mp) {
                     const int u0 = 32 * w + 16 * mp + 4 * q;
-                    const unsigned long long *mk = mask1 + ((w * 2 + mp) * 2 + c) * 4;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        // lane 16q + j of the ballot is this lane's unit and sample
-                        const bool on = __builtin_amdgcn_inverse_ballot_w64(mk[r]);
+                        const bool on = (mbits >> ((c * 2 + mp) * 4 + r)) & 1u;
                         dz1[mp][c][r] = on ? acc[c][mp][r] * un : 0.f;
                         db1[mp][r] += dz1[mp][c][r];
                         put_t<SPLIT>(rA, B_D1TH - B_HTH, B_D1TL - B_HTH, u0 + r, 16 * c + j, ldx(dz1[mp][c][r], fs));

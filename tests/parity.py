@@ -50,3 +50,20 @@ def close(x, y, rtol, floor, name="value", scale=None, skip=None, slack=None, el
             raise AssertionError(f"{name}: {bad.sum()} of {y.size} elements out of bound; worst at {i}: "
                                  f"gpu {x[i]:.9g} oracle {y[i]:.9g} bound {bound[i]:.3g}")
     return err / max(ny, 1e-300)
+
+
+def close_after_adam(x, y, steps, lr, name="value", rtol=1e-5):
+    """Grid parameters after `steps` Adam updates in two runs whose gradients are sums of the same
+    terms added in different orders (atomics).  Adam's update is normalised (at most about lr per
+    step for beta1^2 < beta2), so where a gradient nearly cancels, the reordered sum can move that
+    element's update by up to lr per step in each run.  Checked: normwise within rtol; every
+    element within 2 lr per step; all but 1e-4 of the elements within rtol of max(|y|, steps lr)."""
+    x = np.asarray(x, np.float64).ravel()
+    y = np.asarray(y, np.float64).ravel()
+    assert x.shape == y.shape, f"{name}: shape {x.shape} vs {y.shape}"
+    assert np.isfinite(x).all(), f"{name}: non-finite values"
+    d = np.abs(x - y)
+    assert d.max() <= 2 * lr * steps, f"{name}: {d.max():.3g} beyond Adam's step bound"
+    assert np.linalg.norm(x - y) <= rtol * np.linalg.norm(y) + 1e-30, f"{name}: normwise"
+    loose = d > rtol * np.maximum(np.abs(y), steps * lr)
+    assert loose.mean() <= 1e-4, f"{name}: {loose.sum()} of {y.size} beyond rounding"

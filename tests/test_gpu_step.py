@@ -6,7 +6,7 @@ import torch
 
 import oracle
 import synth
-from parity import FWD, GRAD, close
+from parity import FWD, GRAD, close, close_after_adam
 
 pytestmark = pytest.mark.gpu
 
@@ -102,8 +102,8 @@ def test_graph_replays_match_eager(pkg):
         torch.cuda.synchronize()
         _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
         close(b.loss.cpu().numpy(), a.loss.cpu().numpy(), rtol=1e-5, floor=1e-3, name=f"loss replay {rep}")
-        close(b.density["p"].cpu().numpy(), a.density["p"].cpu().numpy(), rtol=1e-5, floor=1e-3,
-              name=f"density replay {rep}")
+        close_after_adam(b.density["p"].cpu().numpy(), a.density["p"].cpu().numpy(), 2 + rep, a.lr_grid,
+                         name=f"density replay {rep}")
         close(b.mlp_flat["p"].cpu().numpy(), a.mlp_flat["p"].cpu().numpy(), rtol=1e-5, floor=1e-3,
               name=f"mlp replay {rep}")
 
@@ -135,13 +135,14 @@ def test_two_stream_step_matches_sequential(pkg, fused):
         torch.cuda.synchronize()
         for name in ("density", "feat", "mlp_flat"):
             ref = getattr(seq, name)["p"].cpu().numpy()
-            # the fused feature scatter adds the same terms in another order; Adam normalises
-            # each step's update to at most about lr, so a reordered gradient moves a feature by
-            # a fraction of lr per step (steps so far: 2 + rep)
-            scale = np.full(ref.shape, (2 + rep) * seq.lr_grid) if (fused and name == "feat") else None
             for other, tag in ((conc, "eager"), (gr, "graph")):
-                close(getattr(other, name)["p"].cpu().numpy(), ref, rtol=1e-5, floor=1e-3, scale=scale,
-                      name=f"{name} two-stream {tag} step {rep}")
+                got = getattr(other, name)["p"].cpu().numpy()
+                if name == "mlp_flat":  # its gradient is reduced in a fixed order
+                    close(got, ref, rtol=1e-5, floor=1e-3, name=f"{name} two-stream {tag} step {rep}")
+                    continue
+                # grid gradients are sums of atomic adds, whose order differs between runs (and the
+                # fused feature scatter adds the terms in another order by design)
+                close_after_adam(got, ref, 2 + rep, seq.lr_grid, name=f"{name} two-stream {tag} step {rep}")
                 assert not getattr(other, name)["g"].any(), f"{name} gradient not cleared ({tag})"
 
 
