@@ -116,6 +116,31 @@ __device__ __forceinline__ h8 cat(h4 a, h4 b) { return __builtin_shufflevector(a
 // limits are exact: 1/(1 + inf) = 0 and 1/(1 + 0) = 1)
 __device__ __forceinline__ float fast_sigmoid(float z) { return __builtin_amdgcn_rcpf(1.f + __expf(-z)); }
 
+// Reductions over aligned lane groups with DPP moves (no LDS round trip).  quad_perm [1,0,3,2]
+// and [2,3,0,1] reduce each quad; row_half_mirror (lane i of an 8-lane half-row reads lane
+// 7 - i) joins the two quads of a half-row; row_mirror (15 - i) joins the halves of a row.
+template <int CTRL>
+__device__ __forceinline__ int dpp_mov(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_movf(float v) {
+    return __builtin_bit_cast(float, dpp_mov<CTRL>(__builtin_bit_cast(int, v)));
+}
+// min over the 16 lanes of each row
+__device__ __forceinline__ int row16_min(int v) {
+    v = min(v, dpp_mov<0xB1>(v));
+    v = min(v, dpp_mov<0x4E>(v));
+    v = min(v, dpp_mov<0x141>(v));
+    return min(v, dpp_mov<0x140>(v));
+}
+// max over each aligned group of 8 lanes
+__device__ __forceinline__ float group8_max(float v) {
+    v = fmaxf(v, dpp_movf<0xB1>(v));
+    v = fmaxf(v, dpp_movf<0x4E>(v));
+    return fmaxf(v, dpp_movf<0x141>(v));
+}
+
 __device__ __forceinline__ float pow2(int e) { return __builtin_amdgcn_ldexpf(1.f, e); }
 __device__ __forceinline__ float ldx(float v, int e) { return __builtin_amdgcn_ldexpf(v, e); }
 
@@ -180,6 +205,23 @@ __device__ __forceinline__ int ray_in_window(const int *offs, int R, int r0, int
     }
     if (lo == 63 && r0 + 64 <= R && offs[r0 + 64] <= s) return find_ray(offs, R, s);
     return r0 + lo;
+}
+
+// The same ray for the 8 consecutive samples sbase + (lane >> 3) of a wave (sbase wave-uniform
+// and at or after offs[r0]): per sample, a ballot counts the window entries at or before it
+// (a prefix, as offs is non-decreasing), so no lane-to-lane round trips are needed.  All 64
+// lanes must call it.
+__device__ __forceinline__ int ray_of_group8(const int *offs, int R, int r0, int w, int sbase) {
+    const int k = lane() >> 3;
+    int cnt = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int c = __popcll(__ballot(w <= sbase + i));
+        cnt = k == i ? c : cnt;
+    }
+    const int s = sbase + k;
+    if (cnt == 64 && r0 + 64 <= R && offs[r0 + 64] <= s) return find_ray(offs, R, s);
+    return r0 + cnt - 1;
 }
 
 __device__ __forceinline__ int window_entry(const int *offs, int R, int r0) {
@@ -720,13 +762,18 @@ __device__ __forceinline__ GradExp grad_exp(const float *z3p, const float *gr_s,
     return g;
 }
 
+// (W3^T dz3) for unit row r of a lane's 4: one fixed sequence of FMAs, so both roles that form
+// it get the same value bit for bit
+__device__ __forceinline__ float w3t_dz3(const float (&wv)[3][4], const float (&dz3)[3], int r) {
+    return __builtin_fmaf(wv[2][r], dz3[2], __builtin_fmaf(wv[1][r], dz3[1], wv[0][r] * dz3[0]));
+}
+
 // smallest frame the tile allows: F <= 14 + (other operand's exponent) - ceil_exp(bound)
 __device__ __forceinline__ int tile_frame(const int other_e[2], const int k[2]) {
     int f = FRAME_NONE;
 #pragma unroll
     for (int c = 0; c < 2; ++c) f = min(f, 14 + other_e[c] - k[c]);
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) f = min(f, __shfl_xor(f, o, 64));
+    f = row16_min(f);  // over the 16 sample lanes j of the row
     // every lane holds the same value: make it scalar so the (rare) rescale is a real branch
     return __builtin_amdgcn_readfirstlane(f);
 }
@@ -929,7 +976,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
             }
             lds_barrier();
-            // ---- C: dz3, dz2 = mask(h2) W3^T dz3 (VALU), dz2 B operand and frame-scaled dz2^T
+            // ---- C: dz3, dz2 = mask(h2) W3^T dz3 (VALU), dz2 B operand (the C waves write dz2^T)
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
                 const GradExp ge = grad_exp(z3p, gr_s, b3, meta, j);
@@ -946,7 +993,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         float dz2[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
-                            const float d = wv[0][r] * ge.dz3[c][0] + wv[1][r] * ge.dz3[c][1] + wv[2][r] * ge.dz3[c][2];
+                            const float d = w3t_dz3(wv, ge.dz3[c], r);
                             dz2[r] = h2s[(u0 + r) * H2S + 16 * c + j] > 0.f ? d : 0.f;
                         }
                         h4 hi, lo;
@@ -954,10 +1001,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
                         store_h4(hb, 0, ob, hi);
                         if (SPLIT) store_h4(hb, NT * RS2 * 2, ob, lo);
-                        const int fs = frame_shift(F2, se.e1[c]);  // exact for any shift; 0 stays 0
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            put_t<SPLIT>(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2[r], fs));
                     }
                 }
             }
@@ -1030,13 +1073,17 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 for (int o = 0; o < 3; ++o) dw3[o][mp][r] = 0.f;
             }
         int F1 = FRAME_NONE;
+        // the P waves' dW2 frame, followed step by step from the same per-tile inputs (the C
+        // waves write the frame-scaled dz2^T planes that the P waves' dW2 products read)
+        int F2 = FRAME_NONE;
         // inputs of a tile: global loads, in three steps spread over phases so that their
         // latency overlaps other work (ray window; ray search and feature loads; staging)
         float xv[8], grv = 0.f;
         auto load_tile = [&](int t, int r0, int win) {
             const int s = t * NT + xsl;
             const bool sv = s < a.S;
-            const int ray = ray_in_window(a.offs, a.n_rays, r0, win, s);  // all lanes take part
+            // all lanes take part; this wave's samples are t NT + 8 w + (lane >> 3)
+            const int ray = ray_of_group8(a.offs, a.n_rays, r0, win, t * NT + 8 * w);
 #pragma unroll
             for (int e = 0; e < 8; ++e) xv[e] = 0.f;
             grv = 0.f;
@@ -1050,9 +1097,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             float m = 0.f;
 #pragma unroll
             for (int e = 0; e < 8; ++e) m = fmaxf(m, fabsf(xv[e]));
-            m = fmaxf(m, __shfl_xor(m, 1, 64));
-            m = fmaxf(m, __shfl_xor(m, 2, 64));
-            m = fmaxf(m, __shfl_xor(m, 4, 64));
+            m = group8_max(m);  // over the 8 slot groups xg of this sample
             const float sc = pow2(scale_exp(m));
             h4 h0, l0, h1, l1;
             split4(&xv[0], sc, h0, l0);
@@ -1188,6 +1233,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 const SampleExp se = sample_exp(xmax_b + pb * NT, meta, j);
                 const GradExp ge = grad_exp(z3p, gr_b + pb * NT * 4, b3, meta, j);
                 rescale<3>(dW1, F1, tile_frame(se.ex, ge.k1));
+                F2 = min(F2, tile_frame(se.e1, ge.k2));  // as rescale<8> moves it on the P side
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     pg2[c] = ge.g2[c];
@@ -1208,15 +1254,19 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     const float4 x2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + u0);
                     const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
 #pragma unroll
-                    for (int c = 0; c < 2; ++c)
+                    for (int c = 0; c < 2; ++c) {
+                        const int fs = frame_shift(F2, se.e1[c]);  // exact for any shift; 0 stays 0
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const float h2 = h2s[(u0 + r) * H2S + 16 * c + j];
-                            const float d = wv[0][r] * ge.dz3[c][0] + wv[1][r] * ge.dz3[c][1] + wv[2][r] * ge.dz3[c][2];
-                            db2[mp][r] += h2 > 0.f ? d : 0.f;
+                            const float d = w3t_dz3(wv, ge.dz3[c], r);
+                            const float dz2 = h2 > 0.f ? d : 0.f;  // the P waves' value, bit for bit
+                            db2[mp][r] += dz2;
+                            put_t<SPLIT>(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2, fs));
 #pragma unroll
                             for (int o = 0; o < 3; ++o) dw3[o][mp][r] += ge.dz3[c][o] * h2;
                         }
+                    }
                 }
             }
             lds_barrier();
