@@ -976,7 +976,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
             }
             lds_barrier();
-            // ---- C: dz3, dz2 = mask(h2) W3^T dz3 (VALU), dz2 B operand (the C waves write dz2^T)
+            // ---- C: dz3, dz2 = mask(h2) W3^T dz3 (VALU), dz2 B operand, the mp = 0 rows of dz2^T
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
                 const GradExp ge = grad_exp(z3p, gr_s, b3, meta, j);
@@ -1001,6 +1001,12 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
                         store_h4(hb, 0, ob, hi);
                         if (SPLIT) store_h4(hb, NT * RS2 * 2, ob, lo);
+                        if (mp == 0) {  // the C waves write the mp = 1 rows of dz2^T
+                            const int fs = frame_shift(F2, se.e1[c]);  // exact for any shift; 0 stays 0
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                put_t<SPLIT>(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2[r], fs));
+                        }
                     }
                 }
             }
@@ -1074,7 +1080,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             }
         int F1 = FRAME_NONE;
         // the P waves' dW2 frame, followed step by step from the same per-tile inputs (the C
-        // waves write the frame-scaled dz2^T planes that the P waves' dW2 products read)
+        // waves write the mp = 1 rows of the frame-scaled dz2^T planes the dW2 products read)
         int F2 = FRAME_NONE;
         // inputs of a tile: global loads, in three steps spread over phases so that their
         // latency overlaps other work (ray window; ray search and feature loads; staging)
@@ -1133,6 +1139,19 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     dW1[mp][n] = mfma16(dh, bh, dW1[mp][n]);
                 }
             }
+        };
+        // dW3 += dz3 h2^T over this lane's units and samples (h2 of the current tile)
+        auto dw3_step = [&](const float (&dz3)[2][3], int j, int q) {
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const float h2 = h2s[(32 * w + 16 * mp + 4 * q + r) * H2S + 16 * c + j];
+#pragma unroll
+                        for (int o = 0; o < 3; ++o) dw3[o][mp][r] += dz3[c][o] * h2;
+                    }
         };
         // dz1 = mask(h1) W2^T dz2 of a tile (buffers of parity pb, exponents g2/g1/ex of that
         // tile), dfeat partials, frame-scaled dz1^T
@@ -1214,6 +1233,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         lds_barrier();  // staged image and the first tile's inputs
         int it = 0, pbase = -1;
         int pg2[2] = {0, 0}, pg1[2] = {0, 0}, pex[2] = {0, 0};  // exponents of the previous tile
+        float tdz3[2][3];                                         // this tile's dz3 (for dW3 in D)
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
             const int pb = it & 1;
@@ -1227,18 +1247,21 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             if (next) load_tile(tile + gridDim.x, r0n, winn);
             if (pbase >= 0) dw1_step(pb ^ 1);
             lds_barrier();
-            // ---- C: output gradient and exponents of this tile; frame of dW1;
-            //      dW3 += dz3 h2^T, db2 += dz2, db3 += dz3 (VALU, h2 from the P waves)
+            // ---- C: output gradient and exponents of this tile; frames of dW1 and dW2; db2 += dz2,
+            //      db3 += dz3 (VALU, h2 from the P waves); the mp = 1 rows of dz2^T
             {
                 const SampleExp se = sample_exp(xmax_b + pb * NT, meta, j);
                 const GradExp ge = grad_exp(z3p, gr_b + pb * NT * 4, b3, meta, j);
                 rescale<3>(dW1, F1, tile_frame(se.ex, ge.k1));
                 F2 = min(F2, tile_frame(se.e1, ge.k2));  // as rescale<8> moves it on the P side
+                if (SCAT) dw3_step(ge.dz3, j, q);
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     pg2[c] = ge.g2[c];
                     pg1[c] = ge.g1[c];
                     pex[c] = se.ex[c];
+#pragma unroll
+                    for (int o = 0; o < 3; ++o) tdz3[c][o] = ge.dz3[c][o];
                 }
                 if (w == 0 && q == 0) {
 #pragma unroll
@@ -1262,17 +1285,19 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                             const float d = w3t_dz3(wv, ge.dz3[c], r);
                             const float dz2 = h2 > 0.f ? d : 0.f;  // the P waves' value, bit for bit
                             db2[mp][r] += dz2;
-                            put_t<SPLIT>(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2, fs));
-#pragma unroll
-                            for (int o = 0; o < 3; ++o) dw3[o][mp][r] += ge.dz3[c][o] * h2;
+                            if (mp == 1)
+                                put_t<SPLIT>(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2, fs));
                         }
                     }
                 }
             }
             lds_barrier();
             // ---- D: the next tile's inputs -> x planes (the P waves write the previous tile's
-            //      feature gradient meanwhile)
+            //      feature gradient meanwhile); dW3 += dz3 h2^T of this tile (h2 stays until the
+            //      P waves' next layer 2; the fused scatter uses that space in D, so there the
+            //      sums were taken in C)
             if (next) stage_tile(pb ^ 1);
+            if (!SCAT) dw3_step(tdz3, j, q);
             lds_barrier();
             pbase = tile * NT;
         }
