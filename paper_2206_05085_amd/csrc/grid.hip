@@ -79,7 +79,7 @@ int grid_blocks(int64_t work, int per_block = kBlock) {
 
 template <bool W>
 __global__ __launch_bounds__(kBlock) void gather_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
-                                                        float *__restrict__ out) {
+                                                        float *__restrict__ out, int vec_out) {
     for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < S; k += (int64_t)gridDim.x * kBlock) {
         const Tri t = trilinear<W>(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
         float acc[16];
@@ -109,9 +109,18 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(DevGrid g, int64_t S, co
                     if (ch < g.C) acc[ch] += t.w[c] * p[ch];
             }
         }
+        if (vec_out) {
+            // C % 4 == 0 and out 16-byte aligned: the row leaves as C / 4 float4 stores
 #pragma unroll
-        for (int ch = 0; ch < 16; ++ch)
-            if (ch < g.C) out[k * g.C + ch] = acc[ch];
+            for (int q = 0; q < 4; ++q)
+                if (4 * q < g.C)
+                    *reinterpret_cast<float4 *>(out + k * g.C + 4 * q) =
+                        make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int ch = 0; ch < 16; ++ch)
+                if (ch < g.C) out[k * g.C + ch] = acc[ch];
+        }
     }
 }
 
@@ -119,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(DevGrid g, int64_t S, co
 // ray, so contributions to shared vertices are summed in the wave before the atomics.
 template <int NC, bool W>
 __global__ __launch_bounds__(kBlock) void scatter_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
-                                                         const float *__restrict__ gout) {
+                                                         const float *__restrict__ gout, int vec_in) {
     const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
     const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6;
     for (int64_t base = wave * 64; base < S; base += nwaves * 64) {
@@ -131,13 +140,29 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(DevGrid g, int64_t S, c
         for (int ch = 0; ch < NC; ++ch) v[ch] = 0.f;
         if (valid) {
             cl = cell_of<W>(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+            if (NC % 4 == 0 && vec_in) {
+                // C % 4 == 0 and gout 16-byte aligned: the row arrives as C / 4 float4 loads
 #pragma unroll
-            for (int ch = 0; ch < NC; ++ch)
-                if (ch < g.C) v[ch] = gout[k * g.C + ch];
+                for (int q = 0; q < NC / 4; ++q)
+                    if (4 * q < g.C) {
+                        const float4 t = *reinterpret_cast<const float4 *>(gout + k * g.C + 4 * q);
+                        v[4 * q] = t.x;
+                        v[4 * q + 1] = t.y;
+                        v[4 * q + 2] = t.z;
+                        v[4 * q + 3] = t.w;
+                    }
+            } else {
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch)
+                    if (ch < g.C) v[ch] = gout[k * g.C + ch];
+            }
         }
         scatter_wave<NC>(g, valid, cl, v, g.C);
     }
 }
+
+// rows of C floats can move as float4: C % 4 == 0 and the array 16-byte aligned
+inline int vec_rows(const float *p, int C) { return (C & 3) == 0 && ((uintptr_t)p & 15) == 0 ? 1 : 0; }
 
 template <int NC>
 void launch_scatter(const DevGrid &dg, int64_t S, const float *xyz, const float *gout, hipStream_t st) {
@@ -146,10 +171,10 @@ void launch_scatter(const DevGrid &dg, int64_t S, const float *xyz, const float 
     if (blocks > 256 * 16) blocks = 256 * 16;
     if (dg.warp)
         hipLaunchKernelGGL((scatter_kernel<NC, true>), dim3((unsigned)blocks), dim3(kBlock),
-                           scatter_lds_bytes(NC, kBlock), st, dg, S, xyz, gout);
+                           scatter_lds_bytes(NC, kBlock), st, dg, S, xyz, gout, vec_rows(gout, dg.C));
     else
         hipLaunchKernelGGL((scatter_kernel<NC, false>), dim3((unsigned)blocks), dim3(kBlock),
-                           scatter_lds_bytes(NC, kBlock), st, dg, S, xyz, gout);
+                           scatter_lds_bytes(NC, kBlock), st, dg, S, xyz, gout, vec_rows(gout, dg.C));
 }
 
 template <bool W>
@@ -307,10 +332,10 @@ extern "C" int dvgo_grid_gather(const dvgo_grid *g, int64_t n_samples, const flo
         return set_error(DVGO_ERR_SHAPE, "grid data must be 16-byte aligned when ch_stride is a multiple of 4");
     if (dg.warp)
         hipLaunchKernelGGL(gather_kernel<true>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream,
-                           dg, n_samples, xyz, out);
+                           dg, n_samples, xyz, out, vec_rows(out, dg.C));
     else
         hipLaunchKernelGGL(gather_kernel<false>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream,
-                           dg, n_samples, xyz, out);
+                           dg, n_samples, xyz, out, vec_rows(out, dg.C));
     return check_hip(hipGetLastError(), "gather_kernel launch");
 }
 
