@@ -137,8 +137,8 @@ typedef struct dvgo_render_params {
  * prepared: 0 = every call first writes its preparation into the workspace (the weights as
  * scaled FP16 planes, the view encodings of the rays, the first ray of every 32-sample tile).
  * Nonzero = the workspace already holds that preparation and the call skips it: allowed only
- * when the last call on this workspace was a dvgo_mlp_forward / dvgo_mlp_backward /
- * dvgo_mlp_backward_scatter with the same weights (unchanged since), precision, n_rays,
+ * when the last call on this workspace was a dvgo_mlp_prepare / dvgo_mlp_forward /
+ * dvgo_mlp_backward / dvgo_mlp_backward_scatter with the same weights (unchanged since), n_rays,
  * ray_offsets, dirs and n_samples, e.g. the backward that follows the forward of one step.
  * The library cannot check this; a stale workspace gives wrong results, not an error. */
 enum { DVGO_MLP_SPLIT_F16 = 0, DVGO_MLP_F16 = 1 };
@@ -285,6 +285,14 @@ int dvgo_alpha(const dvgo_grid *density, int64_t n_samples, const float *xyz, co
 /* Workspace for the colour MLP (split weight image, per-ray direction encodings, tile
  * start rays and per-block weight-gradient partials). */
 int dvgo_mlp_workspace_size(const dvgo_color_mlp *m, int32_t n_rays, int64_t n_samples, size_t *bytes);
+
+/* The preparation every colour-MLP call starts with, alone: writes into ws the weights as scaled
+ * FP16 planes, the view encodings of the rays and the first ray of each 32-sample tile, so that
+ * following calls on ws with the same weights and batch can set m->prepared (e.g. on another
+ * stream, ahead of the feature gather).  Same arguments and workspace as dvgo_mlp_forward, minus
+ * the features; m->prepared is ignored. */
+int dvgo_mlp_prepare(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
+                     int64_t n_samples, void *ws, size_t ws_bytes, void *stream);
 
 /* Colour MLP forward: rgb [S,3] from feat [S, in_feat] and the direction dirs [R,3] of each
  * sample's ray.  Products run on FP16 matrix cores with every operand split into two FP16

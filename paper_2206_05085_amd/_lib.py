@@ -94,6 +94,7 @@ SIGNATURES = {
     "dvgo_tv_add_grad": (C.c_int, [_PG, _F, _F, _I32, VP]),
     "dvgo_alpha": (C.c_int, [_PG, _I64, VP, VP, _F, VP, VP]),
     "dvgo_mlp_workspace_size": (C.c_int, [_PM, _I32, _I64, _SZP]),
+    "dvgo_mlp_prepare": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, C.c_size_t, VP]),
     "dvgo_mlp_forward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward_scatter": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, _PG, VP, VP, C.c_size_t, VP]),

@@ -1410,12 +1410,13 @@ size_t ws_layout(const dvgo_color_mlp *m, int32_t R, int64_t S, size_t *off_pe, 
 }
 
 int setup(const dvgo_color_mlp *m, int32_t R, const int32_t *offs, const float *dirs, int64_t S, const float *feat,
-          void *ws, size_t ws_bytes, bool bwd, MlpArgs &a) {
+          void *ws, size_t ws_bytes, bool bwd, MlpArgs &a, bool need_feat = true) {
     int rc = check_mlp(m, bwd);
     if (rc) return rc;
     if (R < 0 || S < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays or n_samples");
     if (S >= ((int64_t)1 << 31) / 16) return set_error(DVGO_ERR_RANGE, "n_samples too large");
-    if (S > 0 && (R == 0 || !offs || !dirs || !feat)) return set_error(DVGO_ERR_NULL, "ray_offsets, dirs or feat is NULL");
+    if (S > 0 && (R == 0 || !offs || !dirs || (need_feat && !feat)))
+        return set_error(DVGO_ERR_NULL, "ray_offsets, dirs or feat is NULL");
     size_t off_pe, off_tr, off_part;
     const size_t need = ws_layout(m, R, S, &off_pe, &off_tr, &off_part);
     if (!ws || ws_bytes < need) return set_error(DVGO_ERR_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, need);
@@ -1459,6 +1460,15 @@ extern "C" int dvgo_mlp_workspace_size(const dvgo_color_mlp *m, int32_t n_rays, 
     size_t a, b, c;
     *bytes = ws_layout(m, n_rays, n_samples, &a, &b, &c);
     return DVGO_OK;
+}
+
+extern "C" int dvgo_mlp_prepare(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
+                                const float *dirs, int64_t n_samples, void *ws, size_t ws_bytes, void *stream) {
+    MlpArgs a;
+    int rc = setup(m, n_rays, ray_offsets, dirs, n_samples, nullptr, ws, ws_bytes, false, a, false);
+    if (rc) return rc;
+    if (n_samples == 0) return DVGO_OK;
+    return launch_prep(a, (hipStream_t)stream);
 }
 
 extern "C" int dvgo_mlp_forward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,

@@ -415,17 +415,32 @@ def _mlp_ws(mlp, R, S, ws, dev):
     return ws
 
 
-def mlp_forward(mlp: MLPParams, ray_offsets, dirs, feat, rgb=None, ws=None):
+def mlp_prepare(mlp: MLPParams, ray_offsets, dirs, n_samples, ws):
+    """Write the colour MLP's preparation for this batch into ws (then pass prepared=True)."""
+    import ctypes
+    R = ray_offsets.numel() - 1
+    _chk(ray_offsets, "ray_offsets", torch.int32)
+    _chk(dirs, "dirs", numel=3 * R)
+    call("dvgo_mlp_prepare", ctypes.byref(mlp.struct()), R, _p(ray_offsets), _p(dirs), int(n_samples), _p(ws),
+         ws.numel(), _stream())
+    return ws
+
+
+def mlp_forward(mlp: MLPParams, ray_offsets, dirs, feat, rgb=None, ws=None, prepared=False):
+    """prepared=True: ws already holds this batch's preparation (mlp_prepare or a preceding
+    MLP call with the same weights and batch)."""
     import ctypes
     R = ray_offsets.numel() - 1
     S = feat.shape[0]
     _chk(ray_offsets, "ray_offsets", torch.int32)
     _chk(dirs, "dirs", numel=3 * R)
     _chk(feat, "feat", numel=S * mlp.in_feat)
+    if prepared and ws is None:
+        raise ValueError("prepared=True needs the workspace of the preceding call")
     if rgb is None:
         rgb = torch.empty(S, 3, device=feat.device)
     ws = _mlp_ws(mlp, R, S, ws, feat.device)
-    m = mlp.struct()
+    m = mlp.struct(prepared=prepared)
     call("dvgo_mlp_forward", ctypes.byref(m), R, _p(ray_offsets), _p(dirs), S, _p(feat), _p(rgb), _p(ws),
          ws.numel(), _stream())
     return rgb

@@ -147,10 +147,11 @@ class TrainStep:
         return self.schedule, ms
 
     # --------------------------------------------------------------- stages
-    def forward(self, gathered=False, loss_value=True):
+    def forward(self, gathered=False, loss_value=True, prepared=False):
         """gathered: the features of the samples are already in feat_s.  loss_value=False:
         the loss head writes only the gradients the backward needs (the caller reduces the
-        loss value later, off the backward's path)."""
+        loss value later, off the backward's path).  prepared: the colour MLP's preparation
+        for this step is already in its workspace."""
         b = self.batch
         if self.grid_mode:
             ops.render_forward(b, self.grid("density"), self.grid("color"), None, act_shift_=self.shift,
@@ -159,7 +160,8 @@ class TrainStep:
         else:
             if not gathered:
                 ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
-            ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws)
+            ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws,
+                            prepared=prepared)
             ops.render_forward(b, self.grid("density"), None, self.rgb_s, act_shift_=self.shift, halt_T=self.halt_T,
                                bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist), state=self.state,
                                schedule=self.schedule)
@@ -226,9 +228,10 @@ class TrainStep:
             self.optimise()
             return self.loss
         # Two streams.  main: feature gather, colour head, render forward and backward, colour-head
-        # backward, feature scatter, feature Adam.  side: the binning (needs only the points) from
-        # the start, and after the colour-head backward the density scatter (+ TV), density Adam,
-        # MLP Adam and the loss value beside the feature scatter.  The colour-head backward takes
+        # backward, feature scatter, feature Adam.  side: the Adam step counter, the colour head's
+        # preparation and the binning (need only the batch) from the start, and after the
+        # colour-head backward the density scatter (+ TV), density Adam, MLP Adam and the loss
+        # value beside the feature scatter.  The colour-head backward takes
         # nearly all of a CU's LDS and registers, so nothing is meant to run beside it.  Main
         # hands work to the side once (each hand-over delays main's next kernel in a graph).  Each
         # buffer has one writer at a time; the side joins main at the end.
@@ -237,12 +240,16 @@ class TrainStep:
             self.side = torch.cuda.Stream(device=self.device)
         side = self.side
         b = self.batch
-        side.wait_stream(main)
+        side.wait_stream(main)  # the side's first kernels depend on nothing of this step
+        ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
         with torch.cuda.stream(side):
+            ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+            ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
+            prepared = torch.cuda.Event()
+            prepared.record(side)
             ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
-        ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
-        ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
-        self.forward(gathered=True, loss_value=False)
+        main.wait_event(prepared)  # the colour head's preparation and the step counter
+        self.forward(gathered=True, loss_value=False, prepared=True)
         ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
                             None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
                             schedule=self.schedule, grad_sample_density=self.g_raw)

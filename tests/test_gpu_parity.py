@@ -393,7 +393,10 @@ def _mlp_case(dv, S_lengths, seed, bias_std=0.3, half=False):
     gb = [torch.zeros_like(v) for v in b]
     P = dv.MLPParams(W, b, gW, gb, precision=dv.MLP_F16 if half else dv.MLP_SPLIT_F16)
     ws = torch.empty(dv.mlp_workspace_size(P, R, S), dtype=torch.uint8, device="cuda")
-    rgb = dv.mlp_forward(P, T(offs, torch.int32), T(dirs), T(feat), ws=ws)
+    # the preparation alone, then a forward that reuses it, equals a forward that prepares itself
+    dv.mlp_prepare(P, T(offs, torch.int32), T(dirs), S, ws)
+    rgb = dv.mlp_forward(P, T(offs, torch.int32), T(dirs), T(feat), ws=ws, prepared=True)
+    assert torch.equal(rgb, dv.mlp_forward(P, T(offs, torch.int32), T(dirs), T(feat)))
     # the backward that reuses the forward's preparation (as the training step does) and one
     # that prepares again on a fresh workspace take identical results
     gf = dv.mlp_backward(P, T(offs, torch.int32), T(dirs), T(feat), T(grgb), ws=ws, prepared=True)
