@@ -302,6 +302,18 @@ int dvgo_mlp_prepare(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray
 int dvgo_mlp_forward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
                      int64_t n_samples, const float *feat, float *rgb, void *ws, size_t ws_bytes, void *stream);
 
+/* dvgo_mlp_forward with the feature gather fused in: the features of sample k are the
+ * trilinear lookup of feat_grid at xyz[k] (section 3's interpolation; the grid's warp applied),
+ * computed inside the kernel with the same operations as dvgo_grid_gather, so they equal its
+ * output bit for bit, and written to feat_out [S, in_feat] when feat_out is not NULL (the input
+ * dvgo_mlp_backward recomputes from).  Needs feat_grid->channels == in_feat, in_feat and
+ * ch_stride multiples of 4, and feat_grid->data and feat_out 16-byte aligned
+ * (DVGO_ERR_UNSUPPORTED otherwise).  Same workspace, preparation and rgb output as
+ * dvgo_mlp_forward. */
+int dvgo_mlp_forward_gather(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
+                            int64_t n_samples, const dvgo_grid *feat_grid, const float *xyz, float *feat_out,
+                            float *rgb, void *ws, size_t ws_bytes, void *stream);
+
 /* Colour MLP backward (recomputes the forward, same split-FP16 arithmetic): grad_feat
  * [S, in_feat] written; weight and bias gradients accumulated into m->g*.  A hidden unit whose
  * pre-activation lies within rounding of its ReLU kink may take either side, as in any

@@ -96,6 +96,7 @@ SIGNATURES = {
     "dvgo_mlp_workspace_size": (C.c_int, [_PM, _I32, _I64, _SZP]),
     "dvgo_mlp_prepare": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, C.c_size_t, VP]),
     "dvgo_mlp_forward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, C.c_size_t, VP]),
+    "dvgo_mlp_forward_gather": (C.c_int, [_PM, _I32, VP, VP, _I64, _PG, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward_scatter": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, _PG, VP, VP, C.c_size_t, VP]),
     "dvgo_loss_head": (C.c_int, [_I32, VP, VP, VP, _F, VP, VP, VP, VP]),

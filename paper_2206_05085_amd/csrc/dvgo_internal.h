@@ -294,6 +294,21 @@ __device__ __forceinline__ int corner_off(const DevGrid &g, int c) {
     return ((c >> 2) & 1) * g.sx + ((c >> 1) & 1) * g.sy + (c & 1) * g.cs;
 }
 
+// Channels c0..c0+3 of a trilinear lookup (rows 16-byte aligned, c0 % 4 == 0): corners in the
+// order 0..7, one FMA each, so every kernel that interpolates this way gets the same bits.
+__device__ __forceinline__ float4 interp4(const DevGrid &g, const Tri &t, int c0) {
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const float4 v = *reinterpret_cast<const float4 *>(g.data + t.base + corner_off(g, c) + c0);
+        acc.x = __builtin_fmaf(t.w[c], v.x, acc.x);
+        acc.y = __builtin_fmaf(t.w[c], v.y, acc.y);
+        acc.z = __builtin_fmaf(t.w[c], v.z, acc.z);
+        acc.w = __builtin_fmaf(t.w[c], v.w, acc.w);
+    }
+    return acc;
+}
+
 __device__ __forceinline__ float interp_ch(const DevGrid &g, const Tri &t, int ch) {
     float acc = 0.f;
 #pragma unroll

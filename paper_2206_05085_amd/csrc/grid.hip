@@ -87,17 +87,13 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(DevGrid g, int64_t S, co
         for (int ch = 0; ch < 16; ++ch) acc[ch] = 0.f;
         if ((g.cs & 3) == 0) {
 #pragma unroll
-            for (int c = 0; c < 8; ++c) {
-                const float4 *p = reinterpret_cast<const float4 *>(g.data + t.base + corner_off(g, c));
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (4 * q < g.C) {
-                        const float4 v = p[q];
-                        acc[4 * q] += t.w[c] * v.x;
-                        acc[4 * q + 1] += t.w[c] * v.y;
-                        acc[4 * q + 2] += t.w[c] * v.z;
-                        acc[4 * q + 3] += t.w[c] * v.w;
-                    }
+            for (int q = 0; q < 4; ++q) {
+                if (4 * q < g.C) {
+                    const float4 v = interp4(g, t, 4 * q);
+                    acc[4 * q] = v.x;
+                    acc[4 * q + 1] = v.y;
+                    acc[4 * q + 2] = v.z;
+                    acc[4 * q + 3] = v.w;
                 }
             }
         } else {

@@ -165,9 +165,11 @@ struct MlpArgs {
     int n_params;
     float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
     int nblocks;
-    // fused feature scatter: the feature grid (its grad receives +=) and the sample points
+    // fused feature gather / scatter: the feature grid (read in the forward; its grad receives
+    // += in the fused backward) and the sample points
     DevGrid fg;
     const float *xyz;
+    float *feat_out;  // forward with the gather: the features it used, [S][in_feat] (may be NULL)
 };
 
 // padded input column k -> column of W1 (or -1 for padding)
@@ -383,14 +385,28 @@ __device__ __forceinline__ float4 feat4(const MlpArgs &a, int s, int c0) {
                        c0 + 2 < a.in_feat ? fp[c0 + 2] : 0.f, c0 + 3 < a.in_feat ? fp[c0 + 3] : 0.f);
 }
 
+// Features 4q..4q+3 of sample s looked up in the feature grid (GM = 1 plain, 2 through its warp)
+// and, when asked, written out for the backward.  Needs in_feat % 4 == 0 (checked on the host).
+template <int GM>
+__device__ __forceinline__ float4 gathered4(const MlpArgs &a, int s, int q) {
+    if (4 * q >= a.in_feat) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const float *p = a.xyz + 3 * (int64_t)s;
+    const Tri t = trilinear<GM == 2>(a.fg, p[0], p[1], p[2]);
+    const float4 f = interp4(a.fg, t, 4 * q);
+    if (a.feat_out) *reinterpret_cast<float4 *>(a.feat_out + (int64_t)s * a.in_feat + 4 * q) = f;
+    return f;
+}
+
 // The 8 inputs of operand slot group (kk, q) of a valid sample s on ray `ray`: logical
 // columns k(kk, q, 0..7).  For kk = 0 these are features 4q..4q+3 (view encoding 0..3 when
 // q = 3) and view encoding 4+4q..7+4q; for kk = 1 view encoding 20+4q..23+4q and padding.
+// GM = 0: features from a.feat; 1, 2: looked up in the feature grid (gathered4).
+template <int GM = 0>
 __device__ __forceinline__ void load_x8(const MlpArgs &a, int s, int ray, int kk, int q, float v[8]) {
     const float *pe = a.pe + (int64_t)ray * PEW;
     float4 lo, hi;
     if (kk == 0) {
-        lo = q < 3 ? feat4(a, s, 4 * q) : *reinterpret_cast<const float4 *>(pe);
+        lo = q < 3 ? (GM ? gathered4<GM>(a, s, q) : feat4(a, s, 4 * q)) : *reinterpret_cast<const float4 *>(pe);
         hi = *reinterpret_cast<const float4 *>(pe + 4 + 4 * q);
     } else {
         lo = *reinterpret_cast<const float4 *>(pe + 20 + 4 * q);
@@ -412,7 +428,7 @@ constexpr int FWD_NC = 2;                 // 16-sample column tiles per wave til
 constexpr int FWD_WTILE = 16 * FWD_NC;    // samples per wave tile
 static_assert(FWD_WTILE == TILE, "forward wave tiles are the 32-sample tiles of tile_ray");
 
-template <bool SPLIT>
+template <bool SPLIT, int GM>
 __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char sm[IMG_FWD_END];
     copy_to_lds(sm, a.img, IMG_FWD_END);
@@ -444,7 +460,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
             float xv[2][8], m = 0.f;
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
-                if (sv[c]) load_x8(a, s[c], ray, kk, q, xv[kk]);
+                if (sv[c]) load_x8<GM>(a, s[c], ray, kk, q, xv[kk]);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     if (!sv[c]) xv[kk][e] = 0.f;
@@ -464,6 +480,8 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
                 xh[c][kk] = cat(h0, h1);
                 xl[c][kk] = cat(l0, l1);
             }
+            // with the gather, one column tile's 8 corner rows in flight at a time (registers)
+            if (GM) __builtin_amdgcn_sched_barrier(0);
         }
         // layer 1: h1 = relu(W1 x + b1), kept as the split B operand of layer 2
         h4 hh[FWD_NC][8], hl[FWD_NC][8];
@@ -1443,6 +1461,18 @@ int setup(const dvgo_color_mlp *m, int32_t R, const int32_t *offs, const float *
     return DVGO_OK;
 }
 
+template <int GM>
+int launch_fwd(const MlpArgs &a, const dvgo_color_mlp *m, hipStream_t st) {
+    const int64_t nwt = (a.S + FWD_WTILE - 1) / FWD_WTILE;
+    const int64_t nb = (nwt + FWD_WAVES - 1) / FWD_WAVES;
+    const dim3 grid((int)(nb < MAX_BLOCKS ? nb : MAX_BLOCKS));
+    if (m->precision == DVGO_MLP_F16)
+        hipLaunchKernelGGL((mlp_fwd_kernel<false, GM>), grid, dim3(FWD_THREADS), 0, st, a);
+    else
+        hipLaunchKernelGGL((mlp_fwd_kernel<true, GM>), grid, dim3(FWD_THREADS), 0, st, a);
+    return check_hip(hipGetLastError(), "mlp_fwd_kernel launch");
+}
+
 int launch_prep(const MlpArgs &a, hipStream_t st) {
     const int n = PREP_FIXED_BLOCKS + (a.n_rays + PREP_THREADS - 1) / PREP_THREADS +
                   (a.n_tiles + PREP_THREADS - 1) / PREP_THREADS;
@@ -1485,12 +1515,36 @@ extern "C" int dvgo_mlp_forward(const dvgo_color_mlp *m, int32_t n_rays, const i
         rc = launch_prep(a, st);
         if (rc) return rc;
     }
-    const int64_t nwt = (n_samples + FWD_WTILE - 1) / FWD_WTILE;
-    const int64_t nb = (nwt + FWD_WAVES - 1) / FWD_WAVES;
-    const dim3 grid((int)(nb < MAX_BLOCKS ? nb : MAX_BLOCKS));
-    if (m->precision == DVGO_MLP_F16) hipLaunchKernelGGL(mlp_fwd_kernel<false>, grid, dim3(FWD_THREADS), 0, st, a);
-    else hipLaunchKernelGGL(mlp_fwd_kernel<true>, grid, dim3(FWD_THREADS), 0, st, a);
-    return check_hip(hipGetLastError(), "mlp_fwd_kernel launch");
+    return launch_fwd<0>(a, m, st);
+}
+
+extern "C" int dvgo_mlp_forward_gather(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
+                                       const float *dirs, int64_t n_samples, const dvgo_grid *feat_grid,
+                                       const float *xyz, float *feat_out, float *rgb, void *ws, size_t ws_bytes,
+                                       void *stream) {
+    MlpArgs a;
+    int rc = setup(m, n_rays, ray_offsets, dirs, n_samples, nullptr, ws, ws_bytes, false, a, false);
+    if (rc) return rc;
+    rc = make_dev_grid(feat_grid, "feature grid", &a.fg, false);
+    if (rc) return rc;
+    if (feat_grid->channels != m->in_feat)
+        return set_error(DVGO_ERR_SHAPE, "feature grid channels (%d) != in_feat (%d)", feat_grid->channels, m->in_feat);
+    if ((m->in_feat & 3) || (feat_grid->ch_stride & 3) || ((uintptr_t)feat_grid->data & 15) ||
+        ((uintptr_t)feat_out & 15))
+        return set_error(DVGO_ERR_UNSUPPORTED,
+                         "the fused gather needs in_feat and ch_stride multiples of 4 and 16-byte aligned data and "
+                         "feat_out");
+    if (n_samples == 0) return DVGO_OK;
+    if (!rgb || !xyz) return set_error(DVGO_ERR_NULL, "rgb or xyz is NULL");
+    a.rgb = rgb;
+    a.xyz = xyz;
+    a.feat_out = feat_out;
+    hipStream_t st = (hipStream_t)stream;
+    if (!m->prepared) {
+        rc = launch_prep(a, st);
+        if (rc) return rc;
+    }
+    return a.fg.warp ? launch_fwd<2>(a, m, st) : launch_fwd<1>(a, m, st);
 }
 
 extern "C" int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,

@@ -446,6 +446,28 @@ def mlp_forward(mlp: MLPParams, ray_offsets, dirs, feat, rgb=None, ws=None, prep
     return rgb
 
 
+def mlp_forward_gather(mlp: MLPParams, ray_offsets, dirs, feat_grid: DeviceGrid, xyz, feat_out=None, rgb=None,
+                       ws=None, prepared=False):
+    """Colour MLP forward whose features are looked up in feat_grid at xyz inside the kernel (the
+    same values grid_gather gives, bit for bit); feat_out [S, in_feat] (optional) receives them."""
+    import ctypes
+    R = ray_offsets.numel() - 1
+    S = xyz.shape[0]
+    _chk(ray_offsets, "ray_offsets", torch.int32)
+    _chk(dirs, "dirs", numel=3 * R)
+    _chk(xyz, "xyz", numel=3 * S)
+    if feat_out is not None:
+        _chk(feat_out, "feat_out", numel=S * mlp.in_feat)
+    if prepared and ws is None:
+        raise ValueError("prepared=True needs the workspace of the preceding call")
+    if rgb is None:
+        rgb = torch.empty(S, 3, device=xyz.device)
+    ws = _mlp_ws(mlp, R, S, ws, xyz.device)
+    call("dvgo_mlp_forward_gather", ctypes.byref(mlp.struct(prepared=prepared)), R, _p(ray_offsets), _p(dirs), S,
+         ctypes.byref(feat_grid.struct()), _p(xyz), _p(feat_out), _p(rgb), _p(ws), ws.numel(), _stream())
+    return rgb
+
+
 def mlp_backward(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, grad_feat=None, ws=None, prepared=False):
     """prepared=True reuses the preparation a preceding mlp_forward on the same ws wrote
     (same weights and batch); it needs an explicit ws."""

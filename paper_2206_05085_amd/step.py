@@ -1,7 +1,7 @@
 """The per-ray training step on one GPU: every stage is a libdvgo kernel.
 
 Feature-grid mode (hybrid colour, Table 1):
-    grid_gather(features) -> mlp_forward -> render_forward (density gather, alpha,
+    grid_gather(features) -> mlp_forward (or both in mlp_forward_gather) -> render_forward (density gather, alpha,
     compositing, distortion) -> loss_head -> render_backward (density grad +=, d rgb)
     -> mlp_backward (d features, MLP grads +=) -> grid_scatter (feature grad +=)
     -> grid_adam_step x 3 (density, features, MLP) with zero-gradient skipping on the grids.
@@ -14,6 +14,7 @@ from __future__ import annotations
 
 from typing import Optional
 
+import numpy as np
 import torch
 
 from . import ops
@@ -23,7 +24,7 @@ class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
                  tv=None, warp=None, mlp_precision=0, binned_scatter=True, concurrent=True, fused_scatter=False,
-                 device="cuda"):
+                 fused_gather=True, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
         tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
@@ -38,7 +39,10 @@ class TrainStep:
         the colour head's backward and the feature scatter (stream-ordered, graph-capturable).
         fused_scatter: scatter the feature gradient inside the colour head's backward kernel
         (unwarped feature grids) instead of writing it and scattering it afterwards; saves the
-        per-sample feature-gradient buffer, but measured slower on the config-2 step (off)."""
+        per-sample feature-gradient buffer, but measured slower on the config-2 step (off).
+        fused_gather: look the features up inside the colour head's forward kernel (which also
+        writes them for the backward) instead of a separate gather kernel (feature rows whose
+        channel count is a multiple of 4)."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -53,6 +57,7 @@ class TrainStep:
         self.side = None
         self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
         self.fused = bool(fused_scatter) and self.warp[0] == 0
+        self.fused_gather = bool(fused_gather) and feat is not None and np.shape(feat)[-1] % 4 == 0
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
         self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
         self.density = self._param(dev(density))
@@ -158,10 +163,14 @@ class TrainStep:
                                halt_T=self.halt_T, bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist),
                                state=self.state, schedule=self.schedule)
         else:
-            if not gathered:
-                ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
-            ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws,
-                            prepared=prepared)
+            if self.fused_gather and not gathered:
+                ops.mlp_forward_gather(self.mlp, b.ray_offsets, self.dirs, self.grid("feat"), b.xyz,
+                                       feat_out=self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws, prepared=prepared)
+            else:
+                if not gathered:
+                    ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
+                ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws,
+                                prepared=prepared)
             ops.render_forward(b, self.grid("density"), None, self.rgb_s, act_shift_=self.shift, halt_T=self.halt_T,
                                bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist), state=self.state,
                                schedule=self.schedule)
@@ -241,15 +250,28 @@ class TrainStep:
         side = self.side
         b = self.batch
         side.wait_stream(main)  # the side's first kernels depend on nothing of this step
-        ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
-        with torch.cuda.stream(side):
+        binned = torch.cuda.Event()
+        if self.fused_gather:
+            # the gather runs inside the colour head's forward; its preparation leads on main
             ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
-            ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
-            prepared = torch.cuda.Event()
-            prepared.record(side)
-            ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
-        main.wait_event(prepared)  # the colour head's preparation and the step counter
-        self.forward(gathered=True, loss_value=False, prepared=True)
+            with torch.cuda.stream(side):
+                ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
+                binned.record(side)
+            self.forward(loss_value=False)
+        else:
+            ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
+            with torch.cuda.stream(side):
+                ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+                ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
+                prepared = torch.cuda.Event()
+                prepared.record(side)
+                ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
+                binned.record(side)
+            main.wait_event(prepared)  # the colour head's preparation and the step counter
+            self.forward(gathered=True, loss_value=False, prepared=True)
+        # An edge from the binning into main (long satisfied by now): without one, a graph replay
+        # may launch the binning only behind main's last kernels, and the density work with it.
+        main.wait_event(binned)
         ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
                             None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
                             schedule=self.schedule, grad_sample_density=self.g_raw)

@@ -547,3 +547,46 @@ def test_loss_head(dv):
     _, gr3, gd3 = dv.loss_head(T(rgb), T(tgt), None, 0.01, want_loss=False)
     torch.cuda.synchronize()
     assert gd3 is None and torch.equal(gr3, gr)
+
+
+@pytest.mark.parametrize("case", ["plain", "warped", "f16", "no_feat_out"])
+def test_mlp_forward_gather_equals_gather_then_forward(dv, case):
+    # the colour head's forward with the feature lookup inside the kernel equals the feature gather
+    # followed by the forward, bit for bit (same interpolation operations, same inputs)
+    rng = np.random.default_rng(40)
+    wl = synth.config3(R=64, n=48) if case == "warped" else synth.config2(R=300, n=40)
+    smp = wl.samples
+    mlp = synth.mlp_weights(rng, bias_std=0.3)
+    R, S = smp.n_rays, smp.n_samples
+    say("mlp forward with fused gather,", case, "S =", S)
+    W = [T(w) for w in mlp.W]
+    b = [T(v) for v in mlp.b]
+    P = dv.MLPParams(W, b, None, None, precision=dv.MLP_F16 if case == "f16" else dv.MLP_SPLIT_F16)
+    fg = dgrid(dv, wl.feat)
+    offs, dirs, xyz = T(smp.ray_offsets, torch.int32), T(wl.rays.dirs), T(smp.xyz)
+    feat = dv.grid_gather(fg, xyz)
+    want = dv.mlp_forward(P, offs, dirs, feat)
+    fo = None if case == "no_feat_out" else torch.full((S, 12), 7.0, device="cuda")
+    got = dv.mlp_forward_gather(P, offs, dirs, fg, xyz, feat_out=fo)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
+    if fo is not None:
+        assert torch.equal(fo, feat)
+    # and against the oracle
+    ref = oracle.mlp_forward(mlp, smp.ray_offsets, wl.rays.dirs, oracle.gather(wl.feat, smp.xyz).astype(np.float64),
+                             half=case == "f16")
+    if case != "f16":
+        close(got.cpu().numpy(), ref, **FWD, name="fused-gather rgb")
+
+
+def test_mlp_forward_gather_rejects_unsupported(dv):
+    rng = np.random.default_rng(41)
+    mlp = synth.mlp_weights(rng, bias_std=0.3)
+    P = dv.MLPParams([T(w) for w in mlp.W], [T(v) for v in mlp.b], None, None)
+    data = T(rng.standard_normal((5, 5, 5, 12)))
+    fg = dv.DeviceGrid(data[..., :12], np.float32([-1] * 3), np.float32([1] * 3))
+    offs, dirs, xyz = T(np.int32([0, 3]), torch.int32), T(np.float32([[0, 0, 1]])), T(np.zeros((3, 3), np.float32))
+    say("fused gather: feat_out not 16-byte aligned")
+    bad = torch.empty(3 * 12 + 1, device="cuda")[1:].view(3, 12)
+    with pytest.raises(RuntimeError, match="16-byte aligned"):
+        dv.mlp_forward_gather(P, offs, dirs, fg, xyz, feat_out=bad)
