@@ -571,8 +571,12 @@ def main():
     # ---- per-stage times (eager, events on the launching stream)
     print("[bench] stage timing", file=sys.stderr, flush=True)
     stages = {
+        # the step's forward: feature lookup inside the colour head (the separate gather and
+        # forward are timed too, for comparison; the step does not run them)
         "gather": lambda: ops.grid_gather(st.grid("feat"), batch.xyz, out=st.feat_s),
         "mlp_fwd": lambda: ops.mlp_forward(st.mlp, batch.ray_offsets, st.dirs, st.feat_s, rgb=st.rgb_s, ws=st.mlp_ws),
+        "mlp_fwd_gather": lambda: ops.mlp_forward_gather(st.mlp, batch.ray_offsets, st.dirs, st.grid("feat"), batch.xyz,
+                                                         feat_out=st.feat_s, rgb=st.rgb_s, ws=st.mlp_ws),
         "render_fwd": lambda: ops.render_forward(batch, st.grid("density"), None, st.rgb_s, act_shift_=st.shift,
                                                  out=(st.rgb, st.T, st.dist), state=st.state),
         "loss": lambda: ops.loss_head(st.rgb, st.target, st.dist, st.lam, loss=st.loss, grad_rgb=st.g_rgb,
