@@ -214,7 +214,10 @@ __device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, f
 // nothing is written; within a partly non-zero group the zero-gradient lanes keep their
 // values bit for bit.  Each thread takes ADAM_U groups a stride apart per pass and issues
 // all their gradient loads, then all parameter / moment loads, before it computes, so a
-// wave keeps several independent loads in flight instead of one dependent chain.
+// wave keeps several independent loads in flight instead of one dependent chain.  The skip
+// is decided per 128-byte line (the 8 lanes holding 8 consecutive groups): a line with any
+// non-zero gradient is read and written whole, its zero-gradient elements written back
+// unchanged, so the memory sees full-line writes instead of masked partial ones.
 constexpr int ADAM_U = 4;
 
 __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, int64_t n4) {
@@ -235,7 +238,10 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, 
         for (int u = 0; u < ADAM_U; ++u) {
             const int64_t i = i0 + u * stride;
             const bool any = g[u].x != 0.f || g[u].y != 0.f || g[u].z != 0.f || g[u].w != 0.f;
-            live[u] = i < n4 && (!a.skip || any);
+            // any non-zero gradient among the 8 lanes of this lane's line (groups i & ~7 .. i | 7)
+            const unsigned long long b = __ballot(any);
+            const bool line = ((b >> (lane() & ~7)) & 0xFFull) != 0;
+            live[u] = i < n4 && (!a.skip || line);
             if (live[u]) {
                 p[u] = P[i];
                 m[u] = M[i];

@@ -495,16 +495,27 @@ def test_mlp_f16_multi_block(dv):
 # ---------------------------------------------------------------------- Adam
 
 
-def test_adam(dv):
+@pytest.mark.parametrize("pattern", ["scattered", "runs"])
+def test_adam(dv, pattern):
     rng = np.random.default_rng(30)
     n = 100003
     p, m = rng.standard_normal(n).astype(np.float32), (0.1 * rng.standard_normal(n)).astype(np.float32)
     v = rng.random(n).astype(np.float32) * 0.01
     g = rng.standard_normal(n).astype(np.float32)
-    g[rng.random(n) < 0.4] = 0.0
+    if pattern == "scattered":
+        g[rng.random(n) < 0.4] = 0.0
+    else:
+        # zero and non-zero runs of 1..100 elements: lines (32 floats) wholly zero, wholly
+        # non-zero and mixed, as the vertex rows a batch touches leave them
+        i, on = 0, True
+        while i < n:
+            k = int(rng.integers(1, 101))
+            if not on:
+                g[i:i + k] = 0.0
+            i, on = i + k, not on
     g[7] = -0.0
     tp, tg, tm, tv = T(p), T(g), T(m), T(v)
-    say("adam n =", n)
+    say("adam n =", n, pattern)
     dv.grid_adam_step(tp[1:], tg[1:], tm[1:], tv[1:], lr=0.05, beta1=0.9, beta2=0.99, eps=1e-8, step=3,
                       skip_zero_grad=True, zero_grad_after=True)
     torch.cuda.synchronize()
