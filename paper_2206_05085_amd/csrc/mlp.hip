@@ -480,8 +480,6 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
                 xh[c][kk] = cat(h0, h1);
                 xl[c][kk] = cat(l0, l1);
             }
-            // with the gather, one column tile's 8 corner rows in flight at a time (registers)
-            if (GM) __builtin_amdgcn_sched_barrier(0);
         }
         // layer 1: h1 = relu(W1 x + b1), kept as the split B operand of layer 2
         h4 hh[FWD_NC][8], hl[FWD_NC][8];
@@ -635,7 +633,9 @@ __device__ __forceinline__ h8 glb_h8(const unsigned char *img, int off, int idx)
 }
 
 // fp16(t - h) for h = fp16(t), in one mixed-precision FMA (t * 1 - h rounded once to fp16);
-// t - h is exact in fp32, so this equals (_Float16)(t - (float)h)
+// t - h is exact in fp32, so this equals (_Float16)(t - (float)h).  The instruction writes the
+// low half of its 32-bit destination only; the value is a 16-bit one (held in the low half, as
+// the compiler keeps every half-precision value) and is consumed only by 16-bit LDS stores.
 __device__ __forceinline__ _Float16 lo_part(float t, _Float16 h) {
     _Float16 r;
     asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(r) : "v"(t), "v"(h));
