@@ -186,6 +186,10 @@ __device__ __forceinline__ float corner_weight(const Cell &c, int dx, int dy, in
     return ((dx ? c.fx : 1.f - c.fx) * (dy ? c.fy : 1.f - c.fy)) * (dz ? c.fz : 1.f - c.fz);
 }
 
+// Orders the calling wave's LDS accesses (for the compiler and the hardware) without waiting
+// for its outstanding global stores and atomics, which stay in flight.
+__device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local"); }
+
 // Adjoint of trilinear interpolation for the 64 points held by the lanes of a wave, with
 // the contributions that land on the same vertex summed inside the wave before the atomic.
 //
@@ -268,12 +272,12 @@ __device__ __forceinline__ void scatter_wave(const DevGrid &g, bool valid, const
 #pragma unroll
             for (int ch = 0; ch < NC; ++ch) vals[rank * NC + ch] = acc[c][ch];
         }
-        __threadfence_block();
+        lds_fence();  // the slice is this wave's own: LDS order only, the atomics stay in flight
         for (int i = ln; i < nh * NC; i += 64) {
             const int e = i / NC, ch = i - e * NC;
             if (ch < nch) unsafeAtomicAdd(g.grad + keys[e] + ch, vals[i]);
         }
-        __threadfence_block();
+        lds_fence();
     }
 }
 
