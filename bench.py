@@ -567,6 +567,10 @@ def main():
     batch = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
     st.bind(batch, wl.rays.dirs, wl.target)
     torch.cuda.synchronize()
+    # render kernels' launch shape: longest rays first, waves per block and grid size picked by
+    # the library's autotuner on this batch (outside the timed region, like the capture)
+    st.tune()
+    torch.cuda.synchronize()
 
     # ---- per-stage times (eager, events on the launching stream)
     print("[bench] stage timing", file=sys.stderr, flush=True)
@@ -578,13 +582,13 @@ def main():
         "mlp_fwd_gather": lambda: ops.mlp_forward_gather(st.mlp, batch.ray_offsets, st.dirs, st.grid("feat"), batch.xyz,
                                                          feat_out=st.feat_s, rgb=st.rgb_s, ws=st.mlp_ws),
         "render_fwd": lambda: ops.render_forward(batch, st.grid("density"), None, st.rgb_s, act_shift_=st.shift,
-                                                 out=(st.rgb, st.T, st.dist), state=st.state),
+                                                 out=(st.rgb, st.T, st.dist), state=st.state, schedule=st.schedule),
         "loss": lambda: ops.loss_head(st.rgb, st.target, st.dist, st.lam, loss=st.loss, grad_rgb=st.g_rgb,
                                       grad_dist=st.g_dist),
         "bin": lambda: ops.bin_samples(st.grid("density"), batch.xyz, ws=st.bin_ws),
         "render_bwd": lambda: ops.render_backward(batch, st.grid("density"), None, st.rgb_s, st.T, st.state, st.g_rgb,
                                                   st.g_dist, None, act_shift_=st.shift, grad_sample_rgb=st.g_rgb_s,
-                                                  grad_sample_density=st.g_raw),
+                                                  grad_sample_density=st.g_raw, schedule=st.schedule),
         "scatter_density": lambda: ops.grid_scatter_binned(st.grid("density"), batch.xyz, st.g_raw, st.bin_ws),
         "mlp_bwd": lambda: ops.mlp_backward(st.mlp, batch.ray_offsets, st.dirs, st.feat_s, st.g_rgb_s,
                                             grad_feat=st.g_feat_s, ws=st.mlp_ws),
@@ -682,7 +686,9 @@ def main():
            "config": {"workload": f"fine-stage step: 160^3 density + 160^3x12 features, colour MLP 39-128-128-3, "
                                   f"{R} pinhole rays x 256 samples 20-100% live (S={S}), lambda_dist=0.01, "
                                   f"Adam on grids (skip zero grads) + MLP",
-                      "rays": R, "live_samples": S, "graph": use_graph, "parallelism": "single GPU"},
+                      "rays": R, "live_samples": S, "graph": use_graph, "parallelism": "single GPU",
+                      "render_schedule": {"order": "longest first", "waves_per_block": st.schedule.waves_per_block,
+                                          "grid_waves": st.schedule.grid_waves}},
            "roofline": roof, "roofline_render": roof_render,
            "stages_ms": {k: round(v, 4) for k, v in stage_ms.items()}, "loss": loss, "wall_s": round(wall, 3)}
     if not args.no_tv:

@@ -88,10 +88,12 @@ class TrainStep:
                               channels=3 if which == "color" else None, warp=self.warp[0], warp_b=self.warp[1])
 
     def bind(self, batch: ops.SampleBatch, dirs, target):
-        """Attach a sample batch (already on the GPU) and allocate every per-batch buffer."""
+        """Attach a sample batch (already on the GPU) and allocate every per-batch buffer.  A
+        schedule tuned for an earlier batch is dropped (its ray list belongs to that batch)."""
         R, S = batch.n_rays, batch.n_samples
         d = self.device
         self.batch = batch
+        self.schedule = None
         self.dirs = torch.as_tensor(dirs).to(d, torch.float32).contiguous()
         self.target = torch.as_tensor(target).to(d, torch.float32).contiguous()
         self.rgb, self.T, self.dist = (torch.empty(R, 3, device=d), torch.empty(R, device=d),

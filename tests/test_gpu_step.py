@@ -336,3 +336,38 @@ def test_config4_finite_differences(pkg):
     close(gp[:128], an[:128], **GRAD, name="GPU vs oracle, density")
     close(gp[128:], an[128:], **GRAD, name="GPU vs oracle, features")
     close(gp[smooth], fd[smooth], rtol=2e-4, floor=1e-2, name="GPU vs FD")
+
+
+def test_tuned_schedule_step_and_rebind(pkg):
+    # the step with the autotuned longest-first render schedule takes the same update as the
+    # default schedule; binding another batch drops the schedule (its ray list belongs to the
+    # batch it was tuned on), and the step then runs on the new batch
+    ops, _, step = pkg
+    wl = synth.config2(R=256, n=48)
+    say("tuned render schedule vs default, 48^3, 256 rays; rebind to 100 rays")
+    mk = lambda: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                                mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight)
+    smp = wl.samples
+    a, b = mk(), mk()
+    for st in (a, b):
+        st.bind(ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len),
+                wl.rays.dirs, wl.target)
+    sched, _ = b.tune()
+    assert sched.ray_list is not None and sched.ray_list.numel() == 256
+    for rep in range(2):
+        a.step()
+        b.step()
+        torch.cuda.synchronize()
+        close(b.loss.cpu().numpy(), a.loss.cpu().numpy(), rtol=1e-5, floor=1e-3, name=f"loss {rep}")
+        close(b.mlp_flat["p"].cpu().numpy(), a.mlp_flat["p"].cpu().numpy(), rtol=1e-5, floor=1e-3,
+              name=f"mlp tuned {rep}")
+        close_after_adam(b.density["p"].cpu().numpy(), a.density["p"].cpu().numpy(), 1 + rep, a.lr_grid,
+                         name=f"density tuned {rep}")
+    small = synth.config2(R=100, n=48)
+    s2 = small.samples
+    b.bind(ops.SampleBatch.from_arrays(s2.ray_offsets, s2.xyz, s2.delta, s2.s_mid, s2.s_len), small.rays.dirs,
+           small.target)
+    assert b.schedule is None
+    b.step()
+    torch.cuda.synchronize()
+    assert np.isfinite(b.loss.cpu().numpy()).all()

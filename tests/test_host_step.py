@@ -34,3 +34,17 @@ def test_grid_mode_on_host():
     st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), color=wl.color.data, device="cpu")
     assert st.grid_mode and st.grid("color").channels == 3
     assert torch.equal(st.color["p"], torch.as_tensor(wl.color.data))
+
+
+def test_fused_gather_choice():
+    wl = synth.config2(R=8, n=16)
+    st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                   mlp=(wl.mlp.W, wl.mlp.b), device="cpu")
+    assert st.fused_gather  # 12 feature channels: the gather runs inside the colour head's forward
+    # three feature channels cannot move as float4 rows: the separate gather is kept
+    m3 = synth.mlp_weights(np.random.default_rng(0), C=3)
+    st3 = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data[..., :3],
+                    mlp=(m3.W, m3.b), device="cpu")
+    assert not st3.fused_gather
+    assert not TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                         mlp=(wl.mlp.W, wl.mlp.b), fused_gather=False, device="cpu").fused_gather
