@@ -246,6 +246,65 @@ def proposal_leg(steps=1500, batch=8192, pool=65536, n_eval=8192, log=None, clea
             "speedup_vs_plain256": round(ms_plain / ms_prop, 3), "eval_rays": n_eval, "tau_sweep": sweep}
 
 
+def render_sweep_leg(sizes=(8192, 32768, 131072)):
+    """The render path alone (density gather, alpha, compositing, distortion forward; the
+    backward with per-sample density gradients; binning and the brick-binned density scatter)
+    at growing batches of the same scene and ray recipe, autotuned longest-first schedule each:
+    its algorithmic HBM rate and fraction of the peak (per-ray walks are latency-bound, so the
+    fraction grows as the batch amortises the latency)."""
+    import torch
+    import synth
+    from paper_2206_05085_amd import ops
+    from paper_2206_05085_amd.step import TrainStep
+
+    def timed(f, n=10):
+        for _ in range(2):
+            f()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    rows = []
+    for R in sizes:
+        wl = synth.config2(R=R)
+        smp = wl.samples
+        S = smp.n_samples
+        n = wl.density.data.shape[0]
+        lo, hi = float(wl.density.xyz_min[0]), float(wl.density.xyz_max[0])
+        print(f"[bench] render sweep: {R} rays, S = {S}", file=sys.stderr, flush=True)
+        st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                       mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight)
+        b = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
+        st.bind(b, wl.rays.dirs, wl.target)
+        st.forward()
+        st.tune()
+        dens = st.grid("density")
+        fwd = timed(lambda: ops.render_forward(b, dens, None, st.rgb_s, act_shift_=st.shift, out=(st.rgb, st.T, st.dist),
+                                               state=st.state, schedule=st.schedule))
+        bwd = timed(lambda: ops.render_backward(b, dens, None, st.rgb_s, st.T, st.state, st.g_rgb, st.g_dist, None,
+                                                act_shift_=st.shift, grad_sample_rgb=st.g_rgb_s,
+                                                grad_sample_density=st.g_raw, schedule=st.schedule))
+        binm = timed(lambda: ops.bin_samples(dens, b.xyz, ws=st.bin_ws))
+        sc = timed(lambda: ops.grid_scatter_binned(dens, b.xyz, st.g_raw, st.bin_ws))
+        U = unique_vertices(smp.xyz, n, lo, hi)
+        byts = (S * 36 + U * 4 + R * 24) + (S * 52 + U * 4 + R * 24) + (S * 20 + U * 8)
+        ms = fwd + bwd + sc
+        rows.append({"rays": R, "samples": S, "ms": {"render_fwd": round(fwd, 4), "render_bwd": round(bwd, 4),
+                                                    "bin": round(binm, 4), "scatter_density": round(sc, 4)},
+                     "algorithmic_bytes": int(byts), "GB/s": round(byts / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "schedule": {"waves_per_block": st.schedule.waves_per_block, "grid_waves": st.schedule.grid_waves}})
+        del st, b, wl
+        torch.cuda.empty_cache()
+    return {"kernels": "render_fwd + render_bwd + scatter_density (bytes and rate as in roofline_render; the "
+                       "binning, which needs only the points, is timed beside them)", "sizes": rows}
+
+
 def ragged_leg(R=8192, steps=20, log=None):
     """Unbounded ragged batch (320^3 contracted grids, lognormal lengths 32-1024): render
     forward + backward under three schedules (one wave per ray in batch order; the autotuned
@@ -536,6 +595,7 @@ def main():
     ap.add_argument("--rays", type=int, default=8192)
     ap.add_argument("--no-proposal", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
+    ap.add_argument("--no-render-sweep", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=1500)
     ap.add_argument("--no-tv", action="store_true")
     ap.add_argument("--no-sampler", action="store_true")
@@ -703,6 +763,9 @@ def main():
     if not args.no_ff:
         print("[bench] forward-facing NDC volume: occupancy, plane sampling, step", file=sys.stderr, flush=True)
         out["forward_facing"] = ff_leg(ops, torch)
+        torch.cuda.empty_cache()
+    if not args.no_render_sweep:
+        out["render_batch_sweep"] = render_sweep_leg()
         torch.cuda.empty_cache()
     if not args.no_ragged:
         print("[bench] ragged unbounded batch: schedules", file=sys.stderr, flush=True)
