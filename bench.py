@@ -29,6 +29,10 @@ H, C_IN, N_IN = 128, 12, 39   # MLP widths: hidden, feature channels, input colu
 
 
 TRAFFIC_FILES = {"mlp_bwd": ("profiles/mlp_bwd_config2_hbm_traffic.md", ["paper_2206_05085_amd/csrc/mlp.hip",
+                                                                       "paper_2206_05085_amd/csrc/dvgo_internal.h"]),
+                 # render_fwd + render_bwd + brick_scatter, bytes per step
+                 "render": ("profiles/render_config2_hbm_traffic.md", ["paper_2206_05085_amd/csrc/render.hip",
+                                                                       "paper_2206_05085_amd/csrc/grid.hip",
                                                                        "paper_2206_05085_amd/csrc/dvgo_internal.h"])}
 
 
@@ -740,6 +744,13 @@ def main():
                    "bound": "hbm", "achieved": round(r_bytes / (rt * 1e-3) / 1e9, 1), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(r_bytes / (rt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                    "algorithmic_bytes": int(r_bytes), "unique_density_vertices": U}
+    # bytes the same kernels move past L2 (counter runs): the random trilinear gathers fetch whole
+    # lines for 4-byte values, so this exceeds the algorithmic bytes several times
+    r_traffic = measured_traffic("render")
+    roof_render["traffic"] = r_traffic
+    if r_traffic:
+        roof_render["traffic_GB/s"] = round(r_traffic / (rt * 1e-3) / 1e9, 1)
+        roof_render["traffic_frac"] = round(r_traffic / (rt * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
     out = {"metric": METRIC, "value": round(value, 1), "unit": "ray-samples/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
