@@ -1243,7 +1243,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         make_float4(df[0] * un, df[1] * un, df[2] * un, df[3] * un);
             }
         };
-        if (blockIdx.x < ntiles) {
+        if ((int)blockIdx.x < ntiles) {
             const int r0 = a.tile_ray[blockIdx.x];
             load_tile(blockIdx.x, r0, window_entry(a.offs, a.n_rays, r0));
             stage_tile(0);
