@@ -197,3 +197,38 @@ def test_missing_library_fails_loudly(tmp_path):
             "try:\n    L.lib()\nexcept RuntimeError as e:\n    print('raised', e)\n")
     out = subprocess.check_output([sys.executable, "-c", code], cwd=ROOT).decode()
     assert out.startswith("raised")
+
+
+def test_colour_head_entry_points_validate(L):
+    # dvgo_mlp_prepare / dvgo_mlp_forward_gather reject bad arguments before any GPU work
+    lib = L.lib()
+    m = L.ColorMLP()
+    m.struct_size = C.sizeof(L.ColorMLP)
+    m.in_feat, m.n_freq, m.hidden = 12, 4, 128
+    m.W1 = m.b1 = m.W2 = m.b2 = m.W3 = m.b3 = 256
+    need = C.c_size_t()
+    assert lib.dvgo_mlp_workspace_size(C.byref(m), 4, 10, C.byref(need)) == 0
+    ws_ok = 4096 * 256  # a 256-aligned fake device address; nothing is launched on these paths
+    # prepare: NULL ray arrays, small workspace, bad struct size
+    assert lib.dvgo_mlp_prepare(C.byref(m), 4, None, None, 10, ws_ok, need.value, None) == -1
+    assert lib.dvgo_mlp_prepare(C.byref(m), 4, 256, 256, 10, ws_ok, need.value - 1, None) == -5
+    bad = L.ColorMLP()
+    bad.struct_size = 3
+    assert lib.dvgo_mlp_prepare(C.byref(bad), 4, 256, 256, 10, ws_ok, need.value, None) == -8
+    # forward with the fused gather: NULL grid, channel mismatch, misaligned output rows
+    assert lib.dvgo_mlp_forward_gather(C.byref(m), 4, 256, 256, 10, None, 256, 256, 256, ws_ok, need.value,
+                                       None) == -1
+    g = L.Grid()
+    g.struct_size = C.sizeof(L.Grid)
+    g.nx = g.ny = g.nz = 4
+    g.channels, g.ch_stride = 3, 4
+    g.data = 256
+    g.xyz_min = (C.c_float * 3)(-1, -1, -1)
+    g.xyz_max = (C.c_float * 3)(1, 1, 1)
+    assert lib.dvgo_mlp_forward_gather(C.byref(m), 4, 256, 256, 10, C.byref(g), 256, 256, 256, ws_ok, need.value,
+                                       None) == -2
+    assert "channels" in _err(L)
+    g.channels, g.ch_stride = 12, 12
+    assert lib.dvgo_mlp_forward_gather(C.byref(m), 4, 256, 256, 10, C.byref(g), 256, 260, 256, ws_ok, need.value,
+                                       None) == -7
+    assert "16-byte aligned" in _err(L)
