@@ -238,11 +238,13 @@ class TrainStep:
             self.backward()
             self.optimise()
             return self.loss
-        # Two streams.  main: feature gather, colour head, render forward and backward, colour-head
-        # backward, feature scatter, feature Adam.  side: the Adam step counter, the colour head's
-        # preparation and the binning (need only the batch) from the start, and after the
-        # colour-head backward the density scatter (+ TV), density Adam, MLP Adam and the loss
-        # value beside the feature scatter.  The colour-head backward takes
+        # Two streams.  main: colour head (with the feature gather fused into its forward, else the
+        # gather first), render forward and backward, colour-head backward, feature scatter, feature
+        # Adam.  side: the Adam step counter and the binning (need only the batch) from the start (and
+        # the colour head's preparation when the gather runs apart), and after the colour-head
+        # backward the density scatter (+ TV), density Adam, MLP Adam and the loss value beside the
+        # feature scatter.  Every Adam launch follows the counter: the side's in stream order, the
+        # feature Adam through main's edge from the binning.  The colour-head backward takes
         # nearly all of a CU's LDS and registers, so nothing is meant to run beside it.  Main
         # hands work to the side once (each hand-over delays main's next kernel in a graph).  Each
         # buffer has one writer at a time; the side joins main at the end.
@@ -255,8 +257,8 @@ class TrainStep:
         binned = torch.cuda.Event()
         if self.fused_gather:
             # the gather runs inside the colour head's forward; its preparation leads on main
-            ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
             with torch.cuda.stream(side):
+                ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
                 ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
                 binned.record(side)
             self.forward(loss_value=False)
