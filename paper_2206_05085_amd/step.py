@@ -238,31 +238,27 @@ class TrainStep:
             self.backward()
             self.optimise()
             return self.loss
-        # Two streams.  main: colour head (with the feature gather fused into its forward, else the
-        # gather first), render forward and backward, colour-head backward, feature scatter, feature
-        # Adam.  side: the Adam step counter and the binning (need only the batch) from the start (and
-        # the colour head's preparation when the gather runs apart), and after the colour-head
-        # backward the density scatter (+ TV), density Adam, MLP Adam and the loss value beside the
-        # feature scatter.  Every Adam launch follows the counter: the side's in stream order, the
-        # feature Adam through main's edge from the binning.  The colour-head backward takes
-        # nearly all of a CU's LDS and registers, so nothing is meant to run beside it.  Main
-        # hands work to the side once (each hand-over delays main's next kernel in a graph).  Each
-        # buffer has one writer at a time; the side joins main at the end.
+        # Two streams.  main: the Adam step counter, colour head (with the feature gather fused into
+        # its forward), render forward and backward, colour-head backward, feature scatter, feature
+        # Adam.  side, after the colour-head backward: the binning, density scatter (+ TV), density
+        # Adam, MLP Adam and the loss value, beside the feature scatter.  The colour-head backward
+        # takes nearly all of a CU's LDS and registers, so nothing is meant to run beside it; the
+        # forward runs alone too (the binning beside it slowed it more than the binning costs the
+        # side).  Main hands work to the side once (each hand-over delays main's next kernel in a
+        # graph), and every Adam launch follows the counter in stream order.  With the gather apart
+        # (features not a multiple of 4 channels) the side also runs the counter, the colour head's
+        # preparation and the binning beside the gather.  Each buffer has one writer at a time; the
+        # side joins main at the end.
         main = torch.cuda.current_stream()
         if self.side is None:
             self.side = torch.cuda.Stream(device=self.device)
         side = self.side
         b = self.batch
-        side.wait_stream(main)  # the side's first kernels depend on nothing of this step
-        binned = torch.cuda.Event()
         if self.fused_gather:
-            # the gather runs inside the colour head's forward; its preparation leads on main
-            with torch.cuda.stream(side):
-                ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
-                ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
-                binned.record(side)
+            ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
             self.forward(loss_value=False)
         else:
+            side.wait_stream(main)  # the side's first kernels depend on nothing of this step
             ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
             with torch.cuda.stream(side):
                 ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
@@ -270,12 +266,14 @@ class TrainStep:
                 prepared = torch.cuda.Event()
                 prepared.record(side)
                 ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
+                binned = torch.cuda.Event()
                 binned.record(side)
             main.wait_event(prepared)  # the colour head's preparation and the step counter
             self.forward(gathered=True, loss_value=False, prepared=True)
-        # An edge from the binning into main (long satisfied by now): without one, a graph replay
-        # may launch the binning only behind main's last kernels, and the density work with it.
-        main.wait_event(binned)
+            # An edge from the binning into main (long satisfied by now): without one, a graph
+            # replay may launch the binning only behind main's last kernels, and the density work
+            # with it.
+            main.wait_event(binned)
         ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
                             None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
                             schedule=self.schedule, grad_sample_density=self.g_raw)
@@ -287,6 +285,8 @@ class TrainStep:
                              ws=self.mlp_ws, prepared=True)
         side.wait_stream(main)
         with torch.cuda.stream(side):
+            if self.fused_gather:
+                ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
             ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
             if self.tv is not None:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])

@@ -108,20 +108,24 @@ def test_graph_replays_match_eager(pkg):
               name=f"mlp replay {rep}")
 
 
-@pytest.mark.parametrize("fused", [False, True])
-def test_two_stream_step_matches_sequential(pkg, fused):
+@pytest.mark.parametrize("fused,gather_apart", [(False, False), (True, False), (False, True)])
+def test_two_stream_step_matches_sequential(pkg, fused, gather_apart):
     # the step that overlaps the density scatter and the density / MLP Adam updates on a second
-    # stream (with the feature scatter separate or fused into the colour head's backward) takes
-    # the same update as the strictly sequential step, eagerly and from a graph
+    # stream (with the feature scatter separate or fused into the colour head's backward, and the
+    # feature gather fused into the colour head's forward or run apart, which moves the counter,
+    # the preparation and the binning to the side stream) takes the same update as the strictly
+    # sequential step, eagerly and from a graph
     ops, _, step = pkg
     wl = synth.config2(R=256, n=48)
-    say("two-stream step vs sequential, 48^3, 256 rays, TV on, fused feature scatter", fused)
-    mk = lambda conc, fu=False: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max),
-                                               feat=wl.feat.data, mlp=(wl.mlp.W, wl.mlp.b),
-                                               dist_weight=wl.dist_weight, tv=(1e-3, 1e-4, 1.0, True),
-                                               concurrent=conc, fused_scatter=fu)
+    say("two-stream step vs sequential, 48^3, 256 rays, TV on, fused feature scatter", fused,
+        "gather apart", gather_apart)
+    mk = lambda conc, fu=False, fg=True: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max),
+                                                        feat=wl.feat.data, mlp=(wl.mlp.W, wl.mlp.b),
+                                                        dist_weight=wl.dist_weight, tv=(1e-3, 1e-4, 1.0, True),
+                                                        concurrent=conc, fused_scatter=fu, fused_gather=fg)
     smp = wl.samples
-    seq, conc, gr = mk(False), mk(True, fused), mk(True, fused)
+    seq, conc, gr = mk(False), mk(True, fused, not gather_apart), mk(True, fused, not gather_apart)
+    assert conc.fused_gather == gr.fused_gather == (not gather_apart)
     for st in (seq, conc, gr):
         st.bind(ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len),
                 wl.rays.dirs, wl.target)
