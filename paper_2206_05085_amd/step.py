@@ -35,8 +35,12 @@ class TrainStep:
         binned_scatter: the renderer writes per-sample density gradients, which are scattered
         brick by brick (samples binned once per step) instead of by in-wave aggregated atomics
         inside the render kernel.  concurrent: in the feature-grid mode, run the binning, the
-        density scatter and the density and MLP Adam updates on a second stream, overlapped with
-        the colour head's backward and the feature scatter (stream-ordered, graph-capturable).
+        density scatter, the density and MLP Adam updates and the colour head's preparation for
+        the next step on a second stream, overlapped with the feature scatter and feature Adam
+        (stream-ordered, graph-capturable).  A concurrent step leaves that preparation in the
+        colour head's workspace and sets prepared_ahead, and the next step skips its own; bind(),
+        optimise() and the sequential path clear the flag, and whoever changes the MLP weights in
+        any other way must clear it too.
         fused_scatter: scatter the feature gradient inside the colour head's backward kernel
         (unwarped feature grids) instead of writing it and scattering it afterwards; saves the
         per-sample feature-gradient buffer, but measured slower on the config-2 step (off).
@@ -55,6 +59,7 @@ class TrainStep:
         self.binned = bool(binned_scatter)
         self.concurrent = bool(concurrent)
         self.side = None
+        self.prepared_ahead = False  # the colour head's workspace holds the preparation for the next step
         self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
         self.fused = bool(fused_scatter) and self.warp[0] == 0
         self.fused_gather = bool(fused_gather) and feat is not None and np.shape(feat)[-1] % 4 == 0
@@ -94,6 +99,7 @@ class TrainStep:
         d = self.device
         self.batch = batch
         self.schedule = None
+        self.prepared_ahead = False
         self.dirs = torch.as_tensor(dirs).to(d, torch.float32).contiguous()
         self.target = torch.as_tensor(target).to(d, torch.float32).contiguous()
         self.rgb, self.T, self.dist = (torch.empty(R, 3, device=d), torch.empty(R, device=d),
@@ -204,6 +210,7 @@ class TrainStep:
             ops.tv_add_grad(self.grid("color" if self.grid_mode else "feat"), w_other, delta, dense)
 
     def optimise(self):
+        self.prepared_ahead = False  # the MLP weights change
         ops.counter_add(self.t_dev, 1)
         b1, b2 = self.betas
         groups = [("density", self.lr_grid, True), ("color" if self.grid_mode else "feat", self.lr_grid, True)]
@@ -234,6 +241,7 @@ class TrainStep:
 
     def step(self):
         if not (self.concurrent and self.binned and not self.grid_mode):
+            self.prepared_ahead = False
             self.forward()
             self.backward()
             self.optimise()
@@ -241,7 +249,8 @@ class TrainStep:
         # Two streams.  main: the Adam step counter, colour head (with the feature gather fused into
         # its forward), render forward and backward, colour-head backward, feature scatter, feature
         # Adam.  side, after the colour-head backward: the binning, density scatter (+ TV), density
-        # Adam, MLP Adam and the loss value, beside the feature scatter.  The colour-head backward
+        # Adam, MLP Adam, the colour head's preparation for the next step and the loss value,
+        # beside the feature scatter.  The colour-head backward
         # takes nearly all of a CU's LDS and registers, so nothing is meant to run beside it; the
         # forward runs alone too (the binning beside it slowed it more than the binning costs the
         # side).  Main hands work to the side once (each hand-over delays main's next kernel in a
@@ -256,7 +265,9 @@ class TrainStep:
         b = self.batch
         if self.fused_gather:
             ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
-            self.forward(loss_value=False)
+            if not self.prepared_ahead:
+                ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
+            self.forward(loss_value=False, prepared=True)
         else:
             side.wait_stream(main)  # the side's first kernels depend on nothing of this step
             ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
@@ -292,6 +303,10 @@ class TrainStep:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
             self._adam("density", self.lr_grid, True)
             self._adam("mlp_flat", self.lr_mlp, False)
+            if self.fused_gather:
+                # the next step's preparation, from the updated weights (main reads the workspace
+                # again only after the join)
+                ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
             ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
         if not self.fused:
             ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
@@ -299,13 +314,17 @@ class TrainStep:
             ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
         self._adam("feat", self.lr_grid, True)
         main.wait_stream(side)
+        self.prepared_ahead = self.fused_gather
         return self.loss
 
     # ----------------------------------------------------------- HIP graphs
     def capture(self, warmup: int = 1) -> Optional[torch.cuda.CUDAGraph]:
         """Capture forward+backward+Adam of the bound batch in a graph.  Each replay is one
         full step: the Adam step counter lives on the device and is advanced inside the
-        graph, so replays continue the bias correction exactly like eager steps."""
+        graph, so replays continue the bias correction exactly like eager steps.  A concurrent
+        step captured after the warm-up leaves out its own colour-head preparation and takes the
+        one the previous replay (or the warm-up) left in the workspace: capture again after
+        bind() or after changing the MLP weights outside the step."""
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
