@@ -39,8 +39,8 @@ class TrainStep:
         the next step on a second stream, overlapped with the feature scatter and feature Adam
         (stream-ordered, graph-capturable).  A concurrent step leaves that preparation in the
         colour head's workspace and sets prepared_ahead, and the next step skips its own; bind(),
-        optimise() and the sequential path clear the flag, and whoever changes the MLP weights in
-        any other way must clear it too.
+        optimise() and the sequential path clear the flag, and an in-place torch write to the MLP
+        weights (which bumps their version) makes the next step prepare again.
         fused_scatter: scatter the feature gradient inside the colour head's backward kernel
         (unwarped feature grids) instead of writing it and scattering it afterwards; saves the
         per-sample feature-gradient buffer, but measured slower on the config-2 step (off).
@@ -60,6 +60,7 @@ class TrainStep:
         self.concurrent = bool(concurrent)
         self.side = None
         self.prepared_ahead = False  # the colour head's workspace holds the preparation for the next step
+        self._prep_version = -1  # torch version of the MLP weights that preparation was made from
         self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
         self.fused = bool(fused_scatter) and self.warp[0] == 0
         self.fused_gather = bool(fused_gather) and feat is not None and np.shape(feat)[-1] % 4 == 0
@@ -265,7 +266,9 @@ class TrainStep:
         b = self.batch
         if self.fused_gather:
             ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
-            if not self.prepared_ahead:
+            # in-place torch writes to the weights (or their views) bump their version; the
+            # library's own Adam does not
+            if not self.prepared_ahead or self._prep_version != self.mlp_flat["p"]._version:
                 ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
             self.forward(loss_value=False, prepared=True)
         else:
@@ -315,6 +318,7 @@ class TrainStep:
         self._adam("feat", self.lr_grid, True)
         main.wait_stream(side)
         self.prepared_ahead = self.fused_gather
+        self._prep_version = self.mlp_flat["p"]._version
         return self.loss
 
     # ----------------------------------------------------------- HIP graphs

@@ -150,6 +150,38 @@ def test_two_stream_step_matches_sequential(pkg, fused, gather_apart):
                 assert not getattr(other, name)["g"].any(), f"{name} gradient not cleared ({tag})"
 
 
+def test_prepared_ahead_follows_weight_edits(pkg):
+    # A concurrent step leaves the colour head's preparation for the next step in its workspace;
+    # an in-place torch edit of the MLP weights between steps (through a per-layer view) makes the
+    # next step prepare again, so it matches the sequential step, which always prepares.
+    ops, _, step = pkg
+    wl = synth.config2(R=256, n=48)
+    say("prepared-ahead colour head after an in-place weight edit, 48^3, 256 rays")
+    smp = wl.samples
+    mk = lambda conc: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
+                                     mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight, concurrent=conc)
+    seq, conc = mk(False), mk(True)
+    for st in (seq, conc):
+        st.bind(ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len),
+                wl.rays.dirs, wl.target)
+        st.step()
+        st.step()
+    assert conc.prepared_ahead and not seq.prepared_ahead
+    for st in (seq, conc):
+        with torch.no_grad():
+            st.mlp.W[2].mul_(0.5)  # output layer, in place through its view of the flat parameters
+            st.mlp.b[0].add_(0.25)
+    for rep in range(2):
+        seq.step()
+        conc.step()
+        torch.cuda.synchronize()
+        close(conc.loss.cpu().numpy(), seq.loss.cpu().numpy(), rtol=1e-5, floor=1e-3, name=f"loss after edit {rep}")
+        close(conc.mlp_flat["p"].cpu().numpy(), seq.mlp_flat["p"].cpu().numpy(), rtol=1e-5, floor=1e-3,
+              name=f"mlp after edit {rep}")
+        close_after_adam(conc.density["p"].cpu().numpy(), seq.density["p"].cpu().numpy(), 3 + rep, seq.lr_grid,
+                         name=f"density after edit {rep}")
+
+
 def test_upscale_then_step(pkg):
     # progressive scaling mid-training: 48^3 -> 72^3, moments restarted, the step runs on
     # eagerly and captured again
