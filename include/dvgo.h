@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define DVGO_ABI_VERSION 4
+#define DVGO_ABI_VERSION 5
 
 enum {
     DVGO_OK = 0,
@@ -321,6 +321,21 @@ int dvgo_mlp_forward_gather(const dvgo_color_mlp *m, int32_t n_rays, const int32
 int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
                       int64_t n_samples, const float *feat, const float *grad_rgb, float *grad_feat, void *ws,
                       size_t ws_bytes, void *stream);
+
+/* dvgo_mlp_backward in two parts, so that a caller can take the weight-gradient reduction off
+ * the path of the work that needs only grad_feat (e.g. onto another stream, beside the feature
+ * scatter).  dvgo_mlp_backward_partials: same arguments and outputs as dvgo_mlp_backward except
+ * that the weight and bias gradients stay in ws as one partial sum per block.
+ * dvgo_mlp_reduce_grads: adds those partials into m->g* in the same fixed order as
+ * dvgo_mlp_backward (the two calls together give its gradients bit for bit); m, n_rays,
+ * n_samples and ws as in the partials call.  The partials live in their own part of ws, which
+ * dvgo_mlp_prepare and the forward calls do not touch; the next backward call on ws overwrites
+ * them, so it must follow the reduction. */
+int dvgo_mlp_backward_partials(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
+                               int64_t n_samples, const float *feat, const float *grad_rgb, float *grad_feat, void *ws,
+                               size_t ws_bytes, void *stream);
+int dvgo_mlp_reduce_grads(const dvgo_color_mlp *m, int32_t n_rays, int64_t n_samples, void *ws, size_t ws_bytes,
+                          void *stream);
 
 /* dvgo_mlp_backward with the feature gradient scattered straight into the feature grid:
  * feat_grid->grad += trilinear^T(d loss / d feat) at the points xyz [S,3] (the points the

@@ -9,7 +9,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdvgo.so")
-ABI_VERSION = 4
+ABI_VERSION = 5
 
 VP = C.c_void_p
 OK = 0
@@ -98,6 +98,8 @@ SIGNATURES = {
     "dvgo_mlp_forward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_forward_gather": (C.c_int, [_PM, _I32, VP, VP, _I64, _PG, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
+    "dvgo_mlp_backward_partials": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
+    "dvgo_mlp_reduce_grads": (C.c_int, [_PM, _I32, _I64, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward_scatter": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, _PG, VP, VP, C.c_size_t, VP]),
     "dvgo_loss_head": (C.c_int, [_I32, VP, VP, VP, _F, VP, VP, VP, VP]),
     "dvgo_proposal_coarse": (C.c_int, [_PR, _PG, _F, _F, _F, VP, VP, VP]),

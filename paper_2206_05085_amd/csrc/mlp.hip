@@ -1547,9 +1547,16 @@ extern "C" int dvgo_mlp_forward_gather(const dvgo_color_mlp *m, int32_t n_rays, 
     return a.fg.warp ? launch_fwd<2>(a, m, st) : launch_fwd<1>(a, m, st);
 }
 
-extern "C" int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
-                                 const float *dirs, int64_t n_samples, const float *feat, const float *grad_rgb,
-                                 float *grad_feat, void *ws, size_t ws_bytes, void *stream) {
+namespace {
+
+int launch_reduce(const MlpArgs &a, hipStream_t st) {
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((a.n_params + 63) / 64), dim3(RED_THREADS), 0, st, a);
+    return check_hip(hipGetLastError(), "mlp_reduce_kernel launch");
+}
+
+int mlp_backward_impl(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
+                      int64_t n_samples, const float *feat, const float *grad_rgb, float *grad_feat, void *ws,
+                      size_t ws_bytes, void *stream, bool reduce) {
     MlpArgs a;
     int rc = setup(m, n_rays, ray_offsets, dirs, n_samples, feat, ws, ws_bytes, true, a);
     if (rc) return rc;
@@ -1567,9 +1574,48 @@ extern "C" int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const 
     else
         hipLaunchKernelGGL((mlp_bwd_kernel<true, false>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     rc = check_hip(hipGetLastError(), "mlp_bwd_kernel launch");
+    if (rc || !reduce) return rc;
+    return launch_reduce(a, st);
+}
+
+}  // namespace
+
+extern "C" int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
+                                 const float *dirs, int64_t n_samples, const float *feat, const float *grad_rgb,
+                                 float *grad_feat, void *ws, size_t ws_bytes, void *stream) {
+    return mlp_backward_impl(m, n_rays, ray_offsets, dirs, n_samples, feat, grad_rgb, grad_feat, ws, ws_bytes,
+                             stream, true);
+}
+
+extern "C" int dvgo_mlp_backward_partials(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
+                                          const float *dirs, int64_t n_samples, const float *feat,
+                                          const float *grad_rgb, float *grad_feat, void *ws, size_t ws_bytes,
+                                          void *stream) {
+    return mlp_backward_impl(m, n_rays, ray_offsets, dirs, n_samples, feat, grad_rgb, grad_feat, ws, ws_bytes,
+                             stream, false);
+}
+
+extern "C" int dvgo_mlp_reduce_grads(const dvgo_color_mlp *m, int32_t n_rays, int64_t n_samples, void *ws,
+                                     size_t ws_bytes, void *stream) {
+    int rc = check_mlp(m, true);
     if (rc) return rc;
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((a.n_params + 63) / 64), dim3(RED_THREADS), 0, st, a);
-    return check_hip(hipGetLastError(), "mlp_reduce_kernel launch");
+    if (n_rays < 0 || n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays or n_samples");
+    if (n_samples >= ((int64_t)1 << 31) / 16) return set_error(DVGO_ERR_RANGE, "n_samples too large");
+    size_t off_pe, off_tr, off_part;
+    const size_t need = ws_layout(m, n_rays, n_samples, &off_pe, &off_tr, &off_part);
+    if (!ws || ws_bytes < need) return set_error(DVGO_ERR_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, need);
+    if (((uintptr_t)ws & 255) != 0) return set_error(DVGO_ERR_SHAPE, "workspace must be 256-byte aligned");
+    if (n_samples == 0) return DVGO_OK;
+    MlpArgs a;
+    memset(&a, 0, sizeof(a));
+    a.gW1 = m->gW1; a.gb1 = m->gb1; a.gW2 = m->gW2; a.gb2 = m->gb2; a.gW3 = m->gW3; a.gb3 = m->gb3;
+    a.in_feat = m->in_feat;
+    a.n_freq = m->n_freq;
+    a.n_in = n_in_of(m);
+    a.n_params = n_params_of(m);
+    a.partial = (float *)((char *)ws + off_part);
+    a.nblocks = bwd_blocks(n_samples);
+    return launch_reduce(a, (hipStream_t)stream);
 }
 
 extern "C" int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
@@ -1600,6 +1646,5 @@ extern "C" int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays
         hipLaunchKernelGGL((mlp_bwd_kernel<true, true>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     rc = check_hip(hipGetLastError(), "mlp_bwd_kernel launch");
     if (rc) return rc;
-    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((a.n_params + 63) / 64), dim3(RED_THREADS), 0, st, a);
-    return check_hip(hipGetLastError(), "mlp_reduce_kernel launch");
+    return launch_reduce(a, st);
 }

@@ -17,7 +17,8 @@ from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16
 __all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
-           "grid_scatter", "grid_resample", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_forward", "mlp_backward", "mlp_backward_scatter", "loss_head",
+           "grid_scatter", "grid_resample", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_prepare", "mlp_forward", "mlp_forward_gather", "mlp_backward",
+           "mlp_backward_partials", "mlp_reduce_grads", "mlp_backward_scatter", "loss_head",
            "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
            "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2",
            "MLP_SPLIT_F16", "MLP_F16"]
@@ -471,6 +472,10 @@ def mlp_forward_gather(mlp: MLPParams, ray_offsets, dirs, feat_grid: DeviceGrid,
 def mlp_backward(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, grad_feat=None, ws=None, prepared=False):
     """prepared=True reuses the preparation a preceding mlp_forward on the same ws wrote
     (same weights and batch); it needs an explicit ws."""
+    return _mlp_backward_call("dvgo_mlp_backward", mlp, ray_offsets, dirs, feat, grad_rgb, grad_feat, ws, prepared)
+
+
+def _mlp_backward_call(entry, mlp, ray_offsets, dirs, feat, grad_rgb, grad_feat, ws, prepared):
     import ctypes
     if prepared and ws is None:
         raise ValueError("prepared=True needs the workspace of the preceding call")
@@ -481,9 +486,23 @@ def mlp_backward(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, grad_feat=No
         grad_feat = torch.empty(S, mlp.in_feat, device=feat.device)
     ws = _mlp_ws(mlp, R, S, ws, feat.device)
     m = mlp.struct(need_grad=True, prepared=prepared)
-    call("dvgo_mlp_backward", ctypes.byref(m), R, _p(ray_offsets), _p(dirs), S, _p(feat), _p(grad_rgb),
+    call(entry, ctypes.byref(m), R, _p(ray_offsets), _p(dirs), S, _p(feat), _p(grad_rgb),
          _p(grad_feat), _p(ws), ws.numel(), _stream())
     return grad_feat
+
+
+def mlp_backward_partials(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, ws, grad_feat=None, prepared=False):
+    """mlp_backward with the weight and bias gradients left in ws as per-block partials;
+    mlp_reduce_grads on the same ws adds them into the gradient buffers."""
+    return _mlp_backward_call("dvgo_mlp_backward_partials", mlp, ray_offsets, dirs, feat, grad_rgb, grad_feat, ws,
+                              prepared)
+
+
+def mlp_reduce_grads(mlp: MLPParams, n_rays: int, n_samples: int, ws):
+    """Add the partials a preceding mlp_backward_partials left in ws into mlp.gW / mlp.gb."""
+    import ctypes
+    call("dvgo_mlp_reduce_grads", ctypes.byref(mlp.struct(need_grad=True)), int(n_rays), int(n_samples), _p(ws),
+         ws.numel(), _stream())
 
 
 def mlp_backward_scatter(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, feat_grid: DeviceGrid, xyz, ws=None,

@@ -248,9 +248,10 @@ class TrainStep:
             self.optimise()
             return self.loss
         # Two streams.  main: the Adam step counter, colour head (with the feature gather fused into
-        # its forward), render forward and backward, colour-head backward, feature scatter, feature
-        # Adam.  side, after the colour-head backward: the binning, density scatter (+ TV), density
-        # Adam, MLP Adam, the colour head's preparation for the next step and the loss value,
+        # its forward), render forward and backward, colour-head backward (its weight gradients
+        # left as per-block partials), feature scatter, feature Adam.  side, after the colour-head
+        # backward: the binning, density scatter (+ TV), density Adam, the reduction of the weight
+        # gradients, MLP Adam, the colour head's preparation for the next step and the loss value,
         # beside the feature scatter.  The colour-head backward
         # takes nearly all of a CU's LDS and registers, so nothing is meant to run beside it; the
         # forward runs alone too (the binning beside it slowed it more than the binning costs the
@@ -295,8 +296,9 @@ class TrainStep:
             ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
                                      b.xyz, ws=self.mlp_ws, prepared=True)
         else:
-            ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
-                             ws=self.mlp_ws, prepared=True)
+            # the weight-gradient reduction waits on the side stream: only the MLP Adam needs it
+            ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
+                                      grad_feat=self.g_feat_s, prepared=True)
         side.wait_stream(main)
         with torch.cuda.stream(side):
             if self.fused_gather:
@@ -305,6 +307,8 @@ class TrainStep:
             if self.tv is not None:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
             self._adam("density", self.lr_grid, True)
+            if not self.fused:
+                ops.mlp_reduce_grads(self.mlp, b.n_rays, b.n_samples, self.mlp_ws)
             self._adam("mlp_flat", self.lr_mlp, False)
             if self.fused_gather:
                 # the next step's preparation, from the updated weights (main reads the workspace

@@ -232,3 +232,32 @@ def test_colour_head_entry_points_validate(L):
     assert lib.dvgo_mlp_forward_gather(C.byref(m), 4, 256, 256, 10, C.byref(g), 256, 260, 256, ws_ok, need.value,
                                        None) == -7
     assert "16-byte aligned" in _err(L)
+
+
+def test_split_backward_entry_points_validate(L):
+    # dvgo_mlp_backward_partials / dvgo_mlp_reduce_grads reject bad arguments before any GPU work
+    lib = L.lib()
+    m = L.ColorMLP()
+    m.struct_size = C.sizeof(L.ColorMLP)
+    m.in_feat, m.n_freq, m.hidden = 12, 4, 128
+    m.W1 = m.b1 = m.W2 = m.b2 = m.W3 = m.b3 = 256
+    m.gW1 = m.gb1 = m.gW2 = m.gb2 = m.gW3 = m.gb3 = 256
+    need = C.c_size_t()
+    assert lib.dvgo_mlp_workspace_size(C.byref(m), 4, 100, C.byref(need)) == 0
+    ws = 4096 * 256  # a 256-aligned fake device address; nothing is launched on these paths
+    assert lib.dvgo_mlp_reduce_grads(None, 4, 100, ws, need.value, None) == -1
+    assert lib.dvgo_mlp_reduce_grads(C.byref(m), 4, -1, ws, need.value, None) == -2
+    assert lib.dvgo_mlp_reduce_grads(C.byref(m), 4, 100, ws, need.value - 1, None) == -5
+    assert lib.dvgo_mlp_reduce_grads(C.byref(m), 4, 100, ws + 16, need.value, None) == -2
+    assert "256-byte" in _err(L)
+    bad = L.ColorMLP()
+    bad.struct_size = 3
+    assert lib.dvgo_mlp_reduce_grads(C.byref(bad), 4, 100, ws, need.value, None) == -8
+    m.gW2 = None  # the reduction writes every gradient buffer
+    assert lib.dvgo_mlp_reduce_grads(C.byref(m), 4, 100, ws, need.value, None) == -1
+    assert lib.dvgo_mlp_backward_partials(C.byref(m), 4, 256, 256, 100, 256, 256, 256, ws, need.value, None) == -1
+    m.gW2 = 256
+    assert lib.dvgo_mlp_backward_partials(C.byref(m), 4, 256, 256, 100, 256, None, 256, ws, need.value, None) == -1
+    assert lib.dvgo_mlp_backward_partials(C.byref(m), 4, None, 256, 100, 256, 256, 256, ws, need.value, None) == -1
+    assert lib.dvgo_mlp_backward_partials(C.byref(m), 4, 256, 256, 100, 256, 256, 256, ws, need.value - 1,
+                                          None) == -5

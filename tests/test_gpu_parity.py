@@ -408,6 +408,20 @@ def _mlp_case(dv, S_lengths, seed, bias_std=0.3, half=False):
     assert torch.equal(gf, gf2)
     for x, y in zip(gW + gb, gW2 + gb2):
         assert torch.equal(x, y)
+    # the backward in two parts (per-block partials, then the reduction, with a preparation on
+    # the same workspace in between, as the training step runs them) gives the same bits
+    gW3 = [torch.zeros_like(w) for w in W]
+    gb3 = [torch.zeros_like(v) for v in b]
+    P3 = dv.MLPParams(W, b, gW3, gb3, precision=P.precision)
+    ws3 = torch.empty_like(ws)
+    dv.mlp_prepare(P3, T(offs, torch.int32), T(dirs), S, ws3)
+    gf3 = dv.mlp_backward_partials(P3, T(offs, torch.int32), T(dirs), T(feat), T(grgb), ws3, prepared=True)
+    dv.mlp_prepare(P3, T(offs, torch.int32), T(dirs), S, ws3)
+    dv.mlp_reduce_grads(P3, R, S, ws3)
+    torch.cuda.synchronize()
+    assert torch.equal(gf3, gf2)
+    for x, y in zip(gW3 + gb3, gW2 + gb2):
+        assert torch.equal(x, y)
     f64, g64 = feat.astype(np.float64), grgb.astype(np.float64)
     ref = oracle.mlp_forward(mlp, offs, dirs, f64, half=half)
     rgf, rgW, rgb_ = oracle.mlp_backward(mlp, offs, dirs, f64, g64, half=half)
