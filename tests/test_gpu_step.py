@@ -407,3 +407,87 @@ def test_tuned_schedule_step_and_rebind(pkg):
     b.step()
     torch.cuda.synchronize()
     assert np.isfinite(b.loss.cpu().numpy()).all()
+
+
+def _moment_gradient(m0, m1, v0, v1, p0, p1, b1, skip):
+    """The gradient one Adam update consumed, read back from its first moment:
+    m1 = b1 m0 + (1 - b1) g in float32, so g = (m1 - b1 m0) / (1 - b1) up to the rounding of
+    m1 (returned as a per-element slack).  With skip, an element whose parameter and moments
+    are bit-for-bit unchanged took a zero gradient."""
+    b1 = np.float64(np.float32(b1))
+    c = np.float64(np.float32(1.0) - np.float32(b1))
+    m0d, m1d = m0.astype(np.float64).ravel(), m1.astype(np.float64).ravel()
+    g = (m1d - b1 * m0d) / c
+    slack = 4.0 * 2.0 ** -24 * (np.abs(m1d) + b1 * np.abs(m0d)) / c
+    if skip:
+        same = (m1.ravel() == m0.ravel()) & (v1.ravel() == v0.ravel()) & (p1.ravel() == p0.ravel())
+        g[same] = 0.0
+        slack[same] = 0.0
+    return g, slack
+
+
+@pytest.mark.timeout(600)
+def test_config2_full_size_captured_step(pkg):
+    """The launch configuration the benchmark times: 160^3 density and 160^3x12 feature grids,
+    8192 pinhole rays (S ~ 0.96 M live samples), render kernels on the autotuned longest-first
+    schedule, the two-stream step captured in a HIP graph after one warm-up step.  One replay is
+    checked against the FP64 oracle run from the parameters it started from: colour, distortion
+    and loss of every ray; the gradient of every grid entry and MLP parameter, read back from
+    the first Adam moment the replay wrote; and the replay's Adam update of every parameter,
+    given that gradient."""
+    ops, _, step = pkg
+    wl = synth.config2()
+    smp = wl.samples
+    say("config 2 full size, bench launch configuration: R =", smp.n_rays, "S =", smp.n_samples)
+    st = make_step(step, wl)
+    assert st.concurrent and st.binned and st.fused_gather and not st.fused
+    sched, _ = st.tune()
+    assert sched.ray_list is not None
+    g = st.capture(warmup=1)
+    torch.cuda.synchronize()
+    groups = (("density", st.lr_grid, True), ("feat", st.lr_grid, True), ("mlp_flat", st.lr_mlp, False))
+    before = {k: {q: getattr(st, k)[q].cpu().numpy().copy() for q in ("p", "m", "v", "g")} for k, _, _ in groups}
+    for k, _, _ in groups:
+        assert not before[k]["g"].any(), f"{k}: gradients not cleared by the warm-up step's Adam"
+    g.replay()
+    torch.cuda.synchronize()
+    t = int(st.t_dev.item())
+    assert t == 2
+    after = {k: {q: getattr(st, k)[q].cpu().numpy() for q in ("p", "m", "v")} for k, _, _ in groups}
+    say("replay done; oracle forward + backward from the replay's starting parameters")
+
+    # the oracle's inputs: the parameters the replay started from
+    import dataclasses
+    p0 = {k: before[k]["p"] for k, _, _ in groups}
+    shapes = [w.shape for w in wl.mlp.W] + [b.shape for b in wl.mlp.b]
+    parts = np.split(p0["mlp_flat"], np.cumsum([int(np.prod(s)) for s in shapes])[:-1])
+    mlp0 = synth.MLPWeights([parts[i].reshape(shapes[i]) for i in range(3)],
+                            [parts[3 + i].reshape(shapes[3 + i]) for i in range(3)])
+    wl0 = dataclasses.replace(wl, density=dataclasses.replace(wl.density, data=p0["density"].reshape(wl.density.data.shape)),
+                              feat=dataclasses.replace(wl.feat, data=p0["feat"].reshape(wl.feat.data.shape)), mlp=mlp0)
+    shift = float(np.float32(st.shift))
+    L, o, gd, gfeat, gW, gb = oracle_step_grads(wl0, shift)
+    close(st.rgb.cpu().numpy(), o["rgb"], **FWD, name="rgb")
+    close(st.dist.cpu().numpy(), o["D"], **FWD, name="distortion")
+    close(st.loss.cpu().numpy(), [L], **FWD, name="loss")
+
+    # ReLU units within float32 rounding of their kink: both sides are valid there
+    feat = oracle.gather(wl0.feat, smp.xyz)
+    srgb = oracle.mlp_forward(mlp0, smp.ray_offsets, wl.rays.dirs, feat)
+    _, GC, GD = oracle.loss_head(o["rgb"], wl.target, o["D"], wl.dist_weight)
+    g_srgb = oracle.render_backward(smp, wl0.density, GC, GD, None, srgb=srgb, shift=shift)["grad_srgb"]
+    sf, sW, sb = oracle.mlp_kink_slack(mlp0, smp.ray_offsets, wl.rays.dirs, feat, g_srgb)
+    kink = {"density": np.zeros(gd.size), "feat": np.abs(oracle.scatter(wl0.feat, smp.xyz, sf)).ravel(),
+            "mlp_flat": np.concatenate([np.abs(s).ravel() for s in list(sW) + list(sb)])}
+    want = {"density": gd.ravel(), "feat": gfeat.ravel(),
+            "mlp_flat": np.concatenate([np.asarray(x).ravel() for x in list(gW) + list(gb)])}
+    b1, b2 = st.betas
+    for k, lr, skip in groups:
+        a, z = after[k], before[k]
+        gk, rs = _moment_gradient(z["m"], a["m"], z["v"], a["v"], z["p"], a["p"], b1, skip)
+        say(k, "gradient from the first moment vs oracle;", int((gk != 0).sum()), "non-zero of", gk.size)
+        close(gk, want[k], **GRAD, name=f"grad {k}", slack=rs + kink[k])
+        # the update itself, from the gradient the replay consumed
+        pe, _, _ = oracle.adam(z["p"], gk, z["m"], z["v"], lr, float(np.float32(b1)), float(np.float32(b2)),
+                               st.eps, t, skip_zero=skip)
+        close_after_adam(a["p"], pe, 1, lr, name=f"{k} after Adam")
