@@ -588,6 +588,84 @@ def f16_head_leg(ops, torch, wl, batch, steps=30):
             "precision": "FP16 matrix operands (11-bit significands), FP32 accumulation"}
 
 
+def recompute_memory_leg(reps=5):
+    """Config 4 (the config-2 grids, 16384 rays x 512 samples): device memory and time of one
+    render + distortion forward and backward through the hand-written autograd Function, which
+    keeps one 16-byte checkpoint per ray and 64-sample chunk and recomputes the rest in the
+    backward, against the same loss under plain PyTorch autograd, which keeps its per-sample
+    tensors (alpha, transmittance, weights, the prefix sums of Eq. 2) for the backward.  The
+    density lookup is the same gather Function in both and the per-sample colours are inputs,
+    so the two differ only in what the compositing and the distortion loss keep.  Memory is the
+    peak allocated above the resident inputs, gradients included."""
+    import torch
+    import torch.nn.functional as F
+    import synth
+    from paper_2206_05085_amd import autograd as ag, ops
+    wl = synth.config4()
+    smp = wl.samples
+    R, S = smp.n_rays, smp.n_samples
+    lens = np.diff(smp.ray_offsets)
+    N = int(lens.max())
+    if not np.all((lens == 0) | (lens == N)):
+        raise RuntimeError("the stored-intermediates form needs rays of one length (or none)")
+    batch = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", torch.float32)
+    dens = dev(wl.density.data).requires_grad_(True)
+    srgb = dev(np.random.default_rng(7).random((S, 3))).requires_grad_(True)
+    tgt = dev(wl.target)
+    box = (tuple(wl.density.xyz_min), tuple(wl.density.xyz_max))
+    shift = float(np.float32(ops.act_shift()))
+    lam = wl.dist_weight
+    Rh = S // N  # rays with samples; the others (missing the box) show the background
+    hit = torch.as_tensor(np.flatnonzero(lens), device="cuda")
+    m, l = batch.s_mid.view(Rh, N), batch.s_len.view(Rh, N)
+
+    def recompute():
+        rgb, _, D = ag.render(dens, srgb, batch, box, grid_color=False, act_shift=shift)
+        (((rgb - tgt) ** 2).mean() + lam * D.mean()).backward()
+        return rgb, D
+
+    def stored():
+        raw = ag.gather(dens, batch.xyz, box)[:, 0]
+        a = -torch.expm1(-F.softplus(raw + shift) * batch.delta).view(Rh, N)
+        P = torch.cumprod(1.0 - a, 1)
+        w = a * torch.cat([torch.ones(Rh, 1, device="cuda"), P[:, :-1]], 1)
+        rgb_h = (w.unsqueeze(-1) * srgb.view(Rh, N, 3)).sum(1) + P[:, -1:]  # white background
+        W, Q = torch.cumsum(w, 1) - w, torch.cumsum(w * m, 1) - w * m
+        D_h = 2.0 * (w * (m * W - Q)).sum(1) + (w * w * l).sum(1) / 3.0
+        rgb = torch.ones(R, 3, device="cuda").index_copy(0, hit, rgb_h)
+        D = torch.zeros(R, device="cuda").index_copy(0, hit, D_h)
+        (((rgb - tgt) ** 2).mean() + lam * D.mean()).backward()
+        return rgb, D
+
+    res = {}
+    for name, f in (("recompute", recompute), ("stored", stored)):
+        dens.grad = srgb.grad = None
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        rgb, D = f()
+        torch.cuda.synchronize()
+        peak = torch.cuda.max_memory_allocated() - base
+        out = (rgb.detach().clone(), D.detach().clone(), dens.grad.clone(), srgb.grad.clone())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dens.grad = srgb.grad = None
+            f()
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = (peak, e0.elapsed_time(e1) / reps, out)
+    rel = lambda x, y: float((x - y).norm() / y.norm().clamp_min(1e-30))
+    (pr, tr, a), (ps, ts, b) = res["recompute"], res["stored"]
+    return {"rays": R, "rays_with_samples": Rh, "samples": S, "recompute_peak_mb": round(pr / 1e6, 1), "stored_peak_mb": round(ps / 1e6, 1),
+            "recompute_ms": round(tr, 3), "stored_ms": round(ts, 3),
+            "stored_form": "PyTorch autograd of the same compositing and Eq. 2 distortion (per-sample tensors kept)",
+            "rel_diff": {"rgb": rel(a[0], b[0]), "dist": rel(a[1], b[1]), "grad_density": rel(a[2], b[2]),
+                         "grad_rgb": rel(a[3], b[3])}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -598,6 +676,7 @@ def main():
     ap.add_argument("--cpu-rays", type=int, default=8192)
     ap.add_argument("--rays", type=int, default=8192)
     ap.add_argument("--no-proposal", action="store_true")
+    ap.add_argument("--no-recompute-memory", action="store_true")
     ap.add_argument("--no-ragged", action="store_true")
     ap.add_argument("--no-render-sweep", action="store_true")
     ap.add_argument("--proposal-steps", type=int, default=1500)
@@ -777,6 +856,10 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_render_sweep:
         out["render_batch_sweep"] = render_sweep_leg()
+        torch.cuda.empty_cache()
+    if not args.no_recompute_memory:
+        print("[bench] config 4: recompute-in-backward memory vs stored intermediates", file=sys.stderr, flush=True)
+        out["recompute_memory"] = recompute_memory_leg()
         torch.cuda.empty_cache()
     if not args.no_ragged:
         print("[bench] ragged unbounded batch: schedules", file=sys.stderr, flush=True)
