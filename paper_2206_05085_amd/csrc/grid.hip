@@ -217,8 +217,20 @@ __device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, f
 // wave keeps several independent loads in flight instead of one dependent chain.  The skip
 // is decided per 128-byte line (the 8 lanes holding 8 consecutive groups): a line with any
 // non-zero gradient is read and written whole, its zero-gradient elements written back
-// unchanged, so the memory sees full-line writes instead of masked partial ones.
+// unchanged, so the memory sees full-line writes instead of masked partial ones.  Gradients and
+// moments are read and written nontemporally (streamed past the caches: nothing else in a step
+// reads them again soon), the parameters normally, since the next step's lookups read them back.
 constexpr int ADAM_U = 4;
+
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_nt(float4 *p, float4 a) {
+    const nt_f4 v = {a.x, a.y, a.z, a.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_f4 *>(p));
+}
 
 __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, int64_t n4) {
     adam_bias(a);
@@ -232,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, 
 #pragma unroll
         for (int u = 0; u < ADAM_U; ++u) {
             const int64_t i = i0 + u * stride;
-            g[u] = i < n4 ? G[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+            g[u] = i < n4 ? ld_nt(G + i) : make_float4(0.f, 0.f, 0.f, 0.f);
         }
 #pragma unroll
         for (int u = 0; u < ADAM_U; ++u) {
@@ -244,8 +256,8 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, 
             live[u] = i < n4 && (!a.skip || line);
             if (live[u]) {
                 p[u] = P[i];
-                m[u] = M[i];
-                v[u] = V[i];
+                m[u] = ld_nt(M + i);
+                v[u] = ld_nt(V + i);
             }
         }
 #pragma unroll
@@ -257,9 +269,9 @@ __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, 
             if (!a.skip || g[u].z != 0.f) adam_one(a, g[u].z, p[u].z, m[u].z, v[u].z);
             if (!a.skip || g[u].w != 0.f) adam_one(a, g[u].w, p[u].w, m[u].w, v[u].w);
             P[i] = p[u];
-            M[i] = m[u];
-            V[i] = v[u];
-            if (a.zero) G[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+            st_nt(M + i, m[u]);
+            st_nt(V + i, v[u]);
+            if (a.zero) st_nt(G + i, make_float4(0.f, 0.f, 0.f, 0.f));
         }
     }
     // scalar head [0, head) and tail [head + 4 n4, n)
