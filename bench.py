@@ -588,6 +588,28 @@ def f16_head_leg(ops, torch, wl, batch, steps=30):
             "precision": "FP16 matrix operands (11-bit significands), FP32 accumulation"}
 
 
+def stored_composite(raw, delta, srgb, m, l, shift, hit, R):
+    """Compositing and the distortion loss as plain PyTorch operations on rays of one length N,
+    the way an autograd graph keeps them: alpha = 1 - exp(-softplus(raw + shift) delta), exclusive
+    cumulative product for the transmittance, weights, colour over a white background, and Eq. 2
+    through cumulative sums.  raw, delta: [Rh*N]; srgb: [Rh*N, 3]; m, l: [Rh, N] (normalised
+    midpoints and lengths); hit: indices of the Rh rays with samples among R.  Returns rgb [R, 3]
+    and D [R] (rays without samples: the background, D = 0).  Used as the stored-intermediates
+    baseline of the memory measurement."""
+    import torch
+    import torch.nn.functional as F
+    Rh, N = m.shape
+    a = -torch.expm1(-F.softplus(raw + shift) * delta).view(Rh, N)
+    P = torch.cumprod(1.0 - a, 1)
+    w = a * torch.cat([torch.ones(Rh, 1, device=a.device, dtype=a.dtype), P[:, :-1]], 1)
+    rgb_h = (w.unsqueeze(-1) * srgb.view(Rh, N, 3)).sum(1) + P[:, -1:]
+    W, Q = torch.cumsum(w, 1) - w, torch.cumsum(w * m, 1) - w * m
+    D_h = 2.0 * (w * (m * W - Q)).sum(1) + (w * w * l).sum(1) / 3.0
+    rgb = torch.ones(R, 3, device=a.device, dtype=a.dtype).index_copy(0, hit, rgb_h)
+    D = torch.zeros(R, device=a.device, dtype=a.dtype).index_copy(0, hit, D_h)
+    return rgb, D
+
+
 def recompute_memory_leg(reps=5):
     """Config 4 (the config-2 grids, 16384 rays x 512 samples): device memory and time of one
     render + distortion forward and backward through the hand-written autograd Function, which
@@ -598,7 +620,6 @@ def recompute_memory_leg(reps=5):
     so the two differ only in what the compositing and the distortion loss keep.  Memory is the
     peak allocated above the resident inputs, gradients included."""
     import torch
-    import torch.nn.functional as F
     import synth
     from paper_2206_05085_amd import autograd as ag, ops
     wl = synth.config4()
@@ -627,14 +648,7 @@ def recompute_memory_leg(reps=5):
 
     def stored():
         raw = ag.gather(dens, batch.xyz, box)[:, 0]
-        a = -torch.expm1(-F.softplus(raw + shift) * batch.delta).view(Rh, N)
-        P = torch.cumprod(1.0 - a, 1)
-        w = a * torch.cat([torch.ones(Rh, 1, device="cuda"), P[:, :-1]], 1)
-        rgb_h = (w.unsqueeze(-1) * srgb.view(Rh, N, 3)).sum(1) + P[:, -1:]  # white background
-        W, Q = torch.cumsum(w, 1) - w, torch.cumsum(w * m, 1) - w * m
-        D_h = 2.0 * (w * (m * W - Q)).sum(1) + (w * w * l).sum(1) / 3.0
-        rgb = torch.ones(R, 3, device="cuda").index_copy(0, hit, rgb_h)
-        D = torch.zeros(R, device="cuda").index_copy(0, hit, D_h)
+        rgb, D = stored_composite(raw, batch.delta, srgb, m, l, shift, hit, R)
         (((rgb - tgt) ** 2).mean() + lam * D.mean()).backward()
         return rgb, D
 
