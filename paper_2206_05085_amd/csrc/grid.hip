@@ -218,8 +218,9 @@ __device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, f
 // is decided per 128-byte line (the 8 lanes holding 8 consecutive groups): a line with any
 // non-zero gradient is read and written whole, its zero-gradient elements written back
 // unchanged, so the memory sees full-line writes instead of masked partial ones.  Gradients and
-// moments are read and written nontemporally (streamed past the caches: nothing else in a step
-// reads them again soon), the parameters normally, since the next step's lookups read them back.
+// moments are read and written with the nontemporal (streaming) cache hint, since nothing else in a
+// step reads them again soon; the parameters keep the default policy, since the next step's lookups
+// read them back.
 constexpr int ADAM_U = 4;
 
 typedef float nt_f4 __attribute__((ext_vector_type(4)));
