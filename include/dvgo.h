@@ -13,7 +13,7 @@
  *   whose minimum size is returned by the matching *_size query.
  * Streams:  `stream` is a hipStream_t passed as void* (NULL = the null stream).  Calls are
  *   asynchronous on that stream; argument validation is synchronous and host-side only (it
- *   never reads device memory).
+ *   never reads device memory), except in debug mode (below).
  * Gradients:  gradients into parameter grids and weights are ACCUMULATED (+=), never
  *   overwritten: the caller zeroes them (or lets dvgo_grid_adam_step zero them).  This is the
  *   paper's convention of adding gradients into the tensor between backward and the
@@ -25,7 +25,13 @@
  *   per-sample array; ray_offsets has n_rays+1 non-decreasing entries with ray_offsets[0] = 0
  *   and ray_offsets[n_rays] = n_samples (section 2, uneven numbers of points per ray).
  *   Within a ray s_mid must be non-decreasing (section 2 assumes sorted midpoints).
- *   These two device-side properties are the caller's contract; they are not checked.
+ *   These two device-side properties are the caller's contract.  They are checked on the
+ *   device only in debug mode (dvgo_set_debug, or DVGO_DEBUG=1 in the environment), where
+ *   dvgo_render_forward, dvgo_render_backward and dvgo_distortion_loss first run
+ *   dvgo_validate_samples (synchronously) and return its error; dvgo_validate_samples can also
+ *   be called on its own.  n_samples is at most 715827881 ((2^31)/3 - 1), so that the
+ *   kernels' 32-bit element indices of [S,3] rows cannot overflow; larger batches return
+ *   DVGO_ERR_RANGE.
  * Structs carry `struct_size` = sizeof(struct) for ABI evolution; a mismatch is DVGO_ERR_ABI.
  */
 #ifndef DVGO_H
@@ -38,13 +44,14 @@
 extern "C" {
 #endif
 
-#define DVGO_ABI_VERSION 5
+#define DVGO_ABI_VERSION 6
 
 enum {
     DVGO_OK = 0,
     DVGO_ERR_NULL = -1,        /* a required pointer is NULL */
     DVGO_ERR_SHAPE = -2,       /* inconsistent or unsupported sizes */
     DVGO_ERR_RANGE = -3,       /* a size or index exceeds what the kernels address */
+    DVGO_ERR_UNSORTED = -4,    /* debug validation: s_mid decreases within a ray */
     DVGO_ERR_WORKSPACE = -5,   /* workspace / state buffer smaller than its query says */
     DVGO_ERR_HIP = -6,         /* a HIP runtime call (launch) failed */
     DVGO_ERR_UNSUPPORTED = -7, /* a mode or parameter value that is not implemented */
@@ -138,7 +145,7 @@ typedef struct dvgo_render_params {
  * scaled FP16 planes, the view encodings of the rays, the first ray of every 32-sample tile).
  * Nonzero = the workspace already holds that preparation and the call skips it: allowed only
  * when the last call on this workspace was a dvgo_mlp_prepare / dvgo_mlp_forward /
- * dvgo_mlp_backward / dvgo_mlp_backward_scatter with the same weights (unchanged since), n_rays,
+ * dvgo_mlp_backward with the same weights (unchanged since), n_rays,
  * ray_offsets, dirs and n_samples, e.g. the backward that follows the forward of one step.
  * The library cannot check this; a stale workspace gives wrong results, not an error. */
 enum { DVGO_MLP_SPLIT_F16 = 0, DVGO_MLP_F16 = 1 };
@@ -156,6 +163,28 @@ typedef struct dvgo_color_mlp {
 
 int dvgo_abi_version(void);
 const char *dvgo_last_error(void);
+
+/* Shift b of the density activation sigma = softplus(raw + b) (section 3's density-to-alpha
+ * step): the value for which raw = 0 gives alpha = 1 - exp(-sigma delta_ref) = alpha_init, i.e.
+ * b = ln((1 - alpha_init)^(-1/delta_ref) - 1) (section 5.4 sets alpha_init = 1e-4 at a
+ * 0.5-voxel step, b = -8.517).  Host-only, in double.  Errors: DVGO_ERR_NULL (shift),
+ * DVGO_ERR_RANGE (alpha_init outside (0, 1), delta_ref not positive). */
+int dvgo_act_shift(double alpha_init, double delta_ref, double *shift);
+
+/* Debug mode: on != 0 makes dvgo_render_forward, dvgo_render_backward and dvgo_distortion_loss
+ * validate their batch on the device first (dvgo_validate_samples: synchronous, not for graph
+ * capture).  The initial setting comes from the environment variable DVGO_DEBUG (non-zero =
+ * on).  Returns the previous setting (0 or 1). */
+int dvgo_set_debug(int32_t on);
+
+/* Checks a ragged batch on the device (its ray_offsets and s_mid; the other arrays are not
+ * read): ray_offsets[0] == 0, ray_offsets never decreases and ray_offsets[n_rays] ==
+ * n_samples (else DVGO_ERR_SHAPE), and s_mid is non-decreasing within every ray (section 2's
+ * sorted midpoints; else DVGO_ERR_UNSORTED; a NaN midpoint counts as out of order).  Each ray's
+ * samples are read only after its own offsets were found in range.  Synchronises `stream` to
+ * read the verdict; concurrent calls in one process take turns.  Other errors: DVGO_ERR_NULL,
+ * DVGO_ERR_ABI, DVGO_ERR_HIP. */
+int dvgo_validate_samples(const dvgo_samples *s, void *stream);
 
 /* Size in bytes of the per-batch state that dvgo_render_forward saves for
  * dvgo_render_backward (per-ray halt index and per-64-sample chunk checkpoints). */
@@ -201,12 +230,16 @@ int dvgo_ray_schedule(int32_t n_rays, const int32_t *ray_offsets, int32_t *order
 /* Project autotuner for the render kernels: times forward + backward of this batch for a set
  * of launch shapes (waves per block x persistent grid sizes, honouring p->ray_list) with HIP
  * events on `stream` and returns the fastest in *waves_per_block, *grid_waves (and its time
- * in *ms, may be NULL).  Results are cached per (colour mode, rays, samples, list) in the
- * process; a cached shape returns without timing.  Synchronises the stream and allocates
- * scratch outputs: not for use inside graph capture.  Parameter gradients are untouched. */
+ * in *ms, may be NULL).  sample_density_grad != 0 times the backward variant that writes
+ * per-sample density gradients (grad_sample_density of dvgo_render_backward, for a caller that
+ * scatters them itself); 0 times the variant that scatters into the density grid in the kernel.
+ * Results are cached per (colour mode, distortion, rays, samples, ray list, halt_T, warps of
+ * the grids, backward variant) in the process; a cached shape returns without timing.
+ * Synchronises the stream and allocates scratch outputs: not for use inside graph capture.
+ * Parameter gradients are untouched. */
 int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
-                         const dvgo_grid *color, const float *sample_rgb, int32_t *waves_per_block,
-                         int32_t *grid_waves, float *ms, void *stream);
+                         const dvgo_grid *color, const float *sample_rgb, int32_t sample_density_grad,
+                         int32_t *waves_per_block, int32_t *grid_waves, float *ms, void *stream);
 
 /* Size of the workspace dvgo_distortion_loss needs when grad_w is requested. */
 int dvgo_distortion_workspace_size(int32_t n_rays, int64_t n_samples, size_t *bytes);
@@ -336,17 +369,6 @@ int dvgo_mlp_backward_partials(const dvgo_color_mlp *m, int32_t n_rays, const in
                                size_t ws_bytes, void *stream);
 int dvgo_mlp_reduce_grads(const dvgo_color_mlp *m, int32_t n_rays, int64_t n_samples, void *ws, size_t ws_bytes,
                           void *stream);
-
-/* dvgo_mlp_backward with the feature gradient scattered straight into the feature grid:
- * feat_grid->grad += trilinear^T(d loss / d feat) at the points xyz [S,3] (the points the
- * features were gathered at), instead of writing grad_feat.  The scatter runs inside the
- * backward kernel while its matrix work proceeds; samples in the same cell as their
- * predecessor are summed before the atomics.  feat_grid: in_feat channels, no warp (a warped
- * grid returns DVGO_ERR_UNSUPPORTED; use dvgo_mlp_backward + dvgo_grid_scatter).  Same
- * workspace and weight-gradient outputs as dvgo_mlp_backward. */
-int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
-                              int64_t n_samples, const float *feat, const float *grad_rgb, const dvgo_grid *feat_grid,
-                              const float *xyz, void *ws, size_t ws_bytes, void *stream);
 
 /* Loss head: loss[0] = (1/(3R)) sum ||rgb_r - target_r||^2 + dist_weight (1/R) sum dist_r
  * (dist may be NULL: no distortion term); grad_rgb [R,3] and grad_dist [R] (may be NULL)

@@ -299,18 +299,6 @@ def mlp_forward(mlp, offs, dirs, feat, F=4, half=False):
     return rgb
 
 
-def mlp_margin(mlp, offs, dirs, feat, F=4):
-    """Per-sample relative distance of the colour head's hidden pre-activations from 0."""
-    keep = _Keep()
-    feat = keep(_c(feat, np.float64))
-    P = _mlp_struct(mlp, keep, feat.shape[1], F)
-    offs = keep(_c(offs, np.int32))
-    dirs = keep(_c(dirs, np.float32))
-    out = np.zeros(feat.shape[0])
-    lib().orc_mlp_margin(C.byref(P), C.c_int32(offs.shape[0] - 1), _ptr(offs), _ptr(dirs), _ptr(feat), _ptr(out))
-    return out
-
-
 def mlp_kink_slack(mlp, offs, dirs, feat, grad_rgb, thr=1e-5, F=4, half=False):
     """Per-element slack of the colour-head gradients at ReLU kinks (see orc_mlp_kink_slack).
     Returns (slack_feat [S,C], [W1, W2, W3] slacks, [b1, b2, b3] slacks)."""

@@ -19,6 +19,7 @@
  * can check each line against the paper.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -535,48 +536,6 @@ static void mlp_backward_range(const orc_mlp *P, int32_t R, const int32_t *offs,
     free(x); free(z1); free(h1); free(z2); free(h2); free(d2); free(d1);
 }
 
-/* Distance of every sample from the colour head's ReLU kinks: the smallest |z| / scale
- * over both hidden layers, where scale = |b| + sum |W x| is the magnitude the float32
- * pre-activation is rounded against.  Below ~1e-5 a float32 evaluation may switch the unit
- * the other way than float64 does, a non-differentiable point of the loss. */
-void orc_mlp_margin(const orc_mlp *P, int32_t R, const int32_t *offs, const float *dirs, const double *feat,
-                    double *margin)
-{
-    int64_t S = offs[R];
-    int I = P->C + 3 + 6 * P->F, H = P->H;
-#pragma omp parallel
-    {
-        double *x = malloc(sizeof(double) * I), *h1 = malloc(sizeof(double) * H);
-#pragma omp for schedule(static)
-        for (int64_t k = 0; k < S; ++k) {
-            int64_t r = find_ray(R, offs, k);
-            for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
-            view_pe(dirs + 3 * r, P->F, x + P->C);
-            double mg = INFINITY;
-            for (int i = 0; i < H; ++i) {
-                double z = P->b1[i], a = fabs((double)P->b1[i]);
-                for (int j = 0; j < I; ++j) {
-                    z += (double)P->W1[i * I + j] * x[j];
-                    a += fabs((double)P->W1[i * I + j] * x[j]);
-                }
-                h1[i] = z > 0 ? z : 0.0;
-                if (a > 0 && fabs(z) / a < mg) mg = fabs(z) / a;
-            }
-            for (int i = 0; i < H; ++i) {
-                double z = P->b2[i], a = fabs((double)P->b2[i]);
-                for (int j = 0; j < H; ++j) {
-                    z += (double)P->W2[i * H + j] * h1[j];
-                    a += fabs((double)P->W2[i * H + j] * h1[j]);
-                }
-                if (a > 0 && fabs(z) / a < mg) mg = fabs(z) / a;
-            }
-            margin[k] = mg;
-        }
-        free(x);
-        free(h1);
-    }
-}
-
 /* One sample's contribution to every colour-head gradient, with the ReLU mask of one
  * hidden unit optionally inverted (flip_layer 1 or 2, unit flip_unit; 0 = none).
  * out = [dfeat (C) | dW1 | db1 | dW2 | db2 | dW3 | db3]. */
@@ -637,43 +596,59 @@ void orc_mlp_kink_slack(const orc_mlp *P, int32_t R, const int32_t *offs, const 
     int64_t S = offs[R];
     int I = P->C + 3 + 6 * P->F, H = P->H;
     int64_t np = (int64_t)H * I + H + (int64_t)H * H + H + 3 * H + 3, nout = P->C + np;
-    double *x = malloc(sizeof(double) * I), *a = malloc(sizeof(double) * nout), *b = malloc(sizeof(double) * nout);
-    double *z1 = malloc(sizeof(double) * H), *h1 = malloc(sizeof(double) * H);
-    for (int64_t k = 0; k < S; ++k) {
-        int64_t r = find_ray(R, offs, k);
-        for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
-        view_pe(dirs + 3 * r, P->F, x + P->C);
-        int computed = 0;
-        for (int layer = 1; layer <= 2; ++layer)
-            for (int i = 0; i < H; ++i) {
-                double z, mag;
-                if (layer == 1) {
-                    z = P->b1[i];
-                    mag = fabs((double)P->b1[i]);
-                    for (int j = 0; j < I; ++j) {
-                        const double t = opnd(P, P->W1[i * I + j]) * opnd(P, x[j]);
-                        z += t;
-                        mag += fabs(t);
-                    }
-                    z1[i] = z;
-                    h1[i] = z > 0 ? z : 0.0;
-                } else {
-                    z = P->b2[i];
-                    mag = fabs((double)P->b2[i]);
-                    for (int j = 0; j < H; ++j) {
-                        const double t = opnd(P, P->W2[i * H + j]) * opnd(P, h1[j]);
-                        z += t;
-                        mag += fabs(t);
-                    }
-                }
-                if (!(mag > 0 && fabs(z) < thr * mag)) continue;
-                if (!computed) { mlp_sample_grads(P, x, grad_rgb + 3 * k, 0, 0, a); computed = 1; }
-                mlp_sample_grads(P, x, grad_rgb + 3 * k, layer, i, b);
-                for (int c = 0; c < P->C; ++c) slack_feat[k * P->C + c] += fabs(b[c] - a[c]);
-                for (int64_t q = 0; q < np; ++q) slack_par[q] += fabs(b[P->C + q] - a[P->C + q]);
-            }
+    int nt = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        nt = omp_get_num_threads();
     }
-    free(x); free(a); free(b); free(z1); free(h1);
+    /* one parameter-slack buffer per thread, added in thread order at the end */
+    double *par = calloc((size_t)nt * (size_t)np, sizeof(double));
+#pragma omp parallel
+    {
+        double *x = malloc(sizeof(double) * I), *a = malloc(sizeof(double) * nout), *b = malloc(sizeof(double) * nout);
+        double *z1 = malloc(sizeof(double) * H), *h1 = malloc(sizeof(double) * H);
+        double *mine = par + (size_t)omp_get_thread_num() * (size_t)np;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t k = 0; k < S; ++k) {
+            int64_t r = find_ray(R, offs, k);
+            for (int c = 0; c < P->C; ++c) x[c] = feat[k * P->C + c];
+            view_pe(dirs + 3 * r, P->F, x + P->C);
+            int computed = 0;
+            for (int layer = 1; layer <= 2; ++layer)
+                for (int i = 0; i < H; ++i) {
+                    double z, mag;
+                    if (layer == 1) {
+                        z = P->b1[i];
+                        mag = fabs((double)P->b1[i]);
+                        for (int j = 0; j < I; ++j) {
+                            const double t = opnd(P, P->W1[i * I + j]) * opnd(P, x[j]);
+                            z += t;
+                            mag += fabs(t);
+                        }
+                        z1[i] = z;
+                        h1[i] = z > 0 ? z : 0.0;
+                    } else {
+                        z = P->b2[i];
+                        mag = fabs((double)P->b2[i]);
+                        for (int j = 0; j < H; ++j) {
+                            const double t = opnd(P, P->W2[i * H + j]) * opnd(P, h1[j]);
+                            z += t;
+                            mag += fabs(t);
+                        }
+                    }
+                    if (!(mag > 0 && fabs(z) < thr * mag)) continue;
+                    if (!computed) { mlp_sample_grads(P, x, grad_rgb + 3 * k, 0, 0, a); computed = 1; }
+                    mlp_sample_grads(P, x, grad_rgb + 3 * k, layer, i, b);
+                    for (int c = 0; c < P->C; ++c) slack_feat[k * P->C + c] += fabs(b[c] - a[c]);
+                    for (int64_t q = 0; q < np; ++q) mine[q] += fabs(b[P->C + q] - a[P->C + q]);
+                }
+        }
+        free(x); free(a); free(b); free(z1); free(h1);
+    }
+    for (int t = 0; t < nt; ++t)
+        for (int64_t q = 0; q < np; ++q) slack_par[q] += par[(size_t)t * (size_t)np + q];
+    free(par);
 }
 
 /* Magnitudes the colour head's outputs are conditioned on: the forward and backward passes

@@ -2,7 +2,7 @@
 fields (Sun, Sun & Chen, arXiv 2206.05085): trilinear gathers from dense grids, the
 density-to-alpha activation, front-to-back compositing, the O(N) distortion loss, the
 hand-written backward with scatter-add into the grids, the fused Adam step and the colour
-MLP on FP32 matrix cores.
+MLP on FP16 matrix cores with split (hi + lo) operands, which gives FP32-grade products.
 
 The kernels live in ``libdvgo.so`` (C-ABI declared in ``include/dvgo.h``); ``ops`` is its
 thin binding, ``autograd`` wraps it as torch.autograd.Function, ``step`` drives a whole

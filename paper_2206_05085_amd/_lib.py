@@ -9,11 +9,11 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdvgo.so")
-ABI_VERSION = 5
+ABI_VERSION = 6
 
 VP = C.c_void_p
 OK = 0
-ERRORS = {-1: "ERR_NULL", -2: "ERR_SHAPE", -3: "ERR_RANGE", -5: "ERR_WORKSPACE", -6: "ERR_HIP",
+ERRORS = {-1: "ERR_NULL", -2: "ERR_SHAPE", -3: "ERR_RANGE", -4: "ERR_UNSORTED", -5: "ERR_WORKSPACE", -6: "ERR_HIP",
           -7: "ERR_UNSUPPORTED", -8: "ERR_ABI"}
 COLOR_GRID, COLOR_SAMPLES, COLOR_NONE = 0, 1, 2
 WARP_NONE, WARP_CONTRACT_INF, WARP_CONTRACT_L2 = 0, 1, 2
@@ -75,11 +75,14 @@ _PG, _PS, _PP, _PM = C.POINTER(Grid), C.POINTER(Samples), C.POINTER(RenderParams
 SIGNATURES = {
     "dvgo_abi_version": (C.c_int, []),
     "dvgo_last_error": (C.c_char_p, []),
+    "dvgo_act_shift": (C.c_int, [C.c_double, C.c_double, C.POINTER(C.c_double)]),
+    "dvgo_set_debug": (C.c_int, [_I32]),
+    "dvgo_validate_samples": (C.c_int, [_PS, VP]),
     "dvgo_render_state_size": (C.c_int, [_I32, _I64, _SZP]),
     "dvgo_render_forward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_render_backward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, C.c_size_t, VP, VP, VP, VP, VP, VP]),
     "dvgo_ray_schedule": (C.c_int, [_I32, VP, VP, VP, VP]),
-    "dvgo_render_autotune": (C.c_int, [_PP, _PS, _PG, _PG, VP, C.POINTER(_I32), C.POINTER(_I32),
+    "dvgo_render_autotune": (C.c_int, [_PP, _PS, _PG, _PG, VP, _I32, C.POINTER(_I32), C.POINTER(_I32),
                                        C.POINTER(C.c_float), VP]),
     "dvgo_distortion_workspace_size": (C.c_int, [_I32, _I64, _SZP]),
     "dvgo_distortion_loss": (C.c_int, [_I32, VP, _I64, VP, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
@@ -100,7 +103,6 @@ SIGNATURES = {
     "dvgo_mlp_backward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward_partials": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_reduce_grads": (C.c_int, [_PM, _I32, _I64, VP, C.c_size_t, VP]),
-    "dvgo_mlp_backward_scatter": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, _PG, VP, VP, C.c_size_t, VP]),
     "dvgo_loss_head": (C.c_int, [_I32, VP, VP, VP, _F, VP, VP, VP, VP]),
     "dvgo_proposal_coarse": (C.c_int, [_PR, _PG, _F, _F, _F, VP, VP, VP]),
     "dvgo_proposal_forward": (C.c_int, [_PQ, _I32, VP, VP, VP, VP, VP]),

@@ -331,6 +331,15 @@ int set_error(int code, const char *fmt, ...);
 int check_hip(hipError_t e, const char *what);
 int make_dev_grid(const dvgo_grid *g, const char *name, DevGrid *out, bool need_grad);
 
+// Debug mode (dvgo_set_debug, or DVGO_DEBUG=1 in the environment): the entry points that take a
+// ragged batch first check it on the device with validate_batch (synchronous).
+bool debug_mode();
+int validate_batch(int32_t n_rays, int64_t n_samples, const int32_t *ray_offsets, const float *s_mid, hipStream_t st);
+
+// Largest batch the per-sample kernels address: 3 * n_samples (the xyz and colour rows) stays
+// below 2^31 in their int32 indices.
+constexpr int64_t MAX_SAMPLES = ((int64_t)1 << 31) / 3 - 1;
+
 // checkpoint slot of the chunk starting at sample c0 of ray r (rays own disjoint slot ranges)
 __host__ __device__ __forceinline__ int64_t ckpt_slot(int64_t beg, int r, int64_t c0) {
     return beg / 64 + r + (c0 - beg) / 64;

@@ -165,8 +165,8 @@ struct MlpArgs {
     int n_params;
     float *gW1, *gb1, *gW2, *gb2, *gW3, *gb3;
     int nblocks;
-    // fused feature gather / scatter: the feature grid (read in the forward; its grad receives
-    // += in the fused backward) and the sample points
+    // fused feature gather: the feature grid the forward looks the features up in, and the
+    // sample points
     DevGrid fg;
     const float *xyz;
     float *feat_out;  // forward with the gather: the features it used, [S][in_feat] (may be NULL)
@@ -654,8 +654,8 @@ __device__ __forceinline__ void store_h4(unsigned char *base, int off, int idx, 
     *reinterpret_cast<h4 *>(reinterpret_cast<_Float16 *>(base + off) + idx) = v;
 }
 
-// Block barrier that orders LDS only: the waves' outstanding global stores and atomics (the
-// fused feature scatter) stay in flight across it instead of being drained at every phase.
+// Block barrier that orders LDS only: the waves' outstanding global stores (the feature
+// gradient rows) stay in flight across it instead of being drained at every phase.
 // No global memory is exchanged between the waves of a block inside the backward kernel.
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
@@ -673,63 +673,6 @@ __device__ __forceinline__ void feat_grad_out(const MlpArgs &a, const float *dfp
             a.grad_feat[(int64_t)s * a.in_feat + c] = dfp[(0 * NT + sl) * DFS + c] + dfp[(1 * NT + sl) * DFS + c] +
                                                       dfp[(2 * NT + sl) * DFS + c] + dfp[(3 * NT + sl) * DFS + c];
     }
-}
-
-// Feature gradient of a finished tile scattered straight into the feature grid's gradient
-// (trilinear adjoint): wave w of a role takes samples 8w..8w+7 of the tile, lane = (sample,
-// corner).  A sample in the same cell as the one before it adds its contribution into that
-// sample's lanes first; the remaining (vertex, 12 values) entries are compacted through the
-// wave's LDS slice `stage` (64 x 13 floats) so that consecutive lanes of each atomic
-// instruction add consecutive channels of one vertex row.
-__device__ __forceinline__ void feat_grad_scatter(const MlpArgs &a, const float *dfp, int pbase, int w, int ln,
-                                                  float *stage) {
-    const int sl = 8 * w + (ln >> 3);
-    const int corner = ln & 7;
-    const int dx = (corner >> 2) & 1, dy = (corner >> 1) & 1, dz = corner & 1;
-    const int s = pbase + sl;
-    const bool valid = s < a.S;
-    Cell c{0, 0, 0, 0.f, 0.f, 0.f};
-    if (valid) c = cell_of(a.fg, a.xyz[3 * (int64_t)s], a.xyz[3 * (int64_t)s + 1], a.xyz[3 * (int64_t)s + 2]);
-    const float wgt = valid ? corner_weight(c, dx, dy, dz) : 0.f;
-    float v[12];
-#pragma unroll
-    for (int ch = 0; ch < 12; ++ch)
-        v[ch] = (valid && ch < a.in_feat)
-                    ? wgt * (dfp[(0 * NT + sl) * DFS + ch] + dfp[(1 * NT + sl) * DFS + ch] + dfp[(2 * NT + sl) * DFS + ch] +
-                             dfp[(3 * NT + sl) * DFS + ch])
-                    : 0.f;
-    const int key = valid ? (c.ix * a.fg.n[1] + c.iy) * a.fg.n[2] + c.iz : -1;
-    const int prev = __shfl_up(key, 8, 64);
-    const bool head = valid && ((ln >> 3) == 0 || prev != key);
-    // add the following samples of the same cell (same corner = same vertex)
-    bool open = head;
-#pragma unroll
-    for (int k = 1; k < 8; ++k) {
-        const int src = ln + 8 * k < 64 ? ln + 8 * k : ln;
-        const int nk = __shfl(key, src, 64);
-        open = open && ln + 8 * k < 64 && nk == key;
-#pragma unroll
-        for (int ch = 0; ch < 12; ++ch) {
-            const float t = __shfl(v[ch], src, 64);
-            if (open) v[ch] += t;
-        }
-        if (__ballot(open) == 0ull) break;
-    }
-    const unsigned long long hm = __ballot(head);
-    const int nh = __popcll(hm);
-    if (head) {
-        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(hm >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)hm, 0u));
-        reinterpret_cast<int *>(stage)[rank] = (c.ix + dx) * a.fg.sx + (c.iy + dy) * a.fg.sy + (c.iz + dz) * a.fg.cs;
-#pragma unroll
-        for (int ch = 0; ch < 12; ++ch) stage[64 + rank * 12 + ch] = v[ch];
-    }
-    // LDS-only ordering (the wave's own slice); the atomics stay in flight
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local");
-    for (int i = ln; i < nh * 12; i += 64) {
-        const int e = i / 12, ch = i - e * 12;
-        if (ch < a.in_feat) unsafeAtomicAdd(a.fg.grad + reinterpret_cast<const int *>(stage)[e] + ch, stage[64 + i]);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup", "local");
 }
 
 // Per-sample quantities every wave derives identically from LDS (columns c: sample 16c + j)
@@ -810,7 +753,7 @@ __device__ __forceinline__ void rescale(v4f (&acc)[2][N], int &F, int f) {
     }
 }
 
-template <bool SPLIT, bool SCAT>
+template <bool SPLIT>
 __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char sm[B_END];
     copy_to_lds(sm, a.img + IMG_B1, BS);
@@ -1046,10 +989,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
             }
             // feature gradient of the previous tile (its partials came from the C waves' phase A)
-            if (it > 0) {
-                if (SCAT) feat_grad_scatter(a, dfp, (tile - (int)gridDim.x) * NT, w, ln, h2s + w * 64 * 13);
-                else feat_grad_out(a, dfp, (tile - (int)gridDim.x) * NT, tid);
-            }
+            if (it > 0) feat_grad_out(a, dfp, (tile - (int)gridDim.x) * NT, tid);
             lds_barrier();
         }
         // the C side's last A/B pair
@@ -1272,7 +1212,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 const GradExp ge = grad_exp(z3p, gr_b + pb * NT * 4, b3, meta, j);
                 rescale<3>(dW1, F1, tile_frame(se.ex, ge.k1));
                 F2 = min(F2, tile_frame(se.e1, ge.k2));  // as rescale<8> moves it on the P side
-                if (SCAT) dw3_step(ge.dz3, j, q);
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     pg2[c] = ge.g2[c];
@@ -1312,10 +1251,9 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             lds_barrier();
             // ---- D: the next tile's inputs -> x planes (the P waves write the previous tile's
             //      feature gradient meanwhile); dW3 += dz3 h2^T of this tile (h2 stays until the
-            //      P waves' next layer 2; the fused scatter uses that space in D, so there the
-            //      sums were taken in C)
+            //      P waves' next layer 2)
             if (next) stage_tile(pb ^ 1);
-            if (!SCAT) dw3_step(tdz3, j, q);
+            dw3_step(tdz3, j, q);
             lds_barrier();
             pbase = tile * NT;
         }
@@ -1324,8 +1262,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         lds_barrier();
         if (pbase >= 0) {
             dw1_step((it - 1) & 1);
-            if (SCAT) feat_grad_scatter(a, dfp, pbase, w, lane(), h2s + w * 64 * 13);
-            else feat_grad_out(a, dfp, pbase, ct);
+            feat_grad_out(a, dfp, pbase, ct);
         }
         lds_barrier();
         // ---- partial gradients of the C role: W1, b1, b2, W3, b3
@@ -1570,9 +1507,9 @@ int mlp_backward_impl(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ra
         if (rc) return rc;
     }
     if (m->precision == DVGO_MLP_F16)
-        hipLaunchKernelGGL((mlp_bwd_kernel<false, false>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
+        hipLaunchKernelGGL((mlp_bwd_kernel<false>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     else
-        hipLaunchKernelGGL((mlp_bwd_kernel<true, false>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
+        hipLaunchKernelGGL((mlp_bwd_kernel<true>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     rc = check_hip(hipGetLastError(), "mlp_bwd_kernel launch");
     if (rc || !reduce) return rc;
     return launch_reduce(a, st);
@@ -1616,35 +1553,4 @@ extern "C" int dvgo_mlp_reduce_grads(const dvgo_color_mlp *m, int32_t n_rays, in
     a.partial = (float *)((char *)ws + off_part);
     a.nblocks = bwd_blocks(n_samples);
     return launch_reduce(a, (hipStream_t)stream);
-}
-
-extern "C" int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
-                                         const float *dirs, int64_t n_samples, const float *feat,
-                                         const float *grad_rgb, const dvgo_grid *feat_grid, const float *xyz,
-                                         void *ws, size_t ws_bytes, void *stream) {
-    MlpArgs a;
-    int rc = setup(m, n_rays, ray_offsets, dirs, n_samples, feat, ws, ws_bytes, true, a);
-    if (rc) return rc;
-    rc = make_dev_grid(feat_grid, "feature grid", &a.fg, true);
-    if (rc) return rc;
-    if (feat_grid->channels != m->in_feat)
-        return set_error(DVGO_ERR_SHAPE, "feature grid channels (%d) != in_feat (%d)", feat_grid->channels, m->in_feat);
-    if (feat_grid->warp != DVGO_WARP_NONE)
-        return set_error(DVGO_ERR_UNSUPPORTED, "the fused scatter takes unwarped feature grids");
-    if (n_samples == 0) return DVGO_OK;
-    if (!grad_rgb || !xyz) return set_error(DVGO_ERR_NULL, "grad_rgb or xyz is NULL");
-    a.grad_rgb = grad_rgb;
-    a.xyz = xyz;
-    hipStream_t st = (hipStream_t)stream;
-    if (!m->prepared) {
-        rc = launch_prep(a, st);
-        if (rc) return rc;
-    }
-    if (m->precision == DVGO_MLP_F16)
-        hipLaunchKernelGGL((mlp_bwd_kernel<false, true>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
-    else
-        hipLaunchKernelGGL((mlp_bwd_kernel<true, true>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
-    rc = check_hip(hipGetLastError(), "mlp_bwd_kernel launch");
-    if (rc) return rc;
-    return launch_reduce(a, st);
 }

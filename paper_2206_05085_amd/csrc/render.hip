@@ -299,7 +299,8 @@ int check_samples(const dvgo_samples *s) {
     if (!s) return set_error(DVGO_ERR_NULL, "samples is NULL");
     if (s->struct_size != sizeof(dvgo_samples)) return set_error(DVGO_ERR_ABI, "dvgo_samples.struct_size mismatch");
     if (s->n_rays < 0 || s->n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays or n_samples");
-    if (s->n_samples >= (int64_t)1 << 31) return set_error(DVGO_ERR_RANGE, "n_samples must be < 2^31");
+    if (s->n_samples > MAX_SAMPLES)
+        return set_error(DVGO_ERR_RANGE, "n_samples must be at most %lld", (long long)MAX_SAMPLES);
     if (!s->ray_offsets) return set_error(DVGO_ERR_NULL, "ray_offsets is NULL");
     if (s->n_samples > 0 && (!s->xyz || !s->delta || !s->s_mid || !s->s_len))
         return set_error(DVGO_ERR_NULL, "a per-sample array is NULL");
@@ -440,6 +441,10 @@ extern "C" int dvgo_render_forward(const dvgo_render_params *p, const dvgo_sampl
     a.dist = dist;
     a.sample_w = sample_w;
     split_state(state, s->n_rays, &a.halt_idx, &a.ckpt);
+    if (debug_mode()) {
+        rc = validate_batch(s->n_rays, s->n_samples, s->ray_offsets, s->s_mid, (hipStream_t)stream);
+        if (rc) return rc;
+    }
     if (a.n_list == 0) return DVGO_OK;
     return launch_fwd(p, a, (hipStream_t)stream);
 }
@@ -465,6 +470,10 @@ extern "C" int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samp
     a.grad_srgb = grad_sample_rgb;
     a.grad_raw = grad_sample_density;
     split_state(const_cast<void *>(state), s->n_rays, &a.halt_idx, &a.ckpt);
+    if (debug_mode()) {
+        rc = validate_batch(s->n_rays, s->n_samples, s->ray_offsets, s->s_mid, (hipStream_t)stream);
+        if (rc) return rc;
+    }
     if (a.n_list == 0) return DVGO_OK;
     return launch_bwd(p, a, (hipStream_t)stream);
 }
@@ -511,9 +520,13 @@ struct TuneKey {
     long long n_samples;
     const void *list;
     int n_list;
+    float halt_T;
+    int dens_warp, col_warp;
+    int sample_grad;  // the backward writes per-sample density gradients (no in-kernel scatter)
     bool operator<(const TuneKey &o) const {
-        return std::tie(mode, want_dist, n_rays, n_samples, list, n_list) <
-               std::tie(o.mode, o.want_dist, o.n_rays, o.n_samples, o.list, o.n_list);
+        return std::tie(mode, want_dist, n_rays, n_samples, list, n_list, halt_T, dens_warp, col_warp, sample_grad) <
+               std::tie(o.mode, o.want_dist, o.n_rays, o.n_samples, o.list, o.n_list, o.halt_T, o.dens_warp,
+                        o.col_warp, o.sample_grad);
     }
 };
 struct TuneVal {
@@ -535,14 +548,16 @@ extern "C" int dvgo_ray_schedule(int32_t n_rays, const int32_t *ray_offsets, int
 }
 
 extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
-                                    const dvgo_grid *color, const float *sample_rgb, int32_t *waves_per_block,
-                                    int32_t *grid_waves, float *ms, void *stream) {
+                                    const dvgo_grid *color, const float *sample_rgb, int32_t sample_density_grad,
+                                    int32_t *waves_per_block, int32_t *grid_waves, float *ms, void *stream) {
     RenderArgs a;
     int rc = fill_render_args(p, s, density, color, sample_rgb, false, a);
     if (rc) return rc;
     if (p->color_mode == DVGO_COLOR_NONE) return set_error(DVGO_ERR_UNSUPPORTED, "autotune needs a colour mode");
     if (!waves_per_block || !grid_waves) return set_error(DVGO_ERR_NULL, "output pointers are NULL");
-    const TuneKey key{p->color_mode, p->want_dist, s->n_rays, (long long)s->n_samples, p->ray_list, a.n_list};
+    const int sg = sample_density_grad ? 1 : 0;
+    const TuneKey key{p->color_mode, p->want_dist, s->n_rays, (long long)s->n_samples, p->ray_list, a.n_list,
+                      p->halt_T, a.dens.warp, p->color_mode == DVGO_COLOR_GRID ? a.col.warp : 0, sg};
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(key);
@@ -560,7 +575,8 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
     const size_t n_dens = (size_t)density->nx * density->ny * density->nz * density->ch_stride;
     const size_t n_col = color ? (size_t)color->nx * color->ny * color->nz * color->ch_stride : 0;
     float *buf = nullptr;
-    const size_t nf = (size_t)R * 3 + 2 * (size_t)R + (size_t)R * 3 + 2 * (size_t)R + n_dens + n_col + (size_t)S * 3;
+    const size_t nf = (size_t)R * 3 + 2 * (size_t)R + (size_t)R * 3 + 2 * (size_t)R + n_dens + n_col + (size_t)S * 3 +
+                      (sg ? (size_t)S : 0);
     void *state = nullptr;
     const size_t sb = state_bytes(R, S);
     if (hipMalloc(&buf, nf * sizeof(float)) != hipSuccess || hipMalloc(&state, sb) != hipSuccess) {
@@ -568,7 +584,7 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
         return set_error(DVGO_ERR_HIP, "autotune scratch allocation failed");
     }
     float *rgb = buf, *T = rgb + 3 * (size_t)R, *dist = T + R, *grgb = dist + R, *gdist = grgb + 3 * (size_t)R,
-          *gT = gdist + R, *gden = gT + R, *gcol = gden + n_dens, *gs = gcol + n_col;
+          *gT = gdist + R, *gden = gT + R, *gcol = gden + n_dens, *gs = gcol + n_col, *graw = gs + (size_t)S * 3;
     // the first HIP failure below is kept in rc; later steps are skipped, the scratch is freed
     auto ck = [&rc](hipError_t e, const char *what) {
         if (!rc && e != hipSuccess) rc = check_hip(e, what);
@@ -587,6 +603,7 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
     fa.sample_w = nullptr;
     split_state(state, R, &fa.halt_idx, &fa.ckpt);
     if (!rc) rc = fill_render_args(p, s, &dg, color ? &cg : nullptr, sample_rgb, true, ba);
+    ba.grad_raw = sg ? graw : nullptr;  // the caller's backward variant: per-sample gradients or in-kernel scatter
     ba.T_in = T;
     ba.grad_rgb = grgb;
     ba.grad_dist = p->want_dist ? gdist : nullptr;
@@ -648,7 +665,7 @@ extern "C" int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, 
                                     const float *s_mid, const float *s_len, float *loss, const float *grad_loss,
                                     float *grad_w, void *ws, size_t ws_bytes, void *stream) {
     if (n_rays < 0 || n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays or n_samples");
-    if (n_samples >= (int64_t)1 << 31) return set_error(DVGO_ERR_RANGE, "n_samples must be < 2^31");
+    if (n_samples > MAX_SAMPLES) return set_error(DVGO_ERR_RANGE, "n_samples must be at most %lld", (long long)MAX_SAMPLES);
     if (n_rays == 0) return DVGO_OK;
     if (!ray_offsets) return set_error(DVGO_ERR_NULL, "ray_offsets is NULL");
     if (n_samples > 0 && (!w || !s_mid || !s_len)) return set_error(DVGO_ERR_NULL, "w, s_mid or s_len is NULL");
@@ -659,6 +676,10 @@ extern "C" int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, 
     size_t need = (size_t)ckpt_count(n_rays, n_samples) * sizeof(float2);
     if (bwd && (!ws || ws_bytes < need)) return set_error(DVGO_ERR_WORKSPACE, "workspace too small (%zu < %zu)",
                                                            ws_bytes, need);
+    if (debug_mode()) {
+        const int rc = validate_batch(n_rays, n_samples, ray_offsets, s_mid, (hipStream_t)stream);
+        if (rc) return rc;
+    }
     const dim3 grid((n_rays + 3) / 4), block(256);
     hipLaunchKernelGGL(distortion_kernel, grid, block, 0, (hipStream_t)stream, n_rays, ray_offsets, w, s_mid, s_len,
                        loss, bwd ? grad_loss : nullptr, bwd ? grad_w : nullptr, (float2 *)ws);

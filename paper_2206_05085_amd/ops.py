@@ -4,7 +4,6 @@ device pointers, the current HIP stream); all arithmetic runs in the HIP kernels
 """
 from __future__ import annotations
 
-import math
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -14,11 +13,11 @@ from . import _lib
 from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16, WARP_CONTRACT_INF, WARP_CONTRACT_L2, WARP_NONE, ColorMLP, Grid,
                    Proposal, Rays, RenderParams, Sampler, Samples, call)
 
-__all__ = ["act_shift", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
+__all__ = ["act_shift", "set_debug", "validate_samples", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
            "grid_scatter", "grid_resample", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_prepare", "mlp_forward", "mlp_forward_gather", "mlp_backward",
-           "mlp_backward_partials", "mlp_reduce_grads", "mlp_backward_scatter", "loss_head",
+           "mlp_backward_partials", "mlp_reduce_grads", "loss_head",
            "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
            "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2",
            "MLP_SPLIT_F16", "MLP_F16"]
@@ -50,8 +49,25 @@ def _chk(t, name, dtype=torch.float32, numel=None, last=None):
 
 def act_shift(alpha_init: float = 1e-4, delta_ref: float = 0.5) -> float:
     """Shift b of sigma = softplus(raw + b) such that raw = 0 gives alpha_init at a step of
-    delta_ref voxels (the initial-alpha setting of section 5.4)."""
-    return math.log(math.expm1(-math.log1p(-alpha_init) / delta_ref))
+    delta_ref voxels (the initial-alpha setting of section 5.4); computed by dvgo_act_shift."""
+    import ctypes
+    out = ctypes.c_double()
+    call("dvgo_act_shift", float(alpha_init), float(delta_ref), ctypes.byref(out))
+    return out.value
+
+
+def set_debug(on: bool) -> bool:
+    """Debug mode of the library (batches validated on the device before every render and
+    distortion call); returns the previous setting."""
+    return bool(_lib.lib().dvgo_set_debug(1 if on else 0))
+
+
+def validate_samples(batch: "SampleBatch") -> None:
+    """Checks ray_offsets (0 first, non-decreasing, n_samples last) and per-ray sorted s_mid on
+    the device; raises DvgoError (ERR_SHAPE / ERR_UNSORTED) otherwise.  Synchronises."""
+    import ctypes
+    s = batch.struct()
+    call("dvgo_validate_samples", ctypes.byref(s), _stream())
 
 
 @dataclass
@@ -195,8 +211,11 @@ def ray_schedule(ray_offsets, order=None, class_offsets=None):
 
 def render_autotune(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid] = None,
                     sample_rgb: Optional[torch.Tensor] = None, *, act_shift_: float, halt_T: float = 0.0,
-                    bg=(1.0, 1.0, 1.0), want_dist: bool = True, ray_list: Optional[torch.Tensor] = None):
-    """Runs the library's autotuner; returns (Schedule, ms per forward + backward)."""
+                    bg=(1.0, 1.0, 1.0), want_dist: bool = True, ray_list: Optional[torch.Tensor] = None,
+                    sample_density_grad: bool = False):
+    """Runs the library's autotuner; returns (Schedule, ms per forward + backward).
+    sample_density_grad: time the backward that writes per-sample density gradients (the
+    variant a caller that scatters them itself runs) instead of the in-kernel scatter."""
     import ctypes
     mode = COLOR_GRID if color is not None else COLOR_SAMPLES
     sched = Schedule(ray_list=ray_list)
@@ -206,8 +225,8 @@ def render_autotune(batch: SampleBatch, density: DeviceGrid, color: Optional[Dev
     gc = color.struct() if color is not None else None
     wpb, gw, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0)
     call("dvgo_render_autotune", ctypes.byref(p), ctypes.byref(s), ctypes.byref(gd),
-         ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), ctypes.byref(wpb), ctypes.byref(gw),
-         ctypes.byref(ms), _stream())
+         ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), 1 if sample_density_grad else 0,
+         ctypes.byref(wpb), ctypes.byref(gw), ctypes.byref(ms), _stream())
     return Schedule(ray_list, wpb.value, gw.value), ms.value
 
 
@@ -503,24 +522,6 @@ def mlp_reduce_grads(mlp: MLPParams, n_rays: int, n_samples: int, ws):
     import ctypes
     call("dvgo_mlp_reduce_grads", ctypes.byref(mlp.struct(need_grad=True)), int(n_rays), int(n_samples), _p(ws),
          ws.numel(), _stream())
-
-
-def mlp_backward_scatter(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, feat_grid: DeviceGrid, xyz, ws=None,
-                         prepared=False):
-    """MLP backward (parameter gradients +=) with the feature gradient scattered into
-    feat_grid.grad at xyz inside the kernel (no per-sample feature gradient is written)."""
-    import ctypes
-    if prepared and ws is None:
-        raise ValueError("prepared=True needs the workspace of the preceding call")
-    R = ray_offsets.numel() - 1
-    S = feat.shape[0]
-    _chk(grad_rgb, "grad_rgb", numel=3 * S)
-    _chk(xyz, "xyz", numel=3 * S)
-    dev = feat.device
-    ws = _mlp_ws(mlp, R, S, ws, dev)
-    call("dvgo_mlp_backward_scatter", ctypes.byref(mlp.struct(need_grad=True, prepared=prepared)), R, _p(ray_offsets), _p(dirs), S,
-         _p(feat), _p(grad_rgb), ctypes.byref(feat_grid.struct(need_grad=True)), _p(xyz), _p(ws), ws.numel(),
-         _stream())
 
 
 def loss_head(rgb, target, dist, dist_weight, loss=None, grad_rgb=None, grad_dist=None, want_loss=True,

@@ -23,7 +23,7 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, concurrent=True, fused_scatter=False,
+                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, concurrent=True,
                  fused_gather=True, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
@@ -41,9 +41,6 @@ class TrainStep:
         colour head's workspace and sets prepared_ahead, and the next step skips its own; bind(),
         optimise() and the sequential path clear the flag, and an in-place torch write to the MLP
         weights (which bumps their version) makes the next step prepare again.
-        fused_scatter: scatter the feature gradient inside the colour head's backward kernel
-        (unwarped feature grids) instead of writing it and scattering it afterwards; saves the
-        per-sample feature-gradient buffer, but measured slower on the config-2 step (off).
         fused_gather: look the features up inside the colour head's forward kernel (which also
         writes them for the backward) instead of a separate gather kernel (feature rows whose
         channel count is a multiple of 4)."""
@@ -62,7 +59,6 @@ class TrainStep:
         self.prepared_ahead = False  # the colour head's workspace holds the preparation for the next step
         self._prep_version = -1  # torch version of the MLP weights that preparation was made from
         self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
-        self.fused = bool(fused_scatter) and self.warp[0] == 0
         self.fused_gather = bool(fused_gather) and feat is not None and np.shape(feat)[-1] % 4 == 0
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
         self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
@@ -157,7 +153,8 @@ class TrainStep:
         colour = self.grid("color") if self.grid_mode else None
         srgb = None if self.grid_mode else self.rgb_s
         self.schedule, ms = ops.render_autotune(b, self.grid("density"), colour, srgb, act_shift_=self.shift,
-                                                halt_T=self.halt_T, bg=self.bg, ray_list=order)
+                                                halt_T=self.halt_T, bg=self.bg, ray_list=order,
+                                                sample_density_grad=self.binned)
         return self.schedule, ms
 
     # --------------------------------------------------------------- stages
@@ -224,10 +221,6 @@ class TrainStep:
 
     def _mlp_backward_and_scatter(self):
         b = self.batch
-        if self.fused:
-            ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
-                                     b.xyz, ws=self.mlp_ws, prepared=True)
-            return
         ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
                          ws=self.mlp_ws, prepared=True)
         # the 12-channel feature gradient keeps the in-wave aggregated scatter: its brick tiles
@@ -292,13 +285,9 @@ class TrainStep:
         ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
                             None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
                             schedule=self.schedule, grad_sample_density=self.g_raw)
-        if self.fused:
-            ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
-                                     b.xyz, ws=self.mlp_ws, prepared=True)
-        else:
-            # the weight-gradient reduction waits on the side stream: only the MLP Adam needs it
-            ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
-                                      grad_feat=self.g_feat_s, prepared=True)
+        # the weight-gradient reduction waits on the side stream: only the MLP Adam needs it
+        ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
+                                  grad_feat=self.g_feat_s, prepared=True)
         side.wait_stream(main)
         with torch.cuda.stream(side):
             if self.fused_gather:
@@ -307,16 +296,14 @@ class TrainStep:
             if self.tv is not None:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
             self._adam("density", self.lr_grid, True)
-            if not self.fused:
-                ops.mlp_reduce_grads(self.mlp, b.n_rays, b.n_samples, self.mlp_ws)
+            ops.mlp_reduce_grads(self.mlp, b.n_rays, b.n_samples, self.mlp_ws)
             self._adam("mlp_flat", self.lr_mlp, False)
             if self.fused_gather:
                 # the next step's preparation, from the updated weights (main reads the workspace
                 # again only after the join)
                 ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
             ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
-        if not self.fused:
-            ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+        ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
         if self.tv is not None:
             ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
         self._adam("feat", self.lr_grid, True)

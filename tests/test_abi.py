@@ -261,3 +261,52 @@ def test_split_backward_entry_points_validate(L):
     assert lib.dvgo_mlp_backward_partials(C.byref(m), 4, None, 256, 100, 256, 256, 256, ws, need.value, None) == -1
     assert lib.dvgo_mlp_backward_partials(C.byref(m), 4, 256, 256, 100, 256, 256, 256, ws, need.value - 1,
                                           None) == -5
+
+
+def test_act_shift_entry_point(L, orc):
+    # the library's b gives alpha_init at delta_ref for raw = 0 (its defining identity, section
+    # 5.4), and equals the oracle's independent value
+    import math
+    lib = L.lib()
+    out = C.c_double()
+    for a0, d0 in ((1e-4, 0.5), (1e-2, 1.0), (0.3, 2.0)):
+        assert lib.dvgo_act_shift(a0, d0, C.byref(out)) == 0
+        b = out.value
+        alpha = -math.expm1(-math.log1p(math.exp(b)) * d0)
+        assert alpha == pytest.approx(a0, rel=1e-12)
+        assert b == pytest.approx(orc.act_shift(a0, d0), rel=1e-14)
+    assert lib.dvgo_act_shift(1e-4, 0.5, C.byref(out)) == 0 and out.value == pytest.approx(-8.517043, abs=1e-6)
+    from paper_2206_05085_amd import ops
+    assert ops.act_shift() == out.value
+    assert lib.dvgo_act_shift(0.0, 0.5, C.byref(out)) == -3
+    assert lib.dvgo_act_shift(1.0, 0.5, C.byref(out)) == -3
+    assert lib.dvgo_act_shift(1e-4, 0.0, C.byref(out)) == -3
+    assert lib.dvgo_act_shift(1e-4, 0.5, None) == -1
+
+
+def test_validation_and_size_limits(L):
+    # host-side parts of the batch checks: NULLs, struct size, the n_samples limit that keeps
+    # 3 * n_samples inside the kernels' int32 indices; the debug switch round-trips
+    lib = L.lib()
+    assert lib.dvgo_validate_samples(None, None) == -1
+    s = L.Samples()
+    s.struct_size = 3
+    assert lib.dvgo_validate_samples(C.byref(s), None) == -8
+    s.struct_size = C.sizeof(L.Samples)
+    s.n_rays, s.n_samples = 4, 10
+    assert lib.dvgo_validate_samples(C.byref(s), None) == -1  # NULL s_mid with samples
+    s.s_mid = 64
+    assert lib.dvgo_validate_samples(C.byref(s), None) == -1  # NULL ray_offsets
+    limit = (1 << 31) // 3 - 1
+    p = L.RenderParams()
+    p.struct_size = C.sizeof(L.RenderParams)
+    p.color_mode = L.COLOR_SAMPLES
+    s.ray_offsets = s.xyz = s.delta = s.s_len = 64
+    s.n_samples = limit + 1
+    assert lib.dvgo_render_forward(C.byref(p), C.byref(s), None, None, None, None, None, None, None, None, 0,
+                                   None) == -3
+    assert str(limit) in _err(L)
+    assert lib.dvgo_distortion_loss(4, 64, limit + 1, 64, 64, 64, 64, None, None, None, 0, None) == -3
+    prev = lib.dvgo_set_debug(1)
+    assert lib.dvgo_set_debug(prev) == 1
+    assert L.ERRORS[-4] == "ERR_UNSORTED"

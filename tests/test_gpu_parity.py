@@ -174,34 +174,119 @@ def test_render_edge_cases(dv):
     _check_render(dv, wl, smp, "samples", seed=5, grad_T=False)
 
 
+def _halt_index(w, offs):
+    """Per ray, the number of leading samples with non-zero weight; checks that every later
+    sample has weight exactly 0 (halted samples carry no weight)."""
+    out = np.zeros(len(offs) - 1, np.int64)
+    for r in range(len(offs) - 1):
+        wr = np.asarray(w[offs[r]:offs[r + 1]])
+        nz = np.flatnonzero(wr == 0)
+        h = int(nz[0]) if nz.size else wr.size
+        assert not wr[h:].any(), f"ray {r}: weight after the halt"
+        out[r] = h
+    return out
+
+
 def test_render_halting_paper_mode(dv):
-    # halt at T < 1e-3 (section 3).  A float32/float64 difference can move the halt index
-    # of a ray sitting at the threshold; such rays are compared with the slack the rule
-    # allows (thr * (max|c| + |bg|)), all others exactly as without halting.
-    wl = synth.config1(R=256)
-    wl.density.data += np.float32(6.0)
+    # Section 3 stops tracking a ray once its transmittance is below 1e-3.  Reading R6: T_k is
+    # tested before sample k; sample k and later get no weight and no gradient; T_N := T_k.  The
+    # halt index of a ray whose T crosses the threshold within float32 rounding can differ
+    # between the float32 kernel and the float64 oracle; R6 asks that at least 99.9 % of the rays
+    # agree.  Forward outputs and both grid gradients are compared on the whole batch: exactly
+    # (R16) wherever only agreeing rays contribute, and with the slack a one-interval move of
+    # the halt allows elsewhere (the weight beyond a halt is below thr).
+    wl = synth.config1(R=4096)
+    wl.density.data += np.float32(6.0)   # opaque enough that most rays halt
     smp = wl.samples
+    R, S = smp.n_rays, smp.n_samples
     thr = 1e-3
+    bg = (0.25, 0.5, 1.0)
+    shift = float(np.float32(oracle.act_shift()))
+    rng = np.random.default_rng(8)
+    dens = dgrid(dv, wl.density, grad=True)
+    col = dgrid(dv, wl.color, grad=True, channels=3)
+    b = dbatch(dv, smp)
+    say("render halting thr=1e-3, forward + backward, 4096 rays x 128")
+    w_gpu = torch.empty(S, device="cuda")
+    rgb, Tf, D, state = dv.render_forward(b, dens, col, None, act_shift_=shift, halt_T=thr, bg=bg, sample_w=w_gpu)
+    GC = rng.standard_normal((R, 3)).astype(np.float32)
+    GD = rng.standard_normal(R).astype(np.float32)
+    GT = rng.standard_normal(R).astype(np.float32)
+    dv.render_backward(b, dens, col, None, Tf, state, T(GC), T(GD), T(GT), act_shift_=shift, halt_T=thr, bg=bg)
+    torch.cuda.synchronize()
+    o = oracle.render_forward(smp, wl.density, wl.color, shift=shift, halt_T=thr, bg=bg, want_w=True)
+    og = oracle.render_backward(smp, wl.density, GC.astype(np.float64), GD.astype(np.float64),
+                                GT.astype(np.float64), color=wl.color, shift=shift, halt_T=thr, bg=bg)
+    offs = smp.ray_offsets
+    hg, ho = _halt_index(w_gpu.cpu().numpy(), offs), _halt_index(o["w"], offs)
+    lens = np.diff(offs)
+    agree = hg == ho
+    say("rays halted:", int((ho < lens).sum()), "of", R, "; halt index agrees on", int(agree.sum()))
+    assert (ho < lens).mean() > 0.5
+    assert agree.mean() >= 0.999, f"halt agreement {agree.mean():.5f}"
+    cmax = float(np.abs(wl.color.data).max())
+    rgb, Tf, D = rgb.cpu().numpy(), Tf.cpu().numpy(), D.cpu().numpy()
+    close(rgb[agree], o["rgb"][agree], **FWD, name="rgb (agreeing rays)")
+    close(Tf[agree], o["T"][agree], **FWD, name="T_final (agreeing rays)")
+    close(D[agree], o["D"][agree], **FWD, name="distortion (agreeing rays)")
+    dis = ~agree
+    if dis.any():
+        # beyond the earlier halt at most thr of weight remains: colour moves by thr (|c| + |bg|),
+        # T_N by thr, D by 2 thr + thr^2 (|m_i - m_j| <= 1, weights sum to <= 1)
+        assert (np.abs(rgb[dis] - o["rgb"][dis]) <= thr * (cmax + max(bg)) + 1e-5).all()
+        assert (np.abs(Tf[dis] - o["T"][dis]) <= thr + 1e-6).all()
+        assert (np.abs(D[dis] - o["D"][dis]) <= 3 * thr).all()
+    # gradient slack of the disagreeing rays: per sample of such a ray, dL/dx moves by at most
+    # 2 thr (max|g| + |G_C . bg + G_T|) with |g| <= |G_C|_1 max|c| + 3 |G_D|, times delta (the
+    # logistic factor is <= 1); dL/dc moves by thr |G_C|; each spread over the sample's corners
+    dis_s = np.repeat(dis, lens)
+    gmax = np.abs(GC).sum(1) * cmax + 3 * np.abs(GD)
+    tail = np.abs(GC @ np.asarray(bg, np.float32) + GT)
+    per_ray = 2 * thr * (gmax + tail)
+    bd = np.where(dis_s, np.repeat(per_ray, lens) * smp.delta, 0.0)
+    bc = np.where(dis_s[:, None], thr * np.abs(np.repeat(GC, lens, axis=0)), 0.0)
+    slack_d = oracle.scatter(wl.density, smp.xyz, np.abs(bd)[:, None]) if dis.any() else None
+    slack_c = oracle.scatter(wl.color, smp.xyz, np.abs(bc)) if dis.any() else None
+    close(dens.grad.cpu().numpy(), og["grad_density"], **GRAD, name="grad density (halting)", slack=slack_d)
+    close(col.grad.cpu().numpy(), og["grad_color"], **GRAD, name="grad colour grid (halting)", slack=slack_c)
+
+
+def test_validation_on_device(dv):
+    # debug-mode checks of the batch contract (section 2 assumes sorted midpoints): the explicit
+    # call and the render entry point in debug mode reject broken batches before any kernel runs
+    wl = synth.config1(R=16)
+    smp = wl.samples
+    b = dbatch(dv, smp)
+    say("device validation of a good, an unsorted and a mis-terminated batch")
+    dv.validate_samples(b)
+    bad = dbatch(dv, smp)
+    sm = smp.s_mid.copy()
+    k = int(smp.ray_offsets[5]) + 3
+    sm[k], sm[k + 1] = sm[k + 1], sm[k]
+    bad.s_mid = T(sm)
+    import paper_2206_05085_amd as pkg
+    with pytest.raises(pkg.DvgoError) as e:
+        dv.validate_samples(bad)
+    assert e.value.code == -4
+    short = dbatch(dv, smp)
+    offs = smp.ray_offsets.copy()
+    offs[-1] -= 1
+    short.ray_offsets = T(offs, torch.int32)
+    with pytest.raises(pkg.DvgoError) as e:
+        dv.validate_samples(short)
+    assert e.value.code == -2
     dens = dgrid(dv, wl.density)
     col = dgrid(dv, wl.color, channels=3)
-    b = dbatch(dv, smp)
-    shift = float(np.float32(oracle.act_shift()))
-    say("render halting thr=1e-3, 256 rays")
-    rgb, Tf, D, state = dv.render_forward(b, dens, col, None, act_shift_=shift, halt_T=thr)
-    torch.cuda.synchronize()
-    o = oracle.render_forward(smp, wl.density, wl.color, shift=shift, halt_T=thr)
-    rgb = rgb.cpu().numpy()
-    diff = np.abs(rgb - o["rgb"]).max(axis=1)
-    exact = diff <= 1e-5 * np.maximum(np.abs(o["rgb"]).max(axis=1), 1e-3)
-    assert exact.mean() >= 0.99, f"halt agreement {exact.mean():.4f}"
-    assert (diff[~exact] <= thr * (1.0 + 1.0) + 1e-5).all()
-    assert (Tf.cpu().numpy() >= 0).all()
+    prev = dv.set_debug(True)
+    try:
+        with pytest.raises(pkg.DvgoError) as e:
+            dv.render_forward(bad, dens, col, None, act_shift_=float(oracle.act_shift()))
+        assert e.value.code == -4
+        dv.render_forward(b, dens, col, None, act_shift_=float(oracle.act_shift()))
+        torch.cuda.synchronize()
+    finally:
+        dv.set_debug(prev)
 
-
-# ------------------------------------------------------------ gather / scatter
-
-
-@pytest.mark.parametrize("C", [1, 3, 12])
 def test_gather_scatter(dv, C):
     rng = np.random.default_rng(10 + C)
     g = synth.normal_grid(rng, 24, C)
@@ -460,40 +545,6 @@ def test_mlp_small_ragged(dv):
 def test_mlp_multi_block(dv):
     say("mlp ~40k samples")
     _mlp_case(dv, list(np.random.default_rng(21).integers(0, 300, 256)), seed=22)
-
-
-@pytest.mark.parametrize("half", [False, True])
-def test_mlp_backward_fused_scatter(dv, half):
-    # the feature gradient scattered inside the colour head's backward equals the oracle's
-    # scatter of the oracle's feature gradient (parameter gradients as in the unfused call)
-    wl = synth.config2(R=512, n=40)
-    smp = wl.samples
-    rng = np.random.default_rng(26)
-    S, R = smp.n_samples, smp.n_rays
-    feat = oracle.gather(wl.feat, smp.xyz).astype(np.float32)
-    grgb = rng.standard_normal((S, 3)).astype(np.float32)
-    say("mlp backward with fused feature scatter, 40^3x12, S =", S, "half", half)
-    W = [T(w) for w in wl.mlp.W]
-    b = [T(v) for v in wl.mlp.b]
-    gW = [torch.zeros_like(w) for w in W]
-    gb = [torch.zeros_like(v) for v in b]
-    P = dv.MLPParams(W, b, gW, gb, precision=dv.MLP_F16 if half else dv.MLP_SPLIT_F16)
-    fg = dgrid(dv, wl.feat, grad=True)
-    dv.mlp_backward_scatter(P, T(smp.ray_offsets, torch.int32), T(wl.rays.dirs), T(feat), T(grgb), fg, T(smp.xyz))
-    torch.cuda.synchronize()
-    f64, g64 = feat.astype(np.float64), grgb.astype(np.float64)
-    rgf, rgW, rgb_ = oracle.mlp_backward(wl.mlp, smp.ray_offsets, wl.rays.dirs, f64, g64, half=half)
-    want = oracle.scatter(wl.feat, smp.xyz, rgf)
-    sf, sW, sb = oracle.mlp_kink_slack(wl.mlp, smp.ray_offsets, wl.rays.dirs, f64, g64, thr=1e-4 if half else 1e-5,
-                                       half=half)
-    slack = oracle.scatter(wl.feat, smp.xyz, sf)   # every vertex weight is <= 1
-    gr = GRAD16 if half else GRAD
-    scale = None
-    if half:
-        mf = oracle.mlp_magnitudes(wl.mlp, smp.ray_offsets, wl.rays.dirs, f64, g64, half=True)[1]
-        scale = oracle.scatter(wl.feat, smp.xyz, mf)
-    close(fg.grad.cpu().numpy(), want, **gr, name="fused feature-grid gradient", slack=np.abs(slack), scale=scale)
-    close(gW[1].cpu().numpy(), rgW[1], **gr, name="fused dW2", slack=sW[1])
 
 
 def test_mlp_f16_small_ragged(dv):

@@ -1,5 +1,5 @@
 """Host-side logic of TrainStep (no GPU): construction with every option, the MLP parameter
-views into one flat buffer, and the choice of the fused and two-stream paths."""
+views into one flat buffer, and the choice of the fused-gather and two-stream paths."""
 import numpy as np
 import pytest
 import torch
@@ -10,12 +10,11 @@ from paper_2206_05085_amd.step import TrainStep
 
 
 @pytest.mark.parametrize("kw", [dict(), dict(tv=(1e-5, 1e-6, 1.0, True)), dict(warp=(1, 1.0)),
-                                dict(mlp_precision=1), dict(binned_scatter=False, concurrent=False, fused_scatter=True)])
+                                dict(mlp_precision=1), dict(binned_scatter=False, concurrent=False)])
 def test_construct_on_host(kw):
     wl = synth.config2(R=8, n=16)
     st = TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
                    mlp=(wl.mlp.W, wl.mlp.b), device="cpu", **kw)
-    assert st.fused == (kw.get("fused_scatter", False) and kw.get("warp", (0, 1.0))[0] == 0)
     assert st.binned == kw.get("binned_scatter", True) and st.concurrent == kw.get("concurrent", True)
     assert st.mlp.precision == kw.get("mlp_precision", 0)
     g = st.grid("feat")
