@@ -303,6 +303,38 @@ int dvgo_bin_samples(const dvgo_grid *g, int64_t n_samples, const float *xyz, vo
 int dvgo_grid_scatter_binned(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
                              const void *ws, size_t ws_bytes, void *stream);
 
+/* Owner-computes scatter (the same sum as dvgo_grid_scatter, with no global atomics).  The
+ * grid's vertices are cut into bricks of 8^3 and each vertex belongs to one brick;
+ * dvgo_owner_bin counting-sorts the (sample, brick) pairs of every sample whose cell has corners
+ * in that brick (1 to 8 bricks per sample) into the caller's workspace of
+ * dvgo_owner_workspace_size bytes (256-byte aligned; about 32 bytes per sample).  Bins depend only
+ * on the points and the grid geometry (shape, box, warp): one binning serves every grid of the
+ * same geometry and xyz.  dvgo_grid_scatter_owned then adds g->grad += trilinear^T(grad_out)
+ * (grad_out [S, channels]): one block per brick sums its pairs' contributions to the vertices it
+ * owns on chip and updates each touched vertex once, with a plain read-modify-write (no other
+ * kernel may write g->grad meanwhile; elements whose sum is exactly zero are not written).
+ * n_samples is at most 89478485 (8 pairs per sample must index in int32). */
+int dvgo_owner_workspace_size(const dvgo_grid *g, int64_t n_samples, size_t *bytes);
+int dvgo_owner_bin(const dvgo_grid *g, int64_t n_samples, const float *xyz, void *ws, size_t ws_bytes,
+                   void *stream);
+int dvgo_grid_scatter_owned(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
+                            const void *ws, size_t ws_bytes, void *stream);
+
+/* dvgo_grid_scatter_owned fused with dvgo_grid_adam_step(skip_zero_grad = 1): the gradient of
+ * each grid element is the scatter of grad_out alone (no other gradient term: the dense gradient
+ * is never formed, g->grad is ignored and may be NULL), and every element whose gradient is not
+ * exactly zero takes section 3's Adam update with the same arithmetic as dvgo_grid_adam_step;
+ * elements with a zero gradient (untouched vertices, padding channels) keep p, m and v bit for
+ * bit.  param, exp_avg, exp_avg_sq: the grid's layout [nx][ny][nz][ch_stride]; g->data must be
+ * non-NULL (e.g. param) and is not read.  lr, betas, eps, step and step_dev as in
+ * dvgo_grid_adam_step.  The result equals scatter into a zeroed gradient followed by the skipping
+ * Adam step, up to the order in which each element's terms are summed.  Use the two calls
+ * instead when another term (e.g. dvgo_tv_add_grad) must join the gradient first. */
+int dvgo_grid_scatter_adam(const dvgo_grid *g, int64_t n_samples, const float *xyz, const float *grad_out,
+                           const void *ws, size_t ws_bytes, float *param, float *exp_avg, float *exp_avg_sq, float lr,
+                           float beta1, float beta2, float eps, int32_t step, const int32_t *step_dev,
+                           void *stream);
+
 /* Resampling of a grid to another resolution over the same box (progressive grid scaling, the
  * "grid scaling schedule" of Table 7's footnote): out [nx][ny][nz][src->ch_stride] (written)
  * holds at vertex (i, j, k) the trilinear value of src at xyz_min + (i, j, k) (xyz_max -
@@ -454,6 +486,26 @@ int dvgo_resample_offsets(const dvgo_rays *rays, const float *entropy, float tau
 int dvgo_resample(const dvgo_rays *rays, const float *prob, const float *entropy, float tau,
                   const int32_t *ray_offsets, int32_t n_fine, int32_t n_plain, float voxel, float *xyz, float *delta,
                   float *s_mid, float *s_len, void *stream);
+
+/* Guarded resampling (a reading of the learned proposal that combines section 1's skipping of
+ * empty space with placement by the network): coarse bin b of a ray is occupied when
+ * max(w_coarse[b-1], w_coarse[b], w_coarse[b+1]) >= w_min (weights of dvgo_proposal_coarse);
+ * an occupied bin is cut into n_base equal sub-intervals (n_base = 4: the spacing of plain
+ * 256-sample rendering) plus its share of n_extra more, allotted by prob over the occupied bins:
+ * with S_b the running sum (double, bin order) of prob over the occupied bins before b and S_tot
+ * the total, bin b gets floor(n_extra S_{b+1}/S_tot + 1/2) - floor(n_extra S_b/S_tot + 1/2) (every
+ * occupied bin counts 1 instead when S_tot = 0); unoccupied bins get no sample.  Rays with
+ * entropy > tau take every bin at n_base (plain uniform sampling); rays with t_far <= t_near
+ * take none.  dvgo_resample_guarded_offsets writes counts [R,64] (sub-intervals per bin) and
+ * ray_offsets [R+1]; needs n_base >= 1, n_extra >= 0, n_base + n_extra <= 16384.
+ * dvgo_resample_guarded fills the batch: sub-interval i of bin b cut into m is the sample
+ * s_mid = (b + (i + 1/2)/m)/64, s_len = 1/(64 m), x = o + t d with t = t_near + s_mid (t_far -
+ * t_near), delta = s_len (t_far - t_near)/voxel; outputs hold ray_offsets[R] samples. */
+int dvgo_resample_guarded_offsets(const dvgo_rays *rays, const float *prob, const float *w_coarse,
+                                  const float *entropy, float tau, int32_t n_base, int32_t n_extra, float w_min,
+                                  int32_t *ray_offsets, int32_t *counts, void *stream);
+int dvgo_resample_guarded(const dvgo_rays *rays, const int32_t *ray_offsets, const int32_t *counts, float voxel,
+                          float *xyz, float *delta, float *s_mid, float *s_len, void *stream);
 
 /* ------------------------------------------------------------------ sample producer
  * Builds the ragged batch on the device from rays: points are placed only where a ray

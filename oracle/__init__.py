@@ -133,6 +133,16 @@ def grid_struct(grid, keep):
     return g
 
 
+def threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> int:
+    """Sets the oracle's OpenMP thread count; returns the previous one."""
+    return int(lib().orc_set_threads(C.c_int32(n)))
+
+
 def act_shift(alpha_init=1e-4, delta_ref=0.5) -> float:
     return float(lib().orc_act_shift(alpha_init, delta_ref))
 
@@ -452,6 +462,35 @@ def resample_batch(prob, H, tau, n_fine, n_plain, rays, voxel):
                              _ptr(xyz), _ptr(dl), _ptr(sm), _ptr(sl))
     S = int(offs[-1])
     return dict(ray_offsets=offs, xyz=xyz[:S], delta=dl[:S], s_mid=sm[:S], s_len=sl[:S])
+
+
+def resample_guarded(prob, w_coarse, H, tau, n_base, n_extra, w_min, rays, voxel, want_samples=True):
+    """Guarded resampling (orc_resample_guarded) from the float32 prob, w_coarse [R,64] and H [R]:
+    returns dict(ray_offsets, counts [R,64], and xyz, delta, s_mid, s_len when want_samples)."""
+    keep = _Keep()
+    pr = keep(_c(prob, np.float32))
+    wc = keep(_c(w_coarse, np.float32))
+    Hh = keep(_c(H, np.float32))
+    R, B = pr.shape
+    o = keep(_c(rays.origins, np.float32))
+    d = keep(_c(rays.dirs, np.float32))
+    tn = keep(_c(rays.t_near, np.float32))
+    tf = keep(_c(rays.t_far, np.float32))
+    offs = np.zeros(R + 1, np.int32)
+    counts = np.zeros((R, B), np.int32)
+    lib().orc_resample_guarded(C.c_int32(R), C.c_int32(B), _ptr(pr), _ptr(wc), _ptr(Hh), C.c_float(tau),
+                               C.c_int32(n_base), C.c_int32(n_extra), C.c_float(w_min), _ptr(o), _ptr(d), _ptr(tn),
+                               _ptr(tf), C.c_double(voxel), _ptr(offs), _ptr(counts), None, None, None, None)
+    out = dict(ray_offsets=offs, counts=counts)
+    if want_samples:
+        S = int(offs[-1])
+        xyz, dl, sm, sl = np.zeros((max(S, 1), 3)), np.zeros(max(S, 1)), np.zeros(max(S, 1)), np.zeros(max(S, 1))
+        lib().orc_resample_guarded(C.c_int32(R), C.c_int32(B), _ptr(pr), _ptr(wc), _ptr(Hh), C.c_float(tau),
+                                   C.c_int32(n_base), C.c_int32(n_extra), C.c_float(w_min), _ptr(o), _ptr(d),
+                                   _ptr(tn), _ptr(tf), C.c_double(voxel), _ptr(offs), None, _ptr(xyz), _ptr(dl),
+                                   _ptr(sm), _ptr(sl))
+        out.update(xyz=xyz[:S], delta=dl[:S], s_mid=sm[:S], s_len=sl[:S])
+    return out
 
 
 def softmax_entropy(logits):

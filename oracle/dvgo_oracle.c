@@ -38,6 +38,15 @@ typedef struct {
 
 int orc_version(void) { return ORC_VERSION; }
 
+/* Threads the OpenMP loops use (for timing the oracle on one core and on all of them). */
+int orc_threads(void) { return omp_get_max_threads(); }
+int orc_set_threads(int32_t n)
+{
+    const int prev = omp_get_max_threads();
+    omp_set_num_threads(n > 0 ? n : 1);
+    return prev;
+}
+
 /* Shift b of the density activation.  Section 5.4 fixes the initial alpha (1e-4) at a
  * 0.5-voxel step but does not write the activation out.  Reading: sigma =
  * softplus(raw + b), alpha = 1 - exp(-sigma * delta), with b chosen so that raw = 0 at
@@ -1060,6 +1069,88 @@ void orc_resample_batch(int32_t R, int32_t B, const double *p, const double *H, 
     }
     free(cdf);
     free(s);
+}
+
+/* Guarded resampling (a reading of the learned proposal, which the paper does not have; it
+ * combines section 1's idea of skipping empty space with placement by the proposal):
+ * the 64 coarse bins of a ray are cut into equal sub-intervals, each sample the midpoint of one.
+ *   - Bin b is occupied when its coarse weight or a neighbour's, max(w[b-1], w[b], w[b+1]), is at
+ *     least w_min; unoccupied bins get no sample (space the coarse pass found empty or occluded).
+ *   - An occupied bin gets n_base sub-intervals (n_base = 4 gives plain 256-sample spacing) plus
+ *     its share of n_extra extra ones, allotted by the predicted probabilities over the occupied
+ *     bins: with S_b the running sum (double, bin order) of prob over the occupied bins before b
+ *     and S_tot the total, bin b gets round(n_extra S_{b+1}/S_tot) - round(n_extra S_b/S_tot) with
+ *     round(x) = floor(x + 1/2), so the shares sum to n_extra; if S_tot = 0 every occupied bin
+ *     counts 1 instead of its probability.
+ *   - Fallback rays (H > tau): every bin occupied with n_base sub-intervals and no extras, i.e.
+ *     plain uniform sampling at B n_base samples.  Rays with t_far <= t_near get no samples.
+ * Sample i of a bin b cut into m: s_mid = (b + (i + 1/2)/m)/B, s_len = 1/(B m); x = o + t d,
+ * t = t_near + s_mid (t_far - t_near); delta = s_len (t_far - t_near)/voxel.  Inputs are the
+ * float32 arrays the GPU works on (prob and w_coarse [R,B], H [R]); offs [R+1] is written and
+ * counts [R,B] (may be NULL) receives the sub-interval count of every bin. */
+void orc_resample_guarded(int32_t R, int32_t B, const float *prob, const float *w_coarse, const float *H, float tau,
+                          int32_t n_base, int32_t n_extra, float w_min, const float *o, const float *d, const float *tn,
+                          const float *tf, double voxel, int32_t *offs, int32_t *counts, double *xyz, double *delta,
+                          double *s_mid, double *s_len)
+{
+    int32_t *m = malloc(sizeof(int32_t) * (size_t)R * B);
+    offs[0] = 0;
+    for (int32_t r = 0; r < R; ++r) {
+        int32_t *mr = m + (int64_t)r * B;
+        const float *w = w_coarse + (int64_t)r * B, *p = prob + (int64_t)r * B;
+        int total = 0;
+        if (!(tf[r] > tn[r])) {
+            for (int b = 0; b < B; ++b) mr[b] = 0;
+        } else if (H[r] > tau) {
+            for (int b = 0; b < B; ++b) mr[b] = n_base;
+        } else {
+            int occ[256];
+            double S_tot = 0.0;
+            int n_occ = 0;
+            for (int b = 0; b < B; ++b) {
+                float mx = w[b];
+                if (b > 0 && w[b - 1] > mx) mx = w[b - 1];
+                if (b + 1 < B && w[b + 1] > mx) mx = w[b + 1];
+                occ[b] = mx >= w_min;
+                if (occ[b]) {
+                    S_tot += (double)p[b];
+                    ++n_occ;
+                }
+            }
+            const int uniform = !(S_tot > 0.0);
+            if (uniform) S_tot = (double)n_occ;
+            double S = 0.0;
+            for (int b = 0; b < B; ++b) {
+                if (!occ[b]) {
+                    mr[b] = 0;
+                    continue;
+                }
+                const double lo = floor((double)n_extra * (S / S_tot) + 0.5);
+                S += uniform ? 1.0 : (double)p[b];
+                const double hi = floor((double)n_extra * (S / S_tot) + 0.5);
+                mr[b] = n_base + (int)(hi - lo);
+            }
+        }
+        for (int b = 0; b < B; ++b) total += mr[b];
+        offs[r + 1] = offs[r] + total;
+        if (counts) for (int b = 0; b < B; ++b) counts[(int64_t)r * B + b] = mr[b];
+    }
+    if (xyz) {
+        for (int32_t r = 0; r < R; ++r) {
+            const int32_t *mr = m + (int64_t)r * B;
+            const double len = (double)tf[r] - (double)tn[r];
+            int64_t k = offs[r];
+            for (int b = 0; b < B; ++b)
+                for (int i = 0; i < mr[b]; ++i, ++k) {
+                    const double sm = (b + (i + 0.5) / mr[b]) / B, t = (double)tn[r] + sm * len;
+                    for (int a = 0; a < 3; ++a) xyz[3 * k + a] = (double)o[3 * r + a] + t * (double)d[3 * r + a];
+                    s_mid[k] = sm;
+                    s_len[k] = 1.0 / ((double)B * mr[b]);
+                    delta[k] = s_len[k] * len / voxel;
+                }
+        }
+    }
+    free(m);
 }
 
 /* Softmax probabilities and entropy -sum p ln p of given logits [R,B] (per row). */

@@ -94,6 +94,11 @@ SIGNATURES = {
     "dvgo_grid_resample": (C.c_int, [_PG, _I32, _I32, _I32, VP, VP]),
     "dvgo_bin_samples": (C.c_int, [_PG, _I64, VP, VP, C.c_size_t, VP]),
     "dvgo_grid_scatter_binned": (C.c_int, [_PG, _I64, VP, VP, VP, C.c_size_t, VP]),
+    "dvgo_owner_workspace_size": (C.c_int, [_PG, _I64, _SZP]),
+    "dvgo_owner_bin": (C.c_int, [_PG, _I64, VP, VP, C.c_size_t, VP]),
+    "dvgo_grid_scatter_owned": (C.c_int, [_PG, _I64, VP, VP, VP, C.c_size_t, VP]),
+    "dvgo_grid_scatter_adam": (C.c_int, [_PG, _I64, VP, VP, VP, C.c_size_t, VP, VP, VP, _F, _F, _F, _F, _I32, VP,
+                                         VP]),
     "dvgo_tv_add_grad": (C.c_int, [_PG, _F, _F, _I32, VP]),
     "dvgo_alpha": (C.c_int, [_PG, _I64, VP, VP, _F, VP, VP]),
     "dvgo_mlp_workspace_size": (C.c_int, [_PM, _I32, _I64, _SZP]),
@@ -111,6 +116,8 @@ SIGNATURES = {
     "dvgo_histogram": (C.c_int, [_I32, VP, VP, VP, _I32, _F, VP, VP]),
     "dvgo_resample_offsets": (C.c_int, [_PR, VP, _F, _I32, _I32, VP, VP]),
     "dvgo_resample": (C.c_int, [_PR, VP, VP, _F, VP, _I32, _I32, _F, VP, VP, VP, VP, VP]),
+    "dvgo_resample_guarded_offsets": (C.c_int, [_PR, VP, VP, VP, _F, _I32, _I32, _F, VP, VP, VP]),
+    "dvgo_resample_guarded": (C.c_int, [_PR, VP, VP, _F, VP, VP, VP, VP, VP]),
     "dvgo_sample_count": (C.c_int, [_PSM, _I32, VP, VP, VP, VP, VP, VP]),
     "dvgo_sample_emit": (C.c_int, [_PSM, _I32, VP, VP, VP, _I64, VP, VP, VP, VP, VP]),
     "dvgo_occupancy_update": (C.c_int, [_PG, _F, _F, _F, VP, VP]),

@@ -325,6 +325,71 @@ __device__ __forceinline__ void scatter_ch(const DevGrid &g, const Tri &t, int c
     for (int c = 0; c < 8; ++c) unsafeAtomicAdd(&g.grad[t.base + corner_off(g, c) + ch], t.w[c] * v);
 }
 
+// ------------------------------------------------------------------------------ Adam
+
+// The update of one element (section 3's fused Adam): every kernel that applies Adam uses these
+// expressions, so they agree bit for bit on the same gradient.
+struct AdamArgs {
+    float *p, *g, *m, *v;
+    int64_t n;
+    float lr_t;          // lr / (1 - beta1^t)
+    float inv_sqrt_bc2;  // 1 / sqrt(1 - beta2^t)
+    float b1, b2, eps, lr;
+    const int *step_dev;  // when set, t is read here and lr_t / inv_sqrt_bc2 are recomputed
+    int skip, zero;
+};
+
+__device__ __forceinline__ void adam_bias(AdamArgs &a) {
+    if (a.step_dev) {
+        const int t = *a.step_dev;
+        const double bc1 = 1.0 - pow((double)a.b1, t), bc2 = 1.0 - pow((double)a.b2, t);
+        a.lr_t = (float)((double)a.lr / bc1);
+        a.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
+    }
+}
+
+__device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, float &m, float &v) {
+    m = a.b1 * m + (1.f - a.b1) * g;
+    v = a.b2 * v + (1.f - a.b2) * (g * g);
+    p -= a.lr_t * m / (sqrtf(v) * a.inv_sqrt_bc2 + a.eps);
+}
+
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 ld_nt(const float4 *p) {
+    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void st_nt(float4 *p, float4 a) {
+    const nt_f4 v = {a.x, a.y, a.z, a.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<nt_f4 *>(p));
+}
+
+
+// ------------------------------------------------------------------------ wave runs
+
+// Runs of equal keys among the lanes of a wave: the head of each run (key >= 0) learns the run
+// length; every lane learns its run's head.
+struct Run {
+    bool head;
+    int len, head_lane;
+};
+
+__device__ __forceinline__ Run wave_runs(int key) {
+    const int ln = lane();
+    const int prev = __shfl_up(key, 1, 64);
+    const bool head = key >= 0 && (ln == 0 || prev != key);
+    const bool start = ln == 0 || prev != key;  // a run boundary (invalid lanes start runs too)
+    const unsigned long long starts = __ballot(start);
+    const unsigned long long after = ln == 63 ? 0ull : starts & (~0ull << (ln + 1));
+    const int next = after ? __ffsll((long long)after) - 1 : 64;
+    const unsigned long long upto = starts & (ln == 63 ? ~0ull : ((2ull << ln) - 1));
+    Run r;
+    r.head = head;
+    r.len = next - ln;
+    r.head_lane = 63 - __clzll((long long)upto);
+    return r;
+}
+
 // ------------------------------------------------------------------------- host side
 
 int set_error(int code, const char *fmt, ...);
@@ -335,6 +400,15 @@ int make_dev_grid(const dvgo_grid *g, const char *name, DevGrid *out, bool need_
 // ragged batch first check it on the device with validate_batch (synchronous).
 bool debug_mode();
 int validate_batch(int32_t n_rays, int64_t n_samples, const int32_t *ray_offsets, const float *s_mid, hipStream_t st);
+
+// The distortion loss on given weights (render.hip): argument checks, the bytes of its per-chunk
+// checkpoint scratch, and the launch with a caller-chosen scratch pointer.
+int distortion_check(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w, const float *s_mid,
+                     const float *s_len, const float *loss, const float *grad_loss, const float *grad_w);
+size_t distortion_scratch_bytes(int32_t n_rays, int64_t n_samples);
+int launch_distortion(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w, const float *s_mid,
+                      const float *s_len, float *loss, const float *grad_loss, float *grad_w, void *ckpt,
+                      hipStream_t st);
 
 // Largest batch the per-sample kernels address: 3 * n_samples (the xyz and colour rows) stays
 // below 2^31 in their int32 indices.

@@ -184,31 +184,6 @@ __global__ __launch_bounds__(kBlock) void alpha_kernel(DevGrid g, int64_t S, con
     }
 }
 
-struct AdamArgs {
-    float *p, *g, *m, *v;
-    int64_t n;
-    float lr_t;          // lr / (1 - beta1^t)
-    float inv_sqrt_bc2;  // 1 / sqrt(1 - beta2^t)
-    float b1, b2, eps, lr;
-    const int *step_dev;  // when set, t is read here and lr_t / inv_sqrt_bc2 are recomputed
-    int skip, zero;
-};
-
-__device__ __forceinline__ void adam_bias(AdamArgs &a) {
-    if (a.step_dev) {
-        const int t = *a.step_dev;
-        const double bc1 = 1.0 - pow((double)a.b1, t), bc2 = 1.0 - pow((double)a.b2, t);
-        a.lr_t = (float)((double)a.lr / bc1);
-        a.inv_sqrt_bc2 = (float)(1.0 / sqrt(bc2));
-    }
-}
-
-__device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, float &m, float &v) {
-    m = a.b1 * m + (1.f - a.b1) * g;
-    v = a.b2 * v + (1.f - a.b2) * (g * g);
-    p -= a.lr_t * m / (sqrtf(v) * a.inv_sqrt_bc2 + a.eps);
-}
-
 // Streams the four arrays as float4 (the 16-byte-aligned body) with a scalar head/tail.
 // With skip, a float4 group whose four gradients are all zero is not read further and
 // nothing is written; within a partly non-zero group the zero-gradient lanes keep their
@@ -222,16 +197,6 @@ __device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, f
 // step reads them again soon; the parameters keep the default policy, since the next step's lookups
 // read them back.
 constexpr int ADAM_U = 4;
-
-typedef float nt_f4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ float4 ld_nt(const float4 *p) {
-    const nt_f4 v = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
-    return make_float4(v.x, v.y, v.z, v.w);
-}
-__device__ __forceinline__ void st_nt(float4 *p, float4 a) {
-    const nt_f4 v = {a.x, a.y, a.z, a.w};
-    __builtin_nontemporal_store(v, reinterpret_cast<nt_f4 *>(p));
-}
 
 __global__ __launch_bounds__(kBlock) void adam_kernel(AdamArgs a, int64_t head, int64_t n4) {
     adam_bias(a);
@@ -625,29 +590,6 @@ size_t bin_bytes(int nb, int64_t S, size_t *o_cursor, size_t *o_perm) {
 
 __global__ __launch_bounds__(256) void bin_zero_kernel(int *p, int n) {
     for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
-}
-
-// Runs of equal keys among the lanes of a wave: the head of each run (key >= 0) learns the run
-// length; every lane learns its run's head.
-struct Run {
-    bool head;
-    int len, head_lane;
-};
-
-__device__ __forceinline__ Run wave_runs(int key) {
-    const int ln = lane();
-    const int prev = __shfl_up(key, 1, 64);
-    const bool head = key >= 0 && (ln == 0 || prev != key);
-    const bool start = ln == 0 || prev != key;  // a run boundary (invalid lanes start runs too)
-    const unsigned long long starts = __ballot(start);
-    const unsigned long long after = ln == 63 ? 0ull : starts & (~0ull << (ln + 1));
-    const int next = after ? __ffsll((long long)after) - 1 : 64;
-    const unsigned long long upto = starts & (ln == 63 ? ~0ull : ((2ull << ln) - 1));
-    Run r;
-    r.head = head;
-    r.len = next - ln;
-    r.head_lane = 63 - __clzll((long long)upto);
-    return r;
 }
 
 template <bool W>

@@ -456,6 +456,136 @@ __global__ __launch_bounds__(256) void resample_fill_kernel(RayArgs ra, const fl
     }
 }
 
+// Guarded resampling: the coarse bins the coarse pass found occupied (its weight, or a
+// neighbour's, at least w_min) are cut into n_base sub-intervals plus a share of n_extra allotted
+// by the predicted probabilities; unoccupied bins get none.  One wave per ray, lane = bin for the
+// occupancy test; lane 0 then allots the extras in bin order with a running double sum, so the
+// integers equal those of a sequential evaluation (round(x) = floor(x + 1/2) of n_extra S_b/S_tot,
+// differenced).  counts [R,64] is written; offs[r+1] receives the ray's total for the scan below.
+constexpr int MAX_PER_BIN = 1 << 14;
+
+__global__ __launch_bounds__(256) void guard_count_kernel(RayArgs ra, const float *prob, const float *wc,
+                                                          const float *H, float tau, int n_base, int n_extra,
+                                                          float w_min, int *counts, int *offs) {
+    __shared__ int occ_s[4][NB];
+    __shared__ float p_s[4][NB];
+    const int wv = threadIdx.x >> 6, r = blockIdx.x * 4 + wv, ln = lane();
+    if (r >= ra.R) return;
+    int m = 0;
+    if (ra.tf[r] > ra.tn[r]) {
+        if (H[r] > tau) {
+            m = n_base;
+        } else {
+            const float w = wc[(int64_t)r * NB + ln];
+            const float wl = __shfl_up(w, 1, 64), wr = __shfl_down(w, 1, 64);
+            float mx = w;
+            if (ln > 0 && wl > mx) mx = wl;
+            if (ln < NB - 1 && wr > mx) mx = wr;
+            occ_s[wv][ln] = mx >= w_min ? 1 : 0;
+            p_s[wv][ln] = prob[(int64_t)r * NB + ln];
+            __threadfence_block();
+            if (ln == 0) {
+                double S_tot = 0.0;
+                int n_occ = 0;
+                for (int b = 0; b < NB; ++b)
+                    if (occ_s[wv][b]) {
+                        S_tot += (double)p_s[wv][b];
+                        ++n_occ;
+                    }
+                const bool uniform = !(S_tot > 0.0);
+                if (uniform) S_tot = (double)n_occ;
+                double S = 0.0;
+                for (int b = 0; b < NB; ++b) {
+                    int mb = 0;
+                    if (occ_s[wv][b]) {
+                        const double lo = floor((double)n_extra * (S / S_tot) + 0.5);
+                        S += uniform ? 1.0 : (double)p_s[wv][b];
+                        const double hi = floor((double)n_extra * (S / S_tot) + 0.5);
+                        mb = n_base + (int)(hi - lo);
+                    }
+                    occ_s[wv][b] = mb;  // the bin's count, read back by its lane below
+                }
+            }
+            __threadfence_block();
+            m = occ_s[wv][ln];
+        }
+    }
+    counts[(int64_t)r * NB + ln] = m;
+    int tot = m;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, 64);
+    if (ln == 0) offs[r + 1] = tot;
+}
+
+// offs[0] = 0, offs[1..R] = inclusive prefix of the per-ray totals left there (one block)
+__global__ __launch_bounds__(1024) void guard_scan_kernel(int R, int *offs) {
+    __shared__ int wsum[16];
+    __shared__ int carry;
+    if (threadIdx.x == 0) {
+        carry = 0;
+        offs[0] = 0;
+    }
+    __syncthreads();
+    for (int base = 0; base < R; base += 1024) {
+        const int r = base + threadIdx.x;
+        int v = r < R ? offs[r + 1] : 0;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(v, d, 64);
+            if (lane() >= d) v += t;
+        }
+        if (lane() == 63) wsum[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x < 16) {
+            int t = wsum[threadIdx.x];
+#pragma unroll
+            for (int d = 1; d < 16; d <<= 1) {
+                const int u = __shfl_up(t, d, 16);
+                if ((int)threadIdx.x >= d) t += u;
+            }
+            wsum[threadIdx.x] = t;
+        }
+        __syncthreads();
+        const int wave_off = (threadIdx.x >> 6) ? wsum[(threadIdx.x >> 6) - 1] : 0;
+        if (r < R) offs[r + 1] = carry + wave_off + v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += wsum[15];
+        __syncthreads();
+    }
+}
+
+// one wave per ray, lane = bin: sub-interval i of bin b cut into m sits at
+// s = (b + (i + 1/2)/m)/64, length 1/(64 m); positions formed in double
+__global__ __launch_bounds__(256) void guard_fill_kernel(RayArgs ra, const int *offs, const int *counts, float voxel,
+                                                         float *xyz, float *delta, float *s_mid, float *s_len) {
+    const int wv = threadIdx.x >> 6, r = blockIdx.x * 4 + wv, ln = lane();
+    if (r >= ra.R) return;
+    const int m = counts[(int64_t)r * NB + ln];
+    const int incl = [&] {
+        int v = m;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(v, d, 64);
+            if (ln >= d) v += t;
+        }
+        return v;
+    }();
+    const int64_t k0 = (int64_t)offs[r] + (incl - m);
+    const double a = ra.tn[r], len = (double)ra.tf[r] - (double)ra.tn[r];
+    for (int i = 0; i < m; ++i) {
+        const int64_t k = k0 + i;
+        const double sm = ((double)ln + ((double)i + 0.5) / (double)m) / (double)NB;
+        const double sl = 1.0 / ((double)NB * (double)m);
+        const double t = a + sm * len;
+        xyz[3 * k] = (float)((double)ra.o[3 * r] + t * (double)ra.d[3 * r]);
+        xyz[3 * k + 1] = (float)((double)ra.o[3 * r + 1] + t * (double)ra.d[3 * r + 1]);
+        xyz[3 * k + 2] = (float)((double)ra.o[3 * r + 2] + t * (double)ra.d[3 * r + 2]);
+        s_mid[k] = (float)sm;
+        s_len[k] = (float)sl;
+        delta[k] = (float)(sl * len / (double)voxel);
+    }
+}
+
 // ------------------------------------------------------------------- host side
 
 int check_prop(const dvgo_proposal *p, bool bwd) {
@@ -608,4 +738,38 @@ extern "C" int dvgo_resample(const dvgo_rays *rays, const float *prob, const flo
     hipLaunchKernelGGL(resample_fill_kernel, dim3((rays->n_rays + 3) / 4), dim3(256), 0, (hipStream_t)stream,
                        ray_args(rays), prob, entropy, tau, ray_offsets, n_fine, n_plain, voxel, xyz, delta, s_mid, s_len);
     return check_hip(hipGetLastError(), "resample_fill_kernel launch");
+}
+
+extern "C" int dvgo_resample_guarded_offsets(const dvgo_rays *rays, const float *prob, const float *w_coarse,
+                                             const float *entropy, float tau, int32_t n_base, int32_t n_extra,
+                                             float w_min, int32_t *ray_offsets, int32_t *counts, void *stream) {
+    int rc = check_rays(rays);
+    if (rc) return rc;
+    if (n_base < 1 || n_extra < 0 || n_base + n_extra > MAX_PER_BIN)
+        return set_error(DVGO_ERR_RANGE, "need n_base >= 1, n_extra >= 0, n_base + n_extra <= %d", MAX_PER_BIN);
+    if ((int64_t)rays->n_rays * (NB * (int64_t)n_base + n_extra) >= ((int64_t)1 << 31))
+        return set_error(DVGO_ERR_RANGE, "batch could exceed 2^31 samples");
+    if (!ray_offsets) return set_error(DVGO_ERR_NULL, "ray_offsets is NULL");
+    if (rays->n_rays > 0 && (!prob || !w_coarse || !entropy || !counts))
+        return set_error(DVGO_ERR_NULL, "prob, w_coarse, entropy or counts is NULL");
+    const hipStream_t st = (hipStream_t)stream;
+    if (rays->n_rays > 0)
+        hipLaunchKernelGGL(guard_count_kernel, dim3((rays->n_rays + 3) / 4), dim3(256), 0, st, ray_args(rays), prob,
+                           w_coarse, entropy, tau, n_base, n_extra, w_min, counts, ray_offsets);
+    hipLaunchKernelGGL(guard_scan_kernel, dim3(1), dim3(1024), 0, st, rays->n_rays, ray_offsets);
+    return check_hip(hipGetLastError(), "guarded resampling offsets launch");
+}
+
+extern "C" int dvgo_resample_guarded(const dvgo_rays *rays, const int32_t *ray_offsets, const int32_t *counts,
+                                     float voxel, float *xyz, float *delta, float *s_mid, float *s_len,
+                                     void *stream) {
+    int rc = check_rays(rays);
+    if (rc) return rc;
+    if (rays->n_rays == 0) return DVGO_OK;
+    if (!ray_offsets || !counts || !xyz || !delta || !s_mid || !s_len)
+        return set_error(DVGO_ERR_NULL, "an argument array is NULL");
+    if (!(voxel > 0.f)) return set_error(DVGO_ERR_RANGE, "voxel must be positive");
+    hipLaunchKernelGGL(guard_fill_kernel, dim3((rays->n_rays + 3) / 4), dim3(256), 0, (hipStream_t)stream,
+                       ray_args(rays), ray_offsets, counts, voxel, xyz, delta, s_mid, s_len);
+    return check_hip(hipGetLastError(), "guard_fill_kernel launch");
 }

@@ -661,9 +661,10 @@ extern "C" int dvgo_distortion_workspace_size(int32_t n_rays, int64_t n_samples,
     return DVGO_OK;
 }
 
-extern "C" int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w,
-                                    const float *s_mid, const float *s_len, float *loss, const float *grad_loss,
-                                    float *grad_w, void *ws, size_t ws_bytes, void *stream) {
+namespace dvgo {
+
+int distortion_check(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w, const float *s_mid,
+                     const float *s_len, const float *loss, const float *grad_loss, const float *grad_w) {
     if (n_rays < 0 || n_samples < 0) return set_error(DVGO_ERR_SHAPE, "negative n_rays or n_samples");
     if (n_samples > MAX_SAMPLES) return set_error(DVGO_ERR_RANGE, "n_samples must be at most %lld", (long long)MAX_SAMPLES);
     if (n_rays == 0) return DVGO_OK;
@@ -673,15 +674,37 @@ extern "C" int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, 
     if (!loss && !bwd) return set_error(DVGO_ERR_NULL, "nothing to compute: loss and grad_w are NULL");
     if ((grad_loss == nullptr) != (grad_w == nullptr))
         return set_error(DVGO_ERR_NULL, "grad_loss and grad_w must both be given for the backward");
-    size_t need = (size_t)ckpt_count(n_rays, n_samples) * sizeof(float2);
-    if (bwd && (!ws || ws_bytes < need)) return set_error(DVGO_ERR_WORKSPACE, "workspace too small (%zu < %zu)",
-                                                           ws_bytes, need);
+    return DVGO_OK;
+}
+
+size_t distortion_scratch_bytes(int32_t n_rays, int64_t n_samples) {
+    return (size_t)ckpt_count(n_rays, n_samples) * sizeof(float2);
+}
+
+int launch_distortion(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w, const float *s_mid,
+                      const float *s_len, float *loss, const float *grad_loss, float *grad_w, void *ckpt,
+                      hipStream_t st) {
     if (debug_mode()) {
-        const int rc = validate_batch(n_rays, n_samples, ray_offsets, s_mid, (hipStream_t)stream);
+        const int rc = validate_batch(n_rays, n_samples, ray_offsets, s_mid, st);
         if (rc) return rc;
     }
+    const bool bwd = grad_loss && grad_w;
     const dim3 grid((n_rays + 3) / 4), block(256);
-    hipLaunchKernelGGL(distortion_kernel, grid, block, 0, (hipStream_t)stream, n_rays, ray_offsets, w, s_mid, s_len,
-                       loss, bwd ? grad_loss : nullptr, bwd ? grad_w : nullptr, (float2 *)ws);
+    hipLaunchKernelGGL(distortion_kernel, grid, block, 0, st, n_rays, ray_offsets, w, s_mid, s_len, loss,
+                       bwd ? grad_loss : nullptr, bwd ? grad_w : nullptr, (float2 *)ckpt);
     return check_hip(hipGetLastError(), "distortion_kernel launch");
+}
+
+}  // namespace dvgo
+
+extern "C" int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w,
+                                    const float *s_mid, const float *s_len, float *loss, const float *grad_loss,
+                                    float *grad_w, void *ws, size_t ws_bytes, void *stream) {
+    int rc = distortion_check(n_rays, ray_offsets, n_samples, w, s_mid, s_len, loss, grad_loss, grad_w);
+    if (rc || n_rays == 0) return rc;
+    const size_t need = distortion_scratch_bytes(n_rays, n_samples);
+    if (grad_loss && grad_w && (!ws || ws_bytes < need))
+        return set_error(DVGO_ERR_WORKSPACE, "workspace too small (%zu < %zu)", ws_bytes, need);
+    return launch_distortion(n_rays, ray_offsets, n_samples, w, s_mid, s_len, loss, grad_loss, grad_w, ws,
+                             (hipStream_t)stream);
 }

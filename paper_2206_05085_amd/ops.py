@@ -16,9 +16,9 @@ from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16
 __all__ = ["act_shift", "set_debug", "validate_samples", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
            "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
-           "grid_scatter", "grid_resample", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "alpha", "mlp_workspace_size", "mlp_prepare", "mlp_forward", "mlp_forward_gather", "mlp_backward",
+           "grid_scatter", "grid_resample", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "owner_workspace_size", "owner_bin", "grid_scatter_owned", "grid_scatter_adam", "alpha", "mlp_workspace_size", "mlp_prepare", "mlp_forward", "mlp_forward_gather", "mlp_backward",
            "mlp_backward_partials", "mlp_reduce_grads", "loss_head",
-           "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
+           "resample_guarded_offsets", "resample_guarded", "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
            "COLOR_GRID", "COLOR_SAMPLES", "WARP_NONE", "WARP_CONTRACT_INF", "WARP_CONTRACT_L2",
            "MLP_SPLIT_F16", "MLP_F16"]
 
@@ -397,6 +397,48 @@ def grid_scatter_binned(grid: DeviceGrid, xyz, grad_out, ws):
          ws.numel(), _stream())
 
 
+def owner_workspace_size(grid: DeviceGrid, n_samples: int) -> int:
+    return _size("dvgo_owner_workspace_size", ctypes_byref(grid.struct()), int(n_samples))
+
+
+def owner_bin(grid: DeviceGrid, xyz, ws=None):
+    """Sort the (sample, owning 8^3-vertex brick) pairs of the points (for grid_scatter_owned and
+    grid_scatter_adam); returns ws."""
+    _chk(xyz, "xyz", last=3)
+    S = xyz.numel() // 3
+    if ws is None:
+        ws = torch.empty(max(owner_workspace_size(grid, S), 1), dtype=torch.uint8, device=xyz.device)
+    call("dvgo_owner_bin", ctypes_byref(grid.struct()), S, _p(xyz), _p(ws), ws.numel(), _stream())
+    return ws
+
+
+def grid_scatter_owned(grid: DeviceGrid, xyz, grad_out, ws):
+    """grid.grad += trilinear^T(grad_out), each vertex updated once by its owning brick (bins of
+    owner_bin), with no atomics."""
+    _chk(xyz, "xyz", last=3)
+    S = xyz.numel() // 3
+    _chk(grad_out, "grad_out", numel=S * grid.struct().channels)
+    call("dvgo_grid_scatter_owned", ctypes_byref(grid.struct(need_grad=True)), S, _p(xyz), _p(grad_out), _p(ws),
+         ws.numel(), _stream())
+
+
+def grid_scatter_adam(grid: DeviceGrid, xyz, grad_out, ws, exp_avg, exp_avg_sq, *, lr, beta1=0.9, beta2=0.99,
+                      eps=1e-8, step=0, step_dev=None):
+    """The skipping Adam update of grid.data (in place) with the gradient trilinear^T(grad_out)
+    formed per brick on chip (bins of owner_bin); grid.grad is not used."""
+    _chk(xyz, "xyz", last=3)
+    S = xyz.numel() // 3
+    g = grid.struct()
+    _chk(grad_out, "grad_out", numel=S * g.channels)
+    n = grid.data.numel()
+    for t, nm in ((exp_avg, "exp_avg"), (exp_avg_sq, "exp_avg_sq")):
+        _chk(t, nm, numel=n)
+    if step_dev is not None:
+        _chk(step_dev, "step_dev", torch.int32, numel=1)
+    call("dvgo_grid_scatter_adam", ctypes_byref(g), S, _p(xyz), _p(grad_out), _p(ws), ws.numel(), _p(grid.data),
+         _p(exp_avg), _p(exp_avg_sq), lr, beta1, beta2, eps, step, _p(step_dev), _stream())
+
+
 def ctypes_byref(x):
     import ctypes
     return ctypes.byref(x)
@@ -682,6 +724,40 @@ def resample(rays: RayBatch, prob, entropy, tau, ray_offsets, n_samples, voxel, 
     r = rays.struct()
     call("dvgo_resample", ctypes.byref(r), _p(prob), _p(entropy), tau, _p(ray_offsets), n_fine, n_plain, voxel,
          _p(xyz), _p(dl), _p(sm), _p(sl), _stream())
+    return SampleBatch(ray_offsets, xyz, dl, sm, sl, R, int(n_samples))
+
+
+def resample_guarded_offsets(rays: RayBatch, prob, w_coarse, entropy, tau, n_base=4, n_extra=32, w_min=1e-4,
+                             ray_offsets=None, counts=None):
+    """Guarded resampling layout: occupied coarse bins get n_base + their share of n_extra
+    sub-intervals; returns (ray_offsets [R+1], counts [R,64])."""
+    import ctypes
+    R = rays.n_rays
+    _chk(prob, "prob", numel=64 * R)
+    _chk(w_coarse, "w_coarse", numel=64 * R)
+    _chk(entropy, "entropy", numel=R)
+    dev = prob.device
+    ray_offsets = torch.empty(R + 1, dtype=torch.int32, device=dev) if ray_offsets is None else ray_offsets
+    counts = torch.empty(R, 64, dtype=torch.int32, device=dev) if counts is None else counts
+    r = rays.struct()
+    call("dvgo_resample_guarded_offsets", ctypes.byref(r), _p(prob), _p(w_coarse), _p(entropy), float(tau),
+         int(n_base), int(n_extra), float(w_min), _p(ray_offsets), _p(counts), _stream())
+    return ray_offsets, counts
+
+
+def resample_guarded(rays: RayBatch, ray_offsets, counts, n_samples, voxel, out=None):
+    """Fills the guarded fine batch laid out by resample_guarded_offsets; returns a SampleBatch."""
+    import ctypes
+    R = rays.n_rays
+    _chk(counts, "counts", torch.int32, numel=64 * R)
+    dev = counts.device
+    if out is None:
+        out = (torch.empty(n_samples, 3, device=dev), torch.empty(n_samples, device=dev),
+               torch.empty(n_samples, device=dev), torch.empty(n_samples, device=dev))
+    xyz, dl, sm, sl = out
+    r = rays.struct()
+    call("dvgo_resample_guarded", ctypes.byref(r), _p(ray_offsets), _p(counts), float(voxel), _p(xyz), _p(dl),
+         _p(sm), _p(sl), _stream())
     return SampleBatch(ray_offsets, xyz, dl, sm, sl, R, int(n_samples))
 
 

@@ -4,7 +4,9 @@ Pipeline per batch of rays (every stage a libdvgo kernel):
     proposal_coarse (64 uniform density-only samples -> weights -> ln(1 + w/eps))
     -> proposal_forward (64-64-64-64-64 MLP on BF16 matrix cores: logits, softmax, entropy)
     -> resample_offsets + resample (48 fine samples by inverse CDF; rays whose entropy
-       exceeds tau fall back to 256 uniform samples)
+       exceeds tau fall back to 256 uniform samples), or resample_guarded_offsets +
+       resample_guarded (coarse bins with weight nearby cut at plain spacing plus extra samples
+       by the predicted probabilities; empty and occluded bins skipped)
     -> the usual gather / colour MLP / render on the fine ragged batch.
 Training targets are the 64-bin histograms of the weights of a plain 256-sample render
 (density-only render_forward with per-sample weights -> histogram), the loss is the
@@ -78,3 +80,11 @@ def fine_batch(rays: ops.RayBatch, prob, entropy, tau, voxel, n_fine=48, n_plain
     S = int(offs[-1].item())
     return ops.resample(rays, prob, entropy, tau, offs, S, voxel, n_fine, n_plain)
 
+
+def guarded_batch(rays: ops.RayBatch, prob, w_coarse, entropy, tau, voxel, n_base=4, n_extra=32, w_min=1e-4):
+    """Ragged fine batch by guarded resampling: the coarse bins with weight nearby get n_base
+    sub-intervals plus a share of n_extra by the predicted probabilities, empty or occluded bins
+    none (one host read of the sample count)."""
+    offs, counts = ops.resample_guarded_offsets(rays, prob, w_coarse, entropy, tau, n_base, n_extra, w_min)
+    S = int(offs[-1].item())
+    return ops.resample_guarded(rays, offs, counts, S, voxel)

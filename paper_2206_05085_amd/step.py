@@ -23,7 +23,7 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, concurrent=True,
+                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, owner_scatter=True, concurrent=True,
                  fused_gather=True, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
@@ -34,7 +34,11 @@ class TrainStep:
         (FP32-grade colour head) or ops.MLP_F16 (the cheaper head, FP16 matrix operands).
         binned_scatter: the renderer writes per-sample density gradients, which are scattered
         brick by brick (samples binned once per step) instead of by in-wave aggregated atomics
-        inside the render kernel.  concurrent: in the feature-grid mode, run the binning, the
+        inside the render kernel.  owner_scatter (with binned_scatter): the density and feature
+        gradients are summed by the 8^3-vertex bricks that own the vertices (no atomics), and when
+        no TV term joins them, each grid's Adam update is fused into that sum (its gradient never
+        reaches memory); without it the density uses the atomic brick scatter and the features
+        the in-wave aggregated atomic scatter.  concurrent: in the feature-grid mode, run the binning, the
         density scatter, the density and MLP Adam updates and the colour head's preparation for
         the next step on a second stream, overlapped with the feature scatter and feature Adam
         (stream-ordered, graph-capturable).  A concurrent step leaves that preparation in the
@@ -54,6 +58,7 @@ class TrainStep:
         self.halt_T, self.bg, self.lam = halt_T, tuple(bg), dist_weight
         self.tv = None if tv is None else (float(tv[0]), float(tv[1]), float(tv[2]), bool(tv[3]))
         self.binned = bool(binned_scatter)
+        self.owner = self.binned and bool(owner_scatter)
         self.concurrent = bool(concurrent)
         self.side = None
         self.prepared_ahead = False  # the colour head's workspace holds the preparation for the next step
@@ -79,6 +84,24 @@ class TrainStep:
                                      n_freq=n_freq, precision=mlp_precision)
         self.batch = None
         self.schedule = None
+        self.successor = None
+
+    def share_parameters(self, other: "TrainStep") -> "TrainStep":
+        """Train the parameters (grids, colour head, moments, gradients and the Adam step counter)
+        of `other`: two steps bound to different batches then update one model."""
+        for name in ("density", "color", "feat", "mlp_flat", "mlp"):
+            if hasattr(other, name):
+                setattr(self, name, getattr(other, name))
+        self.t_dev = other.t_dev
+        return self
+
+    def chain(self, successor: "TrainStep") -> "TrainStep":
+        """The step that runs after this one (sharing its parameters, bound to another batch): this
+        step's tail prepares the colour head for it (from the updated weights and its batch), so
+        it skips its own preparation.  Steps (and graphs captured from them) must then run in the
+        chained order."""
+        self.successor = successor
+        return self
 
     @staticmethod
     def _param(p):
@@ -105,8 +128,16 @@ class TrainStep:
         if self.binned:
             # one binning per step serves every grid of the same geometry
             self.g_raw = torch.empty(S, device=d)
-            self.bin_ws = torch.empty(max(ops.bin_workspace_size(self.grid("density"), S), 1), dtype=torch.uint8,
-                                      device=d)
+            if self.owner:
+                self.own_ws = torch.empty(max(ops.owner_workspace_size(self.grid("density"), S), 1),
+                                          dtype=torch.uint8, device=d)
+                other = "color" if self.grid_mode else "feat"
+                same = tuple(getattr(self, other)["p"].shape[:3]) == tuple(self.density["p"].shape[:3])
+                self.own_ws_other = self.own_ws if same else torch.empty(
+                    max(ops.owner_workspace_size(self.grid(other), S), 1), dtype=torch.uint8, device=d)
+            else:
+                self.bin_ws = torch.empty(max(ops.bin_workspace_size(self.grid("density"), S), 1),
+                                          dtype=torch.uint8, device=d)
 
         self.loss = torch.zeros(1, device=d)
         self.g_rgb, self.g_dist = torch.empty(R, 3, device=d), torch.empty(R, device=d)
@@ -183,11 +214,50 @@ class TrainStep:
         ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, grad_rgb=self.g_rgb,
                       grad_dist=self.g_dist, want_loss=loss_value)
 
+    def _bin(self):
+        b = self.batch
+        if self.owner:
+            ops.owner_bin(self.grid("density"), b.xyz, ws=self.own_ws)
+            if self.own_ws_other is not self.own_ws:
+                ops.owner_bin(self.grid("color" if self.grid_mode else "feat"), b.xyz, ws=self.own_ws_other)
+        else:
+            ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
+
+    def _scatter_density(self):
+        b = self.batch
+        if self.owner:
+            ops.grid_scatter_owned(self.grid("density"), b.xyz, self.g_raw, self.own_ws)
+        else:
+            ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
+
+    def _scatter_feat(self):
+        b = self.batch
+        if self.owner:
+            ops.grid_scatter_owned(self.grid("feat"), b.xyz, self.g_feat_s, self.own_ws_other)
+        else:
+            # the 12-channel feature gradient keeps the in-wave aggregated scatter: its 9^3 brick
+            # tiles share half their vertices with neighbours, so brick atomics save nothing there
+            ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+
+    def _update(self, name, ws, vals, tv_w):
+        """The gradient of grid `name` from the per-sample values (owner sum), the TV term, and
+        Adam: fused into one kernel when there is no TV term."""
+        b = self.batch
+        if self.tv is None:
+            d = getattr(self, name)
+            b1, b2 = self.betas
+            ops.grid_scatter_adam(self.grid(name), b.xyz, vals, ws, d["m"], d["v"], lr=self.lr_grid, beta1=b1,
+                                  beta2=b2, eps=self.eps, step_dev=self.t_dev)
+            return
+        ops.grid_scatter_owned(self.grid(name), b.xyz, vals, ws)
+        ops.tv_add_grad(self.grid(name), tv_w, self.tv[2], self.tv[3])
+        self._adam(name, self.lr_grid, True)
+
     def backward(self):
         b = self.batch
         graw = None
         if self.binned:
-            ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
+            self._bin()
             graw = self.g_raw
         if self.grid_mode:
             ops.render_backward(b, self.grid("density"), self.grid("color"), None, self.T, self.state, self.g_rgb,
@@ -198,7 +268,7 @@ class TrainStep:
                                 self.g_dist, None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg,
                                 grad_sample_rgb=self.g_rgb_s, schedule=self.schedule, grad_sample_density=graw)
         if self.binned:
-            ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
+            self._scatter_density()
         if not self.grid_mode:
             self._mlp_backward_and_scatter()
         if self.tv is not None:
@@ -223,9 +293,7 @@ class TrainStep:
         b = self.batch
         ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
                          ws=self.mlp_ws, prepared=True)
-        # the 12-channel feature gradient keeps the in-wave aggregated scatter: its brick tiles
-        # share half their vertices with neighbours, so binning saves no atomics there
-        ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+        self._scatter_feat()
 
     def _adam(self, name, lr, skip):
         b1, b2 = self.betas
@@ -240,30 +308,110 @@ class TrainStep:
             self.backward()
             self.optimise()
             return self.loss
-        # Two streams.  main: the Adam step counter, colour head (with the feature gather fused into
-        # its forward), render forward and backward, colour-head backward (its weight gradients
-        # left as per-block partials), feature scatter, feature Adam.  side, after the colour-head
-        # backward: the binning, density scatter (+ TV), density Adam, the reduction of the weight
-        # gradients, MLP Adam, the colour head's preparation for the next step and the loss value,
-        # beside the feature scatter.  The colour-head backward
-        # takes nearly all of a CU's LDS and registers, so nothing is meant to run beside it; the
-        # forward runs alone too (the binning beside it slowed it more than the binning costs the
-        # side).  Main hands work to the side once (each hand-over delays main's next kernel in a
-        # graph), and every Adam launch follows the counter in stream order.  With the gather apart
-        # (features not a multiple of 4 channels) the side also runs the counter, the colour head's
-        # preparation and the binning beside the gather.  Each buffer has one writer at a time; the
-        # side joins main at the end.
+        if self.owner:
+            return self._step_owner()
+        return self._step_brick()
+
+    def _fork_side(self):
         main = torch.cuda.current_stream()
         if self.side is None:
             self.side = torch.cuda.Stream(device=self.device)
-        side = self.side
+        return main, self.side
+
+    def _prepare_if_stale(self):
+        b = self.batch
+        # in-place torch writes to the weights (or their views) bump their version; the library's
+        # own Adam does not
+        if not self.prepared_ahead or self._prep_version != self.mlp_flat["p"]._version:
+            ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
+
+    def _side_tail(self, main, side, density_work):
+        """After the colour-head backward: the side stream takes the density update, the colour
+        head's weight-gradient reduction and Adam, its preparation for the next step and the loss
+        value; main continues with the feature update."""
+        b = self.batch
+        side.wait_stream(main)
+        with torch.cuda.stream(side):
+            density_work()
+            ops.mlp_reduce_grads(self.mlp, b.n_rays, b.n_samples, self.mlp_ws)
+            self._adam("mlp_flat", self.lr_mlp, False)
+            if self.fused_gather:
+                # the next step's preparation, from the updated weights (main reads the workspace
+                # again only after the join); for a chained successor, with its batch
+                nxt = self.successor or self
+                nb = nxt.batch
+                ops.mlp_prepare(self.mlp, nb.ray_offsets, nxt.dirs, nb.n_samples, nxt.mlp_ws)
+            ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
+
+    def _step_owner(self):
+        # Two streams.  side, from the start: the owner binning of the samples (it depends only on
+        # the points), beside the forward.  main: the Adam step counter, the colour head (with the
+        # feature lookup fused into its forward), render forward and backward (per-sample density
+        # gradients), the colour-head backward (weight gradients left as per-block partials), then
+        # the feature update.  side, after the colour-head backward: the density update, the
+        # colour head's weight-gradient reduction and Adam, its preparation for the next step and
+        # the loss value.  A grid update is the owner-brick sum of its per-sample gradients fused
+        # with its Adam step, or, with a TV term, the sum, the TV gradient and Adam.  Every Adam
+        # launch follows the counter in stream order; each buffer has one writer at a time; the
+        # side joins main at the end.
+        main, side = self._fork_side()
+        b = self.batch
+        side.wait_stream(main)
+        if self.fused_gather:
+            ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+            self._prepare_if_stale()
+            with torch.cuda.stream(side):
+                self._bin()
+                binned = torch.cuda.Event()
+                binned.record(side)
+            self.forward(loss_value=False, prepared=True)
+        else:
+            ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
+            with torch.cuda.stream(side):
+                ops.counter_add(self.t_dev, 1)
+                ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
+                prepared = torch.cuda.Event()
+                prepared.record(side)
+                self._bin()
+                binned = torch.cuda.Event()
+                binned.record(side)
+            main.wait_event(prepared)
+            self.forward(gathered=True, loss_value=False, prepared=True)
+        ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
+                            None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
+                            schedule=self.schedule, grad_sample_density=self.g_raw)
+        ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
+                                  grad_feat=self.g_feat_s, prepared=True)
+        main.wait_event(binned)  # long satisfied; it also keeps a graph replay from delaying the binning
+        tv = self.tv
+        self._side_tail(main, side, lambda: self._update("density", self.own_ws, self.g_raw,
+                                                         tv[0] if tv else 0.0))
+        self._update("feat", self.own_ws_other, self.g_feat_s, tv[1] if tv else 0.0)
+        main.wait_stream(side)
+        self._handed_prep()
+        return self.loss
+
+    def _handed_prep(self):
+        nxt = self.successor or self
+        if nxt is not self:
+            self.prepared_ahead = False
+        nxt.prepared_ahead = self.fused_gather
+        nxt._prep_version = self.mlp_flat["p"]._version
+
+    def _step_brick(self):
+        # Two streams, atomic scatters.  main: the Adam step counter, colour head (with the feature
+        # gather fused into its forward), render forward and backward, colour-head backward (its
+        # weight gradients left as per-block partials), feature scatter, feature Adam.  side, after
+        # the colour-head backward: the binning, density scatter (+ TV), density Adam, the reduction
+        # of the weight gradients, MLP Adam, the colour head's preparation for the next step and the
+        # loss value, beside the feature scatter.  With the gather apart (features not a multiple of
+        # 4 channels) the side also runs the counter, the colour head's preparation and the binning
+        # beside the gather.
+        main, side = self._fork_side()
         b = self.batch
         if self.fused_gather:
             ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
-            # in-place torch writes to the weights (or their views) bump their version; the
-            # library's own Adam does not
-            if not self.prepared_ahead or self._prep_version != self.mlp_flat["p"]._version:
-                ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
+            self._prepare_if_stale()
             self.forward(loss_value=False, prepared=True)
         else:
             side.wait_stream(main)  # the side's first kernels depend on nothing of this step
@@ -288,28 +436,22 @@ class TrainStep:
         # the weight-gradient reduction waits on the side stream: only the MLP Adam needs it
         ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
                                   grad_feat=self.g_feat_s, prepared=True)
-        side.wait_stream(main)
-        with torch.cuda.stream(side):
+
+        def density_work():
             if self.fused_gather:
                 ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
             ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
             if self.tv is not None:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
             self._adam("density", self.lr_grid, True)
-            ops.mlp_reduce_grads(self.mlp, b.n_rays, b.n_samples, self.mlp_ws)
-            self._adam("mlp_flat", self.lr_mlp, False)
-            if self.fused_gather:
-                # the next step's preparation, from the updated weights (main reads the workspace
-                # again only after the join)
-                ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
-            ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
+
+        self._side_tail(main, side, density_work)
         ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
         if self.tv is not None:
             ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
         self._adam("feat", self.lr_grid, True)
         main.wait_stream(side)
-        self.prepared_ahead = self.fused_gather
-        self._prep_version = self.mlp_flat["p"]._version
+        self._handed_prep()
         return self.loss
 
     # ----------------------------------------------------------- HIP graphs

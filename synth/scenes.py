@@ -389,17 +389,24 @@ def config1(R=1024, N=128, n=32) -> Workload:
     return Workload("config1", dens, col, None, None, rays, smp, tgt)
 
 
-def config2(R=8192, N=256, n=160, C=12, lo=0.2, hi=1.0, mlp_bias_std=0.0) -> Workload:
-    """Fine-stage shape: 160^3 density + 160^3x12 features + colour MLP, pinhole rays, ragged mask."""
+def _batch_rng(cfg: int, stream: int, batch: int) -> np.random.Generator:
+    """Stream of batch 0 is the config's own; further batches of the same scene draw from their
+    own seeds (1000 cfg + 100 batch + stream)."""
+    return _rng(cfg, stream) if batch == 0 else np.random.Generator(np.random.PCG64(1000 * cfg + 100 * batch + stream))
+
+
+def config2(R=8192, N=256, n=160, C=12, lo=0.2, hi=1.0, mlp_bias_std=0.0, batch=0) -> Workload:
+    """Fine-stage shape: 160^3 density + 160^3x12 features + colour MLP, pinhole rays, ragged mask.
+    batch > 0: another independently seeded ray batch (rays, mask, targets) of the same scene."""
     c = 2
     dens = blob_density(_rng(c, 0), n)
     feat = normal_grid(_rng(c, 1), n, C)
     mlp = mlp_weights(_rng(c, 2), C, bias_std=mlp_bias_std)
-    rays = pinhole_rays(_rng(c, 3), R)
-    r4 = _rng(c, 4)
+    rays = pinhole_rays(_batch_rng(c, 3, batch), R)
+    r4 = _batch_rng(c, 4, batch)
     frac = r4.uniform(lo, hi, size=R)
     smp = uniform_samples(rays, N, dens.voxel_size(), live_frac=frac, rng=r4)
-    tgt = _rng(c, 5).random((R, 3)).astype(F32)
+    tgt = _batch_rng(c, 5, batch).random((R, 3)).astype(F32)
     return Workload("config2", dens, None, feat, mlp, rays, smp, tgt)
 
 

@@ -196,7 +196,7 @@ def test_render_halting_paper_mode(dv):
     # (R16) wherever only agreeing rays contribute, and with the slack a one-interval move of
     # the halt allows elsewhere (the weight beyond a halt is below thr).
     wl = synth.config1(R=4096)
-    wl.density.data += np.float32(6.0)   # opaque enough that most rays halt
+    wl.density.data += np.float32(8.5)   # opaque enough that most rays halt
     smp = wl.samples
     R, S = smp.n_rays, smp.n_samples
     thr = 1e-3
@@ -287,6 +287,7 @@ def test_validation_on_device(dv):
     finally:
         dv.set_debug(prev)
 
+@pytest.mark.parametrize("C", [1, 3, 12])
 def test_gather_scatter(dv, C):
     rng = np.random.default_rng(10 + C)
     g = synth.normal_grid(rng, 24, C)

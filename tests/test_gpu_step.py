@@ -108,18 +108,21 @@ def test_graph_replays_match_eager(pkg):
               name=f"mlp replay {rep}")
 
 
-@pytest.mark.parametrize("gather_apart", [False, True])
-def test_two_stream_step_matches_sequential(pkg, gather_apart):
-    # the step that overlaps the density scatter and the density / MLP Adam updates on a second
-    # stream (with the feature gather fused into the colour head's forward or run apart, which
-    # moves the counter, the preparation and the binning to the side stream) takes the same update
-    # as the strictly sequential step, eagerly and from a graph
+@pytest.mark.parametrize("gather_apart,tv,owner", [(False, True, True), (True, True, True), (False, False, True),
+                                                   (True, False, True), (False, True, False)])
+def test_two_stream_step_matches_sequential(pkg, gather_apart, tv, owner):
+    # the step that overlaps the density update and the MLP Adam on a second stream (with the
+    # feature gather fused into the colour head's forward or run apart, which moves the counter,
+    # the preparation and the binning to the side stream; with a TV term, or without one, where
+    # each grid's Adam is fused into its owner-brick scatter; or with the atomic scatters) takes the
+    # same update as the strictly sequential step, eagerly and from a graph
     ops, _, step = pkg
     wl = synth.config2(R=256, n=48)
-    say("two-stream step vs sequential, 48^3, 256 rays, TV on, gather apart", gather_apart)
+    say("two-stream step vs sequential, 48^3, 256 rays, gather apart", gather_apart, "TV", tv, "owner", owner)
+    tvt = (1e-3, 1e-4, 1.0, True) if tv else None
     mk = lambda conc, fg=True: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max),
                                               feat=wl.feat.data, mlp=(wl.mlp.W, wl.mlp.b),
-                                              dist_weight=wl.dist_weight, tv=(1e-3, 1e-4, 1.0, True),
+                                              dist_weight=wl.dist_weight, tv=tvt, owner_scatter=owner,
                                               concurrent=conc, fused_gather=fg)
     smp = wl.samples
     seq, conc, gr = mk(False), mk(True, not gather_apart), mk(True, not gather_apart)
@@ -139,12 +142,49 @@ def test_two_stream_step_matches_sequential(pkg, gather_apart):
             ref = getattr(seq, name)["p"].cpu().numpy()
             for other, tag in ((conc, "eager"), (gr, "graph")):
                 got = getattr(other, name)["p"].cpu().numpy()
-                if name == "mlp_flat":  # its gradient is reduced in a fixed order
-                    close(got, ref, rtol=1e-5, floor=1e-3, name=f"{name} two-stream {tag} step {rep}")
-                    continue
-                # grid gradients are sums of atomic adds, whose order differs between runs
-                close_after_adam(got, ref, 2 + rep, seq.lr_grid, name=f"{name} two-stream {tag} step {rep}")
+                # grid gradients are sums whose order differs between runs (atomics, on-chip sums),
+                # and the colour head's gradients follow from the grids of the steps before
+                lr = seq.lr_mlp if name == "mlp_flat" else seq.lr_grid
+                close_after_adam(got, ref, 2 + rep, lr, name=f"{name} two-stream {tag} step {rep}")
                 assert not getattr(other, name)["g"].any(), f"{name} gradient not cleared ({tag})"
+
+
+def test_chained_steps_rotate_batches(pkg):
+    # one model trained on two batches in turn: chained steps sharing the parameters (each step
+    # prepares the colour head for the next batch), replayed from graphs in turn, take the same
+    # updates as a sequential step that is re-bound to each batch before it runs
+    ops, _, step = pkg
+    wa, wb = synth.config2(R=200, n=48), synth.config2(R=240, n=48, batch=1)
+    say("chained steps over two batches, 48^3, 200 and 240 rays")
+    mk = lambda conc: step.TrainStep(wa.density.data, (wa.density.xyz_min, wa.density.xyz_max), feat=wa.feat.data,
+                                     mlp=(wa.mlp.W, wa.mlp.b), dist_weight=wa.dist_weight, concurrent=conc)
+    bat = lambda w: ops.SampleBatch.from_arrays(w.samples.ray_offsets, w.samples.xyz, w.samples.delta,
+                                                w.samples.s_mid, w.samples.s_len)
+    sa, sb = mk(True), mk(True)
+    sb.share_parameters(sa)
+    sa.bind(bat(wa), wa.rays.dirs, wa.target)
+    sb.bind(bat(wb), wb.rays.dirs, wb.target)
+    sa.chain(sb)
+    sb.chain(sa)
+    ref = mk(False)
+    order = [(wa, sa), (wb, sb)]
+    for w, s_ in order:  # eager warm-up, same order on the reference
+        s_.step()
+        ref.bind(bat(w), w.rays.dirs, w.target)
+        ref.step()
+    graphs = [sa.capture(warmup=0), sb.capture(warmup=0)]
+    for rep in range(4):
+        w, _ = order[rep % 2]
+        graphs[rep % 2].replay()
+        ref.bind(bat(w), w.rays.dirs, w.target)
+        ref.step()
+        torch.cuda.synchronize()
+        close(sa.mlp_flat["p"].cpu().numpy(), ref.mlp_flat["p"].cpu().numpy(), rtol=1e-5, floor=1e-3,
+              name=f"mlp after replay {rep}")
+        for name in ("density", "feat"):
+            close_after_adam(sa.__dict__[name]["p"].cpu().numpy(), ref.__dict__[name]["p"].cpu().numpy(), 3 + rep,
+                             sa.lr_grid, name=f"{name} after replay {rep}")
+    assert int(sa.t_dev.item()) == int(ref.t_dev.item()) == 6
 
 
 def test_prepared_ahead_follows_weight_edits(pkg):
