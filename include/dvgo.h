@@ -253,6 +253,18 @@ int dvgo_distortion_loss(int32_t n_rays, const int32_t *ray_offsets, int64_t n_s
                          const float *s_mid, const float *s_len, float *loss, const float *grad_loss, float *grad_w,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* dvgo_distortion_loss for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same computation and
+ * arguments, minus the workspace.  The backward's per-chunk checkpoints live in a fixed 2 MiB
+ * device array inside the library (one per GPU, held until the process ends), so a call
+ * allocates nothing; it accepts batches with n_samples/64 + n_rays + 1 <= 262144 checkpoints
+ * (e.g. 8192 rays of up to about 16.2 M samples in all) and returns DVGO_ERR_RANGE beyond.  Calls
+ * that overlap on one GPU share that array and race: serialise them (one stream, or events).
+ * Results equal dvgo_distortion_loss's bit for bit. */
+int dvgo_distortion_loss_noalloc(int32_t n_rays, const int32_t *ray_offsets, int64_t n_samples, const float *w,
+                                 const float *s_mid, const float *s_len, float *loss, const float *grad_loss,
+                                 float *grad_w, void *stream);
+
 /* Total-variation regulariser of a grid, gradient only (section 2, efficient TV loss: the
  * loss itself is not formed; its gradient is added into the grid gradient between the
  * backward pass and the optimiser step).  Loss read as

@@ -86,6 +86,7 @@ SIGNATURES = {
                                        C.POINTER(C.c_float), VP]),
     "dvgo_distortion_workspace_size": (C.c_int, [_I32, _I64, _SZP]),
     "dvgo_distortion_loss": (C.c_int, [_I32, VP, _I64, VP, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
+    "dvgo_distortion_loss_noalloc": (C.c_int, [_I32, VP, _I64, VP, VP, VP, VP, VP, VP, VP]),
     "dvgo_grid_adam_step": (C.c_int, [VP, VP, VP, VP, _I64, _F, _F, _F, _F, _I32, VP, _I32, _I32, VP]),
     "dvgo_counter_add": (C.c_int, [VP, _I32, VP]),
     "dvgo_grid_gather": (C.c_int, [_PG, _I64, VP, VP, VP]),

@@ -15,7 +15,7 @@ from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16
 
 __all__ = ["act_shift", "set_debug", "validate_samples", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
-           "render_backward", "distortion_workspace_size", "distortion_loss", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
+           "render_backward", "distortion_workspace_size", "distortion_loss", "distortion_loss_noalloc", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
            "grid_scatter", "grid_resample", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "owner_workspace_size", "owner_bin", "grid_scatter_owned", "grid_scatter_adam", "alpha", "mlp_workspace_size", "mlp_prepare", "mlp_forward", "mlp_forward_gather", "mlp_backward",
            "mlp_backward_partials", "mlp_reduce_grads", "loss_head",
            "resample_guarded_offsets", "resample_guarded", "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
@@ -321,6 +321,28 @@ def distortion_loss(ray_offsets, w, s_mid, s_len, grad_loss=None, grad_w=None, l
             ws = torch.empty(distortion_workspace_size(R, S), dtype=torch.uint8, device=w.device)
     call("dvgo_distortion_loss", R, _p(ray_offsets), S, _p(w), _p(s_mid), _p(s_len), _p(loss), _p(grad_loss),
          _p(grad_w), _p(ws), 0 if ws is None else ws.numel(), _stream())
+    return loss, grad_w
+
+
+def distortion_loss_noalloc(ray_offsets, w, s_mid, s_len, grad_loss=None, grad_w=None, loss=None):
+    """distortion_loss without a workspace: the backward's checkpoints live in the library's fixed
+    device array (no allocation by the library; loss / grad_w are allocated here only when not
+    given).  Calls that overlap on one GPU race."""
+    R = ray_offsets.numel() - 1
+    S = w.numel()
+    _chk(ray_offsets, "ray_offsets", torch.int32)
+    for t, n in ((w, "w"), (s_mid, "s_mid"), (s_len, "s_len")):
+        _chk(t, n, numel=S)
+    if loss is None:
+        loss = torch.empty(R, device=w.device)
+    _chk(loss, "loss", numel=R)
+    if grad_loss is not None:
+        _chk(grad_loss, "grad_loss", numel=R)
+        if grad_w is None:
+            grad_w = torch.zeros(S, device=w.device)
+        _chk(grad_w, "grad_w", numel=S)
+    call("dvgo_distortion_loss_noalloc", R, _p(ray_offsets), S, _p(w), _p(s_mid), _p(s_len), _p(loss), _p(grad_loss),
+         _p(grad_w) if grad_loss is not None else None, _stream())
     return loss, grad_w
 
 
