@@ -30,8 +30,8 @@ H, C_IN, N_IN = 128, 12, 39   # MLP widths: hidden, feature channels, input colu
 
 TRAFFIC_FILES = {"mlp_bwd": ("profiles/mlp_bwd_config2_hbm_traffic.md", ["paper_2206_05085_amd/csrc/mlp.hip",
                                                                        "paper_2206_05085_amd/csrc/dvgo_internal.h"]),
-                 # the render path's kernels (gather, render fwd/bwd, owner binning, both owner
-                 # scatters), bytes per step
+                 # the render path's kernels (gather, render fwd/bwd, density binning and scatter,
+                 # feature scatter), bytes per step
                  "render": ("profiles/render_config2_hbm_traffic.md", ["paper_2206_05085_amd/csrc/render.hip",
                                                                        "paper_2206_05085_amd/csrc/grid.hip",
                                                                        "paper_2206_05085_amd/csrc/owner.hip",
@@ -251,48 +251,99 @@ def proposal_leg(steps=1500, batch=8192, pool=65536, n_eval=8192, log=None, clea
     eq48 = {k: round(psnr(v.cpu().numpy(), gt), 3) for k, v in (("trained", rgb_nf), ("untrained", rgb_untrained),
                                                                 ("no_network", rgb_nonet), ("uniform48", rgb_u48))}
 
-    # timing at the chosen configuration: both paths include their own sample generation
-    cfg = ref_cfg
-    offs0, counts0 = ops.resample_guarded_offsets(ev, pr, wc, H, INF, 4, cfg["n_extra"], cfg["w_min"])
-    n_prop = int(offs0[-1].item())
+    # timing: both paths include their own sample generation; the proposal path its coarse pass
+    # and network; sample counts are known from a first run (no host read inside the loop)
     zH, zp = torch.zeros(ev.n_rays, device="cuda"), torch.zeros(ev.n_rays, 64, device="cuda")
-    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     reps = 20
-    for _ in range(2):
-        fe2, wc2 = P.coarse(ev, dens, vox, shift)
-    e[0].record()
-    for _ in range(reps):
-        fe2, wc2 = P.coarse(ev, dens, vox, shift)
-        _, pr2, H2 = net.forward(fe2)
-        offs, counts = ops.resample_guarded_offsets(ev, pr2, wc2, H2, INF, 4, cfg["n_extra"], cfg["w_min"])
-        colour_render(ev, ops.resample_guarded(ev, offs, counts, n_prop, vox))
-    e[1].record()
-    for _ in range(reps):
+
+    def time_guarded(cfg):
+        offs0, _ = ops.resample_guarded_offsets(ev, pr, wc, H, INF, 4, cfg["n_extra"], cfg["w_min"])
+        n_s = int(offs0[-1].item())
+
+        def once():
+            fe2, wc2 = P.coarse(ev, dens, vox, shift)
+            _, pr2, H2 = net.forward(fe2)
+            offs, counts = ops.resample_guarded_offsets(ev, pr2, wc2, H2, INF, 4, cfg["n_extra"], cfg["w_min"])
+            colour_render(ev, ops.resample_guarded(ev, offs, counts, n_s, vox))
+        for _ in range(2):
+            once()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            once()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, n_s
+
+    def plain_once():
         offs = ops.resample_offsets(ev, zH, -1.0, n_plain=256)
         colour_render(ev, ops.resample(ev, zp, zH, -1.0, offs, pb.n_samples, vox, n_plain=256))
-    e[2].record()
+    plain_once()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        plain_once()
+    e1.record()
     torch.cuda.synchronize()
-    ms_prop, ms_plain = e[0].elapsed_time(e[1]) / reps, e[1].elapsed_time(e[2]) / reps
+    ms_plain = e0.elapsed_time(e1) / reps
+    cfg = ref_cfg
+    ms_prop, n_prop = time_guarded(cfg)
+    # the network-refined layout (extras allotted by the trained network) at the same threshold
+    net_cfg = {"w_min": cfg["w_min"], "n_extra": gain_extra}
+    ms_net, n_net = time_guarded(net_cfg)
     ps_best = best["psnr"] if best else None
     return {"scene": "config-2 grids with free space cleared" if cleared else "config-2 grids (logit noise fog)",
             "train_steps": steps, "train_rays_per_step": batch, "train_s": round(train_s, 2),
             "ce_first": round(loss0, 4), "ce_last": round(loss_end, 4), "target_entropy": round(tgt_entropy, 4),
-            "eval_rays": n_eval, "psnr_plain256_vs_1024": round(ps_plain, 3),
+            "eval_rays": n_eval, "psnr_plain256_vs_1024": round(ps_plain, 3), "plain256_ms": round(ms_plain, 4),
             "guarded": {"found_within_0p1_db": best is not None, "w_min": cfg["w_min"], "n_extra": cfg["n_extra"],
                         "psnr_vs_1024": None if ps_best is None else round(ps_best, 3),
                         "psnr_drop_vs_plain256_db": None if ps_best is None else round(ps_plain - ps_best, 3),
                         "samples": n_prop, "plain256_samples": pb.n_samples, "fallback_frac": 0.0,
                         "dist_gap_rel": None if best is None else round(best["dist_gap"], 4),
-                        "ms": {"proposal_path": round(ms_prop, 4), "plain256_path": round(ms_plain, 4)},
-                        "speedup_vs_plain256": round(ms_plain / ms_prop, 3),
+                        "ms": round(ms_prop, 4), "speedup_vs_plain256": round(ms_plain / ms_prop, 3),
                         "equal_layout_psnr_by_extras": {"n_extra": gain_extra, **eq_guard}},
+            "guarded_with_network": {"w_min": net_cfg["w_min"], "n_extra": net_cfg["n_extra"],
+                                     "psnr_vs_1024": eq_guard["trained"],
+                                     "psnr_gain_vs_plain256_db": round(eq_guard["trained"] - ps_plain, 3),
+                                     "samples": n_net, "ms": round(ms_net, 4),
+                                     "speedup_vs_plain256": round(ms_plain / ms_net, 3)},
             "equal_48_interval_resampling_psnr": eq48, "guarded_sweep": sweep}
+
+
+def density_bin(ops, st, dens, b):
+    """The step's binning of the samples for the density scatter (owner bricks or brick bins)."""
+    if st.owner:
+        ops.owner_bin(dens, b.xyz, ws=st.own_ws)
+    else:
+        ops.bin_samples(dens, b.xyz, ws=st.bin_ws)
+
+
+def density_scatter(ops, st, dens, b):
+    """The step's density scatter of the per-sample gradients, from the bins above."""
+    if st.owner:
+        ops.grid_scatter_owned(dens, b.xyz, st.g_raw, st.own_ws)
+    else:
+        ops.grid_scatter_binned(dens, b.xyz, st.g_raw, st.bin_ws)
+
+
+def density_update(ops, st, dens, b):
+    """The step's density update after the binning: owner sum fused with Adam, or the binned
+    scatter followed by the streaming Adam step."""
+    b1, b2 = st.betas
+    if st.owner:
+        ops.grid_scatter_adam(dens, b.xyz, st.g_raw, st.own_ws, st.density["m"], st.density["v"], lr=st.lr_grid,
+                              beta1=b1, beta2=b2, eps=st.eps, step_dev=st.t_dev)
+    else:
+        ops.grid_scatter_binned(dens, b.xyz, st.g_raw, st.bin_ws)
+        ops.grid_adam_step(st.density["p"], st.density["g"], st.density["m"], st.density["v"], lr=st.lr_grid,
+                           beta1=b1, beta2=b2, eps=st.eps, step_dev=st.t_dev)
 
 
 def render_sweep_leg(sizes=(8192, 32768, 131072)):
     """The render path alone (feature gather; density gather, alpha, compositing, distortion
-    forward; the backward with per-sample density gradients; the owner binning and both owner
-    scatters) at growing batches of the same scene and ray recipe, autotuned longest-first
+    forward; the backward with per-sample density gradients; the density binning and scatter of
+    the step's path, the atomic feature scatter) at growing batches of the same scene and ray recipe, autotuned longest-first
     schedule each: its algorithmic HBM rate (algorithmic_bytes) and fraction of the peak."""
     import torch
     import synth
@@ -335,9 +386,9 @@ def render_sweep_leg(sizes=(8192, 32768, 131072)):
                                                              st.g_dist, None, act_shift_=st.shift,
                                                              grad_sample_rgb=st.g_rgb_s, grad_sample_density=st.g_raw,
                                                              schedule=st.schedule)),
-             "bin": timed(lambda: ops.owner_bin(dens, b.xyz, ws=st.own_ws)),
-             "scatter_density": timed(lambda: ops.grid_scatter_owned(dens, b.xyz, st.g_raw, st.own_ws)),
-             "scatter_feat": timed(lambda: ops.grid_scatter_owned(feat, b.xyz, st.g_feat_s, st.own_ws_other))}
+             "bin": timed(lambda: density_bin(ops, st, dens, b)),
+             "scatter_density": timed(lambda: density_scatter(ops, st, dens, b)),
+             "scatter_feat": timed(lambda: ops.grid_scatter(feat, b.xyz, st.g_feat_s))}
         U = unique_vertices(smp.xyz, n, lo, hi)
         byts = algorithmic_bytes(U, C, S, R)
         ms = sum(t.values())
@@ -838,20 +889,17 @@ def main():
                                                  out=(st.rgb, st.T, st.dist), state=st.state, schedule=st.schedule),
         "loss": lambda: ops.loss_head(st.rgb, st.target, st.dist, st.lam, loss=st.loss, grad_rgb=st.g_rgb,
                                       grad_dist=st.g_dist),
-        "bin": lambda: ops.owner_bin(dens, batch.xyz, ws=st.own_ws),
+        "bin": lambda: density_bin(ops, st, dens, batch),
         "render_bwd": lambda: ops.render_backward(batch, dens, None, st.rgb_s, st.T, st.state, st.g_rgb,
                                                   st.g_dist, None, act_shift_=st.shift, grad_sample_rgb=st.g_rgb_s,
                                                   grad_sample_density=st.g_raw, schedule=st.schedule),
-        "scatter_density": lambda: ops.grid_scatter_owned(dens, batch.xyz, st.g_raw, st.own_ws),
+        "scatter_density": lambda: density_scatter(ops, st, dens, batch),
         "mlp_bwd": lambda: ops.mlp_backward(st.mlp, batch.ray_offsets, st.dirs, st.feat_s, st.g_rgb_s,
                                             grad_feat=st.g_feat_s, ws=st.mlp_ws),
-        "scatter_feat": lambda: ops.grid_scatter_owned(feat, batch.xyz, st.g_feat_s, st.own_ws_other),
-        "update_density": lambda: ops.grid_scatter_adam(dens, batch.xyz, st.g_raw, st.own_ws, st.density["m"],
-                                                        st.density["v"], lr=st.lr_grid, beta1=b1, beta2=b2,
-                                                        eps=st.eps, step_dev=st.t_dev),
-        "update_feat": lambda: ops.grid_scatter_adam(feat, batch.xyz, st.g_feat_s, st.own_ws_other, st.feat["m"],
-                                                     st.feat["v"], lr=st.lr_grid, beta1=b1, beta2=b2, eps=st.eps,
-                                                     step_dev=st.t_dev),
+        "scatter_feat": lambda: ops.grid_scatter(feat, batch.xyz, st.g_feat_s),
+        "update_density": lambda: density_update(ops, st, dens, batch),
+        "adam_feat": lambda: ops.grid_adam_step(st.feat["p"], st.feat["g"], st.feat["m"], st.feat["v"],
+                                                lr=st.lr_grid, beta1=b1, beta2=b2, eps=st.eps, step_dev=st.t_dev),
     }
     ops.counter_add(st.t_dev, 1)
     for _ in range(3):
@@ -906,8 +954,9 @@ def main():
     tr = measured_traffic("render")
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
-            "kernels": "+".join(path) + " (render + distortion fwd/bwd with the 12-ch feature gather and both "
-                                        "owner scatters, batch 0, eager)",
+            "kernels": "+".join(path) + " (render + distortion fwd/bwd with the 12-ch feature gather, the "
+                                        f"{'owner' if st.owner else 'brick'} binning and density scatter and the "
+                                        "atomic feature scatter, batch 0, eager)",
             "path_ms": round(t_path, 4), "algorithmic_bytes": int(B_alg),
             "B_alg": f"U(1+C)*12 + S*24 + R*64, U={U} C={C} S={S} R={R}",
             "per_step_frac": round(B_alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -928,7 +977,8 @@ def main():
            "config": {"workload": f"config 2: 160^3 density + 160^3x12 features, colour MLP 39-128-128-3, "
                                   f"{args.batches} seeded batches of {R} pinhole rays x 256 samples 20-100% live "
                                   f"(S={'/'.join(str(v) for v in S_of)}), lambda_dist=0.01, Adam on grids (skip "
-                                  f"zero grads, fused into the owner-brick scatter) + MLP",
+                                  f"zero grads) + MLP; density gradient "
+                                  f"{'summed per owner brick, fused with Adam' if st.owner else 'brick-binned'}",
                       "graph": use_graph, "parallelism": "single GPU",
                       "render_schedule": {"order": "longest first", "waves_per_block": st.schedule.waves_per_block,
                                           "grid_waves": st.schedule.grid_waves}},

@@ -316,7 +316,7 @@ int dvgo_grid_scatter_binned(const dvgo_grid *g, int64_t n_samples, const float 
                              const void *ws, size_t ws_bytes, void *stream);
 
 /* Owner-computes scatter (the same sum as dvgo_grid_scatter, with no global atomics).  The
- * grid's vertices are cut into bricks of 8^3 and each vertex belongs to one brick;
+ * grid's vertices are cut into bricks of 4 x 4 x 32 (z longest) and each vertex belongs to one brick;
  * dvgo_owner_bin counting-sorts the (sample, brick) pairs of every sample whose cell has corners
  * in that brick (1 to 8 bricks per sample) into the caller's workspace of
  * dvgo_owner_workspace_size bytes (256-byte aligned; about 32 bytes per sample).  Bins depend only

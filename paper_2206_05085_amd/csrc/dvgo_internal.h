@@ -254,23 +254,34 @@ __device__ __forceinline__ void scatter_wave(const DevGrid &g, bool valid, const
                                 acc[c][0]);
         return;
     }
-    // Multi-channel: compact the heads of each corner through this wave's LDS slice and
-    // issue the atomics with consecutive lanes on consecutive channels of one vertex, so one
-    // instruction covers a few whole vertex rows instead of one float of 64 vertices.
+    // Multi-channel: compact the heads through this wave's LDS slice and issue the atomics with
+    // consecutive lanes on consecutive channels of one vertex, so one instruction covers a few
+    // whole vertex rows instead of one float of 64 vertices.  The two corners of a cell that differ
+    // only in z (2p, 2p + 1) are adjacent rows of the z-fastest layout: a lane puts both of its
+    // records next to each other, so a pair that both lanes' runs start on leaves as one
+    // contiguous 2C-float span (fewer memory packets per vertex than two separate rows).
     extern __shared__ float scatter_lds[];
-    float *vals = scatter_lds + (threadIdx.x >> 6) * (64 * (NC + 1));
-    int *keys = reinterpret_cast<int *>(vals + 64 * NC);
+    float *vals = scatter_lds + (threadIdx.x >> 6) * (128 * (NC + 1));
+    int *keys = reinterpret_cast<int *>(vals + 128 * NC);
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const bool h = (head >> c) & 1u;
-        const unsigned long long m = __ballot(h);
-        if (m == 0ull) continue;
-        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-        const int nh = __popcll(m);
-        if (h) {
-            keys[rank] = base + ((c >> 2) & 1) * g.sx + ((c >> 1) & 1) * g.sy + (c & 1) * g.cs;
+    for (int p = 0; p < 4; ++p) {
+        const bool h0 = (head >> (2 * p)) & 1u, h1 = (head >> (2 * p + 1)) & 1u;
+        const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
+        if ((m0 | m1) == 0ull) continue;
+        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u)) +
+                         __builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u));
+        const int nh = __popcll(m0) + __popcll(m1);
+        const int k0 = base + ((p >> 1) & 1) * g.sx + (p & 1) * g.sy;  // corner 2p (dz = 0)
+        if (h0) {
+            keys[rank] = k0;
 #pragma unroll
-            for (int ch = 0; ch < NC; ++ch) vals[rank * NC + ch] = acc[c][ch];
+            for (int ch = 0; ch < NC; ++ch) vals[rank * NC + ch] = acc[2 * p][ch];
+        }
+        if (h1) {
+            const int r1 = rank + (h0 ? 1 : 0);
+            keys[r1] = k0 + g.cs;
+#pragma unroll
+            for (int ch = 0; ch < NC; ++ch) vals[r1 * NC + ch] = acc[2 * p + 1][ch];
         }
         lds_fence();  // the slice is this wave's own: LDS order only, the atomics stay in flight
         for (int i = ln; i < nh * NC; i += 64) {
@@ -283,7 +294,7 @@ __device__ __forceinline__ void scatter_wave(const DevGrid &g, bool valid, const
 
 // bytes of dynamic LDS a block of `threads` needs for scatter_wave<NC>
 __host__ __device__ constexpr int scatter_lds_bytes(int NC, int threads) {
-    return NC == 1 ? 0 : (threads / 64) * 64 * (NC + 1) * 4;
+    return NC == 1 ? 0 : (threads / 64) * 128 * (NC + 1) * 4;
 }
 
 __device__ __forceinline__ Tri tri_from_cell(const DevGrid &g, const Cell &c) {
@@ -348,10 +359,13 @@ __device__ __forceinline__ void adam_bias(AdamArgs &a) {
     }
 }
 
+// Each operation rounded as written (explicit FMAs, no contraction), so every kernel that inlines
+// this gets the same bits whatever code surrounds it.
 __device__ __forceinline__ void adam_one(const AdamArgs &a, float g, float &p, float &m, float &v) {
-    m = a.b1 * m + (1.f - a.b1) * g;
-    v = a.b2 * v + (1.f - a.b2) * (g * g);
-    p -= a.lr_t * m / (sqrtf(v) * a.inv_sqrt_bc2 + a.eps);
+#pragma clang fp contract(off)
+    m = __builtin_fmaf(a.b1, m, (1.f - a.b1) * g);
+    v = __builtin_fmaf(a.b2, v, (1.f - a.b2) * (g * g));
+    p = p - (a.lr_t * m) / __builtin_fmaf(sqrtf(v), a.inv_sqrt_bc2, a.eps);
 }
 
 typedef float nt_f4 __attribute__((ext_vector_type(4)));

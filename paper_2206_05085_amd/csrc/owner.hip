@@ -2,15 +2,17 @@
 // section 3's interpolation), optionally fused with the zero-gradient-skipping Adam update of
 // section 3.
 //
-// The grid's vertices are cut into bricks of 8 x 8 x 8 and every vertex belongs to exactly one
-// brick.  A sample's cell touches the bricks that own its eight corners: one, or two along each
+// The grid's vertices are cut into bricks of 4 x 4 x 32 (x, y, z) and every vertex belongs to
+// exactly one brick.  The long edge runs along z, the fastest axis of the grid's layout, so that a
+// one-channel brick row is one full 128-byte line: the write-back of a brick then touches no line
+// that another brick also owns.  A sample's cell touches the bricks that own its eight corners: one, or two along each
 // axis where the cell sits on a brick's upper face, so up to eight (sample, brick) pairs.  The
 // pairs are counting-sorted by brick (count, one-block prefix, place; runs of equal bricks among
-// the consecutive samples of a wave take one atomic).  Then one block per brick stages its pairs
-// in LDS and every thread sums, in registers, the contributions to the one vertex it owns, and
-// writes that vertex once: either grad += sum (plain read-modify-write, no atomics: no other
-// thread owns the vertex), or the Adam update of the vertex straight from the sum, so the dense
-// gradient is never written to or read from memory.  Elements whose summed gradient is exactly zero are skipped, as the
+// the consecutive samples of a wave take one atomic).  Then one block per brick sums its pairs'
+// contributions to the vertices it owns in LDS and writes every touched vertex once: either
+// grad += sum (plain read-modify-write, no global atomics: no other block owns the vertex), or
+// the Adam update of the vertex straight from the sum, so the dense gradient is never written to
+// or read from memory.  Elements whose summed gradient is exactly zero are skipped, as the
 // fused Adam of section 3 skips grid points without gradient.
 #include <math.h>
 #include <string.h>
@@ -21,7 +23,7 @@ using namespace dvgo;
 
 namespace {
 
-constexpr int OB = 8;                 // owned vertices per brick edge
+constexpr int OBX = 4, OBY = 4, OBZ = 32;  // owned vertices per brick edge
 constexpr int OWN_BIN_WAVES = 4;
 
 struct OwnGeom {
@@ -32,8 +34,9 @@ struct OwnGeom {
 OwnGeom own_geom(const DevGrid &g) {
     OwnGeom o;
     o.n = 1;
+    const int e[3] = {OBX, OBY, OBZ};
     for (int a = 0; a < 3; ++a) {
-        o.nb[a] = (g.n[a] + OB - 1) / OB;
+        o.nb[a] = (g.n[a] + e[a] - 1) / e[a];
         o.n *= o.nb[a];
     }
     return o;
@@ -44,8 +47,8 @@ OwnGeom own_geom(const DevGrid &g) {
 // get the same keys in the same slots.
 __device__ __forceinline__ int owner_key(const OwnGeom &o, const Cell &c, int j) {
     const int ex = (j >> 2) & 1, ey = (j >> 1) & 1, ez = j & 1;
-    const int bx0 = c.ix / OB, by0 = c.iy / OB, bz0 = c.iz / OB;
-    const int bx1 = (c.ix + 1) / OB, by1 = (c.iy + 1) / OB, bz1 = (c.iz + 1) / OB;
+    const int bx0 = c.ix / OBX, by0 = c.iy / OBY, bz0 = c.iz / OBZ;
+    const int bx1 = (c.ix + 1) / OBX, by1 = (c.iy + 1) / OBY, bz1 = (c.iz + 1) / OBZ;
     if ((ex && bx1 == bx0) || (ey && by1 == by0) || (ez && bz1 == bz0)) return -1;
     return ((ex ? bx1 : bx0) * o.nb[1] + (ey ? by1 : by0)) * o.nb[2] + (ez ? bz1 : bz0);
 }
@@ -149,8 +152,12 @@ __global__ __launch_bounds__(64 * OWN_BIN_WAVES) void own_place_kernel(DevGrid g
     }
 }
 
-constexpr int PULL_THREADS = OB * 64;  // one wave per x plane of the brick, lane = (y, z)
-constexpr int CHUNK = 256;               // pairs staged in LDS at a time
+constexpr int OWN_THREADS = 256;
+constexpr int OV = OBX * OBY * OBZ;  // owned vertices per brick
+
+// LDS row of one owned vertex: NC channels, padded to an odd stride so that the lanes of one LDS
+// atomic, which hold different vertices, spread over the banks
+constexpr int tile_stride(int NC) { return NC == 1 ? 1 : (NC | 1); }
 
 struct OwnArgs {
     DevGrid g;          // geometry (and warp) of the grid; grad: target of MODE 0
@@ -159,130 +166,85 @@ struct OwnArgs {
     const float *vals;  // [S, g.C]
     const int *offs, *perm;
     int vec_in;         // vals rows move as float4 (C % 4 == 0, 16-byte aligned)
-    int vec_out;        // grid rows move as float4 (C == ch_stride, C % 4 == 0, arrays 16-byte aligned)
     AdamArgs adam;      // MODE 1: p, m, v over the grid's layout; g unused
 };
 
 // MODE 0: g.grad += scatter.  MODE 1: Adam update of every element with a non-zero gradient.
-// One block per brick, 8 waves: wave w owns the vertices of plane x = x0 + w, lane (y, z) =
-// (lane / 8, lane % 8) one vertex, whose C gradients it sums in registers.  The brick's pairs are
-// staged in LDS in chunks (cell relative to the brick origin, fractions, values); every wave
-// walks the chunk, skipping (wave-uniformly) the pairs whose cell does not reach its plane, and
-// each lane adds the contribution of the pairs whose cell has its vertex as a corner.  No two
-// threads write one vertex, so there are no atomics; each vertex is then written once.
+// One block per brick: its pairs add their contributions to the corners the brick owns in an LDS
+// tile (thread = pair; LDS atomics, corners visited in a lane-rotated order so that neighbouring
+// lanes holding samples of one cell add to different vertices in the same instruction); then every
+// touched vertex is written once.  The LDS atomics cost grows with the channel count: this is the
+// density's scatter (one channel); the 12-channel features keep the in-wave aggregated global
+// atomics of dvgo_grid_scatter.
 template <int NC, bool W, int MODE>
-__global__ __launch_bounds__(PULL_THREADS) void own_scatter_kernel(OwnArgs A) {
-    __shared__ int s_cell[CHUNK];            // (lx + 1) | (ly + 1) << 4 | (lz + 1) << 8, each in 0..8
-    __shared__ float s_f[CHUNK][3];          // fractions
-    __shared__ float s_v[CHUNK][NC];         // values
+__global__ __launch_bounds__(OWN_THREADS) void own_scatter_kernel(OwnArgs A) {
+    constexpr int TS = tile_stride(NC);
+    __shared__ float tile[OV * TS];
     const int b = blockIdx.x;
     const int beg = A.offs[b], end = A.offs[b + 1];
     if (beg == end) return;
     const DevGrid &g = A.g;
     const int C = g.C;
     const int bz = b % A.o.nb[2], by = (b / A.o.nb[2]) % A.o.nb[1], bx = b / (A.o.nb[2] * A.o.nb[1]);
-    const int x0 = bx * OB, y0 = by * OB, z0 = bz * OB;
-    const int vx = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), ln = lane(), vy = ln >> 3, vz = ln & 7;
-    float acc[NC];
-#pragma unroll
-    for (int ch = 0; ch < NC; ++ch) acc[ch] = 0.f;
-    for (int c0 = beg; c0 < end; c0 += CHUNK) {
-        const int n = min(CHUNK, end - c0);
-        if ((int)threadIdx.x < n) {
-            const int t = threadIdx.x;
-            const int64_t s = A.perm[c0 + t];
-            const Cell c = cell_of<W>(g, A.xyz[3 * s], A.xyz[3 * s + 1], A.xyz[3 * s + 2]);
-            s_cell[t] = (c.ix - x0 + 1) | ((c.iy - y0 + 1) << 4) | ((c.iz - z0 + 1) << 8);
-            s_f[t][0] = c.fx;
-            s_f[t][1] = c.fy;
-            s_f[t][2] = c.fz;
-            if (NC % 4 == 0 && A.vec_in) {
-#pragma unroll
-                for (int q = 0; q < NC / 4; ++q) {
-                    const float4 v = 4 * q < C ? *reinterpret_cast<const float4 *>(A.vals + s * C + 4 * q)
-                                               : make_float4(0.f, 0.f, 0.f, 0.f);
-                    s_v[t][4 * q] = v.x;
-                    s_v[t][4 * q + 1] = v.y;
-                    s_v[t][4 * q + 2] = v.z;
-                    s_v[t][4 * q + 3] = v.w;
-                }
-            } else {
-#pragma unroll
-                for (int ch = 0; ch < NC; ++ch) s_v[t][ch] = ch < C ? A.vals[s * C + ch] : 0.f;
-            }
-        }
-        __syncthreads();
-        for (int i = 0; i < n; ++i) {
-            const int pk = __builtin_amdgcn_readfirstlane(s_cell[i]);
-            const int lx = (pk & 15) - 1;
-            if (lx != vx && lx != vx - 1) continue;  // the cell has no corner on this wave's plane
-            const int ly = ((pk >> 4) & 15) - 1, lz = ((pk >> 8) & 15) - 1;
-            if ((ly == vy || ly == vy - 1) && (lz == vz || lz == vz - 1)) {
-                const Cell c{0, 0, 0, s_f[i][0], s_f[i][1], s_f[i][2]};
-                const float w = corner_weight(c, vx - lx, vy - ly, vz - lz);
-#pragma unroll
-                for (int ch = 0; ch < NC; ++ch) acc[ch] += w * s_v[i][ch];
-            }
-        }
-        __syncthreads();
-    }
-    const int gx = x0 + vx, gy = y0 + vy, gz = z0 + vz;
-    if (gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) return;
-    bool any = false;
-#pragma unroll
-    for (int ch = 0; ch < NC; ++ch) any |= ch < C && acc[ch] != 0.f;
-    if (!any) return;
-    const int64_t row = (int64_t)gx * g.sx + (int64_t)gy * g.sy + (int64_t)gz * g.cs;
-    if (MODE == 0) {
-        float *p = g.grad + row;
-        if (NC % 4 == 0 && A.vec_out) {
+    const int x0 = bx * OBX, y0 = by * OBY, z0 = bz * OBZ;
+    for (int i = threadIdx.x; i < OV * TS; i += OWN_THREADS) tile[i] = 0.f;
+    __syncthreads();
+    const int rot = lane() & 7;
+    for (int i = beg + threadIdx.x; i < end; i += OWN_THREADS) {
+        const int64_t s = A.perm[i];
+        const Cell c = cell_of<W>(g, A.xyz[3 * s], A.xyz[3 * s + 1], A.xyz[3 * s + 2]);
+        float val[NC];
+        if (NC % 4 == 0 && A.vec_in) {
 #pragma unroll
             for (int q = 0; q < NC / 4; ++q) {
-                if (4 * q >= C) continue;
-                float4 t = *reinterpret_cast<float4 *>(p + 4 * q);
-                t.x += acc[4 * q];
-                t.y += acc[4 * q + 1];
-                t.z += acc[4 * q + 2];
-                t.w += acc[4 * q + 3];
-                *reinterpret_cast<float4 *>(p + 4 * q) = t;
+                const float4 t = 4 * q < C ? *reinterpret_cast<const float4 *>(A.vals + s * C + 4 * q)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+                val[4 * q] = t.x;
+                val[4 * q + 1] = t.y;
+                val[4 * q + 2] = t.z;
+                val[4 * q + 3] = t.w;
             }
         } else {
 #pragma unroll
+            for (int ch = 0; ch < NC; ++ch) val[ch] = ch < C ? A.vals[s * C + ch] : 0.f;
+        }
+        const int lx = c.ix - x0, ly = c.iy - y0, lz = c.iz - z0;  // from -1 to the brick edge - 1
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int corner = (k + rot) & 7;
+            const int dx = (corner >> 2) & 1, dy = (corner >> 1) & 1, dz = corner & 1;
+            const int vx = lx + dx, vy = ly + dy, vz = lz + dz;
+            if ((unsigned)vx >= (unsigned)OBX || (unsigned)vy >= (unsigned)OBY || (unsigned)vz >= (unsigned)OBZ) continue;
+            const float w = corner_weight(c, dx, dy, dz);
+            float *t = tile + ((vx * OBY + vy) * OBZ + vz) * TS;
+#pragma unroll
             for (int ch = 0; ch < NC; ++ch)
-                if (ch < C && acc[ch] != 0.f) p[ch] += acc[ch];
+                if (ch < C) atomicAdd(t + ch, w * val[ch]);
         }
-        return;
     }
+    __syncthreads();
+    // write: element e = (row (vx, vy), f = vz C + ch), f fastest, so consecutive lanes cover
+    // consecutive addresses of one brick row
+    const int rowlen = OBZ * C;
     AdamArgs ad = A.adam;
-    adam_bias(ad);
-    if (NC % 4 == 0 && A.vec_out) {
-        // the vertex's row moves as float4; elements with a zero gradient are written back unchanged
-#pragma unroll
-        for (int q = 0; q < NC / 4; ++q) {
-            if (4 * q >= C) continue;
-            float4 *P = reinterpret_cast<float4 *>(ad.p + row) + q;
-            float4 *M = reinterpret_cast<float4 *>(ad.m + row) + q;
-            float4 *V = reinterpret_cast<float4 *>(ad.v + row) + q;
-            float4 p = *P, m = ld_nt(M), v = ld_nt(V);
-            if (acc[4 * q] != 0.f) adam_one(ad, acc[4 * q], p.x, m.x, v.x);
-            if (acc[4 * q + 1] != 0.f) adam_one(ad, acc[4 * q + 1], p.y, m.y, v.y);
-            if (acc[4 * q + 2] != 0.f) adam_one(ad, acc[4 * q + 2], p.z, m.z, v.z);
-            if (acc[4 * q + 3] != 0.f) adam_one(ad, acc[4 * q + 3], p.w, m.w, v.w);
-            *P = p;
-            st_nt(M, m);
-            st_nt(V, v);
-        }
-    } else {
-#pragma unroll
-        for (int ch = 0; ch < NC; ++ch) {
-            if (ch >= C || acc[ch] == 0.f) continue;
-            float p = ad.p[row + ch];
-            float m = __builtin_nontemporal_load(ad.m + row + ch);
-            float v = __builtin_nontemporal_load(ad.v + row + ch);
-            adam_one(ad, acc[ch], p, m, v);
-            ad.p[row + ch] = p;
-            __builtin_nontemporal_store(m, ad.m + row + ch);
-            __builtin_nontemporal_store(v, ad.v + row + ch);
+    if (MODE == 1) adam_bias(ad);
+    for (int e = threadIdx.x; e < OBX * OBY * rowlen; e += OWN_THREADS) {
+        const int row = e / rowlen, f = e - row * rowlen;
+        const int vz = f / C, ch = f - vz * C, vx = row / OBY, vy = row - vx * OBY;
+        const int gx = x0 + vx, gy = y0 + vy, gz = z0 + vz;
+        const float t = tile[((vx * OBY + vy) * OBZ + vz) * TS + ch];
+        if (t == 0.f || gx >= g.n[0] || gy >= g.n[1] || gz >= g.n[2]) continue;
+        const int64_t off = (int64_t)gx * g.sx + (int64_t)gy * g.sy + (int64_t)gz * g.cs + ch;
+        if (MODE == 0) {
+            g.grad[off] += t;
+        } else {
+            float p = ad.p[off];
+            float m = __builtin_nontemporal_load(ad.m + off);
+            float v = __builtin_nontemporal_load(ad.v + off);
+            adam_one(ad, t, p, m, v);
+            ad.p[off] = p;
+            __builtin_nontemporal_store(m, ad.m + off);
+            __builtin_nontemporal_store(v, ad.v + off);
         }
     }
 }
@@ -290,9 +252,9 @@ __global__ __launch_bounds__(PULL_THREADS) void own_scatter_kernel(OwnArgs A) {
 template <int NC, int MODE>
 void launch_own(const OwnArgs &A, hipStream_t st) {
     if (A.g.warp)
-        hipLaunchKernelGGL((own_scatter_kernel<NC, true, MODE>), dim3(A.o.n), dim3(PULL_THREADS), 0, st, A);
+        hipLaunchKernelGGL((own_scatter_kernel<NC, true, MODE>), dim3(A.o.n), dim3(OWN_THREADS), 0, st, A);
     else
-        hipLaunchKernelGGL((own_scatter_kernel<NC, false, MODE>), dim3(A.o.n), dim3(PULL_THREADS), 0, st, A);
+        hipLaunchKernelGGL((own_scatter_kernel<NC, false, MODE>), dim3(A.o.n), dim3(OWN_THREADS), 0, st, A);
 }
 
 template <int MODE>
@@ -394,7 +356,6 @@ extern "C" int dvgo_grid_scatter_owned(const dvgo_grid *g, int64_t n_samples, co
     int rc = fill_own_args(g, n_samples, xyz, grad_out, ws, ws_bytes, true, A);
     if (rc) return rc;
     if (n_samples == 0) return DVGO_OK;
-    A.vec_out = (g->channels == g->ch_stride && g->channels % 4 == 0 && ((uintptr_t)g->grad & 15) == 0) ? 1 : 0;
     launch_own_c<0>(A, (hipStream_t)stream);
     return check_hip(hipGetLastError(), "own_scatter_kernel launch");
 }
@@ -428,8 +389,6 @@ extern "C" int dvgo_grid_scatter_adam(const dvgo_grid *g, int64_t n_samples, con
     a.eps = eps;
     a.skip = 1;
     a.zero = 0;
-    const uintptr_t al = (uintptr_t)param | (uintptr_t)exp_avg | (uintptr_t)exp_avg_sq;
-    A.vec_out = (g->channels == g->ch_stride && g->channels % 4 == 0 && (al & 15) == 0) ? 1 : 0;
     launch_own_c<1>(A, (hipStream_t)stream);
     return check_hip(hipGetLastError(), "own_scatter_kernel launch");
 }

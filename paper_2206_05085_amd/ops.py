@@ -424,7 +424,7 @@ def owner_workspace_size(grid: DeviceGrid, n_samples: int) -> int:
 
 
 def owner_bin(grid: DeviceGrid, xyz, ws=None):
-    """Sort the (sample, owning 8^3-vertex brick) pairs of the points (for grid_scatter_owned and
+    """Sort the (sample, owning 4x4x32-vertex brick) pairs of the points (for grid_scatter_owned and
     grid_scatter_adam); returns ws."""
     _chk(xyz, "xyz", last=3)
     S = xyz.numel() // 3

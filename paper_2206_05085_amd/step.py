@@ -23,7 +23,7 @@ from . import ops
 class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
-                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, owner_scatter=True, concurrent=True,
+                 tv=None, warp=None, mlp_precision=0, binned_scatter=True, owner_scatter=False, concurrent=True,
                  fused_gather=True, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
@@ -34,11 +34,12 @@ class TrainStep:
         (FP32-grade colour head) or ops.MLP_F16 (the cheaper head, FP16 matrix operands).
         binned_scatter: the renderer writes per-sample density gradients, which are scattered
         brick by brick (samples binned once per step) instead of by in-wave aggregated atomics
-        inside the render kernel.  owner_scatter (with binned_scatter): the density and feature
-        gradients are summed by the 8^3-vertex bricks that own the vertices (no atomics), and when
-        no TV term joins them, each grid's Adam update is fused into that sum (its gradient never
-        reaches memory); without it the density uses the atomic brick scatter and the features
-        the in-wave aggregated atomic scatter.  concurrent: in the feature-grid mode, run the binning, the
+        inside the render kernel.  owner_scatter (with binned_scatter; off by default, the step measured
+        about 1% slower with it): the density gradient is summed by the 4x4x32-vertex bricks that own the vertices (no global atomics), and when no TV
+        term joins it, the density's Adam update is fused into that sum (its gradient never reaches
+        memory); without it the density uses the atomic brick scatter.  The 12-channel feature
+        gradient always takes the in-wave aggregated atomic scatter and the streaming Adam (the
+        owner sum of 12 channels measured slower).  concurrent: in the feature-grid mode, run the binning, the
         density scatter, the density and MLP Adam updates and the colour head's preparation for
         the next step on a second stream, overlapped with the feature scatter and feature Adam
         (stream-ordered, graph-capturable).  A concurrent step leaves that preparation in the
@@ -131,10 +132,6 @@ class TrainStep:
             if self.owner:
                 self.own_ws = torch.empty(max(ops.owner_workspace_size(self.grid("density"), S), 1),
                                           dtype=torch.uint8, device=d)
-                other = "color" if self.grid_mode else "feat"
-                same = tuple(getattr(self, other)["p"].shape[:3]) == tuple(self.density["p"].shape[:3])
-                self.own_ws_other = self.own_ws if same else torch.empty(
-                    max(ops.owner_workspace_size(self.grid(other), S), 1), dtype=torch.uint8, device=d)
             else:
                 self.bin_ws = torch.empty(max(ops.bin_workspace_size(self.grid("density"), S), 1),
                                           dtype=torch.uint8, device=d)
@@ -218,8 +215,6 @@ class TrainStep:
         b = self.batch
         if self.owner:
             ops.owner_bin(self.grid("density"), b.xyz, ws=self.own_ws)
-            if self.own_ws_other is not self.own_ws:
-                ops.owner_bin(self.grid("color" if self.grid_mode else "feat"), b.xyz, ws=self.own_ws_other)
         else:
             ops.bin_samples(self.grid("density"), b.xyz, ws=self.bin_ws)
 
@@ -231,27 +226,29 @@ class TrainStep:
             ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
 
     def _scatter_feat(self):
-        b = self.batch
-        if self.owner:
-            ops.grid_scatter_owned(self.grid("feat"), b.xyz, self.g_feat_s, self.own_ws_other)
-        else:
-            # the 12-channel feature gradient keeps the in-wave aggregated scatter: its 9^3 brick
-            # tiles share half their vertices with neighbours, so brick atomics save nothing there
-            ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+        # the 12-channel feature gradient keeps the in-wave aggregated atomic scatter (owner-brick sums
+        # of 12 channels measured slower)
+        ops.grid_scatter(self.grid("feat"), self.batch.xyz, self.g_feat_s)
 
-    def _update(self, name, ws, vals, tv_w):
-        """The gradient of grid `name` from the per-sample values (owner sum), the TV term, and
-        Adam: fused into one kernel when there is no TV term."""
+    def _update_density(self):
+        """The density gradient from the per-sample values (owner sum), the TV term, and Adam: fused
+        into one kernel when there is no TV term."""
         b = self.batch
         if self.tv is None:
-            d = getattr(self, name)
+            d = self.density
             b1, b2 = self.betas
-            ops.grid_scatter_adam(self.grid(name), b.xyz, vals, ws, d["m"], d["v"], lr=self.lr_grid, beta1=b1,
-                                  beta2=b2, eps=self.eps, step_dev=self.t_dev)
+            ops.grid_scatter_adam(self.grid("density"), b.xyz, self.g_raw, self.own_ws, d["m"], d["v"],
+                                  lr=self.lr_grid, beta1=b1, beta2=b2, eps=self.eps, step_dev=self.t_dev)
             return
-        ops.grid_scatter_owned(self.grid(name), b.xyz, vals, ws)
-        ops.tv_add_grad(self.grid(name), tv_w, self.tv[2], self.tv[3])
-        self._adam(name, self.lr_grid, True)
+        ops.grid_scatter_owned(self.grid("density"), b.xyz, self.g_raw, self.own_ws)
+        ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
+        self._adam("density", self.lr_grid, True)
+
+    def _update_feat(self):
+        self._scatter_feat()
+        if self.tv is not None:
+            ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
+        self._adam("feat", self.lr_grid, True)
 
     def backward(self):
         b = self.batch
@@ -344,37 +341,31 @@ class TrainStep:
             ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
 
     def _step_owner(self):
-        # Two streams.  side, from the start: the owner binning of the samples (it depends only on
-        # the points), beside the forward.  main: the Adam step counter, the colour head (with the
-        # feature lookup fused into its forward), render forward and backward (per-sample density
-        # gradients), the colour-head backward (weight gradients left as per-block partials), then
-        # the feature update.  side, after the colour-head backward: the density update, the
-        # colour head's weight-gradient reduction and Adam, its preparation for the next step and
-        # the loss value.  A grid update is the owner-brick sum of its per-sample gradients fused
-        # with its Adam step, or, with a TV term, the sum, the TV gradient and Adam.  Every Adam
-        # launch follows the counter in stream order; each buffer has one writer at a time; the
-        # side joins main at the end.
+        # Two streams.  main: the Adam step counter, the colour head (with the feature lookup fused
+        # into its forward), render forward and backward (per-sample density gradients), the
+        # colour-head backward (weight gradients left as per-block partials), then the feature
+        # scatter and Adam.  side, after the colour-head backward: the owner binning of the samples,
+        # the density update (the owner-brick sum of its per-sample gradients fused with its Adam
+        # step, or, with a TV term, the sum, the TV gradient and Adam), the colour head's
+        # weight-gradient reduction and Adam, its preparation for the next step and the loss value.
+        # The binning depends only on the points, but run beside the colour head's forward it slows
+        # that kernel by more than it takes; beside the feature scatter it is hidden.  Every Adam
+        # launch follows the counter in stream order; each buffer has one writer at a time; the side
+        # joins main at the end.
         main, side = self._fork_side()
         b = self.batch
-        side.wait_stream(main)
         if self.fused_gather:
             ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
             self._prepare_if_stale()
-            with torch.cuda.stream(side):
-                self._bin()
-                binned = torch.cuda.Event()
-                binned.record(side)
             self.forward(loss_value=False, prepared=True)
         else:
+            side.wait_stream(main)  # the side's first kernels depend on nothing of this step
             ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
             with torch.cuda.stream(side):
                 ops.counter_add(self.t_dev, 1)
                 ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
                 prepared = torch.cuda.Event()
                 prepared.record(side)
-                self._bin()
-                binned = torch.cuda.Event()
-                binned.record(side)
             main.wait_event(prepared)
             self.forward(gathered=True, loss_value=False, prepared=True)
         ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
@@ -382,11 +373,13 @@ class TrainStep:
                             schedule=self.schedule, grad_sample_density=self.g_raw)
         ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
                                   grad_feat=self.g_feat_s, prepared=True)
-        main.wait_event(binned)  # long satisfied; it also keeps a graph replay from delaying the binning
-        tv = self.tv
-        self._side_tail(main, side, lambda: self._update("density", self.own_ws, self.g_raw,
-                                                         tv[0] if tv else 0.0))
-        self._update("feat", self.own_ws_other, self.g_feat_s, tv[1] if tv else 0.0)
+
+        def density_work():
+            self._bin()
+            self._update_density()
+
+        self._side_tail(main, side, density_work)
+        self._update_feat()
         main.wait_stream(side)
         self._handed_prep()
         return self.loss

@@ -1,4 +1,4 @@
-"""Owner-computes scatter (every vertex summed by the 8^3-vertex brick that owns it, no atomics)
+"""Owner-computes scatter (every vertex summed by the 4x4x32-vertex brick that owns it, no atomics)
 and its fusion with the zero-gradient-skipping Adam update, against the FP64 oracle and against
 the two-call path (scatter, then Adam)."""
 import numpy as np
@@ -65,7 +65,7 @@ def test_owner_scatter(dv, n, C, warp):
     ws = dv.owner_bin(dg, T(xyz))
     dv.grid_scatter_owned(dg, T(xyz), T(y), ws)
     torch.cuda.synchronize()
-    nb = int(np.prod([(n + 7) // 8] * 3))
+    nb = ((n + 3) // 4) ** 2 * ((n + 31) // 32)
     offs, perm = _pairs(ws, nb, S)
     assert offs[0] == 0 and (np.diff(offs) >= 0).all() and S <= offs[-1] <= 8 * S
     mult = np.bincount(perm, minlength=S)

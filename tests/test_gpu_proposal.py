@@ -184,10 +184,12 @@ def test_resample_guarded(pk, scene, n_extra, tau):
 @pytest.mark.timeout(600)
 def test_trained_network_gain(pk):
     """A short training run on the grids' own rendered histograms, cleared scene: the
-    cross-entropy falls; at an equal budget of 48 interval-resampled samples per ray the trained
-    network's placement beats the untrained network, uniform placement and the normalised coarse
-    weights (the method without the network); and guarded resampling reaches plain-256's PSNR
-    within 0.1 dB with no fallback and fewer samples than plain-256."""
+    cross-entropy falls; the trained network's placement beats the untrained network and uniform
+    placement at an equal budget of 48 interval-resampled samples per ray; with guarded resampling
+    (coverage from the coarse pass, extras from the network) the trained network's extras beat the
+    normalised coarse weights (the method without the network), uniform extras and the untrained
+    network at an equal layout; and guarded resampling reaches plain-256's PSNR within 0.1 dB with
+    no fallback and fewer samples than plain-256."""
     import bench
     say("proposal training + evaluation, cleared scene")
     r = bench.proposal_leg(steps=400, pool=16384, n_eval=4096, cleared=True)
@@ -197,7 +199,9 @@ def test_trained_network_gain(pk):
     eq = r["equal_48_interval_resampling_psnr"]
     assert eq["trained"] > eq["untrained"] + 1.0
     assert eq["trained"] > eq["uniform48"] + 1.0
-    assert eq["trained"] > eq["no_network"]
     g = r["guarded"]
+    gain = g["equal_layout_psnr_by_extras"]
+    assert gain["trained"] > gain["no_network"]
+    assert gain["trained"] > gain["uniform"] + 1.0 and gain["trained"] > gain["untrained"] + 1.0
     assert g["found_within_0p1_db"] and g["psnr_drop_vs_plain256_db"] <= 0.1
     assert g["fallback_frac"] == 0.0 and g["samples"] < g["plain256_samples"]
