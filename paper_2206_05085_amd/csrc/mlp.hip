@@ -100,14 +100,22 @@ __device__ __forceinline__ int ceil_exp(float m) {
     return k;
 }
 
+// hi and lo parts of two values in packed halves: hi = fp16(t0), fp16(t1) from one packed
+// conversion (round to nearest even, as every float -> half conversion here), lo = fp16(t - hi)
+// of each from one mixed-precision FMA that writes its half of the register directly (t - hi is
+// exact in FP32, so each equals (_Float16)(t - (float)hi)).
+__device__ __forceinline__ void split2(float t0, float t1, unsigned &hi, unsigned &lo) {
+    asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(hi) : "v"(t0), "v"(t1));
+    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(lo) : "v"(t0), "v"(hi));
+    asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(lo) : "v"(t1), "v"(hi));
+}
+
 __device__ __forceinline__ void split4(const float v[4], float sc, h4 &hi, h4 &lo) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const float t = v[r] * sc;
-        const _Float16 h = (_Float16)t;
-        hi[r] = h;
-        lo[r] = (_Float16)(t - (float)h);
-    }
+    uint2 h, l;
+    split2(v[0] * sc, v[1] * sc, h.x, l.x);
+    split2(v[2] * sc, v[3] * sc, h.y, l.y);
+    hi = __builtin_bit_cast(h4, h);
+    lo = __builtin_bit_cast(h4, l);
 }
 
 __device__ __forceinline__ h8 cat(h4 a, h4 b) { return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7); }
@@ -578,10 +586,10 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
 // (4..7) own the same units for the backward chain and hold those rows of W2^T.  The C
 // waves run one tile behind, so every phase pairs P and C work on the same SIMDs.  Phases
 // of iteration t (block-wide barriers between them; the inputs of t are already staged):
-//   A  P: layer 1 of t -> h1 B operand, h1^T, mask bits    C: dz1, dfeat partials, dz1^T of t-1
+//   A  P: layer 1 of t -> h1 plane, mask bits              C: dz1 of t-1 (frame plane), dfeat partials
 //   B  P: layer 2 of t -> h2, logit partials                C: dW1 += dz1^T x of t-1; loads of t+1
-//   C  P: dz3, dz2 of t -> dz2 B operand, dz2^T (frame)     C: dz3, exponents, dW3 b2 b3 sums of t
-//   D  P: dW2 += dz2^T h1 of t; feature gradient of t-1     C: stage t+1
+//   C  P: dz3, dz2 of t -> dz2 plane, half the frame plane  C: dz3, exponents, b2 b3 sums, other half
+//   D  P: dW2 += dz2^T h1 of t; feature gradient of t-1     C: stage t+1; dW3 of t
 // After the last tile one more A/B pair finishes the C side.  Both roles run the same
 // number of barriers, so s_barrier stays matched.
 
@@ -591,19 +599,17 @@ constexpr int NT = TILE;  // samples per block tile (two 16-sample column tiles)
 // LDS of the backward kernel (bytes); the small image part is staged at offset 0
 constexpr int BS = IMG_FWD_END - IMG_B1;             // b1, b2, W3, b3, meta
 constexpr int BSL(int img_off) { return img_off - IMG_B1; }
+// Every activation plane is sample-major ([NT samples][row stride] hi, then lo), written with 8-byte
+// stores of a lane's four units; the weight-gradient products read their unit-major operands from
+// the same planes with transposing LDS reads (see tr_operand).
 constexpr int XB_BYTES = 2 * NT * RS1 * 2;           // x B operand [NT][RS1] hi, lo
-constexpr int XT_BYTES = 2 * NXIN * TS * 2;          // x^T [NXIN][TS] hi, lo
-constexpr int HB_BYTES = 2 * NT * RS2 * 2;           // h1, later dz2, B operand [NT][RS2] hi, lo
-constexpr int B_XB0 = BS;                            // two buffers each (tile parity)
-constexpr int B_XT0 = B_XB0 + 2 * XB_BYTES;
-constexpr int B_HB0 = B_XT0 + 2 * XT_BYTES;
-constexpr int B_HTH = B_HB0 + 2 * HB_BYTES;          // h1^T [H][TS]
-constexpr int B_HTL = B_HTH + H * TS * 2;
-constexpr int B_D2TH = B_HTL + H * TS * 2;           // dz2^T [H][TS] (frame-scaled)
-constexpr int B_D2TL = B_D2TH + H * TS * 2;
-constexpr int B_D1TH = B_D2TL + H * TS * 2;          // dz1^T [H][TS] (frame-scaled)
-constexpr int B_D1TL = B_D1TH + H * TS * 2;
-constexpr int B_Z3P = B_D1TL + H * TS * 2;           // logit partials [4][NT][4] f32
+constexpr int HB_BYTES = 2 * NT * RS2 * 2;           // one [NT][RS2] hi, lo plane
+constexpr int B_XB0 = BS;                            // x: two buffers (tile parity)
+constexpr int B_HB = B_XB0 + 2 * XB_BYTES;           // h1: layer-2 B operand, dW2 B operand
+constexpr int B_DB = B_HB + HB_BYTES;                // dz2: dz1 B operand (per-sample scale)
+constexpr int B_D2S = B_DB + HB_BYTES;               // dz2 in the dW2 frame: dW2 A operand
+constexpr int B_D1S = B_D2S + HB_BYTES;              // dz1 in the dW1 frame: dW1 A operand
+constexpr int B_Z3P = B_D1S + HB_BYTES;              // logit partials [4][NT][4] f32
 constexpr int DFS = 12;                              // row of dfeat partials (features)
 constexpr int B_DFP = B_Z3P + 4 * NT * 4 * 4;        // dfeat partials [4][NT][DFS] f32
 constexpr int H2S = 36;                              // row stride (floats) of the h2 plane
@@ -613,8 +619,8 @@ constexpr int B_XMAX = B_MASK + 2 * 4 * 64 * 2;      // max |x| per sample [2][N
 constexpr int B_GR = B_XMAX + 2 * NT * 4;            // grad_rgb [2][NT][4]
 constexpr int B_END = B_GR + 2 * NT * 16;
 static_assert(B_END <= 160 * 1024, "backward LDS");
-static_assert(B_XB0 % 16 == 0 && B_HB0 % 16 == 0 && B_HTH % 16 == 0 && B_D1TH % 16 == 0 && B_Z3P % 16 == 0 &&
-                  B_DFP % 16 == 0 && B_MASK % 8 == 0,
+static_assert(B_XB0 % 16 == 0 && B_HB % 16 == 0 && B_DB % 16 == 0 && B_D2S % 16 == 0 && B_D1S % 16 == 0 &&
+                  B_Z3P % 16 == 0 && B_DFP % 16 == 0 && B_MASK % 8 == 0,
               "LDS alignment");
 
 // exponent that moves a gradient column into the accumulator frame F (operand scale e of
@@ -642,13 +648,46 @@ __device__ __forceinline__ _Float16 lo_part(float t, _Float16 h) {
     return r;
 }
 
-// write a split value into a transposed plane [unit][TS] (the lo plane only in split mode)
+// four values of one sample (a lane's units u0..u0+3), each moved by 2^e (exact; a zero stays zero
+// for any e), split and stored at element idx of a sample-major plane (lo plane only in split mode)
 template <bool SPLIT>
-__device__ __forceinline__ void put_t(unsigned char *base, int off_h, int off_l, int unit, int col, float t) {
-    const _Float16 h = (_Float16)t;
-    reinterpret_cast<_Float16 *>(base + off_h)[unit * TS + col] = h;
-    if (SPLIT) reinterpret_cast<_Float16 *>(base + off_l)[unit * TS + col] = lo_part(t, h);
+__device__ __forceinline__ void put_split4(unsigned char *plane, int idx, const float v[4], int e) {
+    uint2 hi, lo;
+    split2(ldx(v[0], e), ldx(v[1], e), hi.x, lo.x);
+    split2(ldx(v[2], e), ldx(v[3], e), hi.y, lo.y);
+    *reinterpret_cast<uint2 *>(reinterpret_cast<_Float16 *>(plane) + idx) = hi;
+    if (SPLIT) *reinterpret_cast<uint2 *>(reinterpret_cast<_Float16 *>(plane) + NT * RS2 + idx) = lo;
 }
+
+// 64 bits per lane through the transposing LDS read: within each group of 16 lanes, the four
+// 16-bit elements that lane t' addresses go to lanes 4 (t' mod 4) .. 4 (t' mod 4) + 3, each into
+// element slot t' / 4.
+__device__ __forceinline__ h4 lds_tr4(const unsigned char *p) {
+    typedef short s4 __attribute__((ext_vector_type(4)));
+    const s4 r = __builtin_amdgcn_ds_read_tr16_b64_v4i16((__attribute__((address_space(3))) s4 *)(p));
+    return __builtin_bit_cast(h4, r);
+}
+
+// Unit-major MFMA operand (16 units U0..U0+15 as rows, the tile's 32 samples as K) from a
+// sample-major plane [NT][RS] in which unit U0 + 4a + r sits at column cb + 8a + r (cb = the
+// column of U0; phys slot order, U0 a multiple of 16): lane (q, j) gets unit U0 + j, its K slot
+// 4h + e (h = read, e = element) holding sample 16h + 4e + q.  (The weight-gradient products sum
+// over K, so any slot order serves as long as both operands use this one.)  Lane j of group q
+// addresses the four units U0 + 4 (j mod 4) .. + 3 of sample 4 (j / 4) + q (+16 in the second
+// read), so the four rows one 16-lane group reads lie 4 rows apart: with the 136-half row stride
+// they start 16 banks apart and the group's 8-byte reads hit distinct banks.  The lane offset, in
+// halves, is tr_lane<RS>(), taken once by the caller so that every read of a phase shares one
+// address register.
+template <int RS>
+__device__ __forceinline__ int tr_lane(int j, int q) { return (4 * (j >> 2) + q) * RS + 8 * (j & 3); }
+template <int RS>
+__device__ __forceinline__ h8 tr_operand(const unsigned char *plane, int tl, int cb) {
+    const _Float16 *p = reinterpret_cast<const _Float16 *>(plane) + tl + cb;
+    return cat(lds_tr4(reinterpret_cast<const unsigned char *>(p)),
+               lds_tr4(reinterpret_cast<const unsigned char *>(p + 16 * RS)));
+}
+// column of unit (or logical input) 16 n in the phys slot order of a 128- or 64-wide row
+__device__ __forceinline__ int unit_col(int n) { return 32 * (n >> 1) + 4 * (n & 1); }
 
 __device__ __forceinline__ void store_h4(unsigned char *base, int off, int idx, h4 v) {
     *reinterpret_cast<h4 *>(reinterpret_cast<_Float16 *>(base + off) + idx) = v;
@@ -764,7 +803,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     const float *b2 = reinterpret_cast<const float *>(sm + BSL(IMG_B2));
     const float *W3 = reinterpret_cast<const float *>(sm + BSL(IMG_W3));
     const float *b3 = reinterpret_cast<const float *>(sm + BSL(IMG_B3));
-    unsigned char *rA = lds_region(sm, B_HTH);   // HT, D2T, D1T
+    unsigned char *hb = lds_region(sm, B_HB);    // h1 (per-sample scale)
+    unsigned char *db = lds_region(sm, B_DB);    // dz2 (per-sample scale)
+    unsigned char *d2s = lds_region(sm, B_D2S);  // dz2 in the dW2 frame
+    unsigned char *d1s = lds_region(sm, B_D1S);  // dz1 in the dW1 frame
     unsigned char *rB = lds_region(sm, B_Z3P);   // partials, h2, masks, per-sample values
     float *z3p = reinterpret_cast<float *>(rB);
     float *dfp = reinterpret_cast<float *>(rB + (B_DFP - B_Z3P));
@@ -811,7 +853,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             const float *xmax_s = xmax_b + pb * NT;
             const float *gr_s = gr_b + pb * NT * 4;
             const int xb = B_XB0 + pb * XB_BYTES;
-            unsigned char *hb = lds_region(sm, B_HB0 + pb * HB_BYTES);
             uint16_t *mask1 = mask_b + pb * 256;
             // ---- A: layer 1 for units 32w..; h1 -> B operand, transposed planes, mask bits
             {
@@ -864,12 +905,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
                         store_h4(hb, 0, ob, hi);
                         if (SPLIT) store_h4(hb, NT * RS2 * 2, ob, lo);
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int u = 32 * w + 16 * mp + 4 * q + r;
-                            reinterpret_cast<_Float16 *>(rA)[u * TS + 16 * c + j] = hi[r];
-                            if (SPLIT) reinterpret_cast<_Float16 *>(rA + (B_HTL - B_HTH))[u * TS + 16 * c + j] = lo[r];
-                        }
                     }
                 }
                 mask1[w * 64 + ln] = (uint16_t)mbits;
@@ -960,27 +995,26 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         h4 hi, lo;
                         split4(dz2, pow2(ge.g2[c]), hi, lo);
                         const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
-                        store_h4(hb, 0, ob, hi);
-                        if (SPLIT) store_h4(hb, NT * RS2 * 2, ob, lo);
-                        if (mp == 0) {  // the C waves write the mp = 1 rows of dz2^T
-                            const int fs = frame_shift(F2, se.e1[c]);  // exact for any shift; 0 stays 0
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                put_t<SPLIT>(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2[r], fs));
-                        }
+                        store_h4(db, 0, ob, hi);
+                        if (SPLIT) store_h4(db, NT * RS2 * 2, ob, lo);
+                        // the frame plane (the C waves write the mp = 1 units); exact for any shift
+                        if (mp == 0) put_split4<SPLIT>(d2s, ob, dz2, frame_shift(F2, se.e1[c]));
                     }
                 }
             }
             lds_barrier();
-            // ---- D: dW2 += dz2^T h1 (K = the tile's 32 samples)
+            // ---- D: dW2 += dz2^T h1 (K = the tile's 32 samples; both operands read transposed from
+            //      the sample-major planes)
+            const int tl = tr_lane<RS2>(j, q);
 #pragma unroll
             for (int mp = 0; mp < 2; ++mp) {
-                const int ra = (32 * w + 16 * mp + j) * TS + 8 * q;
-                const h8 ah = lds_h8(rA, B_D2TH - B_HTH, ra), al = lds_h8(rA, B_D2TL - B_HTH, ra);
+                const int cb = unit_col(2 * w + mp);
+                const h8 ah = tr_operand<RS2>(d2s, tl, cb);
+                const h8 al = SPLIT ? tr_operand<RS2>(d2s + NT * RS2 * 2, tl, cb) : ah;
 #pragma unroll
                 for (int n = 0; n < 8; ++n) {
-                    const int rb = (16 * n + j) * TS + 8 * q;
-                    const h8 bh = lds_h8(rA, 0, rb), bl = lds_h8(rA, B_HTL - B_HTH, rb);
+                    const h8 bh = tr_operand<RS2>(hb, tl, unit_col(n));
+                    const h8 bl = SPLIT ? tr_operand<RS2>(hb + NT * RS2 * 2, tl, unit_col(n)) : bh;
                     if (SPLIT) {
                         dW2[mp][n] = mfma16(al, bh, dW2[mp][n]);
                         dW2[mp][n] = mfma16(ah, bl, dW2[mp][n]);
@@ -1056,7 +1090,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 if (xg < 3) grv = a.grad_rgb[(int64_t)s * 3 + xg];
             }
         };
-        // ... and their split into the x planes of buffer pb (x B operand, x^T, max |x|, grad_rgb)
+        // ... and their split into the x plane of buffer pb (layer-1 B operand, read transposed by
+        // dW1), max |x| and grad_rgb
         auto stage_tile = [&](int pb) {
             float m = 0.f;
 #pragma unroll
@@ -1066,30 +1101,29 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             h4 h0, l0, h1, l1;
             split4(&xv[0], sc, h0, l0);
             split4(&xv[4], sc, h1, l1);
-            const int xb = B_XB0 + pb * XB_BYTES, xt = B_XT0 + pb * XT_BYTES;
+            const int xb = B_XB0 + pb * XB_BYTES;
             *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb) + xsl * RS1 + 8 * xg) = cat(h0, h1);
             if (SPLIT)
                 *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb + NT * RS1 * 2) + xsl * RS1 + 8 * xg) =
                     cat(l0, l1);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int k = kidx(xg >> 2, xg & 3, e);
-                if (k < NXIN) put_t<SPLIT>(sm, xt, xt + NXIN * TS * 2, k, xsl, xv[e] * sc);
-            }
             if (xg == 0) xmax_b[pb * NT + xsl] = m;
             if (xg < 4) gr_b[(pb * NT + xsl) * 4 + xg] = grv;
         };
-        // dW1 += dz1^T x of a finished tile (its x^T buffer pb)
+        // dW1 += dz1^T x of a finished tile (its x buffer pb; both operands read transposed from the
+        // sample-major planes; logical inputs 0..47 in the three 16-column blocks)
         auto dw1_step = [&](int pb) {
-            const int xt = B_XT0 + pb * XT_BYTES;
+            const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
+            const int t2 = tr_lane<RS2>(j, q), t1 = tr_lane<RS1>(j, q);
+            const unsigned char *xp = lds_region(sm, B_XB0 + pb * XB_BYTES);
 #pragma unroll
             for (int mp = 0; mp < 2; ++mp) {
-                const int ra = (32 * w + 16 * mp + j) * TS + 8 * q;
-                const h8 dh = lds_h8(rA, B_D1TH - B_HTH, ra), dl = lds_h8(rA, B_D1TL - B_HTH, ra);
+                const int cb = unit_col(2 * w + mp);
+                const h8 dh = tr_operand<RS2>(d1s, t2, cb);
+                const h8 dl = SPLIT ? tr_operand<RS2>(d1s + NT * RS2 * 2, t2, cb) : dh;
 #pragma unroll
                 for (int n = 0; n < 3; ++n) {
-                    const int rb = (16 * n + j) * TS + 8 * q;
-                    const h8 bh = lds_h8(sm, xt, rb), bl = lds_h8(sm, xt + NXIN * TS * 2, rb);
+                    const h8 bh = tr_operand<RS1>(xp, t1, unit_col(n));
+                    const h8 bl = SPLIT ? tr_operand<RS1>(xp + NT * RS1 * 2, t1, unit_col(n)) : bh;
                     if (SPLIT) {
                         dW1[mp][n] = mfma16(dl, bh, dW1[mp][n]);
                         dW1[mp][n] = mfma16(dh, bl, dW1[mp][n]);
@@ -1111,11 +1145,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         for (int o = 0; o < 3; ++o) dw3[o][mp][r] += dz3[c][o] * h2;
                     }
         };
-        // dz1 = mask(h1) W2^T dz2 of a tile (buffers of parity pb, exponents g2/g1/ex of that
-        // tile), dfeat partials, frame-scaled dz1^T
+        // dz1 = mask(h1) W2^T dz2 of a tile (mask bits of parity pb, exponents g2/g1/ex of that
+        // tile), dfeat partials, dz1 in the dW1 frame
         auto dz1_step = [&](int pb, const int g2[2], const int g1[2], const int ex[2]) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
-            const unsigned char *hb = lds_region(sm, B_HB0 + pb * HB_BYTES);
             // this lane's h1 > 0 bits, read before the products so the load is long done
             const unsigned mbits = mask_b[pb * 256 + w * 64 + ln];
             float dz1[2][2][4];
@@ -1129,8 +1162,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 h8 bh[2], bl[2];
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    bh[c] = lds_h8(hb, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
-                    bl[c] = lds_h8(hb, NT * RS2 * 2, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                    bh[c] = lds_h8(db, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                    bl[c] = lds_h8(db, NT * RS2 * 2, (16 * c + j) * RS2 + 32 * kk + 8 * q);
                 }
                 if (SPLIT) {
 #pragma unroll
@@ -1153,14 +1186,13 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 const int fs = frame_shift(F1, ex[c]);  // exact for any shift; 0 stays 0
 #pragma unroll
                 for (int mp = 0; mp < 2; ++mp) {
-                    const int u0 = 32 * w + 16 * mp + 4 * q;
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const bool on = (mbits >> ((c * 2 + mp) * 4 + r)) & 1u;
                         dz1[mp][c][r] = on ? acc[c][mp][r] * un : 0.f;
                         db1[mp][r] += dz1[mp][c][r];
-                        put_t<SPLIT>(rA, B_D1TH - B_HTH, B_D1TL - B_HTH, u0 + r, 16 * c + j, ldx(dz1[mp][c][r], fs));
                     }
+                    put_split4<SPLIT>(d1s, (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp, dz1[mp][c], fs);
                 }
             }
             // dfeat partial over this wave's 32 units: rows = feature 4q + r, column = sample
@@ -1235,16 +1267,18 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        const int fs = frame_shift(F2, se.e1[c]);  // exact for any shift; 0 stays 0
+                        float dz2[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const float h2 = h2s[(u0 + r) * H2S + 16 * c + j];
                             const float d = w3t_dz3(wv, ge.dz3[c], r);
-                            const float dz2 = h2 > 0.f ? d : 0.f;  // the P waves' value, bit for bit
-                            db2[mp][r] += dz2;
-                            if (mp == 1)
-                                put_t<SPLIT>(rA, B_D2TH - B_HTH, B_D2TL - B_HTH, u0 + r, 16 * c + j, ldx(dz2, fs));
+                            dz2[r] = h2 > 0.f ? d : 0.f;  // the P waves' value, bit for bit
+                            db2[mp][r] += dz2[r];
                         }
+                        // the frame plane's mp = 1 units; exact for any shift; 0 stays 0
+                        if (mp == 1)
+                            put_split4<SPLIT>(d2s, (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp, dz2,
+                                              frame_shift(F2, se.e1[c]));
                     }
                 }
             }
