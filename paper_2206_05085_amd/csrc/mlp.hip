@@ -586,10 +586,14 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
 // (4..7) own the same units for the backward chain and hold those rows of W2^T.  The C
 // waves run one tile behind, so every phase pairs P and C work on the same SIMDs.  Phases
 // of iteration t (block-wide barriers between them; the inputs of t are already staged):
-//   A  P: layer 1 of t -> h1 plane, mask bits              C: dz1 of t-1 (frame plane), dfeat partials
+//   A  P: layer 1 of t -> h1 plane, mask bits;              C: dz1 of t-1 (frame plane), dfeat partials
+//         dW2 += dz2^T h1 of t-1
 //   B  P: layer 2 of t -> h2, logit partials                C: dW1 += dz1^T x of t-1; loads of t+1
 //   C  P: dz3, dz2 of t -> dz2 plane, half the frame plane  C: dz3, exponents, b2 b3 sums, other half
-//   D  P: dW2 += dz2^T h1 of t; feature gradient of t-1     C: stage t+1; dW3 of t
+//   D  P: feature gradient of t-1                           C: stage t+1; dW3 of t
+// (dW2 of a tile waits for the next phase A, where the P waves would otherwise idle beside the
+// longer dz1 of the C waves; h1 is double-buffered for it, and the dz2 frame plane and the dW2
+// frame stay put until the next phase C.)
 // After the last tile one more A/B pair finishes the C side.  Both roles run the same
 // number of barriers, so s_barrier stays matched.
 
@@ -605,8 +609,8 @@ constexpr int BSL(int img_off) { return img_off - IMG_B1; }
 constexpr int XB_BYTES = 2 * NT * RS1 * 2;           // x B operand [NT][RS1] hi, lo
 constexpr int HB_BYTES = 2 * NT * RS2 * 2;           // one [NT][RS2] hi, lo plane
 constexpr int B_XB0 = BS;                            // x: two buffers (tile parity)
-constexpr int B_HB = B_XB0 + 2 * XB_BYTES;           // h1: layer-2 B operand, dW2 B operand
-constexpr int B_DB = B_HB + HB_BYTES;                // dz2: dz1 B operand (per-sample scale)
+constexpr int B_HB = B_XB0 + 2 * XB_BYTES;           // h1: layer-2 and dW2 B operand, two (parity)
+constexpr int B_DB = B_HB + 2 * HB_BYTES;            // dz2: dz1 B operand (per-sample scale)
 constexpr int B_D2S = B_DB + HB_BYTES;               // dz2 in the dW2 frame: dW2 A operand
 constexpr int B_D1S = B_D2S + HB_BYTES;              // dz1 in the dW1 frame: dW1 A operand
 constexpr int B_Z3P = B_D1S + HB_BYTES;              // logit partials [4][NT][4] f32
@@ -803,7 +807,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     const float *b2 = reinterpret_cast<const float *>(sm + BSL(IMG_B2));
     const float *W3 = reinterpret_cast<const float *>(sm + BSL(IMG_W3));
     const float *b3 = reinterpret_cast<const float *>(sm + BSL(IMG_B3));
-    unsigned char *hb = lds_region(sm, B_HB);    // h1 (per-sample scale)
     unsigned char *db = lds_region(sm, B_DB);    // dz2 (per-sample scale)
     unsigned char *d2s = lds_region(sm, B_D2S);  // dz2 in the dW2 frame
     unsigned char *d1s = lds_region(sm, B_D1S);  // dz1 in the dW1 frame
@@ -845,11 +848,34 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
 #pragma unroll
             for (int n = 0; n < 8; ++n) dW2[mp][n] = v4f{0.f, 0.f, 0.f, 0.f};
         int F2 = FRAME_NONE;
+        // dW2 += dz2^T h1 of a finished tile (K = its 32 samples; both operands read transposed from
+        // the sample-major planes: the dz2 frame plane and that tile's h1 plane)
+        auto dw2_step = [&](const unsigned char *h1p) {
+            const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
+            const int tl = tr_lane<RS2>(j, q);
+#pragma unroll
+            for (int mp = 0; mp < 2; ++mp) {
+                const int cb = unit_col(2 * w + mp);
+                const h8 ah = tr_operand<RS2>(d2s, tl, cb);
+                const h8 al = SPLIT ? tr_operand<RS2>(d2s + NT * RS2 * 2, tl, cb) : ah;
+#pragma unroll
+                for (int n = 0; n < 8; ++n) {
+                    const h8 bh = tr_operand<RS2>(h1p, tl, unit_col(n));
+                    const h8 bl = SPLIT ? tr_operand<RS2>(h1p + NT * RS2 * 2, tl, unit_col(n)) : bh;
+                    if (SPLIT) {
+                        dW2[mp][n] = mfma16(al, bh, dW2[mp][n]);
+                        dW2[mp][n] = mfma16(ah, bl, dW2[mp][n]);
+                    }
+                    dW2[mp][n] = mfma16(ah, bh, dW2[mp][n]);
+                }
+            }
+        };
         lds_barrier();  // staged image and the first tile's inputs
         int it = 0;
         for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x, ++it) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
             const int pb = it & 1;
+            unsigned char *hb = lds_region(sm, B_HB + pb * HB_BYTES);
             const float *xmax_s = xmax_b + pb * NT;
             const float *gr_s = gr_b + pb * NT * 4;
             const int xb = B_XB0 + pb * XB_BYTES;
@@ -909,6 +935,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
                 mask1[w * 64 + ln] = (uint16_t)mbits;
             }
+            if (it > 0) dw2_step(lds_region(sm, B_HB + (pb ^ 1) * HB_BYTES));
             lds_barrier();
             // ---- B: layer 2 for units 32w.., logit partials
             {
@@ -1003,30 +1030,12 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
             }
             lds_barrier();
-            // ---- D: dW2 += dz2^T h1 (K = the tile's 32 samples; both operands read transposed from
-            //      the sample-major planes)
-            const int tl = tr_lane<RS2>(j, q);
-#pragma unroll
-            for (int mp = 0; mp < 2; ++mp) {
-                const int cb = unit_col(2 * w + mp);
-                const h8 ah = tr_operand<RS2>(d2s, tl, cb);
-                const h8 al = SPLIT ? tr_operand<RS2>(d2s + NT * RS2 * 2, tl, cb) : ah;
-#pragma unroll
-                for (int n = 0; n < 8; ++n) {
-                    const h8 bh = tr_operand<RS2>(hb, tl, unit_col(n));
-                    const h8 bl = SPLIT ? tr_operand<RS2>(hb + NT * RS2 * 2, tl, unit_col(n)) : bh;
-                    if (SPLIT) {
-                        dW2[mp][n] = mfma16(al, bh, dW2[mp][n]);
-                        dW2[mp][n] = mfma16(ah, bl, dW2[mp][n]);
-                    }
-                    dW2[mp][n] = mfma16(ah, bh, dW2[mp][n]);
-                }
-            }
-            // feature gradient of the previous tile (its partials came from the C waves' phase A)
+            // ---- D: feature gradient of the previous tile (its partials came from the C waves' phase A)
             if (it > 0) feat_grad_out(a, dfp, (tile - (int)gridDim.x) * NT, tid);
             lds_barrier();
         }
-        // the C side's last A/B pair
+        // dW2 of the last tile; the C side's last A/B pair
+        if (it > 0) dw2_step(lds_region(sm, B_HB + ((it - 1) & 1) * HB_BYTES));
         lds_barrier();
         lds_barrier();
         // ---- partial gradient of the P role: W2
