@@ -120,6 +120,48 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(DevGrid g, int64_t S, co
     }
 }
 
+// Rows made of whole float4 groups (ch_stride % 4 == 0): G adjacent lanes share a sample, lane
+// r of them taking channels 4r..4r+3 (G = ceil(C / 4)), 64 / G consecutive samples per wave.  The
+// G lanes of a sample read each corner's row as one contiguous span in the same instruction, so a
+// corner costs one or two lines per load rather than G loads spread over G instructions, and the
+// wave's working set stays small enough for the cache to keep the rows its neighbours reuse.
+// Same helper (interp4) as the one-lane-per-sample path and the colour head's fused lookup: the
+// same bits.
+template <int G, bool W>
+__global__ __launch_bounds__(kBlock) void gather_groups_kernel(DevGrid g, int64_t S, const float *__restrict__ xyz,
+                                                               float *__restrict__ out, int vec_out) {
+    constexpr int SPW = 64 / G;  // samples per wave
+    const int ln = lane(), sl = ln / G, r = ln - sl * G;
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / 64);
+    for (int64_t base = ((blockIdx.x * (int64_t)kBlock + threadIdx.x) >> 6) * SPW; base < S; base += nwaves * SPW) {
+        const int64_t k = base + sl;
+        if (sl >= SPW || k >= S) continue;
+        const Tri t = trilinear<W>(g, xyz[3 * k], xyz[3 * k + 1], xyz[3 * k + 2]);
+        const float4 v = interp4(g, t, 4 * r);
+        if (vec_out) {
+            *reinterpret_cast<float4 *>(out + k * g.C + 4 * r) = v;
+        } else {
+            const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (4 * r + i < g.C) out[k * g.C + 4 * r + i] = e[i];
+        }
+    }
+}
+
+template <int G>
+void launch_gather_groups(const DevGrid &dg, int64_t S, const float *xyz, float *out, int vec_out, hipStream_t st) {
+    const int64_t waves = (S + 64 / G - 1) / (64 / G);
+    int64_t blocks = (waves + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > 65535 * 16) blocks = 65535 * 16;
+    if (dg.warp)
+        hipLaunchKernelGGL((gather_groups_kernel<G, true>), dim3((unsigned)blocks), dim3(kBlock), 0, st, dg, S, xyz, out,
+                           vec_out);
+    else
+        hipLaunchKernelGGL((gather_groups_kernel<G, false>), dim3((unsigned)blocks), dim3(kBlock), 0, st, dg, S, xyz,
+                           out, vec_out);
+}
+
 // One lane per sample, 64 consecutive samples per wave: consecutive samples lie along a
 // ray, so contributions to shared vertices are summed in the wave before the atomics.
 template <int NC, bool W>
@@ -310,12 +352,23 @@ extern "C" int dvgo_grid_gather(const dvgo_grid *g, int64_t n_samples, const flo
     if (!xyz || !out) return set_error(DVGO_ERR_NULL, "xyz or out is NULL");
     if ((g->ch_stride & 3) == 0 && ((uintptr_t)g->data & 15))
         return set_error(DVGO_ERR_SHAPE, "grid data must be 16-byte aligned when ch_stride is a multiple of 4");
+    const hipStream_t st = (hipStream_t)stream;
+    const int vec_out = vec_rows(out, dg.C);
+    if ((dg.cs & 3) == 0) {
+        switch ((dg.C + 3) / 4) {
+            case 1: launch_gather_groups<1>(dg, n_samples, xyz, out, vec_out, st); break;
+            case 2: launch_gather_groups<2>(dg, n_samples, xyz, out, vec_out, st); break;
+            case 3: launch_gather_groups<3>(dg, n_samples, xyz, out, vec_out, st); break;
+            default: launch_gather_groups<4>(dg, n_samples, xyz, out, vec_out, st); break;
+        }
+        return check_hip(hipGetLastError(), "gather_groups_kernel launch");
+    }
     if (dg.warp)
-        hipLaunchKernelGGL(gather_kernel<true>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream,
-                           dg, n_samples, xyz, out, vec_rows(out, dg.C));
+        hipLaunchKernelGGL(gather_kernel<true>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, st, dg, n_samples, xyz,
+                           out, vec_out);
     else
-        hipLaunchKernelGGL(gather_kernel<false>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, (hipStream_t)stream,
-                           dg, n_samples, xyz, out, vec_rows(out, dg.C));
+        hipLaunchKernelGGL(gather_kernel<false>, dim3(grid_blocks(n_samples)), dim3(kBlock), 0, st, dg, n_samples, xyz,
+                           out, vec_out);
     return check_hip(hipGetLastError(), "gather_kernel launch");
 }
 

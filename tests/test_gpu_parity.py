@@ -306,6 +306,37 @@ def test_gather_scatter(dv, C):
     close(dg.grad.cpu().numpy(), oracle.scatter(g, xyz, y.astype(np.float64)), **GRAD, name="scatter")
 
 
+@pytest.mark.parametrize("C,cs,warp", [(4, 4, 0), (3, 4, 0), (8, 8, 1), (7, 8, 0), (16, 16, 0), (12, 16, 2)])
+def test_gather_channel_groups(dv, C, cs, warp):
+    # rows of whole float4 groups (ch_stride % 4 == 0): a sample's channel groups are looked up by
+    # adjacent lanes; every group count 1..4, padded rows (channels < ch_stride), the contraction,
+    # and an output that is not 16-byte aligned (scalar stores)
+    rng = np.random.default_rng(60 + C + cs)
+    n = 19
+    lo, hi = (-2.0, 2.0) if warp else (-1.0, 1.0)
+    g = synth.normal_grid(rng, n, C, lo, hi)
+    g.warp, g.warp_b = warp, 1.0
+    S = 4099
+    xyz = rng.uniform(1.2 * lo, 1.2 * hi, (S, 3)).astype(np.float32)
+    if warp:
+        xyz = (xyz * 3.0).astype(np.float32)
+    padded = np.zeros((n, n, n, cs), np.float32)
+    padded[..., :C] = g.data
+    padded[..., C:] = 7.0  # padding channels never reach the output
+    say("gather channel groups C =", C, "ch_stride =", cs, "warp", warp)
+    dg = dv.DeviceGrid(T(padded), g.xyz_min, g.xyz_max, channels=C, warp=warp, warp_b=1.0)
+    absg = synth.Grid(np.abs(g.data), g.xyz_min, g.xyz_max, warp=warp, warp_b=1.0)
+    want = oracle.gather(g, xyz)
+    scale = oracle.gather(absg, xyz)
+    out = dv.grid_gather(dg, T(xyz))
+    buf = torch.zeros(S * C + 1, device="cuda")
+    dv.grid_gather(dg, T(xyz), out=buf[1:].view(S, C))  # 4-byte offset: not 16-byte aligned
+    torch.cuda.synchronize()
+    close(out.cpu().numpy(), want, **FWD, name="gather", scale=scale)
+    assert torch.equal(buf[1:].view(S, C), out), "aligned and unaligned outputs differ"
+    assert buf[0].item() == 0.0
+
+
 @pytest.mark.parametrize("warp,b,C", [(1, 1.0, 12), (2, 1.0, 12), (1, 0.5, 1), (2, 3.0, 3)])
 def test_gather_scatter_contracted(dv, warp, b, C):
     # world points from 0.1 to 1e4 away from the origin, looked up through Eq. 4
