@@ -431,10 +431,10 @@ __device__ __forceinline__ void copy_to_lds(unsigned char *dst, const unsigned c
 
 // ------------------------------------------------------------------ forward
 
-constexpr int FWD_WAVES = 8, FWD_THREADS = 64 * FWD_WAVES;
-constexpr int FWD_NC = 2;                 // 16-sample column tiles per wave tile
+constexpr int FWD_WAVES = 16, FWD_THREADS = 64 * FWD_WAVES;
+constexpr int FWD_NC = 1;                 // 16-sample column tiles per wave tile
 constexpr int FWD_WTILE = 16 * FWD_NC;    // samples per wave tile
-static_assert(FWD_WTILE == TILE, "forward wave tiles are the 32-sample tiles of tile_ray");
+static_assert(TILE % FWD_WTILE == 0, "forward wave tiles split the 32-sample tiles of tile_ray");
 
 template <bool SPLIT, int GM>
 __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
         int s[FWD_NC], ex[FWD_NC], e1[FWD_NC];
         bool sv[FWD_NC];
         h8 xh[FWD_NC][2], xl[FWD_NC][2];
-        const int r0 = a.tile_ray[wt];
+        const int r0 = a.tile_ray[wt / (TILE / FWD_WTILE)];  // first ray of the enclosing tile
         const int win = window_entry(a.offs, a.n_rays, r0);
 #pragma unroll
         for (int c = 0; c < FWD_NC; ++c) {
