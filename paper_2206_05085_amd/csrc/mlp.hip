@@ -103,17 +103,33 @@ __device__ __forceinline__ int ceil_exp(float m) {
 // hi and lo parts of two values in packed halves: hi = fp16(t0), fp16(t1) from one packed
 // conversion (round to nearest even, as every float -> half conversion here), lo = fp16(t - hi)
 // of each from one mixed-precision FMA that writes its half of the register directly (t - hi is
-// exact in FP32, so each equals (_Float16)(t - (float)hi)).
+// exact in FP32, so each equals (_Float16)(t - (float)hi)).  The compiler's hazard tracking does
+// not see these as vector-ALU writes, and a matrix instruction may read a vector register only two
+// wait states after a vector-ALU instruction wrote it: with MM (the results feed a product
+// directly) the block ends with those two (s_nop 1); results that only go to LDS stores need none.
+template <bool MM>
 __device__ __forceinline__ void split2(float t0, float t1, unsigned &hi, unsigned &lo) {
-    asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(hi) : "v"(t0), "v"(t1));
-    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(lo) : "v"(t0), "v"(hi));
-    asm("v_fma_mixhi_f16 %0, %1, 1.0, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]" : "+v"(lo) : "v"(t1), "v"(hi));
+    if (MM)
+        asm("v_cvt_pk_f16_f32 %0, %2, %3\n\t"
+            "v_fma_mixlo_f16 %1, %2, 1.0, -%0 op_sel_hi:[0,0,1]\n\t"
+            "v_fma_mixhi_f16 %1, %3, 1.0, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]\n\t"
+            "s_nop 1"
+            : "=&v"(hi), "=&v"(lo)
+            : "v"(t0), "v"(t1));
+    else
+        asm("v_cvt_pk_f16_f32 %0, %2, %3\n\t"
+            "v_fma_mixlo_f16 %1, %2, 1.0, -%0 op_sel_hi:[0,0,1]\n\t"
+            "v_fma_mixhi_f16 %1, %3, 1.0, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+            : "=&v"(hi), "=&v"(lo)
+            : "v"(t0), "v"(t1));
 }
 
+// MM: the parts feed a matrix product directly (see split2)
+template <bool MM>
 __device__ __forceinline__ void split4(const float v[4], float sc, h4 &hi, h4 &lo) {
     uint2 h, l;
-    split2(v[0] * sc, v[1] * sc, h.x, l.x);
-    split2(v[2] * sc, v[3] * sc, h.y, l.y);
+    split2<MM>(v[0] * sc, v[1] * sc, h.x, l.x);
+    split2<MM>(v[2] * sc, v[3] * sc, h.y, l.y);
     hi = __builtin_bit_cast(h4, h);
     lo = __builtin_bit_cast(h4, l);
 }
@@ -483,8 +499,8 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
                 h4 h0, l0, h1, l1;
-                split4(&xv[kk][0], sc, h0, l0);
-                split4(&xv[kk][4], sc, h1, l1);
+                split4<true>(&xv[kk][0], sc, h0, l0);
+                split4<true>(&xv[kk][4], sc, h1, l1);
                 xh[c][kk] = cat(h0, h1);
                 xl[c][kk] = cat(l0, l1);
             }
@@ -516,7 +532,7 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
                 const float un = pow2(-(meta.sw1 + ex[c]));
                 float v[4] = {fmaxf(fmaf(acc[c][0], un, bb.x), 0.f), fmaxf(fmaf(acc[c][1], un, bb.y), 0.f),
                               fmaxf(fmaf(acc[c][2], un, bb.z), 0.f), fmaxf(fmaf(acc[c][3], un, bb.w), 0.f)};
-                split4(v, pow2(e1[c]), hh[c][m], hl[c][m]);
+                split4<true>(v, pow2(e1[c]), hh[c][m], hl[c][m]);
             }
             // keep the scheduler from hoisting every weight load of the layer (spills)
             __builtin_amdgcn_sched_barrier(0);
@@ -597,7 +613,11 @@ __global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
 // After the last tile one more A/B pair finishes the C side.  Both roles run the same
 // number of barriers, so s_barrier stays matched.
 
-constexpr int BWD_WAVES = 8, BWD_THREADS = 64 * BWD_WAVES;
+constexpr int BWD_MP = 2;                   // 16-unit row tiles of one layer per wave
+constexpr int BWD_RW = 8 / BWD_MP;          // waves per role: BWD_RW x 16 BWD_MP = 128 units
+constexpr int BWD_RT = 64 * BWD_RW;         // threads per role
+constexpr int BWD_WAVES = 2 * BWD_RW, BWD_THREADS = 64 * BWD_WAVES;
+static_assert(BWD_MP == 1 || BWD_MP == 2, "one or two row tiles per wave");
 constexpr int NT = TILE;  // samples per block tile (two 16-sample column tiles)
 
 // LDS of the backward kernel (bytes); the small image part is staged at offset 0
@@ -613,13 +633,13 @@ constexpr int B_HB = B_XB0 + 2 * XB_BYTES;           // h1: layer-2 and dW2 B op
 constexpr int B_DB = B_HB + 2 * HB_BYTES;            // dz2: dz1 B operand (per-sample scale)
 constexpr int B_D2S = B_DB + HB_BYTES;               // dz2 in the dW2 frame: dW2 A operand
 constexpr int B_D1S = B_D2S + HB_BYTES;              // dz1 in the dW1 frame: dW1 A operand
-constexpr int B_Z3P = B_D1S + HB_BYTES;              // logit partials [4][NT][4] f32
+constexpr int B_Z3P = B_D1S + HB_BYTES;              // logit partials [RW][NT][4] f32
 constexpr int DFS = 12;                              // row of dfeat partials (features)
-constexpr int B_DFP = B_Z3P + 4 * NT * 4 * 4;        // dfeat partials [4][NT][DFS] f32
+constexpr int B_DFP = B_Z3P + BWD_RW * NT * 4 * 4;   // dfeat partials [RW][NT][DFS] f32
 constexpr int H2S = 36;                              // row stride (floats) of the h2 plane
-constexpr int B_H2 = B_DFP + 4 * NT * DFS * 4;       // h2 [H][H2S] f32, written by P, read by C
-constexpr int B_MASK = B_H2 + H * H2S * 4;           // h1 > 0 bits per lane [2][4 waves][64 lanes] u16
-constexpr int B_XMAX = B_MASK + 2 * 4 * 64 * 2;      // max |x| per sample [2][NT]
+constexpr int B_H2 = B_DFP + BWD_RW * NT * DFS * 4;  // h2 [H][H2S] f32, written by P, read by C
+constexpr int B_MASK = B_H2 + H * H2S * 4;           // h1 > 0 bits per lane [2][RW waves][64 lanes] u16
+constexpr int B_XMAX = B_MASK + 2 * BWD_RW * 64 * 2; // max |x| per sample [2][NT]
 constexpr int B_GR = B_XMAX + 2 * NT * 4;            // grad_rgb [2][NT][4]
 constexpr int B_END = B_GR + 2 * NT * 16;
 static_assert(B_END <= 160 * 1024, "backward LDS");
@@ -642,23 +662,13 @@ __device__ __forceinline__ h8 glb_h8(const unsigned char *img, int off, int idx)
     return *reinterpret_cast<const h8 *>(reinterpret_cast<const _Float16 *>(img + off) + idx);
 }
 
-// fp16(t - h) for h = fp16(t), in one mixed-precision FMA (t * 1 - h rounded once to fp16);
-// t - h is exact in fp32, so this equals (_Float16)(t - (float)h).  The instruction writes the
-// low half of its 32-bit destination only; the value is a 16-bit one (held in the low half, as
-// the compiler keeps every half-precision value) and is consumed only by 16-bit LDS stores.
-__device__ __forceinline__ _Float16 lo_part(float t, _Float16 h) {
-    _Float16 r;
-    asm("v_fma_mixlo_f16 %0, %1, 1.0, -%2 op_sel_hi:[0,0,1]" : "=v"(r) : "v"(t), "v"(h));
-    return r;
-}
-
 // four values of one sample (a lane's units u0..u0+3), each moved by 2^e (exact; a zero stays zero
 // for any e), split and stored at element idx of a sample-major plane (lo plane only in split mode)
 template <bool SPLIT>
 __device__ __forceinline__ void put_split4(unsigned char *plane, int idx, const float v[4], int e) {
     uint2 hi, lo;
-    split2(ldx(v[0], e), ldx(v[1], e), hi.x, lo.x);
-    split2(ldx(v[2], e), ldx(v[3], e), hi.y, lo.y);
+    split2<false>(ldx(v[0], e), ldx(v[1], e), hi.x, lo.x);
+    split2<false>(ldx(v[2], e), ldx(v[3], e), hi.y, lo.y);
     *reinterpret_cast<uint2 *>(reinterpret_cast<_Float16 *>(plane) + idx) = hi;
     if (SPLIT) *reinterpret_cast<uint2 *>(reinterpret_cast<_Float16 *>(plane) + NT * RS2 + idx) = lo;
 }
@@ -706,15 +716,18 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Feature gradient of a finished tile: the partials of the four C waves, summed in a fixed
-// order; t = the calling thread's index within its 256-thread role.
+// Feature gradient of a finished tile: the partials of the C waves, summed in a fixed order; t =
+// the calling thread's index within its role.
 __device__ __forceinline__ void feat_grad_out(const MlpArgs &a, const float *dfp, int pbase, int t) {
-    for (int i = t; i < NT * a.in_feat; i += 256) {
+    for (int i = t; i < NT * a.in_feat; i += BWD_RT) {
         const int sl = i / a.in_feat, c = i % a.in_feat;
         const int s = pbase + sl;
-        if (s < a.S)
-            a.grad_feat[(int64_t)s * a.in_feat + c] = dfp[(0 * NT + sl) * DFS + c] + dfp[(1 * NT + sl) * DFS + c] +
-                                                      dfp[(2 * NT + sl) * DFS + c] + dfp[(3 * NT + sl) * DFS + c];
+        if (s < a.S) {
+            float g = dfp[sl * DFS + c];
+#pragma unroll
+            for (int ww = 1; ww < BWD_RW; ++ww) g += dfp[(ww * NT + sl) * DFS + c];
+            a.grad_feat[(int64_t)s * a.in_feat + c] = g;
+        }
     }
 }
 
@@ -751,7 +764,7 @@ __device__ __forceinline__ GradExp grad_exp(const float *z3p, const float *gr_s,
         for (int o = 0; o < 3; ++o) {
             float z = b3[o];
 #pragma unroll
-            for (int ww = 0; ww < 4; ++ww) z += z3p[(ww * NT + sl) * 4 + o];
+            for (int ww = 0; ww < BWD_RW; ++ww) z += z3p[(ww * NT + sl) * 4 + o];
             const float y = fast_sigmoid(z);
             g.dz3[c][o] = gr_s[sl * 4 + o] * y * (1.f - y);
             mx = fmaxf(mx, fabsf(g.dz3[c][o]));
@@ -782,12 +795,12 @@ __device__ __forceinline__ int tile_frame(const int other_e[2], const int k[2]) 
     return __builtin_amdgcn_readfirstlane(f);
 }
 
-template <int N>
-__device__ __forceinline__ void rescale(v4f (&acc)[2][N], int &F, int f) {
+template <int M, int N>
+__device__ __forceinline__ void rescale(v4f (&acc)[M][N], int &F, int f) {
     if (f < F) {
         const int d = max(f - F, -300);
 #pragma unroll
-        for (int mp = 0; mp < 2; ++mp)
+        for (int mp = 0; mp < M; ++mp)
 #pragma unroll
             for (int n = 0; n < N; ++n)
 #pragma unroll
@@ -814,8 +827,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     float *z3p = reinterpret_cast<float *>(rB);
     float *dfp = reinterpret_cast<float *>(rB + (B_DFP - B_Z3P));
     float *h2s = reinterpret_cast<float *>(rB + (B_H2 - B_Z3P));
-    // bit (c 2 + mp) 4 + r of lane (j, q) of wave w: h1 > 0 for unit 32w + 16mp + 4q + r, sample
-    // 16c + j; the P wave and the C wave of the same w use the same lane -> (unit, sample) map
+    // bit (c MP + mp) 4 + r of lane (j, q) of wave w: h1 > 0 for unit 16 (MP w + mp) + 4q + r,
+    // sample 16c + j; the P wave and the C wave of the same w use the same lane -> (unit, sample) map
     uint16_t *mask_b = reinterpret_cast<uint16_t *>(rB + (B_MASK - B_Z3P));
     float *xmax_b = reinterpret_cast<float *>(rB + (B_XMAX - B_Z3P));
     float *gr_b = reinterpret_cast<float *>(rB + (B_GR - B_Z3P));
@@ -823,28 +836,28 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     float *P = a.partial + (int64_t)blockIdx.x * a.n_params;
     float *pW1 = P, *pb1 = pW1 + H * a.n_in, *pW2 = pb1 + H, *pb2 = pW2 + H * H, *pW3 = pb2 + H, *pb3 = pW3 + 3 * H;
 
-    if (wave < 4) {
+    if (wave < BWD_RW) {
         // ================================================================ P waves
         const int w = wave;
-        h8 w2h[2][4], w2l[2][4], w1h[2][2], w1l[2][2];
+        h8 w2h[BWD_MP][4], w2l[BWD_MP][4], w1h[BWD_MP][2], w1l[BWD_MP][2];
 #pragma unroll
-        for (int mp = 0; mp < 2; ++mp) {
+        for (int mp = 0; mp < BWD_MP; ++mp) {
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const int o = (32 * w + 16 * mp + j) * RS2 + 32 * kk + 8 * q;
+                const int o = (16 * (BWD_MP * w + mp) + j) * RS2 + 32 * kk + 8 * q;
                 w2h[mp][kk] = glb_h8(a.img, IMG_W2H, o);
                 w2l[mp][kk] = glb_h8(a.img, IMG_W2L, o);
             }
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
-                const int o = (32 * w + 16 * mp + j) * RS1 + 32 * kk + 8 * q;
+                const int o = (16 * (BWD_MP * w + mp) + j) * RS1 + 32 * kk + 8 * q;
                 w1h[mp][kk] = glb_h8(a.img, IMG_W1H, o);
                 w1l[mp][kk] = glb_h8(a.img, IMG_W1L, o);
             }
         }
-        v4f dW2[2][8];
+        v4f dW2[BWD_MP][8];
 #pragma unroll
-        for (int mp = 0; mp < 2; ++mp)
+        for (int mp = 0; mp < BWD_MP; ++mp)
 #pragma unroll
             for (int n = 0; n < 8; ++n) dW2[mp][n] = v4f{0.f, 0.f, 0.f, 0.f};
         int F2 = FRAME_NONE;
@@ -854,8 +867,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
             const int tl = tr_lane<RS2>(j, q);
 #pragma unroll
-            for (int mp = 0; mp < 2; ++mp) {
-                const int cb = unit_col(2 * w + mp);
+            for (int mp = 0; mp < BWD_MP; ++mp) {
+                const int cb = unit_col(BWD_MP * w + mp);
                 const h8 ah = tr_operand<RS2>(d2s, tl, cb);
                 const h8 al = SPLIT ? tr_operand<RS2>(d2s + NT * RS2 * 2, tl, cb) : ah;
 #pragma unroll
@@ -879,16 +892,16 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             const float *xmax_s = xmax_b + pb * NT;
             const float *gr_s = gr_b + pb * NT * 4;
             const int xb = B_XB0 + pb * XB_BYTES;
-            uint16_t *mask1 = mask_b + pb * 256;
-            // ---- A: layer 1 for units 32w..; h1 -> B operand, transposed planes, mask bits
+            uint16_t *mask1 = mask_b + pb * (BWD_RW * 64);
+            // ---- A: layer 1 for this wave's units; h1 -> the h1 plane, mask bits
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
-                v4f acc[2][2];  // [c][mp]
+                v4f acc[2][BWD_MP];  // [c][mp]
                 unsigned mbits = 0;
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
 #pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
+                    for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kk = 0; kk < 2; ++kk) {
                     h8 bh[2], bl[2];
@@ -901,34 +914,34 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
 #pragma unroll
                         for (int c = 0; c < 2; ++c)
 #pragma unroll
-                            for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1l[mp][kk], bh[c], acc[c][mp]);
+                            for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w1l[mp][kk], bh[c], acc[c][mp]);
 #pragma unroll
                         for (int c = 0; c < 2; ++c)
 #pragma unroll
-                            for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1h[mp][kk], bl[c], acc[c][mp]);
+                            for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w1h[mp][kk], bl[c], acc[c][mp]);
                     }
 #pragma unroll
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w1h[mp][kk], bh[c], acc[c][mp]);
+                        for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w1h[mp][kk], bh[c], acc[c][mp]);
                 }
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const float un = pow2(-(meta.sw1 + se.ex[c]));
                     const float sc = pow2(se.e1[c]);
 #pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) {
-                        const float4 bb = *reinterpret_cast<const float4 *>(b1 + 32 * w + 16 * mp + 4 * q);
+                    for (int mp = 0; mp < BWD_MP; ++mp) {
+                        const float4 bb = *reinterpret_cast<const float4 *>(b1 + 16 * (BWD_MP * w + mp) + 4 * q);
                         const float bv[4] = {bb.x, bb.y, bb.z, bb.w};
                         float h1[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             h1[r] = fmaxf(fmaf(acc[c][mp][r], un, bv[r]), 0.f);
-                            mbits |= (h1[r] > 0.f ? 1u : 0u) << ((c * 2 + mp) * 4 + r);
+                            mbits |= (h1[r] > 0.f ? 1u : 0u) << ((c * BWD_MP + mp) * 4 + r);
                         }
                         h4 hi, lo;
-                        split4(h1, sc, hi, lo);
-                        const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
+                        split4<false>(h1, sc, hi, lo);
+                        const int ob = (16 * c + j) * RS2 + unit_col(BWD_MP * w + mp) + 8 * q;
                         store_h4(hb, 0, ob, hi);
                         if (SPLIT) store_h4(hb, NT * RS2 * 2, ob, lo);
                     }
@@ -937,14 +950,14 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             }
             if (it > 0) dw2_step(lds_region(sm, B_HB + (pb ^ 1) * HB_BYTES));
             lds_barrier();
-            // ---- B: layer 2 for units 32w.., logit partials
+            // ---- B: layer 2 for this wave's units, logit partials
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
-                v4f acc[2][2];  // [c][mp]
+                v4f acc[2][BWD_MP];  // [c][mp]
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
 #pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
+                    for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
                     h8 bh[2], bl[2];
@@ -957,24 +970,24 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
 #pragma unroll
                         for (int c = 0; c < 2; ++c)
 #pragma unroll
-                            for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2l[mp][kk], bh[c], acc[c][mp]);
+                            for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w2l[mp][kk], bh[c], acc[c][mp]);
 #pragma unroll
                         for (int c = 0; c < 2; ++c)
 #pragma unroll
-                            for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2h[mp][kk], bl[c], acc[c][mp]);
+                            for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w2h[mp][kk], bl[c], acc[c][mp]);
                     }
 #pragma unroll
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2h[mp][kk], bh[c], acc[c][mp]);
+                        for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w2h[mp][kk], bh[c], acc[c][mp]);
                 }
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const float un = pow2(-(meta.sw2 + se.e1[c]));
                     float zp[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) {
-                        const int u0 = 32 * w + 16 * mp + 4 * q;
+                    for (int mp = 0; mp < BWD_MP; ++mp) {
+                        const int u0 = 16 * (BWD_MP * w + mp) + 4 * q;
                         const float4 bb = *reinterpret_cast<const float4 *>(b2 + u0);
                         const float4 x0 = *reinterpret_cast<const float4 *>(W3 + u0);
                         const float4 x1 = *reinterpret_cast<const float4 *>(W3 + H + u0);
@@ -999,14 +1012,14 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
             }
             lds_barrier();
-            // ---- C: dz3, dz2 = mask(h2) W3^T dz3 (VALU), dz2 B operand, the mp = 0 rows of dz2^T
+            // ---- C: dz3, dz2 = mask(h2) W3^T dz3 (VALU): the dz2 plane and the dz2 frame plane
             {
                 const SampleExp se = sample_exp(xmax_s, meta, j);
                 const GradExp ge = grad_exp(z3p, gr_s, b3, meta, j);
-                rescale<8>(dW2, F2, tile_frame(se.e1, ge.k2));
+                rescale(dW2, F2, tile_frame(se.e1, ge.k2));
 #pragma unroll
-                for (int mp = 0; mp < 2; ++mp) {
-                    const int u0 = 32 * w + 16 * mp + 4 * q;
+                for (int mp = 0; mp < BWD_MP; ++mp) {
+                    const int u0 = 16 * (BWD_MP * w + mp) + 4 * q;
                     const float4 x0 = *reinterpret_cast<const float4 *>(W3 + u0);
                     const float4 x1 = *reinterpret_cast<const float4 *>(W3 + H + u0);
                     const float4 x2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + u0);
@@ -1020,12 +1033,11 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                             dz2[r] = h2s[(u0 + r) * H2S + 16 * c + j] > 0.f ? d : 0.f;
                         }
                         h4 hi, lo;
-                        split4(dz2, pow2(ge.g2[c]), hi, lo);
-                        const int ob = (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp;
+                        split4<false>(dz2, pow2(ge.g2[c]), hi, lo);
+                        const int ob = (16 * c + j) * RS2 + unit_col(BWD_MP * w + mp) + 8 * q;
                         store_h4(db, 0, ob, hi);
                         if (SPLIT) store_h4(db, NT * RS2 * 2, ob, lo);
-                        // the frame plane (the C waves write the mp = 1 units); exact for any shift
-                        if (mp == 0) put_split4<SPLIT>(d2s, ob, dz2, frame_shift(F2, se.e1[c]));
+                        put_split4<SPLIT>(d2s, ob, dz2, frame_shift(F2, se.e1[c]));  // exact for any shift
                     }
                 }
             }
@@ -1041,38 +1053,42 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         // ---- partial gradient of the P role: W2
         const int u2 = F2 == FRAME_NONE ? 0 : -F2;
 #pragma unroll
-        for (int mp = 0; mp < 2; ++mp)
+        for (int mp = 0; mp < BWD_MP; ++mp)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int hrow = 32 * w + 16 * mp + 4 * q + r;
+                const int hrow = 16 * (BWD_MP * w + mp) + 4 * q + r;
 #pragma unroll
                 for (int n = 0; n < 8; ++n) pW2[hrow * H + 16 * n + j] = ldx(dW2[mp][n][r], u2);
             }
     } else {
         // ================================================================ C waves
-        const int w = wave - 4;
-        const int ct = tid - 256;              // 0..255 within the C role
-        const int xsl = ct >> 3, xg = ct & 7;  // input staging: sample xsl, slot group xg
-        h8 w2th[2][4], w2tl[2][4];
+        const int w = wave - BWD_RW;
+        const int ct = tid - BWD_RT;           // index within the C role
+        // input staging: the first 256 threads of the role (waves 0..3), sample xsl, slot group xg
+        const bool stager = w < 4;
+        const int xsl = ct >> 3, xg = ct & 7;
+        h8 w2th[BWD_MP][4], w2tl[BWD_MP][4];
 #pragma unroll
-        for (int mp = 0; mp < 2; ++mp)
+        for (int mp = 0; mp < BWD_MP; ++mp)
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const int o = (32 * w + 16 * mp + j) * RS2 + 32 * kk + 8 * q;
+                const int o = (16 * (BWD_MP * w + mp) + j) * RS2 + 32 * kk + 8 * q;
                 w2th[mp][kk] = glb_h8(a.img, IMG_W2TH, o);
                 w2tl[mp][kk] = glb_h8(a.img, IMG_W2TL, o);
             }
-        const int ofF = j * RS2 + 32 * w + 8 * q;
+        // W1's feature columns, transposed (rows = features), over this wave's units as K: 32 units
+        // (two row tiles) in one 16x16x32 product, or 16 units in one 16x16x16 product
+        const int ofF = j * RS2 + unit_col(BWD_MP * w) + 8 * q;
         const h8 w1fh = glb_h8(a.img, IMG_W1FH, ofF), w1fl = glb_h8(a.img, IMG_W1FL, ofF);
-        v4f dW1[2][3];
+        v4f dW1[BWD_MP][3];
 #pragma unroll
-        for (int mp = 0; mp < 2; ++mp)
+        for (int mp = 0; mp < BWD_MP; ++mp)
 #pragma unroll
             for (int n = 0; n < 3; ++n) dW1[mp][n] = v4f{0.f, 0.f, 0.f, 0.f};
         // lane-local sums over this lane's samples; reduced over the 16 sample lanes at the end
-        float db1[2][4], db2[2][4], dw3[3][2][4], db3[3] = {0.f, 0.f, 0.f};
+        float db1[BWD_MP][4], db2[BWD_MP][4], dw3[3][BWD_MP][4], db3[3] = {0.f, 0.f, 0.f};
 #pragma unroll
-        for (int mp = 0; mp < 2; ++mp)
+        for (int mp = 0; mp < BWD_MP; ++mp)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 db1[mp][r] = db2[mp][r] = 0.f;
@@ -1080,9 +1096,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 for (int o = 0; o < 3; ++o) dw3[o][mp][r] = 0.f;
             }
         int F1 = FRAME_NONE;
-        // the P waves' dW2 frame, followed step by step from the same per-tile inputs (the C
-        // waves write the mp = 1 rows of the frame-scaled dz2^T planes the dW2 products read)
-        int F2 = FRAME_NONE;
         // inputs of a tile: global loads, in three steps spread over phases so that their
         // latency overlaps other work (ray window; ray search and feature loads; staging)
         float xv[8], grv = 0.f;
@@ -1108,8 +1121,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             m = group8_max(m);  // over the 8 slot groups xg of this sample
             const float sc = pow2(scale_exp(m));
             h4 h0, l0, h1, l1;
-            split4(&xv[0], sc, h0, l0);
-            split4(&xv[4], sc, h1, l1);
+            split4<false>(&xv[0], sc, h0, l0);
+            split4<false>(&xv[4], sc, h1, l1);
             const int xb = B_XB0 + pb * XB_BYTES;
             *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb) + xsl * RS1 + 8 * xg) = cat(h0, h1);
             if (SPLIT)
@@ -1125,8 +1138,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             const int t2 = tr_lane<RS2>(j, q), t1 = tr_lane<RS1>(j, q);
             const unsigned char *xp = lds_region(sm, B_XB0 + pb * XB_BYTES);
 #pragma unroll
-            for (int mp = 0; mp < 2; ++mp) {
-                const int cb = unit_col(2 * w + mp);
+            for (int mp = 0; mp < BWD_MP; ++mp) {
+                const int cb = unit_col(BWD_MP * w + mp);
                 const h8 dh = tr_operand<RS2>(d1s, t2, cb);
                 const h8 dl = SPLIT ? tr_operand<RS2>(d1s + NT * RS2 * 2, t2, cb) : dh;
 #pragma unroll
@@ -1144,12 +1157,12 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         // dW3 += dz3 h2^T over this lane's units and samples (h2 of the current tile)
         auto dw3_step = [&](const float (&dz3)[2][3], int j, int q) {
 #pragma unroll
-            for (int mp = 0; mp < 2; ++mp)
+            for (int mp = 0; mp < BWD_MP; ++mp)
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const float h2 = h2s[(32 * w + 16 * mp + 4 * q + r) * H2S + 16 * c + j];
+                        const float h2 = h2s[(16 * (BWD_MP * w + mp) + 4 * q + r) * H2S + 16 * c + j];
 #pragma unroll
                         for (int o = 0; o < 3; ++o) dw3[o][mp][r] += dz3[c][o] * h2;
                     }
@@ -1159,13 +1172,13 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         auto dz1_step = [&](int pb, const int g2[2], const int g1[2], const int ex[2]) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
             // this lane's h1 > 0 bits, read before the products so the load is long done
-            const unsigned mbits = mask_b[pb * 256 + w * 64 + ln];
-            float dz1[2][2][4];
-            v4f acc[2][2];  // [c][mp]
+            const unsigned mbits = mask_b[pb * (BWD_RW * 64) + w * 64 + ln];
+            float dz1[BWD_MP][2][4];
+            v4f acc[2][BWD_MP];  // [c][mp]
 #pragma unroll
             for (int c = 0; c < 2; ++c)
 #pragma unroll
-                for (int mp = 0; mp < 2; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
+                for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 h8 bh[2], bl[2];
@@ -1178,53 +1191,66 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
 #pragma unroll
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2tl[mp][kk], bh[c], acc[c][mp]);
+                        for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w2tl[mp][kk], bh[c], acc[c][mp]);
 #pragma unroll
                     for (int c = 0; c < 2; ++c)
 #pragma unroll
-                        for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2th[mp][kk], bl[c], acc[c][mp]);
+                        for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w2th[mp][kk], bl[c], acc[c][mp]);
                 }
 #pragma unroll
                 for (int c = 0; c < 2; ++c)
 #pragma unroll
-                    for (int mp = 0; mp < 2; ++mp) acc[c][mp] = mfma16(w2th[mp][kk], bh[c], acc[c][mp]);
+                    for (int mp = 0; mp < BWD_MP; ++mp) acc[c][mp] = mfma16(w2th[mp][kk], bh[c], acc[c][mp]);
             }
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const float un = pow2(-(meta.sw2 + g2[c]));
                 const int fs = frame_shift(F1, ex[c]);  // exact for any shift; 0 stays 0
 #pragma unroll
-                for (int mp = 0; mp < 2; ++mp) {
+                for (int mp = 0; mp < BWD_MP; ++mp) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const bool on = (mbits >> ((c * 2 + mp) * 4 + r)) & 1u;
+                        const bool on = (mbits >> ((c * BWD_MP + mp) * 4 + r)) & 1u;
                         dz1[mp][c][r] = on ? acc[c][mp][r] * un : 0.f;
                         db1[mp][r] += dz1[mp][c][r];
                     }
-                    put_split4<SPLIT>(d1s, (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp, dz1[mp][c], fs);
+                    put_split4<SPLIT>(d1s, (16 * c + j) * RS2 + unit_col(BWD_MP * w + mp) + 8 * q, dz1[mp][c], fs);
                 }
             }
-            // dfeat partial over this wave's 32 units: rows = feature 4q + r, column = sample
+            // dfeat partial over this wave's units: rows = feature 4q + r, column = sample
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                h4 h0, l0, h1v, l1v;
                 const float sc = pow2(g1[c]);
-                split4(dz1[0][c], sc, h0, l0);
-                split4(dz1[1][c], sc, h1v, l1v);
-                const h8 bh = cat(h0, h1v), bl = cat(l0, l1v);
                 v4f df = v4f{0.f, 0.f, 0.f, 0.f};
-                if (SPLIT) {
-                    df = mfma16(w1fl, bh, df);
-                    df = mfma16(w1fh, bl, df);
+                if constexpr (BWD_MP == 2) {
+                    h4 h0, l0, h1v, l1v;
+                    split4<true>(dz1[0][c], sc, h0, l0);
+                    split4<true>(dz1[1][c], sc, h1v, l1v);
+                    const h8 bh = cat(h0, h1v), bl = cat(l0, l1v);
+                    if (SPLIT) {
+                        df = mfma16(w1fl, bh, df);
+                        df = mfma16(w1fh, bl, df);
+                    }
+                    df = mfma16(w1fh, bh, df);
+                } else {
+                    // K = this wave's 16 units: slots 4q..4q+3 of the 16x16x16 product
+                    h4 h0, l0;
+                    split4<true>(dz1[0][c], sc, h0, l0);
+                    const h4 ah = __builtin_shufflevector(w1fh, w1fh, 0, 1, 2, 3);
+                    const h4 al = __builtin_shufflevector(w1fl, w1fl, 0, 1, 2, 3);
+                    if (SPLIT) {
+                        df = __builtin_amdgcn_mfma_f32_16x16x16f16(al, h0, df, 0, 0, 0);
+                        df = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, l0, df, 0, 0, 0);
+                    }
+                    df = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, h0, df, 0, 0, 0);
                 }
-                df = mfma16(w1fh, bh, df);
                 const float un = pow2(-(meta.sw1 + g1[c]));
                 if (q < DFS / 4)
                     *reinterpret_cast<float4 *>(dfp + (w * NT + 16 * c + j) * DFS + 4 * q) =
                         make_float4(df[0] * un, df[1] * un, df[2] * un, df[3] * un);
             }
         };
-        if ((int)blockIdx.x < ntiles) {
+        if (stager && (int)blockIdx.x < ntiles) {
             const int r0 = a.tile_ray[blockIdx.x];
             load_tile(blockIdx.x, r0, window_entry(a.offs, a.n_rays, r0));
             stage_tile(0);
@@ -1243,16 +1269,15 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             const int winn = next ? window_entry(a.offs, a.n_rays, r0n) : 0;
             lds_barrier();
             // ---- B: dW1 of the previous tile; loads of the next tile's inputs
-            if (next) load_tile(tile + gridDim.x, r0n, winn);
+            if (next && stager) load_tile(tile + gridDim.x, r0n, winn);
             if (pbase >= 0) dw1_step(pb ^ 1);
             lds_barrier();
-            // ---- C: output gradient and exponents of this tile; frames of dW1 and dW2; db2 += dz2,
-            //      db3 += dz3 (VALU, h2 from the P waves); the mp = 1 rows of dz2^T
+            // ---- C: output gradient and exponents of this tile; the frame of dW1; db2 += dz2,
+            //      db3 += dz3 (VALU, h2 from the P waves)
             {
                 const SampleExp se = sample_exp(xmax_b + pb * NT, meta, j);
                 const GradExp ge = grad_exp(z3p, gr_b + pb * NT * 4, b3, meta, j);
-                rescale<3>(dW1, F1, tile_frame(se.ex, ge.k1));
-                F2 = min(F2, tile_frame(se.e1, ge.k2));  // as rescale<8> moves it on the P side
+                rescale(dW1, F1, tile_frame(se.ex, ge.k1));
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     pg2[c] = ge.g2[c];
@@ -1268,26 +1293,20 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         for (int o = 0; o < 3; ++o) db3[o] += ge.dz3[c][o];
                 }
 #pragma unroll
-                for (int mp = 0; mp < 2; ++mp) {
-                    const int u0 = 32 * w + 16 * mp + 4 * q;
+                for (int mp = 0; mp < BWD_MP; ++mp) {
+                    const int u0 = 16 * (BWD_MP * w + mp) + 4 * q;
                     const float4 x0 = *reinterpret_cast<const float4 *>(W3 + u0);
                     const float4 x1 = *reinterpret_cast<const float4 *>(W3 + H + u0);
                     const float4 x2 = *reinterpret_cast<const float4 *>(W3 + 2 * H + u0);
                     const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        float dz2[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const float h2 = h2s[(u0 + r) * H2S + 16 * c + j];
                             const float d = w3t_dz3(wv, ge.dz3[c], r);
-                            dz2[r] = h2 > 0.f ? d : 0.f;  // the P waves' value, bit for bit
-                            db2[mp][r] += dz2[r];
+                            db2[mp][r] += h2 > 0.f ? d : 0.f;  // the P waves' dz2, bit for bit
                         }
-                        // the frame plane's mp = 1 units; exact for any shift; 0 stays 0
-                        if (mp == 1)
-                            put_split4<SPLIT>(d2s, (16 * c + j) * RS2 + 32 * w + 8 * q + 4 * mp, dz2,
-                                              frame_shift(F2, se.e1[c]));
                     }
                 }
             }
@@ -1295,7 +1314,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             // ---- D: the next tile's inputs -> x planes (the P waves write the previous tile's
             //      feature gradient meanwhile); dW3 += dz3 h2^T of this tile (h2 stays until the
             //      P waves' next layer 2)
-            if (next) stage_tile(pb ^ 1);
+            if (next && stager) stage_tile(pb ^ 1);
             dw3_step(tdz3, j, q);
             lds_barrier();
             pbase = tile * NT;
@@ -1311,10 +1330,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         // ---- partial gradients of the C role: W1, b1, b2, W3, b3
         const int u1 = F1 == FRAME_NONE ? 0 : -F1;
 #pragma unroll
-        for (int mp = 0; mp < 2; ++mp)
+        for (int mp = 0; mp < BWD_MP; ++mp)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int hrow = 32 * w + 16 * mp + 4 * q + r;
+                const int hrow = 16 * (BWD_MP * w + mp) + 4 * q + r;
 #pragma unroll
                 for (int n = 0; n < 3; ++n) {
                     const int c = w1_col(a.in_feat, a.n_freq, 16 * n + j);
