@@ -447,13 +447,22 @@ __device__ __forceinline__ void copy_to_lds(unsigned char *dst, const unsigned c
 
 // ------------------------------------------------------------------ forward
 
-constexpr int FWD_WAVES = 16, FWD_THREADS = 64 * FWD_WAVES;
-constexpr int FWD_NC = 1;                 // 16-sample column tiles per wave tile
-constexpr int FWD_WTILE = 16 * FWD_NC;    // samples per wave tile
-static_assert(TILE % FWD_WTILE == 0, "forward wave tiles split the 32-sample tiles of tile_ray");
+// Wave tiles of the forward: with the feature lookup inside (GM > 0) 16 samples per wave and 16
+// waves per block, so four waves share each SIMD and hide the lookups' latency behind each other's
+// products; with the features read from memory 32 samples per wave and 8 waves, which reuses each
+// weight operand for two column tiles.
+template <int GM>
+struct FwdShape {
+    static constexpr int NC = GM ? 1 : 2;       // 16-sample column tiles per wave tile
+    static constexpr int WAVES = GM ? 16 : 8;   // waves per block
+    static constexpr int THREADS = 64 * WAVES;
+    static constexpr int WTILE = 16 * NC;       // samples per wave tile
+    static_assert(TILE % WTILE == 0, "forward wave tiles split the 32-sample tiles of tile_ray");
+};
 
 template <bool SPLIT, int GM>
-__global__ __launch_bounds__(FWD_THREADS) void mlp_fwd_kernel(MlpArgs a) {
+__global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs a) {
+    constexpr int FWD_NC = FwdShape<GM>::NC, FWD_WAVES = FwdShape<GM>::WAVES, FWD_WTILE = FwdShape<GM>::WTILE;
     __shared__ __attribute__((aligned(16))) unsigned char sm[IMG_FWD_END];
     copy_to_lds(sm, a.img, IMG_FWD_END);
     __syncthreads();
@@ -1462,13 +1471,14 @@ int setup(const dvgo_color_mlp *m, int32_t R, const int32_t *offs, const float *
 
 template <int GM>
 int launch_fwd(const MlpArgs &a, const dvgo_color_mlp *m, hipStream_t st) {
-    const int64_t nwt = (a.S + FWD_WTILE - 1) / FWD_WTILE;
-    const int64_t nb = (nwt + FWD_WAVES - 1) / FWD_WAVES;
+    using F = FwdShape<GM>;
+    const int64_t nwt = (a.S + F::WTILE - 1) / F::WTILE;
+    const int64_t nb = (nwt + F::WAVES - 1) / F::WAVES;
     const dim3 grid((int)(nb < MAX_BLOCKS ? nb : MAX_BLOCKS));
     if (m->precision == DVGO_MLP_F16)
-        hipLaunchKernelGGL((mlp_fwd_kernel<false, GM>), grid, dim3(FWD_THREADS), 0, st, a);
+        hipLaunchKernelGGL((mlp_fwd_kernel<false, GM>), grid, dim3(F::THREADS), 0, st, a);
     else
-        hipLaunchKernelGGL((mlp_fwd_kernel<true, GM>), grid, dim3(FWD_THREADS), 0, st, a);
+        hipLaunchKernelGGL((mlp_fwd_kernel<true, GM>), grid, dim3(F::THREADS), 0, st, a);
     return check_hip(hipGetLastError(), "mlp_fwd_kernel launch");
 }
 
