@@ -20,12 +20,13 @@
 // 16-byte read per part.
 //
 // Forward: each wave owns 16 NC samples and all 128 hidden units; W1 and W2 (both parts)
-// sit in LDS.  Backward: a block's waves own slices of 32 hidden units for the block's
+// sit in LDS.  Backward: a block's waves own slices of 16 BWD_MP hidden units for the block's
 // 32-sample tiles and keep their rows of W1, W2 or W2^T in registers (two roles, see the
-// backward section); activations are exchanged through LDS.  The weight gradients reduce
-// over samples, so their operands are transposed through LDS into sample-slot order; their
-// accumulators carry a power-of-two frame that only ever decreases (rescaled when a tile
-// needs it), and a sample's operands are scaled so that the product lands in that frame.
+// backward section); activations are exchanged through sample-major LDS planes.  The weight
+// gradients reduce over samples, so their unit-major operands are read from those planes with
+// transposing LDS reads; their accumulators carry a power-of-two frame that only ever decreases
+// (rescaled when a tile needs it), and a sample's operands are scaled so that the product lands
+// in that frame.
 #include <string.h>
 
 #include "dvgo_internal.h"
@@ -606,15 +607,16 @@ __global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs 
 
 // ------------------------------------------------------------------ backward
 //
-// Block = 8 waves in two roles.  P waves (0..3) own units 32p..32p+31 of both hidden
-// layers for the forward recompute and hold those rows of W1 and W2 in registers; C waves
-// (4..7) own the same units for the backward chain and hold those rows of W2^T.  The C
-// waves run one tile behind, so every phase pairs P and C work on the same SIMDs.  Phases
+// Block = 2 BWD_RW waves in two roles (8 waves of 32 units each with BWD_MP = 2).  P waves
+// (0..RW-1) own units 16 BWD_MP p .. of both hidden layers for the forward recompute and hold
+// those rows of W1 and W2 in registers; C waves (RW..2RW-1) own the same units for the backward
+// chain and hold those rows of W2^T.  The C waves run one tile behind, so every phase pairs P
+// and C work on the same SIMDs.  Phases
 // of iteration t (block-wide barriers between them; the inputs of t are already staged):
 //   A  P: layer 1 of t -> h1 plane, mask bits;              C: dz1 of t-1 (frame plane), dfeat partials
 //         dW2 += dz2^T h1 of t-1
 //   B  P: layer 2 of t -> h2, logit partials                C: dW1 += dz1^T x of t-1; loads of t+1
-//   C  P: dz3, dz2 of t -> dz2 plane, half the frame plane  C: dz3, exponents, b2 b3 sums, other half
+//   C  P: dz3, dz2 of t -> dz2 plane and its frame plane     C: dz3, exponents, b2 b3 sums
 //   D  P: feature gradient of t-1                           C: stage t+1; dW3 of t
 // (dW2 of a tile waits for the next phase A, where the P waves would otherwise idle beside the
 // longer dz1 of the C waves; h1 is double-buffered for it, and the dz2 frame plane and the dW2
