@@ -41,11 +41,9 @@ typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
 constexpr int H = 128;      // hidden width
 constexpr int KX = 64;      // padded input width: features 0..11, view encoding 12..47, zeros 48..63
-constexpr int NXIN = 48;    // inputs that can be non-zero
 constexpr int PEW = 36;     // per-ray encoding row (input columns 12..47)
 constexpr int RS1 = 72;     // row stride (halves) of a 64-wide operand row
 constexpr int RS2 = 136;    // row stride (halves) of a 128-wide operand row
-constexpr int TS = 40;      // row stride (halves) of a transposed [unit][32 samples] plane
 constexpr int MAXE = 100;   // clamp of scaling exponents
 constexpr int FRAME_NONE = 1 << 20;
 constexpr int MAX_BLOCKS = 256;
@@ -1076,7 +1074,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         const int w = wave - BWD_RW;
         const int ct = tid - BWD_RT;           // index within the C role
         // input staging: the first 256 threads of the role (waves 0..3), sample xsl, slot group xg
-        const bool stager = w < 4;
+        const bool stager = BWD_RW <= 4 || w < 4;
         const int xsl = ct >> 3, xg = ct & 7;
         h8 w2th[BWD_MP][4], w2tl[BWD_MP][4];
 #pragma unroll
@@ -1109,23 +1107,48 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         int F1 = FRAME_NONE;
         // inputs of a tile: global loads, in three steps spread over phases so that their
         // latency overlaps other work (ray window; ray search and feature loads; staging)
-        float xv[8], grv = 0.f;
+        // The loaded values stay raw until stage_tile (phase D), where lanes past the last sample
+        // and the padding columns are zeroed, so that nothing consumes the loads before then.
+        float4 xlo = make_float4(0.f, 0.f, 0.f, 0.f), xhi = xlo;
+        float grv = 0.f;
+        unsigned xok = 0;  // bit 0: xlo is real, bit 1: xhi is real, bit 2: grv is real
         auto load_tile = [&](int t, int r0, int win) {
             const int s = t * NT + xsl;
             const bool sv = s < a.S;
-            // all lanes take part; this wave's samples are t NT + 8 w + (lane >> 3)
-            const int ray = ray_of_group8(a.offs, a.n_rays, r0, win, t * NT + 8 * w);
-#pragma unroll
-            for (int e = 0; e < 8; ++e) xv[e] = 0.f;
-            grv = 0.f;
-            if (sv) {
-                load_x8(a, s, ray, xg >> 2, xg & 3, xv);
-                if (xg < 3) grv = a.grad_rgb[(int64_t)s * 3 + xg];
+            // all lanes take part; this wave's samples are t NT + 8 w + (lane >> 3).  Lanes past the
+            // last sample load from the last sample and its ray (kept in range).
+            const int ray = min(ray_of_group8(a.offs, a.n_rays, r0, win, t * NT + 8 * w), a.n_rays - 1);
+            const int sc = sv ? s : a.S - 1;
+            const int kk = xg >> 2, q = xg & 3;
+            if (a.feat_vec) {
+                // every lane issues the same two 16-byte loads and one 4-byte load, with no divergent
+                // branch around them (divergent branches would make one group's loads wait for the
+                // other's, as both write the same registers)
+                const float *pe = a.pe + (int64_t)ray * PEW;
+                const float *pl = kk == 0 && q < 3 ? a.feat + (int64_t)sc * 12 + 4 * q : pe + (kk == 0 ? 0 : 20 + 4 * q);
+                xlo = *reinterpret_cast<const float4 *>(pl);
+                xhi = *reinterpret_cast<const float4 *>(pe + 4 + 4 * q);
+                grv = a.grad_rgb[(int64_t)sc * 3 + (xg < 3 ? xg : 2)];
+                xok = (sv ? 1u : 0u) | (sv && kk == 0 ? 2u : 0u) | (sv && xg < 3 ? 4u : 0u);
+            } else {
+                float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                float g = 0.f;
+                if (sv) {
+                    load_x8(a, s, ray, kk, q, v);
+                    if (xg < 3) g = a.grad_rgb[(int64_t)s * 3 + xg];
+                }
+                xlo = make_float4(v[0], v[1], v[2], v[3]);
+                xhi = make_float4(v[4], v[5], v[6], v[7]);
+                grv = g;
+                xok = 7u;
             }
         };
         // ... and their split into the x plane of buffer pb (layer-1 B operand, read transposed by
         // dW1), max |x| and grad_rgb
         auto stage_tile = [&](int pb) {
+            const bool l = xok & 1u, h = xok & 2u;
+            const float xv[8] = {l ? xlo.x : 0.f, l ? xlo.y : 0.f, l ? xlo.z : 0.f, l ? xlo.w : 0.f,
+                                 h ? xhi.x : 0.f, h ? xhi.y : 0.f, h ? xhi.z : 0.f, h ? xhi.w : 0.f};
             float m = 0.f;
 #pragma unroll
             for (int e = 0; e < 8; ++e) m = fmaxf(m, fabsf(xv[e]));
@@ -1140,7 +1163,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 *reinterpret_cast<h8 *>(reinterpret_cast<_Float16 *>(sm + xb + NT * RS1 * 2) + xsl * RS1 + 8 * xg) =
                     cat(l0, l1);
             if (xg == 0) xmax_b[pb * NT + xsl] = m;
-            if (xg < 4) gr_b[(pb * NT + xsl) * 4 + xg] = grv;
+            if (xg < 4) gr_b[(pb * NT + xsl) * 4 + xg] = (xok & 4u) ? grv : 0.f;
         };
         // dW1 += dz1^T x of a finished tile (its x buffer pb; both operands read transposed from the
         // sample-major planes; logical inputs 0..47 in the three 16-column blocks)
@@ -1261,10 +1284,21 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                         make_float4(df[0] * un, df[1] * un, df[2] * un, df[3] * un);
             }
         };
-        if (stager && (int)blockIdx.x < ntiles) {
-            const int r0 = a.tile_ray[blockIdx.x];
-            load_tile(blockIdx.x, r0, window_entry(a.offs, a.n_rays, r0));
-            stage_tile(0);
+        // First rays of this block's tiles, 64 iterations at a time: lane l holds that of iteration
+        // wb + l (wb a multiple of 64; indices past the last tile repeat the last tile's ray, a
+        // valid ray).  One load per 64 tiles instead of a dependent load at the head of every tile.
+        auto ray_window = [&](int wb) {
+            const int t = (int)blockIdx.x + (wb + lane()) * (int)gridDim.x;
+            return a.tile_ray[t < ntiles ? t : ntiles - 1];
+        };
+        int trw = 0;
+        if ((int)blockIdx.x < ntiles) {
+            trw = ray_window(0);
+            if (stager) {
+                const int r0 = __builtin_amdgcn_readlane(trw, 0);
+                load_tile(blockIdx.x, r0, window_entry(a.offs, a.n_rays, r0));
+                stage_tile(0);
+            }
         }
         lds_barrier();  // staged image and the first tile's inputs
         int it = 0, pbase = -1;
@@ -1274,14 +1308,17 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
             const int pb = it & 1;
             const bool next = tile + (int)gridDim.x < ntiles;
-            // ---- A: dz1 of the previous tile; ray window of the next tile
-            const int r0n = next ? a.tile_ray[tile + gridDim.x] : 0;
+            // ---- A: ray window of the next tile (its loads are issued first and consumed in B);
+            //      dz1 of the previous tile
+            if (((it + 1) & 63) == 0) trw = ray_window(it + 1);
+            const int r0n = __builtin_amdgcn_readlane(trw, (it + 1) & 63);
+            const int winn = window_entry(a.offs, a.n_rays, r0n);
             if (pbase >= 0) dz1_step(pb ^ 1, pg2, pg1, pex);
-            const int winn = next ? window_entry(a.offs, a.n_rays, r0n) : 0;
             lds_barrier();
-            // ---- B: dW1 of the previous tile; loads of the next tile's inputs
-            if (next && stager) load_tile(tile + gridDim.x, r0n, winn);
+            // ---- B: dW1 of the previous tile; then the loads of the next tile's inputs, whose
+            //      latency runs through phase C (they are staged in D)
             if (pbase >= 0) dw1_step(pb ^ 1);
+            if (stager) load_tile(tile + gridDim.x, r0n, winn);  // past the last tile: zeroed, not staged
             lds_barrier();
             // ---- C: output gradient and exponents of this tile; the frame of dW1; db2 += dz2,
             //      db3 += dz3 (VALU, h2 from the P waves)
