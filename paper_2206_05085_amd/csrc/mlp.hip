@@ -408,28 +408,15 @@ __device__ __forceinline__ float4 feat4(const MlpArgs &a, int s, int c0) {
                        c0 + 2 < a.in_feat ? fp[c0 + 2] : 0.f, c0 + 3 < a.in_feat ? fp[c0 + 3] : 0.f);
 }
 
-// Features 4q..4q+3 of sample s looked up in the feature grid (GM = 1 plain, 2 through its warp)
-// and, when asked, written out for the backward.  Needs in_feat % 4 == 0 (checked on the host).
-template <int GM>
-__device__ __forceinline__ float4 gathered4(const MlpArgs &a, int s, int q) {
-    if (4 * q >= a.in_feat) return make_float4(0.f, 0.f, 0.f, 0.f);
-    const float *p = a.xyz + 3 * (int64_t)s;
-    const Tri t = trilinear<GM == 2>(a.fg, p[0], p[1], p[2]);
-    const float4 f = interp4(a.fg, t, 4 * q);
-    if (a.feat_out) *reinterpret_cast<float4 *>(a.feat_out + (int64_t)s * a.in_feat + 4 * q) = f;
-    return f;
-}
-
-// The 8 inputs of operand slot group (kk, q) of a valid sample s on ray `ray`: logical
-// columns k(kk, q, 0..7).  For kk = 0 these are features 4q..4q+3 (view encoding 0..3 when
-// q = 3) and view encoding 4+4q..7+4q; for kk = 1 view encoding 20+4q..23+4q and padding.
-// GM = 0: features from a.feat; 1, 2: looked up in the feature grid (gathered4).
-template <int GM = 0>
+// The 8 inputs of operand slot group (kk, q) of a valid sample s on ray `ray`, features read
+// from a.feat: logical columns k(kk, q, 0..7).  For kk = 0 these are features 4q..4q+3 (view
+// encoding 0..3 when q = 3) and view encoding 4+4q..7+4q; for kk = 1 view encoding 20+4q..23+4q
+// and padding.  (The kernels use it only for feature rows that cannot be read as float4.)
 __device__ __forceinline__ void load_x8(const MlpArgs &a, int s, int ray, int kk, int q, float v[8]) {
     const float *pe = a.pe + (int64_t)ray * PEW;
     float4 lo, hi;
     if (kk == 0) {
-        lo = q < 3 ? (GM ? gathered4<GM>(a, s, q) : feat4(a, s, 4 * q)) : *reinterpret_cast<const float4 *>(pe);
+        lo = q < 3 ? feat4(a, s, 4 * q) : *reinterpret_cast<const float4 *>(pe);
         hi = *reinterpret_cast<const float4 *>(pe + 4 + 4 * q);
     } else {
         lo = *reinterpret_cast<const float4 *>(pe + 20 + 4 * q);
@@ -477,28 +464,98 @@ __global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs 
     const Meta meta = *reinterpret_cast<const Meta *>(r1 + (IMG_META - IMG_W1H));
     const int ln = lane(), j = ln & 15, q = ln >> 4;
     const int nwt = (a.S + FWD_WTILE - 1) / FWD_WTILE;
-    for (int wt = blockIdx.x * FWD_WAVES + (threadIdx.x >> 6); wt < nwt; wt += gridDim.x * FWD_WAVES) {
+    const int wt0 = blockIdx.x * FWD_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wstep = gridDim.x * FWD_WAVES;
+    if (wt0 >= nwt) return;
+    // First ray of a wave tile's enclosing tile (past the last tile, the last tile's ray), read
+    // through the scalar cache: the index is wave-uniform and the table is read-only here.
+    const __attribute__((address_space(4))) int *tray = (const __attribute__((address_space(4))) int *)a.tile_ray;
+    auto first_ray = [&](int wt) { return tray[(wt < nwt ? wt : nwt - 1) / (TILE / FWD_WTILE)]; };
+    // sample points of a wave tile's feature lookups (the last sample's past the end)
+    auto points = [&](int wt, float (&p)[FWD_NC][3]) {
+#pragma unroll
+        for (int c = 0; c < FWD_NC; ++c) {
+            const int sp = min(wt * FWD_WTILE + 16 * c + j, a.S - 1);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) p[c][d] = a.xyz[3 * (int64_t)sp + d];
+        }
+    };
+    // The ray window entry and the sample points of the next tile are loaded one tile ahead,
+    // so their latency runs behind the products of the tile before.
+    // The output of a tile is stored at the head of the next one (after that tile's wait for its
+    // prefetched values), so that the wait does not include the store.
+    int r0 = first_ray(wt0);
+    int win = window_entry(a.offs, a.n_rays, r0);
+    int r0n = first_ray(wt0 + wstep);
+    float pt[FWD_NC][3];
+    if (GM) points(wt0, pt);
+    float zout[FWD_NC];
+    int sout[FWD_NC];
+#pragma unroll
+    for (int c = 0; c < FWD_NC; ++c) sout[c] = -1;
+    auto store_out = [&]() {
+#pragma unroll
+        for (int c = 0; c < FWD_NC; ++c)
+            if (q < 3 && sout[c] >= 0) a.rgb[(int64_t)sout[c] * 3 + q] = zout[c];
+    };
+    for (int wt = wt0; wt < nwt; wt += wstep) {
         int s[FWD_NC], ex[FWD_NC], e1[FWD_NC];
         bool sv[FWD_NC];
         h8 xh[FWD_NC][2], xl[FWD_NC][2];
-        const int r0 = a.tile_ray[wt / (TILE / FWD_WTILE)];  // first ray of the enclosing tile
-        const int win = window_entry(a.offs, a.n_rays, r0);
+        // this tile's inputs: every lane issues the same loads, with no divergent branch around them
+        // (divergent branches would make one lane group's loads wait for another's).  Slot group
+        // (kk, q): kk = 0 features 4q..4q+3 (view encoding 0..3 when q = 3) and view encoding
+        // 4+4q..7+4q; kk = 1 view encoding 20+4q..23+4q and padding.
+        float4 lo0[FWD_NC], hi0[FWD_NC], lo1[FWD_NC];
+        int ray[FWD_NC];
 #pragma unroll
         for (int c = 0; c < FWD_NC; ++c) {
             s[c] = wt * FWD_WTILE + 16 * c + j;
             sv[c] = s[c] < a.S;
-            int ray = ray_in_window(a.offs, a.n_rays, r0, win, s[c]);
-            if (!sv[c]) ray = 0;
-            float xv[2][8], m = 0.f;
+            ray[c] = min(ray_in_window(a.offs, a.n_rays, r0, win, s[c]), a.n_rays - 1);
+        }
+        store_out();  // the previous tile's output
+        // scalar load of a later tile's first ray, issued after the ray search so that the search's
+        // LDS waits do not wait for it (used one tile later)
+        const int r0f = first_ray(wt + 2 * wstep);
 #pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                if (sv[c]) load_x8<GM>(a, s[c], ray, kk, q, xv[kk]);
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    if (!sv[c]) xv[kk][e] = 0.f;
-                    m = fmaxf(m, fabsf(xv[kk][e]));
-                }
+        for (int c = 0; c < FWD_NC; ++c) {
+            const int sc = sv[c] ? s[c] : a.S - 1;
+            const float *pe = a.pe + (int64_t)ray[c] * PEW;
+            const float4 v0 = *reinterpret_cast<const float4 *>(pe);
+            hi0[c] = *reinterpret_cast<const float4 *>(pe + 4 + 4 * q);
+            lo1[c] = *reinterpret_cast<const float4 *>(pe + 20 + 4 * q);
+            const bool fq = 4 * q < a.in_feat;  // never for q = 3 (at most 12 features)
+            float4 f;
+            if (GM) {
+                const Tri t = trilinear<GM == 2>(a.fg, pt[c][0], pt[c][1], pt[c][2]);
+                f = interp4(a.fg, t, fq ? 4 * q : 0);
+                if (a.feat_out && fq && sv[c])
+                    *reinterpret_cast<float4 *>(a.feat_out + (int64_t)s[c] * a.in_feat + 4 * q) = f;
+            } else if (a.feat_vec) {
+                f = *reinterpret_cast<const float4 *>(a.feat + (int64_t)sc * 12 + (fq ? 4 * q : 0));
+            } else {
+                f = fq ? feat4(a, sc, 4 * q) : make_float4(0.f, 0.f, 0.f, 0.f);
             }
+            lo0[c] = q == 3 ? v0 : (fq ? f : make_float4(0.f, 0.f, 0.f, 0.f));
+        }
+        // the next tile's ray window entry and sample points
+        r0 = r0n;
+        r0n = r0f;
+        win = window_entry(a.offs, a.n_rays, r0);
+        if (GM) points(wt + wstep, pt);
+#pragma unroll
+        for (int c = 0; c < FWD_NC; ++c) {
+            const bool v = sv[c];
+            const float xv[2][8] = {{v ? lo0[c].x : 0.f, v ? lo0[c].y : 0.f, v ? lo0[c].z : 0.f, v ? lo0[c].w : 0.f,
+                                     v ? hi0[c].x : 0.f, v ? hi0[c].y : 0.f, v ? hi0[c].z : 0.f, v ? hi0[c].w : 0.f},
+                                    {v ? lo1[c].x : 0.f, v ? lo1[c].y : 0.f, v ? lo1[c].z : 0.f, v ? lo1[c].w : 0.f,
+                                     0.f, 0.f, 0.f, 0.f}};
+            float m = 0.f;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+                for (int e = 0; e < 8; ++e) m = fmaxf(m, fabsf(xv[kk][e]));
             m = fmaxf(m, __shfl_xor(m, 16, 64));
             m = fmaxf(m, __shfl_xor(m, 32, 64));
             ex[c] = scale_exp(m);
@@ -598,9 +655,11 @@ __global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs 
                 z[c][o] += __shfl_xor(z[c][o], 32, 64);
             }
             const float zq = q == 0 ? z[c][0] : (q == 1 ? z[c][1] : z[c][2]);
-            if (q < 3 && sv[c]) a.rgb[(int64_t)s[c] * 3 + q] = fast_sigmoid(zq + b3[q]);
+            zout[c] = fast_sigmoid(zq + b3[q < 3 ? q : 0]);
+            sout[c] = sv[c] ? s[c] : -1;
         }
     }
+    store_out();
 }
 
 // ------------------------------------------------------------------ backward
