@@ -200,12 +200,28 @@ __device__ __forceinline__ void lds_fence() { __builtin_amdgcn_fence(__ATOMIC_AC
 // vertex follows from its own cell), and alone issues the atomics.  Every contribution is
 // counted once: a non-head belongs to exactly one run, whose head reaches it.  All lanes
 // must call this (it shuffles); lanes with valid == false contribute nothing.
+// Whole-wave DPP shifts by one lane with zero fill (vector-ALU moves, no LDS round trip):
+// from_next: lane l takes lane l + 1's value (lane 63 takes 0); from_prev: lane l takes lane
+// l - 1's (lane 0 takes 0).  The empty asm keeps each shift a move of its own: the compiler
+// would otherwise fold it into the instruction that uses it.
+__device__ __forceinline__ int from_next(int x) {
+    int y = __builtin_amdgcn_update_dpp(0, x, 0x130, 0xF, 0xF, true);
+    asm volatile("" : "+v"(y));
+    return y;
+}
+__device__ __forceinline__ int from_prev(int x) {
+    int y = __builtin_amdgcn_update_dpp(0, x, 0x138, 0xF, 0xF, true);
+    asm volatile("" : "+v"(y));
+    return y;
+}
+__device__ __forceinline__ float from_next(float x) { return __builtin_bit_cast(float, from_next(__builtin_bit_cast(int, x))); }
+
 template <int NC>
 __device__ __forceinline__ void scatter_wave(const DevGrid &g, bool valid, const Cell &cl, const float (&v)[NC],
                                              int nch = NC) {
     const int ln = lane();
-    const int px = __shfl_up(cl.ix, 1, 64), py = __shfl_up(cl.iy, 1, 64), pz = __shfl_up(cl.iz, 1, 64);
-    const bool pvalid = (__shfl_up(valid ? 1 : 0, 1, 64) != 0) && ln > 0;
+    const int px = from_prev(cl.ix), py = from_prev(cl.iy), pz = from_prev(cl.iz);
+    const bool pvalid = from_prev(valid ? 1 : 0) != 0;  // lane 0 has no predecessor
     float acc[8][NC];
     unsigned head = 0;
 #pragma unroll
@@ -219,18 +235,25 @@ __device__ __forceinline__ void scatter_wave(const DevGrid &g, bool valid, const
         for (int ch = 0; ch < NC; ++ch) acc[c][ch] = w * v[ch];
     }
     unsigned active = head;
+    // the values of lane ln + k, moved one lane further each step (zeros past lane 63, so the
+    // validity flag of a lane beyond the wave reads as false)
+    int nx = cl.ix, ny = cl.iy, nz = cl.iz, nval = valid ? 1 : 0;
+    Cell nc = cl;
+    float nv[NC];
+#pragma unroll
+    for (int ch = 0; ch < NC; ++ch) nv[ch] = v[ch];
     for (int k = 1; k < 64; ++k) {
         if (__ballot(active != 0) == 0ull) break;
-        const int src = ln + k < 64 ? ln + k : ln;
-        const int nx = __shfl(cl.ix, src, 64), ny = __shfl(cl.iy, src, 64), nz = __shfl(cl.iz, src, 64);
-        Cell nc;
-        nc.fx = __shfl(cl.fx, src, 64);
-        nc.fy = __shfl(cl.fy, src, 64);
-        nc.fz = __shfl(cl.fz, src, 64);
-        const bool nvalid = (__shfl(valid ? 1 : 0, src, 64) != 0) && ln + k < 64;
-        float nv[NC];
+        nx = from_next(nx);
+        ny = from_next(ny);
+        nz = from_next(nz);
+        nval = from_next(nval);
+        nc.fx = from_next(nc.fx);
+        nc.fy = from_next(nc.fy);
+        nc.fz = from_next(nc.fz);
 #pragma unroll
-        for (int ch = 0; ch < NC; ++ch) nv[ch] = __shfl(v[ch], src, 64);
+        for (int ch = 0; ch < NC; ++ch) nv[ch] = from_next(nv[ch]);
+        const bool nvalid = nval != 0;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             if (!(active & (1u << c))) continue;
