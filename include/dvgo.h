@@ -414,23 +414,6 @@ int dvgo_mlp_backward_partials(const dvgo_color_mlp *m, int32_t n_rays, const in
 int dvgo_mlp_reduce_grads(const dvgo_color_mlp *m, int32_t n_rays, int64_t n_samples, void *ws, size_t ws_bytes,
                           void *stream);
 
-/* dvgo_mlp_backward and dvgo_mlp_backward_partials with the feature scatter fused in (the
- * backward of section 3's trilinear lookup): instead of writing grad_feat, each sample's feature
- * gradient times each of its eight trilinear weights at xyz[k] (the grid's warp applied) is added
- * atomically into feat_grid->grad (+=), as dvgo_grid_scatter does with grad_feat.  The per-sample
- * gradients equal those of dvgo_mlp_backward bit for bit; the grid's sums differ from the
- * two-call path only in the order of their terms.  Needs feat_grid->channels == in_feat
- * (DVGO_ERR_SHAPE) and feat_grid->grad and xyz [S,3] (DVGO_ERR_NULL).  The other arguments, the
- * workspace, the weight gradients (or their partials) and the reduction are as in the unfused
- * calls. */
-int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
-                              int64_t n_samples, const float *feat, const float *grad_rgb, const dvgo_grid *feat_grid,
-                              const float *xyz, void *ws, size_t ws_bytes, void *stream);
-int dvgo_mlp_backward_partials_scatter(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
-                                       const float *dirs, int64_t n_samples, const float *feat, const float *grad_rgb,
-                                       const dvgo_grid *feat_grid, const float *xyz, void *ws, size_t ws_bytes,
-                                       void *stream);
-
 /* Loss head: loss[0] = (1/(3R)) sum ||rgb_r - target_r||^2 + dist_weight (1/R) sum dist_r
  * (dist may be NULL: no distortion term); grad_rgb [R,3] and grad_dist [R] (may be NULL)
  * receive dloss/drgb and dloss/ddist.  The paper weights the distortion term by 1e-2

@@ -108,8 +108,6 @@ SIGNATURES = {
     "dvgo_mlp_forward_gather": (C.c_int, [_PM, _I32, VP, VP, _I64, _PG, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_backward_partials": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, VP, VP, C.c_size_t, VP]),
-    "dvgo_mlp_backward_scatter": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, _PG, VP, VP, C.c_size_t, VP]),
-    "dvgo_mlp_backward_partials_scatter": (C.c_int, [_PM, _I32, VP, VP, _I64, VP, VP, _PG, VP, VP, C.c_size_t, VP]),
     "dvgo_mlp_reduce_grads": (C.c_int, [_PM, _I32, _I64, VP, C.c_size_t, VP]),
     "dvgo_loss_head": (C.c_int, [_I32, VP, VP, VP, _F, VP, VP, VP, VP]),
     "dvgo_proposal_coarse": (C.c_int, [_PR, _PG, _F, _F, _F, VP, VP, VP]),

@@ -709,8 +709,7 @@ constexpr int B_H2 = B_DFP + BWD_RW * NT * DFS * 4;  // h2 [H][H2S] f32, written
 constexpr int B_MASK = B_H2 + H * H2S * 4;           // h1 > 0 bits per lane [2][RW waves][64 lanes] u16
 constexpr int B_XMAX = B_MASK + 2 * BWD_RW * 64 * 2; // max |x| per sample [2][NT]
 constexpr int B_GR = B_XMAX + 2 * NT * 4;            // grad_rgb [2][NT][4]
-constexpr int B_XYZ = B_GR + 2 * NT * 16;            // sample points [3][NT][4] (feature-grid scatter)
-constexpr int B_END = B_XYZ + 3 * NT * 16;
+constexpr int B_END = B_GR + 2 * NT * 16;
 static_assert(B_END <= 160 * 1024, "backward LDS");
 static_assert(B_XB0 % 16 == 0 && B_HB % 16 == 0 && B_DB % 16 == 0 && B_D2S % 16 == 0 && B_D1S % 16 == 0 &&
                   B_Z3P % 16 == 0 && B_DFP % 16 == 0 && B_MASK % 8 == 0,
@@ -878,9 +877,7 @@ __device__ __forceinline__ void rescale(v4f (&acc)[M][N], int &F, int f) {
     }
 }
 
-// SC = 0: the feature gradient of every sample goes to a.grad_feat; SC = 1 (plain grid), 2 (through
-// the grid's warp): it is scattered into the feature grid's gradient instead (a.fg, a.xyz).
-template <bool SPLIT, int SC>
+template <bool SPLIT>
 __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     __shared__ __attribute__((aligned(16))) unsigned char sm[B_END];
     copy_to_lds(sm, a.img + IMG_B1, BS);
@@ -903,32 +900,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
     uint16_t *mask_b = reinterpret_cast<uint16_t *>(rB + (B_MASK - B_Z3P));
     float *xmax_b = reinterpret_cast<float *>(rB + (B_XMAX - B_Z3P));
     float *gr_b = reinterpret_cast<float *>(rB + (B_GR - B_Z3P));
-    float *xyz_b = reinterpret_cast<float *>(rB + (B_XYZ - B_Z3P));
-    // SC > 0: the feature gradient of a finished tile (first sample pbase, sample points in slot
-    // `slot` of the three-tile ring) goes straight into the feature grid's gradient: per sample
-    // and channel the C waves' partials summed in the fixed order of feat_grad_out, times each of
-    // the eight trilinear weights, one atomic add per corner (the grid sums them in any order).
-    // The P waves issue them: they load nothing in the tile loop, so no wait of theirs includes
-    // the atomics.  t = the calling thread's index within its role.
-    auto feat_scatter = [&](int slot, int pbase, int t) {
-        const int C = a.in_feat;
-        const int rounds = (NT * C + BWD_RT - 1) / BWD_RT;  // wave-uniform trip count
-        for (int k = 0; k < rounds; ++k) {
-            const int i = t + k * BWD_RT;
-            const int sl = i / C, c = i - sl * C;
-            if (i >= NT * C || pbase + sl >= a.S) continue;
-            float g = dfp[sl * DFS + c];
-#pragma unroll
-            for (int ww = 1; ww < BWD_RW; ++ww) g += dfp[(ww * NT + sl) * DFS + c];
-            const float *p = xyz_b + (slot * NT + sl) * 4;
-            const Cell cl = cell_of<SC == 2>(a.fg, p[0], p[1], p[2]);
-            const int idx = cl.ix * a.fg.sx + cl.iy * a.fg.sy + cl.iz * a.fg.cs + c;  // < 2^31 (checked on the host)
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-                unsafeAtomicAdd(a.fg.grad + (idx + corner_off(a.fg, k)),
-                                corner_weight(cl, (k >> 2) & 1, (k >> 1) & 1, k & 1) * g);
-        }
-    };
     const int ntiles = a.n_tiles;
     float *P = a.partial + (int64_t)blockIdx.x * a.n_params;
     float *pW1 = P, *pb1 = pW1 + H * a.n_in, *pW2 = pb1 + H, *pb2 = pW2 + H * H, *pW3 = pb2 + H, *pb3 = pW3 + 3 * H;
@@ -950,17 +921,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 const int o = (16 * (BWD_MP * w + mp) + j) * RS1 + 32 * kk + 8 * q;
                 w1h[mp][kk] = glb_h8(a.img, IMG_W1H, o);
                 w1l[mp][kk] = glb_h8(a.img, IMG_W1L, o);
-            }
-        }
-        if (SC) {
-            // the weight loads complete here: a first use inside the tile loop would put their wait
-            // (on the in-order memory counter) behind the feature-grid atomics of the loop's phase D
-#pragma unroll
-            for (int mp = 0; mp < BWD_MP; ++mp) {
-#pragma unroll
-                for (int kk = 0; kk < 4; ++kk) asm volatile("" ::"v"(w2h[mp][kk]), "v"(w2l[mp][kk]));
-#pragma unroll
-                for (int kk = 0; kk < 2; ++kk) asm volatile("" ::"v"(w1h[mp][kk]), "v"(w1l[mp][kk]));
             }
         }
         v4f dW2[BWD_MP][8];
@@ -1150,19 +1110,13 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 }
             }
             lds_barrier();
-            // ---- D: feature gradient of the previous tile (its partials came from the C waves' phase A):
-            //      written per sample, or (SC > 0) scattered into the feature grid
-            if (it > 0) {
-                if (SC) feat_scatter((it - 1) % 3, (tile - (int)gridDim.x) * NT, tid);
-                else feat_grad_out(a, dfp, (tile - (int)gridDim.x) * NT, tid);
-            }
+            // ---- D: feature gradient of the previous tile (its partials came from the C waves' phase A)
+            if (it > 0) feat_grad_out(a, dfp, (tile - (int)gridDim.x) * NT, tid);
             lds_barrier();
         }
-        // dW2 of the last tile; the C side's last A/B pair (SC > 0: the last tile's feature
-        // gradient, whose partials the C waves' last phase A wrote)
+        // dW2 of the last tile; the C side's last A/B pair
         if (it > 0) dw2_step(lds_region(sm, B_HB + ((it - 1) & 1) * HB_BYTES));
         lds_barrier();
-        if (SC && it > 0) feat_scatter((it - 1) % 3, ((int)blockIdx.x + (it - 1) * (int)gridDim.x) * NT, tid);
         lds_barrier();
         // ---- partial gradient of the P role: W2
         const int u2 = F2 == FRAME_NONE ? 0 : -F2;
@@ -1215,7 +1169,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         // The loaded values stay raw until stage_tile (phase D), where lanes past the last sample
         // and the padding columns are zeroed, so that nothing consumes the loads before then.
         float4 xlo = make_float4(0.f, 0.f, 0.f, 0.f), xhi = xlo;
-        float grv = 0.f, xyzv = 0.f;
+        float grv = 0.f;
         unsigned xok = 0;  // bit 0: xlo is real, bit 1: xhi is real, bit 2: grv is real
         auto load_tile = [&](int t, int r0, int win) {
             const int s = t * NT + xsl;
@@ -1234,7 +1188,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 xlo = *reinterpret_cast<const float4 *>(pl);
                 xhi = *reinterpret_cast<const float4 *>(pe + 4 + 4 * q);
                 grv = a.grad_rgb[(int64_t)sc * 3 + (xg < 3 ? xg : 2)];
-                if (SC) xyzv = a.xyz[(int64_t)sc * 3 + (xg < 3 ? xg : 2)];
                 xok = (sv ? 1u : 0u) | (sv && kk == 0 ? 2u : 0u) | (sv && xg < 3 ? 4u : 0u);
             } else {
                 float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -1242,7 +1195,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 if (sv) {
                     load_x8(a, s, ray, kk, q, v);
                     if (xg < 3) g = a.grad_rgb[(int64_t)s * 3 + xg];
-                    if (SC && xg < 3) xyzv = a.xyz[(int64_t)s * 3 + xg];
                 }
                 xlo = make_float4(v[0], v[1], v[2], v[3]);
                 xhi = make_float4(v[4], v[5], v[6], v[7]);
@@ -1252,7 +1204,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         };
         // ... and their split into the x plane of buffer pb (layer-1 B operand, read transposed by
         // dW1), max |x| and grad_rgb
-        auto stage_tile = [&](int pb, int slot) {
+        auto stage_tile = [&](int pb) {
             const bool l = xok & 1u, h = xok & 2u;
             const float xv[8] = {l ? xlo.x : 0.f, l ? xlo.y : 0.f, l ? xlo.z : 0.f, l ? xlo.w : 0.f,
                                  h ? xhi.x : 0.f, h ? xhi.y : 0.f, h ? xhi.z : 0.f, h ? xhi.w : 0.f};
@@ -1271,7 +1223,6 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     cat(l0, l1);
             if (xg == 0) xmax_b[pb * NT + xsl] = m;
             if (xg < 4) gr_b[(pb * NT + xsl) * 4 + xg] = (xok & 4u) ? grv : 0.f;
-            if (SC && xg < 3) xyz_b[(slot * NT + xsl) * 4 + xg] = xyzv;
         };
         // dW1 += dz1^T x of a finished tile (its x buffer pb; both operands read transposed from the
         // sample-major planes; logical inputs 0..47 in the three 16-column blocks)
@@ -1405,7 +1356,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             if (stager) {
                 const int r0 = __builtin_amdgcn_readlane(trw, 0);
                 load_tile(blockIdx.x, r0, window_entry(a.offs, a.n_rays, r0));
-                stage_tile(0, 0);
+                stage_tile(0);
             }
         }
         lds_barrier();  // staged image and the first tile's inputs
@@ -1470,7 +1421,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             // ---- D: the next tile's inputs -> x planes (the P waves write the previous tile's
             //      feature gradient meanwhile); dW3 += dz3 h2^T of this tile (h2 stays until the
             //      P waves' next layer 2)
-            if (next && stager) stage_tile(pb ^ 1, (it + 1) % 3);
+            if (next && stager) stage_tile(pb ^ 1);
             dw3_step(tdz3, j, q);
             lds_barrier();
             pbase = tile * NT;
@@ -1480,7 +1431,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         lds_barrier();
         if (pbase >= 0) {
             dw1_step((it - 1) & 1);
-            if (SC == 0) feat_grad_out(a, dfp, pbase, ct);
+            feat_grad_out(a, dfp, pbase, ct);
         }
         lds_barrier();
         // ---- partial gradients of the C role: W1, b1, b2, W3, b3
@@ -1710,49 +1661,25 @@ int launch_reduce(const MlpArgs &a, hipStream_t st) {
     return check_hip(hipGetLastError(), "mlp_reduce_kernel launch");
 }
 
-template <bool SPLIT>
-void launch_bwd(const MlpArgs &a, int sc, hipStream_t st) {
-    if (sc == 0)
-        hipLaunchKernelGGL((mlp_bwd_kernel<SPLIT, 0>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
-    else if (sc == 1)
-        hipLaunchKernelGGL((mlp_bwd_kernel<SPLIT, 1>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
-    else
-        hipLaunchKernelGGL((mlp_bwd_kernel<SPLIT, 2>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
-}
-
-// feat_grid == nullptr: per-sample feature gradients to grad_feat; otherwise scattered into the
-// grid's gradient at xyz
 int mlp_backward_impl(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets, const float *dirs,
-                      int64_t n_samples, const float *feat, const float *grad_rgb, float *grad_feat,
-                      const dvgo_grid *feat_grid, const float *xyz, void *ws, size_t ws_bytes, void *stream,
-                      bool reduce) {
+                      int64_t n_samples, const float *feat, const float *grad_rgb, float *grad_feat, void *ws,
+                      size_t ws_bytes, void *stream, bool reduce) {
     MlpArgs a;
     int rc = setup(m, n_rays, ray_offsets, dirs, n_samples, feat, ws, ws_bytes, true, a);
     if (rc) return rc;
-    if (feat_grid) {
-        rc = make_dev_grid(feat_grid, "feature grid", &a.fg, true);
-        if (rc) return rc;
-        if (feat_grid->channels != m->in_feat)
-            return set_error(DVGO_ERR_SHAPE, "feature grid channels (%d) != in_feat (%d)", feat_grid->channels,
-                             m->in_feat);
-    }
     if (n_samples == 0) return DVGO_OK;
-    if (!grad_rgb) return set_error(DVGO_ERR_NULL, "grad_rgb is NULL");
-    if (!feat_grid && !grad_feat) return set_error(DVGO_ERR_NULL, "grad_feat is NULL");
-    if (feat_grid && !xyz) return set_error(DVGO_ERR_NULL, "xyz is NULL");
+    if (!grad_rgb || !grad_feat) return set_error(DVGO_ERR_NULL, "grad_rgb or grad_feat is NULL");
     a.grad_rgb = grad_rgb;
     a.grad_feat = grad_feat;
-    a.xyz = xyz;
-    const int sc = feat_grid ? (a.fg.warp ? 2 : 1) : 0;
     hipStream_t st = (hipStream_t)stream;
     if (!m->prepared) {
         rc = launch_prep(a, st);
         if (rc) return rc;
     }
     if (m->precision == DVGO_MLP_F16)
-        launch_bwd<false>(a, sc, st);
+        hipLaunchKernelGGL((mlp_bwd_kernel<false>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     else
-        launch_bwd<true>(a, sc, st);
+        hipLaunchKernelGGL((mlp_bwd_kernel<true>), dim3(a.nblocks), dim3(BWD_THREADS), 0, st, a);
     rc = check_hip(hipGetLastError(), "mlp_bwd_kernel launch");
     if (rc || !reduce) return rc;
     return launch_reduce(a, st);
@@ -1763,35 +1690,16 @@ int mlp_backward_impl(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ra
 extern "C" int dvgo_mlp_backward(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
                                  const float *dirs, int64_t n_samples, const float *feat, const float *grad_rgb,
                                  float *grad_feat, void *ws, size_t ws_bytes, void *stream) {
-    return mlp_backward_impl(m, n_rays, ray_offsets, dirs, n_samples, feat, grad_rgb, grad_feat, nullptr, nullptr,
-                             ws, ws_bytes, stream, true);
+    return mlp_backward_impl(m, n_rays, ray_offsets, dirs, n_samples, feat, grad_rgb, grad_feat, ws, ws_bytes,
+                             stream, true);
 }
 
 extern "C" int dvgo_mlp_backward_partials(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
                                           const float *dirs, int64_t n_samples, const float *feat,
                                           const float *grad_rgb, float *grad_feat, void *ws, size_t ws_bytes,
                                           void *stream) {
-    return mlp_backward_impl(m, n_rays, ray_offsets, dirs, n_samples, feat, grad_rgb, grad_feat, nullptr, nullptr,
-                             ws, ws_bytes, stream, false);
-}
-
-extern "C" int dvgo_mlp_backward_scatter(const dvgo_color_mlp *m, int32_t n_rays, const int32_t *ray_offsets,
-                                         const float *dirs, int64_t n_samples, const float *feat,
-                                         const float *grad_rgb, const dvgo_grid *feat_grid, const float *xyz,
-                                         void *ws, size_t ws_bytes, void *stream) {
-    if (!feat_grid) return set_error(DVGO_ERR_NULL, "feature grid is NULL");
-    return mlp_backward_impl(m, n_rays, ray_offsets, dirs, n_samples, feat, grad_rgb, nullptr, feat_grid, xyz, ws,
-                             ws_bytes, stream, true);
-}
-
-extern "C" int dvgo_mlp_backward_partials_scatter(const dvgo_color_mlp *m, int32_t n_rays,
-                                                  const int32_t *ray_offsets, const float *dirs, int64_t n_samples,
-                                                  const float *feat, const float *grad_rgb,
-                                                  const dvgo_grid *feat_grid, const float *xyz, void *ws,
-                                                  size_t ws_bytes, void *stream) {
-    if (!feat_grid) return set_error(DVGO_ERR_NULL, "feature grid is NULL");
-    return mlp_backward_impl(m, n_rays, ray_offsets, dirs, n_samples, feat, grad_rgb, nullptr, feat_grid, xyz, ws,
-                             ws_bytes, stream, false);
+    return mlp_backward_impl(m, n_rays, ray_offsets, dirs, n_samples, feat, grad_rgb, grad_feat, ws, ws_bytes,
+                             stream, false);
 }
 
 extern "C" int dvgo_mlp_reduce_grads(const dvgo_color_mlp *m, int32_t n_rays, int64_t n_samples, void *ws,

@@ -581,38 +581,6 @@ def mlp_backward_partials(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, ws,
                               prepared)
 
 
-def _mlp_backward_scatter_call(entry, mlp, ray_offsets, dirs, feat, grad_rgb, feat_grid, xyz, ws, prepared):
-    import ctypes
-    if prepared and ws is None:
-        raise ValueError("prepared=True needs the workspace of the preceding call")
-    if feat_grid.grad is None:
-        raise ValueError("the feature grid needs a gradient buffer")
-    R = ray_offsets.numel() - 1
-    S = feat.shape[0]
-    _chk(grad_rgb, "grad_rgb", numel=3 * S)
-    _chk(xyz, "xyz", numel=3 * S)
-    ws = _mlp_ws(mlp, R, S, ws, feat.device)
-    m = mlp.struct(need_grad=True, prepared=prepared)
-    call(entry, ctypes.byref(m), R, _p(ray_offsets), _p(dirs), S, _p(feat), _p(grad_rgb),
-         ctypes.byref(feat_grid.struct()), _p(xyz), _p(ws), ws.numel(), _stream())
-
-
-def mlp_backward_scatter(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, feat_grid: DeviceGrid, xyz, ws=None,
-                         prepared=False):
-    """mlp_backward whose per-sample feature gradients go straight into feat_grid.grad (+=) through
-    the trilinear weights at xyz, as grid_scatter would add them (no per-sample output)."""
-    _mlp_backward_scatter_call("dvgo_mlp_backward_scatter", mlp, ray_offsets, dirs, feat, grad_rgb, feat_grid, xyz,
-                               ws, prepared)
-
-
-def mlp_backward_partials_scatter(mlp: MLPParams, ray_offsets, dirs, feat, grad_rgb, feat_grid: DeviceGrid, xyz, ws,
-                                  prepared=False):
-    """mlp_backward_scatter with the weight and bias gradients left in ws as per-block partials
-    (mlp_reduce_grads adds them)."""
-    _mlp_backward_scatter_call("dvgo_mlp_backward_partials_scatter", mlp, ray_offsets, dirs, feat, grad_rgb,
-                               feat_grid, xyz, ws, prepared)
-
-
 def mlp_reduce_grads(mlp: MLPParams, n_rays: int, n_samples: int, ws):
     """Add the partials a preceding mlp_backward_partials left in ws into mlp.gW / mlp.gb."""
     import ctypes

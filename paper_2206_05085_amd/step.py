@@ -3,8 +3,7 @@
 Feature-grid mode (hybrid colour, Table 1):
     grid_gather(features) -> mlp_forward (or both in mlp_forward_gather) -> render_forward (density gather, alpha,
     compositing, distortion) -> loss_head -> render_backward (density grad +=, d rgb)
-    -> mlp_backward (d features, MLP grads +=) -> grid_scatter (feature grad +=), or both in
-    mlp_backward_scatter
+    -> mlp_backward (d features, MLP grads +=) -> grid_scatter (feature grad +=)
     -> grid_adam_step x 3 (density, features, MLP) with zero-gradient skipping on the grids.
 Colour-grid mode: render_forward/backward with a 3-channel colour grid, then Adam.
 
@@ -25,7 +24,7 @@ class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
                  tv=None, warp=None, mlp_precision=0, binned_scatter=True, owner_scatter=False, concurrent=True,
-                 fused_gather=True, fused_scatter=False, device="cuda"):
+                 fused_gather=True, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
         tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
@@ -49,12 +48,7 @@ class TrainStep:
         weights (which bumps their version) makes the next step prepare again.
         fused_gather: look the features up inside the colour head's forward kernel (which also
         writes them for the backward) instead of a separate gather kernel (feature rows whose
-        channel count is a multiple of 4).  fused_scatter (off by default: the step measured
-        slower with it): the colour head's backward kernel adds each sample's feature gradient
-        into the feature grid's gradient itself (trilinear weights, one atomic per corner and
-        channel) instead of writing per-sample gradients for the separate scatter kernel, whose
-        in-wave merging of consecutive samples issues about half the atomics and which overlaps
-        the second stream's density work."""
+        channel count is a multiple of 4)."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -72,7 +66,6 @@ class TrainStep:
         self._prep_version = -1  # torch version of the MLP weights that preparation was made from
         self.warp = (0, 1.0) if warp is None else (int(warp[0]), float(warp[1]))
         self.fused_gather = bool(fused_gather) and feat is not None and np.shape(feat)[-1] % 4 == 0
-        self.fused_scatter = bool(fused_scatter) and feat is not None
         self.lr_grid, self.lr_mlp, self.betas, self.eps = lr_grid, lr_mlp, betas, eps
         self.t_dev = torch.zeros(1, dtype=torch.int32, device=device)  # Adam step, advanced on the device
         self.density = self._param(dev(density))
@@ -252,8 +245,7 @@ class TrainStep:
         self._adam("density", self.lr_grid, True)
 
     def _update_feat(self):
-        if not self.fused_scatter:
-            self._scatter_feat()
+        self._scatter_feat()
         if self.tv is not None:
             ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
         self._adam("feat", self.lr_grid, True)
@@ -296,24 +288,9 @@ class TrainStep:
 
     def _mlp_backward_and_scatter(self):
         b = self.batch
-        if self.fused_scatter:
-            ops.mlp_backward_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.grid("feat"),
-                                     b.xyz, ws=self.mlp_ws, prepared=True)
-            return
         ops.mlp_backward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, grad_feat=self.g_feat_s,
                          ws=self.mlp_ws, prepared=True)
         self._scatter_feat()
-
-    def _mlp_backward_partials(self):
-        """The colour-head backward with its weight gradients left as per-block partials; the
-        feature gradient scattered inside it (fused_scatter) or written per sample."""
-        b = self.batch
-        if self.fused_scatter:
-            ops.mlp_backward_partials_scatter(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s,
-                                              self.grid("feat"), b.xyz, self.mlp_ws, prepared=True)
-        else:
-            ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
-                                      grad_feat=self.g_feat_s, prepared=True)
 
     def _adam(self, name, lr, skip):
         b1, b2 = self.betas
@@ -394,7 +371,8 @@ class TrainStep:
         ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
                             None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
                             schedule=self.schedule, grad_sample_density=self.g_raw)
-        self._mlp_backward_partials()
+        ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
+                                  grad_feat=self.g_feat_s, prepared=True)
 
         def density_work():
             self._bin()
@@ -449,7 +427,8 @@ class TrainStep:
                             None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
                             schedule=self.schedule, grad_sample_density=self.g_raw)
         # the weight-gradient reduction waits on the side stream: only the MLP Adam needs it
-        self._mlp_backward_partials()
+        ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
+                                  grad_feat=self.g_feat_s, prepared=True)
 
         def density_work():
             if self.fused_gather:
@@ -460,8 +439,7 @@ class TrainStep:
             self._adam("density", self.lr_grid, True)
 
         self._side_tail(main, side, density_work)
-        if not self.fused_scatter:
-            ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
+        ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
         if self.tv is not None:
             ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
         self._adam("feat", self.lr_grid, True)

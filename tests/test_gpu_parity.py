@@ -687,59 +687,6 @@ def test_mlp_forward_gather_equals_gather_then_forward(dv, case):
         close(got.cpu().numpy(), ref, **FWD, name="fused-gather rgb")
 
 
-@pytest.mark.parametrize("case", ["plain", "warped", "f16", "partials", "accumulate", "multi_block"])
-def test_mlp_backward_scatter_equals_backward_then_scatter(dv, case):
-    # the colour head's backward with the feature scatter inside the kernel: the weight gradients
-    # equal the unfused backward's bit for bit (same products, same fixed-order reduction); the
-    # feature grid's gradient equals the unfused backward followed by the grid scatter up to the
-    # order of the summed terms (both are pinned to the oracle by the tests above)
-    rng = np.random.default_rng(43)
-    if case == "warped":
-        wl = synth.config3(R=64, n=48)
-    elif case == "multi_block":
-        wl = synth.config2(R=2048, n=64)
-    else:
-        wl = synth.config2(R=300, n=40)
-    smp = wl.samples
-    mlp = synth.mlp_weights(rng, bias_std=0.3)
-    R, S = smp.n_rays, smp.n_samples
-    say("mlp backward with fused feature scatter,", case, "S =", S)
-    offs, dirs, xyz = T(smp.ray_offsets, torch.int32), T(wl.rays.dirs), T(smp.xyz)
-    feat = dv.grid_gather(dgrid(dv, wl.feat), xyz)
-    grgb = T(rng.standard_normal((S, 3)) * 0.1)
-    g0 = rng.standard_normal(wl.feat.data.shape).astype(np.float32)
-    prec = dv.MLP_F16 if case == "f16" else dv.MLP_SPLIT_F16
-
-    def run(fused):
-        W = [T(w) for w in mlp.W]
-        b = [T(v) for v in mlp.b]
-        gW = [torch.zeros_like(w) for w in W]
-        gb = [torch.zeros_like(v) for v in b]
-        P = dv.MLPParams(W, b, gW, gb, precision=prec)
-        fg = dgrid(dv, wl.feat, grad=True)
-        if case == "accumulate":
-            fg.grad = T(g0)
-        if not fused:
-            gf = dv.mlp_backward(P, offs, dirs, feat, grgb)
-            dv.grid_scatter(fg, xyz, gf)
-        elif case == "partials":
-            ws = torch.empty(dv.mlp_workspace_size(P, R, S), dtype=torch.uint8, device="cuda")
-            dv.mlp_prepare(P, offs, dirs, S, ws)
-            dv.mlp_backward_partials_scatter(P, offs, dirs, feat, grgb, fg, xyz, ws, prepared=True)
-            dv.mlp_reduce_grads(P, R, S, ws)
-        else:
-            dv.mlp_backward_scatter(P, offs, dirs, feat, grgb, fg, xyz)
-        torch.cuda.synchronize()
-        return fg.grad.cpu().numpy(), [x.cpu().numpy() for x in gW + gb]
-
-    gu, wu = run(True)
-    gt, wt = run(False)
-    for x, y in zip(wu, wt):
-        np.testing.assert_array_equal(x, y)
-    assert np.abs(gt - (g0 if case == "accumulate" else 0.0)).max() > 0  # the scatter added something
-    close(gu, gt, **GRAD, name="fused feature scatter vs backward + scatter")
-
-
 def test_mlp_forward_gather_rejects_unsupported(dv):
     rng = np.random.default_rng(41)
     mlp = synth.mlp_weights(rng, bias_std=0.3)

@@ -43,24 +43,21 @@ def oracle_step_grads(wl, shift):
     return L, o, og["grad_density"], gfeat, gW, gb
 
 
-def make_step(step_mod, wl, **kw):
+def make_step(step_mod, wl):
     from paper_2206_05085_amd import ops
     st = step_mod.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max), feat=wl.feat.data,
-                            mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight, **kw)
+                            mlp=(wl.mlp.W, wl.mlp.b), dist_weight=wl.dist_weight)
     smp = wl.samples
     b = ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len)
     st.bind(b, wl.rays.dirs, wl.target)
     return st
 
 
-@pytest.mark.parametrize("fused_scatter", [False, True])
-def test_whole_step_gradients(pkg, fused_scatter):
-    # every gradient of one step against the oracle's, with the feature scatter apart or fused into
-    # the colour head's backward
+def test_whole_step_gradients(pkg):
     ops, _, step = pkg
     wl = synth.config2(R=384, n=64, mlp_bias_std=0.2)
-    say("whole step, 64^3 grids, 384 pinhole rays, S =", wl.samples.n_samples, "fused scatter", fused_scatter)
-    st = make_step(step, wl, fused_scatter=fused_scatter)
+    say("whole step, 64^3 grids, 384 pinhole rays, S =", wl.samples.n_samples)
+    st = make_step(step, wl)
     st.forward()
     st.backward()
     torch.cuda.synchronize()
@@ -111,29 +108,24 @@ def test_graph_replays_match_eager(pkg):
               name=f"mlp replay {rep}")
 
 
-@pytest.mark.parametrize("gather_apart,tv,owner,fs", [(False, True, True, False), (True, True, True, False),
-                                                      (False, False, True, False), (True, False, True, False),
-                                                      (False, True, False, False), (False, False, False, True),
-                                                      (True, True, True, True)])
-def test_two_stream_step_matches_sequential(pkg, gather_apart, tv, owner, fs):
+@pytest.mark.parametrize("gather_apart,tv,owner", [(False, True, True), (True, True, True), (False, False, True),
+                                                   (True, False, True), (False, True, False)])
+def test_two_stream_step_matches_sequential(pkg, gather_apart, tv, owner):
     # the step that overlaps the density update and the MLP Adam on a second stream (with the
     # feature gather fused into the colour head's forward or run apart, which moves the counter,
     # the preparation and the binning to the side stream; with a TV term, or without one, where
-    # each grid's Adam is fused into its owner-brick scatter; or with the atomic scatters; with the
-    # feature scatter apart or fused into the colour head's backward) takes the same update as the
-    # strictly sequential step with every stage apart, eagerly and from a graph
+    # each grid's Adam is fused into its owner-brick scatter; or with the atomic scatters) takes the
+    # same update as the strictly sequential step, eagerly and from a graph
     ops, _, step = pkg
     wl = synth.config2(R=256, n=48)
-    say("two-stream step vs sequential, 48^3, 256 rays, gather apart", gather_apart, "TV", tv, "owner", owner,
-        "fused scatter", fs)
+    say("two-stream step vs sequential, 48^3, 256 rays, gather apart", gather_apart, "TV", tv, "owner", owner)
     tvt = (1e-3, 1e-4, 1.0, True) if tv else None
-    mk = lambda conc, fg=True, f=False: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max),
-                                                       feat=wl.feat.data, mlp=(wl.mlp.W, wl.mlp.b),
-                                                       dist_weight=wl.dist_weight, tv=tvt, owner_scatter=owner,
-                                                       concurrent=conc, fused_gather=fg, fused_scatter=f)
+    mk = lambda conc, fg=True: step.TrainStep(wl.density.data, (wl.density.xyz_min, wl.density.xyz_max),
+                                              feat=wl.feat.data, mlp=(wl.mlp.W, wl.mlp.b),
+                                              dist_weight=wl.dist_weight, tv=tvt, owner_scatter=owner,
+                                              concurrent=conc, fused_gather=fg)
     smp = wl.samples
-    seq, conc, gr = mk(False), mk(True, not gather_apart, fs), mk(True, not gather_apart, fs)
-    assert conc.fused_scatter == gr.fused_scatter == fs
+    seq, conc, gr = mk(False), mk(True, not gather_apart), mk(True, not gather_apart)
     assert conc.fused_gather == gr.fused_gather == (not gather_apart)
     for st in (seq, conc, gr):
         st.bind(ops.SampleBatch.from_arrays(smp.ray_offsets, smp.xyz, smp.delta, smp.s_mid, smp.s_len),
