@@ -1262,6 +1262,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         };
         // dz1 = mask(h1) W2^T dz2 of a tile (mask bits of parity pb, exponents g2/g1/ex of that
         // tile), dfeat partials, dz1 in the dW1 frame
+        float kdz1[BWD_MP][2][4];  // dz1 of the last dz1_step, for its feature partials
         auto dz1_step = [&](int pb, const int g2[2], const int g1[2], const int ex[2]) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
             // this lane's h1 > 0 bits, read before the products so the load is long done
@@ -1310,15 +1311,26 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     put_split4<SPLIT>(d1s, (16 * c + j) * RS2 + unit_col(BWD_MP * w + mp) + 8 * q, dz1[mp][c], fs);
                 }
             }
-            // dfeat partial over this wave's units: rows = feature 4q + r, column = sample
+#pragma unroll
+            for (int mp = 0; mp < BWD_MP; ++mp)
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) kdz1[mp][c][r] = dz1[mp][c][r];
+        };
+        // dfeat partial of the tile whose dz1 the last dz1_step computed (kdz1; exponents g1 of that
+        // tile) over this wave's units: rows = feature 4q + r, column = sample.  It runs in phase B,
+        // where the C waves wait for the P waves' layer 2, instead of lengthening phase A.
+        auto dfeat_step = [&](const int g1[2]) {
+            const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
                 const float sc = pow2(g1[c]);
                 v4f df = v4f{0.f, 0.f, 0.f, 0.f};
                 if constexpr (BWD_MP == 2) {
                     h4 h0, l0, h1v, l1v;
-                    split4<true>(dz1[0][c], sc, h0, l0);
-                    split4<true>(dz1[1][c], sc, h1v, l1v);
+                    split4<true>(kdz1[0][c], sc, h0, l0);
+                    split4<true>(kdz1[1][c], sc, h1v, l1v);
                     const h8 bh = cat(h0, h1v), bl = cat(l0, l1v);
                     if (SPLIT) {
                         df = mfma16(w1fl, bh, df);
@@ -1328,7 +1340,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 } else {
                     // K = this wave's 16 units: slots 4q..4q+3 of the 16x16x16 product
                     h4 h0, l0;
-                    split4<true>(dz1[0][c], sc, h0, l0);
+                    split4<true>(kdz1[0][c], sc, h0, l0);
                     const h4 ah = __builtin_shufflevector(w1fh, w1fh, 0, 1, 2, 3);
                     const h4 al = __builtin_shufflevector(w1fl, w1fl, 0, 1, 2, 3);
                     if (SPLIT) {
@@ -1376,7 +1388,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             lds_barrier();
             // ---- B: dW1 of the previous tile; then the loads of the next tile's inputs, whose
             //      latency runs through phase C (they are staged in D)
-            if (pbase >= 0) dw1_step(pb ^ 1);
+            if (pbase >= 0) {
+                dw1_step(pb ^ 1);
+                dfeat_step(pg1);
+            }
             if (stager) load_tile(tile + gridDim.x, r0n, winn);  // past the last tile: zeroed, not staged
             lds_barrier();
             // ---- C: output gradient and exponents of this tile; the frame of dW1; db2 += dz2,
@@ -1427,7 +1442,10 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             pbase = tile * NT;
         }
         // ---- the last tile: A (dz1), B (dW1 and the feature gradient)
-        if (pbase >= 0) dz1_step((it - 1) & 1, pg2, pg1, pex);
+        if (pbase >= 0) {
+            dz1_step((it - 1) & 1, pg2, pg1, pex);
+            dfeat_step(pg1);  // before the barrier: feat_grad_out below reads every wave's partials
+        }
         lds_barrier();
         if (pbase >= 0) {
             dw1_step((it - 1) & 1);
