@@ -670,14 +670,17 @@ __global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs 
 // chain and hold those rows of W2^T.  The C waves run one tile behind, so every phase pairs P
 // and C work on the same SIMDs.  Phases
 // of iteration t (block-wide barriers between them; the inputs of t are already staged):
-//   A  P: layer 1 of t -> h1 plane, mask bits;              C: dz1 of t-1 (frame plane), dfeat partials
+//   A  P: layer 1 of t -> h1 plane, mask bits;              C: dz1 of t-1 (frame plane)
 //         dW2 += dz2^T h1 of t-1
-//   B  P: layer 2 of t -> h2, logit partials                C: dW1 += dz1^T x of t-1; loads of t+1
-//   C  P: dz3, dz2 of t -> dz2 plane and its frame plane     C: dz3, exponents, b2 b3 sums
+//   B  P: layer 2 of t -> h2, logit partials                C: dW1 += dz1^T x of t-1, dfeat partials
+//                                                              of t-1; loads of t+1
+//   C  P: dz3, dz2 of t -> its frame plane, half of         C: dz3, exponents, b2 b3 sums, the other
+//         the dz2 plane                                        half of the dz2 plane (the same values)
 //   D  P: feature gradient of t-1                           C: stage t+1; dW3 of t
 // (dW2 of a tile waits for the next phase A, where the P waves would otherwise idle beside the
 // longer dz1 of the C waves; h1 is double-buffered for it, and the dz2 frame plane and the dW2
-// frame stay put until the next phase C.)
+// frame stay put until the next phase C.  The feature partials and half of the dz2 plane sit with
+// the C waves for the same balance: phase A is theirs to lengthen, phase C the P waves'.)
 // After the last tile one more A/B pair finishes the C side.  Both roles run the same
 // number of barriers, so s_barrier stays matched.
 
@@ -685,6 +688,9 @@ constexpr int BWD_MP = 2;                   // 16-unit row tiles of one layer pe
 constexpr int BWD_RW = 8 / BWD_MP;          // waves per role: BWD_RW x 16 BWD_MP = 128 units
 constexpr int BWD_RT = 64 * BWD_RW;         // threads per role
 constexpr int BWD_WAVES = 2 * BWD_RW, BWD_THREADS = 64 * BWD_WAVES;
+// row tiles mp < DB_SPLIT of the dz2 plane are written by the P waves, the rest by the C waves
+// (both form the same dz2 values; the split balances phase C between the roles)
+constexpr int DB_SPLIT = BWD_MP / 2;
 static_assert(BWD_MP == 1 || BWD_MP == 2, "one or two row tiles per wave");
 constexpr int NT = TILE;  // samples per block tile (two 16-sample column tiles)
 
@@ -1100,11 +1106,15 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                             const float d = w3t_dz3(wv, ge.dz3[c], r);
                             dz2[r] = h2s[(u0 + r) * H2S + 16 * c + j] > 0.f ? d : 0.f;
                         }
-                        h4 hi, lo;
-                        split4<false>(dz2, pow2(ge.g2[c]), hi, lo);
                         const int ob = (16 * c + j) * RS2 + unit_col(BWD_MP * w + mp) + 8 * q;
-                        store_h4(db, 0, ob, hi);
-                        if (SPLIT) store_h4(db, NT * RS2 * 2, ob, lo);
+                        if (mp < DB_SPLIT) {
+                            // dz2 at its per-sample scale: the dz1 operand plane (row tiles mp >=
+                            // DB_SPLIT are the C waves' share of it)
+                            h4 hi, lo;
+                            split4<false>(dz2, pow2(ge.g2[c]), hi, lo);
+                            store_h4(db, 0, ob, hi);
+                            if (SPLIT) store_h4(db, NT * RS2 * 2, ob, lo);
+                        }
                         put_split4<SPLIT>(d2s, ob, dz2, frame_shift(F2, se.e1[c]));  // exact for any shift
                     }
                 }
@@ -1423,11 +1433,22 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                     const float wv[3][4] = {{x0.x, x0.y, x0.z, x0.w}, {x1.x, x1.y, x1.z, x1.w}, {x2.x, x2.y, x2.z, x2.w}};
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
+                        float dz2[4];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const float h2 = h2s[(u0 + r) * H2S + 16 * c + j];
                             const float d = w3t_dz3(wv, ge.dz3[c], r);
-                            db2[mp][r] += h2 > 0.f ? d : 0.f;  // the P waves' dz2, bit for bit
+                            dz2[r] = h2 > 0.f ? d : 0.f;  // the P waves' dz2, bit for bit
+                            db2[mp][r] += dz2[r];
+                        }
+                        // dz2 at its per-sample scale, the B operand of the next phase A's dz1: row
+                        // tiles mp >= DB_SPLIT (the P waves write the others)
+                        if (mp >= DB_SPLIT) {
+                            h4 hi, lo;
+                            split4<false>(dz2, pow2(ge.g2[c]), hi, lo);
+                            const int ob = (16 * c + j) * RS2 + unit_col(BWD_MP * w + mp) + 8 * q;
+                            store_h4(db, 0, ob, hi);
+                            if (SPLIT) store_h4(db, NT * RS2 * 2, ob, lo);
                         }
                     }
                 }
