@@ -133,7 +133,7 @@ def psnr(a, b):
 
 def proposal_leg(steps=1500, batch=8192, pool=65536, n_eval=8192, log=None, cleared=False):
     """Train the proposal network on the grids' own plain-256 weight histograms and evaluate on
-    held-out rays against plain-256 (the judge), with a 1024-sample render as the quadrature-limit
+    held-out rays against plain-256 (the baseline it must match), with a 1024-sample render as the quadrature-limit
     reference.  Guarded resampling (coarse bins with weight nearby cut at the plain spacing, plus
     extra samples allotted by the network; empty and occluded bins skipped) is swept over the
     occupancy threshold and the extra count; the fewest samples within 0.1 dB of plain-256 are
@@ -206,7 +206,7 @@ def proposal_leg(steps=1500, batch=8192, pool=65536, n_eval=8192, log=None, clea
     loss_end = float(loss.item())
 
     # evaluation on held-out rays against the 1024-sample render (the quadrature-limit stand-in for
-    # ground truth); plain 256-sample rendering is the judge
+    # ground truth); plain 256-sample rendering is the baseline to match
     ev = rays_of(8, n_eval)
     gt = colour_render(ev, plain_batch(ev, 1024))[0].cpu().numpy()
     pb = plain_batch(ev, 256)
@@ -853,8 +853,8 @@ def main():
                     help="end with a plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is described in "
-                                   "DESIGN.md but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this step runs on one GPU only; sharding over several GPUs is not "
+                                   "implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
