@@ -244,10 +244,12 @@ class TrainStep:
         ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
         self._adam("density", self.lr_grid, True)
 
-    def _update_feat(self):
+    def _update_feat(self, counted=None):
         self._scatter_feat()
         if self.tv is not None:
             ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
+        if counted is not None:
+            torch.cuda.current_stream().wait_event(counted)  # this step's Adam counter
         self._adam("feat", self.lr_grid, True)
 
     def backward(self):
@@ -322,13 +324,19 @@ class TrainStep:
         if not self.prepared_ahead or self._prep_version != self.mlp_flat["p"]._version:
             ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
 
-    def _side_tail(self, main, side, density_work):
+    def _side_tail(self, main, side, density_work, count=False):
         """After the colour-head backward: the side stream takes the density update, the colour
         head's weight-gradient reduction and Adam, its preparation for the next step and the loss
-        value; main continues with the feature update."""
+        value; main continues with the feature update.  count: the side first advances the Adam
+        step counter (off main's path); the returned event marks it, for main's feature Adam."""
         b = self.batch
         side.wait_stream(main)
+        counted = None
         with torch.cuda.stream(side):
+            if count:
+                ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+                counted = torch.cuda.Event()
+                counted.record(side)
             density_work()
             ops.mlp_reduce_grads(self.mlp, b.n_rays, b.n_samples, self.mlp_ws)
             self._adam("mlp_flat", self.lr_mlp, False)
@@ -339,23 +347,25 @@ class TrainStep:
                 nb = nxt.batch
                 ops.mlp_prepare(self.mlp, nb.ray_offsets, nxt.dirs, nb.n_samples, nxt.mlp_ws)
             ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
+        return counted
 
     def _step_owner(self):
-        # Two streams.  main: the Adam step counter, the colour head (with the feature lookup fused
-        # into its forward), render forward and backward (per-sample density gradients), the
-        # colour-head backward (weight gradients left as per-block partials), then the feature
-        # scatter and Adam.  side, after the colour-head backward: the owner binning of the samples,
+        # Two streams.  main: the colour head (with the feature lookup fused into its forward),
+        # render forward and backward (per-sample density gradients), the colour-head backward
+        # (weight gradients left as per-block partials), then the feature scatter and Adam (after an
+        # event for the counter).  side, after the colour-head backward: the Adam step counter, the
+        # owner binning of the samples,
         # the density update (the owner-brick sum of its per-sample gradients fused with its Adam
         # step, or, with a TV term, the sum, the TV gradient and Adam), the colour head's
         # weight-gradient reduction and Adam, its preparation for the next step and the loss value.
         # The binning depends only on the points, but run beside the colour head's forward it slows
         # that kernel by more than it takes; beside the feature scatter it is hidden.  Every Adam
-        # launch follows the counter in stream order; each buffer has one writer at a time; the side
-        # joins main at the end.
+        # launch follows the counter (in stream order, or through the event); each buffer has one
+        # writer at a time; the side joins main at the end.
         main, side = self._fork_side()
         b = self.batch
         if self.fused_gather:
-            ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+            # the Adam step counter advances on the side stream after the colour-head backward
             self._prepare_if_stale()
             self.forward(loss_value=False, prepared=True)
         else:
@@ -378,8 +388,8 @@ class TrainStep:
             self._bin()
             self._update_density()
 
-        self._side_tail(main, side, density_work)
-        self._update_feat()
+        counted = self._side_tail(main, side, density_work, count=self.fused_gather)
+        self._update_feat(counted)
         main.wait_stream(side)
         self._handed_prep()
         return self.loss
@@ -392,10 +402,11 @@ class TrainStep:
         nxt._prep_version = self.mlp_flat["p"]._version
 
     def _step_brick(self):
-        # Two streams, atomic scatters.  main: the Adam step counter, colour head (with the feature
-        # gather fused into its forward), render forward and backward, colour-head backward (its
-        # weight gradients left as per-block partials), feature scatter, feature Adam.  side, after
-        # the colour-head backward: the binning, density scatter (+ TV), density Adam, the reduction
+        # Two streams, atomic scatters.  main: colour head (with the feature gather fused into its
+        # forward), render forward and backward, colour-head backward (its weight gradients left as
+        # per-block partials), feature scatter, feature Adam (after an event for the counter).  side,
+        # after the colour-head backward: the Adam step counter, the binning, density scatter (+ TV),
+        # density Adam, the reduction
         # of the weight gradients, MLP Adam, the colour head's preparation for the next step and the
         # loss value, beside the feature scatter.  With the gather apart (features not a multiple of
         # 4 channels) the side also runs the counter, the colour head's preparation and the binning
@@ -403,7 +414,7 @@ class TrainStep:
         main, side = self._fork_side()
         b = self.batch
         if self.fused_gather:
-            ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
+            # the Adam step counter advances on the side stream after the colour-head backward
             self._prepare_if_stale()
             self.forward(loss_value=False, prepared=True)
         else:
@@ -438,10 +449,12 @@ class TrainStep:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
             self._adam("density", self.lr_grid, True)
 
-        self._side_tail(main, side, density_work)
+        counted = self._side_tail(main, side, density_work, count=self.fused_gather)
         ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
         if self.tv is not None:
             ops.tv_add_grad(self.grid("feat"), self.tv[1], self.tv[2], self.tv[3])
+        if counted is not None:
+            main.wait_event(counted)  # this step's Adam counter
         self._adam("feat", self.lr_grid, True)
         main.wait_stream(side)
         self._handed_prep()
