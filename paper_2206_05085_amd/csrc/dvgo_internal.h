@@ -222,96 +222,108 @@ __device__ __forceinline__ void scatter_wave(const DevGrid &g, bool valid, const
     const int ln = lane();
     const int px = from_prev(cl.ix), py = from_prev(cl.iy), pz = from_prev(cl.iz);
     const bool pvalid = from_prev(valid ? 1 : 0) != 0;  // lane 0 has no predecessor
-    float acc[8][NC];
-    unsigned head = 0;
+    const int base = cl.ix * g.sx + cl.iy * g.sy + cl.iz * g.cs;
+    // The corners go in groups: with many channels four at a time, since their accumulators are the
+    // largest register set of the scatter and halving them lets more waves share a SIMD (the walk
+    // then runs once per group).
+    constexpr int CG = NC > 4 ? 4 : 8;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
-        const int ax = cl.ix + dx - px, ay = cl.iy + dy - py, az = cl.iz + dz - pz;
-        const bool prev_touches = pvalid && (unsigned)ax <= 1u && (unsigned)ay <= 1u && (unsigned)az <= 1u;
-        if (valid && !prev_touches) head |= 1u << c;
-        const float w = corner_weight(cl, dx, dy, dz);
+    for (int c0 = 0; c0 < 8; c0 += CG) {
+        float acc[CG][NC];
+        unsigned head = 0;  // bit cc: corner c0 + cc heads its run
 #pragma unroll
-        for (int ch = 0; ch < NC; ++ch) acc[c][ch] = w * v[ch];
-    }
-    unsigned active = head;
-    // the values of lane ln + k, moved one lane further each step (zeros past lane 63, so the
-    // validity flag of a lane beyond the wave reads as false)
-    int nx = cl.ix, ny = cl.iy, nz = cl.iz, nval = valid ? 1 : 0;
-    Cell nc = cl;
-    float nv[NC];
+        for (int cc = 0; cc < CG; ++cc) {
+            const int c = c0 + cc;
+            const int dx = (c >> 2) & 1, dy = (c >> 1) & 1, dz = c & 1;
+            const int ax = cl.ix + dx - px, ay = cl.iy + dy - py, az = cl.iz + dz - pz;
+            const bool prev_touches = pvalid && (unsigned)ax <= 1u && (unsigned)ay <= 1u && (unsigned)az <= 1u;
+            if (valid && !prev_touches) head |= 1u << cc;
+            const float w = corner_weight(cl, dx, dy, dz);
 #pragma unroll
-    for (int ch = 0; ch < NC; ++ch) nv[ch] = v[ch];
-    for (int k = 1; k < 64; ++k) {
-        if (__ballot(active != 0) == 0ull) break;
-        nx = from_next(nx);
-        ny = from_next(ny);
-        nz = from_next(nz);
-        nval = from_next(nval);
-        nc.fx = from_next(nc.fx);
-        nc.fy = from_next(nc.fy);
-        nc.fz = from_next(nc.fz);
+            for (int ch = 0; ch < NC; ++ch) acc[cc][ch] = w * v[ch];
+        }
+        unsigned active = head;
+        // the values of lane ln + k, moved one lane further each step (zeros past lane 63, so the
+        // validity flag of a lane beyond the wave reads as false)
+        int nx = cl.ix, ny = cl.iy, nz = cl.iz, nval = valid ? 1 : 0;
+        Cell nc = cl;
+        float nv[NC];
 #pragma unroll
-        for (int ch = 0; ch < NC; ++ch) nv[ch] = from_next(nv[ch]);
-        const bool nvalid = nval != 0;
+        for (int ch = 0; ch < NC; ++ch) nv[ch] = v[ch];
+        for (int k = 1; k < 64; ++k) {
+            if (__ballot(active != 0) == 0ull) break;
+            nx = from_next(nx);
+            ny = from_next(ny);
+            nz = from_next(nz);
+            nval = from_next(nval);
+            nc.fx = from_next(nc.fx);
+            nc.fy = from_next(nc.fy);
+            nc.fz = from_next(nc.fz);
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-            if (!(active & (1u << c))) continue;
-            const int ax = cl.ix + ((c >> 2) & 1) - nx, ay = cl.iy + ((c >> 1) & 1) - ny,
-                      az = cl.iz + (c & 1) - nz;
-            if (nvalid && (unsigned)ax <= 1u && (unsigned)ay <= 1u && (unsigned)az <= 1u) {
-                const float w = corner_weight(nc, ax, ay, az);
+            for (int ch = 0; ch < NC; ++ch) nv[ch] = from_next(nv[ch]);
+            const bool nvalid = nval != 0;
 #pragma unroll
-                for (int ch = 0; ch < NC; ++ch) acc[c][ch] += w * nv[ch];
-            } else {
-                active &= ~(1u << c);
+            for (int cc = 0; cc < CG; ++cc) {
+                if (!(active & (1u << cc))) continue;
+                const int c = c0 + cc;
+                const int ax = cl.ix + ((c >> 2) & 1) - nx, ay = cl.iy + ((c >> 1) & 1) - ny,
+                          az = cl.iz + (c & 1) - nz;
+                if (nvalid && (unsigned)ax <= 1u && (unsigned)ay <= 1u && (unsigned)az <= 1u) {
+                    const float w = corner_weight(nc, ax, ay, az);
+#pragma unroll
+                    for (int ch = 0; ch < NC; ++ch) acc[cc][ch] += w * nv[ch];
+                } else {
+                    active &= ~(1u << cc);
+                }
             }
         }
-    }
-    const int base = cl.ix * g.sx + cl.iy * g.sy + cl.iz * g.cs;
-    if (NC == 1) {
+        if (NC == 1) {
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (head & (1u << c))
-                unsafeAtomicAdd(g.grad + base + ((c >> 2) & 1) * g.sx + ((c >> 1) & 1) * g.sy + (c & 1) * g.cs,
-                                acc[c][0]);
-        return;
-    }
-    // Multi-channel: compact the heads through this wave's LDS slice and issue the atomics with
-    // consecutive lanes on consecutive channels of one vertex, so one instruction covers a few
-    // whole vertex rows instead of one float of 64 vertices.  The two corners of a cell that differ
-    // only in z (2p, 2p + 1) are adjacent rows of the z-fastest layout: a lane puts both of its
-    // records next to each other, so a pair that both lanes' runs start on leaves as one
-    // contiguous 2C-float span (fewer memory packets per vertex than two separate rows).
-    extern __shared__ float scatter_lds[];
-    float *vals = scatter_lds + (threadIdx.x >> 6) * (128 * (NC + 1));
-    int *keys = reinterpret_cast<int *>(vals + 128 * NC);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const bool h0 = (head >> (2 * p)) & 1u, h1 = (head >> (2 * p + 1)) & 1u;
-        const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
-        if ((m0 | m1) == 0ull) continue;
-        const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u)) +
-                         __builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u));
-        const int nh = __popcll(m0) + __popcll(m1);
-        const int k0 = base + ((p >> 1) & 1) * g.sx + (p & 1) * g.sy;  // corner 2p (dz = 0)
-        if (h0) {
-            keys[rank] = k0;
-#pragma unroll
-            for (int ch = 0; ch < NC; ++ch) vals[rank * NC + ch] = acc[2 * p][ch];
+            for (int cc = 0; cc < CG; ++cc) {
+                const int c = c0 + cc;
+                if (head & (1u << cc))
+                    unsafeAtomicAdd(g.grad + base + ((c >> 2) & 1) * g.sx + ((c >> 1) & 1) * g.sy + (c & 1) * g.cs,
+                                    acc[cc][0]);
+            }
+            continue;
         }
-        if (h1) {
-            const int r1 = rank + (h0 ? 1 : 0);
-            keys[r1] = k0 + g.cs;
+        // Multi-channel: compact the heads through this wave's LDS slice and issue the atomics with
+        // consecutive lanes on consecutive channels of one vertex, so one instruction covers a few
+        // whole vertex rows instead of one float of 64 vertices.  The two corners of a cell that
+        // differ only in z (2p, 2p + 1) are adjacent rows of the z-fastest layout: a lane puts both
+        // of its records next to each other, so a pair that both lanes' runs start on leaves as one
+        // contiguous 2C-float span (fewer memory packets per vertex than two separate rows).
+        extern __shared__ float scatter_lds[];
+        float *vals = scatter_lds + (threadIdx.x >> 6) * (128 * (NC + 1));
+        int *keys = reinterpret_cast<int *>(vals + 128 * NC);
 #pragma unroll
-            for (int ch = 0; ch < NC; ++ch) vals[r1 * NC + ch] = acc[2 * p + 1][ch];
+        for (int pp = 0; pp < CG / 2; ++pp) {
+            const int p = c0 / 2 + pp;  // corners 2p, 2p + 1 (bits 2pp, 2pp + 1 of head)
+            const bool h0 = (head >> (2 * pp)) & 1u, h1 = (head >> (2 * pp + 1)) & 1u;
+            const unsigned long long m0 = __ballot(h0), m1 = __ballot(h1);
+            if ((m0 | m1) == 0ull) continue;
+            const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(m0 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m0, 0u)) +
+                             __builtin_amdgcn_mbcnt_hi((unsigned)(m1 >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m1, 0u));
+            const int nh = __popcll(m0) + __popcll(m1);
+            const int k0 = base + ((p >> 1) & 1) * g.sx + (p & 1) * g.sy;  // corner 2p (dz = 0)
+            if (h0) {
+                keys[rank] = k0;
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch) vals[rank * NC + ch] = acc[2 * pp][ch];
+            }
+            if (h1) {
+                const int r1 = rank + (h0 ? 1 : 0);
+                keys[r1] = k0 + g.cs;
+#pragma unroll
+                for (int ch = 0; ch < NC; ++ch) vals[r1 * NC + ch] = acc[2 * pp + 1][ch];
+            }
+            lds_fence();  // the slice is this wave's own: LDS order only, the atomics stay in flight
+            for (int i = ln; i < nh * NC; i += 64) {
+                const int e = i / NC, ch = i - e * NC;
+                if (ch < nch) unsafeAtomicAdd(g.grad + keys[e] + ch, vals[i]);
+            }
+            lds_fence();
         }
-        lds_fence();  // the slice is this wave's own: LDS order only, the atomics stay in flight
-        for (int i = ln; i < nh * NC; i += 64) {
-            const int e = i / NC, ch = i - e * NC;
-            if (ch < nch) unsafeAtomicAdd(g.grad + keys[e] + ch, vals[i]);
-        }
-        lds_fence();
     }
 }
 
