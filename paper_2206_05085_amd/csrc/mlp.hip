@@ -676,7 +676,8 @@ __global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs 
 //                                                              of t-1; loads of t+1
 //   C  P: dz3, dz2 of t -> its frame plane, half of         C: dz3, exponents, b2 b3 sums, the other
 //         the dz2 plane                                        half of the dz2 plane (the same values)
-//   D  P: feature gradient of t-1                           C: stage t+1; dW3 of t
+//   D  P: feature gradient of t-1                           C: stage t+1; dW3 of t; the first dz2
+//                                                              operands of dz1 of t
 // (dW2 of a tile waits for the next phase A, where the P waves would otherwise idle beside the
 // longer dz1 of the C waves; h1 is double-buffered for it, and the dz2 frame plane and the dW2
 // frame stay put until the next phase C.  The feature partials and half of the dz2 plane sit with
@@ -1273,10 +1274,23 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
         // dz1 = mask(h1) W2^T dz2 of a tile (mask bits of parity pb, exponents g2/g1/ex of that
         // tile), dfeat partials, dz1 in the dW1 frame
         float kdz1[BWD_MP][2][4];  // dz1 of the last dz1_step, for its feature partials
-        auto dz1_step = [&](int pb, const int g2[2], const int g1[2], const int ex[2]) {
+        // The first K-step's dz2 operands and the mask bits of the next dz1_step, read at the end of
+        // phase D (the dz2 plane and the mask of that tile are complete there and stay put until the
+        // next phase C / A), so that dz1's first products do not wait for LDS at the head of phase A.
+        h8 pf_bh[2], pf_bl[2];
+        unsigned pf_mbits = 0;
+        auto dz1_prefetch = [&](int pb) {
             const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
-            // this lane's h1 > 0 bits, read before the products so the load is long done
-            const unsigned mbits = mask_b[pb * (BWD_RW * 64) + w * 64 + ln];
+            pf_mbits = mask_b[pb * (BWD_RW * 64) + w * 64 + ln];
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                pf_bh[c] = lds_h8(db, 0, (16 * c + j) * RS2 + 8 * q);
+                pf_bl[c] = lds_h8(db, NT * RS2 * 2, (16 * c + j) * RS2 + 8 * q);
+            }
+        };
+        auto dz1_step = [&](const int g2[2], const int g1[2], const int ex[2]) {
+            const int ln = fresh(lane()), j = ln & 15, q = ln >> 4;
+            const unsigned mbits = pf_mbits;  // this lane's h1 > 0 bits (prefetched)
             float dz1[BWD_MP][2][4];
             v4f acc[2][BWD_MP];  // [c][mp]
 #pragma unroll
@@ -1288,8 +1302,8 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
                 h8 bh[2], bl[2];
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    bh[c] = lds_h8(db, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
-                    bl[c] = lds_h8(db, NT * RS2 * 2, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                    bh[c] = kk == 0 ? pf_bh[c] : lds_h8(db, 0, (16 * c + j) * RS2 + 32 * kk + 8 * q);
+                    bl[c] = kk == 0 ? pf_bl[c] : lds_h8(db, NT * RS2 * 2, (16 * c + j) * RS2 + 32 * kk + 8 * q);
                 }
                 if (SPLIT) {
 #pragma unroll
@@ -1394,7 +1408,7 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             if (((it + 1) & 63) == 0) trw = ray_window(it + 1);
             const int r0n = __builtin_amdgcn_readlane(trw, (it + 1) & 63);
             const int winn = window_entry(a.offs, a.n_rays, r0n);
-            if (pbase >= 0) dz1_step(pb ^ 1, pg2, pg1, pex);
+            if (pbase >= 0) dz1_step(pg2, pg1, pex);
             lds_barrier();
             // ---- B: dW1 of the previous tile; then the loads of the next tile's inputs, whose
             //      latency runs through phase C (they are staged in D)
@@ -1459,12 +1473,13 @@ __global__ __launch_bounds__(BWD_THREADS) void mlp_bwd_kernel(MlpArgs a) {
             //      P waves' next layer 2)
             if (next && stager) stage_tile(pb ^ 1);
             dw3_step(tdz3, j, q);
+            dz1_prefetch(pb);  // for the next phase A's dz1 of this tile
             lds_barrier();
             pbase = tile * NT;
         }
         // ---- the last tile: A (dz1), B (dW1 and the feature gradient)
         if (pbase >= 0) {
-            dz1_step((it - 1) & 1, pg2, pg1, pex);
+            dz1_step(pg2, pg1, pex);  // operands prefetched in the last phase D
             dfeat_step(pg1);  // before the barrier: feat_grad_out below reads every wave's partials
         }
         lds_barrier();
