@@ -325,10 +325,13 @@ class TrainStep:
             ops.mlp_prepare(self.mlp, b.ray_offsets, self.dirs, b.n_samples, self.mlp_ws)
 
     def _side_tail(self, main, side, density_work, count=False):
-        """After the colour-head backward: the side stream takes the density update, the colour
-        head's weight-gradient reduction and Adam, its preparation for the next step and the loss
-        value; main continues with the feature update.  count: the side first advances the Adam
-        step counter (off main's path); the returned event marks it, for main's feature Adam."""
+        """After the colour-head backward: the side stream takes the colour head's weight-gradient
+        reduction and Adam, its preparation for the next step, the loss value and then the density
+        work (density_work); main continues with the feature update.  The colour head's short chain goes first:
+        behind the density update it would run alone after main's feature Adam, the density Adam
+        being slowed by sharing HBM with it (1.1% of the config-2 step).  count: the side first
+        advances the Adam step counter (off main's path); the returned event marks it, for main's
+        feature Adam."""
         b = self.batch
         side.wait_stream(main)
         counted = None
@@ -337,7 +340,6 @@ class TrainStep:
                 ops.counter_add(self.t_dev, 1)  # the Adam step, before any update of this step
                 counted = torch.cuda.Event()
                 counted.record(side)
-            density_work()
             ops.mlp_reduce_grads(self.mlp, b.n_rays, b.n_samples, self.mlp_ws)
             self._adam("mlp_flat", self.lr_mlp, False)
             if self.fused_gather:
@@ -347,6 +349,7 @@ class TrainStep:
                 nb = nxt.batch
                 ops.mlp_prepare(self.mlp, nb.ray_offsets, nxt.dirs, nb.n_samples, nxt.mlp_ws)
             ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, want_grad=False)
+            density_work()
         return counted
 
     def _step_owner(self):
@@ -354,10 +357,10 @@ class TrainStep:
         # render forward and backward (per-sample density gradients), the colour-head backward
         # (weight gradients left as per-block partials), then the feature scatter and Adam (after an
         # event for the counter).  side, after the colour-head backward: the Adam step counter, the
-        # owner binning of the samples,
-        # the density update (the owner-brick sum of its per-sample gradients fused with its Adam
-        # step, or, with a TV term, the sum, the TV gradient and Adam), the colour head's
-        # weight-gradient reduction and Adam, its preparation for the next step and the loss value.
+        # colour head's weight-gradient reduction and Adam, its preparation for the next step, the
+        # loss value, the owner binning of the samples and the density update (the owner-brick sum
+        # of its per-sample gradients fused with its Adam step, or, with a TV term, the sum, the TV
+        # gradient and Adam).
         # The binning depends only on the points, but run beside the colour head's forward it slows
         # that kernel by more than it takes; beside the feature scatter it is hidden.  Every Adam
         # launch follows the counter (in stream order, or through the event); each buffer has one
@@ -405,10 +408,10 @@ class TrainStep:
         # Two streams, atomic scatters.  main: colour head (with the feature gather fused into its
         # forward), render forward and backward, colour-head backward (its weight gradients left as
         # per-block partials), feature scatter, feature Adam (after an event for the counter).  side,
-        # after the colour-head backward: the Adam step counter, the binning, density scatter (+ TV),
-        # density Adam, the reduction
-        # of the weight gradients, MLP Adam, the colour head's preparation for the next step and the
-        # loss value, beside the feature scatter.  With the gather apart (features not a multiple of
+        # after the colour-head backward: the Adam step counter, the reduction of the weight
+        # gradients, MLP Adam, the colour head's preparation for the next step, the loss value, the
+        # binning and density scatter (+ TV), beside the feature scatter and Adam; after the join,
+        # main runs the density Adam.  With the gather apart (features not a multiple of
         # 4 channels) the side also runs the counter, the colour head's preparation and the binning
         # beside the gather.
         main, side = self._fork_side()
@@ -447,7 +450,6 @@ class TrainStep:
             ops.grid_scatter_binned(self.grid("density"), b.xyz, self.g_raw, self.bin_ws)
             if self.tv is not None:
                 ops.tv_add_grad(self.grid("density"), self.tv[0], self.tv[2], self.tv[3])
-            self._adam("density", self.lr_grid, True)
 
         counted = self._side_tail(main, side, density_work, count=self.fused_gather)
         ops.grid_scatter(self.grid("feat"), b.xyz, self.g_feat_s)
@@ -457,6 +459,9 @@ class TrainStep:
             main.wait_event(counted)  # this step's Adam counter
         self._adam("feat", self.lr_grid, True)
         main.wait_stream(side)
+        # the density Adam last, on main: beside the feature Adam (both HBM-bound) it slowed that
+        # update by more than it takes alone
+        self._adam("density", self.lr_grid, True)
         self._handed_prep()
         return self.loss
 
