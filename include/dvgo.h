@@ -187,7 +187,8 @@ int dvgo_set_debug(int32_t on);
 int dvgo_validate_samples(const dvgo_samples *s, void *stream);
 
 /* Size in bytes of the per-batch state that dvgo_render_forward saves for
- * dvgo_render_backward (per-ray halt index and per-64-sample chunk checkpoints). */
+ * dvgo_render_backward (per-ray halt index, per-64-sample chunk checkpoints and each sample's
+ * interpolated density logit raw_k: 4 bytes per sample plus ~20 bytes per ray). */
 int dvgo_render_state_size(int32_t n_rays, int64_t n_samples, size_t *bytes);
 
 /* Forward volume rendering of a ragged batch (section 3 rendering utilities, section 2 Eq. 1).
@@ -204,8 +205,10 @@ int dvgo_render_forward(const dvgo_render_params *p, const dvgo_samples *s, cons
                         const dvgo_grid *color, const float *sample_rgb, float *rgb, float *T_final, float *dist,
                         float *sample_w, void *state, size_t state_bytes, void *stream);
 
-/* Backward of dvgo_render_forward (recomputes each ray from the saved chunk checkpoints;
- * no per-sample intermediates are stored).  Upstream gradients: grad_rgb [R,3] (required),
+/* Backward of dvgo_render_forward (recomputes each ray's transmittance, weights and
+ * distortion prefixes from the saved chunk checkpoints and the saved density logits raw_k:
+ * the density grid is not read again, so it must not change between the two calls; the
+ * colour grid, in grid mode, is looked up again).  Upstream gradients: grad_rgb [R,3] (required),
  * grad_dist [R] and grad_T [R] (NULL = zero).  T_final must be the forward's output.
  * Writes: density->grad += dL/d(density values); in grid mode color->grad += dL/d(colour
  * values); in sample mode grad_sample_rgb [S,3] = dL/dc (overwritten; zero for halted

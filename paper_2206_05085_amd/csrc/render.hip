@@ -45,6 +45,7 @@ struct RenderArgs {
     float *rgb, *T_final, *dist, *sample_w;
     int *halt_idx;
     float4 *ckpt;
+    float *raw_saved;  // each sample's interpolated density logit, written by the forward
     // backward
     const float *T_in, *grad_rgb, *grad_dist, *grad_T;
     float *grad_srgb;
@@ -99,6 +100,39 @@ __device__ __forceinline__ void load_sample(const RenderArgs &a, int k, bool has
     s.mn = has_next ? a.s_mid[k + 1] : 0.f;
 }
 
+// The backward's loader: the density logit comes from the forward's saved copy (no density
+// lookup), and the optical depth and alpha follow from it exactly as in the forward.  The
+// points are read only where a cell is still needed: the colour grid's lookup and scatter, or
+// the density scatter inside the kernel.
+template <int MODE, bool WARP>
+__device__ __forceinline__ void load_sample_bwd(const RenderArgs &a, int k, bool has_next, SampleIn &s) {
+    s.raw = a.raw_saved[k];
+    if (MODE == DVGO_COLOR_GRID || !a.grad_raw) {
+        const float px = a.xyz[3 * k], py = a.xyz[3 * k + 1], pz = a.xyz[3 * k + 2];
+        if (!a.grad_raw) s.cd = cell_of<WARP>(a.dens, px, py, pz);
+        if (MODE == DVGO_COLOR_GRID) {
+            s.cc = cell_of<WARP>(a.col, px, py, pz);
+            const Tri tc = tri_from_cell(a.col, s.cc);
+            s.c0 = interp_ch(a.col, tc, 0);
+            s.c1 = interp_ch(a.col, tc, 1);
+            s.c2 = interp_ch(a.col, tc, 2);
+        }
+    }
+    if (MODE == DVGO_COLOR_SAMPLES) {
+        s.c0 = a.srgb[3 * k];
+        s.c1 = a.srgb[3 * k + 1];
+        s.c2 = a.srgb[3 * k + 2];
+    } else if (MODE != DVGO_COLOR_GRID) {
+        s.c0 = s.c1 = s.c2 = 0.f;
+    }
+    s.delta = a.delta[k];
+    s.x = softplusf(s.raw + a.act_shift) * s.delta;
+    s.alpha = -expm1f(-s.x);
+    s.m = a.s_mid[k];
+    s.l = a.s_len[k];
+    s.mn = has_next ? a.s_mid[k + 1] : 0.f;
+}
+
 template <int MODE, bool WARP>
 __device__ __forceinline__ void render_fwd_ray(const RenderArgs &a, int r) {
     const int ln = lane();
@@ -114,8 +148,12 @@ __device__ __forceinline__ void render_fwd_ray(const RenderArgs &a, int r) {
         const bool valid = k < end;
         const bool has_next = k + 1 < end;
         SampleIn s;
-        if (valid) load_sample<MODE, WARP>(a, k, has_next, s);
-        else zero_sample(s);
+        if (valid) {
+            load_sample<MODE, WARP>(a, k, has_next, s);
+            a.raw_saved[k] = s.raw;
+        } else {
+            zero_sample(s);
+        }
         const float xi = wave_incl(s.x);
         const float T = expf(-(L + wave_excl(xi)));
         if (a.halt_T > 0.f) {
@@ -195,8 +233,8 @@ __device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
         const bool valid = k < hend;
         const bool has_next = k + 1 < hend;
         SampleIn s;
-        if (valid) load_sample<MODE, WARP>(a, k, has_next, s);
-        else zero_sample(s);
+        zero_sample(s);
+        if (valid) load_sample_bwd<MODE, WARP>(a, k, has_next, s);
         const float xi = wave_incl(s.x);
         const float T = expf(-(cp.x + wave_excl(xi)));
         const float Tn = expf(-(cp.x + xi));
@@ -406,13 +444,17 @@ int launch_bwd(const dvgo_render_params *p, const RenderArgs &a, hipStream_t st)
     return check_hip(hipGetLastError(), "render_bwd_kernel launch");
 }
 
+// state: halt index [R] | chunk checkpoints [ckpt_count] | density logits [S], each part
+// 256-byte aligned
 size_t state_bytes(int32_t n_rays, int64_t n_samples) {
-    return align_up((size_t)n_rays * 4, 256) + (size_t)ckpt_count(n_rays, n_samples) * sizeof(float4);
+    return align_up((size_t)n_rays * 4, 256) + align_up((size_t)ckpt_count(n_rays, n_samples) * sizeof(float4), 256) +
+           (size_t)n_samples * 4;
 }
 
-void split_state(void *state, int32_t n_rays, int **halt, float4 **ck) {
+void split_state(void *state, int32_t n_rays, int64_t n_samples, int **halt, float4 **ck, float **raw) {
     *halt = (int *)state;
     *ck = (float4 *)((char *)state + align_up((size_t)n_rays * 4, 256));
+    *raw = (float *)((char *)*ck + align_up((size_t)ckpt_count(n_rays, n_samples) * sizeof(float4), 256));
 }
 
 }  // namespace
@@ -440,7 +482,7 @@ extern "C" int dvgo_render_forward(const dvgo_render_params *p, const dvgo_sampl
     a.T_final = T_final;
     a.dist = dist;
     a.sample_w = sample_w;
-    split_state(state, s->n_rays, &a.halt_idx, &a.ckpt);
+    split_state(state, s->n_rays, s->n_samples, &a.halt_idx, &a.ckpt, &a.raw_saved);
     if (debug_mode()) {
         rc = validate_batch(s->n_rays, s->n_samples, s->ray_offsets, s->s_mid, (hipStream_t)stream);
         if (rc) return rc;
@@ -469,7 +511,7 @@ extern "C" int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samp
     a.grad_T = grad_T;
     a.grad_srgb = grad_sample_rgb;
     a.grad_raw = grad_sample_density;
-    split_state(const_cast<void *>(state), s->n_rays, &a.halt_idx, &a.ckpt);
+    split_state(const_cast<void *>(state), s->n_rays, s->n_samples, &a.halt_idx, &a.ckpt, &a.raw_saved);
     if (debug_mode()) {
         rc = validate_batch(s->n_rays, s->n_samples, s->ray_offsets, s->s_mid, (hipStream_t)stream);
         if (rc) return rc;
@@ -601,7 +643,7 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
     fa.T_final = T;
     fa.dist = dist;
     fa.sample_w = nullptr;
-    split_state(state, R, &fa.halt_idx, &fa.ckpt);
+    split_state(state, R, S, &fa.halt_idx, &fa.ckpt, &fa.raw_saved);
     if (!rc) rc = fill_render_args(p, s, &dg, color ? &cg : nullptr, sample_rgb, true, ba);
     ba.grad_raw = sg ? graw : nullptr;  // the caller's backward variant: per-sample gradients or in-kernel scatter
     ba.T_in = T;
@@ -611,6 +653,7 @@ extern "C" int dvgo_render_autotune(const dvgo_render_params *p, const dvgo_samp
     ba.grad_srgb = gs;
     ba.halt_idx = fa.halt_idx;
     ba.ckpt = fa.ckpt;
+    ba.raw_saved = fa.raw_saved;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     ck(hipEventCreate(&e0), "autotune event");
     ck(hipEventCreate(&e1), "autotune event");
