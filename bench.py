@@ -386,18 +386,23 @@ def render_sweep_leg(sizes=(8192, 32768, 131072)):
                                                              st.g_dist, None, act_shift_=st.shift,
                                                              grad_sample_rgb=st.g_rgb_s, grad_sample_density=st.g_raw,
                                                              schedule=st.schedule)),
+             "render_train": timed(lambda: ops.render_train(b, dens, None, st.rgb_s, st.target, st.lam,
+                                                            act_shift_=st.shift, out=(st.rgb, st.T, st.dist),
+                                                            state=st.state, grad_sample_rgb=st.g_rgb_s,
+                                                            schedule=st.schedule, grad_sample_density=st.g_raw)),
              "bin": timed(lambda: density_bin(ops, st, dens, b)),
              "scatter_density": timed(lambda: density_scatter(ops, st, dens, b)),
              "scatter_feat": timed(lambda: ops.grid_scatter(feat, b.xyz, st.g_feat_s))}
         U = unique_vertices(smp.xyz, n, lo, hi)
         byts = algorithmic_bytes(U, C, S, R)
-        ms = sum(t.values())
+        ms = sum(v for k, v in t.items() if k not in ("render_fwd", "render_bwd"))
         rows.append({"rays": R, "samples": S, "ms": {k: round(v, 4) for k, v in t.items()},
                      "algorithmic_bytes": int(byts), "GB/s": round(byts / (ms * 1e-3) / 1e9, 1),
                      "frac_hbm": round(byts / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)})
         del st, b, wl
         torch.cuda.empty_cache()
-    return {"kernels": "gather + render_fwd + render_bwd + bin + scatter_density + scatter_feat", "sizes": rows}
+    return {"kernels": "gather + render_train + bin + scatter_density + scatter_feat (render_fwd and render_bwd: "
+                       "the same walks as two launches, for reference)", "sizes": rows}
 
 
 def ragged_leg(R=8192, steps=20, log=None):
@@ -889,6 +894,10 @@ def main():
                                                  out=(st.rgb, st.T, st.dist), state=st.state, schedule=st.schedule),
         "loss": lambda: ops.loss_head(st.rgb, st.target, st.dist, st.lam, loss=st.loss, grad_rgb=st.g_rgb,
                                       grad_dist=st.g_dist),
+        "render_train": lambda: ops.render_train(batch, dens, None, st.rgb_s, st.target, st.lam, act_shift_=st.shift,
+                                                 out=(st.rgb, st.T, st.dist), state=st.state,
+                                                 grad_sample_rgb=st.g_rgb_s, schedule=st.schedule,
+                                                 grad_sample_density=st.g_raw),
         "bin": lambda: density_bin(ops, st, dens, batch),
         "render_bwd": lambda: ops.render_backward(batch, dens, None, st.rgb_s, st.T, st.state, st.g_rgb,
                                                   st.g_dist, None, act_shift_=st.shift, grad_sample_rgb=st.g_rgb_s,
@@ -948,13 +957,14 @@ def main():
     # ---- rooflines
     U = unique_vertices(smp.xyz, n, lo, hi)
     B_alg = algorithmic_bytes(U, C, S, R)
-    path = ("gather", "render_fwd", "render_bwd", "bin", "scatter_density", "scatter_feat")
+    path = ("gather", "render_train", "bin", "scatter_density", "scatter_feat")
     t_path = sum(stage_ms[k] for k in path)
     ach = B_alg / (t_path * 1e-3) / 1e9
     tr = measured_traffic("render")
     roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": tr,
-            "kernels": "+".join(path) + " (render + distortion fwd/bwd with the 12-ch feature gather, the "
+            "kernels": "+".join(path) + " (render + distortion forward, loss gradient and backward in one launch, "
+                                        "with the 12-ch feature gather, the "
                                         f"{'owner' if st.owner else 'brick'} binning and density scatter and the "
                                         "atomic feature scatter, batch 0, eager)",
             "path_ms": round(t_path, 4), "algorithmic_bytes": int(B_alg),

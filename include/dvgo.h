@@ -223,6 +223,24 @@ int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samples *s, con
                          size_t state_bytes, const float *grad_rgb, const float *grad_dist, const float *grad_T,
                          float *grad_sample_rgb, float *grad_sample_density, void *stream);
 
+/* Forward, loss gradient and backward of a training step's rendering in one launch (each ray's
+ * wave runs dvgo_render_forward's walk, forms its own loss gradient, then
+ * dvgo_render_backward's walk).  The loss is the one dvgo_loss_head computes:
+ * L = sum_r |rgb_r - target_r|^2 / (3 R) + dist_weight sum_r dist_r / R (the photometric MSE
+ * plus the weighted distortion term of section 2; its dist term only with want_dist), so ray r's
+ * upstream gradients are dL/drgb_r = 2 (rgb_r - target_r) / (3 R) and dL/ddist_r =
+ * dist_weight / R, and dL/dT_final = 0.  target [R,3] (device), dist_weight >= 0.
+ * Outputs, bit for bit as dvgo_render_forward, then dvgo_loss_head without the loss value,
+ * then dvgo_render_backward would give them: rgb [R,3], T_final [R], dist [R] (want_dist),
+ * state (as the forward leaves it), grad_sample_rgb [S,3] (sample mode, overwritten) and
+ * either grad_sample_density [S] (overwritten) or density->grad += (when it is NULL); in grid
+ * mode color->grad +=.  The loss value itself is not computed (dvgo_loss_head gives it from
+ * rgb and dist).  Errors as for the two calls; DVGO_COLOR_NONE is not accepted. */
+int dvgo_render_train(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                      const dvgo_grid *color, const float *sample_rgb, const float *target, float dist_weight,
+                      float *rgb, float *T_final, float *dist, void *state, size_t state_bytes,
+                      float *grad_sample_rgb, float *grad_sample_density, void *stream);
+
 /* Schedule of a ragged batch: order [R] = the rays sorted by decreasing number of 64-sample
  * chunks (ceil(length/64), lengths above 63 chunks share the last class; order within a
  * class is unspecified), and class_offsets [65]: order[class_offsets[k] .. class_offsets[k+1])

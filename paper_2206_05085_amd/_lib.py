@@ -81,6 +81,7 @@ SIGNATURES = {
     "dvgo_render_state_size": (C.c_int, [_I32, _I64, _SZP]),
     "dvgo_render_forward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, VP, VP, VP, C.c_size_t, VP]),
     "dvgo_render_backward": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, VP, C.c_size_t, VP, VP, VP, VP, VP, VP]),
+    "dvgo_render_train": (C.c_int, [_PP, _PS, _PG, _PG, VP, VP, _F, VP, VP, VP, VP, C.c_size_t, VP, VP, VP]),
     "dvgo_ray_schedule": (C.c_int, [_I32, VP, VP, VP, VP]),
     "dvgo_render_autotune": (C.c_int, [_PP, _PS, _PG, _PG, VP, _I32, C.POINTER(_I32), C.POINTER(_I32),
                                        C.POINTER(C.c_float), VP]),

@@ -48,6 +48,8 @@ struct RenderArgs {
     float *raw_saved;  // each sample's interpolated density logit, written by the forward
     // backward
     const float *T_in, *grad_rgb, *grad_dist, *grad_T;
+    const float *target;  // fused forward + loss + backward: per-ray target colours and the
+    float lam;            // distortion weight of the loss
     float *grad_srgb;
     float *grad_raw;  // per-sample density-logit gradient (written instead of the density scatter)
     // schedule: rays ray_list[0..n_list) (identity when NULL), taken by the waves of the grid
@@ -133,8 +135,22 @@ __device__ __forceinline__ void load_sample_bwd(const RenderArgs &a, int k, bool
     s.mn = has_next ? a.s_mid[k + 1] : 0.f;
 }
 
+// What the forward of one ray leaves in registers (the same in every lane, and the values it
+// stores): colour, final transmittance, halt index.
+struct RayFwd {
+    float c0, c1, c2, TN;
+    int halt;
+};
+
+// The backward's per-ray inputs: upstream gradients of colour, distortion and final
+// transmittance, the forward's final transmittance and halt index.
+struct RayGrad {
+    float g0, g1, g2, gD, gT, T_in;
+    int hend;
+};
+
 template <int MODE, bool WARP>
-__device__ __forceinline__ void render_fwd_ray(const RenderArgs &a, int r) {
+__device__ __forceinline__ RayFwd render_fwd_ray(const RenderArgs &a, int r) {
     const int ln = lane();
     const int beg = a.offs[r], end = a.offs[r + 1];
     float L = 0.f, W = 0.f, Q = 0.f;
@@ -184,19 +200,24 @@ __device__ __forceinline__ void render_fwd_ray(const RenderArgs &a, int r) {
             break;
         }
     }
-    accC0 = wave_sum(accC0);
-    accC1 = wave_sum(accC1);
-    accC2 = wave_sum(accC2);
+    // the butterfly sums may differ in the last bit between lanes: lane 0's are the results
+    const float TN = halt < end ? T_halt : expf(-L);
+    RayFwd f;
+    f.c0 = bcast(wave_sum(accC0), 0) + TN * a.bg0;
+    f.c1 = bcast(wave_sum(accC1), 0) + TN * a.bg1;
+    f.c2 = bcast(wave_sum(accC2), 0) + TN * a.bg2;
+    f.TN = TN;
+    f.halt = halt;
     accD = wave_sum(accD);
     if (ln == 0) {
-        const float TN = halt < end ? T_halt : expf(-L);
-        a.rgb[3 * r] = accC0 + TN * a.bg0;
-        a.rgb[3 * r + 1] = accC1 + TN * a.bg1;
-        a.rgb[3 * r + 2] = accC2 + TN * a.bg2;
+        a.rgb[3 * r] = f.c0;
+        a.rgb[3 * r + 1] = f.c1;
+        a.rgb[3 * r + 2] = f.c2;
         a.T_final[r] = TN;
         if (a.want_dist) a.dist[r] = accD;
         a.halt_idx[r] = halt;
     }
+    return f;
 }
 
 template <int MODE, bool WARP>
@@ -205,14 +226,12 @@ __global__ __launch_bounds__(1024) void render_fwd_kernel(RenderArgs a) {
 }
 
 template <int MODE, bool WARP>
-__device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
+__device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r, const RayGrad &in) {
     const int ln = lane();
     const int beg = a.offs[r], end = a.offs[r + 1];
-    const int hend = a.halt_idx[r];
-    const float g0 = a.grad_rgb[3 * r], g1 = a.grad_rgb[3 * r + 1], g2 = a.grad_rgb[3 * r + 2];
-    const float gD = a.grad_dist ? a.grad_dist[r] : 0.f;
-    const float gT = a.grad_T ? a.grad_T[r] : 0.f;
-    float Scar = (g0 * a.bg0 + g1 * a.bg1 + g2 * a.bg2 + gT) * a.T_in[r];
+    const int hend = in.hend;
+    const float g0 = in.g0, g1 = in.g1, g2 = in.g2, gD = in.gD;
+    float Scar = (g0 * a.bg0 + g1 * a.bg1 + g2 * a.bg2 + in.gT) * in.T_in;
     float Wgt = 0.f, Qp = 0.f;
     if (MODE == DVGO_COLOR_SAMPLES) {
         for (int k = hend + ln; k < end; k += 64) {
@@ -273,7 +292,42 @@ __device__ __forceinline__ void render_bwd_ray(const RenderArgs &a, int r) {
 
 template <int MODE, bool WARP>
 __global__ __launch_bounds__(1024) void render_bwd_kernel(RenderArgs a) {
-    FOR_EACH_RAY(a, r) render_bwd_ray<MODE, WARP>(a, r);
+    FOR_EACH_RAY(a, r) {
+        RayGrad in;
+        in.hend = a.halt_idx[r];
+        in.g0 = a.grad_rgb[3 * r];
+        in.g1 = a.grad_rgb[3 * r + 1];
+        in.g2 = a.grad_rgb[3 * r + 2];
+        in.gD = a.grad_dist ? a.grad_dist[r] : 0.f;
+        in.gT = a.grad_T ? a.grad_T[r] : 0.f;
+        in.T_in = a.T_in[r];
+        render_bwd_ray<MODE, WARP>(a, r, in);
+    }
+}
+
+// Forward, loss gradient and backward of each ray in one pass of its wave.  The loss is the
+// training loss of the step, L = sum_r |rgb_r - target_r|^2 / (3 R) + lam sum_r dist_r / R
+// (photometric MSE plus the weighted distortion of section 2), whose gradient for ray r needs
+// only that ray's colour: dL/drgb_r = 2 (rgb_r - target_r) / (3 R), dL/ddist_r = lam / R.
+// The backward then reads the checkpoints and density logits this wave has just stored.
+template <int MODE, bool WARP>
+__global__ __launch_bounds__(1024) void render_train_kernel(RenderArgs a) {
+    const float inv3R = 1.f / (3.f * (float)a.n_rays), invR = 1.f / (float)a.n_rays;
+    FOR_EACH_RAY(a, r) {
+        const RayFwd f = render_fwd_ray<MODE, WARP>(a, r);
+        RayGrad in;
+        in.g0 = 2.f * (f.c0 - a.target[3 * r]) * inv3R;
+        in.g1 = 2.f * (f.c1 - a.target[3 * r + 1]) * inv3R;
+        in.g2 = 2.f * (f.c2 - a.target[3 * r + 2]) * inv3R;
+        in.gD = a.want_dist ? a.lam * invR : 0.f;
+        in.gT = 0.f;
+        in.T_in = f.TN;
+        in.hend = f.halt;
+        // the other lanes' stores of this wave (checkpoints, logits) complete before the reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        render_bwd_ray<MODE, WARP>(a, r, in);
+    }
 }
 
 // Standalone distortion loss on given weights; forward sweep, then (if requested) a
@@ -430,6 +484,22 @@ void launch_bwd_w(const dvgo_render_params *p, const Launch &L, const RenderArgs
         hipLaunchKernelGGL((render_bwd_kernel<DVGO_COLOR_SAMPLES, W>), L.grid, L.block, 0, st, a);
 }
 
+template <bool W>
+void launch_train_w(const dvgo_render_params *p, const Launch &L, const RenderArgs &a, hipStream_t st) {
+    if (p->color_mode == DVGO_COLOR_GRID)
+        hipLaunchKernelGGL((render_train_kernel<DVGO_COLOR_GRID, W>), L.grid, L.block,
+                           scatter_lds_bytes(3, L.block.x), st, a);
+    else
+        hipLaunchKernelGGL((render_train_kernel<DVGO_COLOR_SAMPLES, W>), L.grid, L.block, 0, st, a);
+}
+
+int launch_train(const dvgo_render_params *p, const RenderArgs &a, hipStream_t st) {
+    const Launch L = launch_shape(p, a.n_list);
+    if (any_warp(p, a)) launch_train_w<true>(p, L, a, st);
+    else launch_train_w<false>(p, L, a, st);
+    return check_hip(hipGetLastError(), "render_train_kernel launch");
+}
+
 int launch_fwd(const dvgo_render_params *p, const RenderArgs &a, hipStream_t st) {
     const Launch L = launch_shape(p, a.n_list);
     if (any_warp(p, a)) launch_fwd_w<true>(p, L, a, st);
@@ -518,6 +588,41 @@ extern "C" int dvgo_render_backward(const dvgo_render_params *p, const dvgo_samp
     }
     if (a.n_list == 0) return DVGO_OK;
     return launch_bwd(p, a, (hipStream_t)stream);
+}
+
+extern "C" int dvgo_render_train(const dvgo_render_params *p, const dvgo_samples *s, const dvgo_grid *density,
+                                 const dvgo_grid *color, const float *sample_rgb, const float *target,
+                                 float dist_weight, float *rgb, float *T_final, float *dist, void *state,
+                                 size_t state_bytes_, float *grad_sample_rgb, float *grad_sample_density,
+                                 void *stream) {
+    RenderArgs a;
+    int rc = fill_render_args(p, s, density, color, sample_rgb, true, a, grad_sample_density == nullptr);
+    if (rc) return rc;
+    if (s->n_rays == 0) return DVGO_OK;
+    if (!rgb || !T_final || !state || !target) return set_error(DVGO_ERR_NULL, "rgb, T_final, state or target is NULL");
+    if (p->want_dist && !dist) return set_error(DVGO_ERR_NULL, "dist is NULL with want_dist");
+    if (p->color_mode == DVGO_COLOR_SAMPLES && s->n_samples > 0 && !grad_sample_rgb)
+        return set_error(DVGO_ERR_NULL, "grad_sample_rgb is NULL in DVGO_COLOR_SAMPLES mode");
+    if (!(dist_weight >= 0.f && dist_weight <= 3.4e38f))
+        return set_error(DVGO_ERR_RANGE, "dist_weight must be finite and >= 0");
+    if (state_bytes_ < state_bytes(s->n_rays, s->n_samples))
+        return set_error(DVGO_ERR_WORKSPACE, "state buffer too small (%zu < %zu)", state_bytes_,
+                         state_bytes(s->n_rays, s->n_samples));
+    a.rgb = rgb;
+    a.T_final = T_final;
+    a.dist = dist;
+    a.sample_w = nullptr;
+    a.target = target;
+    a.lam = dist_weight;
+    a.grad_srgb = grad_sample_rgb;
+    a.grad_raw = grad_sample_density;
+    split_state(state, s->n_rays, s->n_samples, &a.halt_idx, &a.ckpt, &a.raw_saved);
+    if (debug_mode()) {
+        rc = validate_batch(s->n_rays, s->n_samples, s->ray_offsets, s->s_mid, (hipStream_t)stream);
+        if (rc) return rc;
+    }
+    if (a.n_list == 0) return DVGO_OK;
+    return launch_train(p, a, (hipStream_t)stream);
 }
 
 // ------------------------------------------------------------------- scheduling

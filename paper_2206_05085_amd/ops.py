@@ -15,7 +15,7 @@ from ._lib import (COLOR_GRID, COLOR_NONE, COLOR_SAMPLES, MLP_F16, MLP_SPLIT_F16
 
 __all__ = ["act_shift", "set_debug", "validate_samples", "SampleBatch", "DeviceGrid", "MLPParams", "Schedule", "ray_schedule", "render_autotune",
            "render_state_size", "render_forward",
-           "render_backward", "distortion_workspace_size", "distortion_loss", "distortion_loss_noalloc", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
+           "render_backward", "render_train", "distortion_workspace_size", "distortion_loss", "distortion_loss_noalloc", "grid_adam_step", "counter_add", "grid_gather", "tv_add_grad",
            "grid_scatter", "grid_resample", "bin_workspace_size", "bin_samples", "grid_scatter_binned", "owner_workspace_size", "owner_bin", "grid_scatter_owned", "grid_scatter_adam", "alpha", "mlp_workspace_size", "mlp_prepare", "mlp_forward", "mlp_forward_gather", "mlp_backward",
            "mlp_backward_partials", "mlp_reduce_grads", "loss_head",
            "resample_guarded_offsets", "resample_guarded", "SamplerSpec", "sample_count", "sample_emit", "sample_rays", "occupancy_update",
@@ -298,6 +298,39 @@ def render_backward(batch: SampleBatch, density: DeviceGrid, color: Optional[Dev
          ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), _p(T_final), _p(state), state.numel(),
          _p(grad_rgb), _p(grad_dist), _p(grad_T), _p(grad_sample_rgb), _p(grad_sample_density), _stream())
     return grad_sample_rgb
+
+
+def render_train(batch: SampleBatch, density: DeviceGrid, color: Optional[DeviceGrid], sample_rgb, target,
+                 dist_weight: float, *, act_shift_: float, halt_T: float = 0.0, bg=(1.0, 1.0, 1.0),
+                 want_dist: bool = True, out=None, state: Optional[torch.Tensor] = None, grad_sample_rgb=None,
+                 schedule: Optional[Schedule] = None, grad_sample_density=None):
+    """render_forward, the loss head's gradients (MSE + dist_weight * distortion) and
+    render_backward in one launch.  Returns (rgb, T_final, dist or None, state, grad_sample_rgb)."""
+    import ctypes
+    mode = COLOR_GRID if color is not None else COLOR_SAMPLES
+    R, S = batch.n_rays, batch.n_samples
+    dev = batch.xyz.device
+    if out is None:
+        out = (torch.empty(R, 3, device=dev), torch.empty(R, device=dev), torch.empty(R, device=dev))
+    rgb, T, dist = out
+    if state is None:
+        state = torch.empty(render_state_size(R, S), dtype=torch.uint8, device=dev)
+    _chk(target, "target", numel=3 * R)
+    if sample_rgb is not None:
+        _chk(sample_rgb, "sample_rgb", numel=3 * S)
+    if mode == COLOR_SAMPLES and grad_sample_rgb is None:
+        grad_sample_rgb = torch.empty(S, 3, device=dev)
+    if grad_sample_density is not None:
+        _chk(grad_sample_density, "grad_sample_density", numel=S)
+    p = _params(act_shift_, halt_T, bg, mode, want_dist, schedule)
+    s = batch.struct()
+    gd = density.struct(need_grad=grad_sample_density is None)
+    gc = color.struct(need_grad=True) if color is not None else None
+    call("dvgo_render_train", ctypes.byref(p), ctypes.byref(s), ctypes.byref(gd),
+         ctypes.byref(gc) if gc is not None else None, _p(sample_rgb), _p(target), float(dist_weight), _p(rgb), _p(T),
+         _p(dist) if want_dist else None, _p(state), state.numel(), _p(grad_sample_rgb), _p(grad_sample_density),
+         _stream())
+    return rgb, T, (dist if want_dist else None), state, grad_sample_rgb
 
 
 def distortion_workspace_size(n_rays: int, n_samples: int) -> int:

@@ -24,7 +24,7 @@ class TrainStep:
     def __init__(self, density, box, *, feat=None, color=None, mlp=None, n_freq=4, act_shift=None, halt_T=0.0,
                  bg=(1.0, 1.0, 1.0), dist_weight=0.01, lr_grid=0.1, lr_mlp=1e-3, betas=(0.9, 0.99), eps=1e-8,
                  tv=None, warp=None, mlp_precision=0, binned_scatter=True, owner_scatter=False, concurrent=True,
-                 fused_gather=True, device="cuda"):
+                 fused_gather=True, fused_render=True, device="cuda"):
         """density [n,n,n,1]; feat [n,n,n,C] with mlp = ([W1,W2,W3],[b1,b2,b3]) (MLP mode), or
         color [n,n,n,3] (grid mode).  Arrays may be numpy or torch; they are copied to the GPU.
         tv: optional (weight_density, weight_feat_or_color, huber_delta, dense) total-variation
@@ -48,7 +48,9 @@ class TrainStep:
         weights (which bumps their version) makes the next step prepare again.
         fused_gather: look the features up inside the colour head's forward kernel (which also
         writes them for the backward) instead of a separate gather kernel (feature rows whose
-        channel count is a multiple of 4)."""
+        channel count is a multiple of 4).  fused_render: in the concurrent step, the render
+        forward, the loss gradient and the render backward run as one launch
+        (ops.render_train; bit for bit the same results as the three calls)."""
         def dev(a):
             return torch.as_tensor(a).to(device=device, dtype=torch.float32).contiguous()
 
@@ -61,6 +63,7 @@ class TrainStep:
         self.binned = bool(binned_scatter)
         self.owner = self.binned and bool(owner_scatter)
         self.concurrent = bool(concurrent)
+        self.fused_render = bool(fused_render)
         self.side = None
         self.prepared_ahead = False  # the colour head's workspace holds the preparation for the next step
         self._prep_version = -1  # torch version of the MLP weights that preparation was made from
@@ -197,19 +200,40 @@ class TrainStep:
                                halt_T=self.halt_T, bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist),
                                state=self.state, schedule=self.schedule)
         else:
-            if self.fused_gather and not gathered:
-                ops.mlp_forward_gather(self.mlp, b.ray_offsets, self.dirs, self.grid("feat"), b.xyz,
-                                       feat_out=self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws, prepared=prepared)
-            else:
-                if not gathered:
-                    ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
-                ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws,
-                                prepared=prepared)
+            self._colour_forward(gathered, prepared)
             ops.render_forward(b, self.grid("density"), None, self.rgb_s, act_shift_=self.shift, halt_T=self.halt_T,
                                bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist), state=self.state,
                                schedule=self.schedule)
         ops.loss_head(self.rgb, self.target, self.dist, self.lam, loss=self.loss, grad_rgb=self.g_rgb,
                       grad_dist=self.g_dist, want_loss=loss_value)
+
+    def _colour_forward(self, gathered, prepared):
+        b = self.batch
+        if self.fused_gather and not gathered:
+            ops.mlp_forward_gather(self.mlp, b.ray_offsets, self.dirs, self.grid("feat"), b.xyz,
+                                   feat_out=self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws, prepared=prepared)
+        else:
+            if not gathered:
+                ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)
+            ops.mlp_forward(self.mlp, b.ray_offsets, self.dirs, self.feat_s, rgb=self.rgb_s, ws=self.mlp_ws,
+                            prepared=prepared)
+
+    def _render_fwd_bwd(self, gathered=False, prepared=False):
+        """The concurrent step's forward and render backward: the colour head's forward, then the
+        render forward, the loss gradients and the render backward (per-sample density gradients
+        into g_raw, colour gradients into g_rgb_s), as one fused launch or as three."""
+        b = self.batch
+        if self.fused_render:
+            self._colour_forward(gathered, prepared)
+            ops.render_train(b, self.grid("density"), None, self.rgb_s, self.target, self.lam, act_shift_=self.shift,
+                             halt_T=self.halt_T, bg=self.bg, want_dist=True, out=(self.rgb, self.T, self.dist),
+                             state=self.state, grad_sample_rgb=self.g_rgb_s, schedule=self.schedule,
+                             grad_sample_density=self.g_raw)
+            return
+        self.forward(gathered=gathered, loss_value=False, prepared=prepared)
+        ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
+                            None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
+                            schedule=self.schedule, grad_sample_density=self.g_raw)
 
     def _bin(self):
         b = self.batch
@@ -370,7 +394,7 @@ class TrainStep:
         if self.fused_gather:
             # the Adam step counter advances on the side stream after the colour-head backward
             self._prepare_if_stale()
-            self.forward(loss_value=False, prepared=True)
+            self._render_fwd_bwd(prepared=True)
         else:
             side.wait_stream(main)  # the side's first kernels depend on nothing of this step
             ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
@@ -380,10 +404,7 @@ class TrainStep:
                 prepared = torch.cuda.Event()
                 prepared.record(side)
             main.wait_event(prepared)
-            self.forward(gathered=True, loss_value=False, prepared=True)
-        ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
-                            None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
-                            schedule=self.schedule, grad_sample_density=self.g_raw)
+            self._render_fwd_bwd(gathered=True, prepared=True)
         ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
                                   grad_feat=self.g_feat_s, prepared=True)
 
@@ -419,7 +440,7 @@ class TrainStep:
         if self.fused_gather:
             # the Adam step counter advances on the side stream after the colour-head backward
             self._prepare_if_stale()
-            self.forward(loss_value=False, prepared=True)
+            self._render_fwd_bwd(prepared=True)
         else:
             side.wait_stream(main)  # the side's first kernels depend on nothing of this step
             ops.grid_gather(self.grid("feat"), b.xyz, out=self.feat_s)  # enqueued first: launched first
@@ -432,14 +453,11 @@ class TrainStep:
                 binned = torch.cuda.Event()
                 binned.record(side)
             main.wait_event(prepared)  # the colour head's preparation and the step counter
-            self.forward(gathered=True, loss_value=False, prepared=True)
+            self._render_fwd_bwd(gathered=True, prepared=True)
             # An edge from the binning into main (long satisfied by now): without one, a graph
             # replay may launch the binning only behind main's last kernels, and the density work
             # with it.
             main.wait_event(binned)
-        ops.render_backward(b, self.grid("density"), None, self.rgb_s, self.T, self.state, self.g_rgb, self.g_dist,
-                            None, act_shift_=self.shift, halt_T=self.halt_T, bg=self.bg, grad_sample_rgb=self.g_rgb_s,
-                            schedule=self.schedule, grad_sample_density=self.g_raw)
         # the weight-gradient reduction waits on the side stream: only the MLP Adam needs it
         ops.mlp_backward_partials(self.mlp, b.ray_offsets, self.dirs, self.feat_s, self.g_rgb_s, self.mlp_ws,
                                   grad_feat=self.g_feat_s, prepared=True)
