@@ -432,6 +432,33 @@ __device__ __forceinline__ void copy_to_lds(unsigned char *dst, const unsigned c
 }
 
 // ------------------------------------------------------------------ forward
+//
+// The forward's LDS copy of the weight image re-strides the FP16 weight rows.  On gfx950 the
+// operand reads of a row tile (lane j reads row j, lane group q the 16 bytes at 16 q) run without
+// bank conflicts when the row stride is 32 bytes more than a multiple of 64; the image's strides
+// (272 and 144 bytes, which the backward's planes share) are 16 bytes more and read about 1.7x
+// slower (measured with this read pattern in isolation: ~120 against ~205 bytes per clock per CU).
+constexpr int FRS2 = 144;  // halves per W2 row in the forward's LDS (128 used)
+constexpr int FRS1 = 80;   // halves per W1 row in the forward's LDS (64 used)
+constexpr int F_W2H = 0;
+constexpr int F_W2L = F_W2H + H * FRS2 * 2;
+constexpr int F_W1H = F_W2L + H * FRS2 * 2;
+constexpr int F_W1L = F_W1H + H * FRS1 * 2;
+constexpr int F_SMALL = F_W1L + H * FRS1 * 2;          // b1, b2, W3, b3, meta, laid out as in the image
+constexpr int F_END = F_SMALL + (IMG_FWD_END - IMG_B1);
+static_assert((FRS2 * 2) % 64 == 32 && (FRS1 * 2) % 64 == 32 && F_SMALL % 16 == 0, "forward LDS strides");
+static_assert(F_END <= 160 * 1024, "forward LDS block");
+
+// rows of row_bytes (a multiple of 16) from src with stride sstride to dst with stride dstride
+__device__ __forceinline__ void copy_rows_to_lds(unsigned char *dst, int dstride, const unsigned char *src,
+                                                 int sstride, int rows, int row_bytes) {
+    const int chunks = row_bytes / 16;
+    for (int i = threadIdx.x; i < rows * chunks; i += blockDim.x) {
+        const int r = i / chunks, c = i - r * chunks;
+        *reinterpret_cast<uint4 *>(dst + r * dstride + 16 * c) =
+            *reinterpret_cast<const uint4 *>(src + r * sstride + 16 * c);
+    }
+}
 
 // Wave tiles of the forward: with the feature lookup inside (GM > 0) 16 samples per wave and 16
 // waves per block, so four waves share each SIMD and hide the lookups' latency behind each other's
@@ -449,19 +476,24 @@ struct FwdShape {
 template <bool SPLIT, int GM>
 __global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs a) {
     constexpr int FWD_NC = FwdShape<GM>::NC, FWD_WAVES = FwdShape<GM>::WAVES, FWD_WTILE = FwdShape<GM>::WTILE;
-    __shared__ __attribute__((aligned(16))) unsigned char sm[IMG_FWD_END];
-    copy_to_lds(sm, a.img, IMG_FWD_END);
+    __shared__ __attribute__((aligned(16))) unsigned char sm[F_END];
+    copy_rows_to_lds(sm + F_W2H, FRS2 * 2, a.img + IMG_W2H, RS2 * 2, H, H * 2);
+    copy_rows_to_lds(sm + F_W2L, FRS2 * 2, a.img + IMG_W2L, RS2 * 2, H, H * 2);
+    copy_rows_to_lds(sm + F_W1H, FRS1 * 2, a.img + IMG_W1H, RS1 * 2, H, 64 * 2);
+    copy_rows_to_lds(sm + F_W1L, FRS1 * 2, a.img + IMG_W1L, RS1 * 2, H, 64 * 2);
+    copy_to_lds(sm + F_SMALL, a.img + IMG_B1, IMG_FWD_END - IMG_B1);
     __syncthreads();
-    const _Float16 *W2h = reinterpret_cast<const _Float16 *>(sm + IMG_W2H);
-    const _Float16 *W2l = reinterpret_cast<const _Float16 *>(sm + IMG_W2L);
-    const unsigned char *r1 = lds_region(sm, IMG_W1H);
+    const _Float16 *W2h = reinterpret_cast<const _Float16 *>(sm + F_W2H);
+    const _Float16 *W2l = reinterpret_cast<const _Float16 *>(sm + F_W2L);
+    const unsigned char *r1 = lds_region(sm, F_W1H);
     const _Float16 *W1h = reinterpret_cast<const _Float16 *>(r1);
-    const _Float16 *W1l = reinterpret_cast<const _Float16 *>(r1 + (IMG_W1L - IMG_W1H));
-    const float *b1 = reinterpret_cast<const float *>(r1 + (IMG_B1 - IMG_W1H));
-    const float *b2 = reinterpret_cast<const float *>(r1 + (IMG_B2 - IMG_W1H));
-    const float *W3 = reinterpret_cast<const float *>(r1 + (IMG_W3 - IMG_W1H));
-    const float *b3 = reinterpret_cast<const float *>(r1 + (IMG_B3 - IMG_W1H));
-    const Meta meta = *reinterpret_cast<const Meta *>(r1 + (IMG_META - IMG_W1H));
+    const _Float16 *W1l = reinterpret_cast<const _Float16 *>(r1 + (F_W1L - F_W1H));
+    const unsigned char *rs = r1 + (F_SMALL - F_W1H);
+    const float *b1 = reinterpret_cast<const float *>(rs);
+    const float *b2 = reinterpret_cast<const float *>(rs + (IMG_B2 - IMG_B1));
+    const float *W3 = reinterpret_cast<const float *>(rs + (IMG_W3 - IMG_B1));
+    const float *b3 = reinterpret_cast<const float *>(rs + (IMG_B3 - IMG_B1));
+    const Meta meta = *reinterpret_cast<const Meta *>(rs + (IMG_META - IMG_B1));
     const int ln = lane(), j = ln & 15, q = ln >> 4;
     const int nwt = (a.S + FWD_WTILE - 1) / FWD_WTILE;
     const int wt0 = blockIdx.x * FWD_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -579,7 +611,7 @@ __global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs 
             for (int c = 0; c < FWD_NC; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kk = 0; kk < 2; ++kk) {
-                const int o = (16 * m + j) * RS1 + 32 * kk + 8 * q;
+                const int o = (16 * m + j) * FRS1 + 32 * kk + 8 * q;
                 const h8 ah = *reinterpret_cast<const h8 *>(W1h + o);
                 const h8 al = *reinterpret_cast<const h8 *>(W1l + o);
                 if (SPLIT) {
@@ -613,7 +645,7 @@ __global__ __launch_bounds__(FwdShape<GM>::THREADS) void mlp_fwd_kernel(MlpArgs 
             for (int c = 0; c < FWD_NC; ++c) acc[c] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                const int o = (16 * m + j) * RS2 + 32 * kk + 8 * q;
+                const int o = (16 * m + j) * FRS2 + 32 * kk + 8 * q;
                 const h8 ah = *reinterpret_cast<const h8 *>(W2h + o);
                 const h8 al = *reinterpret_cast<const h8 *>(W2l + o);
                 if (SPLIT) {
